@@ -1,0 +1,215 @@
+"""CPU oracle for connection generation and calibration.
+
+TEST INFRASTRUCTURE ONLY: the plain, slow reference the GPU path is checked
+against.  Only the test suite, the smoke check and the CPU-baseline leg of the
+benchmark may import this package.  It shares no code with the GPU library and
+the GPU library never loads it.
+
+The arithmetic lives in ``ng_oracle.c`` (plain C, built with gcc); this module
+only marshals arguments.  Call objects are duck-typed: any object with the
+attributes ``rule``, ``src``, ``tgt``, ``k_or_n``, ``weight`` and ``delay``
+(see ``paper_2306_09855_amd.workloads.Call``) is accepted.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ng_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+RULES = {
+    "one_to_one": 0,
+    "all_to_all": 1,
+    "fixed_indegree": 2,
+    "fixed_outdegree": 3,
+    "fixed_total_number": 4,
+}
+KINDS = {"const": 0, "normal": 1, "uniform_int": 2, "uniform": 3}
+
+
+def build() -> str:
+    """Compile the oracle with gcc (contraction off so fp32 steps are exact IEEE ops)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+           "-fno-fast-math", "-Wall", "-o", _LIB + ".tmp", _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+class _Call(ctypes.Structure):
+    _fields_ = [
+        ("rule", ctypes.c_int32),
+        ("s0", ctypes.c_uint32), ("ns", ctypes.c_uint32),
+        ("t0", ctypes.c_uint32), ("nt", ctypes.c_uint32),
+        ("k_or_n", ctypes.c_uint64),
+        ("w_kind", ctypes.c_int32), ("w_a", ctypes.c_double), ("w_b", ctypes.c_double),
+        ("d_kind", ctypes.c_int32), ("d_a", ctypes.c_double), ("d_b", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB)
+        u32, u64, i32, f32, f64 = (ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32,
+                                   ctypes.c_float, ctypes.c_double)
+        P = ctypes.POINTER
+        L.ora_philox4x32_10.argtypes = [P(u32), P(u32), P(u32)]
+        L.ora_philox4x32_10.restype = None
+        L.ora_word.argtypes = [u64, u32, u32, u64]
+        L.ora_word.restype = u32
+        L.ora_rand_below.argtypes = [u32, u32]
+        L.ora_rand_below.restype = u32
+        L.ora_rand_below_batch.argtypes = [ctypes.c_void_p, u64, u32, ctypes.c_void_p]
+        L.ora_rand_below_batch.restype = None
+        L.ora_normal_weight.argtypes = [u32, u32, f64, f64]
+        L.ora_normal_weight.restype = f64
+        L.ora_uniform_weight.argtypes = [u32, f64, f64]
+        L.ora_uniform_weight.restype = f64
+        L.ora_delay_steps.argtypes = [f32, f32]
+        L.ora_delay_steps.restype = i32
+        L.ora_uniform_ms_delay.argtypes = [u32, f64, f64, f32]
+        L.ora_uniform_ms_delay.restype = i32
+        L.ora_count.argtypes = [P(_Call)]
+        L.ora_count.restype = ctypes.c_int64
+        L.ora_words_per_synapse.argtypes = [P(_Call)]
+        L.ora_words_per_synapse.restype = ctypes.c_int
+        L.ora_synapse.argtypes = [u64, f32, u32, P(_Call), u64, P(u32), P(u32), P(f64), P(i32)]
+        L.ora_synapse.restype = ctypes.c_int
+        vp = ctypes.c_void_p
+        L.ora_connect.argtypes = [u64, f32, u32, P(_Call), vp, vp, vp, vp]
+        L.ora_connect.restype = ctypes.c_int
+        L.ora_calibrate.argtypes = [u64, u32, vp, vp, vp, vp, vp, P(u64)]
+        L.ora_calibrate.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def to_struct(call) -> _Call:
+    wk, wa, wb = (tuple(call.weight) + (0.0, 0.0))[:3]
+    dk, da, db = (tuple(call.delay) + (0.0, 0.0))[:3]
+    return _Call(RULES[call.rule], int(call.src[0]), int(call.src[1]),
+                 int(call.tgt[0]), int(call.tgt[1]), int(call.k_or_n),
+                 KINDS[wk], float(wa), float(wb), KINDS[dk], float(da), float(db))
+
+
+# --- elementary pieces --------------------------------------------------------
+def philox(ctr, key):
+    c = (ctypes.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    o = (ctypes.c_uint32 * 4)()
+    lib().ora_philox4x32_10(c, k, o)
+    return [int(v) for v in o]
+
+
+def word(seed: int, c: int, s: int, q: int) -> int:
+    return int(lib().ora_word(seed, c, s, q))
+
+
+def rand_below(x, n: int) -> np.ndarray:
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.uint32))
+    out = np.empty_like(x)
+    lib().ora_rand_below_batch(_ptr(x), x.size, n, _ptr(out))
+    return out
+
+
+def normal_weight(y0: int, y1: int, mean: float, sd: float) -> float:
+    return float(lib().ora_normal_weight(y0, y1, mean, sd))
+
+
+def uniform_weight(y0: int, lo: float, hi: float) -> float:
+    return float(lib().ora_uniform_weight(y0, lo, hi))
+
+
+def delay_steps(d_ms: float, h: float) -> int:
+    return int(lib().ora_delay_steps(d_ms, h))
+
+
+def uniform_ms_delay(x: int, lo: float, hi: float, h: float) -> int:
+    return int(lib().ora_uniform_ms_delay(x, lo, hi, h))
+
+
+def count(call) -> int:
+    return int(lib().ora_count(ctypes.byref(to_struct(call))))
+
+
+def words_per_synapse(call) -> int:
+    return int(lib().ora_words_per_synapse(ctypes.byref(to_struct(call))))
+
+
+# --- generation ---------------------------------------------------------------
+def synapse(seed: int, h: float, connect_id: int, call, i: int):
+    s, t = ctypes.c_uint32(), ctypes.c_uint32()
+    w, d = ctypes.c_double(), ctypes.c_int32()
+    rc = lib().ora_synapse(seed, h, connect_id, ctypes.byref(to_struct(call)), i,
+                           ctypes.byref(s), ctypes.byref(t), ctypes.byref(w), ctypes.byref(d))
+    if rc != 0:
+        raise ValueError("invalid call")
+    return int(s.value), int(t.value), float(w.value), int(d.value)
+
+
+def connect(seed: int, h: float, connect_id: int, call):
+    """All synapses of one Connect call in creation order: (src, tgt, w fp64, delay)."""
+    st = to_struct(call)
+    n = int(lib().ora_count(ctypes.byref(st)))
+    if n < 0:
+        raise ValueError("invalid call")
+    src = np.empty(n, np.uint32)
+    tgt = np.empty(n, np.uint32)
+    w = np.empty(n, np.float64)
+    d = np.empty(n, np.int32)
+    if lib().ora_connect(seed, h, connect_id, ctypes.byref(st), _ptr(src), _ptr(tgt),
+                         _ptr(w), _ptr(d)) != 0:
+        raise ValueError("invalid call")
+    return src, tgt, w, d
+
+
+def calibrate(n_nodes: int, src: np.ndarray, delay: np.ndarray):
+    """Stable order by (source, delay) and the connection-group index.
+
+    Returns (perm, group_ptr, group_start) with perm[j] the creation index at
+    sorted position j, group_ptr the n_nodes+1 values p_i of Eq. (14) and
+    group_start the G+1 group boundaries."""
+    src = np.ascontiguousarray(src, dtype=np.uint32)
+    delay = np.ascontiguousarray(delay, dtype=np.int32)
+    n = src.size
+    perm = np.empty(n, np.uint64)
+    gptr = np.empty(n_nodes + 1, np.uint32)
+    gstart = np.empty(n + 1, np.uint32)
+    ng = ctypes.c_uint64()
+    if lib().ora_calibrate(n, n_nodes, _ptr(src), _ptr(delay), _ptr(perm), _ptr(gptr),
+                           _ptr(gstart), ctypes.byref(ng)) != 0:
+        raise ValueError("source index out of range")
+    return perm, gptr, gstart[: ng.value + 1].copy()
+
+
+def build_network(seed: int, h: float, n_nodes: int, calls, first_connect_id: int = 0):
+    """Connect every call in order, then calibrate.
+
+    Returns a dict with creation-order arrays (src, tgt, w, delay), the
+    calibrated arrays (s_src, s_tgt, s_w, s_delay), perm, group_ptr and
+    group_start."""
+    parts = [connect(seed, h, first_connect_id + c, call) for c, call in enumerate(calls)]
+    if parts:
+        src, tgt, w, d = (np.concatenate([p[k] for p in parts]) for k in range(4))
+    else:
+        src, tgt, w, d = (np.empty(0, np.uint32), np.empty(0, np.uint32),
+                          np.empty(0, np.float64), np.empty(0, np.int32))
+    perm, gptr, gstart = calibrate(n_nodes, src, d)
+    return dict(src=src, tgt=tgt, w=w, delay=d, perm=perm,
+                s_src=src[perm], s_tgt=tgt[perm], s_w=w[perm], s_delay=d[perm],
+                group_ptr=gptr, group_start=gstart)

@@ -1,0 +1,278 @@
+/*
+ * CPU oracle: plain, slow reference of connection generation and calibration.
+ *
+ * TEST INFRASTRUCTURE ONLY -- see ng_oracle.h.  Every function here follows a
+ * passage of Golosio et al. (arXiv 2306.09855) or the frozen random-number
+ * contract stated in ng_oracle.h; nothing is blocked, fused or reordered
+ * beyond what those definitions state.  Build with -ffp-contract=off.
+ */
+#include "ng_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---------------------------------------------------------------------- */
+/* Philox4x32-10, Salmon et al. SC'11: 10 rounds of the S-box built from    */
+/* two 32x32->64 multiplications, with a Weyl sequence for the round keys. */
+/* ---------------------------------------------------------------------- */
+#define PHILOX_M0 0xD2511F53u
+#define PHILOX_M1 0xCD9E8D57u
+#define PHILOX_W0 0x9E3779B9u /* golden ratio */
+#define PHILOX_W1 0xBB67AE85u /* sqrt(3) - 1 */
+
+void ora_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; round++) {
+    if (round > 0) { /* key schedule: bump before every round but the first */
+      k0 += PHILOX_W0;
+      k1 += PHILOX_W1;
+    }
+    uint64_t p0 = (uint64_t)PHILOX_M0 * x0;
+    uint64_t p1 = (uint64_t)PHILOX_M1 * x2;
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t y0 = hi1 ^ x1 ^ k0;
+    uint32_t y1 = lo1;
+    uint32_t y2 = hi0 ^ x3 ^ k1;
+    uint32_t y3 = lo0;
+    x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+  }
+  out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+uint32_t ora_word(uint64_t seed, uint32_t c, uint32_t s, uint64_t q) {
+  uint64_t j = q >> 2;
+  uint32_t ctr[4] = {(uint32_t)j, (uint32_t)(j >> 32), c, s};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t out[4];
+  ora_philox4x32_10(ctr, key, out);
+  return out[q & 3];
+}
+
+/* rand(N) of Sec. 2.1: a uniform integer in [0, N); fixed-point product. */
+uint32_t ora_rand_below(uint32_t x, uint32_t n) {
+  return (uint32_t)(((uint64_t)x * (uint64_t)n) >> 32);
+}
+
+void ora_rand_below_batch(const uint32_t* x, uint64_t count, uint32_t n, uint32_t* out) {
+  for (uint64_t k = 0; k < count; k++) out[k] = ora_rand_below(x[k], n);
+}
+
+/* 24-bit uniforms: u1 in (0,1], u2 in [0,1), both exact in fp32 and fp64 */
+static double unit_open0(uint32_t y) { return ((double)(y >> 8) + 1.0) * (1.0 / 16777216.0); }
+static double unit_open1(uint32_t y) { return (double)(y >> 8) * (1.0 / 16777216.0); }
+
+/* Normal weight: Box-Muller, cosine branch, evaluated in fp64. */
+double ora_normal_weight(uint32_t y0, uint32_t y1, double mean, double sd) {
+  const double two_pi = 6.283185307179586476925286766559;
+  double u1 = unit_open0(y0);
+  double u2 = unit_open1(y1);
+  double z = sqrt(-2.0 * log(u1)) * cos(two_pi * u2);
+  return mean + sd * z;
+}
+
+double ora_uniform_weight(uint32_t y0, double lo, double hi) {
+  return lo + (hi - lo) * unit_open1(y0);
+}
+
+/* Sec. 2.1: a delay in ms becomes an integer number of steps by dividing by
+ * the resolution and rounding; anything below one step becomes one step.
+ * Rounding is to nearest, ties to even.  fp32 throughout. */
+int32_t ora_delay_steps(float d_ms, float h) {
+  float q = d_ms / h;
+  float r = rintf(q);
+  if (r < 1.0f) return 1;
+  return (int32_t)r;
+}
+
+int32_t ora_uniform_ms_delay(uint32_t x, double lo, double hi, float h) {
+  float u = (float)(x >> 8) * (1.0f / 16777216.0f);
+  float d_ms = fmaf((float)(hi - lo), u, (float)lo);
+  return ora_delay_steps(d_ms, h);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Connection rules, Sec. 2.1 Eqs. (4)-(13)                                */
+/* ---------------------------------------------------------------------- */
+int64_t ora_count(const ora_call* c) {
+  if ((uint64_t)c->s0 + c->ns > 0xFFFFFFFFull || (uint64_t)c->t0 + c->nt > 0xFFFFFFFFull)
+    return -1;
+  switch (c->rule) {
+    case ORA_ONE_TO_ONE: /* N_new = N_sources = N_targets */
+      if (c->ns != c->nt) return -1;
+      return (int64_t)c->ns;
+    case ORA_ALL_TO_ALL: /* N_new = N_sources * N_targets */
+      return (int64_t)c->ns * (int64_t)c->nt;
+    case ORA_FIXED_OUTDEGREE: /* N_new = N_sources * K, random targets need N_t > 0 */
+      if (c->nt == 0 && c->ns > 0 && c->k_or_n > 0) return -1;
+      return (int64_t)c->ns * (int64_t)c->k_or_n;
+    case ORA_FIXED_INDEGREE: /* N_new = N_targets * K, random sources need N_s > 0 */
+      if (c->ns == 0 && c->nt > 0 && c->k_or_n > 0) return -1;
+      return (int64_t)c->nt * (int64_t)c->k_or_n;
+    case ORA_FIXED_TOTAL_NUMBER: /* N_new given */
+      if ((c->ns == 0 || c->nt == 0) && c->k_or_n > 0) return -1;
+      return (int64_t)c->k_or_n;
+    default:
+      return -1;
+  }
+}
+
+static int delay_is_random(const ora_call* c) { return c->d_kind != ORA_CONST; }
+
+int ora_words_per_synapse(const ora_call* c) {
+  int draws = 0;
+  if (c->rule == ORA_FIXED_INDEGREE || c->rule == ORA_FIXED_TOTAL_NUMBER) draws++; /* source */
+  if (c->rule == ORA_FIXED_OUTDEGREE || c->rule == ORA_FIXED_TOTAL_NUMBER) draws++; /* target */
+  if (delay_is_random(c)) draws++;
+  return draws;
+}
+
+int ora_synapse(uint64_t seed, float h, uint32_t cid, const ora_call* c, uint64_t i,
+                uint32_t* src, uint32_t* tgt, double* w, int32_t* delay) {
+  uint64_t w0 = (uint64_t)ora_words_per_synapse(c);
+  uint64_t q = i * w0; /* first stream-0 word of synapse i */
+  uint64_t k = c->k_or_n;
+  uint64_t s_off = 0, t_off = 0;
+  switch (c->rule) {
+    case ORA_ONE_TO_ONE: /* Eqs. (4)-(5) */
+      s_off = i;
+      t_off = i;
+      break;
+    case ORA_ALL_TO_ALL: /* Eqs. (6)-(7) */
+      s_off = i / c->nt;
+      t_off = i % c->nt;
+      break;
+    case ORA_FIXED_OUTDEGREE: /* Eqs. (8)-(9) */
+      s_off = i / k;
+      t_off = ora_rand_below(ora_word(seed, cid, 0, q), c->nt);
+      q++;
+      break;
+    case ORA_FIXED_INDEGREE: /* Eqs. (10)-(11) */
+      s_off = ora_rand_below(ora_word(seed, cid, 0, q), c->ns);
+      q++;
+      t_off = i / k;
+      break;
+    case ORA_FIXED_TOTAL_NUMBER: /* Eqs. (12)-(13): source draw, then target draw */
+      s_off = ora_rand_below(ora_word(seed, cid, 0, q), c->ns);
+      q++;
+      t_off = ora_rand_below(ora_word(seed, cid, 0, q), c->nt);
+      q++;
+      break;
+    default:
+      return -1;
+  }
+  *src = c->s0 + (uint32_t)s_off;
+  *tgt = c->t0 + (uint32_t)t_off;
+
+  switch (c->d_kind) {
+    case ORA_CONST:
+      *delay = ora_delay_steps((float)c->d_a, h);
+      break;
+    case ORA_UNIFORM_INT: { /* integer steps lo..hi */
+      uint32_t lo = (uint32_t)c->d_a, hi = (uint32_t)c->d_b;
+      *delay = (int32_t)(lo + ora_rand_below(ora_word(seed, cid, 0, q), hi - lo + 1));
+      break;
+    }
+    case ORA_UNIFORM:
+      *delay = ora_uniform_ms_delay(ora_word(seed, cid, 0, q), c->d_a, c->d_b, h);
+      break;
+    default:
+      return -1;
+  }
+
+  switch (c->w_kind) {
+    case ORA_CONST:
+      *w = c->w_a;
+      break;
+    case ORA_NORMAL:
+      *w = ora_normal_weight(ora_word(seed, cid, 1, 2 * i), ora_word(seed, cid, 1, 2 * i + 1),
+                             c->w_a, c->w_b);
+      break;
+    case ORA_UNIFORM:
+      *w = ora_uniform_weight(ora_word(seed, cid, 1, 2 * i), c->w_a, c->w_b);
+      break;
+    default:
+      return -1;
+  }
+  return 0;
+}
+
+int ora_connect(uint64_t seed, float h, uint32_t cid, const ora_call* c, uint32_t* src,
+                uint32_t* tgt, double* w, int32_t* delay) {
+  int64_t n = ora_count(c);
+  if (n < 0) return -1;
+  for (int64_t i = 0; i < n; i++)
+    if (ora_synapse(seed, h, cid, c, (uint64_t)i, &src[i], &tgt[i], &w[i], &delay[i]) != 0)
+      return -1;
+  return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Calibration, Sec. 2.2                                                    */
+/* ---------------------------------------------------------------------- */
+typedef struct {
+  uint32_t src;
+  int32_t delay;
+  uint64_t idx;
+} sort_item;
+
+/* Source is the first key and delay the second; the creation index breaks
+ * ties, so the order is total and equals a stable sort by (source, delay). */
+static int cmp_item(const void* a, const void* b) {
+  const sort_item* x = (const sort_item*)a;
+  const sort_item* y = (const sort_item*)b;
+  if (x->src != y->src) return x->src < y->src ? -1 : 1;
+  if (x->delay != y->delay) return x->delay < y->delay ? -1 : 1;
+  if (x->idx != y->idx) return x->idx < y->idx ? -1 : 1;
+  return 0;
+}
+
+int ora_calibrate(uint64_t n, uint32_t n_nodes, const uint32_t* src, const int32_t* delay,
+                  uint64_t* perm, uint32_t* group_ptr, uint32_t* group_start,
+                  uint64_t* n_groups) {
+  for (uint64_t j = 0; j < n; j++)
+    if (src[j] >= n_nodes) return -1;
+
+  sort_item* items = (sort_item*)malloc((n ? n : 1) * sizeof(sort_item));
+  if (!items) return -1;
+  for (uint64_t j = 0; j < n; j++) {
+    items[j].src = src[j];
+    items[j].delay = delay[j];
+    items[j].idx = j;
+  }
+  qsort(items, n, sizeof(sort_item), cmp_item);
+  for (uint64_t j = 0; j < n; j++) perm[j] = items[j].idx;
+
+  /* A connection starts a group when its source or its delay differs from
+   * those of the previous connection.  Count groups per source (G_i) and
+   * record the position of each group's first connection. */
+  uint64_t* g_count = (uint64_t*)calloc((size_t)n_nodes + 1, sizeof(uint64_t));
+  if (!g_count) {
+    free(items);
+    return -1;
+  }
+  uint64_t g = 0;
+  for (uint64_t j = 0; j < n; j++) {
+    int first = (j == 0) || items[j].src != items[j - 1].src ||
+                items[j].delay != items[j - 1].delay;
+    if (first) {
+      group_start[g] = (uint32_t)j;
+      g_count[items[j].src]++;
+      g++;
+    }
+  }
+  group_start[g] = (uint32_t)n;
+  *n_groups = g;
+
+  /* Eq. (14): p_i = sum_{j<i} G_j, p_0 = 0, for i = 0..n_nodes */
+  uint64_t acc = 0;
+  for (uint32_t i = 0; i <= n_nodes; i++) {
+    group_ptr[i] = (uint32_t)acc;
+    if (i < n_nodes) acc += g_count[i];
+  }
+  free(g_count);
+  free(items);
+  return 0;
+}

@@ -1,0 +1,97 @@
+/*
+ * CPU oracle for rule-based connection generation and calibration.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the independent, plain and slow
+ * reference that the GPU path is checked against.  Only the test suite, the
+ * smoke check and the CPU-baseline leg of the benchmark may load it.  It shares
+ * no code, header, table or constant with the GPU library, and the GPU library
+ * never loads it.
+ *
+ * What it computes (Golosio et al., "Runtime Construction of Large-Scale
+ * Spiking Neuronal Network Models on GPU Devices"):
+ *   - node groups as consecutive index ranges (Sec. 2.1),
+ *   - the five connection rules, Eqs. (4)-(13) of Sec. 2.1,
+ *   - weights and delays: constant or drawn from a distribution, delays
+ *     converted from ms to integer time steps with a minimum of one step
+ *     (Sec. 2.1, last paragraph),
+ *   - calibration: ordering by source (first key) and delay (second key),
+ *     connection-group boundaries, group counts G_i and their cumulative sum
+ *     p_i of Eq. (14) (Sec. 2.2).
+ *
+ * The random draws follow one frozen contract (the paper uses an unspecified
+ * cuRAND generator and states that a change of generator preserves the
+ * connectivity only statistically, Sec. 2.7):
+ *   Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), key = seed split in two
+ *   32-bit halves, word stream W_{c,s}[q] = Philox(ctr = (q/4 low, q/4 high,
+ *   c, s))[q mod 4] for connect call c and stream s (0: index and delay draws,
+ *   1: weight draws).
+ *
+ * Floating point: weights are evaluated in double precision (fp64).  The
+ * ms-to-step delay conversion decides an integer, so it is evaluated in fp32,
+ * the precision the GPU path uses for the same decision.
+ */
+#ifndef NG_ORACLE_H
+#define NG_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORA_ONE_TO_ONE = 0, ORA_ALL_TO_ALL = 1, ORA_FIXED_INDEGREE = 2,
+       ORA_FIXED_OUTDEGREE = 3, ORA_FIXED_TOTAL_NUMBER = 4 };
+
+/* distribution kinds of a weight or delay specification */
+enum { ORA_CONST = 0, ORA_NORMAL = 1, ORA_UNIFORM_INT = 2, ORA_UNIFORM = 3 };
+
+typedef struct {
+  int32_t rule;
+  uint32_t s0, ns;      /* source range [s0, s0+ns) */
+  uint32_t t0, nt;      /* target range [t0, t0+nt) */
+  uint64_t k_or_n;      /* K for in/out-degree, total for fixed_total_number */
+  int32_t w_kind;  double w_a, w_b;   /* CONST a | NORMAL(mean a, sd b) | UNIFORM [a,b) */
+  int32_t d_kind;  double d_a, d_b;   /* CONST a ms | UNIFORM_INT {a..b} steps | UNIFORM [a,b) ms */
+} ora_call;
+
+/* Philox4x32-10 block function */
+void ora_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+/* word q of stream s of connect call c */
+uint32_t ora_word(uint64_t seed, uint32_t c, uint32_t s, uint64_t q);
+/* rand(n): uniform integer in [0, n) from one 32-bit word, floor(x*n / 2^32) */
+uint32_t ora_rand_below(uint32_t x, uint32_t n);
+void ora_rand_below_batch(const uint32_t* x, uint64_t count, uint32_t n, uint32_t* out);
+/* weight transforms from stream-1 words */
+double ora_normal_weight(uint32_t y0, uint32_t y1, double mean, double sd);
+double ora_uniform_weight(uint32_t y0, double lo, double hi);
+/* delay in ms -> integer steps (fp32), minimum one step */
+int32_t ora_delay_steps(float d_ms, float h);
+/* uniform ms delay from one stream-0 word, then to steps */
+int32_t ora_uniform_ms_delay(uint32_t x, double lo, double hi, float h);
+
+/* number of connections a call creates, or -1 if the call is invalid */
+int64_t ora_count(const ora_call* call);
+/* stream-0 words a synapse consumes */
+int ora_words_per_synapse(const ora_call* call);
+
+/* synapse i of connect call `connect_id` */
+int ora_synapse(uint64_t seed, float h, uint32_t connect_id, const ora_call* call,
+                uint64_t i, uint32_t* src, uint32_t* tgt, double* w, int32_t* delay);
+/* all synapses of one call, in creation order; returns 0 or -1 */
+int ora_connect(uint64_t seed, float h, uint32_t connect_id, const ora_call* call,
+                uint32_t* src, uint32_t* tgt, double* w, int32_t* delay);
+
+/* Calibration of n connections held in creation order.
+ * perm[j]        = creation index of the connection at sorted position j
+ * group_ptr[i]   = p_i of Eq. (14), i = 0..n_nodes (n_nodes+1 entries)
+ * group_start[g] = sorted position of the first connection of group g,
+ *                  g = 0..G, with group_start[G] = n (capacity n+1)
+ * *n_groups      = G
+ * Returns 0, or -1 if a source index is >= n_nodes. */
+int ora_calibrate(uint64_t n, uint32_t n_nodes, const uint32_t* src, const int32_t* delay,
+                  uint64_t* perm, uint32_t* group_ptr, uint32_t* group_start,
+                  uint64_t* n_groups);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,148 @@
+"""Pins of the oracle's connection rules (Sec. 2.1, Eqs. (4)-(13)).
+
+Each rule fixes something exactly: the identity of one_to_one, each pair once
+for all_to_all, exact out-degree / in-degree / total counts, index ranges.  The
+random index and delay draws are checked for uniformity (chi-square at a
+pre-registered alpha of 1e-4 on fixed seeds, so the outcome is deterministic)
+and fixed_total_number's source and target draws for independence.
+"""
+import os
+
+import numpy as np
+import pytest
+from scipy import stats
+
+import oracle
+from paper_2306_09855_amd.workloads import Call, microcircuit_table, two_pop_mixed
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ALPHA = 1e-4
+SEED, H = 12345, 0.1
+
+
+def _conn(call, cid=0, seed=SEED):
+    return oracle.connect(seed, H, cid, call)
+
+
+def test_fig1_all_to_all_golden():
+    rows = np.loadtxt(os.path.join(HERE, "golden", "fig1_all_to_all.txt"), dtype=np.int64)
+    src, tgt, _, _ = _conn(Call("all_to_all", (0, 4), (4, 3)))
+    assert src.size == 12
+    assert np.array_equal(src, rows[:, 1]) and np.array_equal(tgt, rows[:, 2])
+
+
+def test_one_to_one_identity():
+    c = Call("one_to_one", (17, 500), (900, 500))
+    src, tgt, _, _ = _conn(c)
+    i = np.arange(500)
+    assert np.array_equal(src - 17, i) and np.array_equal(tgt - 900, i)
+    assert oracle.count(Call("one_to_one", (0, 5), (0, 6))) == -1
+
+
+def test_all_to_all_each_pair_once():
+    c = Call("all_to_all", (100, 37), (3, 53))
+    src, tgt, _, _ = _conn(c)
+    assert src.size == 37 * 53
+    pairs = set(zip(src.tolist(), tgt.tolist()))
+    assert pairs == {(s, t) for s in range(100, 137) for t in range(3, 56)}
+    # creation order: source-major (Eqs. (6)-(7))
+    assert np.all(np.diff(src.astype(np.int64)) >= 0)
+
+
+def test_fixed_outdegree_exact_and_uniform():
+    K, ns, nt = 40, 300, 1000
+    src, tgt, _, _ = _conn(Call("fixed_outdegree", (1000, ns), (0, nt), K), cid=2)
+    assert src.size == ns * K
+    assert np.array_equal(np.bincount(src - 1000, minlength=ns), np.full(ns, K))
+    assert np.array_equal(src - 1000, np.arange(ns * K) // K)
+    assert tgt.min() >= 0 and tgt.max() < nt
+    cnt = np.bincount(tgt, minlength=nt)
+    assert stats.chisquare(cnt).pvalue > ALPHA
+
+
+def test_fixed_indegree_exact_and_uniform():
+    K, ns, nt = 100, 1000, 1000
+    src, tgt, _, _ = _conn(Call("fixed_indegree", (0, ns), (ns, nt), K))
+    assert src.size == nt * K
+    assert np.array_equal(np.bincount(tgt - ns, minlength=nt), np.full(nt, K))
+    assert np.array_equal(tgt - ns, np.arange(nt * K) // K)
+    assert src.min() >= 0 and src.max() < ns
+    assert stats.chisquare(np.bincount(src, minlength=ns)).pvalue > ALPHA
+
+
+def test_fixed_total_number_exact_uniform_independent():
+    n, ns, nt = 200_000, 20, 30
+    src, tgt, _, _ = _conn(Call("fixed_total_number", (500, ns), (40, nt), n), cid=5)
+    assert src.size == n
+    assert src.min() >= 500 and src.max() < 500 + ns and tgt.min() >= 40 and tgt.max() < 40 + nt
+    assert stats.chisquare(np.bincount(src - 500, minlength=ns)).pvalue > ALPHA
+    assert stats.chisquare(np.bincount(tgt - 40, minlength=nt)).pvalue > ALPHA
+    table = np.zeros((ns, nt))
+    np.add.at(table, (src - 500, tgt - 40), 1)
+    assert stats.chi2_contingency(table).pvalue > ALPHA
+
+
+def test_uniform_int_delays():
+    n = 100_000
+    _, _, _, d = _conn(Call("fixed_total_number", (0, 50), (0, 50), n, delay=("uniform_int", 1, 20)), cid=1)
+    assert d.min() == 1 and d.max() == 20
+    assert stats.chisquare(np.bincount(d, minlength=21)[1:]).pvalue > ALPHA
+
+
+def test_const_delay_and_weight():
+    src, tgt, w, d = _conn(Call("all_to_all", (0, 10), (0, 10), 0, ("const", -2.25), ("const", 1.5)))
+    assert np.all(w == -2.25)
+    assert np.all(d == 15)       # 1.5 ms at h = 0.1 ms
+    _, _, _, d = _conn(Call("all_to_all", (0, 2), (0, 2), 0, ("const", 1.0), ("const", 0.01)))
+    assert np.all(d == 1)        # below one step -> one step
+
+
+def test_weights_normal_per_call():
+    n = 50_000
+    _, _, w, _ = _conn(Call("fixed_total_number", (0, 10), (0, 10), n, ("normal", -0.5, 0.05)), cid=9)
+    assert stats.kstest(w, "norm", args=(-0.5, 0.05)).pvalue > ALPHA
+
+
+def test_streams_are_distinct_across_calls_and_seeds():
+    c = Call("fixed_total_number", (0, 1000), (0, 1000), 1000)
+    a = _conn(c, cid=0)
+    b = _conn(c, cid=1)
+    s2 = _conn(c, cid=0, seed=SEED + 1)
+    assert not np.array_equal(a[0], b[0]) and not np.array_equal(a[0], s2[0])
+    # same (seed, call id) -> same connections
+    again = _conn(c, cid=0)
+    for x, y in zip(a, again):
+        assert np.array_equal(x, y)
+
+
+def test_synapse_matches_connect():
+    c = Call("fixed_indegree", (3, 77), (1000, 50), 13, ("uniform", -1.0, 2.0), ("uniform", 0.5, 3.0))
+    src, tgt, w, d = _conn(c, cid=4)
+    for i in (0, 1, 2, 3, 4, 5, 100, 649):
+        assert oracle.synapse(SEED, H, 4, c, i) == (int(src[i]), int(tgt[i]), float(w[i]), int(d[i]))
+
+
+def test_words_per_synapse():
+    dr, dc = ("uniform_int", 1, 5), ("const", 1.0)
+    assert oracle.words_per_synapse(Call("one_to_one", (0, 1), (0, 1), 0, delay=dr)) == 1
+    assert oracle.words_per_synapse(Call("all_to_all", (0, 1), (0, 1), 0, delay=dc)) == 0
+    assert oracle.words_per_synapse(Call("fixed_indegree", (0, 1), (0, 1), 1, delay=dr)) == 2
+    assert oracle.words_per_synapse(Call("fixed_outdegree", (0, 1), (0, 1), 1, delay=dc)) == 1
+    assert oracle.words_per_synapse(Call("fixed_total_number", (0, 1), (0, 1), 1, delay=dr)) == 3
+
+
+def test_counts():
+    assert oracle.count(Call("all_to_all", (0, 7), (0, 9))) == 63
+    assert oracle.count(Call("fixed_outdegree", (0, 7), (0, 9), 4)) == 28
+    assert oracle.count(Call("fixed_indegree", (0, 7), (0, 9), 4)) == 36
+    assert oracle.count(Call("fixed_total_number", (0, 7), (0, 9), 1234)) == 1234
+    assert oracle.count(Call("fixed_total_number", (0, 0), (0, 9), 5)) == -1
+    assert oracle.count(Call("fixed_indegree", (2**32 - 2, 5), (0, 9), 1)) == -1
+
+
+def test_workload_tables():
+    # the microcircuit stand-in table sums exactly to the requested total
+    t = microcircuit_table(300_000_000)
+    assert t.sum() == 300_000_000 and t.shape == (8, 8) and t.min() > 0
+    wl = two_pop_mixed()
+    assert wl.n_syn == 154_000_000
