@@ -1,0 +1,184 @@
+#!/usr/bin/env python3
+"""Benchmark: synapses built + calibrated per second on one MI355X.
+
+A step is one pass of the whole hot path over the microcircuit-shaped
+network (77,169 nodes in 8 populations, 64 fixed_total_number Connect calls,
+3.0e8 synapses): reset the context, create the nodes, issue every Connect
+call (generation kernels), then calibrate (radix-sort passes and the group
+index).  Inputs are the call descriptions; nothing is copied from the host
+inside the timed region.
+
+Prints one JSON line (rank 0) with the throughput, the roofline of the
+dominant kernel measured with HIP events on the context's stream, and the
+CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "synapses built+calibrated/sec at 3e8 synapses; p50/p99 ng_connect latency"
+HBM_PEAK_GBS = 8000.0
+# paper, Table 2: A100 node connection 0.08 s + calibration 0.408 s for ~3e8 synapses
+PAPER_A100_SYN_PER_S = 3.0e8 / (0.08 + 0.408)
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(kernel: str, n_syn: int, passes: int) -> float | None:
+    """Bytes a kernel must move per step (not what it happens to move)."""
+    per = {
+        "generate": 14.0,                 # write src, tgt, w, delay once
+        "generate_batch": 14.0,
+        "downsweep": 26.0 * passes,       # read one record, write one record, per pass
+        "upsweep": 6.0 + 4.0 * (passes - 1),  # read the key (src + delay, then key)
+        "group_flags": 6.0,               # read src + delay
+        "group_write": 6.0,
+    }.get(kernel)
+    return None if per is None else per * n_syn
+
+
+def cpu_baseline(sample_syn: int) -> dict:
+    import oracle
+    from paper_2306_09855_amd import workloads as W
+    wl = W.microcircuit(total=sample_syn)
+    log(f"cpu baseline: oracle on {wl.n_syn:.3g} synapses ...")
+    t0 = time.perf_counter()
+    oracle.build_network(wl.seed, wl.h, wl.n_nodes, wl.calls)
+    dt = time.perf_counter() - t0
+    return {"value": wl.n_syn / dt, "unit": "synapses/s", "cores": 1, "kind": "oracle",
+            "seconds": dt, "cpu": platform.processor() or platform.machine(),
+            "sample": (f"microcircuit populations (77,169 nodes), 64 fixed_total_number calls scaled to "
+                       f"{wl.n_syn} synapses in total; generation + calibration, single thread")}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batched", action="store_true", help="use ng_connect_batch for the 64 calls")
+    ap.add_argument("--radix-bits", type=int, default=11)
+    ap.add_argument("--ranges", type=int, default=1024)
+    ap.add_argument("--block-size", type=int, default=1 << 24)
+    ap.add_argument("--cpu-sample", type=float, default=1.5e7, help="synapses of the oracle sample; 0 skips")
+    ap.add_argument("--total", type=float, default=3.0e8)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build measures one GPU; the multi-GPU path is a design only",
+                          "n_gpus": args.gpus}))
+        return 2
+
+    import torch
+    from paper_2306_09855_amd import ng
+    from paper_2306_09855_amd import workloads as W
+    from paper_2306_09855_amd.network import Network, arena_bytes_for
+
+    torch.cuda.set_device(0)
+    wl = W.microcircuit(total=int(args.total))
+    n_syn = wl.n_syn
+    arena = arena_bytes_for(n_syn, wl.n_nodes, wl.max_delay, args.block_size, args.radix_bits)
+    log(f"workload microcircuit: {wl.n_nodes} nodes, {len(wl.calls)} calls, {n_syn:.3g} synapses, "
+        f"arena {arena / 2**30:.1f} GiB")
+    net = Network(wl.seed, wl.h, args.block_size, arena)
+    net.tune(args.radix_bits, args.ranges)
+    ctx = net.ctx
+    calls = [ng.call_args(c) for c in wl.calls]
+    batch = [list(x) for x in zip(*calls)]
+
+    def step():
+        ng.ng_reset(ctx)
+        for n in wl.populations:
+            ng.ng_create_nodes(ctx, n)
+        if args.batched:
+            ng.ng_connect_batch(ctx, *batch)
+        else:
+            for a in calls:
+                ng.ng_connect(ctx, *a)
+        ng.ng_calibrate(ctx)
+
+    for i in range(args.warmup):
+        step()
+        ng.ng_sync(ctx)
+        log(f"warmup {i + 1}/{args.warmup} done")
+
+    ng.ng_enable_timing(ctx, True)
+    ng.ng_read_timing(ctx, reset=True)
+    stream = torch.cuda.ExternalStream(net.stream) if net.stream else torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for i in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kernels = ng.ng_read_timing(ctx, reset=True)
+    ng.ng_enable_timing(ctx, False)
+    log(f"timed {args.steps} steps in {t1 - t0:.4f} s")
+
+    wall = t1 - t0
+    dev_ms = e0.elapsed_time(e1)
+    ms_per_step = 1e3 * wall / args.steps
+    value = args.steps * n_syn / wall
+
+    # digit passes the calibration used
+    dbits = int(wl.max_delay).bit_length()
+    sbits = int(wl.n_nodes - 1).bit_length()
+    passes = max(1, -(-(sbits + dbits) // args.radix_bits))
+    per_kernel = {}
+    for name, (launches, total_ms) in kernels.items():
+        ms = total_ms / args.steps
+        ab = algorithmic_bytes(name, n_syn, passes)
+        per_kernel[name] = {"launches_per_step": launches / args.steps, "ms_per_step": round(ms, 4),
+                            "GBps_algorithmic": None if ab is None or ms == 0 else round(ab / ms / 1e6, 1)}
+    dom = max(kernels.items(), key=lambda kv: kv[1][1])[0] if kernels else None
+    roofline = None
+    if dom is not None:
+        launches, total_ms = kernels[dom]
+        ab_step = algorithmic_bytes(dom, n_syn, passes)
+        if ab_step is not None:
+            per_launch_bytes = ab_step * args.steps / launches
+            avg_s = total_ms / launches / 1e3
+            achieved = per_launch_bytes / avg_s / 1e9
+            roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                        "bytes_per_launch": per_launch_bytes, "avg_launch_ms": round(avg_s * 1e3, 4)}
+    path_alg = 42.0 * n_syn  # write each record once, read it and write it sorted once
+    result = {
+        "metric": METRIC, "value": value, "unit": "synapses/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": round(value / PAPER_A100_SYN_PER_S, 2) if n_syn == 3e8 else None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "microcircuit", "n_nodes": wl.n_nodes, "n_calls": len(wl.calls),
+                   "n_syn": n_syn, "rule": "fixed_total_number", "delays": "uniform_int 1..30",
+                   "weights": "normal fp32", "form": "batched" if args.batched else "plain",
+                   "block_size": args.block_size, "radix_bits": args.radix_bits, "ranges": args.ranges,
+                   "sort_passes": passes},
+        "device_ms_per_step": round(dev_ms / args.steps, 4),
+        "path_roofline": {"algorithmic_bytes_per_step": path_alg,
+                          "frac": round(path_alg / (ms_per_step / 1e3) / (HBM_PEAK_GBS * 1e9), 4)},
+        "roofline": roofline,
+        "kernels": per_kernel,
+    }
+    net.close()
+    if args.cpu_sample > 0:
+        result["cpu_baseline"] = cpu_baseline(int(args.cpu_sample))
+    print(json.dumps(result))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

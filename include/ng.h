@@ -1,0 +1,226 @@
+/*
+ * ng.h -- C ABI of the MI355X connectivity builder.
+ *
+ * Builds spiking-network connectivity directly in device memory from
+ * high-level connection rules and then calibrates it, following Golosio et
+ * al., "Runtime Construction of Large-Scale Spiking Neuronal Network Models
+ * on GPU Devices" (arXiv 2306.09855):
+ *   ng_create_nodes   node creation (Sec. 2.6, stage "node creation")
+ *   ng_connect        one Connect call (Sec. 2.1: rules of Eqs. (4)-(13),
+ *                     blocks of Eq. (1), connection numbering of Eqs. (2)-(3))
+ *   ng_calibrate      ordering by (source, delay) and the connection-group
+ *                     index of Eq. (14) (Sec. 2.2; stage "calibration")
+ *   ng_get_connections / ng_copy_connections   read the result back
+ *
+ * Conventions
+ *   - Every call returns an ng_status; 0 is success, negative is an error.
+ *     ng_last_error() gives a message for the calling thread's last error.
+ *     No C++ exception crosses this boundary.
+ *   - Device memory: the caller hands ng_create one device buffer (the arena);
+ *     the context carves all of its device allocations out of it and never
+ *     allocates device memory itself.  The arena and the stream must outlive
+ *     the context.
+ *   - Work is enqueued on the caller's HIP stream and is asynchronous unless a
+ *     function says it synchronizes.  Errors raised by kernels are reported by
+ *     the next synchronizing call as NG_ERR_DEVICE and stay sticky.
+ *   - A context is not thread-safe; use one context per thread or lock.
+ *
+ * Random numbers (the paper uses cuRAND and notes that a change of generator
+ * preserves the network only statistically, Sec. 2.7).  The contract here:
+ *   Philox4x32-10 (Salmon et al., SC'11), key = (seed mod 2^32, seed >> 32).
+ *   Word q of stream s of Connect call c is word (q mod 4) of the block with
+ *   counter (q/4 mod 2^32, q/4 >> 32, c, s).  Stream 0 holds index and delay
+ *   draws: synapse i of a call uses words i*w0 .. i*w0+w0-1 in the order
+ *   [source draw][target draw][delay draw], each present only if random
+ *   (w0 = number of random draws).  Stream 1 holds weight draws: words 2i and
+ *   2i+1 of synapse i.  rand(N) = floor(x * N / 2^32) for a word x.
+ *   Normal weights: Box-Muller, cosine branch, u1 = (y0>>8 + 1)/2^24,
+ *   u2 = (y1>>8)/2^24, computed in fp32 and stored as fp32.
+ */
+#ifndef NG_H
+#define NG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NG_OK = 0,
+  NG_ERR_INVALID_ARG = -1, /* bad range, spec or pointer; nothing changed */
+  NG_ERR_OOM = -2,         /* the arena cannot hold the request; nothing changed */
+  NG_ERR_UNSUPPORTED = -3, /* valid request this library does not implement */
+  NG_ERR_STATE = -4,       /* call not allowed in the current state */
+  NG_ERR_TOO_LARGE = -5,   /* more than 2^32-1 connections in one context */
+  NG_ERR_DEVICE = -6       /* a HIP call or kernel failed (sticky) */
+} ng_status;
+
+typedef struct ng_ctx ng_ctx;
+
+/* A node group of consecutive indices [first, first+n) (Sec. 2.1). */
+typedef struct {
+  uint32_t first, n;
+} ng_range;
+
+/* Connection rules of Sec. 2.1, autapses and multapses allowed. */
+typedef enum {
+  NG_ONE_TO_ONE = 0,         /* Eqs. (4)-(5): N_new = N_s = N_t         */
+  NG_ALL_TO_ALL = 1,         /* Eqs. (6)-(7): N_new = N_s * N_t         */
+  NG_FIXED_INDEGREE = 2,     /* Eqs. (10)-(11): N_new = N_t * K          */
+  NG_FIXED_OUTDEGREE = 3,    /* Eqs. (8)-(9): N_new = N_s * K           */
+  NG_FIXED_TOTAL_NUMBER = 4  /* Eqs. (12)-(13): N_new = N                */
+} ng_rule;
+
+typedef struct {
+  int32_t rule;            /* ng_rule */
+  int32_t allow_autapses;  /* must be 1, or the ranges must not overlap */
+  int32_t allow_multapses; /* must be 1 (the paper's rules allow multapses) */
+  int32_t reserved;
+  uint64_t k_or_n;         /* K for in/out-degree, N for fixed_total_number */
+} ng_conn_spec;
+
+/* Weight and delay specifications (Sec. 2.1, last paragraph). */
+typedef enum {
+  NG_CONST = 0,       /* weight: a.  delay: a in ms -> steps                    */
+  NG_NORMAL = 1,      /* weight only: Normal(mean a, sd b), b >= 0               */
+  NG_UNIFORM_INT = 2, /* delay only: integer steps uniform in {a..b}, 1 <= a <= b */
+  NG_UNIFORM = 3      /* weight: uniform in [a, b).  delay: ms uniform in [a, b) */
+} ng_dist;
+
+typedef struct {
+  int32_t kind; /* ng_dist */
+  int32_t reserved;
+  double a, b;
+} ng_param;
+
+typedef struct {
+  ng_param weight, delay;
+} ng_syn_spec;
+
+typedef struct {
+  uint64_t block_size; /* connections per block B (Eq. (1)); power of two,
+                          2^16 .. 2^30; 0 selects 2^24 */
+  uint64_t seed;       /* Philox key */
+  float h_ms;          /* time resolution for ms -> step conversion; 0 -> 0.1 */
+  int32_t reserved;
+} ng_config;
+
+/* Read-only view of the connections of a context.
+ * Connection j (0 <= j < n_conns) lives in block j / block_size at offset
+ * o = j % block_size.  Block b starts at device address block_base[b]:
+ *   uint32_t src[B] at +0, uint32_t tgt[B] at +4B, float w[B] at +8B,
+ *   int16_t delay[B] at +12B  (B = block_size, 14 bytes per connection).
+ * Before calibration connections are in creation order (calls in issue order,
+ * then i_newconns); after it they are ordered by (source, delay), ties in
+ * creation order.  group_ptr[i] (i = 0..n_nodes) is p_i of Eq. (14); the
+ * groups of source i are g = group_ptr[i] .. group_ptr[i+1]-1 and group g
+ * holds connections group_start[g] .. group_start[g+1]-1.
+ * All pointers are borrowed: valid until the next mutating call on the
+ * context.  block_base is a host array; everything else is device memory. */
+typedef struct {
+  uint64_t n_conns;
+  uint64_t n_groups;          /* G; 0 if not calibrated */
+  uint64_t block_size;
+  uint32_t n_nodes;
+  uint32_t n_blocks;
+  int32_t calibrated;
+  int32_t reserved;
+  void* const* block_base;    /* host array [n_blocks] of device pointers */
+  const uint32_t* group_ptr;  /* device [n_nodes + 1]; NULL if not calibrated */
+  const uint32_t* group_start;/* device [n_groups + 1]; NULL if not calibrated */
+} ng_conn_view;
+
+/* Create a context over the caller's device arena [arena, arena + bytes) on
+ * the current HIP device; all work goes to `stream` (a hipStream_t, NULL =
+ * null stream).  The arena must be 256-byte aligned. */
+int ng_create(const ng_config* cfg, void* arena, uint64_t arena_bytes, void* stream,
+              ng_ctx** out);
+/* Wait for the context's work and release it (the arena stays the caller's). */
+int ng_destroy(ng_ctx* ctx);
+
+/* Append n nodes; *out = {first new index, n}.  Host only. */
+int ng_create_nodes(ng_ctx* ctx, uint32_t n, ng_range* out);
+
+/* One Connect call (Sec. 2.1).  Validates, reserves blocks by Eq. (1) and
+ * enqueues the generation kernel; returns without waiting.  All-or-nothing:
+ * on error nothing changes and no call id is consumed.  The call creates
+ * connections [*out_first, *out_first + *out_n) in creation order and uses
+ * Philox call id *out_connect_id.  Any output pointer may be NULL. */
+int ng_connect(ng_ctx* ctx, ng_range src, ng_range tgt, const ng_conn_spec* conn,
+               const ng_syn_spec* syn, uint32_t* out_connect_id, uint64_t* out_first,
+               uint64_t* out_n);
+
+/* Many Connect calls at once, with results identical to issuing them one by
+ * one with ng_connect in array order: one generation kernel for all of them.
+ * out_first (may be NULL) receives each call's first connection index. */
+int ng_connect_batch(ng_ctx* ctx, uint32_t n_calls, const ng_range* src, const ng_range* tgt,
+                     const ng_conn_spec* conn, const ng_syn_spec* syn, uint64_t* out_first);
+
+/* Calibration (Sec. 2.2): stable sort of all connections by (source, delay)
+ * and the group index (Eq. (14)).  Asynchronous.  Connecting after a
+ * calibration is allowed; the next calibration sorts everything again, with
+ * the same result as a single calibration at the end. */
+int ng_calibrate(ng_ctx* ctx);
+
+/* Wait for all enqueued work; reports kernel errors. */
+int ng_sync(ng_ctx* ctx);
+
+/* Fill *out with a view of the connections (synchronizes). */
+int ng_get_connections(ng_ctx* ctx, ng_conn_view* out);
+
+/* Copy connections [first, first+count) into caller buffers (host or device
+ * pointers, any may be NULL to skip that array).  Synchronizes. */
+int ng_copy_connections(ng_ctx* ctx, uint64_t first, uint64_t count, uint32_t* src,
+                        uint32_t* tgt, float* w, int16_t* delay);
+
+/* Copy the group index into caller buffers (host or device; NULL skips):
+ * group_ptr [n_nodes + 1] and group_start [n_groups + 1] of the last
+ * calibration.  Synchronizes.  NG_ERR_STATE if not calibrated. */
+int ng_copy_group_index(ng_ctx* ctx, uint32_t* group_ptr, uint32_t* group_start);
+
+/* Calibration schedule: radix digit width in bits (4..11; default 11) and
+ * the number of static ranges the sort passes split the input into (8..65536;
+ * default 1024).  Results do not depend on either; speed does. */
+int ng_set_tuning(ng_ctx* ctx, int radix_bits, uint32_t target_ranges);
+
+/* Arena bytes in use now, at peak, and the largest free extent. */
+int ng_memory_stats(ng_ctx* ctx, uint64_t* used, uint64_t* peak, uint64_t* largest_free);
+
+/* Drop all nodes and connections (the context and its arena stay); the
+ * next call ids start at 0 again.  Asynchronous: pending work still runs. */
+int ng_reset(ng_ctx* ctx);
+
+/* Per-kernel device time: with timing on, every kernel launch of the context
+ * is bracketed by HIP events on its stream.  ng_read_timing synchronizes and
+ * reports, per kernel name, the number of launches and the summed time. */
+typedef struct {
+  char name[24];
+  uint64_t launches;
+  double total_ms;
+} ng_kernel_time;
+int ng_enable_timing(ng_ctx* ctx, int on);
+int ng_read_timing(ng_ctx* ctx, ng_kernel_time* out, int capacity, int* count, int reset);
+
+/* Message of the calling thread's last error ("" if none). */
+const char* ng_last_error(void);
+
+/* --- pure host helpers (no device work) ---------------------------------- */
+
+/* Eq. (1): blocks to add so that n_conns + n_new connections fit in blocks of
+ * size block_size, given n_blocks already allocated (never negative). */
+uint64_t ng_blocks_needed(uint64_t n_conns, uint64_t n_new, uint64_t block_size,
+                          uint64_t n_blocks);
+
+/* Validate a Connect call against n_nodes existing nodes and return the
+ * number of connections it creates (Sec. 2.1). */
+int ng_plan_count(uint32_t n_nodes, ng_range src, ng_range tgt, const ng_conn_spec* conn,
+                  const ng_syn_spec* syn, float h_ms, uint64_t* out_n);
+
+/* Library version string. */
+const char* ng_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NG_H */

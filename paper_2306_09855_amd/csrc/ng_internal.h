@@ -1,0 +1,92 @@
+// Internal interface between the host runtime (ng_runtime.cpp) and the HIP
+// kernels (ng_kernels.hip).  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ng {
+
+// Connection storage: fixed-size blocks of B connections (Sec. 2.1), each
+// block a structure of arrays -- src u32[B] | tgt u32[B] | w f32[B] | delay i16[B].
+constexpr uint64_t kBytesPerConn = 14;
+
+// Delay and weight kinds after host-side planning.
+enum : uint32_t { W_CONST = 0, W_NORMAL = 1, W_UNIFORM = 3 };
+enum : uint32_t { D_CONST = 0, D_UNIFORM_INT = 2, D_UNIFORM_MS = 3 };
+
+// One planned Connect call, as the generation kernels consume it.
+struct GenDesc {
+  uint64_t pos0;     // creation position of synapse 0 (global connection index)
+  uint32_t n_new;    // synapses in this call (< 2^32)
+  uint32_t cid;      // connect call id (Philox counter word 2)
+  uint32_t rule;     // ng_rule
+  uint32_t k;        // K for in/out-degree (N_new < 2^32 bounds it)
+  uint32_t s0, ns, t0, nt;
+  uint32_t w_kind;   // W_*
+  uint32_t d_kind;   // D_*
+  float w_a, w_b;    // CONST: a | NORMAL: mean, sd | UNIFORM: lo, (hi - lo)
+  int32_t d_const;   // D_CONST: steps
+  uint32_t d_lo;     // D_UNIFORM_INT: lo steps
+  uint32_t d_range;  // D_UNIFORM_INT: hi - lo + 1
+  float d_ms_lo, d_ms_width, h;  // D_UNIFORM_MS
+  uint64_t group0;   // batched form: index of this call's first 4-synapse group
+};
+
+// --- generation -----------------------------------------------------------
+hipError_t launch_generate(const GenDesc& d, uint64_t seed, char* const* d_blocks, int log2B,
+                           hipStream_t s);
+// All calls of a batch in one launch; d_descs[n_calls] device array sorted by
+// group0, total_groups = sum of ceil(n_new / 4).
+hipError_t launch_generate_batch(const GenDesc* d_descs, uint32_t n_calls, uint64_t total_groups,
+                                 uint64_t seed, char* const* d_blocks, int log2B, hipStream_t s);
+
+// --- calibration ----------------------------------------------------------
+struct SortGeom {
+  uint64_t n;              // records
+  uint32_t tile;           // records per tile
+  uint32_t tiles_per_range;
+  uint32_t n_ranges;
+  uint32_t ranges_per_xcd; // launch = 8 * ranges_per_xcd workgroups
+};
+
+struct SortIO {
+  // blocked SoA input (first pass) or key/payload arrays
+  char* const* in_blocks;   // device block table, or nullptr
+  const uint32_t* in_keys;
+  const uint2* in_pay;      // (tgt, w bits)
+  // blocked SoA output (last pass) or key/payload arrays
+  char* const* out_blocks;
+  uint32_t* out_keys;
+  uint2* out_pay;
+  int log2B;
+  uint32_t dbits;           // key = src << dbits | delay
+};
+
+int sort_tile_size(int radix_bits);
+hipError_t launch_upsweep(const SortGeom& g, const SortIO& io, int radix_bits, uint32_t shift,
+                          uint32_t* counts, hipStream_t s);
+hipError_t launch_downsweep(const SortGeom& g, const SortIO& io, int radix_bits, uint32_t shift,
+                            const uint32_t* offsets, hipStream_t s);
+
+// Exclusive scan of n u32 values (in may equal out).  tmp needs
+// scan_tmp_words(n) words.  If total != nullptr the sum is written there.
+uint64_t scan_tmp_words(uint64_t n);
+hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* tmp,
+                                 uint32_t* total, hipStream_t s);
+
+// tab[first + k] = ptrs[k] for k < count <= 8
+hipError_t launch_set_ptrs(char** tab, uint32_t first, uint32_t count, const uint64_t* ptrs,
+                           hipStream_t s);
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, uint64_t n, hipStream_t s);
+
+// Connection-group index over sorted blocked SoA (Sec. 2.2, Eq. (14)).
+//   tile_flags[n_tiles] (scratch), G[n_nodes+1] zeroed before the call.
+uint32_t gi_tile_size();
+hipError_t launch_group_flags(char* const* blocks, int log2B, uint64_t n, uint32_t* tile_flags,
+                              uint32_t* G, hipStream_t s);
+hipError_t launch_group_write(char* const* blocks, int log2B, uint64_t n,
+                              const uint32_t* tile_base, uint32_t* group_start, hipStream_t s);
+
+}  // namespace ng

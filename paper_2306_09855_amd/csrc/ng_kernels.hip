@@ -1,0 +1,783 @@
+// HIP kernels for gfx950 (MI355X): connection generation and calibration.
+//
+// Generation (Sec. 2.1 of Golosio et al.): one lane produces four
+// consecutive synapses of a Connect call -- Philox4x32-10 words in
+// registers, the rule's index formulas (Eqs. (4)-(13)), delay and weight
+// transforms -- and stores them into the block-structured SoA storage.
+//
+// Calibration (Sec. 2.2): a stable LSD radix sort by key = src << dbits |
+// delay, built from reduce-then-scan passes over static ranges:
+//   upsweep    per-range digit histogram (LDS atomics)
+//   scan       device-wide exclusive scan of the digit-major count matrix
+//   downsweep  per tile: stable wave64 ballot ranking, LDS staging, then
+//              runs of equal digits written to their global positions
+// Ranges are laid out XCD-aware: workgroup w runs on XCD w % 8, and each XCD
+// gets a contiguous span of ranges, so the output runs of neighbouring
+// ranges meet in one L2.  Then the connection-group index (Eq. (14)).
+#include "ng_internal.h"
+
+namespace ng {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11)
+// ---------------------------------------------------------------------------
+constexpr uint32_t kPhiloxMul0 = 0xD2511F53u;
+constexpr uint32_t kPhiloxMul1 = 0xCD9E8D57u;
+constexpr uint32_t kWeyl0 = 0x9E3779B9u;
+constexpr uint32_t kWeyl1 = 0xBB67AE85u;
+
+__device__ __forceinline__ void philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                         uint32_t k0, uint32_t k1, uint32_t* out) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t a = (uint64_t)c0 * kPhiloxMul0;
+    const uint64_t b = (uint64_t)c2 * kPhiloxMul1;
+    const uint32_t n0 = (uint32_t)(b >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(a >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)b;
+    c3 = (uint32_t)a;
+    c0 = n0;
+    c2 = n2;
+    k0 += kWeyl0;
+    k1 += kWeyl1;
+  }
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
+// word block j of stream s of call cid
+__device__ __forceinline__ void philox_block(uint64_t j, uint32_t cid, uint32_t s, uint32_t key0,
+                                             uint32_t key1, uint32_t* out) {
+  philox10((uint32_t)j, (uint32_t)(j >> 32), cid, s, key0, key1, out);
+}
+
+// rand(N): floor(x * N / 2^32)
+__device__ __forceinline__ uint32_t rand_below(uint32_t x, uint32_t n) { return __umulhi(x, n); }
+
+constexpr float kInv2p24 = 5.9604644775390625e-08f;  // 2^-24
+
+enum { R_ONE_TO_ONE = 0, R_ALL_TO_ALL = 1, R_INDEG = 2, R_OUTDEG = 3, R_TOTAL = 4 };
+
+template <int RULE>
+struct RuleDraws {
+  static constexpr int value = RULE == R_TOTAL ? 2 : (RULE == R_INDEG || RULE == R_OUTDEG) ? 1 : 0;
+};
+
+struct Quad {
+  uint32_t s[4], t[4];
+  float w[4];
+  int32_t d[4];
+};
+
+// Synapses i0..i0+3 of one call (i0 = 4g).  W0 = stream-0 words per synapse.
+template <int RULE, bool DRAND>
+__device__ __forceinline__ void gen_quad(const GenDesc& d, uint32_t g, uint32_t key0, uint32_t key1,
+                                         Quad& q) {
+  constexpr int NIDX = RuleDraws<RULE>::value;
+  constexpr int W0 = NIDX + (DRAND ? 1 : 0);
+  const uint32_t i0 = g << 2;
+  uint32_t x[W0 > 0 ? 4 * W0 : 1];
+#pragma unroll
+  for (int m = 0; m < W0; ++m)
+    philox_block((uint64_t)g * W0 + m, d.cid, 0u, key0, key1, &x[4 * m]);
+
+  // source / target indices, Eqs. (4)-(13)
+  if constexpr (RULE == R_ONE_TO_ONE) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      q.s[r] = d.s0 + i0 + r;
+      q.t[r] = d.t0 + i0 + r;
+    }
+  } else if constexpr (RULE == R_ALL_TO_ALL) {
+    uint32_t a = i0 / d.nt, b = i0 - a * d.nt;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      q.s[r] = d.s0 + a;
+      q.t[r] = d.t0 + b;
+      if (++b == d.nt) { b = 0; ++a; }
+    }
+  } else if constexpr (RULE == R_OUTDEG) {
+    uint32_t a = i0 / d.k, b = i0 - a * d.k;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      q.s[r] = d.s0 + a;
+      q.t[r] = d.t0 + rand_below(x[r * W0], d.nt);
+      if (++b == d.k) { b = 0; ++a; }
+    }
+  } else if constexpr (RULE == R_INDEG) {
+    uint32_t a = i0 / d.k, b = i0 - a * d.k;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      q.s[r] = d.s0 + rand_below(x[r * W0], d.ns);
+      q.t[r] = d.t0 + a;
+      if (++b == d.k) { b = 0; ++a; }
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      q.s[r] = d.s0 + rand_below(x[r * W0], d.ns);
+      q.t[r] = d.t0 + rand_below(x[r * W0 + 1], d.nt);
+    }
+  }
+
+  // delays (Sec. 2.1): integer steps, or ms -> steps with a one-step minimum
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    if constexpr (DRAND) {
+      const uint32_t xd = x[r * W0 + NIDX];
+      if (d.d_kind == D_UNIFORM_INT) {
+        q.d[r] = (int32_t)(d.d_lo + rand_below(xd, d.d_range));
+      } else {
+        const float u = (float)(xd >> 8) * kInv2p24;
+        const float ms = __fmaf_rn(d.d_ms_width, u, d.d_ms_lo);
+        const float steps = rintf(__fdiv_rn(ms, d.h));
+        q.d[r] = steps < 1.0f ? 1 : (int32_t)steps;
+      }
+    } else {
+      q.d[r] = d.d_const;
+    }
+  }
+
+  // weights from stream 1, words 2i and 2i+1
+  if (d.w_kind == W_CONST) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) q.w[r] = d.w_a;
+  } else {
+    uint32_t y[8];
+    philox_block(2ull * g, d.cid, 1u, key0, key1, &y[0]);
+    philox_block(2ull * g + 1, d.cid, 1u, key0, key1, &y[4]);
+    if (d.w_kind == W_NORMAL) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float u1 = (float)((y[2 * r] >> 8) + 1u) * kInv2p24;  // (0, 1]
+        const float u2 = (float)(y[2 * r + 1] >> 8) * kInv2p24;     // [0, 1)
+        const float rad = __fsqrt_rn(-2.0f * logf(u1));
+        const float z = rad * cospif(2.0f * u2);
+        q.w[r] = __fmaf_rn(d.w_b, z, d.w_a);
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float u = (float)(y[2 * r] >> 8) * kInv2p24;
+        q.w[r] = __fmaf_rn(d.w_b, u, d.w_a);
+      }
+    }
+  }
+}
+
+// Block layout: src u32[B] | tgt u32[B] | w f32[B] | delay i16[B]
+__device__ __forceinline__ void store_one(char* const* __restrict__ blocks, int log2B, uint64_t p,
+                                          uint32_t s, uint32_t t, float w, int32_t dl) {
+  const uint64_t B = 1ull << log2B;
+  char* base = blocks[p >> log2B];
+  const uint64_t o = p & (B - 1);
+  reinterpret_cast<uint32_t*>(base)[o] = s;
+  reinterpret_cast<uint32_t*>(base + 4 * B)[o] = t;
+  reinterpret_cast<float*>(base + 8 * B)[o] = w;
+  reinterpret_cast<int16_t*>(base + 12 * B)[o] = (int16_t)dl;
+}
+
+__device__ __forceinline__ void store_quad(char* const* __restrict__ blocks, int log2B, uint64_t p0,
+                                           uint32_t nvalid, const Quad& q) {
+  if (nvalid == 4 && (p0 & 3) == 0) {
+    const uint64_t B = 1ull << log2B;
+    char* base = blocks[p0 >> log2B];
+    const uint64_t o = p0 & (B - 1);
+    *reinterpret_cast<uint4*>(base + 4 * o) = make_uint4(q.s[0], q.s[1], q.s[2], q.s[3]);
+    *reinterpret_cast<uint4*>(base + 4 * B + 4 * o) = make_uint4(q.t[0], q.t[1], q.t[2], q.t[3]);
+    *reinterpret_cast<float4*>(base + 8 * B + 4 * o) = make_float4(q.w[0], q.w[1], q.w[2], q.w[3]);
+    const uint32_t d01 = ((uint32_t)q.d[0] & 0xFFFFu) | ((uint32_t)q.d[1] << 16);
+    const uint32_t d23 = ((uint32_t)q.d[2] & 0xFFFFu) | ((uint32_t)q.d[3] << 16);
+    *reinterpret_cast<uint2*>(base + 12 * B + 2 * o) = make_uint2(d01, d23);
+  } else {
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if ((uint32_t)r < nvalid) store_one(blocks, log2B, p0 + r, q.s[r], q.t[r], q.w[r], q.d[r]);
+  }
+}
+
+constexpr int kGenThreads = 256;
+
+template <int RULE, bool DRAND>
+__global__ __launch_bounds__(kGenThreads) void k_generate(GenDesc d, uint32_t key0, uint32_t key1,
+                                                          char* const* __restrict__ blocks, int log2B) {
+  const uint32_t ngroups = (uint32_t)(((uint64_t)d.n_new + 3) >> 2);
+  for (uint32_t g = blockIdx.x * kGenThreads + threadIdx.x; g < ngroups;
+       g += gridDim.x * kGenThreads) {
+    Quad q;
+    gen_quad<RULE, DRAND>(d, g, key0, key1, q);
+    const uint32_t i0 = g << 2;
+    store_quad(blocks, log2B, d.pos0 + i0, min(4u, d.n_new - i0), q);
+  }
+}
+
+template <bool DRAND>
+__device__ __forceinline__ void gen_any(const GenDesc& d, uint32_t g, uint32_t key0, uint32_t key1,
+                                        Quad& q) {
+  switch (d.rule) {
+    case R_ONE_TO_ONE: gen_quad<R_ONE_TO_ONE, DRAND>(d, g, key0, key1, q); break;
+    case R_ALL_TO_ALL: gen_quad<R_ALL_TO_ALL, DRAND>(d, g, key0, key1, q); break;
+    case R_INDEG: gen_quad<R_INDEG, DRAND>(d, g, key0, key1, q); break;
+    case R_OUTDEG: gen_quad<R_OUTDEG, DRAND>(d, g, key0, key1, q); break;
+    default: gen_quad<R_TOTAL, DRAND>(d, g, key0, key1, q); break;
+  }
+}
+
+// Batched form: a grid-stride loop over the 4-synapse groups of all calls;
+// each lane finds its call by binary search over the calls' first groups.
+__global__ __launch_bounds__(kGenThreads) void k_generate_batch(const GenDesc* __restrict__ descs,
+                                                                uint32_t n_calls, uint64_t total_groups,
+                                                                uint32_t key0, uint32_t key1,
+                                                                char* const* __restrict__ blocks,
+                                                                int log2B) {
+  for (uint64_t gg = (uint64_t)blockIdx.x * kGenThreads + threadIdx.x; gg < total_groups;
+       gg += (uint64_t)gridDim.x * kGenThreads) {
+    uint32_t lo = 0, hi = n_calls - 1;
+    while (lo < hi) {  // last call with group0 <= gg
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (descs[mid].group0 <= gg) lo = mid; else hi = mid - 1;
+    }
+    const GenDesc d = descs[lo];
+    const uint32_t g = (uint32_t)(gg - d.group0);
+    Quad q;
+    if (d.d_kind == D_CONST) gen_any<false>(d, g, key0, key1, q);
+    else gen_any<true>(d, g, key0, key1, q);
+    const uint32_t i0 = g << 2;
+    store_quad(blocks, log2B, d.pos0 + i0, min(4u, d.n_new - i0), q);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Workgroup scan helpers (256 threads = 4 waves of 64)
+// ---------------------------------------------------------------------------
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t n = __shfl_up(v, o, 64);
+    if (lane >= o) v += n;
+  }
+  return v;
+}
+
+// Exclusive scan of one value per thread across the workgroup; returns the
+// thread's exclusive prefix and sets *total.  s_tmp holds kWaves words.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s_tmp,
+                                                         uint32_t* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t inc = wave_inclusive_scan(v);
+  if (lane == 63) s_tmp[wave] = inc;
+  __syncthreads();
+  uint32_t wave_off = 0, sum = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) {
+    const uint32_t t = s_tmp[w];
+    if (w < wave) wave_off += t;
+    sum += t;
+  }
+  __syncthreads();
+  *total = sum;
+  return wave_off + inc - v;
+}
+
+// ---------------------------------------------------------------------------
+// Radix sort passes
+// ---------------------------------------------------------------------------
+constexpr int kItems = 16;
+constexpr int kTile = kThreads * kItems;  // 4096 records
+
+__device__ __forceinline__ int range_index(const SortGeom& g) {
+  const uint32_t w = blockIdx.x;
+  const uint32_t r = (w & 7u) * g.ranges_per_xcd + (w >> 3);
+  return r < g.n_ranges ? (int)r : -1;
+}
+
+template <bool IN_BLOCKED>
+__device__ __forceinline__ uint32_t load_key(const SortIO& io, uint64_t j) {
+  if constexpr (IN_BLOCKED) {
+    const uint64_t B = 1ull << io.log2B;
+    const char* base = io.in_blocks[j >> io.log2B];
+    const uint64_t o = j & (B - 1);
+    const uint32_t s = reinterpret_cast<const uint32_t*>(base)[o];
+    const uint32_t dl = (uint16_t)reinterpret_cast<const int16_t*>(base + 12 * B)[o];
+    return (s << io.dbits) | dl;
+  } else {
+    return io.in_keys[j];
+  }
+}
+
+template <int RB, bool IN_BLOCKED>
+__global__ __launch_bounds__(kThreads) void k_upsweep(SortGeom g, SortIO io, uint32_t shift,
+                                                      uint32_t nbits, uint32_t* __restrict__ counts) {
+  constexpr int NB = 1 << RB;
+  __shared__ uint32_t hist[NB];
+  const int r = range_index(g);
+  if (r < 0) return;
+  const uint32_t nd = 1u << nbits, mask = nd - 1;
+  for (uint32_t d = threadIdx.x; d < nd; d += kThreads) hist[d] = 0;
+  __syncthreads();
+  const uint64_t start = (uint64_t)r * g.tiles_per_range * kTile;
+  const uint64_t end = min(start + (uint64_t)g.tiles_per_range * kTile, g.n);
+  for (uint64_t base = start; base < end; base += kTile) {
+    uint32_t key[kItems];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      const uint64_t j = base + k * kThreads + threadIdx.x;
+      key[k] = j < end ? load_key<IN_BLOCKED>(io, j) : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      const uint64_t j = base + k * kThreads + threadIdx.x;
+      if (j < end) atomicAdd(&hist[(key[k] >> shift) & mask], 1u);
+    }
+  }
+  __syncthreads();
+  for (uint32_t d = threadIdx.x; d < nd; d += kThreads) counts[(uint64_t)d * g.n_ranges + r] = hist[d];
+}
+
+template <int RB, bool IN_BLOCKED, bool OUT_BLOCKED>
+__global__ __launch_bounds__(kThreads) void k_downsweep(SortGeom g, SortIO io, uint32_t shift,
+                                                        uint32_t nbits,
+                                                        const uint32_t* __restrict__ offsets) {
+  constexpr int NB = 1 << RB;
+  __shared__ uint32_t s_keys[kTile];
+  __shared__ uint2 s_pay[kTile];
+  __shared__ uint32_t s_wh[kWaves][NB];  // per-wave digit counts, then per-wave prefixes
+  __shared__ uint32_t s_start[NB + 1];   // tile-local digit starts
+  __shared__ uint32_t s_run[NB];         // next global position per digit
+  __shared__ uint32_t s_tmp[kWaves];
+
+  const int r = range_index(g);
+  if (r < 0) return;
+  const uint32_t nd = 1u << nbits, mask = nd - 1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (uint32_t d = threadIdx.x; d < nd; d += kThreads) {
+    s_run[d] = offsets[(uint64_t)d * g.n_ranges + r];
+#pragma unroll
+    for (int v = 0; v < kWaves; ++v) s_wh[v][d] = 0;
+  }
+  __syncthreads();
+
+  const uint64_t start = (uint64_t)r * g.tiles_per_range * kTile;
+  const uint64_t end = min(start + (uint64_t)g.tiles_per_range * kTile, g.n);
+  const uint64_t B = 1ull << io.log2B;
+  const uint32_t dmask = (1u << io.dbits) - 1;
+
+  for (uint64_t base = start; base < end; base += kTile) {
+    const uint32_t cnt = (uint32_t)min((uint64_t)kTile, end - base);
+    // wave w ranks tile records [w*1024, (w+1)*1024) in 16 batches of 64, in order
+    uint32_t key[kItems];
+    uint2 pay[kItems];
+    if constexpr (IN_BLOCKED) {
+      const char* blk = io.in_blocks[base >> io.log2B];
+      const uint64_t o0 = base & (B - 1);
+      const uint32_t* src = reinterpret_cast<const uint32_t*>(blk) + o0;
+      const uint32_t* tgt = reinterpret_cast<const uint32_t*>(blk + 4 * B) + o0;
+      const uint32_t* wb = reinterpret_cast<const uint32_t*>(blk + 8 * B) + o0;
+      const int16_t* del = reinterpret_cast<const int16_t*>(blk + 12 * B) + o0;
+#pragma unroll
+      for (int k = 0; k < kItems; ++k) {
+        const uint32_t lj = (uint32_t)(wave * kItems * 64 + k * 64 + lane);
+        if (lj < cnt) {
+          key[k] = (src[lj] << io.dbits) | (uint16_t)del[lj];
+          pay[k] = make_uint2(tgt[lj], wb[lj]);
+        } else {
+          key[k] = 0;
+          pay[k] = make_uint2(0, 0);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < kItems; ++k) {
+        const uint32_t lj = (uint32_t)(wave * kItems * 64 + k * 64 + lane);
+        if (lj < cnt) {
+          key[k] = io.in_keys[base + lj];
+          pay[k] = io.in_pay[base + lj];
+        } else {
+          key[k] = 0;
+          pay[k] = make_uint2(0, 0);
+        }
+      }
+    }
+
+    uint32_t rank[kItems];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      const uint32_t lj = (uint32_t)(wave * kItems * 64 + k * 64 + lane);
+      const bool valid = lj < cnt;
+      const uint32_t dg = (key[k] >> shift) & mask;
+      uint64_t peers = __ballot(valid);
+#pragma unroll
+      for (int b = 0; b < RB; ++b) {
+        if ((uint32_t)b < nbits) {
+          const bool bit = (dg >> b) & 1u;
+          const uint64_t m = __ballot(bit);
+          peers &= bit ? m : ~m;
+        }
+      }
+      const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+          (uint32_t)(peers >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
+      const uint32_t tot = (uint32_t)__popcll(peers);
+      uint32_t prev = 0;
+      if (valid) prev = s_wh[wave][dg];
+      if (valid && below == 0) s_wh[wave][dg] = prev + tot;
+      rank[k] = prev + below;
+    }
+    __syncthreads();
+
+    // per digit: prefixes over waves and the tile total
+    for (uint32_t d = threadIdx.x; d < nd; d += kThreads) {
+      uint32_t acc = 0;
+#pragma unroll
+      for (int v = 0; v < kWaves; ++v) {
+        const uint32_t c = s_wh[v][d];
+        s_wh[v][d] = acc;
+        acc += c;
+      }
+      s_start[d] = acc;
+    }
+    __syncthreads();
+    {  // exclusive scan of the tile's digit totals; each thread owns a run of digits
+      const uint32_t per = (nd + kThreads - 1) / kThreads;
+      const uint32_t d0 = threadIdx.x * per;
+      uint32_t local = 0;
+      for (uint32_t d = d0; d < min(d0 + per, nd); ++d) local += s_start[d];
+      uint32_t total;
+      uint32_t run = block_exclusive_scan(local, s_tmp, &total);
+      for (uint32_t d = d0; d < min(d0 + per, nd); ++d) {
+        const uint32_t c = s_start[d];
+        s_start[d] = run;
+        run += c;
+      }
+      if (threadIdx.x == 0) s_start[nd] = total;
+    }
+    __syncthreads();
+
+    // stable placement inside the tile
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      const uint32_t lj = (uint32_t)(wave * kItems * 64 + k * 64 + lane);
+      if (lj < cnt) {
+        const uint32_t dg = (key[k] >> shift) & mask;
+        const uint32_t lp = s_start[dg] + s_wh[wave][dg] + rank[k];
+        s_keys[lp] = key[k];
+        s_pay[lp] = pay[k];
+      }
+    }
+    __syncthreads();
+
+    // runs of equal digits go to consecutive global positions
+#pragma unroll 4
+    for (int k = 0; k < kItems; ++k) {
+      const uint32_t lp = (uint32_t)(k * kThreads + threadIdx.x);
+      if (lp < cnt) {
+        const uint32_t kk = s_keys[lp];
+        const uint2 pp = s_pay[lp];
+        const uint32_t dg = (kk >> shift) & mask;
+        const uint64_t dest = (uint64_t)s_run[dg] + (lp - s_start[dg]);
+        if constexpr (OUT_BLOCKED) {
+          char* blk = io.out_blocks[dest >> io.log2B];
+          const uint64_t o = dest & (B - 1);
+          reinterpret_cast<uint32_t*>(blk)[o] = kk >> io.dbits;
+          reinterpret_cast<uint32_t*>(blk + 4 * B)[o] = pp.x;
+          reinterpret_cast<uint32_t*>(blk + 8 * B)[o] = pp.y;
+          reinterpret_cast<int16_t*>(blk + 12 * B)[o] = (int16_t)(kk & dmask);
+        } else {
+          io.out_keys[dest] = kk;
+          io.out_pay[dest] = pp;
+        }
+      }
+    }
+    __syncthreads();
+    for (uint32_t d = threadIdx.x; d < nd; d += kThreads) {
+      s_run[d] += s_start[d + 1] - s_start[d];
+#pragma unroll
+      for (int v = 0; v < kWaves; ++v) s_wh[v][d] = 0;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Device-wide exclusive scan (reduce, scan of partials, downsweep)
+// ---------------------------------------------------------------------------
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kThreads * kScanItems;
+
+__global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t* __restrict__ in, uint64_t n,
+                                                          uint32_t* __restrict__ partial) {
+  __shared__ uint32_t s_tmp[kWaves];
+  const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+  uint32_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const uint64_t j = base + k * kThreads + threadIdx.x;
+    if (j < n) sum += in[j];
+  }
+  uint32_t total;
+  block_exclusive_scan(sum, s_tmp, &total);
+  if (threadIdx.x == 0) partial[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_partials(uint32_t* __restrict__ partial, uint64_t nb,
+                                                            uint32_t* __restrict__ total_out) {
+  __shared__ uint32_t s_tmp[kWaves];
+  uint32_t carry = 0;
+  for (uint64_t base = 0; base < nb; base += kThreads) {
+    const uint64_t j = base + threadIdx.x;
+    const uint32_t v = j < nb ? partial[j] : 0u;
+    uint32_t total;
+    const uint32_t ex = block_exclusive_scan(v, s_tmp, &total);
+    if (j < nb) partial[j] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0 && total_out) *total_out = carry;
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_down(const uint32_t* in, uint32_t* out, uint64_t n,
+                                                        const uint32_t* __restrict__ partial) {
+  __shared__ uint32_t s_tmp[kWaves];
+  const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const uint64_t j = base + k;
+    v[k] = j < n ? in[j] : 0u;
+    sum += v[k];
+  }
+  uint32_t total;
+  uint32_t run = partial[blockIdx.x] + block_exclusive_scan(sum, s_tmp, &total);
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const uint64_t j = base + k;
+    if (j < n) out[j] = run;
+    run += v[k];
+  }
+}
+
+__global__ void k_set_ptrs(char** tab, uint32_t first, uint32_t count, uint64_t p0, uint64_t p1,
+                           uint64_t p2, uint64_t p3, uint64_t p4, uint64_t p5, uint64_t p6,
+                           uint64_t p7) {
+  const uint64_t v[8] = {p0, p1, p2, p3, p4, p5, p6, p7};
+  const uint32_t t = threadIdx.x;
+  if (t < count && t < 8) tab[first + t] = reinterpret_cast<char*>(v[t]);
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t value, uint64_t n) {
+  for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+       j += (uint64_t)gridDim.x * blockDim.x)
+    p[j] = value;
+}
+
+// ---------------------------------------------------------------------------
+// Connection-group index (Sec. 2.2): a connection opens a group when its
+// source or delay differs from those of the previous connection.
+// ---------------------------------------------------------------------------
+constexpr int kGiItems = 16;
+constexpr int kGiTile = kThreads * kGiItems;
+
+__device__ __forceinline__ void load_src_delay(char* const* __restrict__ blocks, int log2B, uint64_t j,
+                                               uint32_t& s, int32_t& dl) {
+  const uint64_t B = 1ull << log2B;
+  const char* base = blocks[j >> log2B];
+  const uint64_t o = j & (B - 1);
+  s = reinterpret_cast<const uint32_t*>(base)[o];
+  dl = reinterpret_cast<const int16_t*>(base + 12 * B)[o];
+}
+
+__device__ __forceinline__ bool opens_group(char* const* __restrict__ blocks, int log2B, uint64_t j,
+                                            uint32_t& s) {
+  int32_t dl;
+  load_src_delay(blocks, log2B, j, s, dl);
+  if (j == 0) return true;
+  uint32_t ps;
+  int32_t pd;
+  load_src_delay(blocks, log2B, j - 1, ps, pd);
+  return ps != s || pd != dl;
+}
+
+__global__ __launch_bounds__(kThreads) void k_group_flags(char* const* __restrict__ blocks, int log2B,
+                                                          uint64_t n, uint32_t* __restrict__ tile_flags,
+                                                          uint32_t* __restrict__ G) {
+  __shared__ uint32_t s_tmp[kWaves];
+  const uint64_t base = (uint64_t)blockIdx.x * kGiTile + (uint64_t)threadIdx.x * kGiItems;
+  uint32_t c = 0;
+  for (int k = 0; k < kGiItems; ++k) {
+    const uint64_t j = base + k;
+    if (j < n) {
+      uint32_t s;
+      if (opens_group(blocks, log2B, j, s)) {
+        ++c;
+        atomicAdd(&G[s], 1u);
+      }
+    }
+  }
+  uint32_t total;
+  block_exclusive_scan(c, s_tmp, &total);
+  if (threadIdx.x == 0) tile_flags[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kThreads) void k_group_write(char* const* __restrict__ blocks, int log2B,
+                                                          uint64_t n, const uint32_t* __restrict__ tile_base,
+                                                          uint32_t* __restrict__ group_start) {
+  __shared__ uint32_t s_tmp[kWaves];
+  const uint64_t base = (uint64_t)blockIdx.x * kGiTile + (uint64_t)threadIdx.x * kGiItems;
+  uint32_t f = 0;  // bit k: position base + k opens a group
+  for (int k = 0; k < kGiItems; ++k) {
+    const uint64_t j = base + k;
+    uint32_t s;
+    if (j < n && opens_group(blocks, log2B, j, s)) f |= 1u << k;
+  }
+  uint32_t total;
+  uint32_t gidx = tile_base[blockIdx.x] + block_exclusive_scan((uint32_t)__popc(f), s_tmp, &total);
+  for (int k = 0; k < kGiItems; ++k) {
+    const uint64_t j = base + k;
+    if (f & (1u << k)) group_start[gidx++] = (uint32_t)j;
+    if (j + 1 == n) group_start[gidx] = (uint32_t)n;  // group_start[G] = n
+  }
+}
+
+template <int RB>
+hipError_t upsweep_rb(const SortGeom& g, const SortIO& io, uint32_t shift, uint32_t nbits,
+                      uint32_t* counts, hipStream_t s) {
+  const dim3 grid(8 * g.ranges_per_xcd);
+  if (io.in_blocks)
+    hipLaunchKernelGGL((k_upsweep<RB, true>), grid, dim3(kThreads), 0, s, g, io, shift, nbits, counts);
+  else
+    hipLaunchKernelGGL((k_upsweep<RB, false>), grid, dim3(kThreads), 0, s, g, io, shift, nbits, counts);
+  return hipGetLastError();
+}
+
+template <int RB>
+hipError_t downsweep_rb(const SortGeom& g, const SortIO& io, uint32_t shift, uint32_t nbits,
+                        const uint32_t* offsets, hipStream_t s) {
+  const dim3 grid(8 * g.ranges_per_xcd);
+  const bool ib = io.in_blocks != nullptr, ob = io.out_blocks != nullptr;
+  if (ib && ob)
+    hipLaunchKernelGGL((k_downsweep<RB, true, true>), grid, dim3(kThreads), 0, s, g, io, shift, nbits, offsets);
+  else if (ib)
+    hipLaunchKernelGGL((k_downsweep<RB, true, false>), grid, dim3(kThreads), 0, s, g, io, shift, nbits, offsets);
+  else if (ob)
+    hipLaunchKernelGGL((k_downsweep<RB, false, true>), grid, dim3(kThreads), 0, s, g, io, shift, nbits, offsets);
+  else
+    hipLaunchKernelGGL((k_downsweep<RB, false, false>), grid, dim3(kThreads), 0, s, g, io, shift, nbits, offsets);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launch wrappers
+// ---------------------------------------------------------------------------
+template <int RULE>
+static void gen_launch(const GenDesc& d, uint32_t k0, uint32_t k1, char* const* blocks, int log2B,
+                       dim3 grid, hipStream_t s) {
+  if (d.d_kind == D_CONST)
+    hipLaunchKernelGGL((k_generate<RULE, false>), grid, dim3(kGenThreads), 0, s, d, k0, k1, blocks, log2B);
+  else
+    hipLaunchKernelGGL((k_generate<RULE, true>), grid, dim3(kGenThreads), 0, s, d, k0, k1, blocks, log2B);
+}
+
+static uint32_t gen_grid(uint64_t groups) {
+  const uint64_t need = (groups + kGenThreads - 1) / kGenThreads;
+  return (uint32_t)(need < 16384 ? (need ? need : 1) : 16384);
+}
+
+hipError_t launch_generate(const GenDesc& d, uint64_t seed, char* const* d_blocks, int log2B,
+                           hipStream_t s) {
+  if (d.n_new == 0) return hipSuccess;
+  const dim3 grid(gen_grid(((uint64_t)d.n_new + 3) / 4));
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  switch (d.rule) {
+    case R_ONE_TO_ONE: gen_launch<R_ONE_TO_ONE>(d, k0, k1, d_blocks, log2B, grid, s); break;
+    case R_ALL_TO_ALL: gen_launch<R_ALL_TO_ALL>(d, k0, k1, d_blocks, log2B, grid, s); break;
+    case R_INDEG: gen_launch<R_INDEG>(d, k0, k1, d_blocks, log2B, grid, s); break;
+    case R_OUTDEG: gen_launch<R_OUTDEG>(d, k0, k1, d_blocks, log2B, grid, s); break;
+    case R_TOTAL: gen_launch<R_TOTAL>(d, k0, k1, d_blocks, log2B, grid, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_generate_batch(const GenDesc* d_descs, uint32_t n_calls, uint64_t total_groups,
+                                 uint64_t seed, char* const* d_blocks, int log2B, hipStream_t s) {
+  if (n_calls == 0 || total_groups == 0) return hipSuccess;
+  const dim3 grid(gen_grid(total_groups));
+  hipLaunchKernelGGL(k_generate_batch, grid, dim3(kGenThreads), 0, s, d_descs, n_calls, total_groups,
+                     (uint32_t)seed, (uint32_t)(seed >> 32), d_blocks, log2B);
+  return hipGetLastError();
+}
+
+int sort_tile_size(int) { return kTile; }
+
+hipError_t launch_upsweep(const SortGeom& g, const SortIO& io, int radix_bits, uint32_t shift,
+                          uint32_t* counts, hipStream_t s) {
+  (void)radix_bits;
+  return radix_bits <= 8 ? upsweep_rb<8>(g, io, shift, (uint32_t)radix_bits, counts, s)
+                         : upsweep_rb<11>(g, io, shift, (uint32_t)radix_bits, counts, s);
+}
+
+hipError_t launch_downsweep(const SortGeom& g, const SortIO& io, int radix_bits, uint32_t shift,
+                            const uint32_t* offsets, hipStream_t s) {
+  return radix_bits <= 8 ? downsweep_rb<8>(g, io, shift, (uint32_t)radix_bits, offsets, s)
+                         : downsweep_rb<11>(g, io, shift, (uint32_t)radix_bits, offsets, s);
+}
+
+uint64_t scan_tmp_words(uint64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+
+hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* tmp,
+                                 uint32_t* total, hipStream_t s) {
+  const uint64_t nb = (n + kScanTile - 1) / kScanTile;
+  if (nb == 0) {
+    if (total) hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, total, 0u, (uint64_t)1);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_scan_reduce, dim3((uint32_t)nb), dim3(kThreads), 0, s, in, n, tmp);
+  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kThreads), 0, s, tmp, nb, total);
+  hipLaunchKernelGGL(k_scan_down, dim3((uint32_t)nb), dim3(kThreads), 0, s, in, out, n, tmp);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_ptrs(char** tab, uint32_t first, uint32_t count, const uint64_t* v,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_set_ptrs, dim3(1), dim3(64), 0, s, tab, first, count, v[0], v[1], v[2], v[3],
+                     v[4], v[5], v[6], v[7]);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, uint64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  uint64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_fill_u32, dim3((uint32_t)blocks), dim3(256), 0, s, p, value, n);
+  return hipGetLastError();
+}
+
+uint32_t gi_tile_size() { return kGiTile; }
+
+hipError_t launch_group_flags(char* const* blocks, int log2B, uint64_t n, uint32_t* tile_flags,
+                              uint32_t* G, hipStream_t s) {
+  const uint64_t nt = (n + kGiTile - 1) / kGiTile;
+  if (nt == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_group_flags, dim3((uint32_t)nt), dim3(kThreads), 0, s, blocks, log2B, n,
+                     tile_flags, G);
+  return hipGetLastError();
+}
+
+hipError_t launch_group_write(char* const* blocks, int log2B, uint64_t n, const uint32_t* tile_base,
+                              uint32_t* group_start, hipStream_t s) {
+  const uint64_t nt = (n + kGiTile - 1) / kGiTile;
+  if (nt == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_group_write, dim3((uint32_t)nt), dim3(kThreads), 0, s, blocks, log2B, n,
+                     tile_base, group_start);
+  return hipGetLastError();
+}
+
+}  // namespace ng

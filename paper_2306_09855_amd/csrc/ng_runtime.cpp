@@ -1,0 +1,796 @@
+// Host runtime of the connectivity builder: context, arena sub-allocator,
+// Connect planning (Sec. 2.1: rule counts, Eq. (1) blocks, Eqs. (2)-(3)
+// numbering) and calibration orchestration (Sec. 2.2).  All device work is
+// enqueued on the caller's stream; nothing here computes connections on the
+// host.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/ng.h"
+#include "ng_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+constexpr uint64_t kAlign = 256;
+
+// First-fit sub-allocator over the caller's arena (host bookkeeping only).
+class Arena {
+ public:
+  void init(char* base, uint64_t size) {
+    base_ = base;
+    size_ = size;
+    free_.clear();
+    if (size) free_[0] = size;
+  }
+  char* alloc(uint64_t bytes) {
+    bytes = round_up(bytes ? bytes : 1);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        const uint64_t off = it->first, sz = it->second;
+        free_.erase(it);
+        if (sz > bytes) free_[off + bytes] = sz - bytes;
+        used_ += bytes;
+        peak_ = std::max(peak_, used_);
+        return base_ + off;
+      }
+    }
+    return nullptr;
+  }
+  void release(char* p, uint64_t bytes) {
+    if (!p) return;
+    bytes = round_up(bytes ? bytes : 1);
+    uint64_t off = (uint64_t)(p - base_);
+    used_ -= bytes;
+    auto next = free_.lower_bound(off);
+    if (next != free_.end() && off + bytes == next->first) {
+      bytes += next->second;
+      next = free_.erase(next);
+    }
+    if (next != free_.begin()) {
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == off) {
+        prev->second += bytes;
+        return;
+      }
+    }
+    free_[off] = bytes;
+  }
+  uint64_t used() const { return used_; }
+  uint64_t peak() const { return peak_; }
+  uint64_t largest_free() const {
+    uint64_t m = 0;
+    for (auto& kv : free_) m = std::max(m, kv.second);
+    return m;
+  }
+  static uint64_t round_up(uint64_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
+
+ private:
+  char* base_ = nullptr;
+  uint64_t size_ = 0;
+  std::map<uint64_t, uint64_t> free_;
+  uint64_t used_ = 0, peak_ = 0;
+};
+
+// A set of arena allocations made all-or-nothing.
+struct AllocSet {
+  Arena* arena;
+  std::vector<std::pair<char*, uint64_t>> items;
+  bool ok = true;
+  explicit AllocSet(Arena* a) : arena(a) {}
+  char* get(uint64_t bytes) {
+    if (!ok) return nullptr;
+    char* p = arena->alloc(bytes);
+    if (!p) {
+      ok = false;
+      return nullptr;
+    }
+    items.emplace_back(p, bytes);
+    return p;
+  }
+  void release_all() {
+    for (auto& it : items) arena->release(it.first, it.second);
+    items.clear();
+  }
+};
+
+int bitwidth(uint64_t v) {
+  int b = 0;
+  while (v) {
+    ++b;
+    v >>= 1;
+  }
+  return b;
+}
+
+// fp32 ms -> steps, one-step minimum (Sec. 2.1)
+int64_t delay_steps_f32(float ms, float h) {
+  const float q = ms / h;
+  const float r = std::rint(q);
+  if (!(r >= 1.0f)) return 1;
+  if (r > 2147483647.0f) return INT64_MAX;
+  return (int64_t)r;
+}
+
+struct Plan {
+  ng::GenDesc d{};
+  uint64_t n_new = 0;
+  int32_t max_delay = 1;
+};
+
+int plan_call(uint32_t n_nodes, ng_range src, ng_range tgt, const ng_conn_spec* conn,
+              const ng_syn_spec* syn, float h, Plan* out) {
+  if (!conn || !syn) return fail(NG_ERR_INVALID_ARG, "null connection or synapse spec");
+  if ((uint64_t)src.first + src.n > n_nodes || (uint64_t)tgt.first + tgt.n > n_nodes)
+    return fail(NG_ERR_INVALID_ARG, "node range [%u,+%u) or [%u,+%u) exceeds the %u created nodes",
+                src.first, src.n, tgt.first, tgt.n, n_nodes);
+  if (!conn->allow_multapses)
+    return fail(NG_ERR_UNSUPPORTED, "allow_multapses = 0 is not implemented (the rules allow multapses)");
+  if (!conn->allow_autapses) {
+    const bool overlap = src.n && tgt.n && src.first < tgt.first + tgt.n && tgt.first < src.first + src.n;
+    if (overlap)
+      return fail(NG_ERR_UNSUPPORTED, "allow_autapses = 0 with overlapping ranges is not implemented");
+  }
+  const uint64_t ns = src.n, nt = tgt.n, k = conn->k_or_n;
+  uint64_t n = 0;
+  switch (conn->rule) {
+    case NG_ONE_TO_ONE:
+      if (ns != nt) return fail(NG_ERR_INVALID_ARG, "one_to_one needs equal ranges (%llu vs %llu)",
+                                (unsigned long long)ns, (unsigned long long)nt);
+      n = ns;
+      break;
+    case NG_ALL_TO_ALL: n = ns * nt; break;
+    case NG_FIXED_INDEGREE:
+      if (k > 0xFFFFFFFFull) return fail(NG_ERR_TOO_LARGE, "K too large");
+      n = nt * k;
+      if (n && ns == 0) return fail(NG_ERR_INVALID_ARG, "fixed_indegree needs a non-empty source range");
+      break;
+    case NG_FIXED_OUTDEGREE:
+      if (k > 0xFFFFFFFFull) return fail(NG_ERR_TOO_LARGE, "K too large");
+      n = ns * k;
+      if (n && nt == 0) return fail(NG_ERR_INVALID_ARG, "fixed_outdegree needs a non-empty target range");
+      break;
+    case NG_FIXED_TOTAL_NUMBER:
+      n = k;
+      if (n && (ns == 0 || nt == 0))
+        return fail(NG_ERR_INVALID_ARG, "fixed_total_number needs non-empty ranges");
+      break;
+    default: return fail(NG_ERR_INVALID_ARG, "unknown rule %d", conn->rule);
+  }
+  if (n > 0xFFFFFFFFull) return fail(NG_ERR_TOO_LARGE, "a call may create at most 2^32-1 connections");
+
+  ng::GenDesc d{};
+  d.n_new = (uint32_t)n;
+  d.rule = (uint32_t)conn->rule;
+  d.k = (uint32_t)k;
+  d.s0 = src.first;
+  d.ns = src.n;
+  d.t0 = tgt.first;
+  d.nt = tgt.n;
+  d.h = h;
+
+  const ng_param& w = syn->weight;
+  if (!std::isfinite(w.a) || !std::isfinite(w.b)) return fail(NG_ERR_INVALID_ARG, "non-finite weight parameter");
+  switch (w.kind) {
+    case NG_CONST: d.w_kind = ng::W_CONST; d.w_a = (float)w.a; break;
+    case NG_NORMAL:
+      if (w.b < 0) return fail(NG_ERR_INVALID_ARG, "normal weight needs sd >= 0");
+      d.w_kind = ng::W_NORMAL; d.w_a = (float)w.a; d.w_b = (float)w.b;
+      break;
+    case NG_UNIFORM:
+      if (w.b < w.a) return fail(NG_ERR_INVALID_ARG, "uniform weight needs a <= b");
+      d.w_kind = ng::W_UNIFORM; d.w_a = (float)w.a; d.w_b = (float)(w.b - w.a);
+      break;
+    default: return fail(NG_ERR_INVALID_ARG, "unsupported weight distribution %d", w.kind);
+  }
+
+  const ng_param& dl = syn->delay;
+  if (!std::isfinite(dl.a) || !std::isfinite(dl.b)) return fail(NG_ERR_INVALID_ARG, "non-finite delay parameter");
+  int64_t maxd = 1;
+  switch (dl.kind) {
+    case NG_CONST: {
+      const int64_t st = delay_steps_f32((float)dl.a, h);
+      if (st > 32767) return fail(NG_ERR_INVALID_ARG, "delay exceeds 32767 steps");
+      d.d_kind = ng::D_CONST;
+      d.d_const = (int32_t)st;
+      maxd = st;
+      break;
+    }
+    case NG_UNIFORM_INT: {
+      if (dl.a != std::floor(dl.a) || dl.b != std::floor(dl.b) || dl.a < 1 || dl.b < dl.a || dl.b > 32767)
+        return fail(NG_ERR_INVALID_ARG, "uniform_int delay needs integers 1 <= a <= b <= 32767");
+      d.d_kind = ng::D_UNIFORM_INT;
+      d.d_lo = (uint32_t)dl.a;
+      d.d_range = (uint32_t)(dl.b - dl.a + 1);
+      maxd = (int64_t)dl.b;
+      break;
+    }
+    case NG_UNIFORM: {
+      if (dl.a < 0 || dl.b < dl.a) return fail(NG_ERR_INVALID_ARG, "uniform ms delay needs 0 <= a <= b");
+      d.d_kind = ng::D_UNIFORM_MS;
+      d.d_ms_lo = (float)dl.a;
+      d.d_ms_width = (float)(dl.b - dl.a);
+      // the largest step count is reached at u -> 1 (every fp32 step is monotone)
+      maxd = delay_steps_f32(std::fmaf(d.d_ms_width, 1.0f, d.d_ms_lo), h);
+      if (maxd > 32767) return fail(NG_ERR_INVALID_ARG, "delay exceeds 32767 steps");
+      break;
+    }
+    default: return fail(NG_ERR_INVALID_ARG, "unsupported delay distribution %d", dl.kind);
+  }
+  out->d = d;
+  out->n_new = n;
+  out->max_delay = (int32_t)maxd;
+  return NG_OK;
+}
+
+}  // namespace
+
+struct ng_ctx {
+  ng_config cfg{};
+  int log2B = 24;
+  uint64_t B = 1ull << 24;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  Arena arena;
+
+  uint32_t n_nodes = 0;
+  uint32_t next_cid = 0;
+  uint64_t n_conns = 0;
+  int32_t max_delay = 1;
+
+  std::vector<char*> blocks;      // current storage, host copy of the device table
+  char** d_tab[2] = {nullptr, nullptr};
+  int cur = 0;                    // d_tab[cur] describes `blocks`
+  uint32_t tab_cap = 0;
+
+  bool calibrated = false;
+  uint32_t* d_group_ptr = nullptr;
+  uint64_t group_ptr_bytes = 0;
+  uint32_t* d_group_start = nullptr;
+  uint64_t group_start_bytes = 0;
+  uint32_t* d_scalars = nullptr;  // [0] = G
+  uint32_t gi_nodes = 0;          // n_nodes the index was built for
+
+  int radix_bits = 11;
+  uint32_t target_ranges = 1024;
+  int sticky = NG_OK;
+  std::string sticky_msg;
+
+  // optional per-kernel timing with HIP events on the context's stream
+  struct Timed {
+    const char* name;
+    hipEvent_t a, b;
+  };
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<Timed> pending;
+  std::map<std::string, std::pair<double, uint64_t>> timing_acc;
+
+  // pinned staging for batched descriptors
+  ng::GenDesc* h_stage = nullptr;
+  uint64_t h_stage_cap = 0;
+  hipEvent_t stage_done = nullptr;
+};
+
+namespace {
+
+int dev_fail(ng_ctx* c, hipError_t e, const char* what) {
+  c->sticky = NG_ERR_DEVICE;
+  c->sticky_msg = std::string(what) + ": " + hipGetErrorString(e);
+  return fail(NG_ERR_DEVICE, "%s", c->sticky_msg.c_str());
+}
+
+#define NG_HIP(ctx, expr, what)                 \
+  do {                                          \
+    hipError_t e_ = (expr);                     \
+    if (e_ != hipSuccess) return dev_fail(ctx, e_, what); \
+  } while (0)
+
+hipEvent_t take_event(ng_ctx* c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Launch `expr` on the context stream; with timing on, bracket it by events.
+#define NG_LAUNCH(ctx, name, expr)                                              \
+  do {                                                                          \
+    hipEvent_t a_ = nullptr;                                                    \
+    if ((ctx)->timing && (a_ = take_event(ctx)) != nullptr)                     \
+      (void)hipEventRecord(a_, (ctx)->stream);                                  \
+    hipError_t e_ = (expr);                                                     \
+    if (e_ != hipSuccess) return dev_fail(ctx, e_, name);                       \
+    if (a_) {                                                                   \
+      hipEvent_t b_ = take_event(ctx);                                          \
+      if (b_) {                                                                 \
+        (void)hipEventRecord(b_, (ctx)->stream);                                \
+        (ctx)->pending.push_back({name, a_, b_});                               \
+      } else {                                                                  \
+        (ctx)->ev_pool.push_back(a_);                                           \
+      }                                                                         \
+    }                                                                           \
+  } while (0)
+
+void collect_timing(ng_ctx* c) {
+  for (auto& t : c->pending) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+      auto& acc = c->timing_acc[t.name];
+      acc.first += ms;
+      acc.second += 1;
+    }
+    c->ev_pool.push_back(t.a);
+    c->ev_pool.push_back(t.b);
+  }
+  c->pending.clear();
+}
+
+int enter(ng_ctx* c) {
+  if (!c) return fail(NG_ERR_INVALID_ARG, "null context");
+  if (c->sticky != NG_OK) return fail(c->sticky, "%s", c->sticky_msg.c_str());
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return dev_fail(c, e, "hipSetDevice");
+  return NG_OK;
+}
+
+// Write block pointers into a device table through kernel arguments (no host
+// buffer lifetime to track).
+hipError_t set_table(char** tab, uint32_t first, const std::vector<char*>& ptrs, uint32_t from,
+                     hipStream_t s) {
+  for (uint32_t i = from; i < ptrs.size(); i += 8) {
+    uint64_t v[8] = {0};
+    const uint32_t cnt = std::min<uint32_t>(8, (uint32_t)ptrs.size() - i);
+    for (uint32_t k = 0; k < cnt; ++k) v[k] = (uint64_t)ptrs[i + k];
+    hipError_t e = ng::launch_set_ptrs(tab, first + (i - from), cnt, v, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Eq. (1) plus allocation; all-or-nothing.
+int reserve_blocks(ng_ctx* c, uint64_t n_new) {
+  const uint64_t nb = ng_blocks_needed(c->n_conns, n_new, c->B, c->blocks.size());
+  if (c->blocks.size() + nb > c->tab_cap) return fail(NG_ERR_OOM, "block table full");
+  std::vector<char*> fresh;
+  for (uint64_t b = 0; b < nb; ++b) {
+    char* p = c->arena.alloc(ng::kBytesPerConn * c->B);
+    if (!p) {
+      for (char* q : fresh) c->arena.release(q, ng::kBytesPerConn * c->B);
+      return fail(NG_ERR_OOM, "arena cannot hold %llu more blocks of %llu connections",
+                  (unsigned long long)nb, (unsigned long long)c->B);
+    }
+    fresh.push_back(p);
+  }
+  const uint32_t first = (uint32_t)c->blocks.size();
+  for (char* p : fresh) c->blocks.push_back(p);
+  if (!fresh.empty()) NG_HIP(c, set_table(c->d_tab[c->cur], first, c->blocks, first, c->stream), "block table");
+  return NG_OK;
+}
+
+void release_index(ng_ctx* c) {
+  c->arena.release((char*)c->d_group_ptr, c->group_ptr_bytes);
+  c->arena.release((char*)c->d_group_start, c->group_start_bytes);
+  c->d_group_ptr = c->d_group_start = nullptr;
+  c->group_ptr_bytes = c->group_start_bytes = 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ng_version(void) { return "ng 0.1 gfx950"; }
+
+const char* ng_last_error(void) { return g_err.c_str(); }
+
+uint64_t ng_blocks_needed(uint64_t n_conns, uint64_t n_new, uint64_t block_size, uint64_t n_blocks) {
+  if (block_size == 0) return 0;
+  const uint64_t need = (n_conns + n_new + block_size - 1) / block_size;  // Eq. (1)
+  return need > n_blocks ? need - n_blocks : 0;
+}
+
+int ng_plan_count(uint32_t n_nodes, ng_range src, ng_range tgt, const ng_conn_spec* conn,
+                  const ng_syn_spec* syn, float h_ms, uint64_t* out_n) {
+  Plan p;
+  const int rc = plan_call(n_nodes, src, tgt, conn, syn, h_ms > 0 ? h_ms : 0.1f, &p);
+  if (rc == NG_OK && out_n) *out_n = p.n_new;
+  return rc;
+}
+
+int ng_create(const ng_config* cfg, void* arena, uint64_t arena_bytes, void* stream, ng_ctx** out) {
+  if (!cfg || !out) return fail(NG_ERR_INVALID_ARG, "null config or output");
+  if (!arena || ((uintptr_t)arena % kAlign)) return fail(NG_ERR_INVALID_ARG, "arena must be 256-byte aligned");
+  uint64_t B = cfg->block_size ? cfg->block_size : (1ull << 24);
+  if (B & (B - 1) || B < (1ull << 16) || B > (1ull << 30))
+    return fail(NG_ERR_INVALID_ARG, "block_size must be a power of two in [2^16, 2^30]");
+  if (!(cfg->h_ms >= 0) || !std::isfinite(cfg->h_ms)) return fail(NG_ERR_INVALID_ARG, "bad time resolution");
+  ng_ctx* c = new ng_ctx();
+  c->cfg = *cfg;
+  c->cfg.block_size = B;
+  if (c->cfg.h_ms == 0) c->cfg.h_ms = 0.1f;
+  c->B = B;
+  c->log2B = bitwidth(B) - 1;
+  c->stream = (hipStream_t)stream;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return fail(NG_ERR_DEVICE, "no HIP device");
+  }
+  c->arena.init((char*)arena, arena_bytes);
+  c->tab_cap = (uint32_t)std::min<uint64_t>(arena_bytes / (ng::kBytesPerConn * B) + 2, 1u << 20);
+  for (int t = 0; t < 2; ++t) {
+    c->d_tab[t] = (char**)c->arena.alloc(8ull * c->tab_cap);
+    if (!c->d_tab[t]) {
+      delete c;
+      return fail(NG_ERR_OOM, "arena too small");
+    }
+  }
+  c->d_scalars = (uint32_t*)c->arena.alloc(64);
+  if (!c->d_scalars) {
+    delete c;
+    return fail(NG_ERR_OOM, "arena too small");
+  }
+  if (hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming) != hipSuccess) {
+    delete c;
+    return fail(NG_ERR_DEVICE, "hipEventCreate failed");
+  }
+  *out = c;
+  return NG_OK;
+}
+
+int ng_destroy(ng_ctx* c) {
+  if (!c) return NG_OK;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  if (c->h_stage) (void)hipHostFree(c->h_stage);
+  if (c->stage_done) (void)hipEventDestroy(c->stage_done);
+  collect_timing(c);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  delete c;
+  return NG_OK;
+}
+
+int ng_create_nodes(ng_ctx* c, uint32_t n, ng_range* out) {
+  if (int rc = enter(c)) return rc;
+  if ((uint64_t)c->n_nodes + n > 0xFFFFFFFFull) return fail(NG_ERR_TOO_LARGE, "too many nodes");
+  if (out) *out = ng_range{c->n_nodes, n};
+  c->n_nodes += n;
+  if (n) c->calibrated = false;  // the group index covers the old node count
+  return NG_OK;
+}
+
+int ng_connect(ng_ctx* c, ng_range src, ng_range tgt, const ng_conn_spec* conn, const ng_syn_spec* syn,
+               uint32_t* out_cid, uint64_t* out_first, uint64_t* out_n) {
+  if (int rc = enter(c)) return rc;
+  Plan p;
+  if (int rc = plan_call(c->n_nodes, src, tgt, conn, syn, c->cfg.h_ms, &p)) return rc;
+  if (c->next_cid == 0xFFFFFFFFu) return fail(NG_ERR_TOO_LARGE, "connect call ids exhausted");
+  if (c->n_conns + p.n_new > 0xFFFFFFFFull)
+    return fail(NG_ERR_TOO_LARGE, "a context holds at most 2^32-1 connections");
+  if (int rc = reserve_blocks(c, p.n_new)) return rc;
+  p.d.pos0 = c->n_conns;
+  p.d.cid = c->next_cid;
+  if (p.n_new) {
+    NG_LAUNCH(c, "generate", ng::launch_generate(p.d, c->cfg.seed, c->d_tab[c->cur], c->log2B, c->stream));
+    c->calibrated = false;
+  }
+  if (out_cid) *out_cid = c->next_cid;
+  if (out_first) *out_first = c->n_conns;
+  if (out_n) *out_n = p.n_new;
+  c->next_cid++;
+  c->n_conns += p.n_new;
+  c->max_delay = std::max(c->max_delay, p.max_delay);
+  return NG_OK;
+}
+
+int ng_connect_batch(ng_ctx* c, uint32_t n_calls, const ng_range* src, const ng_range* tgt,
+                     const ng_conn_spec* conn, const ng_syn_spec* syn, uint64_t* out_first) {
+  if (int rc = enter(c)) return rc;
+  if (n_calls == 0) return NG_OK;
+  if (!src || !tgt || !conn || !syn) return fail(NG_ERR_INVALID_ARG, "null array");
+  if ((uint64_t)c->next_cid + n_calls > 0xFFFFFFFFull) return fail(NG_ERR_TOO_LARGE, "connect call ids exhausted");
+  std::vector<ng::GenDesc> descs;
+  descs.reserve(n_calls);
+  uint64_t pos = c->n_conns, groups = 0;
+  int32_t maxd = c->max_delay;
+  for (uint32_t i = 0; i < n_calls; ++i) {
+    Plan p;
+    if (int rc = plan_call(c->n_nodes, src[i], tgt[i], &conn[i], &syn[i], c->cfg.h_ms, &p)) {
+      g_err = "call " + std::to_string(i) + ": " + g_err;
+      return rc;
+    }
+    p.d.pos0 = pos;
+    p.d.cid = c->next_cid + i;
+    p.d.group0 = groups;
+    pos += p.n_new;
+    groups += (p.n_new + 3) / 4;
+    maxd = std::max(maxd, p.max_delay);
+    if (pos > 0xFFFFFFFFull) return fail(NG_ERR_TOO_LARGE, "a context holds at most 2^32-1 connections");
+    if (out_first) out_first[i] = p.d.pos0;
+    if (p.n_new) descs.push_back(p.d);
+  }
+  const uint64_t total = pos - c->n_conns;
+  const uint64_t desc_bytes = descs.size() * sizeof(ng::GenDesc);
+  char* d_descs = nullptr;
+  if (!descs.empty()) {
+    d_descs = c->arena.alloc(desc_bytes);
+    if (!d_descs) return fail(NG_ERR_OOM, "arena cannot hold the call descriptors");
+  }
+  if (int rc = reserve_blocks(c, total)) {
+    c->arena.release(d_descs, desc_bytes);
+    return rc;
+  }
+  if (!descs.empty()) {
+    // pinned staging, reused once the previous upload has completed
+    NG_HIP(c, hipEventSynchronize(c->stage_done), "stage wait");
+    if (c->h_stage_cap < descs.size()) {
+      if (c->h_stage) (void)hipHostFree(c->h_stage);
+      c->h_stage = nullptr;
+      NG_HIP(c, hipHostMalloc((void**)&c->h_stage, desc_bytes, hipHostMallocDefault), "hipHostMalloc");
+      c->h_stage_cap = descs.size();
+    }
+    memcpy(c->h_stage, descs.data(), desc_bytes);
+    NG_HIP(c, hipMemcpyAsync(d_descs, c->h_stage, desc_bytes, hipMemcpyHostToDevice, c->stream), "upload");
+    NG_HIP(c, hipEventRecord(c->stage_done, c->stream), "event");
+    NG_LAUNCH(c, "generate_batch",
+              ng::launch_generate_batch((const ng::GenDesc*)d_descs, (uint32_t)descs.size(), groups,
+                                        c->cfg.seed, c->d_tab[c->cur], c->log2B, c->stream));
+    c->arena.release(d_descs, desc_bytes);  // stream-ordered reuse is safe
+    c->calibrated = false;
+  }
+  c->next_cid += n_calls;
+  c->n_conns = pos;
+  c->max_delay = maxd;
+  return NG_OK;
+}
+
+int ng_set_tuning(ng_ctx* c, int radix_bits, uint32_t target_ranges) {
+  if (!c) return fail(NG_ERR_INVALID_ARG, "null context");
+  if (radix_bits < 4 || radix_bits > 11) return fail(NG_ERR_INVALID_ARG, "radix_bits must be in [4, 11]");
+  if (target_ranges < 8 || target_ranges > (1u << 16)) return fail(NG_ERR_INVALID_ARG, "target_ranges in [8, 65536]");
+  c->radix_bits = radix_bits;
+  c->target_ranges = target_ranges;
+  return NG_OK;
+}
+
+int ng_calibrate(ng_ctx* c) {
+  if (int rc = enter(c)) return rc;
+  if (c->calibrated) return NG_OK;
+  const uint64_t N = c->n_conns;
+  const uint32_t nn = c->n_nodes;
+  const int sbits = bitwidth(nn > 0 ? nn - 1 : 0);
+  const int dbits = bitwidth((uint64_t)c->max_delay);
+  const int keybits = sbits + dbits;
+  if (keybits > 32) return fail(NG_ERR_UNSUPPORTED, "source+delay keys wider than 32 bits");
+  const int RB = c->radix_bits;
+  const int passes = std::max(1, (keybits + RB - 1) / RB);
+
+  // sort geometry
+  ng::SortGeom g{};
+  const uint32_t tile = (uint32_t)ng::sort_tile_size(RB);
+  g.n = N;
+  g.tile = tile;
+  const uint64_t n_tiles = (N + tile - 1) / tile;
+  g.tiles_per_range = (uint32_t)std::max<uint64_t>(1, (n_tiles + c->target_ranges - 1) / c->target_ranges);
+  g.n_ranges = (uint32_t)((n_tiles + g.tiles_per_range - 1) / g.tiles_per_range);
+  g.ranges_per_xcd = (g.n_ranges + 7) / 8;
+
+  const uint64_t nblk = (N + c->B - 1) / c->B;
+  if (nblk > c->tab_cap) return fail(NG_ERR_OOM, "block table full");
+  const uint64_t gi_tiles = (N + ng::gi_tile_size() - 1) / ng::gi_tile_size();
+  const uint64_t gcap = std::min<uint64_t>(N, (uint64_t)nn * (uint64_t)c->max_delay) + 1;
+  const uint64_t counts_n = ((uint64_t)1 << std::min(RB, keybits > 0 ? keybits : 1)) * g.n_ranges;
+
+  AllocSet as(&c->arena);
+  std::vector<char*> nblocks;
+  for (uint64_t b = 0; b < nblk && as.ok; ++b) nblocks.push_back(as.get(ng::kBytesPerConn * c->B));
+  uint32_t* keys[2] = {nullptr, nullptr};
+  uint2* pay[2] = {nullptr, nullptr};
+  for (int t = 0; t < std::min(passes - 1, 2); ++t) {
+    keys[t] = (uint32_t*)as.get(4 * std::max<uint64_t>(N, 1));
+    pay[t] = (uint2*)as.get(8 * std::max<uint64_t>(N, 1));
+  }
+  uint32_t* counts = (uint32_t*)as.get(4 * std::max<uint64_t>(counts_n, 1));
+  const uint64_t tmp_words = std::max({ng::scan_tmp_words(counts_n), ng::scan_tmp_words(nn + 1ull),
+                                       ng::scan_tmp_words(gi_tiles)});
+  uint32_t* scan_tmp = (uint32_t*)as.get(4 * tmp_words);
+  uint32_t* G = (uint32_t*)as.get(4 * (nn + 1ull));
+  uint32_t* tile_flags = (uint32_t*)as.get(4 * std::max<uint64_t>(gi_tiles, 1));
+  // the new index replaces the old one, so release the old one first
+  const uint64_t gp_bytes = 4 * (nn + 1ull), gs_bytes = 4 * gcap;
+  release_index(c);
+  uint32_t* gptr = (uint32_t*)c->arena.alloc(gp_bytes);
+  uint32_t* gstart = gptr ? (uint32_t*)c->arena.alloc(gs_bytes) : nullptr;
+  if (!as.ok || !gptr || !gstart) {
+    as.release_all();
+    c->arena.release((char*)gptr, gp_bytes);
+    c->arena.release((char*)gstart, gs_bytes);
+    return fail(NG_ERR_OOM, "arena cannot hold the calibration buffers (N=%llu)", (unsigned long long)N);
+  }
+  const int nxt = 1 - c->cur;
+  hipStream_t s = c->stream;
+  NG_HIP(c, set_table(c->d_tab[nxt], 0, nblocks, 0, s), "block table");
+
+  // --- LSD radix passes ----------------------------------------------------
+  if (N > 0) {
+    int shift = 0;
+    const int base_bits = keybits / passes, extra = keybits % passes;
+    for (int p = 0; p < passes; ++p) {
+      const int nbits = base_bits + (p < extra ? 1 : 0);
+      ng::SortIO io{};
+      io.log2B = c->log2B;
+      io.dbits = (uint32_t)dbits;
+      if (p == 0) io.in_blocks = c->d_tab[c->cur];
+      else {
+        io.in_keys = keys[(p - 1) & 1];
+        io.in_pay = pay[(p - 1) & 1];
+      }
+      if (p == passes - 1) io.out_blocks = c->d_tab[nxt];
+      else {
+        io.out_keys = keys[p & 1];
+        io.out_pay = pay[p & 1];
+      }
+      const uint64_t cn = ((uint64_t)1 << nbits) * g.n_ranges;
+      NG_LAUNCH(c, "upsweep", ng::launch_upsweep(g, io, nbits, (uint32_t)shift, counts, s));
+      NG_LAUNCH(c, "scan", ng::launch_exclusive_scan(counts, counts, cn, scan_tmp, nullptr, s));
+      NG_LAUNCH(c, "downsweep", ng::launch_downsweep(g, io, nbits, (uint32_t)shift, counts, s));
+      shift += nbits;
+    }
+  }
+
+  // --- group index, Eq. (14) ---------------------------------------------
+  NG_LAUNCH(c, "fill", ng::launch_fill_u32(G, 0u, nn + 1ull, s));
+  if (N > 0) {
+    NG_LAUNCH(c, "group_flags", ng::launch_group_flags(c->d_tab[nxt], c->log2B, N, tile_flags, G, s));
+    NG_LAUNCH(c, "scan", ng::launch_exclusive_scan(tile_flags, tile_flags, gi_tiles, scan_tmp, c->d_scalars, s));
+    NG_LAUNCH(c, "group_write", ng::launch_group_write(c->d_tab[nxt], c->log2B, N, tile_flags, gstart, s));
+  } else {
+    NG_LAUNCH(c, "fill", ng::launch_fill_u32(c->d_scalars, 0u, 1, s));
+    NG_LAUNCH(c, "fill", ng::launch_fill_u32(gstart, 0u, 1, s));
+  }
+  NG_LAUNCH(c, "scan", ng::launch_exclusive_scan(G, gptr, nn + 1ull, scan_tmp, nullptr, s));
+
+  // old storage and scratch return to the arena (stream-ordered reuse)
+  for (char* b : c->blocks) c->arena.release(b, ng::kBytesPerConn * c->B);
+  for (size_t i = nblk; i < as.items.size(); ++i) c->arena.release(as.items[i].first, as.items[i].second);
+  c->blocks = nblocks;
+  c->cur = nxt;
+  c->d_group_ptr = gptr;
+  c->group_ptr_bytes = gp_bytes;
+  c->d_group_start = gstart;
+  c->group_start_bytes = gs_bytes;
+  c->gi_nodes = nn;
+  c->calibrated = true;
+  return NG_OK;
+}
+
+int ng_reset(ng_ctx* c) {
+  if (int rc = enter(c)) return rc;
+  for (char* b : c->blocks) c->arena.release(b, ng::kBytesPerConn * c->B);
+  c->blocks.clear();
+  release_index(c);
+  c->n_nodes = 0;
+  c->next_cid = 0;
+  c->n_conns = 0;
+  c->max_delay = 1;
+  c->calibrated = false;
+  c->gi_nodes = 0;
+  return NG_OK;
+}
+
+int ng_enable_timing(ng_ctx* c, int on) {
+  if (!c) return fail(NG_ERR_INVALID_ARG, "null context");
+  c->timing = on != 0;
+  return NG_OK;
+}
+
+int ng_read_timing(ng_ctx* c, ng_kernel_time* out, int capacity, int* count, int reset) {
+  if (int rc = ng_sync(c)) return rc;
+  collect_timing(c);
+  int n = 0;
+  for (auto& kv : c->timing_acc) {
+    if (out && n < capacity) {
+      memset(&out[n], 0, sizeof(out[n]));
+      strncpy(out[n].name, kv.first.c_str(), sizeof(out[n].name) - 1);
+      out[n].launches = kv.second.second;
+      out[n].total_ms = kv.second.first;
+    }
+    ++n;
+  }
+  if (count) *count = n;
+  if (reset) c->timing_acc.clear();
+  return NG_OK;
+}
+
+int ng_sync(ng_ctx* c) {
+  if (int rc = enter(c)) return rc;
+  NG_HIP(c, hipStreamSynchronize(c->stream), "kernel execution");
+  return NG_OK;
+}
+
+int ng_get_connections(ng_ctx* c, ng_conn_view* out) {
+  if (!out) return fail(NG_ERR_INVALID_ARG, "null view");
+  if (int rc = ng_sync(c)) return rc;
+  memset(out, 0, sizeof *out);
+  out->n_conns = c->n_conns;
+  out->block_size = c->B;
+  out->n_nodes = c->n_nodes;
+  out->n_blocks = (uint32_t)c->blocks.size();
+  out->block_base = (void* const*)c->blocks.data();
+  out->calibrated = c->calibrated ? 1 : 0;
+  if (c->calibrated) {
+    uint32_t G = 0;
+    NG_HIP(c, hipMemcpy(&G, c->d_scalars, 4, hipMemcpyDeviceToHost), "read G");
+    out->n_groups = G;
+    out->group_ptr = c->d_group_ptr;
+    out->group_start = c->d_group_start;
+  }
+  return NG_OK;
+}
+
+int ng_copy_connections(ng_ctx* c, uint64_t first, uint64_t count, uint32_t* src, uint32_t* tgt, float* w,
+                        int16_t* delay) {
+  if (int rc = ng_sync(c)) return rc;
+  if (first > c->n_conns || count > c->n_conns - first)
+    return fail(NG_ERR_INVALID_ARG, "range [%llu,+%llu) outside the %llu connections",
+                (unsigned long long)first, (unsigned long long)count, (unsigned long long)c->n_conns);
+  uint64_t done = 0;
+  while (done < count) {
+    const uint64_t j = first + done;
+    const uint64_t b = j >> c->log2B, o = j & (c->B - 1);
+    const uint64_t len = std::min(count - done, c->B - o);
+    char* base = c->blocks[b];
+    if (src) NG_HIP(c, hipMemcpyAsync(src + done, base + 4 * o, 4 * len, hipMemcpyDefault, c->stream), "copy");
+    if (tgt) NG_HIP(c, hipMemcpyAsync(tgt + done, base + 4 * c->B + 4 * o, 4 * len, hipMemcpyDefault, c->stream), "copy");
+    if (w) NG_HIP(c, hipMemcpyAsync(w + done, base + 8 * c->B + 4 * o, 4 * len, hipMemcpyDefault, c->stream), "copy");
+    if (delay)
+      NG_HIP(c, hipMemcpyAsync(delay + done, base + 12 * c->B + 2 * o, 2 * len, hipMemcpyDefault, c->stream), "copy");
+    done += len;
+  }
+  NG_HIP(c, hipStreamSynchronize(c->stream), "copy");
+  return NG_OK;
+}
+
+int ng_copy_group_index(ng_ctx* c, uint32_t* group_ptr, uint32_t* group_start) {
+  if (int rc = ng_sync(c)) return rc;
+  if (!c->calibrated) return fail(NG_ERR_STATE, "not calibrated");
+  uint32_t G = 0;
+  NG_HIP(c, hipMemcpy(&G, c->d_scalars, 4, hipMemcpyDeviceToHost), "read G");
+  if (group_ptr)
+    NG_HIP(c, hipMemcpy(group_ptr, c->d_group_ptr, 4 * (c->gi_nodes + 1ull), hipMemcpyDefault), "copy");
+  if (group_start)
+    NG_HIP(c, hipMemcpy(group_start, c->d_group_start, 4 * (G + 1ull), hipMemcpyDefault), "copy");
+  return NG_OK;
+}
+
+int ng_memory_stats(ng_ctx* c, uint64_t* used, uint64_t* peak, uint64_t* largest_free) {
+  if (!c) return fail(NG_ERR_INVALID_ARG, "null context");
+  if (used) *used = c->arena.used();
+  if (peak) *peak = c->arena.peak();
+  if (largest_free) *largest_free = c->arena.largest_free();
+  return NG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,108 @@
+"""A thin convenience wrapper over the C ABI: one context on a torch arena.
+
+Everything it does is marshalling: nodes, Connect calls and calibration go
+straight to libng.so; ``fetch`` copies the device result into host or device
+buffers the caller can inspect.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import ng
+
+
+def arena_bytes_for(n_syn: int, n_nodes: int, max_delay: int = 63, block_size: int = 1 << 24,
+                    radix_bits: int = 11, slack: float = 1.15) -> int:
+    """Arena size that holds n_syn connections through one calibration."""
+    blocks = -(-max(n_syn, 1) // block_size)
+    store = 14 * block_size * blocks                 # creation-order blocks
+    sorted_store = store                             # calibrated blocks
+    scratch = 2 * 12 * n_syn                         # two key/payload buffers (3+ passes)
+    counts = 4 * (1 << radix_bits) * 1024 * 2
+    index = 4 * (n_nodes + 1) * 3 + 4 * (min(n_syn, n_nodes * max_delay) + 1) + 4 * (n_syn // 4096 + 8)
+    total = int((store + sorted_store + scratch + counts + index) * slack) + (64 << 20)
+    return (total + 4095) // 4096 * 4096
+
+
+class Network:
+    def __init__(self, seed: int, h: float = 0.1, block_size: int = 0, arena_bytes: int = 1 << 30,
+                 stream: int | None = None, device: str = "cuda"):
+        self.arena_bytes = int(arena_bytes)
+        self.arena = ng.arena_for(self.arena_bytes, device)
+        self.stream = ng.current_stream() if stream is None else stream
+        cfg = ng.ng_config(int(block_size), int(seed), float(h), 0)
+        self.ctx = ng.ng_create(cfg, self.arena, self.arena_bytes, self.stream)
+
+    # -- construction ---------------------------------------------------------
+    def create(self, n: int):
+        r = ng.ng_create_nodes(self.ctx, int(n))
+        return r.first, r.n
+
+    def connect(self, call):
+        return ng.ng_connect(self.ctx, *ng.call_args(call))
+
+    def connect_batch(self, calls):
+        args = [ng.call_args(c) for c in calls]
+        return ng.ng_connect_batch(self.ctx, [a[0] for a in args], [a[1] for a in args],
+                                   [a[2] for a in args], [a[3] for a in args])
+
+    def calibrate(self):
+        ng.ng_calibrate(self.ctx)
+
+    def sync(self):
+        ng.ng_sync(self.ctx)
+
+    def tune(self, radix_bits: int, target_ranges: int):
+        ng.ng_set_tuning(self.ctx, radix_bits, target_ranges)
+
+    def build(self, workload, batched: bool = False, calibrate: bool = True):
+        for n in workload.populations:
+            self.create(n)
+        if batched:
+            self.connect_batch(workload.calls)
+        else:
+            for c in workload.calls:
+                self.connect(c)
+        if calibrate:
+            self.calibrate()
+        return self
+
+    # -- read back -----------------------------------------------------------------
+    def view(self):
+        return ng.ng_get_connections(self.ctx)
+
+    def fetch(self, first: int = 0, count: int | None = None, device: bool = False):
+        v = self.view()
+        n = v.n_conns - first if count is None else count
+        if device:
+            mk = lambda dt: torch.empty(n, dtype=dt, device="cuda")  # noqa: E731
+            out = dict(src=mk(torch.int32), tgt=mk(torch.int32), w=mk(torch.float32), delay=mk(torch.int16))
+        else:
+            out = dict(src=np.empty(n, np.uint32), tgt=np.empty(n, np.uint32), w=np.empty(n, np.float32),
+                       delay=np.empty(n, np.int16))
+        if n:
+            ng.ng_copy_connections(self.ctx, first, n, out["src"], out["tgt"], out["w"], out["delay"])
+        return out
+
+    def group_index(self):
+        v = self.view()
+        gp = np.empty(v.n_nodes + 1, np.uint32)
+        gs = np.empty(v.n_groups + 1, np.uint32)
+        ng.ng_copy_group_index(self.ctx, gp, gs)
+        return gp, gs
+
+    def memory_stats(self):
+        return ng.ng_memory_stats(self.ctx)
+
+    def close(self):
+        if self.ctx is not None:
+            ng.ng_destroy(self.ctx)
+            self.ctx = None
+            self.arena = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,277 @@
+"""Python binding of the C ABI in include/ng.h (argument marshalling only).
+
+Every function here has the name of the C entry point it wraps and raises
+``NGError`` on a non-zero status.  All connection generation, sorting and
+indexing runs in the HIP kernels of ``libng.so``; there is no fallback: if the
+library is missing, ``lib()`` raises.
+
+torch is imported before the library is loaded so that the process holds a
+single HIP runtime (torch's); torch also supplies the device arena and the
+stream (see ``arena_for``/``current_stream``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import torch  # noqa: F401  (load torch's HIP runtime first)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libng.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "ng.h")
+
+NG_OK, NG_ERR_INVALID_ARG, NG_ERR_OOM, NG_ERR_UNSUPPORTED = 0, -1, -2, -3
+NG_ERR_STATE, NG_ERR_TOO_LARGE, NG_ERR_DEVICE = -4, -5, -6
+
+NG_ONE_TO_ONE, NG_ALL_TO_ALL, NG_FIXED_INDEGREE, NG_FIXED_OUTDEGREE, NG_FIXED_TOTAL_NUMBER = range(5)
+NG_CONST, NG_NORMAL, NG_UNIFORM_INT, NG_UNIFORM = range(4)
+
+RULE_CODES = {"one_to_one": NG_ONE_TO_ONE, "all_to_all": NG_ALL_TO_ALL,
+              "fixed_indegree": NG_FIXED_INDEGREE, "fixed_outdegree": NG_FIXED_OUTDEGREE,
+              "fixed_total_number": NG_FIXED_TOTAL_NUMBER}
+DIST_CODES = {"const": NG_CONST, "normal": NG_NORMAL, "uniform_int": NG_UNIFORM_INT,
+              "uniform": NG_UNIFORM}
+
+
+class NGError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"ng status {status}: {msg}")
+        self.status = status
+
+
+class ng_range(ctypes.Structure):
+    _fields_ = [("first", ctypes.c_uint32), ("n", ctypes.c_uint32)]
+
+
+class ng_conn_spec(ctypes.Structure):
+    _fields_ = [("rule", ctypes.c_int32), ("allow_autapses", ctypes.c_int32),
+                ("allow_multapses", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("k_or_n", ctypes.c_uint64)]
+
+
+class ng_param(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("a", ctypes.c_double), ("b", ctypes.c_double)]
+
+
+class ng_syn_spec(ctypes.Structure):
+    _fields_ = [("weight", ng_param), ("delay", ng_param)]
+
+
+class ng_config(ctypes.Structure):
+    _fields_ = [("block_size", ctypes.c_uint64), ("seed", ctypes.c_uint64),
+                ("h_ms", ctypes.c_float), ("reserved", ctypes.c_int32)]
+
+
+class ng_conn_view(ctypes.Structure):
+    _fields_ = [("n_conns", ctypes.c_uint64), ("n_groups", ctypes.c_uint64),
+                ("block_size", ctypes.c_uint64), ("n_nodes", ctypes.c_uint32),
+                ("n_blocks", ctypes.c_uint32), ("calibrated", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("block_base", ctypes.POINTER(ctypes.c_void_p)),
+                ("group_ptr", ctypes.c_void_p), ("group_start", ctypes.c_void_p)]
+
+
+class ng_kernel_time(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libng.so (built by __graft_entry__.build()); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        P, vp = ctypes.POINTER, ctypes.c_void_p
+        u32, u64, i32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32
+        sig = {
+            "ng_create": ([P(ng_config), vp, u64, vp, P(vp)], ctypes.c_int),
+            "ng_destroy": ([vp], ctypes.c_int),
+            "ng_create_nodes": ([vp, u32, P(ng_range)], ctypes.c_int),
+            "ng_connect": ([vp, ng_range, ng_range, P(ng_conn_spec), P(ng_syn_spec), P(u32), P(u64),
+                            P(u64)], ctypes.c_int),
+            "ng_connect_batch": ([vp, u32, P(ng_range), P(ng_range), P(ng_conn_spec), P(ng_syn_spec),
+                                  P(u64)], ctypes.c_int),
+            "ng_calibrate": ([vp], ctypes.c_int),
+            "ng_sync": ([vp], ctypes.c_int),
+            "ng_get_connections": ([vp, P(ng_conn_view)], ctypes.c_int),
+            "ng_copy_connections": ([vp, u64, u64, vp, vp, vp, vp], ctypes.c_int),
+            "ng_copy_group_index": ([vp, vp, vp], ctypes.c_int),
+            "ng_set_tuning": ([vp, ctypes.c_int, u32], ctypes.c_int),
+            "ng_memory_stats": ([vp, P(u64), P(u64), P(u64)], ctypes.c_int),
+            "ng_reset": ([vp], ctypes.c_int),
+            "ng_enable_timing": ([vp, ctypes.c_int], ctypes.c_int),
+            "ng_read_timing": ([vp, P(ng_kernel_time), ctypes.c_int, P(ctypes.c_int), ctypes.c_int],
+                               ctypes.c_int),
+            "ng_last_error": ([], ctypes.c_char_p),
+            "ng_blocks_needed": ([u64, u64, u64, u64], u64),
+            "ng_plan_count": ([u32, ng_range, ng_range, P(ng_conn_spec), P(ng_syn_spec), ctypes.c_float,
+                               P(u64)], ctypes.c_int),
+            "ng_version": ([], ctypes.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def declared_symbols() -> list:
+    """Names of the functions include/ng.h declares."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ng_[a-z_]+)\s*\(", text)))
+
+
+def _check(rc: int):
+    if rc != NG_OK:
+        raise NGError(rc, ng_last_error())
+
+
+def _vp(x) -> ctypes.c_void_p:
+    if x is None:
+        return ctypes.c_void_p(0)
+    if isinstance(x, torch.Tensor):
+        return ctypes.c_void_p(x.data_ptr())
+    if hasattr(x, "ctypes"):  # numpy
+        return x.ctypes.data_as(ctypes.c_void_p)
+    return ctypes.c_void_p(int(x))
+
+
+# --- marshalling of workload descriptions ----------------------------------
+def conn_spec(rule: str, k_or_n: int = 0, allow_autapses: int = 1, allow_multapses: int = 1) -> ng_conn_spec:
+    return ng_conn_spec(RULE_CODES[rule], allow_autapses, allow_multapses, 0, int(k_or_n))
+
+
+def param(spec) -> ng_param:
+    kind, a, b = (tuple(spec) + (0.0, 0.0))[:3]
+    return ng_param(DIST_CODES[kind], 0, float(a), float(b))
+
+
+def syn_spec(weight, delay) -> ng_syn_spec:
+    return ng_syn_spec(param(weight), param(delay))
+
+
+def call_args(call):
+    """(src range, tgt range, conn spec, syn spec) of a workloads.Call."""
+    return (ng_range(*call.src), ng_range(*call.tgt), conn_spec(call.rule, call.k_or_n),
+            syn_spec(call.weight, call.delay))
+
+
+# --- entry points ------------------------------------------------------------
+def ng_version() -> str:
+    return lib().ng_version().decode()
+
+
+def ng_last_error() -> str:
+    return lib().ng_last_error().decode()
+
+
+def ng_blocks_needed(n_conns: int, n_new: int, block_size: int, n_blocks: int) -> int:
+    return int(lib().ng_blocks_needed(n_conns, n_new, block_size, n_blocks))
+
+
+def ng_plan_count(n_nodes: int, src: ng_range, tgt: ng_range, conn: ng_conn_spec, syn: ng_syn_spec,
+                  h_ms: float = 0.1) -> int:
+    out = ctypes.c_uint64()
+    _check(lib().ng_plan_count(n_nodes, src, tgt, ctypes.byref(conn), ctypes.byref(syn), h_ms,
+                               ctypes.byref(out)))
+    return int(out.value)
+
+
+def ng_create(cfg: ng_config, arena, arena_bytes: int, stream) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(lib().ng_create(ctypes.byref(cfg), _vp(arena), arena_bytes, _vp(stream), ctypes.byref(h)))
+    return h
+
+
+def ng_destroy(ctx) -> None:
+    _check(lib().ng_destroy(ctx))
+
+
+def ng_create_nodes(ctx, n: int) -> ng_range:
+    r = ng_range()
+    _check(lib().ng_create_nodes(ctx, n, ctypes.byref(r)))
+    return r
+
+
+def ng_connect(ctx, src: ng_range, tgt: ng_range, conn: ng_conn_spec, syn: ng_syn_spec):
+    cid, first, n = ctypes.c_uint32(), ctypes.c_uint64(), ctypes.c_uint64()
+    _check(lib().ng_connect(ctx, src, tgt, ctypes.byref(conn), ctypes.byref(syn), ctypes.byref(cid),
+                            ctypes.byref(first), ctypes.byref(n)))
+    return int(cid.value), int(first.value), int(n.value)
+
+
+def ng_connect_batch(ctx, srcs, tgts, conns, syns):
+    n = len(srcs)
+    S = (ng_range * n)(*srcs)
+    T = (ng_range * n)(*tgts)
+    C = (ng_conn_spec * n)(*conns)
+    Y = (ng_syn_spec * n)(*syns)
+    first = (ctypes.c_uint64 * n)()
+    _check(lib().ng_connect_batch(ctx, n, S, T, C, Y, first))
+    return [int(v) for v in first]
+
+
+def ng_calibrate(ctx) -> None:
+    _check(lib().ng_calibrate(ctx))
+
+
+def ng_sync(ctx) -> None:
+    _check(lib().ng_sync(ctx))
+
+
+def ng_get_connections(ctx) -> ng_conn_view:
+    v = ng_conn_view()
+    _check(lib().ng_get_connections(ctx, ctypes.byref(v)))
+    return v
+
+
+def ng_copy_connections(ctx, first: int, count: int, src=None, tgt=None, w=None, delay=None) -> None:
+    _check(lib().ng_copy_connections(ctx, first, count, _vp(src), _vp(tgt), _vp(w), _vp(delay)))
+
+
+def ng_copy_group_index(ctx, group_ptr=None, group_start=None) -> None:
+    _check(lib().ng_copy_group_index(ctx, _vp(group_ptr), _vp(group_start)))
+
+
+def ng_reset(ctx) -> None:
+    _check(lib().ng_reset(ctx))
+
+
+def ng_enable_timing(ctx, on: bool = True) -> None:
+    _check(lib().ng_enable_timing(ctx, 1 if on else 0))
+
+
+def ng_read_timing(ctx, reset: bool = True) -> dict:
+    """{kernel name: (launches, total ms)} of the timed launches so far."""
+    cap = 64
+    arr = (ng_kernel_time * cap)()
+    n = ctypes.c_int()
+    _check(lib().ng_read_timing(ctx, arr, cap, ctypes.byref(n), 1 if reset else 0))
+    return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms)) for i in range(min(n.value, cap))}
+
+
+def ng_set_tuning(ctx, radix_bits: int, target_ranges: int) -> None:
+    _check(lib().ng_set_tuning(ctx, radix_bits, target_ranges))
+
+
+def ng_memory_stats(ctx):
+    u, p, f = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+    _check(lib().ng_memory_stats(ctx, ctypes.byref(u), ctypes.byref(p), ctypes.byref(f)))
+    return int(u.value), int(p.value), int(f.value)
+
+
+# --- torch plumbing: device memory and streams ----------------------------------
+def arena_for(nbytes: int, device: str = "cuda") -> torch.Tensor:
+    """A device buffer the context carves its allocations from."""
+    return torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+
+
+def current_stream() -> int:
+    return torch.cuda.current_stream().cuda_stream

@@ -1,0 +1,90 @@
+"""Full-size parity: the microcircuit-shaped network of 77,169 nodes and
+3.0e8 synapses in 64 fixed_total_number calls, in the launch configuration
+the benchmark times (one ng_connect per call, then ng_calibrate).
+
+The oracle cannot rebuild 3e8 synapses in test time, so:
+  * creation order is checked element by element at sampled positions (every
+    call's first and last synapse plus random ones), each recomputed by the
+    oracle one synapse at a time;
+  * the calibrated order is checked by properties that hold at any size:
+    keys non-decreasing, and the result equals a stable sort (torch's, an
+    independent implementation) of the checked creation-order arrays;
+  * the group index is recomputed from the sorted keys with plain tensor ops.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2306_09855_amd import workloads as W
+from parity import check_equal, check_weights
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2306_09855_amd.network import Network, arena_bytes_for  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def microcircuit_full():
+    wl = W.microcircuit()
+    assert wl.n_syn == 300_000_000
+    net = Network(wl.seed, wl.h, 0, arena_bytes_for(wl.n_syn, wl.n_nodes, wl.max_delay))
+    net.build(wl, calibrate=False)
+    created = net.fetch(device=True)
+    net.calibrate()
+    out = net.fetch(device=True)
+    gp, gs = net.group_index()
+    net.close()
+    yield wl, created, out, gp, gs
+    del created, out
+    torch.cuda.empty_cache()
+
+
+def test_creation_order_sampled(microcircuit_full):
+    wl, created, _, _, _ = microcircuit_full
+    rng = np.random.default_rng(2024)
+    starts = np.concatenate([[0], np.cumsum([c.n_syn() for c in wl.calls])])
+    picks = [(c, 0) for c in range(len(wl.calls))] + [(c, wl.calls[c].n_syn() - 1) for c in range(len(wl.calls))]
+    for pos in rng.integers(0, wl.n_syn, 3000):
+        c = int(np.searchsorted(starts, pos, side="right") - 1)
+        picks.append((c, int(pos - starts[c])))
+    pos = np.array([starts[c] + i for c, i in picks], dtype=np.int64)
+    ref = np.array([oracle.synapse(wl.seed, wl.h, c, wl.calls[c], i) for c, i in picks], dtype=object)
+    idx = torch.from_numpy(pos).cuda()
+    check_equal(created["src"][idx].cpu().numpy().view(np.uint32), ref[:, 0].astype(np.int64), "src")
+    check_equal(created["tgt"][idx].cpu().numpy().view(np.uint32), ref[:, 1].astype(np.int64), "tgt")
+    check_equal(created["delay"][idx].cpu().numpy(), ref[:, 3].astype(np.int64), "delay")
+    base = np.array([wl.calls[c].weight[1] for c, _ in picks])
+    check_weights(created["w"][idx].cpu().numpy(), ref[:, 2].astype(np.float64), base, "w")
+
+
+def test_calibrated_is_stable_sort(microcircuit_full):
+    wl, created, out, _, _ = microcircuit_full
+    dbits = int(wl.max_delay).bit_length()
+    key_c = (created["src"].to(torch.int64) << dbits) | created["delay"].to(torch.int64)
+    key_s = (out["src"].to(torch.int64) << dbits) | out["delay"].to(torch.int64)
+    assert bool((key_s[1:] >= key_s[:-1]).all())
+    _, order = torch.sort(key_c, stable=True)
+    del key_c
+    for k in ("src", "tgt", "delay"):
+        assert torch.equal(created[k][order], out[k]), k
+    assert torch.equal(created["w"][order].view(torch.int32), out["w"].view(torch.int32))
+
+
+def test_group_index_full(microcircuit_full):
+    wl, _, out, gp, gs = microcircuit_full
+    dbits = int(wl.max_delay).bit_length()
+    key = (out["src"].to(torch.int64) << dbits) | out["delay"].to(torch.int64)
+    flag = torch.ones_like(key, dtype=torch.bool)
+    flag[1:] = key[1:] != key[:-1]
+    starts = torch.nonzero(flag).flatten()
+    G = int(starts.numel())
+    assert gs.size == G + 1 and gs[-1] == wl.n_syn
+    assert torch.equal(torch.from_numpy(gs[:-1].astype(np.int64)).cuda(), starts)
+    per_src = torch.bincount(out["src"][starts].to(torch.int64), minlength=wl.n_nodes)
+    ptr = torch.zeros(wl.n_nodes + 1, dtype=torch.int64, device="cuda")
+    ptr[1:] = torch.cumsum(per_src, 0)
+    assert torch.equal(torch.from_numpy(gp.astype(np.int64)).cuda(), ptr)

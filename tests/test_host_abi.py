@@ -1,0 +1,123 @@
+"""CPU-only checks of the C-ABI library: it loads, exports every declared
+symbol, and its pure host logic (Eq. (1) block planning, Connect validation
+and counts of Sec. 2.1) behaves as specified.  No device work is done here."""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+ng = pytest.importorskip("paper_2306_09855_amd.ng")
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(ng.LIB_PATH):
+        pytest.skip("libng.so not built")
+    return ng.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = ng.declared_symbols()
+    assert "ng_connect" in names and "ng_calibrate" in names and "ng_get_connections" in names
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    # and the binding wraps each of them under the same name
+    assert not [n for n in names if not hasattr(ng, n)]
+
+
+def test_version(L):
+    assert "gfx950" in ng.ng_version()
+
+
+def test_blocks_needed_fig1_golden(L):
+    rows = np.loadtxt(os.path.join(HERE, "golden", "fig1_blocks.txt"), dtype=np.int64)
+    for B, n_conns, n_blocks, n_new, n_newblocks, n_prev2 in rows:
+        assert ng.ng_blocks_needed(int(n_conns), int(n_new), int(B), int(n_blocks)) == n_newblocks
+        # Eq. (3): the new connections that precede block b = 2 fill the rest of block 1
+        assert B * n_blocks - n_conns == n_prev2
+
+
+@pytest.mark.parametrize("n_conns,n_new,B,n_blocks,expected", [
+    (0, 0, 10, 0, 0),          # nothing to store
+    (0, 1, 10, 0, 1),
+    (0, 10, 10, 0, 1),         # exactly one full block
+    (0, 11, 10, 0, 2),
+    (5, 5, 10, 1, 0),          # fills the free slots of the last block
+    (5, 6, 10, 1, 1),
+    (20, 0, 10, 2, 0),
+    (3, 1, 10, 4, 0),          # spare capacity: never negative
+    (10**7 - 1, 2, 10**7, 1, 1),
+    (300_000_000, 0, 1 << 24, 18, 0),
+    (0, 300_000_000, 1 << 24, 0, 18),
+])
+def test_blocks_needed_eq1(L, n_conns, n_new, B, n_blocks, expected):
+    assert ng.ng_blocks_needed(n_conns, n_new, B, n_blocks) == expected
+
+
+def _count(n_nodes, rule, src, tgt, k=0, w=("normal", 0.5, 0.05), d=("uniform_int", 1, 20), h=0.1):
+    return ng.ng_plan_count(n_nodes, ng.ng_range(*src), ng.ng_range(*tgt), ng.conn_spec(rule, k),
+                            ng.syn_spec(w, d), h)
+
+
+def test_plan_counts(L):
+    assert _count(100, "one_to_one", (0, 10), (50, 10)) == 10
+    assert _count(100, "all_to_all", (0, 7), (10, 9)) == 63
+    assert _count(100, "fixed_indegree", (0, 7), (10, 9), 4) == 36
+    assert _count(100, "fixed_outdegree", (0, 7), (10, 9), 4) == 28
+    assert _count(100, "fixed_total_number", (0, 7), (10, 9), 12345) == 12345
+    assert _count(100, "fixed_total_number", (0, 7), (10, 9), 0) == 0
+    assert _count(100, "all_to_all", (0, 0), (10, 9)) == 0
+
+
+@pytest.mark.parametrize("args,status", [
+    ((100, "one_to_one", (0, 10), (50, 11)), ng.NG_ERR_INVALID_ARG),       # Eqs. (4)-(5) need N_s = N_t
+    ((100, "all_to_all", (95, 10), (0, 5)), ng.NG_ERR_INVALID_ARG),        # range past the created nodes
+    ((100, "fixed_indegree", (0, 0), (0, 5), 3), ng.NG_ERR_INVALID_ARG),   # no sources to draw from
+    ((100, "fixed_outdegree", (0, 5), (0, 0), 3), ng.NG_ERR_INVALID_ARG),
+    ((100, "fixed_total_number", (0, 5), (0, 0), 3), ng.NG_ERR_INVALID_ARG),
+    ((100_000, "all_to_all", (0, 70_000), (0, 70_000)), ng.NG_ERR_TOO_LARGE),
+])
+def test_plan_errors(L, args, status):
+    with pytest.raises(ng.NGError) as e:
+        _count(*args)
+    assert e.value.status == status
+
+
+def test_spec_errors(L):
+    bad = [
+        dict(w=("normal", 0.5, -1.0)),
+        dict(w=("uniform", 2.0, 1.0)),
+        dict(w=("uniform_int", 1, 2)),
+        dict(d=("uniform_int", 0, 5)),
+        dict(d=("uniform_int", 1.5, 5)),
+        dict(d=("uniform_int", 1, 40000)),
+        dict(d=("normal", 1.0, 0.1)),
+        dict(d=("const", 10000.0)),       # 100000 steps at h = 0.1
+    ]
+    for kw in bad:
+        with pytest.raises(ng.NGError) as e:
+            _count(100, "all_to_all", (0, 3), (0, 3), **kw)
+        assert e.value.status == ng.NG_ERR_INVALID_ARG, kw
+
+
+def test_autapse_multapse_flags(L):
+    spec = ng.conn_spec("fixed_indegree", 3, allow_autapses=0)
+    syn = ng.syn_spec(("const", 1.0), ("const", 1.0))
+    # disjoint ranges: autapses cannot occur, accepted
+    assert ng.ng_plan_count(10, ng.ng_range(0, 5), ng.ng_range(5, 5), spec, syn, 0.1) == 15
+    with pytest.raises(ng.NGError) as e:
+        ng.ng_plan_count(10, ng.ng_range(0, 5), ng.ng_range(3, 5), spec, syn, 0.1)
+    assert e.value.status == ng.NG_ERR_UNSUPPORTED
+    with pytest.raises(ng.NGError) as e:
+        ng.ng_plan_count(10, ng.ng_range(0, 5), ng.ng_range(5, 5),
+                         ng.conn_spec("fixed_indegree", 3, allow_multapses=0), syn, 0.1)
+    assert e.value.status == ng.NG_ERR_UNSUPPORTED
+
+
+def test_arena_for_sizes():
+    from paper_2306_09855_amd.network import arena_bytes_for
+    assert arena_bytes_for(300_000_000, 77169, 30) > 2 * 14 * 300_000_000
+    assert arena_bytes_for(0, 1) > 0
