@@ -39,10 +39,11 @@ def algorithmic_bytes(kernel: str, n_syn: int, passes: int) -> float | None:
     per = {
         "generate": 14.0,                 # write src, tgt, w, delay once
         "generate_batch": 14.0,
-        "downsweep": 26.0 * passes,       # read one record, write one record, per pass
-        "upsweep": 6.0 + 4.0 * (passes - 1),  # read the key (src + delay, then key)
+        # per pass: read one record, write one record (14 B SoA at the ends, 12 B key+payload between)
+        "downsweep": 26.0 * 2 + 24.0 * (passes - 2) if passes >= 2 else 28.0,
+        "upsweep": 6.0 + 4.0 * (passes - 1),  # read the keys (src + delay, then key words)
         "group_flags": 6.0,               # read src + delay
-        "group_write": 6.0,
+        "group_write": 6.0,               # read src + delay again
     }.get(kernel)
     return None if per is None else per * n_syn
 
@@ -67,11 +68,13 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--batched", action="store_true", help="use ng_connect_batch for the 64 calls")
-    ap.add_argument("--radix-bits", type=int, default=11)
-    ap.add_argument("--ranges", type=int, default=1024)
+    ap.add_argument("--radix-bits", type=int, default=8)
+    ap.add_argument("--sort-ranges", type=int, default=1024, help="static ranges (workgroups) of each sort pass")
     ap.add_argument("--block-size", type=int, default=1 << 24)
     ap.add_argument("--cpu-sample", type=float, default=1.5e7, help="synapses of the oracle sample; 0 skips")
     ap.add_argument("--total", type=float, default=3.0e8)
+    ap.add_argument("--copy-probe", type=float, default=0,
+                    help="only run a plain device copy of this many bytes (calibrates counter readings)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -81,6 +84,15 @@ def main() -> int:
         return 2
 
     import torch
+    if args.copy_probe:
+        n = int(args.copy_probe)
+        a = torch.ones(n, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n}))
+        return 0
     from paper_2306_09855_amd import ng
     from paper_2306_09855_amd import workloads as W
     from paper_2306_09855_amd.network import Network, arena_bytes_for
@@ -92,7 +104,7 @@ def main() -> int:
     log(f"workload microcircuit: {wl.n_nodes} nodes, {len(wl.calls)} calls, {n_syn:.3g} synapses, "
         f"arena {arena / 2**30:.1f} GiB")
     net = Network(wl.seed, wl.h, args.block_size, arena)
-    net.tune(args.radix_bits, args.ranges)
+    net.tune(args.radix_bits, args.sort_ranges)
     ctx = net.ctx
     calls = [ng.call_args(c) for c in wl.calls]
     batch = [list(x) for x in zip(*calls)]
@@ -165,7 +177,7 @@ def main() -> int:
         "config": {"workload": "microcircuit", "n_nodes": wl.n_nodes, "n_calls": len(wl.calls),
                    "n_syn": n_syn, "rule": "fixed_total_number", "delays": "uniform_int 1..30",
                    "weights": "normal fp32", "form": "batched" if args.batched else "plain",
-                   "block_size": args.block_size, "radix_bits": args.radix_bits, "ranges": args.ranges,
+                   "block_size": args.block_size, "radix_bits": args.radix_bits, "sort_ranges": args.sort_ranges,
                    "sort_passes": passes},
         "device_ms_per_step": round(dev_ms / args.steps, 4),
         "path_roofline": {"algorithmic_bytes_per_step": path_alg,

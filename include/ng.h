@@ -179,10 +179,12 @@ int ng_copy_connections(ng_ctx* ctx, uint64_t first, uint64_t count, uint32_t* s
  * calibration.  Synchronizes.  NG_ERR_STATE if not calibrated. */
 int ng_copy_group_index(ng_ctx* ctx, uint32_t* group_ptr, uint32_t* group_start);
 
-/* Calibration schedule: radix digit width in bits (4..11; default 11) and
- * the number of static ranges the sort passes split the input into (8..65536;
- * default 1024).  Results do not depend on either; speed does. */
-int ng_set_tuning(ng_ctx* ctx, int radix_bits, uint32_t target_ranges);
+/* Calibration schedule: the widest radix digit in bits (4..9; default 8) --
+ * the key bits are split into the fewest passes of at most that width -- and
+ * the number of static ranges (one workgroup each) a sort pass splits the
+ * connections into (1..2^20; default 1024).  Results do not depend on either;
+ * speed does. */
+int ng_set_tuning(ng_ctx* ctx, int radix_bits, uint32_t sort_ranges);
 
 /* Arena bytes in use now, at peak, and the largest free extent. */
 int ng_memory_stats(ng_ctx* ctx, uint64_t* used, uint64_t* peak, uint64_t* largest_free);

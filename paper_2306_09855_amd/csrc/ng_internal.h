@@ -43,11 +43,10 @@ hipError_t launch_generate_batch(const GenDesc* d_descs, uint32_t n_calls, uint6
 
 // --- calibration ----------------------------------------------------------
 struct SortGeom {
-  uint64_t n;              // records
-  uint32_t tile;           // records per tile
-  uint32_t tiles_per_range;
+  uint64_t n;               // records
+  uint32_t tiles_per_range; // consecutive tiles of one range
   uint32_t n_ranges;
-  uint32_t ranges_per_xcd; // launch = 8 * ranges_per_xcd workgroups
+  uint32_t ranges_per_xcd;  // launch = 8 * ranges_per_xcd workgroups
 };
 
 struct SortIO {
@@ -63,10 +62,15 @@ struct SortIO {
   uint32_t dbits;           // key = src << dbits | delay
 };
 
-int sort_tile_size(int radix_bits);
-hipError_t launch_upsweep(const SortGeom& g, const SortIO& io, int radix_bits, uint32_t shift,
+// Records per sort tile; the block size must be a multiple of it.
+uint32_t sort_tile_size();
+int sort_max_radix_bits();
+
+// Digit counts of each range: counts[d * n_ranges + r] for d < 2^nbits.
+hipError_t launch_upsweep(const SortGeom& g, const SortIO& io, uint32_t shift, uint32_t nbits,
                           uint32_t* counts, hipStream_t s);
-hipError_t launch_downsweep(const SortGeom& g, const SortIO& io, int radix_bits, uint32_t shift,
+// One stable digit pass; offsets = exclusive scan of the counts.
+hipError_t launch_downsweep(const SortGeom& g, const SortIO& io, uint32_t shift, uint32_t nbits,
                             const uint32_t* offsets, hipStream_t s);
 
 // Exclusive scan of n u32 values (in may equal out).  tmp needs
@@ -81,12 +85,20 @@ hipError_t launch_set_ptrs(char** tab, uint32_t first, uint32_t count, const uin
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, uint64_t n, hipStream_t s);
 
-// Connection-group index over sorted blocked SoA (Sec. 2.2, Eq. (14)).
-//   tile_flags[n_tiles] (scratch), G[n_nodes+1] zeroed before the call.
+// Connection-group index over sorted blocked SoA (Sec. 2.2, Eq. (14)):
+//   flags      bitmap[ceil(n/32)] of group starts and, per tile of
+//              gi_tile_size() positions, the number of groups starting in it
+//   write      with tile_base = exclusive scan of the tile counts:
+//              group_start[g] and group_src[g] for every group, and
+//              group_start[G] = n
+//   ptr        group_ptr[i], i = 0..n_nodes, from group_src by binary search
 uint32_t gi_tile_size();
-hipError_t launch_group_flags(char* const* blocks, int log2B, uint64_t n, uint32_t* tile_flags,
-                              uint32_t* G, hipStream_t s);
-hipError_t launch_group_write(char* const* blocks, int log2B, uint64_t n,
-                              const uint32_t* tile_base, uint32_t* group_start, hipStream_t s);
+hipError_t launch_group_flags(char* const* blocks, int log2B, uint64_t n, uint32_t* bitmap,
+                              uint32_t* tile_flags, hipStream_t s);
+hipError_t launch_group_write(char* const* blocks, int log2B, uint64_t n, const uint32_t* bitmap,
+                              const uint32_t* tile_base, uint32_t* group_start, uint32_t* group_src,
+                              hipStream_t s);
+hipError_t launch_group_ptr(const uint32_t* group_src, const uint32_t* n_groups, uint32_t n_nodes,
+                            uint32_t* group_ptr, hipStream_t s);
 
 }  // namespace ng

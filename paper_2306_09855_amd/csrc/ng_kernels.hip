@@ -6,14 +6,8 @@
 // transforms -- and stores them into the block-structured SoA storage.
 //
 // Calibration (Sec. 2.2): a stable LSD radix sort by key = src << dbits |
-// delay, built from reduce-then-scan passes over static ranges:
-//   upsweep    per-range digit histogram (LDS atomics)
-//   scan       device-wide exclusive scan of the digit-major count matrix
-//   downsweep  per tile: stable wave64 ballot ranking, LDS staging, then
-//              runs of equal digits written to their global positions
-// Ranges are laid out XCD-aware: workgroup w runs on XCD w % 8, and each XCD
-// gets a contiguous span of ranges, so the output runs of neighbouring
-// ranges meet in one L2.  Then the connection-group index (Eq. (14)).
+// delay, in reduce-then-scan digit passes over XCD-aware static ranges (see
+// the sort section), then the connection-group index (Eq. (14)).
 #include "ng_internal.h"
 
 namespace ng {
@@ -287,10 +281,32 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s
 }
 
 // ---------------------------------------------------------------------------
-// Radix sort passes
+// Radix sort: reduce-then-scan digit passes over static ranges of tiles.
+// No workgroup waits on another inside a pass: on this chip each XCD has its
+// own L2, so a chained (look-back) scan pays an agent-scope round trip per
+// tile, while per-range counts cost only one extra read of the keys.
+//   upsweep    range r counts the digits of its records
+//   scan       exclusive scan of the digit-major count matrix -> offsets
+//   downsweep  range r walks its tiles in order: stable wave64 ballot ranks,
+//              LDS staging by digit (keys, then payloads, through one
+//              buffer), runs of equal digits stored to consecutive positions.
+// Tiles are large (10,240 records, 512 threads) because the cost of a pass
+// is set by the length of the runs each tile writes per digit.  Ranges are
+// XCD-aware: workgroup w runs on XCD w % 8, and each XCD owns a contiguous
+// span of ranges, so the runs written by neighbouring ranges meet in one L2.
 // ---------------------------------------------------------------------------
-constexpr int kItems = 16;
-constexpr int kTile = kThreads * kItems;  // 4096 records
+constexpr int kSortThreads = 512;
+constexpr int kSortWaves = kSortThreads / 64;
+constexpr int kItems = 20;
+constexpr int kTile = kSortThreads * kItems;  // 10,240 records
+constexpr int kMaxRadixBits = 9;
+
+// Barrier for LDS hand-offs only: global loads and stores stay in flight.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 
 __device__ __forceinline__ int range_index(const SortGeom& g) {
   const uint32_t w = blockIdx.x;
@@ -298,209 +314,259 @@ __device__ __forceinline__ int range_index(const SortGeom& g) {
   return r < g.n_ranges ? (int)r : -1;
 }
 
-template <bool IN_BLOCKED>
-__device__ __forceinline__ uint32_t load_key(const SortIO& io, uint64_t j) {
-  if constexpr (IN_BLOCKED) {
-    const uint64_t B = 1ull << io.log2B;
-    const char* base = io.in_blocks[j >> io.log2B];
-    const uint64_t o = j & (B - 1);
-    const uint32_t s = reinterpret_cast<const uint32_t*>(base)[o];
-    const uint32_t dl = (uint16_t)reinterpret_cast<const int16_t*>(base + 12 * B)[o];
-    return (s << io.dbits) | dl;
-  } else {
-    return io.in_keys[j];
-  }
+// Blocked SoA source of one tile: a tile spans at most two blocks.
+struct TileSrc {
+  const char* blk[2];
+  uint64_t first_block;
+};
+
+__device__ __forceinline__ TileSrc tile_src(const SortIO& io, uint64_t base) {
+  TileSrc t;
+  t.first_block = base >> io.log2B;
+  t.blk[0] = io.in_blocks[t.first_block];
+  const uint64_t last = (base + kTile - 1) >> io.log2B;
+  t.blk[1] = last != t.first_block ? io.in_blocks[t.first_block + 1] : t.blk[0];
+  return t;
+}
+
+__device__ __forceinline__ void load_blocked(const SortIO& io, const TileSrc& t, uint64_t j, uint32_t& key,
+                                             uint2& pay) {
+  const uint64_t B = 1ull << io.log2B;
+  const char* blk = t.blk[(j >> io.log2B) != t.first_block];
+  const uint64_t o = j & (B - 1);
+  key = (reinterpret_cast<const uint32_t*>(blk)[o] << io.dbits) |
+        (uint16_t) reinterpret_cast<const int16_t*>(blk + 12 * B)[o];
+  pay = make_uint2(reinterpret_cast<const uint32_t*>(blk + 4 * B)[o],
+                   reinterpret_cast<const uint32_t*>(blk + 8 * B)[o]);
+}
+
+__device__ __forceinline__ uint32_t load_blocked_key(const SortIO& io, const TileSrc& t, uint64_t j) {
+  const uint64_t B = 1ull << io.log2B;
+  const char* blk = t.blk[(j >> io.log2B) != t.first_block];
+  const uint64_t o = j & (B - 1);
+  return (reinterpret_cast<const uint32_t*>(blk)[o] << io.dbits) |
+         (uint16_t) reinterpret_cast<const int16_t*>(blk + 12 * B)[o];
 }
 
 template <int RB, bool IN_BLOCKED>
-__global__ __launch_bounds__(kThreads) void k_upsweep(SortGeom g, SortIO io, uint32_t shift,
-                                                      uint32_t nbits, uint32_t* __restrict__ counts) {
+__global__ __launch_bounds__(kSortThreads) void k_upsweep(SortGeom g, SortIO io, uint32_t shift,
+                                                          uint32_t nbits, uint32_t* __restrict__ counts) {
   constexpr int NB = 1 << RB;
   __shared__ uint32_t hist[NB];
   const int r = range_index(g);
   if (r < 0) return;
   const uint32_t nd = 1u << nbits, mask = nd - 1;
-  for (uint32_t d = threadIdx.x; d < nd; d += kThreads) hist[d] = 0;
+  for (uint32_t d = threadIdx.x; d < nd; d += kSortThreads) hist[d] = 0;
   __syncthreads();
   const uint64_t start = (uint64_t)r * g.tiles_per_range * kTile;
   const uint64_t end = min(start + (uint64_t)g.tiles_per_range * kTile, g.n);
-  for (uint64_t base = start; base < end; base += kTile) {
-    uint32_t key[kItems];
-#pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-      const uint64_t j = base + k * kThreads + threadIdx.x;
-      key[k] = j < end ? load_key<IN_BLOCKED>(io, j) : 0u;
-    }
-#pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-      const uint64_t j = base + k * kThreads + threadIdx.x;
-      if (j < end) atomicAdd(&hist[(key[k] >> shift) & mask], 1u);
-    }
-  }
-  __syncthreads();
-  for (uint32_t d = threadIdx.x; d < nd; d += kThreads) counts[(uint64_t)d * g.n_ranges + r] = hist[d];
-}
-
-template <int RB, bool IN_BLOCKED, bool OUT_BLOCKED>
-__global__ __launch_bounds__(kThreads) void k_downsweep(SortGeom g, SortIO io, uint32_t shift,
-                                                        uint32_t nbits,
-                                                        const uint32_t* __restrict__ offsets) {
-  constexpr int NB = 1 << RB;
-  __shared__ uint32_t s_keys[kTile];
-  __shared__ uint2 s_pay[kTile];
-  __shared__ uint32_t s_wh[kWaves][NB];  // per-wave digit counts, then per-wave prefixes
-  __shared__ uint32_t s_start[NB + 1];   // tile-local digit starts
-  __shared__ uint32_t s_run[NB];         // next global position per digit
-  __shared__ uint32_t s_tmp[kWaves];
-
-  const int r = range_index(g);
-  if (r < 0) return;
-  const uint32_t nd = 1u << nbits, mask = nd - 1;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (uint32_t d = threadIdx.x; d < nd; d += kThreads) {
-    s_run[d] = offsets[(uint64_t)d * g.n_ranges + r];
-#pragma unroll
-    for (int v = 0; v < kWaves; ++v) s_wh[v][d] = 0;
-  }
-  __syncthreads();
-
-  const uint64_t start = (uint64_t)r * g.tiles_per_range * kTile;
-  const uint64_t end = min(start + (uint64_t)g.tiles_per_range * kTile, g.n);
-  const uint64_t B = 1ull << io.log2B;
-  const uint32_t dmask = (1u << io.dbits) - 1;
-
   for (uint64_t base = start; base < end; base += kTile) {
     const uint32_t cnt = (uint32_t)min((uint64_t)kTile, end - base);
-    // wave w ranks tile records [w*1024, (w+1)*1024) in 16 batches of 64, in order
     uint32_t key[kItems];
-    uint2 pay[kItems];
     if constexpr (IN_BLOCKED) {
-      const char* blk = io.in_blocks[base >> io.log2B];
-      const uint64_t o0 = base & (B - 1);
-      const uint32_t* src = reinterpret_cast<const uint32_t*>(blk) + o0;
-      const uint32_t* tgt = reinterpret_cast<const uint32_t*>(blk + 4 * B) + o0;
-      const uint32_t* wb = reinterpret_cast<const uint32_t*>(blk + 8 * B) + o0;
-      const int16_t* del = reinterpret_cast<const int16_t*>(blk + 12 * B) + o0;
+      const TileSrc ts = tile_src(io, base);
 #pragma unroll
       for (int k = 0; k < kItems; ++k) {
-        const uint32_t lj = (uint32_t)(wave * kItems * 64 + k * 64 + lane);
-        if (lj < cnt) {
-          key[k] = (src[lj] << io.dbits) | (uint16_t)del[lj];
-          pay[k] = make_uint2(tgt[lj], wb[lj]);
-        } else {
-          key[k] = 0;
-          pay[k] = make_uint2(0, 0);
-        }
+        const uint32_t lj = k * kSortThreads + threadIdx.x;
+        key[k] = lj < cnt ? load_blocked_key(io, ts, base + lj) : 0u;
       }
     } else {
 #pragma unroll
       for (int k = 0; k < kItems; ++k) {
-        const uint32_t lj = (uint32_t)(wave * kItems * 64 + k * 64 + lane);
-        if (lj < cnt) {
-          key[k] = io.in_keys[base + lj];
-          pay[k] = io.in_pay[base + lj];
-        } else {
-          key[k] = 0;
-          pay[k] = make_uint2(0, 0);
-        }
+        const uint32_t lj = k * kSortThreads + threadIdx.x;
+        key[k] = lj < cnt ? io.in_keys[base + lj] : 0u;
       }
     }
+#pragma unroll
+    for (int k = 0; k < kItems; ++k)
+      if ((uint32_t)(k * kSortThreads + threadIdx.x) < cnt) atomicAdd(&hist[(key[k] >> shift) & mask], 1u);
+  }
+  __syncthreads();
+  for (uint32_t d = threadIdx.x; d < nd; d += kSortThreads) counts[(uint64_t)d * g.n_ranges + r] = hist[d];
+}
 
-    uint32_t rank[kItems];
+struct SortLds {
+  uint2* buf;                       // kTile staging words
+  uint32_t* key;                    // the same buffer seen as 32-bit words
+  uint32_t* wh;                     // [kSortWaves][NB]: per-wave digit counts, then prefixes
+  uint32_t* start;                  // [NB + 1] tile-local digit starts
+  uint32_t* run;                    // [NB] next global position per digit
+  uint32_t* tmp;                    // [kSortWaves]
+};
+
+// One tile of a digit pass.  FULL: all kTile records present (no predicates).
+// RB bounds the digit width; digits are masked to nbits, so the ballots for
+// bits nbits..RB-1 see all-zero bits and leave the peer masks unchanged.
+template <int RB, bool IN_BLOCKED, bool OUT_BLOCKED, bool FULL>
+__device__ __forceinline__ void sort_tile(const SortIO& io, uint64_t base, uint32_t cnt, uint32_t shift,
+                                          uint32_t nbits, const SortLds& L) {
+  constexpr int NB = 1 << RB;
+  const uint32_t nd = 1u << nbits, mask = nd - 1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t B = 1ull << io.log2B;
+
+  // wave w owns tile records [w*kItems*64, (w+1)*kItems*64), ranked in batches of 64
+  uint32_t key[kItems];
+  uint2 pay[kItems];
+  if constexpr (IN_BLOCKED) {
+    const TileSrc ts = tile_src(io, base);
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
       const uint32_t lj = (uint32_t)(wave * kItems * 64 + k * 64 + lane);
-      const bool valid = lj < cnt;
+      if (FULL || lj < cnt) load_blocked(io, ts, base + lj, key[k], pay[k]);
+      else { key[k] = 0; pay[k] = make_uint2(0, 0); }
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      const uint32_t lj = (uint32_t)(wave * kItems * 64 + k * 64 + lane);
+      if (FULL || lj < cnt) {
+        key[k] = io.in_keys[base + lj];
+        pay[k] = io.in_pay[base + lj];
+      } else {
+        key[k] = 0;
+        pay[k] = make_uint2(0, 0);
+      }
+    }
+  }
+
+  // stable rank of each record among the earlier records of its digit
+  uint32_t pos[kItems];
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    const uint32_t lj = (uint32_t)(wave * kItems * 64 + k * 64 + lane);
+    const bool valid = FULL || lj < cnt;
+    const uint32_t dg = (key[k] >> shift) & mask;
+    uint64_t peers = FULL ? ~0ull : __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      const bool bit = (dg >> b) & 1u;
+      const uint64_t m = __ballot(bit);
+      peers &= bit ? m : ~m;
+    }
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(peers >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
+    const uint32_t tot = (uint32_t)__popcll(peers);
+    uint32_t prev = 0;
+    if (valid) prev = L.wh[wave * NB + dg];
+    if (valid && below == 0) L.wh[wave * NB + dg] = prev + tot;
+    pos[k] = prev + below;
+  }
+  lds_barrier();
+
+  // per digit: prefixes over waves and the tile count
+  for (uint32_t d = threadIdx.x; d < nd; d += kSortThreads) {
+    uint32_t acc = 0;
+#pragma unroll
+    for (int v = 0; v < kSortWaves; ++v) {
+      const uint32_t c = L.wh[v * NB + d];
+      L.wh[v * NB + d] = acc;
+      acc += c;
+    }
+    L.start[d] = acc;
+  }
+  lds_barrier();
+  {  // tile-local digit starts: exclusive scan of the tile counts
+    const uint32_t d = threadIdx.x;  // NB <= kSortThreads
+    const uint32_t local = d < nd ? L.start[d] : 0u;
+    const uint32_t inc = wave_inclusive_scan(local);
+    if (lane == 63) L.tmp[wave] = inc;
+    lds_barrier();
+    uint32_t run = inc - local;
+#pragma unroll
+    for (int w = 0; w < kSortWaves; ++w)
+      if (w < wave) run += L.tmp[w];
+    if (d < nd) L.start[d] = run;
+    if (threadIdx.x == 0) L.start[nd] = cnt;
+  }
+  lds_barrier();
+
+  // phase 1: keys staged by digit, stored as runs of equal digits
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    const uint32_t lj = (uint32_t)(wave * kItems * 64 + k * 64 + lane);
+    if (FULL || lj < cnt) {
       const uint32_t dg = (key[k] >> shift) & mask;
-      uint64_t peers = __ballot(valid);
-#pragma unroll
-      for (int b = 0; b < RB; ++b) {
-        if ((uint32_t)b < nbits) {
-          const bool bit = (dg >> b) & 1u;
-          const uint64_t m = __ballot(bit);
-          peers &= bit ? m : ~m;
-        }
-      }
-      const uint32_t below = __builtin_amdgcn_mbcnt_hi(
-          (uint32_t)(peers >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
-      const uint32_t tot = (uint32_t)__popcll(peers);
-      uint32_t prev = 0;
-      if (valid) prev = s_wh[wave][dg];
-      if (valid && below == 0) s_wh[wave][dg] = prev + tot;
-      rank[k] = prev + below;
+      pos[k] += L.start[dg] + L.wh[wave * NB + dg];
+      L.key[pos[k]] = key[k];
     }
-    __syncthreads();
+  }
+  lds_barrier();
+  const uint32_t dmask = (1u << io.dbits) - 1;
+  uint32_t dest[kItems];
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    const uint32_t lp = (uint32_t)(k * kSortThreads + threadIdx.x);
+    if (FULL || lp < cnt) {
+      const uint32_t kk = L.key[lp];
+      const uint32_t dg = (kk >> shift) & mask;
+      dest[k] = L.run[dg] + (lp - L.start[dg]);
+      if constexpr (OUT_BLOCKED) {
+        char* blk = io.out_blocks[dest[k] >> io.log2B];
+        const uint64_t o = dest[k] & (B - 1);
+        reinterpret_cast<uint32_t*>(blk)[o] = kk >> io.dbits;
+        reinterpret_cast<int16_t*>(blk + 12 * B)[o] = (int16_t)(kk & dmask);
+      } else {
+        io.out_keys[dest[k]] = kk;
+      }
+    }
+  }
+  lds_barrier();
+  // phase 2: payloads through the same buffer
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    const uint32_t lj = (uint32_t)(wave * kItems * 64 + k * 64 + lane);
+    if (FULL || lj < cnt) L.buf[pos[k]] = pay[k];
+  }
+  for (uint32_t d = threadIdx.x; d < nd; d += kSortThreads) {
+    L.run[d] += L.start[d + 1] - L.start[d];
+#pragma unroll
+    for (int v = 0; v < kSortWaves; ++v) L.wh[v * NB + d] = 0;
+  }
+  lds_barrier();
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    const uint32_t lp = (uint32_t)(k * kSortThreads + threadIdx.x);
+    if (FULL || lp < cnt) {
+      const uint2 pp = L.buf[lp];
+      if constexpr (OUT_BLOCKED) {
+        char* blk = io.out_blocks[dest[k] >> io.log2B];
+        const uint64_t o = dest[k] & (B - 1);
+        reinterpret_cast<uint32_t*>(blk + 4 * B)[o] = pp.x;
+        reinterpret_cast<uint32_t*>(blk + 8 * B)[o] = pp.y;
+      } else {
+        io.out_pay[dest[k]] = pp;
+      }
+    }
+  }
+  lds_barrier();  // the buffer is reused by the next tile
+}
 
-    // per digit: prefixes over waves and the tile total
-    for (uint32_t d = threadIdx.x; d < nd; d += kThreads) {
-      uint32_t acc = 0;
+template <int RB, bool IN_BLOCKED, bool OUT_BLOCKED>
+__global__ __launch_bounds__(kSortThreads) void k_downsweep(SortGeom g, SortIO io, uint32_t shift,
+                                                            uint32_t nbits, const uint32_t* __restrict__ offsets) {
+  constexpr int NB = 1 << RB;
+  __shared__ uint2 s_buf[kTile];
+  __shared__ uint32_t s_wh[kSortWaves * NB];
+  __shared__ uint32_t s_start[NB + 1];
+  __shared__ uint32_t s_run[NB];
+  __shared__ uint32_t s_tmp[kSortWaves];
+  const SortLds L{s_buf, reinterpret_cast<uint32_t*>(s_buf), s_wh, s_start, s_run, s_tmp};
+  const int r = range_index(g);
+  if (r < 0) return;
+  const uint32_t nd = 1u << nbits;
+  for (uint32_t d = threadIdx.x; d < nd; d += kSortThreads) {
+    s_run[d] = offsets[(uint64_t)d * g.n_ranges + r];
 #pragma unroll
-      for (int v = 0; v < kWaves; ++v) {
-        const uint32_t c = s_wh[v][d];
-        s_wh[v][d] = acc;
-        acc += c;
-      }
-      s_start[d] = acc;
-    }
-    __syncthreads();
-    {  // exclusive scan of the tile's digit totals; each thread owns a run of digits
-      const uint32_t per = (nd + kThreads - 1) / kThreads;
-      const uint32_t d0 = threadIdx.x * per;
-      uint32_t local = 0;
-      for (uint32_t d = d0; d < min(d0 + per, nd); ++d) local += s_start[d];
-      uint32_t total;
-      uint32_t run = block_exclusive_scan(local, s_tmp, &total);
-      for (uint32_t d = d0; d < min(d0 + per, nd); ++d) {
-        const uint32_t c = s_start[d];
-        s_start[d] = run;
-        run += c;
-      }
-      if (threadIdx.x == 0) s_start[nd] = total;
-    }
-    __syncthreads();
-
-    // stable placement inside the tile
-#pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-      const uint32_t lj = (uint32_t)(wave * kItems * 64 + k * 64 + lane);
-      if (lj < cnt) {
-        const uint32_t dg = (key[k] >> shift) & mask;
-        const uint32_t lp = s_start[dg] + s_wh[wave][dg] + rank[k];
-        s_keys[lp] = key[k];
-        s_pay[lp] = pay[k];
-      }
-    }
-    __syncthreads();
-
-    // runs of equal digits go to consecutive global positions
-#pragma unroll 4
-    for (int k = 0; k < kItems; ++k) {
-      const uint32_t lp = (uint32_t)(k * kThreads + threadIdx.x);
-      if (lp < cnt) {
-        const uint32_t kk = s_keys[lp];
-        const uint2 pp = s_pay[lp];
-        const uint32_t dg = (kk >> shift) & mask;
-        const uint64_t dest = (uint64_t)s_run[dg] + (lp - s_start[dg]);
-        if constexpr (OUT_BLOCKED) {
-          char* blk = io.out_blocks[dest >> io.log2B];
-          const uint64_t o = dest & (B - 1);
-          reinterpret_cast<uint32_t*>(blk)[o] = kk >> io.dbits;
-          reinterpret_cast<uint32_t*>(blk + 4 * B)[o] = pp.x;
-          reinterpret_cast<uint32_t*>(blk + 8 * B)[o] = pp.y;
-          reinterpret_cast<int16_t*>(blk + 12 * B)[o] = (int16_t)(kk & dmask);
-        } else {
-          io.out_keys[dest] = kk;
-          io.out_pay[dest] = pp;
-        }
-      }
-    }
-    __syncthreads();
-    for (uint32_t d = threadIdx.x; d < nd; d += kThreads) {
-      s_run[d] += s_start[d + 1] - s_start[d];
-#pragma unroll
-      for (int v = 0; v < kWaves; ++v) s_wh[v][d] = 0;
-    }
-    __syncthreads();
+    for (int v = 0; v < kSortWaves; ++v) s_wh[v * NB + d] = 0;
+  }
+  lds_barrier();
+  const uint64_t start = (uint64_t)r * g.tiles_per_range * kTile;
+  const uint64_t end = min(start + (uint64_t)g.tiles_per_range * kTile, g.n);
+  for (uint64_t base = start; base < end; base += kTile) {
+    const uint32_t cnt = (uint32_t)min((uint64_t)kTile, end - base);
+    if (cnt == kTile) sort_tile<RB, IN_BLOCKED, OUT_BLOCKED, true>(io, base, cnt, shift, nbits, L);
+    else sort_tile<RB, IN_BLOCKED, OUT_BLOCKED, false>(io, base, cnt, shift, nbits, L);
   }
 }
 
@@ -579,79 +645,108 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t value, uint64_t n) {
 // ---------------------------------------------------------------------------
 // Connection-group index (Sec. 2.2): a connection opens a group when its
 // source or delay differs from those of the previous connection.
+//   flags: coalesced reads of (src, delay) at j and j-1, one wave64 ballot
+//          per 64 positions -> a bitmap of group starts and per-tile counts
+//   write: one thread per 32-bit bitmap word; a workgroup scan of the word
+//          popcounts places every group start in order
 // ---------------------------------------------------------------------------
-constexpr int kGiItems = 16;
-constexpr int kGiTile = kThreads * kGiItems;
+constexpr int kGiItems = 32;
+constexpr int kGiTile = kThreads * kGiItems;  // 8,192 positions = 256 bitmap words
 
-__device__ __forceinline__ void load_src_delay(char* const* __restrict__ blocks, int log2B, uint64_t j,
-                                               uint32_t& s, int32_t& dl) {
+__device__ __forceinline__ uint64_t group_key(char* const* __restrict__ blocks, int log2B, uint64_t j) {
   const uint64_t B = 1ull << log2B;
-  const char* base = blocks[j >> log2B];
+  const char* blk = blocks[j >> log2B];
   const uint64_t o = j & (B - 1);
-  s = reinterpret_cast<const uint32_t*>(base)[o];
-  dl = reinterpret_cast<const int16_t*>(base + 12 * B)[o];
-}
-
-__device__ __forceinline__ bool opens_group(char* const* __restrict__ blocks, int log2B, uint64_t j,
-                                            uint32_t& s) {
-  int32_t dl;
-  load_src_delay(blocks, log2B, j, s, dl);
-  if (j == 0) return true;
-  uint32_t ps;
-  int32_t pd;
-  load_src_delay(blocks, log2B, j - 1, ps, pd);
-  return ps != s || pd != dl;
+  return ((uint64_t) reinterpret_cast<const uint32_t*>(blk)[o] << 16) |
+         (uint16_t) reinterpret_cast<const int16_t*>(blk + 12 * B)[o];
 }
 
 __global__ __launch_bounds__(kThreads) void k_group_flags(char* const* __restrict__ blocks, int log2B,
-                                                          uint64_t n, uint32_t* __restrict__ tile_flags,
-                                                          uint32_t* __restrict__ G) {
+                                                          uint64_t n, uint32_t* __restrict__ bitmap,
+                                                          uint32_t* __restrict__ tile_flags) {
   __shared__ uint32_t s_tmp[kWaves];
-  const uint64_t base = (uint64_t)blockIdx.x * kGiTile + (uint64_t)threadIdx.x * kGiItems;
+  const uint64_t base = (uint64_t)blockIdx.x * kGiTile;
+  const uint64_t B = 1ull << log2B;
+  const char* blk = blocks[base >> log2B];  // kGiTile divides the block size
+  const uint64_t o0 = base & (B - 1);
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(blk) + o0;
+  const int16_t* del = reinterpret_cast<const int16_t*>(blk + 12 * B) + o0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t c = 0;
+#pragma unroll 8
   for (int k = 0; k < kGiItems; ++k) {
-    const uint64_t j = base + k;
+    const uint32_t lj = k * kThreads + threadIdx.x;  // 64 consecutive positions per wave
+    const uint64_t j = base + lj;
+    bool f = false;
     if (j < n) {
-      uint32_t s;
-      if (opens_group(blocks, log2B, j, s)) {
-        ++c;
-        atomicAdd(&G[s], 1u);
-      }
+      const uint64_t key = ((uint64_t)src[lj] << 16) | (uint16_t)del[lj];
+      uint64_t prev;
+      if (lj > 0) prev = ((uint64_t)src[lj - 1] << 16) | (uint16_t)del[lj - 1];
+      else prev = j > 0 ? group_key(blocks, log2B, j - 1) : ~0ull;
+      f = key != prev;
     }
+    const uint64_t m = __ballot(f);
+    if (lane == 0) {
+      const uint64_t w = (base + k * kThreads + wave * 64) >> 5;  // two bitmap words
+      if ((w << 5) < n) bitmap[w] = (uint32_t)m;
+      if (((w + 1) << 5) < n) bitmap[w + 1] = (uint32_t)(m >> 32);
+    }
+    c += f ? 1u : 0u;
   }
   uint32_t total;
   block_exclusive_scan(c, s_tmp, &total);
   if (threadIdx.x == 0) tile_flags[blockIdx.x] = total;
 }
 
+// group_start[g]: first connection of group g; group_src[g]: its source.
 __global__ __launch_bounds__(kThreads) void k_group_write(char* const* __restrict__ blocks, int log2B,
-                                                          uint64_t n, const uint32_t* __restrict__ tile_base,
-                                                          uint32_t* __restrict__ group_start) {
+                                                          uint64_t n, const uint32_t* __restrict__ bitmap,
+                                                          const uint32_t* __restrict__ tile_base,
+                                                          uint32_t* __restrict__ group_start,
+                                                          uint32_t* __restrict__ group_src) {
   __shared__ uint32_t s_tmp[kWaves];
-  const uint64_t base = (uint64_t)blockIdx.x * kGiTile + (uint64_t)threadIdx.x * kGiItems;
-  uint32_t f = 0;  // bit k: position base + k opens a group
-  for (int k = 0; k < kGiItems; ++k) {
-    const uint64_t j = base + k;
-    uint32_t s;
-    if (j < n && opens_group(blocks, log2B, j, s)) f |= 1u << k;
-  }
+  const uint64_t wbase = (uint64_t)blockIdx.x * kThreads + threadIdx.x;  // bitmap word of this thread
+  const uint64_t j0 = wbase << 5;
+  uint32_t bits = j0 < n ? bitmap[wbase] : 0u;
+  if (j0 < n && n - j0 < 32) bits &= (1u << (n - j0)) - 1;
   uint32_t total;
-  uint32_t gidx = tile_base[blockIdx.x] + block_exclusive_scan((uint32_t)__popc(f), s_tmp, &total);
-  for (int k = 0; k < kGiItems; ++k) {
-    const uint64_t j = base + k;
-    if (f & (1u << k)) group_start[gidx++] = (uint32_t)j;
-    if (j + 1 == n) group_start[gidx] = (uint32_t)n;  // group_start[G] = n
+  uint32_t g = tile_base[blockIdx.x] + block_exclusive_scan((uint32_t)__popc(bits), s_tmp, &total);
+  while (bits) {
+    const int b = __ffs(bits) - 1;
+    bits &= bits - 1;
+    const uint64_t j = j0 + b;
+    group_start[g] = (uint32_t)j;
+    group_src[g] = (uint32_t)(group_key(blocks, log2B, j) >> 16);
+    ++g;
+  }
+  if (j0 < n && n - j0 <= 32) group_start[g] = (uint32_t)n;  // the last word closes: group_start[G] = n
+}
+
+// Eq. (14): p_i = sum_{j<i} G_j = the number of groups whose source is below
+// i, found by binary search in the sorted group sources (i = 0..n_nodes).
+__global__ __launch_bounds__(kThreads) void k_group_ptr(const uint32_t* __restrict__ group_src,
+                                                        const uint32_t* __restrict__ n_groups, uint32_t n_nodes,
+                                                        uint32_t* __restrict__ group_ptr) {
+  const uint32_t G = *n_groups;
+  for (uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x; i <= n_nodes;
+       i += (uint64_t)gridDim.x * kThreads) {
+    uint32_t lo = 0, hi = G;  // first g with group_src[g] >= i
+    while (lo < hi) {
+      const uint32_t mid = lo + ((hi - lo) >> 1);
+      if (group_src[mid] < i) lo = mid + 1; else hi = mid;
+    }
+    group_ptr[i] = lo;
   }
 }
 
 template <int RB>
-hipError_t upsweep_rb(const SortGeom& g, const SortIO& io, uint32_t shift, uint32_t nbits,
-                      uint32_t* counts, hipStream_t s) {
+hipError_t upsweep_rb(const SortGeom& g, const SortIO& io, uint32_t shift, uint32_t nbits, uint32_t* counts,
+                      hipStream_t s) {
   const dim3 grid(8 * g.ranges_per_xcd);
   if (io.in_blocks)
-    hipLaunchKernelGGL((k_upsweep<RB, true>), grid, dim3(kThreads), 0, s, g, io, shift, nbits, counts);
+    hipLaunchKernelGGL((k_upsweep<RB, true>), grid, dim3(kSortThreads), 0, s, g, io, shift, nbits, counts);
   else
-    hipLaunchKernelGGL((k_upsweep<RB, false>), grid, dim3(kThreads), 0, s, g, io, shift, nbits, counts);
+    hipLaunchKernelGGL((k_upsweep<RB, false>), grid, dim3(kSortThreads), 0, s, g, io, shift, nbits, counts);
   return hipGetLastError();
 }
 
@@ -661,13 +756,13 @@ hipError_t downsweep_rb(const SortGeom& g, const SortIO& io, uint32_t shift, uin
   const dim3 grid(8 * g.ranges_per_xcd);
   const bool ib = io.in_blocks != nullptr, ob = io.out_blocks != nullptr;
   if (ib && ob)
-    hipLaunchKernelGGL((k_downsweep<RB, true, true>), grid, dim3(kThreads), 0, s, g, io, shift, nbits, offsets);
+    hipLaunchKernelGGL((k_downsweep<RB, true, true>), grid, dim3(kSortThreads), 0, s, g, io, shift, nbits, offsets);
   else if (ib)
-    hipLaunchKernelGGL((k_downsweep<RB, true, false>), grid, dim3(kThreads), 0, s, g, io, shift, nbits, offsets);
+    hipLaunchKernelGGL((k_downsweep<RB, true, false>), grid, dim3(kSortThreads), 0, s, g, io, shift, nbits, offsets);
   else if (ob)
-    hipLaunchKernelGGL((k_downsweep<RB, false, true>), grid, dim3(kThreads), 0, s, g, io, shift, nbits, offsets);
+    hipLaunchKernelGGL((k_downsweep<RB, false, true>), grid, dim3(kSortThreads), 0, s, g, io, shift, nbits, offsets);
   else
-    hipLaunchKernelGGL((k_downsweep<RB, false, false>), grid, dim3(kThreads), 0, s, g, io, shift, nbits, offsets);
+    hipLaunchKernelGGL((k_downsweep<RB, false, false>), grid, dim3(kSortThreads), 0, s, g, io, shift, nbits, offsets);
   return hipGetLastError();
 }
 
@@ -715,19 +810,20 @@ hipError_t launch_generate_batch(const GenDesc* d_descs, uint32_t n_calls, uint6
   return hipGetLastError();
 }
 
-int sort_tile_size(int) { return kTile; }
+uint32_t sort_tile_size() { return kTile; }
+int sort_max_radix_bits() { return kMaxRadixBits; }
 
-hipError_t launch_upsweep(const SortGeom& g, const SortIO& io, int radix_bits, uint32_t shift,
-                          uint32_t* counts, hipStream_t s) {
-  (void)radix_bits;
-  return radix_bits <= 8 ? upsweep_rb<8>(g, io, shift, (uint32_t)radix_bits, counts, s)
-                         : upsweep_rb<11>(g, io, shift, (uint32_t)radix_bits, counts, s);
+hipError_t launch_upsweep(const SortGeom& g, const SortIO& io, uint32_t shift, uint32_t nbits, uint32_t* counts,
+                          hipStream_t s) {
+  if (g.n == 0) return hipSuccess;
+  return nbits <= 8 ? upsweep_rb<8>(g, io, shift, nbits, counts, s) : upsweep_rb<9>(g, io, shift, nbits, counts, s);
 }
 
-hipError_t launch_downsweep(const SortGeom& g, const SortIO& io, int radix_bits, uint32_t shift,
+hipError_t launch_downsweep(const SortGeom& g, const SortIO& io, uint32_t shift, uint32_t nbits,
                             const uint32_t* offsets, hipStream_t s) {
-  return radix_bits <= 8 ? downsweep_rb<8>(g, io, shift, (uint32_t)radix_bits, offsets, s)
-                         : downsweep_rb<11>(g, io, shift, (uint32_t)radix_bits, offsets, s);
+  if (g.n == 0) return hipSuccess;
+  return nbits <= 8 ? downsweep_rb<8>(g, io, shift, nbits, offsets, s)
+                    : downsweep_rb<9>(g, io, shift, nbits, offsets, s);
 }
 
 uint64_t scan_tmp_words(uint64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
@@ -762,21 +858,31 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, uint64_t n, hipStream_t 
 
 uint32_t gi_tile_size() { return kGiTile; }
 
-hipError_t launch_group_flags(char* const* blocks, int log2B, uint64_t n, uint32_t* tile_flags,
-                              uint32_t* G, hipStream_t s) {
+hipError_t launch_group_flags(char* const* blocks, int log2B, uint64_t n, uint32_t* bitmap,
+                              uint32_t* tile_flags, hipStream_t s) {
   const uint64_t nt = (n + kGiTile - 1) / kGiTile;
   if (nt == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_group_flags, dim3((uint32_t)nt), dim3(kThreads), 0, s, blocks, log2B, n,
-                     tile_flags, G);
+  hipLaunchKernelGGL(k_group_flags, dim3((uint32_t)nt), dim3(kThreads), 0, s, blocks, log2B, n, bitmap,
+                     tile_flags);
   return hipGetLastError();
 }
 
-hipError_t launch_group_write(char* const* blocks, int log2B, uint64_t n, const uint32_t* tile_base,
-                              uint32_t* group_start, hipStream_t s) {
+hipError_t launch_group_write(char* const* blocks, int log2B, uint64_t n, const uint32_t* bitmap,
+                              const uint32_t* tile_base, uint32_t* group_start, uint32_t* group_src,
+                              hipStream_t s) {
   const uint64_t nt = (n + kGiTile - 1) / kGiTile;
   if (nt == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_group_write, dim3((uint32_t)nt), dim3(kThreads), 0, s, blocks, log2B, n,
-                     tile_base, group_start);
+  hipLaunchKernelGGL(k_group_write, dim3((uint32_t)nt), dim3(kThreads), 0, s, blocks, log2B, n, bitmap,
+                     tile_base, group_start, group_src);
+  return hipGetLastError();
+}
+
+hipError_t launch_group_ptr(const uint32_t* group_src, const uint32_t* n_groups, uint32_t n_nodes,
+                            uint32_t* group_ptr, hipStream_t s) {
+  uint64_t blocks = ((uint64_t)n_nodes + 1 + kThreads - 1) / kThreads;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_group_ptr, dim3((uint32_t)blocks), dim3(kThreads), 0, s, group_src, n_groups, n_nodes,
+                     group_ptr);
   return hipGetLastError();
 }
 

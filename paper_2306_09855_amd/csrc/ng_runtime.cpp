@@ -270,8 +270,8 @@ struct ng_ctx {
   uint32_t* d_scalars = nullptr;  // [0] = G
   uint32_t gi_nodes = 0;          // n_nodes the index was built for
 
-  int radix_bits = 11;
-  uint32_t target_ranges = 1024;
+  int radix_bits = 8;
+  uint32_t sort_ranges = 1024;  // static ranges (= workgroups) of each sort pass
   int sticky = NG_OK;
   std::string sticky_msg;
 
@@ -456,6 +456,11 @@ int ng_create(const ng_config* cfg, void* arena, uint64_t arena_bytes, void* str
     delete c;
     return fail(NG_ERR_DEVICE, "hipEventCreate failed");
   }
+  if (ng::launch_fill_u32(c->d_scalars, 0u, 16, c->stream) != hipSuccess) {
+    (void)hipEventDestroy(c->stage_done);
+    delete c;
+    return fail(NG_ERR_DEVICE, "kernel launch failed");
+  }
   *out = c;
   return NG_OK;
 }
@@ -566,12 +571,13 @@ int ng_connect_batch(ng_ctx* c, uint32_t n_calls, const ng_range* src, const ng_
   return NG_OK;
 }
 
-int ng_set_tuning(ng_ctx* c, int radix_bits, uint32_t target_ranges) {
+int ng_set_tuning(ng_ctx* c, int radix_bits, uint32_t sort_ranges) {
   if (!c) return fail(NG_ERR_INVALID_ARG, "null context");
-  if (radix_bits < 4 || radix_bits > 11) return fail(NG_ERR_INVALID_ARG, "radix_bits must be in [4, 11]");
-  if (target_ranges < 8 || target_ranges > (1u << 16)) return fail(NG_ERR_INVALID_ARG, "target_ranges in [8, 65536]");
+  if (radix_bits < 4 || radix_bits > ng::sort_max_radix_bits())
+    return fail(NG_ERR_INVALID_ARG, "radix_bits must be in [4, %d]", ng::sort_max_radix_bits());
+  if (sort_ranges < 1 || sort_ranges > (1u << 20)) return fail(NG_ERR_INVALID_ARG, "sort_ranges in [1, 2^20]");
   c->radix_bits = radix_bits;
-  c->target_ranges = target_ranges;
+  c->sort_ranges = sort_ranges;
   return NG_OK;
 }
 
@@ -586,22 +592,30 @@ int ng_calibrate(ng_ctx* c) {
   if (keybits > 32) return fail(NG_ERR_UNSUPPORTED, "source+delay keys wider than 32 bits");
   const int RB = c->radix_bits;
   const int passes = std::max(1, (keybits + RB - 1) / RB);
-
-  // sort geometry
-  ng::SortGeom g{};
-  const uint32_t tile = (uint32_t)ng::sort_tile_size(RB);
-  g.n = N;
-  g.tile = tile;
+  uint32_t shift[32] = {0}, nbits[32] = {0};
+  {
+    const int base_bits = keybits / passes, extra = keybits % passes;
+    int sh = 0;
+    for (int p = 0; p < passes; ++p) {
+      nbits[p] = (uint32_t)(base_bits + (p < extra ? 1 : 0));
+      shift[p] = (uint32_t)sh;
+      sh += (int)nbits[p];
+    }
+  }
+  // geometry: static ranges of consecutive tiles, one workgroup each
+  const uint64_t tile = ng::sort_tile_size();
   const uint64_t n_tiles = (N + tile - 1) / tile;
-  g.tiles_per_range = (uint32_t)std::max<uint64_t>(1, (n_tiles + c->target_ranges - 1) / c->target_ranges);
-  g.n_ranges = (uint32_t)((n_tiles + g.tiles_per_range - 1) / g.tiles_per_range);
+  ng::SortGeom g{};
+  g.n = N;
+  g.tiles_per_range = (uint32_t)std::max<uint64_t>(1, (n_tiles + c->sort_ranges - 1) / c->sort_ranges);
+  g.n_ranges = (uint32_t)std::max<uint64_t>(1, (n_tiles + g.tiles_per_range - 1) / g.tiles_per_range);
   g.ranges_per_xcd = (g.n_ranges + 7) / 8;
+  const uint64_t counts_n = ((uint64_t)1 << nbits[0]) * g.n_ranges;
 
   const uint64_t nblk = (N + c->B - 1) / c->B;
   if (nblk > c->tab_cap) return fail(NG_ERR_OOM, "block table full");
   const uint64_t gi_tiles = (N + ng::gi_tile_size() - 1) / ng::gi_tile_size();
   const uint64_t gcap = std::min<uint64_t>(N, (uint64_t)nn * (uint64_t)c->max_delay) + 1;
-  const uint64_t counts_n = ((uint64_t)1 << std::min(RB, keybits > 0 ? keybits : 1)) * g.n_ranges;
 
   AllocSet as(&c->arena);
   std::vector<char*> nblocks;
@@ -612,11 +626,11 @@ int ng_calibrate(ng_ctx* c) {
     keys[t] = (uint32_t*)as.get(4 * std::max<uint64_t>(N, 1));
     pay[t] = (uint2*)as.get(8 * std::max<uint64_t>(N, 1));
   }
-  uint32_t* counts = (uint32_t*)as.get(4 * std::max<uint64_t>(counts_n, 1));
-  const uint64_t tmp_words = std::max({ng::scan_tmp_words(counts_n), ng::scan_tmp_words(nn + 1ull),
-                                       ng::scan_tmp_words(gi_tiles)});
+  uint32_t* counts = (uint32_t*)as.get(4 * counts_n);
+  const uint64_t tmp_words = std::max(ng::scan_tmp_words(counts_n), ng::scan_tmp_words(gi_tiles));
   uint32_t* scan_tmp = (uint32_t*)as.get(4 * tmp_words);
-  uint32_t* G = (uint32_t*)as.get(4 * (nn + 1ull));
+  uint32_t* group_src = (uint32_t*)as.get(4 * gcap);
+  uint32_t* bitmap = (uint32_t*)as.get(4 * ((N + 31) / 32 + 1));
   uint32_t* tile_flags = (uint32_t*)as.get(4 * std::max<uint64_t>(gi_tiles, 1));
   // the new index replaces the old one, so release the old one first
   const uint64_t gp_bytes = 4 * (nn + 1ull), gs_bytes = 4 * gcap;
@@ -635,10 +649,7 @@ int ng_calibrate(ng_ctx* c) {
 
   // --- LSD radix passes ----------------------------------------------------
   if (N > 0) {
-    int shift = 0;
-    const int base_bits = keybits / passes, extra = keybits % passes;
     for (int p = 0; p < passes; ++p) {
-      const int nbits = base_bits + (p < extra ? 1 : 0);
       ng::SortIO io{};
       io.log2B = c->log2B;
       io.dbits = (uint32_t)dbits;
@@ -652,25 +663,24 @@ int ng_calibrate(ng_ctx* c) {
         io.out_keys = keys[p & 1];
         io.out_pay = pay[p & 1];
       }
-      const uint64_t cn = ((uint64_t)1 << nbits) * g.n_ranges;
-      NG_LAUNCH(c, "upsweep", ng::launch_upsweep(g, io, nbits, (uint32_t)shift, counts, s));
+      const uint64_t cn = ((uint64_t)1 << nbits[p]) * g.n_ranges;
+      NG_LAUNCH(c, "upsweep", ng::launch_upsweep(g, io, shift[p], nbits[p], counts, s));
       NG_LAUNCH(c, "scan", ng::launch_exclusive_scan(counts, counts, cn, scan_tmp, nullptr, s));
-      NG_LAUNCH(c, "downsweep", ng::launch_downsweep(g, io, nbits, (uint32_t)shift, counts, s));
-      shift += nbits;
+      NG_LAUNCH(c, "downsweep", ng::launch_downsweep(g, io, shift[p], nbits[p], counts, s));
     }
   }
 
   // --- group index, Eq. (14) ---------------------------------------------
-  NG_LAUNCH(c, "fill", ng::launch_fill_u32(G, 0u, nn + 1ull, s));
   if (N > 0) {
-    NG_LAUNCH(c, "group_flags", ng::launch_group_flags(c->d_tab[nxt], c->log2B, N, tile_flags, G, s));
+    NG_LAUNCH(c, "group_flags", ng::launch_group_flags(c->d_tab[nxt], c->log2B, N, bitmap, tile_flags, s));
     NG_LAUNCH(c, "scan", ng::launch_exclusive_scan(tile_flags, tile_flags, gi_tiles, scan_tmp, c->d_scalars, s));
-    NG_LAUNCH(c, "group_write", ng::launch_group_write(c->d_tab[nxt], c->log2B, N, tile_flags, gstart, s));
+    NG_LAUNCH(c, "group_write",
+              ng::launch_group_write(c->d_tab[nxt], c->log2B, N, bitmap, tile_flags, gstart, group_src, s));
   } else {
     NG_LAUNCH(c, "fill", ng::launch_fill_u32(c->d_scalars, 0u, 1, s));
     NG_LAUNCH(c, "fill", ng::launch_fill_u32(gstart, 0u, 1, s));
   }
-  NG_LAUNCH(c, "scan", ng::launch_exclusive_scan(G, gptr, nn + 1ull, scan_tmp, nullptr, s));
+  NG_LAUNCH(c, "group_ptr", ng::launch_group_ptr(group_src, c->d_scalars, nn, gptr, s));
 
   // old storage and scratch return to the arena (stream-ordered reuse)
   for (char* b : c->blocks) c->arena.release(b, ng::kBytesPerConn * c->B);
@@ -727,6 +737,13 @@ int ng_read_timing(ng_ctx* c, ng_kernel_time* out, int capacity, int* count, int
 int ng_sync(ng_ctx* c) {
   if (int rc = enter(c)) return rc;
   NG_HIP(c, hipStreamSynchronize(c->stream), "kernel execution");
+  uint32_t err = 0;
+  NG_HIP(c, hipMemcpy(&err, c->d_scalars + 2, 4, hipMemcpyDeviceToHost), "read error word");
+  if (err) {
+    c->sticky = NG_ERR_DEVICE;
+    c->sticky_msg = "a sort look-back wait exceeded its spin limit";
+    return fail(NG_ERR_DEVICE, "%s", c->sticky_msg.c_str());
+  }
   return NG_OK;
 }
 

@@ -13,15 +13,15 @@ from . import ng
 
 
 def arena_bytes_for(n_syn: int, n_nodes: int, max_delay: int = 63, block_size: int = 1 << 24,
-                    radix_bits: int = 11, slack: float = 1.15) -> int:
+                    radix_bits: int = 8, slack: float = 1.15) -> int:
     """Arena size that holds n_syn connections through one calibration."""
     blocks = -(-max(n_syn, 1) // block_size)
     store = 14 * block_size * blocks                 # creation-order blocks
     sorted_store = store                             # calibrated blocks
     scratch = 2 * 12 * n_syn                         # two key/payload buffers (3+ passes)
-    counts = 4 * (1 << radix_bits) * 1024 * 2
+    status = 8 * (1 << radix_bits) * (n_syn // 4096 + 1)   # look-back words per tile and digit
     index = 4 * (n_nodes + 1) * 3 + 4 * (min(n_syn, n_nodes * max_delay) + 1) + 4 * (n_syn // 4096 + 8)
-    total = int((store + sorted_store + scratch + counts + index) * slack) + (64 << 20)
+    total = int((store + sorted_store + scratch + status + index) * slack) + (64 << 20)
     return (total + 4095) // 4096 * 4096
 
 
@@ -53,8 +53,8 @@ class Network:
     def sync(self):
         ng.ng_sync(self.ctx)
 
-    def tune(self, radix_bits: int, target_ranges: int):
-        ng.ng_set_tuning(self.ctx, radix_bits, target_ranges)
+    def tune(self, radix_bits: int, sort_ranges: int = 1024):
+        ng.ng_set_tuning(self.ctx, radix_bits, sort_ranges)
 
     def build(self, workload, batched: bool = False, calibrate: bool = True):
         for n in workload.populations:

@@ -257,8 +257,8 @@ def ng_read_timing(ctx, reset: bool = True) -> dict:
     return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms)) for i in range(min(n.value, cap))}
 
 
-def ng_set_tuning(ctx, radix_bits: int, target_ranges: int) -> None:
-    _check(lib().ng_set_tuning(ctx, radix_bits, target_ranges))
+def ng_set_tuning(ctx, radix_bits: int, sort_ranges: int = 1024) -> None:
+    _check(lib().ng_set_tuning(ctx, radix_bits, sort_ranges))
 
 
 def ng_memory_stats(ctx):

@@ -101,9 +101,10 @@ def test_batch_equals_plain_and_oracle():
     check_calibrated(o2, gp2, gs2, ref, wl.calls)
 
 
-@pytest.mark.parametrize("tuning", [(4, 8), (8, 8), (8, 4096), (11, 16), (9, 50)])
+@pytest.mark.parametrize("tuning", [(4, 1024), (5, 1), (7, 3), (8, 9), (9, 100000)])
 def test_schedule_invariance(tuning):
-    # digit widths 4..11 (2..5 passes) and range counts give identical results
+    # digit widths 4..9 (2..5 passes) and range counts (a single range, counts
+    # that are not multiples of 8, more ranges than tiles) give identical results
     wl = W.microcircuit(scale=0.02)
     _check_all(wl, tuning=tuning)
 
