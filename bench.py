@@ -67,7 +67,12 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--batched", action="store_true", help="use ng_connect_batch for the 64 calls")
+    ap.add_argument("--workload", default="microcircuit", choices=["microcircuit", "batch_mixed"],
+                    help="microcircuit: 64 calls, 3.0e8 synapses; batch_mixed: 4,096 uneven calls, ~4.3e8")
+    ap.add_argument("--form", default="plain", choices=["plain", "batched", "graph"],
+                    help="plain: one ng_connect per call; batched: one ng_connect_batch; "
+                         "graph: the batched build captured once and replayed")
+    ap.add_argument("--tune", action="store_true", help="pick the sort schedule with the autotuner first")
     ap.add_argument("--radix-bits", type=int, default=8)
     ap.add_argument("--sort-ranges", type=int, default=1024, help="static ranges (workgroups) of each sort pass")
     ap.add_argument("--block-size", type=int, default=1 << 24)
@@ -98,27 +103,48 @@ def main() -> int:
     from paper_2306_09855_amd.network import Network, arena_bytes_for
 
     torch.cuda.set_device(0)
-    wl = W.microcircuit(total=int(args.total))
+    if args.workload == "microcircuit":
+        wl = W.microcircuit(total=int(args.total))
+    else:
+        wl = W.batch_mixed()
     n_syn = wl.n_syn
-    arena = arena_bytes_for(n_syn, wl.n_nodes, wl.max_delay, args.block_size, args.radix_bits)
-    log(f"workload microcircuit: {wl.n_nodes} nodes, {len(wl.calls)} calls, {n_syn:.3g} synapses, "
-        f"arena {arena / 2**30:.1f} GiB")
-    net = Network(wl.seed, wl.h, args.block_size, arena)
+    arena = arena_bytes_for(n_syn, wl.n_nodes, wl.max_delay, args.block_size, 9)
+    log(f"workload {wl.name}: {wl.n_nodes} nodes, {len(wl.calls)} calls, {n_syn:.3g} synapses, "
+        f"arena {arena / 2**30:.1f} GiB, form {args.form}")
+    side = torch.cuda.Stream()  # graphs cannot capture the null stream
+    net = Network(wl.seed, wl.h, args.block_size, arena, stream=side.cuda_stream)
+    if args.tune:
+        from paper_2306_09855_amd.autotune import tune
+        args.radix_bits, args.sort_ranges = tune(net, wl)
+        log(f"autotuner: radix_bits={args.radix_bits} sort_ranges={args.sort_ranges}")
     net.tune(args.radix_bits, args.sort_ranges)
     ctx = net.ctx
     calls = [ng.call_args(c) for c in wl.calls]
     batch = [list(x) for x in zip(*calls)]
 
-    def step():
-        ng.ng_reset(ctx)
+    def build():
         for n in wl.populations:
             ng.ng_create_nodes(ctx, n)
-        if args.batched:
-            ng.ng_connect_batch(ctx, *batch)
-        else:
+        if args.form == "plain":
             for a in calls:
                 ng.ng_connect(ctx, *a)
+        else:
+            ng.ng_connect_batch(ctx, *batch)
         ng.ng_calibrate(ctx)
+
+    graph = None
+    if args.form == "graph":
+        ng.ng_reset(ctx)
+        ng.ng_graph_begin(ctx)
+        build()
+        graph = ng.ng_graph_end(ctx)
+
+    def step():
+        if graph is not None:
+            ng.ng_graph_launch(graph, wl.seed)
+        else:
+            ng.ng_reset(ctx)
+            build()
 
     for i in range(args.warmup):
         step()
@@ -139,6 +165,15 @@ def main() -> int:
     t1 = time.perf_counter()
     kernels = ng.ng_read_timing(ctx, reset=True)
     ng.ng_enable_timing(ctx, False)
+    if graph is not None:  # replays carry no per-kernel events: time one eager build instead
+        ng.ng_graph_destroy(graph)
+        graph = None
+        ng.ng_enable_timing(ctx, True)
+        for _ in range(args.steps):
+            ng.ng_reset(ctx)
+            build()
+        kernels = ng.ng_read_timing(ctx, reset=True)
+        ng.ng_enable_timing(ctx, False)
     log(f"timed {args.steps} steps in {t1 - t0:.4f} s")
 
     wall = t1 - t0
@@ -172,11 +207,14 @@ def main() -> int:
     result = {
         "metric": METRIC, "value": value, "unit": "synapses/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": round(value / PAPER_A100_SYN_PER_S, 2) if n_syn == 3e8 else None,
+        "scaling": "weak",
+        "vs_baseline": round(value / PAPER_A100_SYN_PER_S, 2) if wl.name == "microcircuit" and n_syn == 3e8 else None,
         "dtype": "u32", "data": "synthetic",
-        "config": {"workload": "microcircuit", "n_nodes": wl.n_nodes, "n_calls": len(wl.calls),
-                   "n_syn": n_syn, "rule": "fixed_total_number", "delays": "uniform_int 1..30",
-                   "weights": "normal fp32", "form": "batched" if args.batched else "plain",
+        "config": {"workload": wl.name, "n_nodes": wl.n_nodes, "n_calls": len(wl.calls),
+                   "n_syn": n_syn,
+                   "rule": "fixed_total_number" if wl.name == "microcircuit" else "mixed",
+                   "delays": f"uniform_int 1..{wl.max_delay}",
+                   "weights": "normal fp32", "form": args.form,
                    "block_size": args.block_size, "radix_bits": args.radix_bits, "sort_ranges": args.sort_ranges,
                    "sort_passes": passes},
         "device_ms_per_step": round(dev_ms / args.steps, 4),
@@ -186,7 +224,7 @@ def main() -> int:
         "kernels": per_kernel,
     }
     net.close()
-    if args.cpu_sample > 0:
+    if args.cpu_sample > 0 and wl.name == "microcircuit":
         result["cpu_baseline"] = cpu_baseline(int(args.cpu_sample))
     print(json.dumps(result))
     return 0

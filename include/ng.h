@@ -204,6 +204,25 @@ typedef struct {
 int ng_enable_timing(ng_ctx* ctx, int on);
 int ng_read_timing(ng_ctx* ctx, ng_kernel_time* out, int capacity, int* count, int reset);
 
+/* --- captured graphs (batched form) -------------------------------------
+ * ng_graph_begin starts capturing the context's stream (which must not be
+ * the null stream); the following ng_create_nodes / ng_connect /
+ * ng_connect_batch / ng_calibrate calls enqueue nothing runnable -- their
+ * kernels and descriptor uploads become graph nodes.  ng_graph_end closes
+ * the capture.  ng_graph_launch writes `seed` as the Philox key and replays
+ * the captured work on the context stream: the same calls rebuilt for that
+ * seed, results identical to issuing the calls directly with that seed
+ * (Discussion: parameter scans rebuild the same structure many times).
+ * While a graph exists the context is frozen: calls that change it return
+ * NG_ERR_STATE; reading (ng_get_connections, ng_copy_*) is allowed.
+ * During capture, calls that synchronize return NG_ERR_STATE.
+ * staging_bytes: pinned host bytes for batch descriptors (0: 4 MiB). */
+typedef struct ng_graph ng_graph;
+int ng_graph_begin(ng_ctx* ctx, uint64_t staging_bytes);
+int ng_graph_end(ng_ctx* ctx, ng_graph** out);
+int ng_graph_launch(ng_graph* graph, uint64_t seed);
+int ng_graph_destroy(ng_graph* graph);
+
 /* Message of the calling thread's last error ("" if none). */
 const char* ng_last_error(void);
 

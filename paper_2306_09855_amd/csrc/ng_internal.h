@@ -34,12 +34,13 @@ struct GenDesc {
 };
 
 // --- generation -----------------------------------------------------------
-hipError_t launch_generate(const GenDesc& d, uint64_t seed, char* const* d_blocks, int log2B,
+// d_key: the Philox key (seed low word, seed high word) in device memory.
+hipError_t launch_generate(const GenDesc& d, const uint32_t* d_key, char* const* d_blocks, int log2B,
                            hipStream_t s);
 // All calls of a batch in one launch; d_descs[n_calls] device array sorted by
 // group0, total_groups = sum of ceil(n_new / 4).
 hipError_t launch_generate_batch(const GenDesc* d_descs, uint32_t n_calls, uint64_t total_groups,
-                                 uint64_t seed, char* const* d_blocks, int log2B, hipStream_t s);
+                                 const uint32_t* d_key, char* const* d_blocks, int log2B, hipStream_t s);
 
 // --- calibration ----------------------------------------------------------
 struct SortGeom {

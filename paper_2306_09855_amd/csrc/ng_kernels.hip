@@ -196,8 +196,9 @@ __device__ __forceinline__ void store_quad(char* const* __restrict__ blocks, int
 constexpr int kGenThreads = 256;
 
 template <int RULE, bool DRAND>
-__global__ __launch_bounds__(kGenThreads) void k_generate(GenDesc d, uint32_t key0, uint32_t key1,
+__global__ __launch_bounds__(kGenThreads) void k_generate(GenDesc d, const uint32_t* __restrict__ key,
                                                           char* const* __restrict__ blocks, int log2B) {
+  const uint32_t key0 = key[0], key1 = key[1];  // the seed lives in device memory (graph replays)
   const uint32_t ngroups = (uint32_t)(((uint64_t)d.n_new + 3) >> 2);
   for (uint32_t g = blockIdx.x * kGenThreads + threadIdx.x; g < ngroups;
        g += gridDim.x * kGenThreads) {
@@ -224,9 +225,10 @@ __device__ __forceinline__ void gen_any(const GenDesc& d, uint32_t g, uint32_t k
 // each lane finds its call by binary search over the calls' first groups.
 __global__ __launch_bounds__(kGenThreads) void k_generate_batch(const GenDesc* __restrict__ descs,
                                                                 uint32_t n_calls, uint64_t total_groups,
-                                                                uint32_t key0, uint32_t key1,
+                                                                const uint32_t* __restrict__ key,
                                                                 char* const* __restrict__ blocks,
                                                                 int log2B) {
+  const uint32_t key0 = key[0], key1 = key[1];
   for (uint64_t gg = (uint64_t)blockIdx.x * kGenThreads + threadIdx.x; gg < total_groups;
        gg += (uint64_t)gridDim.x * kGenThreads) {
     uint32_t lo = 0, hi = n_calls - 1;
@@ -772,12 +774,12 @@ hipError_t downsweep_rb(const SortGeom& g, const SortIO& io, uint32_t shift, uin
 // launch wrappers
 // ---------------------------------------------------------------------------
 template <int RULE>
-static void gen_launch(const GenDesc& d, uint32_t k0, uint32_t k1, char* const* blocks, int log2B,
-                       dim3 grid, hipStream_t s) {
+static void gen_launch(const GenDesc& d, const uint32_t* key, char* const* blocks, int log2B, dim3 grid,
+                       hipStream_t s) {
   if (d.d_kind == D_CONST)
-    hipLaunchKernelGGL((k_generate<RULE, false>), grid, dim3(kGenThreads), 0, s, d, k0, k1, blocks, log2B);
+    hipLaunchKernelGGL((k_generate<RULE, false>), grid, dim3(kGenThreads), 0, s, d, key, blocks, log2B);
   else
-    hipLaunchKernelGGL((k_generate<RULE, true>), grid, dim3(kGenThreads), 0, s, d, k0, k1, blocks, log2B);
+    hipLaunchKernelGGL((k_generate<RULE, true>), grid, dim3(kGenThreads), 0, s, d, key, blocks, log2B);
 }
 
 static uint32_t gen_grid(uint64_t groups) {
@@ -785,28 +787,27 @@ static uint32_t gen_grid(uint64_t groups) {
   return (uint32_t)(need < 16384 ? (need ? need : 1) : 16384);
 }
 
-hipError_t launch_generate(const GenDesc& d, uint64_t seed, char* const* d_blocks, int log2B,
+hipError_t launch_generate(const GenDesc& d, const uint32_t* d_key, char* const* d_blocks, int log2B,
                            hipStream_t s) {
   if (d.n_new == 0) return hipSuccess;
   const dim3 grid(gen_grid(((uint64_t)d.n_new + 3) / 4));
-  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
   switch (d.rule) {
-    case R_ONE_TO_ONE: gen_launch<R_ONE_TO_ONE>(d, k0, k1, d_blocks, log2B, grid, s); break;
-    case R_ALL_TO_ALL: gen_launch<R_ALL_TO_ALL>(d, k0, k1, d_blocks, log2B, grid, s); break;
-    case R_INDEG: gen_launch<R_INDEG>(d, k0, k1, d_blocks, log2B, grid, s); break;
-    case R_OUTDEG: gen_launch<R_OUTDEG>(d, k0, k1, d_blocks, log2B, grid, s); break;
-    case R_TOTAL: gen_launch<R_TOTAL>(d, k0, k1, d_blocks, log2B, grid, s); break;
+    case R_ONE_TO_ONE: gen_launch<R_ONE_TO_ONE>(d, d_key, d_blocks, log2B, grid, s); break;
+    case R_ALL_TO_ALL: gen_launch<R_ALL_TO_ALL>(d, d_key, d_blocks, log2B, grid, s); break;
+    case R_INDEG: gen_launch<R_INDEG>(d, d_key, d_blocks, log2B, grid, s); break;
+    case R_OUTDEG: gen_launch<R_OUTDEG>(d, d_key, d_blocks, log2B, grid, s); break;
+    case R_TOTAL: gen_launch<R_TOTAL>(d, d_key, d_blocks, log2B, grid, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_generate_batch(const GenDesc* d_descs, uint32_t n_calls, uint64_t total_groups,
-                                 uint64_t seed, char* const* d_blocks, int log2B, hipStream_t s) {
+                                 const uint32_t* d_key, char* const* d_blocks, int log2B, hipStream_t s) {
   if (n_calls == 0 || total_groups == 0) return hipSuccess;
   const dim3 grid(gen_grid(total_groups));
-  hipLaunchKernelGGL(k_generate_batch, grid, dim3(kGenThreads), 0, s, d_descs, n_calls, total_groups,
-                     (uint32_t)seed, (uint32_t)(seed >> 32), d_blocks, log2B);
+  hipLaunchKernelGGL(k_generate_batch, grid, dim3(kGenThreads), 0, s, d_descs, n_calls, total_groups, d_key,
+                     d_blocks, log2B);
   return hipGetLastError();
 }
 

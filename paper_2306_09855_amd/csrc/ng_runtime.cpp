@@ -285,6 +285,14 @@ struct ng_ctx {
   std::vector<Timed> pending;
   std::map<std::string, std::pair<double, uint64_t>> timing_acc;
 
+  // graph capture: while capturing, nothing may synchronize; descriptors go
+  // to a pinned region the graph owns.  A context with live graphs is frozen.
+  bool capturing = false;
+  bool timing_before_capture = false;
+  char* cap_stage = nullptr;
+  uint64_t cap_stage_cap = 0, cap_stage_used = 0;
+  int frozen = 0;
+
   // pinned staging for batched descriptors
   ng::GenDesc* h_stage = nullptr;
   uint64_t h_stage_cap = 0;
@@ -369,6 +377,24 @@ hipError_t set_table(char** tab, uint32_t first, const std::vector<char*>& ptrs,
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+// The Philox key lives in device memory (d_scalars[4..5]) so that a captured
+// graph can be replayed with another seed.
+uint32_t* key_ptr(ng_ctx* c) { return c->d_scalars + 4; }
+
+hipError_t set_seed(ng_ctx* c, uint64_t seed) {
+  return ng::launch_set_ptrs(reinterpret_cast<char**>(key_ptr(c)), 0, 1, &seed, c->stream);
+}
+
+int mutable_state(ng_ctx* c) {
+  if (c->frozen) return fail(NG_ERR_STATE, "the context has live graphs; destroy them before changing it");
+  return NG_OK;
+}
+
+int not_capturing(ng_ctx* c) {
+  if (c->capturing) return fail(NG_ERR_STATE, "not allowed while a graph is being captured");
+  return NG_OK;
 }
 
 // Eq. (1) plus allocation; all-or-nothing.
@@ -456,7 +482,8 @@ int ng_create(const ng_config* cfg, void* arena, uint64_t arena_bytes, void* str
     delete c;
     return fail(NG_ERR_DEVICE, "hipEventCreate failed");
   }
-  if (ng::launch_fill_u32(c->d_scalars, 0u, 16, c->stream) != hipSuccess) {
+  if (ng::launch_fill_u32(c->d_scalars, 0u, 16, c->stream) != hipSuccess ||
+      set_seed(c, c->cfg.seed) != hipSuccess) {
     (void)hipEventDestroy(c->stage_done);
     delete c;
     return fail(NG_ERR_DEVICE, "kernel launch failed");
@@ -479,6 +506,7 @@ int ng_destroy(ng_ctx* c) {
 
 int ng_create_nodes(ng_ctx* c, uint32_t n, ng_range* out) {
   if (int rc = enter(c)) return rc;
+  if (int rc = mutable_state(c)) return rc;
   if ((uint64_t)c->n_nodes + n > 0xFFFFFFFFull) return fail(NG_ERR_TOO_LARGE, "too many nodes");
   if (out) *out = ng_range{c->n_nodes, n};
   c->n_nodes += n;
@@ -489,6 +517,7 @@ int ng_create_nodes(ng_ctx* c, uint32_t n, ng_range* out) {
 int ng_connect(ng_ctx* c, ng_range src, ng_range tgt, const ng_conn_spec* conn, const ng_syn_spec* syn,
                uint32_t* out_cid, uint64_t* out_first, uint64_t* out_n) {
   if (int rc = enter(c)) return rc;
+  if (int rc = mutable_state(c)) return rc;
   Plan p;
   if (int rc = plan_call(c->n_nodes, src, tgt, conn, syn, c->cfg.h_ms, &p)) return rc;
   if (c->next_cid == 0xFFFFFFFFu) return fail(NG_ERR_TOO_LARGE, "connect call ids exhausted");
@@ -498,7 +527,7 @@ int ng_connect(ng_ctx* c, ng_range src, ng_range tgt, const ng_conn_spec* conn, 
   p.d.pos0 = c->n_conns;
   p.d.cid = c->next_cid;
   if (p.n_new) {
-    NG_LAUNCH(c, "generate", ng::launch_generate(p.d, c->cfg.seed, c->d_tab[c->cur], c->log2B, c->stream));
+    NG_LAUNCH(c, "generate", ng::launch_generate(p.d, key_ptr(c), c->d_tab[c->cur], c->log2B, c->stream));
     c->calibrated = false;
   }
   if (out_cid) *out_cid = c->next_cid;
@@ -513,6 +542,7 @@ int ng_connect(ng_ctx* c, ng_range src, ng_range tgt, const ng_conn_spec* conn, 
 int ng_connect_batch(ng_ctx* c, uint32_t n_calls, const ng_range* src, const ng_range* tgt,
                      const ng_conn_spec* conn, const ng_syn_spec* syn, uint64_t* out_first) {
   if (int rc = enter(c)) return rc;
+  if (int rc = mutable_state(c)) return rc;
   if (n_calls == 0) return NG_OK;
   if (!src || !tgt || !conn || !syn) return fail(NG_ERR_INVALID_ARG, "null array");
   if ((uint64_t)c->next_cid + n_calls > 0xFFFFFFFFull) return fail(NG_ERR_TOO_LARGE, "connect call ids exhausted");
@@ -547,7 +577,18 @@ int ng_connect_batch(ng_ctx* c, uint32_t n_calls, const ng_range* src, const ng_
     c->arena.release(d_descs, desc_bytes);
     return rc;
   }
-  if (!descs.empty()) {
+  if (!descs.empty() && c->capturing) {
+    // the upload becomes a graph node reading this pinned region on every replay
+    const uint64_t need = (desc_bytes + 255) / 256 * 256;
+    if (c->cap_stage_used + need > c->cap_stage_cap) {
+      c->arena.release(d_descs, desc_bytes);
+      return fail(NG_ERR_OOM, "graph staging region full (%llu bytes)", (unsigned long long)c->cap_stage_cap);
+    }
+    char* h = c->cap_stage + c->cap_stage_used;
+    c->cap_stage_used += need;
+    memcpy(h, descs.data(), desc_bytes);
+    NG_HIP(c, hipMemcpyAsync(d_descs, h, desc_bytes, hipMemcpyHostToDevice, c->stream), "upload");
+  } else if (!descs.empty()) {
     // pinned staging, reused once the previous upload has completed
     NG_HIP(c, hipEventSynchronize(c->stage_done), "stage wait");
     if (c->h_stage_cap < descs.size()) {
@@ -559,9 +600,11 @@ int ng_connect_batch(ng_ctx* c, uint32_t n_calls, const ng_range* src, const ng_
     memcpy(c->h_stage, descs.data(), desc_bytes);
     NG_HIP(c, hipMemcpyAsync(d_descs, c->h_stage, desc_bytes, hipMemcpyHostToDevice, c->stream), "upload");
     NG_HIP(c, hipEventRecord(c->stage_done, c->stream), "event");
+  }
+  if (!descs.empty()) {
     NG_LAUNCH(c, "generate_batch",
               ng::launch_generate_batch((const ng::GenDesc*)d_descs, (uint32_t)descs.size(), groups,
-                                        c->cfg.seed, c->d_tab[c->cur], c->log2B, c->stream));
+                                        key_ptr(c), c->d_tab[c->cur], c->log2B, c->stream));
     c->arena.release(d_descs, desc_bytes);  // stream-ordered reuse is safe
     c->calibrated = false;
   }
@@ -583,6 +626,7 @@ int ng_set_tuning(ng_ctx* c, int radix_bits, uint32_t sort_ranges) {
 
 int ng_calibrate(ng_ctx* c) {
   if (int rc = enter(c)) return rc;
+  if (int rc = mutable_state(c)) return rc;
   if (c->calibrated) return NG_OK;
   const uint64_t N = c->n_conns;
   const uint32_t nn = c->n_nodes;
@@ -698,6 +742,7 @@ int ng_calibrate(ng_ctx* c) {
 
 int ng_reset(ng_ctx* c) {
   if (int rc = enter(c)) return rc;
+  if (int rc = mutable_state(c)) return rc;
   for (char* b : c->blocks) c->arena.release(b, ng::kBytesPerConn * c->B);
   c->blocks.clear();
   release_index(c);
@@ -707,6 +752,93 @@ int ng_reset(ng_ctx* c) {
   c->max_delay = 1;
   c->calibrated = false;
   c->gi_nodes = 0;
+  return NG_OK;
+}
+
+}  // extern "C"
+
+struct ng_graph {
+  ng_ctx* ctx = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  char* stage = nullptr;  // pinned descriptors the graph's upload nodes read
+};
+
+extern "C" {
+
+int ng_graph_begin(ng_ctx* c, uint64_t staging_bytes) {
+  if (int rc = enter(c)) return rc;
+  if (int rc = not_capturing(c)) return rc;
+  if (int rc = mutable_state(c)) return rc;
+  if (c->stream == nullptr) return fail(NG_ERR_STATE, "graph capture needs a non-default stream");
+  if (staging_bytes == 0) staging_bytes = 4ull << 20;
+  NG_HIP(c, hipHostMalloc((void**)&c->cap_stage, staging_bytes, hipHostMallocDefault), "hipHostMalloc");
+  c->cap_stage_cap = staging_bytes;
+  c->cap_stage_used = 0;
+  hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    (void)hipHostFree(c->cap_stage);
+    c->cap_stage = nullptr;
+    return dev_fail(c, e, "hipStreamBeginCapture");
+  }
+  c->capturing = true;
+  c->timing_before_capture = c->timing;
+  c->timing = false;
+  return NG_OK;
+}
+
+int ng_graph_end(ng_ctx* c, ng_graph** out) {
+  if (!c || !out) return fail(NG_ERR_INVALID_ARG, "null argument");
+  if (!c->capturing) return fail(NG_ERR_STATE, "no capture in progress");
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(c->stream, &graph);
+  c->capturing = false;
+  c->timing = c->timing_before_capture;
+  if (e != hipSuccess) {
+    (void)hipHostFree(c->cap_stage);
+    c->cap_stage = nullptr;
+    return dev_fail(c, e, "hipStreamEndCapture");
+  }
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    (void)hipHostFree(c->cap_stage);
+    c->cap_stage = nullptr;
+    return dev_fail(c, e, "hipGraphInstantiate");
+  }
+  ng_graph* g = new ng_graph();
+  g->ctx = c;
+  g->graph = graph;
+  g->exec = exec;
+  g->stage = c->cap_stage;
+  c->cap_stage = nullptr;
+  c->frozen++;
+  *out = g;
+  return NG_OK;
+}
+
+int ng_graph_launch(ng_graph* g, uint64_t seed) {
+  if (!g) return fail(NG_ERR_INVALID_ARG, "null graph");
+  ng_ctx* c = g->ctx;
+  if (int rc = enter(c)) return rc;
+  if (int rc = not_capturing(c)) return rc;
+  NG_HIP(c, set_seed(c, seed), "seed");
+  NG_HIP(c, hipGraphLaunch(g->exec, c->stream), "hipGraphLaunch");
+  c->cfg.seed = seed;
+  return NG_OK;
+}
+
+int ng_graph_destroy(ng_graph* g) {
+  if (!g) return NG_OK;
+  ng_ctx* c = g->ctx;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipGraphExecDestroy(g->exec);
+  (void)hipGraphDestroy(g->graph);
+  if (g->stage) (void)hipHostFree(g->stage);
+  c->frozen--;
+  delete g;
   return NG_OK;
 }
 
@@ -736,6 +868,7 @@ int ng_read_timing(ng_ctx* c, ng_kernel_time* out, int capacity, int* count, int
 
 int ng_sync(ng_ctx* c) {
   if (int rc = enter(c)) return rc;
+  if (int rc = not_capturing(c)) return rc;
   NG_HIP(c, hipStreamSynchronize(c->stream), "kernel execution");
   uint32_t err = 0;
   NG_HIP(c, hipMemcpy(&err, c->d_scalars + 2, 4, hipMemcpyDeviceToHost), "read error word");

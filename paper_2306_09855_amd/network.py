@@ -106,3 +106,24 @@ class Network:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class Graph:
+    """A captured build (batched form) that can be replayed with any seed."""
+
+    def __init__(self, net: Network, build_fn):
+        ng.ng_graph_begin(net.ctx)
+        try:
+            build_fn(net)
+        except Exception:
+            ng.ng_graph_destroy(ng.ng_graph_end(net.ctx))
+            raise
+        self.handle = ng.ng_graph_end(net.ctx)
+
+    def launch(self, seed: int):
+        ng.ng_graph_launch(self.handle, seed)
+
+    def close(self):
+        if self.handle is not None:
+            ng.ng_graph_destroy(self.handle)
+            self.handle = None

@@ -107,6 +107,10 @@ def lib():
             "ng_enable_timing": ([vp, ctypes.c_int], ctypes.c_int),
             "ng_read_timing": ([vp, P(ng_kernel_time), ctypes.c_int, P(ctypes.c_int), ctypes.c_int],
                                ctypes.c_int),
+            "ng_graph_begin": ([vp, u64], ctypes.c_int),
+            "ng_graph_end": ([vp, P(vp)], ctypes.c_int),
+            "ng_graph_launch": ([vp, u64], ctypes.c_int),
+            "ng_graph_destroy": ([vp], ctypes.c_int),
             "ng_last_error": ([], ctypes.c_char_p),
             "ng_blocks_needed": ([u64, u64, u64, u64], u64),
             "ng_plan_count": ([u32, ng_range, ng_range, P(ng_conn_spec), P(ng_syn_spec), ctypes.c_float,
@@ -255,6 +259,24 @@ def ng_read_timing(ctx, reset: bool = True) -> dict:
     n = ctypes.c_int()
     _check(lib().ng_read_timing(ctx, arr, cap, ctypes.byref(n), 1 if reset else 0))
     return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms)) for i in range(min(n.value, cap))}
+
+
+def ng_graph_begin(ctx, staging_bytes: int = 0) -> None:
+    _check(lib().ng_graph_begin(ctx, staging_bytes))
+
+
+def ng_graph_end(ctx) -> ctypes.c_void_p:
+    g = ctypes.c_void_p()
+    _check(lib().ng_graph_end(ctx, ctypes.byref(g)))
+    return g
+
+
+def ng_graph_launch(graph, seed: int) -> None:
+    _check(lib().ng_graph_launch(graph, seed))
+
+
+def ng_graph_destroy(graph) -> None:
+    _check(lib().ng_graph_destroy(graph))
 
 
 def ng_set_tuning(ctx, radix_bits: int, sort_ranges: int = 1024) -> None:
