@@ -48,6 +48,31 @@ def algorithmic_bytes(kernel: str, n_syn: int, passes: int) -> float | None:
     return None if per is None else per * n_syn
 
 
+def kernels_fingerprint() -> str:
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2306_09855_amd", "csrc", "ng_kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None if there is none or the kernels changed since it was taken."""
+    import glob
+    fp = kernels_fingerprint()
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*traffic*.md")):
+        for line in open(path):
+            line = line.strip()
+            if not line.startswith("{"):
+                continue
+            try:
+                rec = json.loads(line)
+            except ValueError:
+                continue
+            if rec.get("kernel") == kernel and rec.get("workload") == workload and rec.get("kernels_sha") == fp:
+                return rec["bytes_per_launch"]
+    return None
+
+
 def cpu_baseline(sample_syn: int) -> dict:
     import oracle
     from paper_2306_09855_amd import workloads as W
@@ -60,6 +85,144 @@ def cpu_baseline(sample_syn: int) -> dict:
             "seconds": dt, "cpu": platform.processor() or platform.machine(),
             "sample": (f"microcircuit populations (77,169 nodes), 64 fixed_total_number calls scaled to "
                        f"{wl.n_syn} synapses in total; generation + calibration, single thread")}
+
+
+def _events(trace):
+    ev = []
+    for ei, ep in enumerate(trace):
+        ev.append((ep.times[0], ei, "create", None))
+        for j, c in enumerate(ep.calls):
+            ev.append((ep.times[1 + j], ei, "connect", c))
+        ev.append((ep.times[-2], ei, "calibrate", None))
+        ev.append((ep.times[-1], ei, "close", None))
+    ev.sort(key=lambda e: (e[0], e[1]))
+    return ev
+
+
+def _wait_until(t):
+    while True:
+        d = t - time.perf_counter()
+        if d <= 0:
+            return
+        if d > 3e-4:
+            time.sleep(d - 2e-4)
+
+
+def _pct(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs), q)) if xs else None
+
+
+def serve_run(trace, n_streams, arena_bytes, block_size):
+    """The trace through the server: requests submitted at their arrival times."""
+    import torch
+    from paper_2306_09855_amd import ng
+    streams = [torch.cuda.Stream() for _ in range(n_streams)]
+    arena = ng.arena_for(arena_bytes)
+    srv = ng.ng_server_create(ng.ng_server_config(block_size, 0.1, 0, 0, 0), arena, arena_bytes,
+                              [s.cuda_stream for s in streams])
+    sessions, tickets = {}, []
+    t0 = time.perf_counter()
+    for (t, ei, kind, c) in _events(trace):
+        _wait_until(t0 + t)
+        if kind == "create":
+            sessions[ei] = ng.ng_session_open(srv, trace[ei].seed)
+            tickets.append((ng.ng_submit_create_nodes(sessions[ei], trace[ei].n_nodes)[1], kind, 0))
+        elif kind == "connect":
+            tickets.append((ng.ng_submit_connect(sessions[ei], *ng.call_args(c)), kind, c.n_syn()))
+        elif kind == "calibrate":
+            tickets.append((ng.ng_submit_calibrate(sessions[ei]), kind, 0))
+        else:
+            tickets.append((ng.ng_submit_close(sessions[ei]), kind, 0))
+    lat, first, last, syn, bad = [], None, 0, 0, 0
+    for (tk, kind, n) in tickets:
+        info = ng.ng_wait(srv, tk)
+        bad += info.status != 0
+        first = info.arrival_ns if first is None else min(first, info.arrival_ns)
+        last = max(last, info.done_ns)
+        if kind == "connect":
+            lat.append((info.done_ns - info.arrival_ns) / 1e6)
+            syn += n
+    stats = ng.ng_server_get_stats(srv)
+    ng.ng_server_destroy(srv)
+    span = (last - first) / 1e9
+    return {"synapses": syn, "seconds": round(span, 4), "synapses_per_s": syn / span,
+            "connect_p50_ms": _pct(lat, 50), "connect_p99_ms": _pct(lat, 99), "failed": bad,
+            "launches": stats["launches"], "calls_per_launch": round(stats["packed_calls"] / max(stats["launches"], 1), 2),
+            "peak_arena_GiB": round(stats["peak_arena_bytes"] / 2**30, 2)}
+
+
+def plain_run(trace, block_size):
+    """The same trace served one request at a time, each synchronized (FIFO)."""
+    import torch
+    from paper_2306_09855_amd import ng
+    from paper_2306_09855_amd.network import arena_bytes_for
+    stream = torch.cuda.Stream()
+    pool = {}   # arena tensors by size, reused across episodes
+    ctxs, arenas, lat, syn = {}, {}, [], 0
+    t0 = time.perf_counter()
+    first = last = None
+    for (t, ei, kind, c) in _events(trace):
+        arrival = t0 + t
+        _wait_until(arrival)
+        ep = trace[ei]
+        if kind == "create":
+            need = arena_bytes_for(ep.n_syn, ep.n_nodes, 63, block_size, 9)
+            size = 1 << max(24, (need - 1).bit_length())
+            a = pool.pop(size, None)
+            if a is None:
+                a = ng.arena_for(size)
+            arenas[ei] = a
+            ctxs[ei] = ng.ng_create(ng.ng_config(block_size, ep.seed, 0.1, 0), a, size, stream.cuda_stream)
+            ng.ng_create_nodes(ctxs[ei], ep.n_nodes)
+        elif kind == "connect":
+            ng.ng_connect(ctxs[ei], *ng.call_args(c))
+            ng.ng_sync(ctxs[ei])
+            syn += c.n_syn()
+        elif kind == "calibrate":
+            ng.ng_calibrate(ctxs[ei])
+            ng.ng_sync(ctxs[ei])
+        else:
+            ng.ng_destroy(ctxs.pop(ei))
+            a = arenas.pop(ei)
+            pool[a.numel()] = a
+        done = time.perf_counter()
+        first = arrival if first is None else min(first, arrival)
+        last = done
+        if kind == "connect":
+            lat.append((done - arrival) * 1e3)
+    span = last - first
+    return {"synapses": syn, "seconds": round(span, 4), "synapses_per_s": syn / span,
+            "connect_p50_ms": _pct(lat, 50), "connect_p99_ms": _pct(lat, 99)}
+
+
+def serving_bench(episodes_per_slot=2, n_streams=4, block_size=1 << 20, load=0.5):
+    """Serving form against the plain sequential path on the same trace.
+
+    capacity: every request arrives at once (a backlog): synapses/s of both;
+    latency: Poisson arrivals at `load` x the plain path's request capacity:
+    p50/p99 of Connect latency (arrival to completion) for both."""
+    from paper_2306_09855_amd import workloads as W
+    burst = W.serving_trace(episodes_per_slot=episodes_per_slot, burst=True)
+    n_req = sum(len(e.calls) + 3 for e in burst)
+    total = sum(e.n_syn for e in burst)
+    arena = int(max(64 << 30, 3.2 * 14 * total))
+    log(f"serving: {len(burst)} sessions, {n_req} requests, {total:.3g} synapses")
+    plain_cap = plain_run(burst, block_size)
+    log(f"serving: plain backlog {plain_cap['seconds']} s")
+    served_cap = serve_run(burst, n_streams, arena, block_size)
+    log(f"serving: served backlog {served_cap['seconds']} s")
+    rate = load * n_req / plain_cap["seconds"]
+    timed = W.serving_trace(episodes_per_slot=episodes_per_slot, rate=rate)
+    plain_lat = plain_run(timed, block_size)
+    served_lat = serve_run(timed, n_streams, arena, block_size)
+    log(f"serving: latency runs done (rate {rate:.0f} req/s)")
+    return {"sessions": len(burst), "slots": 32, "requests": n_req, "synapses": total,
+            "streams": n_streams, "block_size": block_size,
+            "backlog": {"served": served_cap, "plain": plain_cap,
+                        "speedup": round(served_cap["synapses_per_s"] / plain_cap["synapses_per_s"], 2)},
+            "poisson": {"rate_req_per_s": round(rate, 1), "load_vs_plain_capacity": load,
+                        "served": served_lat, "plain": plain_lat}}
 
 
 def main() -> int:
@@ -76,8 +239,10 @@ def main() -> int:
     ap.add_argument("--radix-bits", type=int, default=8)
     ap.add_argument("--sort-ranges", type=int, default=1024, help="static ranges (workgroups) of each sort pass")
     ap.add_argument("--block-size", type=int, default=1 << 24)
-    ap.add_argument("--cpu-sample", type=float, default=1.5e7, help="synapses of the oracle sample; 0 skips")
+    ap.add_argument("--cpu-sample", type=float, default=6e7, help="synapses of the oracle sample; 0 skips")
     ap.add_argument("--total", type=float, default=3.0e8)
+    ap.add_argument("--serve", type=int, default=1,
+                    help="also run the serving trace (32 sessions; p50/p99 Connect latency); 0 skips")
     ap.add_argument("--copy-probe", type=float, default=0,
                     help="only run a plain device copy of this many bytes (calibrates counter readings)")
     args = ap.parse_args()
@@ -201,7 +366,8 @@ def main() -> int:
             avg_s = total_ms / launches / 1e3
             achieved = per_launch_bytes / avg_s / 1e9
             roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                        "traffic": measured_traffic(dom, wl.name),
                         "bytes_per_launch": per_launch_bytes, "avg_launch_ms": round(avg_s * 1e3, 4)}
     path_alg = 42.0 * n_syn  # write each record once, read it and write it sorted once
     result = {
@@ -224,6 +390,13 @@ def main() -> int:
         "kernels": per_kernel,
     }
     net.close()
+    del net
+    torch.cuda.empty_cache()
+    if args.serve:
+        sv = serving_bench()
+        result["serving"] = sv
+        result["latency_p50_ms"] = sv["poisson"]["served"]["connect_p50_ms"]
+        result["latency_p99_ms"] = sv["poisson"]["served"]["connect_p99_ms"]
     if args.cpu_sample > 0 and wl.name == "microcircuit":
         result["cpu_baseline"] = cpu_baseline(int(args.cpu_sample))
     print(json.dumps(result))

@@ -223,6 +223,60 @@ int ng_graph_end(ng_ctx* ctx, ng_graph** out);
 int ng_graph_launch(ng_graph* graph, uint64_t seed);
 int ng_graph_destroy(ng_graph* graph);
 
+/* --- serving form ----------------------------------------------------------
+ * A server runs many model-building sessions over one device arena and a few
+ * streams.  Client threads submit requests; ng_submit_* only enqueue and
+ * return a ticket.  A scheduler thread admits requests in arrival order (each
+ * session's in the order submitted) while the arena has room -- a request
+ * that does not fit waits until memory comes back (another calibration's
+ * scratch, a closed session) and fails with NG_ERR_OOM only when nothing
+ * could bring memory back.  Connect calls admitted together from the sessions
+ * sharing a stream run as one generation launch; calibrations run on their
+ * session's stream, overlapping with other streams.  The arithmetic is that
+ * of a context of its own: a session's connections equal the same calls on
+ * ng_connect with the same seed.  Sessions are spread over the streams
+ * round-robin.  All streams must be non-null. */
+typedef struct ng_server ng_server;
+typedef struct ng_session ng_session;
+typedef struct {
+  uint64_t block_size;  /* as ng_config.block_size */
+  float h_ms;           /* as ng_config.h_ms */
+  int32_t radix_bits;   /* 0: default schedule, else as ng_set_tuning */
+  uint32_t sort_ranges; /* as ng_set_tuning (used when radix_bits != 0) */
+  uint32_t reserved;
+} ng_server_config;
+typedef struct {
+  int32_t status;       /* the request's own result (ng_status) */
+  int32_t kind;         /* 0 create_nodes, 1 connect, 2 calibrate, 3 close */
+  uint64_t n_conns;     /* connect: connections created; calibrate: connections sorted */
+  int64_t arrival_ns, admit_ns, done_ns;  /* host steady clock since the server started */
+} ng_ticket_info;
+typedef struct {
+  uint64_t submitted, launches, packed_calls, max_calls_per_launch, calibrations;
+  uint64_t sessions_opened, peak_arena_bytes, arena_used_bytes;
+} ng_server_stats;
+int ng_server_create(const ng_server_config* cfg, void* arena, uint64_t arena_bytes,
+                     void* const* streams, int n_streams, ng_server** out);
+/* Finish all submitted work, close the remaining sessions, release the server. */
+int ng_server_destroy(ng_server* server);
+int ng_session_open(ng_server* server, uint64_t seed, ng_session** out);
+/* Node creation is ordered with the session's other requests; the range is
+ * returned at once. */
+int ng_submit_create_nodes(ng_session* session, uint32_t n, ng_range* out, uint64_t* ticket);
+int ng_submit_connect(ng_session* session, ng_range src, ng_range tgt, const ng_conn_spec* conn,
+                      const ng_syn_spec* syn, uint64_t* ticket);
+int ng_submit_calibrate(ng_session* session, uint64_t* ticket);
+/* Close after the session's earlier requests; the handle is invalid afterwards. */
+int ng_submit_close(ng_session* session, uint64_t* ticket);
+/* Wait up to timeout_ns (< 0: forever) for a ticket.  NG_OK: finished, *out
+ * filled (out->status is the request's result) and the ticket consumed;
+ * NG_ERR_STATE: still running (the ticket stays valid). */
+int ng_wait(ng_server* server, uint64_t ticket, int64_t timeout_ns, ng_ticket_info* out);
+/* The session's context, for ng_get_connections / ng_copy_*; only while the
+ * session has no request pending. */
+int ng_session_context(ng_session* session, ng_ctx** out);
+int ng_server_get_stats(ng_server* server, ng_server_stats* out);
+
 /* Message of the calling thread's last error ("" if none). */
 const char* ng_last_error(void);
 

@@ -30,7 +30,10 @@ struct GenDesc {
   uint32_t d_lo;     // D_UNIFORM_INT: lo steps
   uint32_t d_range;  // D_UNIFORM_INT: hi - lo + 1
   float d_ms_lo, d_ms_width, h;  // D_UNIFORM_MS
+  int32_t max_delay; // largest delay this call can produce (host bookkeeping)
   uint64_t group0;   // batched form: index of this call's first 4-synapse group
+  char* const* blocks;        // batched form: block table of the call's context
+  const uint32_t* key;        // batched form: Philox key of the call's context
 };
 
 // --- generation -----------------------------------------------------------
@@ -38,9 +41,10 @@ struct GenDesc {
 hipError_t launch_generate(const GenDesc& d, const uint32_t* d_key, char* const* d_blocks, int log2B,
                            hipStream_t s);
 // All calls of a batch in one launch; d_descs[n_calls] device array sorted by
-// group0, total_groups = sum of ceil(n_new / 4).
+// group0, total_groups = sum of ceil(n_new / 4).  Each descriptor names its
+// own block table and key, so one launch may serve several contexts.
 hipError_t launch_generate_batch(const GenDesc* d_descs, uint32_t n_calls, uint64_t total_groups,
-                                 const uint32_t* d_key, char* const* d_blocks, int log2B, hipStream_t s);
+                                 int log2B, hipStream_t s);
 
 // --- calibration ----------------------------------------------------------
 struct SortGeom {

@@ -225,10 +225,7 @@ __device__ __forceinline__ void gen_any(const GenDesc& d, uint32_t g, uint32_t k
 // each lane finds its call by binary search over the calls' first groups.
 __global__ __launch_bounds__(kGenThreads) void k_generate_batch(const GenDesc* __restrict__ descs,
                                                                 uint32_t n_calls, uint64_t total_groups,
-                                                                const uint32_t* __restrict__ key,
-                                                                char* const* __restrict__ blocks,
                                                                 int log2B) {
-  const uint32_t key0 = key[0], key1 = key[1];
   for (uint64_t gg = (uint64_t)blockIdx.x * kGenThreads + threadIdx.x; gg < total_groups;
        gg += (uint64_t)gridDim.x * kGenThreads) {
     uint32_t lo = 0, hi = n_calls - 1;
@@ -237,12 +234,13 @@ __global__ __launch_bounds__(kGenThreads) void k_generate_batch(const GenDesc* _
       if (descs[mid].group0 <= gg) lo = mid; else hi = mid - 1;
     }
     const GenDesc d = descs[lo];
+    const uint32_t key0 = d.key[0], key1 = d.key[1];
     const uint32_t g = (uint32_t)(gg - d.group0);
     Quad q;
     if (d.d_kind == D_CONST) gen_any<false>(d, g, key0, key1, q);
     else gen_any<true>(d, g, key0, key1, q);
     const uint32_t i0 = g << 2;
-    store_quad(blocks, log2B, d.pos0 + i0, min(4u, d.n_new - i0), q);
+    store_quad(d.blocks, log2B, d.pos0 + i0, min(4u, d.n_new - i0), q);
   }
 }
 
@@ -803,11 +801,10 @@ hipError_t launch_generate(const GenDesc& d, const uint32_t* d_key, char* const*
 }
 
 hipError_t launch_generate_batch(const GenDesc* d_descs, uint32_t n_calls, uint64_t total_groups,
-                                 const uint32_t* d_key, char* const* d_blocks, int log2B, hipStream_t s) {
+                                 int log2B, hipStream_t s) {
   if (n_calls == 0 || total_groups == 0) return hipSuccess;
   const dim3 grid(gen_grid(total_groups));
-  hipLaunchKernelGGL(k_generate_batch, grid, dim3(kGenThreads), 0, s, d_descs, n_calls, total_groups, d_key,
-                     d_blocks, log2B);
+  hipLaunchKernelGGL(k_generate_batch, grid, dim3(kGenThreads), 0, s, d_descs, n_calls, total_groups, log2B);
   return hipGetLastError();
 }
 

@@ -1,0 +1,297 @@
+// Internal: the host runtime's context and helpers, shared by the context
+// API (ng_runtime.cpp) and the serving layer (ng_server.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/ng.h"
+#include "ng_internal.h"
+
+namespace ngrt {
+
+int fail(int code, const char* fmt, ...);
+
+constexpr uint64_t kAlign = 256;
+
+// First-fit sub-allocator over the caller's arena (host bookkeeping only).
+// Thread-safe.  A context that owns its arena frees immediately (reuse is
+// ordered by its single stream); an arena shared by contexts on several
+// streams gets frees through release_after(), which holds the range until an
+// event recorded after its last use has completed.
+class Arena {
+ public:
+  ~Arena() {
+    for (auto& d : deferred_) (void)hipEventDestroy(d.ev);
+  }
+  void init(char* base, uint64_t size) {
+    base_ = base;
+    size_ = size;
+    free_.clear();
+    if (size) free_[0] = size;
+  }
+  char* alloc(uint64_t bytes) {
+    std::lock_guard<std::mutex> lk(mu_);
+    reclaim_locked();
+    bytes = round_up(bytes ? bytes : 1);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        const uint64_t off = it->first, sz = it->second;
+        free_.erase(it);
+        if (sz > bytes) free_[off + bytes] = sz - bytes;
+        used_ += bytes;
+        peak_ = std::max(peak_, used_);
+        return base_ + off;
+      }
+    }
+    return nullptr;
+  }
+  void release(char* p, uint64_t bytes) {
+    std::lock_guard<std::mutex> lk(mu_);
+    release_locked(p, bytes);
+  }
+  // release once `ev` (recorded after the last use) has completed; takes the event
+  void release_after(char* p, uint64_t bytes, hipEvent_t ev) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(mu_);
+    deferred_.push_back({p, bytes, ev});
+  }
+  uint64_t deferred_bytes() {
+    std::lock_guard<std::mutex> lk(mu_);
+    reclaim_locked();
+    uint64_t b = 0;
+    for (auto& d : deferred_) b += round_up(d.bytes ? d.bytes : 1);
+    return b;
+  }
+  uint64_t size() const { return size_; }
+
+ private:
+  struct Deferred {
+    char* p;
+    uint64_t bytes;
+    hipEvent_t ev;
+  };
+  void reclaim_locked() {
+    size_t k = 0;
+    for (size_t i = 0; i < deferred_.size(); ++i) {
+      if (hipEventQuery(deferred_[i].ev) == hipSuccess) {
+        release_locked(deferred_[i].p, deferred_[i].bytes);
+        (void)hipEventDestroy(deferred_[i].ev);
+      } else {
+        deferred_[k++] = deferred_[i];
+      }
+    }
+    deferred_.resize(k);
+  }
+  void release_locked(char* p, uint64_t bytes) {
+    if (!p) return;
+    bytes = round_up(bytes ? bytes : 1);
+    uint64_t off = (uint64_t)(p - base_);
+    used_ -= bytes;
+    auto next = free_.lower_bound(off);
+    if (next != free_.end() && off + bytes == next->first) {
+      bytes += next->second;
+      next = free_.erase(next);
+    }
+    if (next != free_.begin()) {
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == off) {
+        prev->second += bytes;
+        return;
+      }
+    }
+    free_[off] = bytes;
+  }
+
+ public:
+  uint64_t used() const { return used_; }
+  uint64_t peak() const { return peak_; }
+  uint64_t largest_free() {
+    std::lock_guard<std::mutex> lk(mu_);
+    reclaim_locked();
+    uint64_t m = 0;
+    for (auto& kv : free_) m = std::max(m, kv.second);
+    return m;
+  }
+  static uint64_t round_up(uint64_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
+
+ private:
+  char* base_ = nullptr;
+  uint64_t size_ = 0;
+  std::map<uint64_t, uint64_t> free_;
+  uint64_t used_ = 0, peak_ = 0;
+  std::mutex mu_;
+  std::vector<Deferred> deferred_;
+};
+
+
+int bitwidth(uint64_t v);
+int64_t delay_steps_f32(float ms, float h);
+
+struct Plan {
+  ng::GenDesc d{};
+  uint64_t n_new = 0;
+  int32_t max_delay = 1;
+};
+
+// Validate one Connect call and fill its generation descriptor (Sec. 2.1).
+int plan_call(uint32_t n_nodes, ng_range src, ng_range tgt, const ng_conn_spec* conn,
+              const ng_syn_spec* syn, float h, Plan* out);
+
+}  // namespace ngrt
+
+struct ng_ctx {
+  ng_config cfg{};
+  int log2B = 24;
+  uint64_t B = 1ull << 24;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  ngrt::Arena own_arena;
+  ngrt::Arena* arena = &own_arena;  // a server's shared arena for sessions
+  bool shared_arena = false;        // frees wait for this context's stream
+  uint64_t held = 0;                // arena bytes this context holds
+  uint64_t need = 0;                // bytes the last NG_ERR_OOM asked for
+
+  uint32_t n_nodes = 0;
+  uint32_t next_cid = 0;
+  uint64_t n_conns = 0;
+  int32_t max_delay = 1;
+
+  std::vector<char*> blocks;      // current storage, host copy of the device table
+  char** d_tab[2] = {nullptr, nullptr};
+  int cur = 0;                    // d_tab[cur] describes `blocks`
+  uint32_t tab_cap = 0;
+
+  bool calibrated = false;
+  uint32_t* d_group_ptr = nullptr;
+  uint64_t group_ptr_bytes = 0;
+  uint32_t* d_group_start = nullptr;
+  uint64_t group_start_bytes = 0;
+  uint32_t* d_scalars = nullptr;  // [0] = G
+  uint32_t gi_nodes = 0;          // n_nodes the index was built for
+
+  int radix_bits = 8;
+  uint32_t sort_ranges = 1024;  // static ranges (= workgroups) of each sort pass
+  int sticky = NG_OK;
+  std::string sticky_msg;
+
+  // optional per-kernel timing with HIP events on the context's stream
+  struct Timed {
+    const char* name;
+    hipEvent_t a, b;
+  };
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<Timed> pending;
+  std::map<std::string, std::pair<double, uint64_t>> timing_acc;
+
+  // graph capture: while capturing, nothing may synchronize; descriptors go
+  // to a pinned region the graph owns.  A context with live graphs is frozen.
+  bool capturing = false;
+  bool timing_before_capture = false;
+  char* cap_stage = nullptr;
+  uint64_t cap_stage_cap = 0, cap_stage_used = 0;
+  int frozen = 0;
+
+  // pinned staging for batched descriptors
+  ng::GenDesc* h_stage = nullptr;
+  uint64_t h_stage_cap = 0;
+  hipEvent_t stage_done = nullptr;
+};
+
+namespace ngrt {
+
+// Allocate from the context's arena, counting what the context holds.
+char* ctx_alloc(ng_ctx* c, uint64_t bytes);
+
+// A set of context allocations made all-or-nothing.
+struct AllocSet {
+  ng_ctx* ctx;
+  std::vector<std::pair<char*, uint64_t>> items;
+  bool ok = true;
+  uint64_t asked = 0;  // everything requested, also after a failure
+  explicit AllocSet(ng_ctx* c) : ctx(c) {}
+  char* get(uint64_t bytes) {
+    asked += Arena::round_up(bytes ? bytes : 1);
+    if (!ok) return nullptr;
+    char* p = ctx_alloc(ctx, bytes);
+    if (!p) {
+      ok = false;
+      return nullptr;
+    }
+    items.emplace_back(p, bytes);
+    return p;
+  }
+  // nothing was enqueued on these yet: return them at once
+  void release_all() {
+    for (auto& it : items) {
+      ctx->arena->release(it.first, it.second);
+      ctx->held -= Arena::round_up(it.second ? it.second : 1);
+    }
+    items.clear();
+  }
+};
+
+int dev_fail(ng_ctx* c, hipError_t e, const char* what);
+hipEvent_t take_event(ng_ctx* c);
+void collect_timing(ng_ctx* c);
+int enter(ng_ctx* c);
+hipError_t set_table(char** tab, uint32_t first, const std::vector<char*>& ptrs, uint32_t from,
+                     hipStream_t s);
+uint32_t* key_ptr(ng_ctx* c);
+hipError_t set_seed(ng_ctx* c, uint64_t seed);
+int mutable_state(ng_ctx* c);
+int not_capturing(ng_ctx* c);
+int reserve_blocks(ng_ctx* c, uint64_t n_new);
+void release_index(ng_ctx* c);
+// Return memory to the context's arena (deferred past the stream's pending
+// work when the arena is shared).
+void ctx_free(ng_ctx* c, char* p, uint64_t bytes);
+// A context over a shared arena on `stream` (server sessions).
+int ctx_init(const ng_config* cfg, Arena* shared, char* base, uint64_t bytes, hipStream_t stream,
+             ng_ctx** out);
+int ctx_create_shared(const ng_config* cfg, Arena* arena, hipStream_t stream, ng_ctx** out);
+// Release everything a context holds in its arena, then delete it.
+void ctx_destroy_release(ng_ctx* c);
+// Plan a Connect call and reserve its blocks without launching it; the
+// descriptor carries the block table and key of this context.
+int connect_prepare(ng_ctx* c, ng_range src, ng_range tgt, const ng_conn_spec* conn,
+                    const ng_syn_spec* syn, ng::GenDesc* out, uint64_t* out_n);
+// NG_OK if every descriptor names a block table and a key (checked on the host
+// before any batched launch).
+int check_descs(const std::vector<ng::GenDesc>& descs);
+// Commit a prepared call: consume its call id and count its connections.
+void connect_commit(ng_ctx* c, const ng::GenDesc& d, int32_t max_delay);
+
+}  // namespace ngrt
+
+#define NG_HIP(ctx, expr, what)                 \
+  do {                                          \
+    hipError_t e_ = (expr);                     \
+    if (e_ != hipSuccess) return dev_fail(ctx, e_, what); \
+  } while (0)
+
+// Launch `expr` on the context stream; with timing on, bracket it by events.
+#define NG_LAUNCH(ctx, name, expr)                                              \
+  do {                                                                          \
+    hipEvent_t a_ = nullptr;                                                    \
+    if ((ctx)->timing && (a_ = take_event(ctx)) != nullptr)                     \
+      (void)hipEventRecord(a_, (ctx)->stream);                                  \
+    hipError_t e_ = (expr);                                                     \
+    if (e_ != hipSuccess) return dev_fail(ctx, e_, name);                       \
+    if (a_) {                                                                   \
+      hipEvent_t b_ = take_event(ctx);                                          \
+      if (b_) {                                                                 \
+        (void)hipEventRecord(b_, (ctx)->stream);                                \
+        (ctx)->pending.push_back({name, a_, b_});                               \
+      } else {                                                                  \
+        (ctx)->ev_pool.push_back(a_);                                           \
+      }                                                                         \
+    }                                                                           \
+  } while (0)

@@ -14,10 +14,10 @@
 #include <string>
 #include <vector>
 
-#include "../../include/ng.h"
-#include "ng_internal.h"
+#include "ng_rt.h"
 
-namespace {
+namespace ngrt {
+
 
 thread_local std::string g_err;
 
@@ -31,87 +31,6 @@ int fail(int code, const char* fmt, ...) {
   return code;
 }
 
-constexpr uint64_t kAlign = 256;
-
-// First-fit sub-allocator over the caller's arena (host bookkeeping only).
-class Arena {
- public:
-  void init(char* base, uint64_t size) {
-    base_ = base;
-    size_ = size;
-    free_.clear();
-    if (size) free_[0] = size;
-  }
-  char* alloc(uint64_t bytes) {
-    bytes = round_up(bytes ? bytes : 1);
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second >= bytes) {
-        const uint64_t off = it->first, sz = it->second;
-        free_.erase(it);
-        if (sz > bytes) free_[off + bytes] = sz - bytes;
-        used_ += bytes;
-        peak_ = std::max(peak_, used_);
-        return base_ + off;
-      }
-    }
-    return nullptr;
-  }
-  void release(char* p, uint64_t bytes) {
-    if (!p) return;
-    bytes = round_up(bytes ? bytes : 1);
-    uint64_t off = (uint64_t)(p - base_);
-    used_ -= bytes;
-    auto next = free_.lower_bound(off);
-    if (next != free_.end() && off + bytes == next->first) {
-      bytes += next->second;
-      next = free_.erase(next);
-    }
-    if (next != free_.begin()) {
-      auto prev = std::prev(next);
-      if (prev->first + prev->second == off) {
-        prev->second += bytes;
-        return;
-      }
-    }
-    free_[off] = bytes;
-  }
-  uint64_t used() const { return used_; }
-  uint64_t peak() const { return peak_; }
-  uint64_t largest_free() const {
-    uint64_t m = 0;
-    for (auto& kv : free_) m = std::max(m, kv.second);
-    return m;
-  }
-  static uint64_t round_up(uint64_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
-
- private:
-  char* base_ = nullptr;
-  uint64_t size_ = 0;
-  std::map<uint64_t, uint64_t> free_;
-  uint64_t used_ = 0, peak_ = 0;
-};
-
-// A set of arena allocations made all-or-nothing.
-struct AllocSet {
-  Arena* arena;
-  std::vector<std::pair<char*, uint64_t>> items;
-  bool ok = true;
-  explicit AllocSet(Arena* a) : arena(a) {}
-  char* get(uint64_t bytes) {
-    if (!ok) return nullptr;
-    char* p = arena->alloc(bytes);
-    if (!p) {
-      ok = false;
-      return nullptr;
-    }
-    items.emplace_back(p, bytes);
-    return p;
-  }
-  void release_all() {
-    for (auto& it : items) arena->release(it.first, it.second);
-    items.clear();
-  }
-};
 
 int bitwidth(uint64_t v) {
   int b = 0;
@@ -130,12 +49,6 @@ int64_t delay_steps_f32(float ms, float h) {
   if (r > 2147483647.0f) return INT64_MAX;
   return (int64_t)r;
 }
-
-struct Plan {
-  ng::GenDesc d{};
-  uint64_t n_new = 0;
-  int32_t max_delay = 1;
-};
 
 int plan_call(uint32_t n_nodes, ng_range src, ng_range tgt, const ng_conn_spec* conn,
               const ng_syn_spec* syn, float h, Plan* out) {
@@ -242,76 +155,12 @@ int plan_call(uint32_t n_nodes, ng_range src, ng_range tgt, const ng_conn_spec* 
   return NG_OK;
 }
 
-}  // namespace
-
-struct ng_ctx {
-  ng_config cfg{};
-  int log2B = 24;
-  uint64_t B = 1ull << 24;
-  hipStream_t stream = nullptr;
-  int device = 0;
-  Arena arena;
-
-  uint32_t n_nodes = 0;
-  uint32_t next_cid = 0;
-  uint64_t n_conns = 0;
-  int32_t max_delay = 1;
-
-  std::vector<char*> blocks;      // current storage, host copy of the device table
-  char** d_tab[2] = {nullptr, nullptr};
-  int cur = 0;                    // d_tab[cur] describes `blocks`
-  uint32_t tab_cap = 0;
-
-  bool calibrated = false;
-  uint32_t* d_group_ptr = nullptr;
-  uint64_t group_ptr_bytes = 0;
-  uint32_t* d_group_start = nullptr;
-  uint64_t group_start_bytes = 0;
-  uint32_t* d_scalars = nullptr;  // [0] = G
-  uint32_t gi_nodes = 0;          // n_nodes the index was built for
-
-  int radix_bits = 8;
-  uint32_t sort_ranges = 1024;  // static ranges (= workgroups) of each sort pass
-  int sticky = NG_OK;
-  std::string sticky_msg;
-
-  // optional per-kernel timing with HIP events on the context's stream
-  struct Timed {
-    const char* name;
-    hipEvent_t a, b;
-  };
-  bool timing = false;
-  std::vector<hipEvent_t> ev_pool;
-  std::vector<Timed> pending;
-  std::map<std::string, std::pair<double, uint64_t>> timing_acc;
-
-  // graph capture: while capturing, nothing may synchronize; descriptors go
-  // to a pinned region the graph owns.  A context with live graphs is frozen.
-  bool capturing = false;
-  bool timing_before_capture = false;
-  char* cap_stage = nullptr;
-  uint64_t cap_stage_cap = 0, cap_stage_used = 0;
-  int frozen = 0;
-
-  // pinned staging for batched descriptors
-  ng::GenDesc* h_stage = nullptr;
-  uint64_t h_stage_cap = 0;
-  hipEvent_t stage_done = nullptr;
-};
-
-namespace {
 
 int dev_fail(ng_ctx* c, hipError_t e, const char* what) {
   c->sticky = NG_ERR_DEVICE;
   c->sticky_msg = std::string(what) + ": " + hipGetErrorString(e);
   return fail(NG_ERR_DEVICE, "%s", c->sticky_msg.c_str());
 }
-
-#define NG_HIP(ctx, expr, what)                 \
-  do {                                          \
-    hipError_t e_ = (expr);                     \
-    if (e_ != hipSuccess) return dev_fail(ctx, e_, what); \
-  } while (0)
 
 hipEvent_t take_event(ng_ctx* c) {
   if (!c->ev_pool.empty()) {
@@ -323,25 +172,6 @@ hipEvent_t take_event(ng_ctx* c) {
   if (hipEventCreate(&e) != hipSuccess) return nullptr;
   return e;
 }
-
-// Launch `expr` on the context stream; with timing on, bracket it by events.
-#define NG_LAUNCH(ctx, name, expr)                                              \
-  do {                                                                          \
-    hipEvent_t a_ = nullptr;                                                    \
-    if ((ctx)->timing && (a_ = take_event(ctx)) != nullptr)                     \
-      (void)hipEventRecord(a_, (ctx)->stream);                                  \
-    hipError_t e_ = (expr);                                                     \
-    if (e_ != hipSuccess) return dev_fail(ctx, e_, name);                       \
-    if (a_) {                                                                   \
-      hipEvent_t b_ = take_event(ctx);                                          \
-      if (b_) {                                                                 \
-        (void)hipEventRecord(b_, (ctx)->stream);                                \
-        (ctx)->pending.push_back({name, a_, b_});                               \
-      } else {                                                                  \
-        (ctx)->ev_pool.push_back(a_);                                           \
-      }                                                                         \
-    }                                                                           \
-  } while (0)
 
 void collect_timing(ng_ctx* c) {
   for (auto& t : c->pending) {
@@ -400,12 +230,16 @@ int not_capturing(ng_ctx* c) {
 // Eq. (1) plus allocation; all-or-nothing.
 int reserve_blocks(ng_ctx* c, uint64_t n_new) {
   const uint64_t nb = ng_blocks_needed(c->n_conns, n_new, c->B, c->blocks.size());
-  if (c->blocks.size() + nb > c->tab_cap) return fail(NG_ERR_OOM, "block table full");
+  if (c->blocks.size() + nb > c->tab_cap) {
+    c->need = ~0ull;  // no release elsewhere makes room in the table
+    return fail(NG_ERR_OOM, "block table full");
+  }
   std::vector<char*> fresh;
   for (uint64_t b = 0; b < nb; ++b) {
-    char* p = c->arena.alloc(ng::kBytesPerConn * c->B);
+    char* p = ctx_alloc(c, ng::kBytesPerConn * c->B);
     if (!p) {
-      for (char* q : fresh) c->arena.release(q, ng::kBytesPerConn * c->B);
+      for (char* q : fresh) ctx_free(c, q, ng::kBytesPerConn * c->B);
+      c->need = nb * Arena::round_up(ng::kBytesPerConn * c->B);
       return fail(NG_ERR_OOM, "arena cannot hold %llu more blocks of %llu connections",
                   (unsigned long long)nb, (unsigned long long)c->B);
     }
@@ -418,13 +252,140 @@ int reserve_blocks(ng_ctx* c, uint64_t n_new) {
 }
 
 void release_index(ng_ctx* c) {
-  c->arena.release((char*)c->d_group_ptr, c->group_ptr_bytes);
-  c->arena.release((char*)c->d_group_start, c->group_start_bytes);
+  ctx_free(c, (char*)c->d_group_ptr, c->group_ptr_bytes);
+  ctx_free(c, (char*)c->d_group_start, c->group_start_bytes);
   c->d_group_ptr = c->d_group_start = nullptr;
   c->group_ptr_bytes = c->group_start_bytes = 0;
 }
 
-}  // namespace
+int check_descs(const std::vector<ng::GenDesc>& descs) {
+  for (const auto& d : descs)
+    if (!d.blocks || !d.key) return fail(NG_ERR_STATE, "internal: a generation descriptor has no block table or key");
+  return NG_OK;
+}
+
+char* ctx_alloc(ng_ctx* c, uint64_t bytes) {
+  char* p = c->arena->alloc(bytes);
+  if (p) c->held += Arena::round_up(bytes ? bytes : 1);
+  return p;
+}
+
+void ctx_free(ng_ctx* c, char* p, uint64_t bytes) {
+  if (!p) return;
+  c->held -= Arena::round_up(bytes ? bytes : 1);
+  if (!c->shared_arena) {
+    c->arena->release(p, bytes);
+    return;
+  }
+  hipEvent_t ev = nullptr;
+  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess &&
+      hipEventRecord(ev, c->stream) == hipSuccess) {
+    c->arena->release_after(p, bytes, ev);
+  } else {
+    // cannot order the release: wait for the stream instead
+    if (ev) (void)hipEventDestroy(ev);
+    (void)hipStreamSynchronize(c->stream);
+    c->arena->release(p, bytes);
+  }
+}
+
+// Common construction: an own arena over [base, base + bytes), or a shared one.
+int ctx_init(const ng_config* cfg, Arena* shared, char* base, uint64_t bytes, hipStream_t stream,
+             ng_ctx** out) {
+  if (!cfg || !out) return fail(NG_ERR_INVALID_ARG, "null config or output");
+  uint64_t B = cfg->block_size ? cfg->block_size : (1ull << 24);
+  if (B & (B - 1) || B < (1ull << 16) || B > (1ull << 30))
+    return fail(NG_ERR_INVALID_ARG, "block_size must be a power of two in [2^16, 2^30]");
+  if (!(cfg->h_ms >= 0) || !std::isfinite(cfg->h_ms)) return fail(NG_ERR_INVALID_ARG, "bad time resolution");
+  ng_ctx* c = new ng_ctx();
+  c->cfg = *cfg;
+  c->cfg.block_size = B;
+  if (c->cfg.h_ms == 0) c->cfg.h_ms = 0.1f;
+  c->B = B;
+  c->log2B = bitwidth(B) - 1;
+  c->stream = stream;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return fail(NG_ERR_DEVICE, "no HIP device");
+  }
+  if (shared) {
+    c->arena = shared;
+    c->shared_arena = true;
+    bytes = shared->size();
+  } else {
+    c->arena->init(base, bytes);
+  }
+  c->tab_cap = (uint32_t)std::min<uint64_t>(bytes / (ng::kBytesPerConn * B) + 2, 1u << 20);
+  for (int t = 0; t < 2; ++t) c->d_tab[t] = (char**)ctx_alloc(c, 8ull * c->tab_cap);
+  c->d_scalars = (uint32_t*)ctx_alloc(c, 64);
+  if (!c->d_tab[0] || !c->d_tab[1] || !c->d_scalars) {
+    for (int t = 0; t < 2; ++t)
+      if (c->d_tab[t]) c->arena->release((char*)c->d_tab[t], 8ull * c->tab_cap);
+    if (c->d_scalars) c->arena->release((char*)c->d_scalars, 64);
+    delete c;
+    return fail(NG_ERR_OOM, "arena too small");
+  }
+  if (hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming) != hipSuccess) {
+    delete c;
+    return fail(NG_ERR_DEVICE, "hipEventCreate failed");
+  }
+  if (ng::launch_fill_u32(c->d_scalars, 0u, 16, c->stream) != hipSuccess ||
+      set_seed(c, c->cfg.seed) != hipSuccess) {
+    (void)hipEventDestroy(c->stage_done);
+    delete c;
+    return fail(NG_ERR_DEVICE, "kernel launch failed");
+  }
+  *out = c;
+  return NG_OK;
+}
+
+int ctx_create_shared(const ng_config* cfg, Arena* arena, hipStream_t stream, ng_ctx** out) {
+  return ctx_init(cfg, arena, nullptr, 0, stream, out);
+}
+
+void ctx_destroy_release(ng_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  for (char* b : c->blocks) ctx_free(c, b, ng::kBytesPerConn * c->B);
+  c->blocks.clear();
+  release_index(c);
+  for (int t = 0; t < 2; ++t) ctx_free(c, (char*)c->d_tab[t], 8ull * c->tab_cap);
+  ctx_free(c, (char*)c->d_scalars, 64);
+  if (c->h_stage) (void)hipHostFree(c->h_stage);
+  if (c->stage_done) (void)hipEventDestroy(c->stage_done);
+  collect_timing(c);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  delete c;
+}
+
+int connect_prepare(ng_ctx* c, ng_range src, ng_range tgt, const ng_conn_spec* conn,
+                    const ng_syn_spec* syn, ng::GenDesc* out, uint64_t* out_n) {
+  Plan p;
+  if (int rc = plan_call(c->n_nodes, src, tgt, conn, syn, c->cfg.h_ms, &p)) return rc;
+  if (c->next_cid == 0xFFFFFFFFu) return fail(NG_ERR_TOO_LARGE, "connect call ids exhausted");
+  if (c->n_conns + p.n_new > 0xFFFFFFFFull)
+    return fail(NG_ERR_TOO_LARGE, "a context holds at most 2^32-1 connections");
+  if (int rc = reserve_blocks(c, p.n_new)) return rc;
+  p.d.pos0 = c->n_conns;
+  p.d.cid = c->next_cid;
+  p.d.blocks = c->d_tab[c->cur];
+  p.d.key = key_ptr(c);
+  p.d.max_delay = p.max_delay;
+  *out = p.d;
+  if (out_n) *out_n = p.n_new;
+  return NG_OK;
+}
+
+void connect_commit(ng_ctx* c, const ng::GenDesc& d, int32_t max_delay) {
+  c->next_cid++;
+  c->n_conns += d.n_new;
+  c->max_delay = std::max(c->max_delay, max_delay);
+  if (d.n_new) c->calibrated = false;
+}
+
+}  // namespace ngrt
+
+using namespace ngrt;
 
 extern "C" {
 
@@ -447,49 +408,8 @@ int ng_plan_count(uint32_t n_nodes, ng_range src, ng_range tgt, const ng_conn_sp
 }
 
 int ng_create(const ng_config* cfg, void* arena, uint64_t arena_bytes, void* stream, ng_ctx** out) {
-  if (!cfg || !out) return fail(NG_ERR_INVALID_ARG, "null config or output");
   if (!arena || ((uintptr_t)arena % kAlign)) return fail(NG_ERR_INVALID_ARG, "arena must be 256-byte aligned");
-  uint64_t B = cfg->block_size ? cfg->block_size : (1ull << 24);
-  if (B & (B - 1) || B < (1ull << 16) || B > (1ull << 30))
-    return fail(NG_ERR_INVALID_ARG, "block_size must be a power of two in [2^16, 2^30]");
-  if (!(cfg->h_ms >= 0) || !std::isfinite(cfg->h_ms)) return fail(NG_ERR_INVALID_ARG, "bad time resolution");
-  ng_ctx* c = new ng_ctx();
-  c->cfg = *cfg;
-  c->cfg.block_size = B;
-  if (c->cfg.h_ms == 0) c->cfg.h_ms = 0.1f;
-  c->B = B;
-  c->log2B = bitwidth(B) - 1;
-  c->stream = (hipStream_t)stream;
-  if (hipGetDevice(&c->device) != hipSuccess) {
-    delete c;
-    return fail(NG_ERR_DEVICE, "no HIP device");
-  }
-  c->arena.init((char*)arena, arena_bytes);
-  c->tab_cap = (uint32_t)std::min<uint64_t>(arena_bytes / (ng::kBytesPerConn * B) + 2, 1u << 20);
-  for (int t = 0; t < 2; ++t) {
-    c->d_tab[t] = (char**)c->arena.alloc(8ull * c->tab_cap);
-    if (!c->d_tab[t]) {
-      delete c;
-      return fail(NG_ERR_OOM, "arena too small");
-    }
-  }
-  c->d_scalars = (uint32_t*)c->arena.alloc(64);
-  if (!c->d_scalars) {
-    delete c;
-    return fail(NG_ERR_OOM, "arena too small");
-  }
-  if (hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming) != hipSuccess) {
-    delete c;
-    return fail(NG_ERR_DEVICE, "hipEventCreate failed");
-  }
-  if (ng::launch_fill_u32(c->d_scalars, 0u, 16, c->stream) != hipSuccess ||
-      set_seed(c, c->cfg.seed) != hipSuccess) {
-    (void)hipEventDestroy(c->stage_done);
-    delete c;
-    return fail(NG_ERR_DEVICE, "kernel launch failed");
-  }
-  *out = c;
-  return NG_OK;
+  return ctx_init(cfg, nullptr, (char*)arena, arena_bytes, (hipStream_t)stream, out);
 }
 
 int ng_destroy(ng_ctx* c) {
@@ -518,24 +438,14 @@ int ng_connect(ng_ctx* c, ng_range src, ng_range tgt, const ng_conn_spec* conn, 
                uint32_t* out_cid, uint64_t* out_first, uint64_t* out_n) {
   if (int rc = enter(c)) return rc;
   if (int rc = mutable_state(c)) return rc;
-  Plan p;
-  if (int rc = plan_call(c->n_nodes, src, tgt, conn, syn, c->cfg.h_ms, &p)) return rc;
-  if (c->next_cid == 0xFFFFFFFFu) return fail(NG_ERR_TOO_LARGE, "connect call ids exhausted");
-  if (c->n_conns + p.n_new > 0xFFFFFFFFull)
-    return fail(NG_ERR_TOO_LARGE, "a context holds at most 2^32-1 connections");
-  if (int rc = reserve_blocks(c, p.n_new)) return rc;
-  p.d.pos0 = c->n_conns;
-  p.d.cid = c->next_cid;
-  if (p.n_new) {
-    NG_LAUNCH(c, "generate", ng::launch_generate(p.d, key_ptr(c), c->d_tab[c->cur], c->log2B, c->stream));
-    c->calibrated = false;
-  }
-  if (out_cid) *out_cid = c->next_cid;
-  if (out_first) *out_first = c->n_conns;
-  if (out_n) *out_n = p.n_new;
-  c->next_cid++;
-  c->n_conns += p.n_new;
-  c->max_delay = std::max(c->max_delay, p.max_delay);
+  ng::GenDesc d;
+  uint64_t n = 0;
+  if (int rc = connect_prepare(c, src, tgt, conn, syn, &d, &n)) return rc;
+  if (n) NG_LAUNCH(c, "generate", ng::launch_generate(d, key_ptr(c), c->d_tab[c->cur], c->log2B, c->stream));
+  if (out_cid) *out_cid = d.cid;
+  if (out_first) *out_first = d.pos0;
+  if (out_n) *out_n = n;
+  connect_commit(c, d, d.max_delay);
   return NG_OK;
 }
 
@@ -559,6 +469,7 @@ int ng_connect_batch(ng_ctx* c, uint32_t n_calls, const ng_range* src, const ng_
     p.d.pos0 = pos;
     p.d.cid = c->next_cid + i;
     p.d.group0 = groups;
+    p.d.key = key_ptr(c);
     pos += p.n_new;
     groups += (p.n_new + 3) / 4;
     maxd = std::max(maxd, p.max_delay);
@@ -570,18 +481,23 @@ int ng_connect_batch(ng_ctx* c, uint32_t n_calls, const ng_range* src, const ng_
   const uint64_t desc_bytes = descs.size() * sizeof(ng::GenDesc);
   char* d_descs = nullptr;
   if (!descs.empty()) {
-    d_descs = c->arena.alloc(desc_bytes);
+    d_descs = ctx_alloc(c, desc_bytes);
     if (!d_descs) return fail(NG_ERR_OOM, "arena cannot hold the call descriptors");
   }
   if (int rc = reserve_blocks(c, total)) {
-    c->arena.release(d_descs, desc_bytes);
+    ctx_free(c, d_descs, desc_bytes);
+    return rc;
+  }
+  for (auto& d : descs) d.blocks = c->d_tab[c->cur];
+  if (int rc = check_descs(descs)) {
+    ctx_free(c, d_descs, desc_bytes);
     return rc;
   }
   if (!descs.empty() && c->capturing) {
     // the upload becomes a graph node reading this pinned region on every replay
     const uint64_t need = (desc_bytes + 255) / 256 * 256;
     if (c->cap_stage_used + need > c->cap_stage_cap) {
-      c->arena.release(d_descs, desc_bytes);
+      ctx_free(c, d_descs, desc_bytes);
       return fail(NG_ERR_OOM, "graph staging region full (%llu bytes)", (unsigned long long)c->cap_stage_cap);
     }
     char* h = c->cap_stage + c->cap_stage_used;
@@ -604,8 +520,8 @@ int ng_connect_batch(ng_ctx* c, uint32_t n_calls, const ng_range* src, const ng_
   if (!descs.empty()) {
     NG_LAUNCH(c, "generate_batch",
               ng::launch_generate_batch((const ng::GenDesc*)d_descs, (uint32_t)descs.size(), groups,
-                                        key_ptr(c), c->d_tab[c->cur], c->log2B, c->stream));
-    c->arena.release(d_descs, desc_bytes);  // stream-ordered reuse is safe
+                                        c->log2B, c->stream));
+    ctx_free(c, d_descs, desc_bytes);  // stream-ordered reuse is safe
     c->calibrated = false;
   }
   c->next_cid += n_calls;
@@ -657,11 +573,14 @@ int ng_calibrate(ng_ctx* c) {
   const uint64_t counts_n = ((uint64_t)1 << nbits[0]) * g.n_ranges;
 
   const uint64_t nblk = (N + c->B - 1) / c->B;
-  if (nblk > c->tab_cap) return fail(NG_ERR_OOM, "block table full");
+  if (nblk > c->tab_cap) {
+    c->need = ~0ull;
+    return fail(NG_ERR_OOM, "block table full");
+  }
   const uint64_t gi_tiles = (N + ng::gi_tile_size() - 1) / ng::gi_tile_size();
   const uint64_t gcap = std::min<uint64_t>(N, (uint64_t)nn * (uint64_t)c->max_delay) + 1;
 
-  AllocSet as(&c->arena);
+  AllocSet as(c);
   std::vector<char*> nblocks;
   for (uint64_t b = 0; b < nblk && as.ok; ++b) nblocks.push_back(as.get(ng::kBytesPerConn * c->B));
   uint32_t* keys[2] = {nullptr, nullptr};
@@ -679,12 +598,14 @@ int ng_calibrate(ng_ctx* c) {
   // the new index replaces the old one, so release the old one first
   const uint64_t gp_bytes = 4 * (nn + 1ull), gs_bytes = 4 * gcap;
   release_index(c);
-  uint32_t* gptr = (uint32_t*)c->arena.alloc(gp_bytes);
-  uint32_t* gstart = gptr ? (uint32_t*)c->arena.alloc(gs_bytes) : nullptr;
+  uint32_t* gptr = (uint32_t*)ctx_alloc(c, gp_bytes);
+  uint32_t* gstart = gptr ? (uint32_t*)ctx_alloc(c, gs_bytes) : nullptr;
   if (!as.ok || !gptr || !gstart) {
     as.release_all();
-    c->arena.release((char*)gptr, gp_bytes);
-    c->arena.release((char*)gstart, gs_bytes);
+    ctx_free(c, (char*)gptr, gp_bytes);
+    ctx_free(c, (char*)gstart, gs_bytes);
+    c->need = as.asked + Arena::round_up(gp_bytes) + Arena::round_up(gs_bytes);
+    c->calibrated = false;  // the old index was released to make room
     return fail(NG_ERR_OOM, "arena cannot hold the calibration buffers (N=%llu)", (unsigned long long)N);
   }
   const int nxt = 1 - c->cur;
@@ -727,8 +648,8 @@ int ng_calibrate(ng_ctx* c) {
   NG_LAUNCH(c, "group_ptr", ng::launch_group_ptr(group_src, c->d_scalars, nn, gptr, s));
 
   // old storage and scratch return to the arena (stream-ordered reuse)
-  for (char* b : c->blocks) c->arena.release(b, ng::kBytesPerConn * c->B);
-  for (size_t i = nblk; i < as.items.size(); ++i) c->arena.release(as.items[i].first, as.items[i].second);
+  for (char* b : c->blocks) ctx_free(c, b, ng::kBytesPerConn * c->B);
+  for (size_t i = nblk; i < as.items.size(); ++i) ctx_free(c, as.items[i].first, as.items[i].second);
   c->blocks = nblocks;
   c->cur = nxt;
   c->d_group_ptr = gptr;
@@ -743,7 +664,7 @@ int ng_calibrate(ng_ctx* c) {
 int ng_reset(ng_ctx* c) {
   if (int rc = enter(c)) return rc;
   if (int rc = mutable_state(c)) return rc;
-  for (char* b : c->blocks) c->arena.release(b, ng::kBytesPerConn * c->B);
+  for (char* b : c->blocks) ctx_free(c, b, ng::kBytesPerConn * c->B);
   c->blocks.clear();
   release_index(c);
   c->n_nodes = 0;
@@ -937,9 +858,9 @@ int ng_copy_group_index(ng_ctx* c, uint32_t* group_ptr, uint32_t* group_start) {
 
 int ng_memory_stats(ng_ctx* c, uint64_t* used, uint64_t* peak, uint64_t* largest_free) {
   if (!c) return fail(NG_ERR_INVALID_ARG, "null context");
-  if (used) *used = c->arena.used();
-  if (peak) *peak = c->arena.peak();
-  if (largest_free) *largest_free = c->arena.largest_free();
+  if (used) *used = c->arena->used();
+  if (peak) *peak = c->arena->peak();
+  if (largest_free) *largest_free = c->arena->largest_free();
   return NG_OK;
 }
 

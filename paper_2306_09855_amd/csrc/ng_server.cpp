@@ -1,0 +1,518 @@
+// Serving form: many model-building sessions share one device arena and a few
+// streams.  Client threads submit node creation, Connect, Calibrate and Close
+// requests; one scheduler thread admits them in arrival order (each session's
+// requests in its own order) as memory in the shared arena allows, packs the
+// admitted Connect calls of all sessions on a stream into a single generation
+// launch, and runs calibrations on their sessions' streams, so the work of
+// different sessions overlaps on the device.  Every request carries its
+// arrival, admission and completion times (host steady clock).
+//
+// Arithmetic is unchanged: a session's result equals the same calls issued on
+// a context of its own (same seed, same call order).
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <thread>
+#include <unordered_map>
+
+#include "ng_rt.h"
+
+using namespace ngrt;
+
+namespace {
+
+int64_t now_ns(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// An event shared by every request finished by the same launch.
+struct EventBox {
+  hipEvent_t ev = nullptr;
+  ~EventBox() {
+    if (ev) (void)hipEventDestroy(ev);
+  }
+};
+
+enum ReqKind { REQ_CREATE_NODES = 0, REQ_CONNECT = 1, REQ_CALIBRATE = 2, REQ_CLOSE = 3 };
+
+struct Request {
+  uint64_t ticket = 0;
+  ng_session* sess = nullptr;
+  int kind = REQ_CONNECT;
+  uint32_t n_nodes = 0;
+  ng_range src{}, tgt{};
+  ng_conn_spec conn{};
+  ng_syn_spec syn{};
+  int64_t arrival_ns = 0, admit_ns = 0, done_ns = 0;
+  int32_t status = NG_OK;
+  uint64_t n_conns = 0;
+  std::string msg;
+  std::shared_ptr<EventBox> done_ev;
+  bool done = false;
+};
+
+// Pinned upload region for one packed launch; reusable once its copy ran.
+struct Stage {
+  char* p = nullptr;
+  uint64_t cap = 0;
+  std::shared_ptr<EventBox> busy;  // event after the upload that reads it
+};
+
+}  // namespace
+
+struct ng_session {
+  ng_server* server = nullptr;
+  ng_ctx* ctx = nullptr;
+  int stream = 0;
+  uint32_t client_nodes = 0;   // node count as the client sees it (ranges returned at submit)
+  std::deque<Request*> queue;  // submitted, not yet admitted, in order
+  bool close_submitted = false;
+};
+
+struct ng_server {
+  ng_server_config cfg{};
+  int log2B = 24;
+  Arena arena;
+  std::vector<ng_session*> sessions;  // open sessions
+  std::vector<hipStream_t> streams;
+  std::vector<std::vector<Stage>> stages;
+  int device = 0;
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::thread thr;
+  bool stop = false;
+  bool new_arrivals = false;
+  uint64_t next_ticket = 1;
+  std::deque<Request*> arrivals;                  // global arrival order
+  std::unordered_map<uint64_t, Request*> tickets;  // not yet collected by ng_wait
+  std::vector<Request*> inflight;
+  ng_server_stats stats{};
+
+  void run();
+  void finish(Request* r, int32_t status, const std::string& msg = "");
+  int stage_upload(int k, const std::vector<ng::GenDesc>& descs, ng::GenDesc** d_out, uint64_t* bytes);
+};
+
+void ng_server::finish(Request* r, int32_t status, const std::string& msg) {
+  r->status = status;
+  r->msg = msg;
+  r->done = true;
+  r->done_ns = now_ns(t0);
+  cv_done.notify_all();
+}
+
+// Copy descriptors to the device through a pinned stage of stream k.
+int ng_server::stage_upload(int k, const std::vector<ng::GenDesc>& descs, ng::GenDesc** d_out,
+                            uint64_t* bytes) {
+  const uint64_t nb = descs.size() * sizeof(ng::GenDesc);
+  char* d = arena.alloc(nb);
+  if (!d) return NG_ERR_OOM;
+  Stage* st = nullptr;
+  for (auto& s : stages[k])
+    if (s.cap >= nb && (!s.busy || hipEventQuery(s.busy->ev) == hipSuccess)) {
+      st = &s;
+      break;
+    }
+  if (!st) {
+    Stage s;
+    s.cap = std::max<uint64_t>(nb, 1 << 16);
+    if (hipHostMalloc((void**)&s.p, s.cap, hipHostMallocDefault) != hipSuccess) {
+      arena.release(d, nb);
+      return NG_ERR_DEVICE;
+    }
+    stages[k].push_back(s);
+    st = &stages[k].back();
+  }
+  memcpy(st->p, descs.data(), nb);
+  if (hipMemcpyAsync(d, st->p, nb, hipMemcpyHostToDevice, streams[k]) != hipSuccess) {
+    arena.release(d, nb);
+    return NG_ERR_DEVICE;
+  }
+  auto box = std::make_shared<EventBox>();
+  if (hipEventCreateWithFlags(&box->ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventRecord(box->ev, streams[k]) != hipSuccess)
+    return NG_ERR_DEVICE;
+  st->busy = box;
+  *d_out = (ng::GenDesc*)d;
+  *bytes = nb;
+  return NG_OK;
+}
+
+void ng_server::run() {
+  (void)hipSetDevice(device);
+  const int ns = (int)streams.size();
+  std::unique_lock<std::mutex> lk(mu);
+  bool progress = true;
+  for (;;) {
+    // Sleep until something can change: new requests, or (polling every 20 us)
+    // device work or memory releases still pending.
+    const bool pending = !inflight.empty() || arena.deferred_bytes() != 0;
+    if (!pending && !progress)
+      cv_work.wait(lk, [&] { return stop || new_arrivals; });
+    else if (pending)
+      cv_work.wait_for(lk, std::chrono::microseconds(20), [&] { return stop || new_arrivals; });
+    new_arrivals = false;
+    if (stop && arrivals.empty() && inflight.empty()) break;
+    const size_t inflight_before = inflight.size();
+
+    // completions
+    for (size_t i = 0; i < inflight.size();) {
+      Request* r = inflight[i];
+      if (hipEventQuery(r->done_ev->ev) == hipSuccess) {
+        finish(r, NG_OK);
+        inflight[i] = inflight.back();
+        inflight.pop_back();
+      } else {
+        ++i;
+      }
+    }
+
+    // admission, in arrival order; a session whose head request must wait
+    // blocks its later requests (per-session order is kept)
+    std::vector<std::vector<ng::GenDesc>> descs(ns);
+    std::vector<std::vector<Request*>> packed(ns);
+    std::vector<ng_session*> blocked;
+    auto is_blocked = [&](ng_session* s) {
+      return std::find(blocked.begin(), blocked.end(), s) != blocked.end();
+    };
+    auto flush = [&](int k) {
+      if (descs[k].empty()) return;
+      uint64_t groups = 0;
+      for (auto& d : descs[k]) {
+        d.group0 = groups;
+        groups += ((uint64_t)d.n_new + 3) / 4;
+      }
+      ng::GenDesc* d_descs = nullptr;
+      uint64_t nb = 0;
+      int rc = check_descs(descs[k]);
+      if (rc == NG_OK) rc = stage_upload(k, descs[k], &d_descs, &nb);
+      hipError_t e = hipSuccess;
+      std::shared_ptr<EventBox> box;
+      if (rc == NG_OK) {
+        e = ng::launch_generate_batch(d_descs, (uint32_t)descs[k].size(), groups, log2B, streams[k]);
+        box = std::make_shared<EventBox>();
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&box->ev, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(box->ev, streams[k]);
+        hipEvent_t fe = nullptr;  // descriptors return to the arena after the launch
+        if (hipEventCreateWithFlags(&fe, hipEventDisableTiming) == hipSuccess &&
+            hipEventRecord(fe, streams[k]) == hipSuccess)
+          arena.release_after((char*)d_descs, nb, fe);
+        stats.launches++;
+        stats.packed_calls += descs[k].size();
+        if (descs[k].size() > stats.max_calls_per_launch) stats.max_calls_per_launch = descs[k].size();
+      }
+      for (Request* r : packed[k]) {
+        if (rc != NG_OK || e != hipSuccess) {
+          finish(r, NG_ERR_DEVICE, "packed generation launch failed");
+        } else {
+          r->done_ev = box;
+          inflight.push_back(r);
+        }
+      }
+      descs[k].clear();
+      packed[k].clear();
+    };
+    // A request that does not fit waits for memory to come back (another
+    // session's release or close).  It fails at once if it would not fit even
+    // with every other session gone, and otherwise when nothing can bring
+    // memory back: the device is idle, no freed memory is pending, no other
+    // request was admitted this round and no other session holds arena memory.
+    const bool idle_device = inflight.empty();
+    bool admitted_any = false;
+    auto hopeless = [&](ng_session* me) {
+      if (me->ctx->need > arena.size() - std::min(arena.size(), me->ctx->held)) return true;
+      if (!idle_device || admitted_any || arena.deferred_bytes() != 0) return false;
+      for (ng_session* o : sessions)
+        if (o != me && o->ctx && o->ctx->held != 0) return false;
+      return true;
+    };
+    for (auto it = arrivals.begin(); it != arrivals.end();) {
+      Request* r = *it;
+      ng_session* s = r->sess;
+      if (is_blocked(s) || s->queue.empty() || s->queue.front() != r) {
+        ++it;
+        continue;
+      }
+      ng_ctx* c = s->ctx;
+      const int k = s->stream;
+      bool admitted = true;
+      switch (r->kind) {
+        case REQ_CREATE_NODES: {
+          ng_range out;
+          const int rc = ng_create_nodes(c, r->n_nodes, &out);
+          r->admit_ns = now_ns(t0);
+          finish(r, rc, rc ? ng_last_error() : "");
+          break;
+        }
+        case REQ_CONNECT: {
+          ng::GenDesc d;
+          uint64_t n = 0;
+          const int rc = connect_prepare(c, r->src, r->tgt, &r->conn, &r->syn, &d, &n);
+          if (rc == NG_ERR_OOM && !hopeless(s)) {
+            admitted = false;  // wait for memory to come back
+            break;
+          }
+          r->admit_ns = now_ns(t0);
+          if (rc != NG_OK) {
+            finish(r, rc, ng_last_error());
+            break;
+          }
+          connect_commit(c, d, d.max_delay);
+          r->n_conns = n;
+          if (n == 0) {
+            finish(r, NG_OK);
+          } else {
+            descs[k].push_back(d);
+            packed[k].push_back(r);
+          }
+          break;
+        }
+        case REQ_CALIBRATE: {
+          flush(k);  // the session's pending connects run first on its stream
+          const int rc = ng_calibrate(c);
+          if (rc == NG_ERR_OOM && !hopeless(s)) {
+            admitted = false;
+            break;
+          }
+          r->admit_ns = now_ns(t0);
+          if (rc != NG_OK) {
+            finish(r, rc, ng_last_error());
+            break;
+          }
+          r->n_conns = c->n_conns;
+          auto box = std::make_shared<EventBox>();
+          if (hipEventCreateWithFlags(&box->ev, hipEventDisableTiming) != hipSuccess ||
+              hipEventRecord(box->ev, streams[k]) != hipSuccess) {
+            finish(r, NG_ERR_DEVICE, "event");
+            break;
+          }
+          r->done_ev = box;
+          inflight.push_back(r);
+          stats.calibrations++;
+          break;
+        }
+        case REQ_CLOSE: {
+          flush(k);
+          r->admit_ns = now_ns(t0);
+          ctx_destroy_release(c);  // frees wait for the stream's pending work
+          s->ctx = nullptr;
+          finish(r, NG_OK);
+          break;
+        }
+      }
+      if (!admitted) {
+        blocked.push_back(s);
+        ++it;
+        continue;
+      }
+      admitted_any = true;
+      s->queue.pop_front();
+      it = arrivals.erase(it);
+      if (r->kind == REQ_CLOSE) {
+        sessions.erase(std::find(sessions.begin(), sessions.end(), s));
+        delete s;
+      }
+    }
+    for (int k = 0; k < ns; ++k) flush(k);
+    progress = admitted_any || inflight.size() != inflight_before;
+    if (stop && !progress && inflight.empty() && arena.deferred_bytes() == 0) {
+      // shutting down with requests that can never be admitted
+      for (Request* r : arrivals) {
+        r->admit_ns = now_ns(t0);
+        finish(r, NG_ERR_STATE, "server shut down before the request could run");
+        if (r->sess) r->sess->queue.clear();
+      }
+      arrivals.clear();
+      break;
+    }
+    const uint64_t used = arena.used();
+    if (used > stats.peak_arena_bytes) stats.peak_arena_bytes = used;
+  }
+}
+
+extern "C" {
+
+int ng_server_create(const ng_server_config* cfg, void* arena, uint64_t arena_bytes, void* const* streams,
+                     int n_streams, ng_server** out) {
+  if (!cfg || !out || !arena || n_streams < 1 || n_streams > 64 || !streams)
+    return fail(NG_ERR_INVALID_ARG, "bad server arguments");
+  if ((uintptr_t)arena % kAlign) return fail(NG_ERR_INVALID_ARG, "arena must be 256-byte aligned");
+  for (int i = 0; i < n_streams; ++i)
+    if (!streams[i]) return fail(NG_ERR_INVALID_ARG, "server streams must not be the null stream");
+  ng_server* s = new ng_server();
+  s->cfg = *cfg;
+  s->arena.init((char*)arena, arena_bytes);
+  for (int i = 0; i < n_streams; ++i) s->streams.push_back((hipStream_t)streams[i]);
+  s->stages.resize(n_streams);
+  const uint64_t B = cfg->block_size ? cfg->block_size : (1ull << 24);
+  if (B & (B - 1) || B < (1ull << 16) || B > (1ull << 30)) {
+    delete s;
+    return fail(NG_ERR_INVALID_ARG, "block_size must be a power of two in [2^16, 2^30]");
+  }
+  s->log2B = bitwidth(B) - 1;
+  if (hipGetDevice(&s->device) != hipSuccess) {
+    delete s;
+    return fail(NG_ERR_DEVICE, "no HIP device");
+  }
+  s->thr = std::thread([s] { s->run(); });
+  *out = s;
+  return NG_OK;
+}
+
+int ng_server_destroy(ng_server* s) {
+  if (!s) return NG_OK;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv_work.notify_all();
+  s->thr.join();
+  (void)hipSetDevice(s->device);
+  for (hipStream_t st : s->streams) (void)hipStreamSynchronize(st);
+  for (ng_session* ss : s->sessions) {  // sessions never closed
+    ctx_destroy_release(ss->ctx);
+    delete ss;
+  }
+  for (auto& kv : s->tickets) delete kv.second;
+  for (auto& v : s->stages)
+    for (auto& st : v) (void)hipHostFree(st.p);
+  delete s;
+  return NG_OK;
+}
+
+int ng_session_open(ng_server* s, uint64_t seed, ng_session** out) {
+  if (!s || !out) return fail(NG_ERR_INVALID_ARG, "null argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  ng_config cfg{};
+  cfg.block_size = s->cfg.block_size;
+  cfg.seed = seed;
+  cfg.h_ms = s->cfg.h_ms;
+  const int k = (int)(s->stats.sessions_opened % s->streams.size());
+  ng_ctx* c = nullptr;
+  if (int rc = ctx_create_shared(&cfg, &s->arena, s->streams[k], &c)) return rc;
+  if (s->cfg.radix_bits)
+    (void)ng_set_tuning(c, s->cfg.radix_bits, s->cfg.sort_ranges ? s->cfg.sort_ranges : 1024);
+  ng_session* ss = new ng_session();
+  ss->server = s;
+  ss->ctx = c;
+  ss->stream = k;
+  s->sessions.push_back(ss);
+  s->stats.sessions_opened++;
+  *out = ss;
+  return NG_OK;
+}
+
+static int submit(ng_session* ss, Request* r, uint64_t* ticket) {
+  ng_server* s = ss->server;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (ss->close_submitted) {
+      delete r;
+      return fail(NG_ERR_STATE, "session is closing");
+    }
+    r->ticket = s->next_ticket++;
+    r->sess = ss;
+    r->arrival_ns = now_ns(s->t0);
+    if (r->kind == REQ_CLOSE) ss->close_submitted = true;
+    s->arrivals.push_back(r);
+    s->new_arrivals = true;
+    ss->queue.push_back(r);
+    s->tickets[r->ticket] = r;
+    s->stats.submitted++;
+    if (ticket) *ticket = r->ticket;
+  }
+  s->cv_work.notify_one();
+  return NG_OK;
+}
+
+int ng_submit_create_nodes(ng_session* ss, uint32_t n, ng_range* out, uint64_t* ticket) {
+  if (!ss) return fail(NG_ERR_INVALID_ARG, "null session");
+  Request* r = new Request();
+  r->kind = REQ_CREATE_NODES;
+  r->n_nodes = n;
+  {
+    std::lock_guard<std::mutex> lk(ss->server->mu);
+    if ((uint64_t)ss->client_nodes + n > 0xFFFFFFFFull) {
+      delete r;
+      return fail(NG_ERR_TOO_LARGE, "too many nodes");
+    }
+    if (out) *out = ng_range{ss->client_nodes, n};
+    ss->client_nodes += n;
+  }
+  return submit(ss, r, ticket);
+}
+
+int ng_submit_connect(ng_session* ss, ng_range src, ng_range tgt, const ng_conn_spec* conn,
+                      const ng_syn_spec* syn, uint64_t* ticket) {
+  if (!ss || !conn || !syn) return fail(NG_ERR_INVALID_ARG, "null argument");
+  Request* r = new Request();
+  r->kind = REQ_CONNECT;
+  r->src = src;
+  r->tgt = tgt;
+  r->conn = *conn;
+  r->syn = *syn;
+  return submit(ss, r, ticket);
+}
+
+int ng_submit_calibrate(ng_session* ss, uint64_t* ticket) {
+  if (!ss) return fail(NG_ERR_INVALID_ARG, "null session");
+  Request* r = new Request();
+  r->kind = REQ_CALIBRATE;
+  return submit(ss, r, ticket);
+}
+
+int ng_submit_close(ng_session* ss, uint64_t* ticket) {
+  if (!ss) return fail(NG_ERR_INVALID_ARG, "null session");
+  Request* r = new Request();
+  r->kind = REQ_CLOSE;
+  return submit(ss, r, ticket);
+}
+
+int ng_wait(ng_server* s, uint64_t ticket, int64_t timeout_ns, ng_ticket_info* out) {
+  if (!s) return fail(NG_ERR_INVALID_ARG, "null server");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->tickets.find(ticket);
+  if (it == s->tickets.end()) return fail(NG_ERR_INVALID_ARG, "unknown ticket %llu", (unsigned long long)ticket);
+  Request* r = it->second;
+  auto pred = [&] { return r->done; };
+  if (timeout_ns < 0) {
+    s->cv_done.wait(lk, pred);
+  } else if (!s->cv_done.wait_for(lk, std::chrono::nanoseconds(timeout_ns), pred)) {
+    return fail(NG_ERR_STATE, "ticket %llu not finished yet", (unsigned long long)ticket);
+  }
+  if (out) {
+    memset(out, 0, sizeof *out);
+    out->status = r->status;
+    out->kind = r->kind;
+    out->n_conns = r->n_conns;
+    out->arrival_ns = r->arrival_ns;
+    out->admit_ns = r->admit_ns;
+    out->done_ns = r->done_ns;
+  }
+  if (r->status != NG_OK) fail(r->status, "%s", r->msg.c_str());
+  s->tickets.erase(it);
+  delete r;
+  return NG_OK;
+}
+
+int ng_session_context(ng_session* ss, ng_ctx** out) {
+  if (!ss || !out) return fail(NG_ERR_INVALID_ARG, "null argument");
+  std::lock_guard<std::mutex> lk(ss->server->mu);
+  if (!ss->queue.empty()) return fail(NG_ERR_STATE, "the session has requests not yet admitted");
+  *out = ss->ctx;
+  return NG_OK;
+}
+
+int ng_server_get_stats(ng_server* s, ng_server_stats* out) {
+  if (!s || !out) return fail(NG_ERR_INVALID_ARG, "null argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  *out = s->stats;
+  out->arena_used_bytes = s->arena.used();
+  return NG_OK;
+}
+
+}  // extern "C"

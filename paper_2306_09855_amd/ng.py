@@ -76,15 +76,31 @@ class ng_kernel_time(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double)]
 
 
+class ng_server_config(ctypes.Structure):
+    _fields_ = [("block_size", ctypes.c_uint64), ("h_ms", ctypes.c_float), ("radix_bits", ctypes.c_int32),
+                ("sort_ranges", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class ng_ticket_info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("kind", ctypes.c_int32), ("n_conns", ctypes.c_uint64),
+                ("arrival_ns", ctypes.c_int64), ("admit_ns", ctypes.c_int64), ("done_ns", ctypes.c_int64)]
+
+
+class ng_server_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in ("submitted", "launches", "packed_calls", "max_calls_per_launch",
+                                                "calibrations", "sessions_opened", "peak_arena_bytes",
+                                                "arena_used_bytes")]
+
+
 _lib = None
 
 
 def lib():
-    """Load libng.so (built by __graft_entry__.build()); raise if it is missing."""
+    """Load libng.so (built by paper_2306_09855_amd/build.py); raise if it is missing."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+            raise RuntimeError(f"{LIB_PATH} is not built; run python paper_2306_09855_amd/build.py first")
         L = ctypes.CDLL(LIB_PATH)
         P, vp = ctypes.POINTER, ctypes.c_void_p
         u32, u64, i32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32
@@ -111,6 +127,17 @@ def lib():
             "ng_graph_end": ([vp, P(vp)], ctypes.c_int),
             "ng_graph_launch": ([vp, u64], ctypes.c_int),
             "ng_graph_destroy": ([vp], ctypes.c_int),
+            "ng_server_create": ([P(ng_server_config), vp, u64, P(vp), ctypes.c_int, P(vp)], ctypes.c_int),
+            "ng_server_destroy": ([vp], ctypes.c_int),
+            "ng_session_open": ([vp, u64, P(vp)], ctypes.c_int),
+            "ng_submit_create_nodes": ([vp, u32, P(ng_range), P(u64)], ctypes.c_int),
+            "ng_submit_connect": ([vp, ng_range, ng_range, P(ng_conn_spec), P(ng_syn_spec), P(u64)],
+                                  ctypes.c_int),
+            "ng_submit_calibrate": ([vp, P(u64)], ctypes.c_int),
+            "ng_submit_close": ([vp, P(u64)], ctypes.c_int),
+            "ng_wait": ([vp, u64, ctypes.c_int64, P(ng_ticket_info)], ctypes.c_int),
+            "ng_session_context": ([vp, P(vp)], ctypes.c_int),
+            "ng_server_get_stats": ([vp, P(ng_server_stats)], ctypes.c_int),
             "ng_last_error": ([], ctypes.c_char_p),
             "ng_blocks_needed": ([u64, u64, u64, u64], u64),
             "ng_plan_count": ([u32, ng_range, ng_range, P(ng_conn_spec), P(ng_syn_spec), ctypes.c_float,
@@ -287,6 +314,67 @@ def ng_memory_stats(ctx):
     u, p, f = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
     _check(lib().ng_memory_stats(ctx, ctypes.byref(u), ctypes.byref(p), ctypes.byref(f)))
     return int(u.value), int(p.value), int(f.value)
+
+
+# --- serving form -------------------------------------------------------------------
+def ng_server_create(cfg: ng_server_config, arena, arena_bytes: int, streams) -> ctypes.c_void_p:
+    arr = (ctypes.c_void_p * len(streams))(*[int(x) for x in streams])
+    h = ctypes.c_void_p()
+    _check(lib().ng_server_create(ctypes.byref(cfg), _vp(arena), arena_bytes, arr, len(streams),
+                                  ctypes.byref(h)))
+    return h
+
+
+def ng_server_destroy(server) -> None:
+    _check(lib().ng_server_destroy(server))
+
+
+def ng_session_open(server, seed: int) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(lib().ng_session_open(server, seed, ctypes.byref(h)))
+    return h
+
+
+def ng_submit_create_nodes(session, n: int):
+    r, t = ng_range(), ctypes.c_uint64()
+    _check(lib().ng_submit_create_nodes(session, n, ctypes.byref(r), ctypes.byref(t)))
+    return (r.first, r.n), int(t.value)
+
+
+def ng_submit_connect(session, src: ng_range, tgt: ng_range, conn: ng_conn_spec, syn: ng_syn_spec) -> int:
+    t = ctypes.c_uint64()
+    _check(lib().ng_submit_connect(session, src, tgt, ctypes.byref(conn), ctypes.byref(syn), ctypes.byref(t)))
+    return int(t.value)
+
+
+def ng_submit_calibrate(session) -> int:
+    t = ctypes.c_uint64()
+    _check(lib().ng_submit_calibrate(session, ctypes.byref(t)))
+    return int(t.value)
+
+
+def ng_submit_close(session) -> int:
+    t = ctypes.c_uint64()
+    _check(lib().ng_submit_close(session, ctypes.byref(t)))
+    return int(t.value)
+
+
+def ng_wait(server, ticket: int, timeout_ns: int = -1) -> ng_ticket_info:
+    info = ng_ticket_info()
+    _check(lib().ng_wait(server, ticket, timeout_ns, ctypes.byref(info)))
+    return info
+
+
+def ng_session_context(session) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(lib().ng_session_context(session, ctypes.byref(h)))
+    return h
+
+
+def ng_server_get_stats(server) -> dict:
+    st = ng_server_stats()
+    _check(lib().ng_server_get_stats(server, ctypes.byref(st)))
+    return {n: int(getattr(st, n)) for n, _ in ng_server_stats._fields_}
 
 
 # --- torch plumbing: device memory and streams ----------------------------------

@@ -188,3 +188,46 @@ def batch_mixed(seed: int = 12345, n_calls: int = 4096, n_nodes: int = 1_000_000
 def by_name(name: str, **kw) -> Workload:
     return {"two_pop_indegree": two_pop_indegree, "two_pop_mixed": two_pop_mixed,
             "microcircuit": microcircuit, "batch_mixed": batch_mixed}[name](**kw)
+
+
+@dataclass
+class Episode:
+    """One model-building session of the serving trace."""
+    slot: int
+    seed: int
+    n_nodes: int
+    calls: list
+    times: list          # arrival times (s) of: create_nodes, each connect, calibrate, close
+
+    @property
+    def n_syn(self) -> int:
+        return int(sum(c.n_syn() for c in self.calls))
+
+
+def serving_trace(n_slots: int = 32, episodes_per_slot: int = 3, rate: float = 2000.0,
+                  lo_exp: float = 3.0, hi_exp: float = 7.0, gen_seed: int = 5,
+                  burst: bool = False) -> list:
+    """Episodes of the serving workload.
+
+    Each of ``n_slots`` clients runs ``episodes_per_slot`` sessions back to back:
+    create floor(10^U(4,6)) nodes, M ~ U{4..32} Connect calls of log-uniform
+    size in [10^lo_exp, 10^hi_exp] with mixed rules inside the session's nodes
+    (as ``batch_mixed``), calibrate, close.  Requests of a client arrive as a
+    Poisson process of rate ``rate / n_slots``; with ``burst`` every request
+    arrives at time 0 (a backlog that measures capacity)."""
+    rng = np.random.default_rng(gen_seed)
+    out = []
+    for slot in range(n_slots):
+        t = 0.0
+        for e in range(episodes_per_slot):
+            n_nodes = int(10 ** rng.uniform(4.0, 6.0))
+            m = int(rng.integers(4, 33))
+            sub = batch_mixed(seed=0, n_calls=m, n_nodes=n_nodes, lo_exp=lo_exp, hi_exp=hi_exp,
+                              gen_seed=int(rng.integers(1 << 31)))
+            times = []
+            for _ in range(m + 3):
+                if not burst:
+                    t += rng.exponential(n_slots / rate)
+                times.append(t)
+            out.append(Episode(slot, int(rng.integers(1, 1 << 62)), n_nodes, sub.calls, times))
+    return out
