@@ -145,10 +145,13 @@ def serve_run(trace, n_streams, arena_bytes, block_size):
             syn += n
     stats = ng.ng_server_get_stats(srv)
     ng.ng_server_destroy(srv)
+    del arena
+    torch.cuda.empty_cache()
     span = (last - first) / 1e9
     return {"synapses": syn, "seconds": round(span, 4), "synapses_per_s": syn / span,
             "connect_p50_ms": _pct(lat, 50), "connect_p99_ms": _pct(lat, 99), "failed": bad,
             "launches": stats["launches"], "calls_per_launch": round(stats["packed_calls"] / max(stats["launches"], 1), 2),
+            "calibrate_packs": stats["calibrate_packs"], "max_sessions_per_pack": stats["max_sessions_per_pack"],
             "peak_arena_GiB": round(stats["peak_arena_bytes"] / 2**30, 2)}
 
 
@@ -191,38 +194,53 @@ def plain_run(trace, block_size):
         last = done
         if kind == "connect":
             lat.append((done - arrival) * 1e3)
+    for c in ctxs.values():
+        ng.ng_destroy(c)
+    ctxs.clear()
+    arenas.clear()
+    pool.clear()
+    torch.cuda.empty_cache()
     span = last - first
     return {"synapses": syn, "seconds": round(span, 4), "synapses_per_s": syn / span,
             "connect_p50_ms": _pct(lat, 50), "connect_p99_ms": _pct(lat, 99)}
 
 
-def serving_bench(episodes_per_slot=2, n_streams=4, block_size=1 << 20, load=0.5):
-    """Serving form against the plain sequential path on the same trace.
+def serving_bench(n_streams=4, block_size=1 << 20, loads=(0.5, 1.0, 2.0, 4.0), burst_episodes=2,
+                  sweep_episodes=15, arena_bytes=128 << 30):
+    """Serving form against the plain sequential path.
 
-    capacity: every request arrives at once (a backlog): synapses/s of both;
-    latency: Poisson arrivals at `load` x the plain path's request capacity:
-    p50/p99 of Connect latency (arrival to completion) for both."""
+    capacity: a backlog (every request of 32 clients x burst_episodes sessions
+    at time 0): synapses/s of both paths.
+    sweep: Poisson arrivals (32 clients x sweep_episodes sessions, about 10,000
+    requests) at each load x the plain path's request capacity: p50/p99
+    Connect latency (arrival to device completion) and synapses/s of both."""
     from paper_2306_09855_amd import workloads as W
-    burst = W.serving_trace(episodes_per_slot=episodes_per_slot, burst=True)
+    warm = W.serving_trace(n_slots=8, episodes_per_slot=1, burst=True, gen_seed=6)
+    plain_run(warm, block_size)
+    serve_run(warm, n_streams, arena_bytes, block_size)
+    burst = W.serving_trace(episodes_per_slot=burst_episodes, burst=True)
     n_req = sum(len(e.calls) + 3 for e in burst)
     total = sum(e.n_syn for e in burst)
-    arena = int(max(64 << 30, 3.2 * 14 * total))
-    log(f"serving: {len(burst)} sessions, {n_req} requests, {total:.3g} synapses")
+    log(f"serving: backlog of {len(burst)} sessions, {n_req} requests, {total:.3g} synapses")
     plain_cap = plain_run(burst, block_size)
-    log(f"serving: plain backlog {plain_cap['seconds']} s")
-    served_cap = serve_run(burst, n_streams, arena, block_size)
-    log(f"serving: served backlog {served_cap['seconds']} s")
-    rate = load * n_req / plain_cap["seconds"]
-    timed = W.serving_trace(episodes_per_slot=episodes_per_slot, rate=rate)
-    plain_lat = plain_run(timed, block_size)
-    served_lat = serve_run(timed, n_streams, arena, block_size)
-    log(f"serving: latency runs done (rate {rate:.0f} req/s)")
-    return {"sessions": len(burst), "slots": 32, "requests": n_req, "synapses": total,
-            "streams": n_streams, "block_size": block_size,
-            "backlog": {"served": served_cap, "plain": plain_cap,
+    served_cap = serve_run(burst, n_streams, arena_bytes, block_size)
+    log(f"serving: backlog plain {plain_cap['seconds']} s, served {served_cap['seconds']} s")
+    plain_rate = n_req / plain_cap["seconds"]
+    sweep = []
+    for load in loads:
+        timed = W.serving_trace(episodes_per_slot=sweep_episodes, rate=load * plain_rate)
+        n_t = sum(len(e.calls) + 3 for e in timed)
+        p = plain_run(timed, block_size)
+        sv = serve_run(timed, n_streams, arena_bytes, block_size)
+        sweep.append({"load_vs_plain_capacity": load, "rate_req_per_s": round(load * plain_rate, 1),
+                      "requests": n_t, "plain": p, "served": sv})
+        log(f"serving: load {load}: {n_t} requests, connect p50/p99 plain {p['connect_p50_ms']:.3g}/"
+            f"{p['connect_p99_ms']:.3g} ms, served {sv['connect_p50_ms']:.3g}/{sv['connect_p99_ms']:.3g} ms")
+    return {"clients": 32, "streams": n_streams, "block_size": block_size, "arena_GiB": arena_bytes / 2**30,
+            "backlog": {"sessions": len(burst), "requests": n_req, "synapses": total,
+                        "served": served_cap, "plain": plain_cap,
                         "speedup": round(served_cap["synapses_per_s"] / plain_cap["synapses_per_s"], 2)},
-            "poisson": {"rate_req_per_s": round(rate, 1), "load_vs_plain_capacity": load,
-                        "served": served_lat, "plain": plain_lat}}
+            "sweep": sweep}
 
 
 def main() -> int:
@@ -236,7 +254,7 @@ def main() -> int:
                     help="plain: one ng_connect per call; batched: one ng_connect_batch; "
                          "graph: the batched build captured once and replayed")
     ap.add_argument("--tune", action="store_true", help="pick the sort schedule with the autotuner first")
-    ap.add_argument("--radix-bits", type=int, default=8)
+    ap.add_argument("--radix-bits", type=int, default=9, help="widest digit (fewest passes)")
     ap.add_argument("--sort-ranges", type=int, default=1024, help="static ranges (workgroups) of each sort pass")
     ap.add_argument("--block-size", type=int, default=1 << 24)
     ap.add_argument("--cpu-sample", type=float, default=6e7, help="synapses of the oracle sample; 0 skips")
@@ -395,8 +413,10 @@ def main() -> int:
     if args.serve:
         sv = serving_bench()
         result["serving"] = sv
-        result["latency_p50_ms"] = sv["poisson"]["served"]["connect_p50_ms"]
-        result["latency_p99_ms"] = sv["poisson"]["served"]["connect_p99_ms"]
+        at1 = next(x for x in sv["sweep"] if x["load_vs_plain_capacity"] == 1.0)
+        result["latency_p50_ms"] = at1["served"]["connect_p50_ms"]
+        result["latency_p99_ms"] = at1["served"]["connect_p99_ms"]
+        result["latency_load"] = "Poisson arrivals at the plain path's capacity, served form"
     if args.cpu_sample > 0 and wl.name == "microcircuit":
         result["cpu_baseline"] = cpu_baseline(int(args.cpu_sample))
     print(json.dumps(result))

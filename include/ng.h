@@ -10,6 +10,7 @@
  *                     blocks of Eq. (1), connection numbering of Eqs. (2)-(3))
  *   ng_calibrate      ordering by (source, delay) and the connection-group
  *                     index of Eq. (14) (Sec. 2.2; stage "calibration")
+ *   ng_calibrate_many the same for several contexts in shared launches
  *   ng_get_connections / ng_copy_connections   read the result back
  *
  * Conventions
@@ -163,6 +164,20 @@ int ng_connect_batch(ng_ctx* ctx, uint32_t n_calls, const ng_range* src, const n
  * the same result as a single calibration at the end. */
 int ng_calibrate(ng_ctx* ctx);
 
+/* Calibrate n contexts together (Sec. 2.2 applied to each): every context is
+ * one segment of the same sort launches and of the same group-index
+ * launches, so many small networks cost the launches of one.  Each context's
+ * result is identical to ng_calibrate on it.  The work runs on ctxs[0]'s
+ * stream; every other context's stream is ordered before it and after it
+ * with events, so later work on any of the streams sees the result.
+ * Contexts already calibrated are skipped.  Requirements: distinct contexts
+ * on one device with one block size, none frozen by a live graph, none being
+ * captured (NG_ERR_INVALID_ARG / NG_ERR_STATE otherwise).  Scratch shared by
+ * the segments comes from ctxs[0]'s arena, the rest from each context's own.
+ * All-or-nothing on NG_ERR_OOM: no context changes except that a context's
+ * stale group index (it was uncalibrated) may have been released. */
+int ng_calibrate_many(ng_ctx* const* ctxs, uint32_t n);
+
 /* Wait for all enqueued work; reports kernel errors. */
 int ng_sync(ng_ctx* ctx);
 
@@ -179,8 +194,9 @@ int ng_copy_connections(ng_ctx* ctx, uint64_t first, uint64_t count, uint32_t* s
  * calibration.  Synchronizes.  NG_ERR_STATE if not calibrated. */
 int ng_copy_group_index(ng_ctx* ctx, uint32_t* group_ptr, uint32_t* group_start);
 
-/* Calibration schedule: the widest radix digit in bits (4..9; default 8) --
- * the key bits are split into the fewest passes of at most that width -- and
+/* Calibration schedule: the widest radix digit in bits (4..9; default 9) --
+ * the key bits are split into the fewest passes of at most that width, as
+ * evenly as possible (22-bit keys: 8+7+7; 26-bit keys: 9+9+8) -- and
  * the number of static ranges (one workgroup each) a sort pass splits the
  * connections into (1..2^20; default 1024).  Results do not depend on either;
  * speed does. */
@@ -229,10 +245,15 @@ int ng_graph_destroy(ng_graph* graph);
  * return a ticket.  A scheduler thread admits requests in arrival order (each
  * session's in the order submitted) while the arena has room -- a request
  * that does not fit waits until memory comes back (another calibration's
- * scratch, a closed session) and fails with NG_ERR_OOM only when nothing
- * could bring memory back.  Connect calls admitted together from the sessions
- * sharing a stream run as one generation launch; calibrations run on their
- * session's stream, overlapping with other streams.  The arithmetic is that
+ * scratch, another session's close) and fails with NG_ERR_OOM at once when
+ * it would not fit even with every other session gone, or later when nothing
+ * could bring memory back (the device is idle and no other session holds
+ * arena memory).  A request can therefore wait for as long as another
+ * session stays open; ng_wait's timeout bounds the client's wait.  Connect
+ * calls admitted together from the sessions sharing a stream run as one
+ * generation launch; calibrations admitted together run as one packed
+ * calibration (ng_calibrate_many) when their memory allows, else one by one
+ * on their session's stream.  The arithmetic is that
  * of a context of its own: a session's connections equal the same calls on
  * ng_connect with the same seed.  Sessions are spread over the streams
  * round-robin.  All streams must be non-null. */
@@ -254,6 +275,8 @@ typedef struct {
 typedef struct {
   uint64_t submitted, launches, packed_calls, max_calls_per_launch, calibrations;
   uint64_t sessions_opened, peak_arena_bytes, arena_used_bytes;
+  uint64_t calibrate_packs;        /* calibrations of several sessions run together */
+  uint64_t max_sessions_per_pack;
 } ng_server_stats;
 int ng_server_create(const ng_server_config* cfg, void* arena, uint64_t arena_bytes,
                      void* const* streams, int n_streams, ng_server** out);

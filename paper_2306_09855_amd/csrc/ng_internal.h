@@ -47,13 +47,7 @@ hipError_t launch_generate_batch(const GenDesc* d_descs, uint32_t n_calls, uint6
                                  int log2B, hipStream_t s);
 
 // --- calibration ----------------------------------------------------------
-struct SortGeom {
-  uint64_t n;               // records
-  uint32_t tiles_per_range; // consecutive tiles of one range
-  uint32_t n_ranges;
-  uint32_t ranges_per_xcd;  // launch = 8 * ranges_per_xcd workgroups
-};
-
+// Input and output of one digit pass of one segment.
 struct SortIO {
   // blocked SoA input (first pass) or key/payload arrays
   char* const* in_blocks;   // device block table, or nullptr
@@ -67,16 +61,43 @@ struct SortIO {
   uint32_t dbits;           // key = src << dbits | delay
 };
 
-// Records per sort tile; the block size must be a multiple of it.
+// One segment of a digit pass.  A segment is one context's independent sort;
+// several segments run in one launch.  Ranges (runs of consecutive tiles, one
+// workgroup each) are numbered across segments from range0, and the digit
+// counts of the segments lie one after another in one array
+// (counts[cbase + d * n_ranges + r]), so that one exclusive scan serves all:
+// a segment's scanned offsets then start at base = the records of the
+// segments before it (mod 2^32), which the downsweep subtracts.
+struct SortSeg {
+  SortIO io;
+  uint64_t n;               // records
+  uint64_t cbase;
+  uint32_t shift, nbits;    // digit of this pass
+  uint32_t tiles_per_range, n_ranges, range0;
+  uint32_t base;
+};
+
+// A digit pass over n_segs segments that agree on in/out kind (first pass
+// reads blocks, last pass writes blocks).  With one segment it travels by
+// value in `one` and no device table is read.
+struct SortPack {
+  const SortSeg* segs;            // device [n_segs] (n_segs > 1)
+  const uint32_t* seg_of_range;   // device [total_ranges] (n_segs > 1)
+  uint32_t n_segs;
+  uint32_t total_ranges;
+  uint32_t ranges_per_xcd;        // launch = 8 * ranges_per_xcd workgroups
+  uint32_t max_nbits;
+  SortSeg one;
+};
+
+// Records per sort tile (a tile may straddle two blocks).
 uint32_t sort_tile_size();
 int sort_max_radix_bits();
 
-// Digit counts of each range: counts[d * n_ranges + r] for d < 2^nbits.
-hipError_t launch_upsweep(const SortGeom& g, const SortIO& io, uint32_t shift, uint32_t nbits,
-                          uint32_t* counts, hipStream_t s);
+// Digit counts of every range of every segment.
+hipError_t launch_upsweep(const SortPack& pk, uint32_t* counts, hipStream_t s);
 // One stable digit pass; offsets = exclusive scan of the counts.
-hipError_t launch_downsweep(const SortGeom& g, const SortIO& io, uint32_t shift, uint32_t nbits,
-                            const uint32_t* offsets, hipStream_t s);
+hipError_t launch_downsweep(const SortPack& pk, const uint32_t* offsets, hipStream_t s);
 
 // Exclusive scan of n u32 values (in may equal out).  tmp needs
 // scan_tmp_words(n) words.  If total != nullptr the sum is written there.
@@ -90,20 +111,45 @@ hipError_t launch_set_ptrs(char** tab, uint32_t first, uint32_t count, const uin
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, uint64_t n, hipStream_t s);
 
-// Connection-group index over sorted blocked SoA (Sec. 2.2, Eq. (14)):
-//   flags      bitmap[ceil(n/32)] of group starts and, per tile of
-//              gi_tile_size() positions, the number of groups starting in it
-//   write      with tile_base = exclusive scan of the tile counts:
-//              group_start[g] and group_src[g] for every group, and
-//              group_start[G] = n
-//   ptr        group_ptr[i], i = 0..n_nodes, from group_src by binary search
+// Connection-group index over sorted blocked SoA (Sec. 2.2, Eq. (14)), for
+// one or several segments:
+//   flags      per segment a bitmap[ceil(n/32)] of group starts; per tile of
+//              gi_tile_size() positions (tiles numbered across segments from
+//              tile0) the number of groups starting in it -> tile_flags
+//   write      with tile_base = exclusive scan of tile_flags over all tiles
+//              (tile_base[total_tiles] = the grand total): group_start[g] and
+//              group_src[g] of every group of every segment
+//   ptr        per segment: G = its tile_base span, *n_groups = G,
+//              group_start[G] = n, group_ptr[i] for i = 0..n_nodes by binary
+//              search in group_src
+struct GiSeg {
+  char* const* blocks;      // sorted blocked SoA
+  uint64_t n;
+  uint32_t* bitmap;         // ceil(n/32) + 1 words
+  uint32_t* group_start;    // capacity G + 1
+  uint32_t* group_src;      // capacity G
+  uint32_t* group_ptr;      // n_nodes + 1
+  uint32_t* n_groups;       // out: G
+  uint32_t tile0, n_tiles;  // gi tiles
+  uint32_t n_nodes;
+  uint32_t ptr_block0, n_ptr_blocks;  // workgroups of the ptr step
+  uint32_t pad;
+};
+
+struct GiPack {
+  const GiSeg* segs;               // device [n_segs] (n_segs > 1)
+  const uint32_t* seg_of_tile;     // device [total_tiles] (n_segs > 1)
+  const uint32_t* seg_of_ptr_block;// device [total_ptr_blocks] (n_segs > 1)
+  uint32_t n_segs, total_tiles, total_ptr_blocks;
+  int log2B;
+  GiSeg one;
+};
+
 uint32_t gi_tile_size();
-hipError_t launch_group_flags(char* const* blocks, int log2B, uint64_t n, uint32_t* bitmap,
-                              uint32_t* tile_flags, hipStream_t s);
-hipError_t launch_group_write(char* const* blocks, int log2B, uint64_t n, const uint32_t* bitmap,
-                              const uint32_t* tile_base, uint32_t* group_start, uint32_t* group_src,
-                              hipStream_t s);
-hipError_t launch_group_ptr(const uint32_t* group_src, const uint32_t* n_groups, uint32_t n_nodes,
-                            uint32_t* group_ptr, hipStream_t s);
+// workgroups of the ptr step for a segment of n_nodes nodes
+uint32_t gi_ptr_blocks(uint32_t n_nodes);
+hipError_t launch_group_flags(const GiPack& pk, uint32_t* tile_flags, hipStream_t s);
+hipError_t launch_group_write(const GiPack& pk, const uint32_t* tile_base, hipStream_t s);
+hipError_t launch_group_ptr(const GiPack& pk, const uint32_t* tile_base, hipStream_t s);
 
 }  // namespace ng

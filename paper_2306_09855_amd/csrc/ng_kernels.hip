@@ -308,10 +308,16 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-__device__ __forceinline__ int range_index(const SortGeom& g) {
+__device__ __forceinline__ int range_index(const SortPack& pk) {
   const uint32_t w = blockIdx.x;
-  const uint32_t r = (w & 7u) * g.ranges_per_xcd + (w >> 3);
-  return r < g.n_ranges ? (int)r : -1;
+  const uint32_t r = (w & 7u) * pk.ranges_per_xcd + (w >> 3);
+  return r < pk.total_ranges ? (int)r : -1;
+}
+
+// The segment a global range belongs to (uniform across the workgroup).
+__device__ __forceinline__ SortSeg sort_seg(const SortPack& pk, uint32_t gr) {
+  if (pk.n_segs == 1) return pk.one;
+  return pk.segs[pk.seg_of_range[gr]];
 }
 
 // Blocked SoA source of one tile: a tile spans at most two blocks.
@@ -320,11 +326,11 @@ struct TileSrc {
   uint64_t first_block;
 };
 
-__device__ __forceinline__ TileSrc tile_src(const SortIO& io, uint64_t base) {
+__device__ __forceinline__ TileSrc tile_src(const SortIO& io, uint64_t base, uint32_t cnt) {
   TileSrc t;
   t.first_block = base >> io.log2B;
   t.blk[0] = io.in_blocks[t.first_block];
-  const uint64_t last = (base + kTile - 1) >> io.log2B;
+  const uint64_t last = (base + cnt - 1) >> io.log2B;  // cnt >= 1
   t.blk[1] = last != t.first_block ? io.in_blocks[t.first_block + 1] : t.blk[0];
   return t;
 }
@@ -349,22 +355,24 @@ __device__ __forceinline__ uint32_t load_blocked_key(const SortIO& io, const Til
 }
 
 template <int RB, bool IN_BLOCKED>
-__global__ __launch_bounds__(kSortThreads) void k_upsweep(SortGeom g, SortIO io, uint32_t shift,
-                                                          uint32_t nbits, uint32_t* __restrict__ counts) {
+__global__ __launch_bounds__(kSortThreads) void k_upsweep(SortPack pk, uint32_t* __restrict__ counts) {
   constexpr int NB = 1 << RB;
   __shared__ uint32_t hist[NB];
-  const int r = range_index(g);
-  if (r < 0) return;
-  const uint32_t nd = 1u << nbits, mask = nd - 1;
+  const int gr = range_index(pk);
+  if (gr < 0) return;
+  const SortSeg sg = sort_seg(pk, (uint32_t)gr);
+  const SortIO& io = sg.io;
+  const uint32_t r = (uint32_t)gr - sg.range0, shift = sg.shift;
+  const uint32_t nd = 1u << sg.nbits, mask = nd - 1;
   for (uint32_t d = threadIdx.x; d < nd; d += kSortThreads) hist[d] = 0;
   __syncthreads();
-  const uint64_t start = (uint64_t)r * g.tiles_per_range * kTile;
-  const uint64_t end = min(start + (uint64_t)g.tiles_per_range * kTile, g.n);
+  const uint64_t start = (uint64_t)r * sg.tiles_per_range * kTile;
+  const uint64_t end = min(start + (uint64_t)sg.tiles_per_range * kTile, sg.n);
   for (uint64_t base = start; base < end; base += kTile) {
     const uint32_t cnt = (uint32_t)min((uint64_t)kTile, end - base);
     uint32_t key[kItems];
     if constexpr (IN_BLOCKED) {
-      const TileSrc ts = tile_src(io, base);
+      const TileSrc ts = tile_src(io, base, cnt);
 #pragma unroll
       for (int k = 0; k < kItems; ++k) {
         const uint32_t lj = k * kSortThreads + threadIdx.x;
@@ -382,7 +390,7 @@ __global__ __launch_bounds__(kSortThreads) void k_upsweep(SortGeom g, SortIO io,
       if ((uint32_t)(k * kSortThreads + threadIdx.x) < cnt) atomicAdd(&hist[(key[k] >> shift) & mask], 1u);
   }
   __syncthreads();
-  for (uint32_t d = threadIdx.x; d < nd; d += kSortThreads) counts[(uint64_t)d * g.n_ranges + r] = hist[d];
+  for (uint32_t d = threadIdx.x; d < nd; d += kSortThreads) counts[sg.cbase + (uint64_t)d * sg.n_ranges + r] = hist[d];
 }
 
 struct SortLds {
@@ -409,7 +417,7 @@ __device__ __forceinline__ void sort_tile(const SortIO& io, uint64_t base, uint3
   uint32_t key[kItems];
   uint2 pay[kItems];
   if constexpr (IN_BLOCKED) {
-    const TileSrc ts = tile_src(io, base);
+    const TileSrc ts = tile_src(io, base, cnt);
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
       const uint32_t lj = (uint32_t)(wave * kItems * 64 + k * 64 + lane);
@@ -543,8 +551,7 @@ __device__ __forceinline__ void sort_tile(const SortIO& io, uint64_t base, uint3
 }
 
 template <int RB, bool IN_BLOCKED, bool OUT_BLOCKED>
-__global__ __launch_bounds__(kSortThreads) void k_downsweep(SortGeom g, SortIO io, uint32_t shift,
-                                                            uint32_t nbits, const uint32_t* __restrict__ offsets) {
+__global__ __launch_bounds__(kSortThreads) void k_downsweep(SortPack pk, const uint32_t* __restrict__ offsets) {
   constexpr int NB = 1 << RB;
   __shared__ uint2 s_buf[kTile];
   __shared__ uint32_t s_wh[kSortWaves * NB];
@@ -552,21 +559,23 @@ __global__ __launch_bounds__(kSortThreads) void k_downsweep(SortGeom g, SortIO i
   __shared__ uint32_t s_run[NB];
   __shared__ uint32_t s_tmp[kSortWaves];
   const SortLds L{s_buf, reinterpret_cast<uint32_t*>(s_buf), s_wh, s_start, s_run, s_tmp};
-  const int r = range_index(g);
-  if (r < 0) return;
+  const int gr = range_index(pk);
+  if (gr < 0) return;
+  const SortSeg sg = sort_seg(pk, (uint32_t)gr);
+  const uint32_t r = (uint32_t)gr - sg.range0, shift = sg.shift, nbits = sg.nbits;
   const uint32_t nd = 1u << nbits;
   for (uint32_t d = threadIdx.x; d < nd; d += kSortThreads) {
-    s_run[d] = offsets[(uint64_t)d * g.n_ranges + r];
+    s_run[d] = offsets[sg.cbase + (uint64_t)d * sg.n_ranges + r] - sg.base;
 #pragma unroll
     for (int v = 0; v < kSortWaves; ++v) s_wh[v * NB + d] = 0;
   }
   lds_barrier();
-  const uint64_t start = (uint64_t)r * g.tiles_per_range * kTile;
-  const uint64_t end = min(start + (uint64_t)g.tiles_per_range * kTile, g.n);
+  const uint64_t start = (uint64_t)r * sg.tiles_per_range * kTile;
+  const uint64_t end = min(start + (uint64_t)sg.tiles_per_range * kTile, sg.n);
   for (uint64_t base = start; base < end; base += kTile) {
     const uint32_t cnt = (uint32_t)min((uint64_t)kTile, end - base);
-    if (cnt == kTile) sort_tile<RB, IN_BLOCKED, OUT_BLOCKED, true>(io, base, cnt, shift, nbits, L);
-    else sort_tile<RB, IN_BLOCKED, OUT_BLOCKED, false>(io, base, cnt, shift, nbits, L);
+    if (cnt == kTile) sort_tile<RB, IN_BLOCKED, OUT_BLOCKED, true>(sg.io, base, cnt, shift, nbits, L);
+    else sort_tile<RB, IN_BLOCKED, OUT_BLOCKED, false>(sg.io, base, cnt, shift, nbits, L);
   }
 }
 
@@ -661,11 +670,19 @@ __device__ __forceinline__ uint64_t group_key(char* const* __restrict__ blocks, 
          (uint16_t) reinterpret_cast<const int16_t*>(blk + 12 * B)[o];
 }
 
-__global__ __launch_bounds__(kThreads) void k_group_flags(char* const* __restrict__ blocks, int log2B,
-                                                          uint64_t n, uint32_t* __restrict__ bitmap,
-                                                          uint32_t* __restrict__ tile_flags) {
+__device__ __forceinline__ GiSeg gi_seg(const GiPack& pk, const uint32_t* table, uint32_t i) {
+  if (pk.n_segs == 1) return pk.one;
+  return pk.segs[table[i]];
+}
+
+__global__ __launch_bounds__(kThreads) void k_group_flags(GiPack pk, uint32_t* __restrict__ tile_flags) {
   __shared__ uint32_t s_tmp[kWaves];
-  const uint64_t base = (uint64_t)blockIdx.x * kGiTile;
+  const GiSeg sg = gi_seg(pk, pk.seg_of_tile, blockIdx.x);
+  const int log2B = pk.log2B;
+  const uint64_t n = sg.n;
+  char* const* blocks = sg.blocks;
+  uint32_t* bitmap = sg.bitmap;
+  const uint64_t base = (uint64_t)(blockIdx.x - sg.tile0) * kGiTile;
   const uint64_t B = 1ull << log2B;
   const char* blk = blocks[base >> log2B];  // kGiTile divides the block size
   const uint64_t o0 = base & (B - 1);
@@ -699,70 +716,71 @@ __global__ __launch_bounds__(kThreads) void k_group_flags(char* const* __restric
 }
 
 // group_start[g]: first connection of group g; group_src[g]: its source.
-__global__ __launch_bounds__(kThreads) void k_group_write(char* const* __restrict__ blocks, int log2B,
-                                                          uint64_t n, const uint32_t* __restrict__ bitmap,
-                                                          const uint32_t* __restrict__ tile_base,
-                                                          uint32_t* __restrict__ group_start,
-                                                          uint32_t* __restrict__ group_src) {
+__global__ __launch_bounds__(kThreads) void k_group_write(GiPack pk, const uint32_t* __restrict__ tile_base) {
   __shared__ uint32_t s_tmp[kWaves];
-  const uint64_t wbase = (uint64_t)blockIdx.x * kThreads + threadIdx.x;  // bitmap word of this thread
+  const GiSeg sg = gi_seg(pk, pk.seg_of_tile, blockIdx.x);
+  const uint64_t n = sg.n;
+  const uint64_t wbase = (uint64_t)(blockIdx.x - sg.tile0) * kThreads + threadIdx.x;  // bitmap word
   const uint64_t j0 = wbase << 5;
-  uint32_t bits = j0 < n ? bitmap[wbase] : 0u;
+  uint32_t bits = j0 < n ? sg.bitmap[wbase] : 0u;
   if (j0 < n && n - j0 < 32) bits &= (1u << (n - j0)) - 1;
   uint32_t total;
-  uint32_t g = tile_base[blockIdx.x] + block_exclusive_scan((uint32_t)__popc(bits), s_tmp, &total);
+  uint32_t g = tile_base[blockIdx.x] - tile_base[sg.tile0] +
+               block_exclusive_scan((uint32_t)__popc(bits), s_tmp, &total);
   while (bits) {
     const int b = __ffs(bits) - 1;
     bits &= bits - 1;
     const uint64_t j = j0 + b;
-    group_start[g] = (uint32_t)j;
-    group_src[g] = (uint32_t)(group_key(blocks, log2B, j) >> 16);
+    sg.group_start[g] = (uint32_t)j;
+    sg.group_src[g] = (uint32_t)(group_key(sg.blocks, pk.log2B, j) >> 16);
     ++g;
   }
-  if (j0 < n && n - j0 <= 32) group_start[g] = (uint32_t)n;  // the last word closes: group_start[G] = n
 }
 
 // Eq. (14): p_i = sum_{j<i} G_j = the number of groups whose source is below
 // i, found by binary search in the sorted group sources (i = 0..n_nodes).
-__global__ __launch_bounds__(kThreads) void k_group_ptr(const uint32_t* __restrict__ group_src,
-                                                        const uint32_t* __restrict__ n_groups, uint32_t n_nodes,
-                                                        uint32_t* __restrict__ group_ptr) {
-  const uint32_t G = *n_groups;
-  for (uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x; i <= n_nodes;
-       i += (uint64_t)gridDim.x * kThreads) {
+__global__ __launch_bounds__(kThreads) void k_group_ptr(GiPack pk, const uint32_t* __restrict__ tile_base) {
+  const GiSeg sg = gi_seg(pk, pk.seg_of_ptr_block, blockIdx.x);
+  const uint32_t lb = blockIdx.x - sg.ptr_block0;
+  const uint32_t G = tile_base[sg.tile0 + sg.n_tiles] - tile_base[sg.tile0];
+  if (lb == 0 && threadIdx.x == 0) {
+    *sg.n_groups = G;
+    sg.group_start[G] = (uint32_t)sg.n;  // group_start[G] = n closes the last group
+  }
+  const uint32_t* group_src = sg.group_src;
+  for (uint64_t i = (uint64_t)lb * kThreads + threadIdx.x; i <= sg.n_nodes;
+       i += (uint64_t)sg.n_ptr_blocks * kThreads) {
     uint32_t lo = 0, hi = G;  // first g with group_src[g] >= i
     while (lo < hi) {
       const uint32_t mid = lo + ((hi - lo) >> 1);
       if (group_src[mid] < i) lo = mid + 1; else hi = mid;
     }
-    group_ptr[i] = lo;
+    sg.group_ptr[i] = lo;
   }
 }
 
 template <int RB>
-hipError_t upsweep_rb(const SortGeom& g, const SortIO& io, uint32_t shift, uint32_t nbits, uint32_t* counts,
-                      hipStream_t s) {
-  const dim3 grid(8 * g.ranges_per_xcd);
-  if (io.in_blocks)
-    hipLaunchKernelGGL((k_upsweep<RB, true>), grid, dim3(kSortThreads), 0, s, g, io, shift, nbits, counts);
+hipError_t upsweep_rb(const SortPack& pk, uint32_t* counts, hipStream_t s) {
+  const dim3 grid(8 * pk.ranges_per_xcd);
+  if (pk.one.io.in_blocks)
+    hipLaunchKernelGGL((k_upsweep<RB, true>), grid, dim3(kSortThreads), 0, s, pk, counts);
   else
-    hipLaunchKernelGGL((k_upsweep<RB, false>), grid, dim3(kSortThreads), 0, s, g, io, shift, nbits, counts);
+    hipLaunchKernelGGL((k_upsweep<RB, false>), grid, dim3(kSortThreads), 0, s, pk, counts);
   return hipGetLastError();
 }
 
 template <int RB>
-hipError_t downsweep_rb(const SortGeom& g, const SortIO& io, uint32_t shift, uint32_t nbits,
-                        const uint32_t* offsets, hipStream_t s) {
-  const dim3 grid(8 * g.ranges_per_xcd);
-  const bool ib = io.in_blocks != nullptr, ob = io.out_blocks != nullptr;
+hipError_t downsweep_rb(const SortPack& pk, const uint32_t* offsets, hipStream_t s) {
+  const dim3 grid(8 * pk.ranges_per_xcd);
+  const bool ib = pk.one.io.in_blocks != nullptr, ob = pk.one.io.out_blocks != nullptr;
   if (ib && ob)
-    hipLaunchKernelGGL((k_downsweep<RB, true, true>), grid, dim3(kSortThreads), 0, s, g, io, shift, nbits, offsets);
+    hipLaunchKernelGGL((k_downsweep<RB, true, true>), grid, dim3(kSortThreads), 0, s, pk, offsets);
   else if (ib)
-    hipLaunchKernelGGL((k_downsweep<RB, true, false>), grid, dim3(kSortThreads), 0, s, g, io, shift, nbits, offsets);
+    hipLaunchKernelGGL((k_downsweep<RB, true, false>), grid, dim3(kSortThreads), 0, s, pk, offsets);
   else if (ob)
-    hipLaunchKernelGGL((k_downsweep<RB, false, true>), grid, dim3(kSortThreads), 0, s, g, io, shift, nbits, offsets);
+    hipLaunchKernelGGL((k_downsweep<RB, false, true>), grid, dim3(kSortThreads), 0, s, pk, offsets);
   else
-    hipLaunchKernelGGL((k_downsweep<RB, false, false>), grid, dim3(kSortThreads), 0, s, g, io, shift, nbits, offsets);
+    hipLaunchKernelGGL((k_downsweep<RB, false, false>), grid, dim3(kSortThreads), 0, s, pk, offsets);
   return hipGetLastError();
 }
 
@@ -811,17 +829,16 @@ hipError_t launch_generate_batch(const GenDesc* d_descs, uint32_t n_calls, uint6
 uint32_t sort_tile_size() { return kTile; }
 int sort_max_radix_bits() { return kMaxRadixBits; }
 
-hipError_t launch_upsweep(const SortGeom& g, const SortIO& io, uint32_t shift, uint32_t nbits, uint32_t* counts,
-                          hipStream_t s) {
-  if (g.n == 0) return hipSuccess;
-  return nbits <= 8 ? upsweep_rb<8>(g, io, shift, nbits, counts, s) : upsweep_rb<9>(g, io, shift, nbits, counts, s);
+hipError_t launch_upsweep(const SortPack& pk, uint32_t* counts, hipStream_t s) {
+  if (pk.total_ranges == 0) return hipSuccess;
+  if (pk.max_nbits > (uint32_t)kMaxRadixBits) return hipErrorInvalidValue;
+  return pk.max_nbits <= 8 ? upsweep_rb<8>(pk, counts, s) : upsweep_rb<9>(pk, counts, s);
 }
 
-hipError_t launch_downsweep(const SortGeom& g, const SortIO& io, uint32_t shift, uint32_t nbits,
-                            const uint32_t* offsets, hipStream_t s) {
-  if (g.n == 0) return hipSuccess;
-  return nbits <= 8 ? downsweep_rb<8>(g, io, shift, nbits, offsets, s)
-                    : downsweep_rb<9>(g, io, shift, nbits, offsets, s);
+hipError_t launch_downsweep(const SortPack& pk, const uint32_t* offsets, hipStream_t s) {
+  if (pk.total_ranges == 0) return hipSuccess;
+  if (pk.max_nbits > (uint32_t)kMaxRadixBits) return hipErrorInvalidValue;
+  return pk.max_nbits <= 8 ? downsweep_rb<8>(pk, offsets, s) : downsweep_rb<9>(pk, offsets, s);
 }
 
 uint64_t scan_tmp_words(uint64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
@@ -856,31 +873,26 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, uint64_t n, hipStream_t 
 
 uint32_t gi_tile_size() { return kGiTile; }
 
-hipError_t launch_group_flags(char* const* blocks, int log2B, uint64_t n, uint32_t* bitmap,
-                              uint32_t* tile_flags, hipStream_t s) {
-  const uint64_t nt = (n + kGiTile - 1) / kGiTile;
-  if (nt == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_group_flags, dim3((uint32_t)nt), dim3(kThreads), 0, s, blocks, log2B, n, bitmap,
-                     tile_flags);
+uint32_t gi_ptr_blocks(uint32_t n_nodes) {
+  const uint64_t b = ((uint64_t)n_nodes + 1 + kThreads - 1) / kThreads;
+  return (uint32_t)(b < 4096 ? b : 4096);
+}
+
+hipError_t launch_group_flags(const GiPack& pk, uint32_t* tile_flags, hipStream_t s) {
+  if (pk.total_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_group_flags, dim3(pk.total_tiles), dim3(kThreads), 0, s, pk, tile_flags);
   return hipGetLastError();
 }
 
-hipError_t launch_group_write(char* const* blocks, int log2B, uint64_t n, const uint32_t* bitmap,
-                              const uint32_t* tile_base, uint32_t* group_start, uint32_t* group_src,
-                              hipStream_t s) {
-  const uint64_t nt = (n + kGiTile - 1) / kGiTile;
-  if (nt == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_group_write, dim3((uint32_t)nt), dim3(kThreads), 0, s, blocks, log2B, n, bitmap,
-                     tile_base, group_start, group_src);
+hipError_t launch_group_write(const GiPack& pk, const uint32_t* tile_base, hipStream_t s) {
+  if (pk.total_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_group_write, dim3(pk.total_tiles), dim3(kThreads), 0, s, pk, tile_base);
   return hipGetLastError();
 }
 
-hipError_t launch_group_ptr(const uint32_t* group_src, const uint32_t* n_groups, uint32_t n_nodes,
-                            uint32_t* group_ptr, hipStream_t s) {
-  uint64_t blocks = ((uint64_t)n_nodes + 1 + kThreads - 1) / kThreads;
-  if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_group_ptr, dim3((uint32_t)blocks), dim3(kThreads), 0, s, group_src, n_groups, n_nodes,
-                     group_ptr);
+hipError_t launch_group_ptr(const GiPack& pk, const uint32_t* tile_base, hipStream_t s) {
+  if (pk.total_ptr_blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_group_ptr, dim3(pk.total_ptr_blocks), dim3(kThreads), 0, s, pk, tile_base);
   return hipGetLastError();
 }
 

@@ -176,7 +176,7 @@ struct ng_ctx {
   uint32_t* d_scalars = nullptr;  // [0] = G
   uint32_t gi_nodes = 0;          // n_nodes the index was built for
 
-  int radix_bits = 8;
+  int radix_bits = 9;  // widest digit: the fewest passes
   uint32_t sort_ranges = 1024;  // static ranges (= workgroups) of each sort pass
   int sticky = NG_OK;
   std::string sticky_msg;
@@ -199,10 +199,12 @@ struct ng_ctx {
   uint64_t cap_stage_cap = 0, cap_stage_used = 0;
   int frozen = 0;
 
-  // pinned staging for batched descriptors
-  ng::GenDesc* h_stage = nullptr;
-  uint64_t h_stage_cap = 0;
+  // pinned staging for descriptor uploads
+  char* h_stage = nullptr;
+  uint64_t h_stage_cap = 0;  // bytes
   hipEvent_t stage_done = nullptr;
+  // orders this context's stream against another one (packed calibration)
+  hipEvent_t order_ev = nullptr;
 };
 
 namespace ngrt {
@@ -263,6 +265,14 @@ void ctx_destroy_release(ng_ctx* c);
 // descriptor carries the block table and key of this context.
 int connect_prepare(ng_ctx* c, ng_range src, ng_range tgt, const ng_conn_spec* conn,
                     const ng_syn_spec* syn, ng::GenDesc* out, uint64_t* out_n);
+// Upload `bytes` of host data to device memory on the context's stream:
+// through the graph's own pinned region while capturing, else through the
+// context's pinned staging buffer (reused once its last upload completed).
+int stage_upload(ng_ctx* c, void* d_dst, const void* src, uint64_t bytes);
+// Calibrate n distinct contexts with one sequence of launches on the first
+// one's stream (each context is one segment of the sorts); the others'
+// streams are ordered before and after with events.
+int calibrate_many(ng_ctx* const* cs, uint32_t n);
 // NG_OK if every descriptor names a block table and a key (checked on the host
 // before any batched launch).
 int check_descs(const std::vector<ng::GenDesc>& descs);

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -264,6 +265,18 @@ int check_descs(const std::vector<ng::GenDesc>& descs) {
   return NG_OK;
 }
 
+// Host-side resources of a context: pinned staging, events.
+void ctx_host_release(ng_ctx* c) {
+  if (c->h_stage) (void)hipHostFree(c->h_stage);
+  c->h_stage = nullptr;
+  if (c->stage_done) (void)hipEventDestroy(c->stage_done);
+  if (c->order_ev) (void)hipEventDestroy(c->order_ev);
+  c->stage_done = c->order_ev = nullptr;
+  collect_timing(c);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  c->ev_pool.clear();
+}
+
 char* ctx_alloc(ng_ctx* c, uint64_t bytes) {
   char* p = c->arena->alloc(bytes);
   if (p) c->held += Arena::round_up(bytes ? bytes : 1);
@@ -325,13 +338,15 @@ int ctx_init(const ng_config* cfg, Arena* shared, char* base, uint64_t bytes, hi
     delete c;
     return fail(NG_ERR_OOM, "arena too small");
   }
-  if (hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming) != hipSuccess) {
+  if (hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->order_ev, hipEventDisableTiming) != hipSuccess) {
+    ctx_host_release(c);
     delete c;
     return fail(NG_ERR_DEVICE, "hipEventCreate failed");
   }
   if (ng::launch_fill_u32(c->d_scalars, 0u, 16, c->stream) != hipSuccess ||
       set_seed(c, c->cfg.seed) != hipSuccess) {
-    (void)hipEventDestroy(c->stage_done);
+    ctx_host_release(c);
     delete c;
     return fail(NG_ERR_DEVICE, "kernel launch failed");
   }
@@ -351,10 +366,7 @@ void ctx_destroy_release(ng_ctx* c) {
   release_index(c);
   for (int t = 0; t < 2; ++t) ctx_free(c, (char*)c->d_tab[t], 8ull * c->tab_cap);
   ctx_free(c, (char*)c->d_scalars, 64);
-  if (c->h_stage) (void)hipHostFree(c->h_stage);
-  if (c->stage_done) (void)hipEventDestroy(c->stage_done);
-  collect_timing(c);
-  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  ctx_host_release(c);
   delete c;
 }
 
@@ -375,6 +387,399 @@ int connect_prepare(ng_ctx* c, ng_range src, ng_range tgt, const ng_conn_spec* c
   if (out_n) *out_n = p.n_new;
   return NG_OK;
 }
+
+int stage_upload(ng_ctx* c, void* d_dst, const void* src, uint64_t bytes) {
+  if (bytes == 0) return NG_OK;
+  if (c->capturing) {
+    // the upload becomes a graph node reading this pinned region on every replay
+    const uint64_t need = (bytes + 255) / 256 * 256;
+    if (c->cap_stage_used + need > c->cap_stage_cap)
+      return fail(NG_ERR_OOM, "graph staging region full (%llu bytes)", (unsigned long long)c->cap_stage_cap);
+    char* h = c->cap_stage + c->cap_stage_used;
+    c->cap_stage_used += need;
+    memcpy(h, src, bytes);
+    NG_HIP(c, hipMemcpyAsync(d_dst, h, bytes, hipMemcpyHostToDevice, c->stream), "upload");
+    return NG_OK;
+  }
+  NG_HIP(c, hipEventSynchronize(c->stage_done), "stage wait");
+  if (c->h_stage_cap < bytes) {
+    if (c->h_stage) (void)hipHostFree(c->h_stage);
+    c->h_stage = nullptr;
+    c->h_stage_cap = 0;
+    NG_HIP(c, hipHostMalloc((void**)&c->h_stage, bytes, hipHostMallocDefault), "hipHostMalloc");
+    c->h_stage_cap = bytes;
+  }
+  memcpy(c->h_stage, src, bytes);
+  NG_HIP(c, hipMemcpyAsync(d_dst, c->h_stage, bytes, hipMemcpyHostToDevice, c->stream), "upload");
+  NG_HIP(c, hipEventRecord(c->stage_done, c->stream), "event");
+  return NG_OK;
+}
+
+namespace {
+
+// One context's part of a (packed) calibration.
+struct CalSeg {
+  ng_ctx* c = nullptr;
+  uint64_t N = 0;
+  uint32_t nn = 0;
+  int dbits = 0, passes = 1;
+  uint32_t shift[32] = {0}, nbits[32] = {0};
+  uint32_t tiles_per_range = 0, n_ranges = 0;
+  uint64_t gi_tiles = 0, gcap = 1;
+  std::unique_ptr<AllocSet> as;
+  std::vector<char*> nblocks;
+  uint32_t* keys[2] = {nullptr, nullptr};
+  uint2* pay[2] = {nullptr, nullptr};
+  uint32_t* group_src = nullptr;
+  uint32_t* bitmap = nullptr;
+  uint32_t* gptr = nullptr;
+  uint32_t* gstart = nullptr;
+  uint64_t gp_bytes = 0, gs_bytes = 0;
+  int nxt = 0;
+};
+
+// Digit schedule and geometry (no allocation).
+int cal_plan(CalSeg& g) {
+  ng_ctx* c = g.c;
+  g.N = c->n_conns;
+  g.nn = c->n_nodes;
+  const int sbits = bitwidth(g.nn > 0 ? g.nn - 1 : 0);
+  g.dbits = bitwidth((uint64_t)c->max_delay);
+  const int keybits = sbits + g.dbits;
+  if (keybits > 32) return fail(NG_ERR_UNSUPPORTED, "source+delay keys wider than 32 bits");
+  const int RB = c->radix_bits;
+  g.passes = std::max(1, (keybits + RB - 1) / RB);
+  const int base_bits = keybits / g.passes, extra = keybits % g.passes;
+  int sh = 0;
+  for (int p = 0; p < g.passes; ++p) {
+    g.nbits[p] = (uint32_t)(base_bits + (p < extra ? 1 : 0));
+    g.shift[p] = (uint32_t)sh;
+    sh += (int)g.nbits[p];
+  }
+  // static ranges of consecutive tiles, one workgroup each
+  const uint64_t tile = ng::sort_tile_size();
+  const uint64_t n_tiles = (g.N + tile - 1) / tile;
+  g.tiles_per_range = (uint32_t)std::max<uint64_t>(1, (n_tiles + c->sort_ranges - 1) / c->sort_ranges);
+  g.n_ranges = (uint32_t)((n_tiles + g.tiles_per_range - 1) / g.tiles_per_range);
+  g.gi_tiles = (g.N + ng::gi_tile_size() - 1) / ng::gi_tile_size();
+  g.gcap = std::min<uint64_t>(g.N, (uint64_t)g.nn * (uint64_t)c->max_delay) + 1;
+  const uint64_t nblk = (g.N + c->B - 1) / c->B;
+  if (nblk > c->tab_cap) {
+    c->need = ~0ull;  // no release elsewhere makes room in the table
+    return fail(NG_ERR_OOM, "block table full");
+  }
+  return NG_OK;
+}
+
+// Per-context buffers, all-or-nothing.  The context is uncalibrated, so its
+// old index is stale and is released first to make room.
+int cal_alloc(CalSeg& g) {
+  ng_ctx* c = g.c;
+  g.as.reset(new AllocSet(c));
+  AllocSet& as = *g.as;
+  const uint64_t nblk = (g.N + c->B - 1) / c->B;
+  for (uint64_t b = 0; b < nblk && as.ok; ++b) g.nblocks.push_back(as.get(ng::kBytesPerConn * c->B));
+  for (int t = 0; t < std::min(g.passes - 1, 2); ++t) {
+    g.keys[t] = (uint32_t*)as.get(4 * std::max<uint64_t>(g.N, 1));
+    g.pay[t] = (uint2*)as.get(8 * std::max<uint64_t>(g.N, 1));
+  }
+  g.group_src = (uint32_t*)as.get(4 * g.gcap);
+  g.bitmap = (uint32_t*)as.get(4 * ((g.N + 31) / 32 + 1));
+  g.gp_bytes = 4 * (g.nn + 1ull);
+  g.gs_bytes = 4 * g.gcap;
+  release_index(c);
+  c->calibrated = false;
+  g.gptr = (uint32_t*)ctx_alloc(c, g.gp_bytes);
+  g.gstart = g.gptr ? (uint32_t*)ctx_alloc(c, g.gs_bytes) : nullptr;
+  if (!as.ok || !g.gptr || !g.gstart) {
+    as.release_all();
+    ctx_free(c, (char*)g.gptr, g.gp_bytes);
+    ctx_free(c, (char*)g.gstart, g.gs_bytes);
+    g.gptr = g.gstart = nullptr;
+    g.nblocks.clear();
+    c->need = as.asked + Arena::round_up(g.gp_bytes) + Arena::round_up(g.gs_bytes);
+    return fail(NG_ERR_OOM, "arena cannot hold the calibration buffers (N=%llu)", (unsigned long long)g.N);
+  }
+  g.nxt = 1 - c->cur;
+  return NG_OK;
+}
+
+void cal_release(CalSeg& g) {
+  if (!g.as) return;
+  g.as->release_all();
+  ctx_free(g.c, (char*)g.gptr, g.gp_bytes);
+  ctx_free(g.c, (char*)g.gstart, g.gs_bytes);
+  g.gptr = g.gstart = nullptr;
+  g.nblocks.clear();
+  g.as.reset();
+}
+
+ng::SortSeg sort_seg(const CalSeg& g, int p) {
+  ng_ctx* c = g.c;
+  ng::SortSeg s{};
+  s.io.log2B = c->log2B;
+  s.io.dbits = (uint32_t)g.dbits;
+  if (p == 0) s.io.in_blocks = c->d_tab[c->cur];
+  else {
+    s.io.in_keys = g.keys[(p - 1) & 1];
+    s.io.in_pay = g.pay[(p - 1) & 1];
+  }
+  if (p == g.passes - 1) s.io.out_blocks = c->d_tab[g.nxt];
+  else {
+    s.io.out_keys = g.keys[p & 1];
+    s.io.out_pay = g.pay[p & 1];
+  }
+  s.n = g.N;
+  s.shift = g.shift[p];
+  s.nbits = g.nbits[p];
+  s.tiles_per_range = g.tiles_per_range;
+  s.n_ranges = g.n_ranges;
+  return s;
+}
+
+uint64_t align256(uint64_t x) { return (x + 255) / 256 * 256; }
+
+}  // namespace
+
+int calibrate_many(ng_ctx* const* cs, uint32_t n) {
+  if (n == 0) return NG_OK;
+  if (!cs) return fail(NG_ERR_INVALID_ARG, "null context array");
+  for (uint32_t i = 0; i < n; ++i) {
+    if (int rc = enter(cs[i])) return rc;
+    if (int rc = mutable_state(cs[i])) return rc;
+    for (uint32_t j = 0; j < i; ++j)
+      if (cs[j] == cs[i]) return fail(NG_ERR_INVALID_ARG, "a context appears twice");
+    if (n > 1) {
+      if (cs[i]->capturing) return fail(NG_ERR_STATE, "packed calibration cannot be captured");
+      if (cs[i]->device != cs[0]->device) return fail(NG_ERR_INVALID_ARG, "contexts on different devices");
+      if (cs[i]->log2B != cs[0]->log2B) return fail(NG_ERR_INVALID_ARG, "contexts with different block sizes");
+    }
+  }
+  std::vector<CalSeg> segs;
+  for (uint32_t i = 0; i < n; ++i)
+    if (!cs[i]->calibrated) {
+      segs.emplace_back();
+      segs.back().c = cs[i];
+    }
+  if (segs.empty()) return NG_OK;
+  if (hipSetDevice(segs[0].c->device) != hipSuccess) return fail(NG_ERR_DEVICE, "hipSetDevice");
+  for (auto& g : segs)
+    if (int rc = cal_plan(g)) return rc;
+  ng_ctx* c0 = segs[0].c;
+  const bool multi = segs.size() > 1;
+
+  // sort packs: segments with records, grouped by their number of passes
+  std::map<int, std::vector<uint32_t>> packs;
+  for (uint32_t k = 0; k < segs.size(); ++k)
+    if (segs[k].N > 0) packs[segs[k].passes].push_back(k);
+  uint64_t counts_max = 0, tables = 0;
+  for (auto& pr : packs) {
+    uint64_t ranges = 0;
+    for (uint32_t k : pr.second) ranges += segs[k].n_ranges;
+    if (ranges > 0xFFFFFFFFull) return fail(NG_ERR_TOO_LARGE, "too many sort ranges");
+    for (int p = 0; p < pr.first; ++p) {
+      uint64_t cn = 0;
+      for (uint32_t k : pr.second) cn += ((uint64_t)1 << segs[k].nbits[p]) * segs[k].n_ranges;
+      counts_max = std::max(counts_max, cn);
+    }
+    tables += align256(sizeof(ng::SortSeg) * pr.second.size() * pr.first) + align256(4 * ranges);
+  }
+  uint64_t total_tiles = 0, total_ptr_blocks = 0;
+  for (auto& g : segs) {
+    total_tiles += g.gi_tiles;
+    total_ptr_blocks += ng::gi_ptr_blocks(g.nn);
+  }
+  if (total_tiles >= 0xFFFFFFFFull || total_ptr_blocks >= 0xFFFFFFFFull)
+    return fail(NG_ERR_TOO_LARGE, "too many index tiles");
+  tables += align256(sizeof(ng::GiSeg) * segs.size()) + align256(4 * total_tiles) + align256(4 * total_ptr_blocks);
+  if (!multi) tables = 0;
+
+  // allocation: per-context buffers, then the shared scratch from the first
+  for (size_t k = 0; k < segs.size(); ++k) {
+    if (int rc = cal_alloc(segs[k])) {
+      for (size_t j = 0; j < k; ++j) cal_release(segs[j]);
+      return rc;
+    }
+  }
+  AllocSet shared(c0);
+  uint32_t* counts = (uint32_t*)shared.get(4 * std::max<uint64_t>(counts_max, 1));
+  const uint64_t tmp_words = std::max(ng::scan_tmp_words(counts_max), ng::scan_tmp_words(total_tiles));
+  uint32_t* scan_tmp = (uint32_t*)shared.get(4 * tmp_words);
+  uint32_t* tile_flags = (uint32_t*)shared.get(4 * (total_tiles + 1));
+  char* d_tables = tables ? shared.get(tables) : nullptr;
+  if (!shared.ok) {
+    const uint64_t asked = shared.asked;
+    shared.release_all();
+    for (auto& g : segs) cal_release(g);
+    c0->need = asked;
+    return fail(NG_ERR_OOM, "arena cannot hold the calibration scratch");
+  }
+
+  // host images of the pack descriptors
+  struct PackLaunch {
+    int passes;
+    std::vector<ng::SortPack> pass;
+    std::vector<uint64_t> counts_n;
+  };
+  std::vector<PackLaunch> launches;
+  std::vector<char> h_tables(tables);
+  uint64_t toff = 0;
+  for (auto& pr : packs) {
+    const int P = pr.first;
+    const std::vector<uint32_t>& ks = pr.second;
+    PackLaunch pl;
+    pl.passes = P;
+    uint32_t total_ranges = 0;
+    std::vector<uint32_t> range0(ks.size());
+    for (size_t i = 0; i < ks.size(); ++i) {
+      range0[i] = total_ranges;
+      total_ranges += segs[ks[i]].n_ranges;
+    }
+    ng::SortSeg* h_segs = nullptr;
+    uint32_t* h_sor = nullptr;
+    const ng::SortSeg* d_segs = nullptr;
+    const uint32_t* d_sor = nullptr;
+    if (multi) {
+      h_segs = reinterpret_cast<ng::SortSeg*>(h_tables.data() + toff);
+      d_segs = reinterpret_cast<const ng::SortSeg*>(d_tables + toff);
+      toff += align256(sizeof(ng::SortSeg) * ks.size() * P);
+      h_sor = reinterpret_cast<uint32_t*>(h_tables.data() + toff);
+      d_sor = reinterpret_cast<const uint32_t*>(d_tables + toff);
+      toff += align256(4 * (uint64_t)total_ranges);
+      for (size_t i = 0; i < ks.size(); ++i)
+        for (uint32_t r = 0; r < segs[ks[i]].n_ranges; ++r) h_sor[range0[i] + r] = (uint32_t)i;
+    }
+    for (int p = 0; p < P; ++p) {
+      ng::SortPack pk{};
+      uint64_t cbase = 0, before = 0;
+      for (size_t i = 0; i < ks.size(); ++i) {
+        ng::SortSeg sg = sort_seg(segs[ks[i]], p);
+        sg.range0 = range0[i];
+        sg.cbase = cbase;
+        sg.base = (uint32_t)before;  // mod 2^32, as the u32 scan wraps
+        cbase += ((uint64_t)1 << sg.nbits) * sg.n_ranges;
+        before += sg.n;
+        pk.max_nbits = std::max(pk.max_nbits, sg.nbits);
+        if (i == 0) pk.one = sg;
+        if (multi) h_segs[(size_t)p * ks.size() + i] = sg;
+      }
+      pk.n_segs = (uint32_t)ks.size();
+      pk.total_ranges = total_ranges;
+      pk.ranges_per_xcd = (total_ranges + 7) / 8;
+      if (multi) {
+        pk.segs = d_segs + (size_t)p * ks.size();
+        pk.seg_of_range = d_sor;
+      }
+      pl.pass.push_back(pk);
+      pl.counts_n.push_back(cbase);
+    }
+    launches.push_back(std::move(pl));
+  }
+  ng::GiPack gp{};
+  {
+    ng::GiSeg* h_gs = nullptr;
+    uint32_t *h_sot = nullptr, *h_sopb = nullptr;
+    if (multi) {
+      h_gs = reinterpret_cast<ng::GiSeg*>(h_tables.data() + toff);
+      gp.segs = reinterpret_cast<const ng::GiSeg*>(d_tables + toff);
+      toff += align256(sizeof(ng::GiSeg) * segs.size());
+      h_sot = reinterpret_cast<uint32_t*>(h_tables.data() + toff);
+      gp.seg_of_tile = reinterpret_cast<const uint32_t*>(d_tables + toff);
+      toff += align256(4 * total_tiles);
+      h_sopb = reinterpret_cast<uint32_t*>(h_tables.data() + toff);
+      gp.seg_of_ptr_block = reinterpret_cast<const uint32_t*>(d_tables + toff);
+      toff += align256(4 * total_ptr_blocks);
+    }
+    uint32_t tile0 = 0, pb0 = 0;
+    for (size_t k = 0; k < segs.size(); ++k) {
+      const CalSeg& g = segs[k];
+      ng::GiSeg s{};
+      s.blocks = g.c->d_tab[g.nxt];
+      s.n = g.N;
+      s.bitmap = g.bitmap;
+      s.group_start = g.gstart;
+      s.group_src = g.group_src;
+      s.group_ptr = g.gptr;
+      s.n_groups = g.c->d_scalars;
+      s.tile0 = tile0;
+      s.n_tiles = (uint32_t)g.gi_tiles;
+      s.n_nodes = g.nn;
+      s.ptr_block0 = pb0;
+      s.n_ptr_blocks = ng::gi_ptr_blocks(g.nn);
+      if (multi) {
+        h_gs[k] = s;
+        for (uint32_t t = 0; t < s.n_tiles; ++t) h_sot[tile0 + t] = (uint32_t)k;
+        for (uint32_t b = 0; b < s.n_ptr_blocks; ++b) h_sopb[pb0 + b] = (uint32_t)k;
+      }
+      if (k == 0) gp.one = s;
+      tile0 += s.n_tiles;
+      pb0 += s.n_ptr_blocks;
+    }
+    gp.n_segs = (uint32_t)segs.size();
+    gp.total_tiles = tile0;
+    gp.total_ptr_blocks = pb0;
+    gp.log2B = c0->log2B;
+  }
+
+  // launches, all on the first context's stream
+  hipStream_t s = c0->stream;
+  auto run = [&]() -> int {
+    if (multi) {
+      for (auto& g : segs)
+        if (g.c->stream != s) {
+          NG_HIP(c0, hipEventRecord(g.c->order_ev, g.c->stream), "event");
+          NG_HIP(c0, hipStreamWaitEvent(s, g.c->order_ev, 0), "stream wait");
+        }
+      if (int rc = stage_upload(c0, d_tables, h_tables.data(), tables)) return rc;
+    }
+    for (auto& g : segs) NG_HIP(c0, set_table(g.c->d_tab[g.nxt], 0, g.nblocks, 0, s), "block table");
+    for (auto& pl : launches)
+      for (int p = 0; p < pl.passes; ++p) {
+        NG_LAUNCH(c0, "upsweep", ng::launch_upsweep(pl.pass[p], counts, s));
+        NG_LAUNCH(c0, "scan", ng::launch_exclusive_scan(counts, counts, pl.counts_n[p], scan_tmp, nullptr, s));
+        NG_LAUNCH(c0, "downsweep", ng::launch_downsweep(pl.pass[p], counts, s));
+      }
+    NG_LAUNCH(c0, "group_flags", ng::launch_group_flags(gp, tile_flags, s));
+    NG_LAUNCH(c0, "scan", ng::launch_exclusive_scan(tile_flags, tile_flags, total_tiles, scan_tmp,
+                                                     tile_flags + total_tiles, s));
+    NG_LAUNCH(c0, "group_write", ng::launch_group_write(gp, tile_flags, s));
+    NG_LAUNCH(c0, "group_ptr", ng::launch_group_ptr(gp, tile_flags, s));
+    if (multi) {
+      NG_HIP(c0, hipEventRecord(c0->order_ev, s), "event");
+      for (auto& g : segs)
+        if (g.c->stream != s) NG_HIP(c0, hipStreamWaitEvent(g.c->stream, c0->order_ev, 0), "stream wait");
+    }
+    return NG_OK;
+  };
+  if (int rc = run()) {
+    // device state of every context is now unknown
+    for (auto& g : segs)
+      if (g.c != c0 && c0->sticky != NG_OK) {
+        g.c->sticky = c0->sticky;
+        g.c->sticky_msg = c0->sticky_msg;
+      }
+    return rc;
+  }
+
+  // old storage and scratch return to the arenas (ordered after the launches)
+  for (auto& g : segs) {
+    ng_ctx* c = g.c;
+    for (char* b : c->blocks) ctx_free(c, b, ng::kBytesPerConn * c->B);
+    const size_t nblk = g.nblocks.size();
+    for (size_t i = nblk; i < g.as->items.size(); ++i) ctx_free(c, g.as->items[i].first, g.as->items[i].second);
+    c->blocks = g.nblocks;
+    c->cur = g.nxt;
+    c->d_group_ptr = g.gptr;
+    c->group_ptr_bytes = g.gp_bytes;
+    c->d_group_start = g.gstart;
+    c->group_start_bytes = g.gs_bytes;
+    c->gi_nodes = g.nn;
+    c->calibrated = true;
+  }
+  for (auto& it : shared.items) ctx_free(c0, it.first, it.second);
+  return NG_OK;
+}
+
 
 void connect_commit(ng_ctx* c, const ng::GenDesc& d, int32_t max_delay) {
   c->next_cid++;
@@ -416,10 +821,7 @@ int ng_destroy(ng_ctx* c) {
   if (!c) return NG_OK;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
-  if (c->h_stage) (void)hipHostFree(c->h_stage);
-  if (c->stage_done) (void)hipEventDestroy(c->stage_done);
-  collect_timing(c);
-  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  ctx_host_release(c);
   delete c;
   return NG_OK;
 }
@@ -493,29 +895,11 @@ int ng_connect_batch(ng_ctx* c, uint32_t n_calls, const ng_range* src, const ng_
     ctx_free(c, d_descs, desc_bytes);
     return rc;
   }
-  if (!descs.empty() && c->capturing) {
-    // the upload becomes a graph node reading this pinned region on every replay
-    const uint64_t need = (desc_bytes + 255) / 256 * 256;
-    if (c->cap_stage_used + need > c->cap_stage_cap) {
+  if (!descs.empty()) {
+    if (int rc = stage_upload(c, d_descs, descs.data(), desc_bytes)) {
       ctx_free(c, d_descs, desc_bytes);
-      return fail(NG_ERR_OOM, "graph staging region full (%llu bytes)", (unsigned long long)c->cap_stage_cap);
+      return rc;
     }
-    char* h = c->cap_stage + c->cap_stage_used;
-    c->cap_stage_used += need;
-    memcpy(h, descs.data(), desc_bytes);
-    NG_HIP(c, hipMemcpyAsync(d_descs, h, desc_bytes, hipMemcpyHostToDevice, c->stream), "upload");
-  } else if (!descs.empty()) {
-    // pinned staging, reused once the previous upload has completed
-    NG_HIP(c, hipEventSynchronize(c->stage_done), "stage wait");
-    if (c->h_stage_cap < descs.size()) {
-      if (c->h_stage) (void)hipHostFree(c->h_stage);
-      c->h_stage = nullptr;
-      NG_HIP(c, hipHostMalloc((void**)&c->h_stage, desc_bytes, hipHostMallocDefault), "hipHostMalloc");
-      c->h_stage_cap = descs.size();
-    }
-    memcpy(c->h_stage, descs.data(), desc_bytes);
-    NG_HIP(c, hipMemcpyAsync(d_descs, c->h_stage, desc_bytes, hipMemcpyHostToDevice, c->stream), "upload");
-    NG_HIP(c, hipEventRecord(c->stage_done, c->stream), "event");
   }
   if (!descs.empty()) {
     NG_LAUNCH(c, "generate_batch",
@@ -540,126 +924,9 @@ int ng_set_tuning(ng_ctx* c, int radix_bits, uint32_t sort_ranges) {
   return NG_OK;
 }
 
-int ng_calibrate(ng_ctx* c) {
-  if (int rc = enter(c)) return rc;
-  if (int rc = mutable_state(c)) return rc;
-  if (c->calibrated) return NG_OK;
-  const uint64_t N = c->n_conns;
-  const uint32_t nn = c->n_nodes;
-  const int sbits = bitwidth(nn > 0 ? nn - 1 : 0);
-  const int dbits = bitwidth((uint64_t)c->max_delay);
-  const int keybits = sbits + dbits;
-  if (keybits > 32) return fail(NG_ERR_UNSUPPORTED, "source+delay keys wider than 32 bits");
-  const int RB = c->radix_bits;
-  const int passes = std::max(1, (keybits + RB - 1) / RB);
-  uint32_t shift[32] = {0}, nbits[32] = {0};
-  {
-    const int base_bits = keybits / passes, extra = keybits % passes;
-    int sh = 0;
-    for (int p = 0; p < passes; ++p) {
-      nbits[p] = (uint32_t)(base_bits + (p < extra ? 1 : 0));
-      shift[p] = (uint32_t)sh;
-      sh += (int)nbits[p];
-    }
-  }
-  // geometry: static ranges of consecutive tiles, one workgroup each
-  const uint64_t tile = ng::sort_tile_size();
-  const uint64_t n_tiles = (N + tile - 1) / tile;
-  ng::SortGeom g{};
-  g.n = N;
-  g.tiles_per_range = (uint32_t)std::max<uint64_t>(1, (n_tiles + c->sort_ranges - 1) / c->sort_ranges);
-  g.n_ranges = (uint32_t)std::max<uint64_t>(1, (n_tiles + g.tiles_per_range - 1) / g.tiles_per_range);
-  g.ranges_per_xcd = (g.n_ranges + 7) / 8;
-  const uint64_t counts_n = ((uint64_t)1 << nbits[0]) * g.n_ranges;
+int ng_calibrate(ng_ctx* c) { return calibrate_many(&c, 1); }
 
-  const uint64_t nblk = (N + c->B - 1) / c->B;
-  if (nblk > c->tab_cap) {
-    c->need = ~0ull;
-    return fail(NG_ERR_OOM, "block table full");
-  }
-  const uint64_t gi_tiles = (N + ng::gi_tile_size() - 1) / ng::gi_tile_size();
-  const uint64_t gcap = std::min<uint64_t>(N, (uint64_t)nn * (uint64_t)c->max_delay) + 1;
-
-  AllocSet as(c);
-  std::vector<char*> nblocks;
-  for (uint64_t b = 0; b < nblk && as.ok; ++b) nblocks.push_back(as.get(ng::kBytesPerConn * c->B));
-  uint32_t* keys[2] = {nullptr, nullptr};
-  uint2* pay[2] = {nullptr, nullptr};
-  for (int t = 0; t < std::min(passes - 1, 2); ++t) {
-    keys[t] = (uint32_t*)as.get(4 * std::max<uint64_t>(N, 1));
-    pay[t] = (uint2*)as.get(8 * std::max<uint64_t>(N, 1));
-  }
-  uint32_t* counts = (uint32_t*)as.get(4 * counts_n);
-  const uint64_t tmp_words = std::max(ng::scan_tmp_words(counts_n), ng::scan_tmp_words(gi_tiles));
-  uint32_t* scan_tmp = (uint32_t*)as.get(4 * tmp_words);
-  uint32_t* group_src = (uint32_t*)as.get(4 * gcap);
-  uint32_t* bitmap = (uint32_t*)as.get(4 * ((N + 31) / 32 + 1));
-  uint32_t* tile_flags = (uint32_t*)as.get(4 * std::max<uint64_t>(gi_tiles, 1));
-  // the new index replaces the old one, so release the old one first
-  const uint64_t gp_bytes = 4 * (nn + 1ull), gs_bytes = 4 * gcap;
-  release_index(c);
-  uint32_t* gptr = (uint32_t*)ctx_alloc(c, gp_bytes);
-  uint32_t* gstart = gptr ? (uint32_t*)ctx_alloc(c, gs_bytes) : nullptr;
-  if (!as.ok || !gptr || !gstart) {
-    as.release_all();
-    ctx_free(c, (char*)gptr, gp_bytes);
-    ctx_free(c, (char*)gstart, gs_bytes);
-    c->need = as.asked + Arena::round_up(gp_bytes) + Arena::round_up(gs_bytes);
-    c->calibrated = false;  // the old index was released to make room
-    return fail(NG_ERR_OOM, "arena cannot hold the calibration buffers (N=%llu)", (unsigned long long)N);
-  }
-  const int nxt = 1 - c->cur;
-  hipStream_t s = c->stream;
-  NG_HIP(c, set_table(c->d_tab[nxt], 0, nblocks, 0, s), "block table");
-
-  // --- LSD radix passes ----------------------------------------------------
-  if (N > 0) {
-    for (int p = 0; p < passes; ++p) {
-      ng::SortIO io{};
-      io.log2B = c->log2B;
-      io.dbits = (uint32_t)dbits;
-      if (p == 0) io.in_blocks = c->d_tab[c->cur];
-      else {
-        io.in_keys = keys[(p - 1) & 1];
-        io.in_pay = pay[(p - 1) & 1];
-      }
-      if (p == passes - 1) io.out_blocks = c->d_tab[nxt];
-      else {
-        io.out_keys = keys[p & 1];
-        io.out_pay = pay[p & 1];
-      }
-      const uint64_t cn = ((uint64_t)1 << nbits[p]) * g.n_ranges;
-      NG_LAUNCH(c, "upsweep", ng::launch_upsweep(g, io, shift[p], nbits[p], counts, s));
-      NG_LAUNCH(c, "scan", ng::launch_exclusive_scan(counts, counts, cn, scan_tmp, nullptr, s));
-      NG_LAUNCH(c, "downsweep", ng::launch_downsweep(g, io, shift[p], nbits[p], counts, s));
-    }
-  }
-
-  // --- group index, Eq. (14) ---------------------------------------------
-  if (N > 0) {
-    NG_LAUNCH(c, "group_flags", ng::launch_group_flags(c->d_tab[nxt], c->log2B, N, bitmap, tile_flags, s));
-    NG_LAUNCH(c, "scan", ng::launch_exclusive_scan(tile_flags, tile_flags, gi_tiles, scan_tmp, c->d_scalars, s));
-    NG_LAUNCH(c, "group_write",
-              ng::launch_group_write(c->d_tab[nxt], c->log2B, N, bitmap, tile_flags, gstart, group_src, s));
-  } else {
-    NG_LAUNCH(c, "fill", ng::launch_fill_u32(c->d_scalars, 0u, 1, s));
-    NG_LAUNCH(c, "fill", ng::launch_fill_u32(gstart, 0u, 1, s));
-  }
-  NG_LAUNCH(c, "group_ptr", ng::launch_group_ptr(group_src, c->d_scalars, nn, gptr, s));
-
-  // old storage and scratch return to the arena (stream-ordered reuse)
-  for (char* b : c->blocks) ctx_free(c, b, ng::kBytesPerConn * c->B);
-  for (size_t i = nblk; i < as.items.size(); ++i) ctx_free(c, as.items[i].first, as.items[i].second);
-  c->blocks = nblocks;
-  c->cur = nxt;
-  c->d_group_ptr = gptr;
-  c->group_ptr_bytes = gp_bytes;
-  c->d_group_start = gstart;
-  c->group_start_bytes = gs_bytes;
-  c->gi_nodes = nn;
-  c->calibrated = true;
-  return NG_OK;
-}
+int ng_calibrate_many(ng_ctx* const* ctxs, uint32_t n) { return calibrate_many(ctxs, n); }
 
 int ng_reset(ng_ctx* c) {
   if (int rc = enter(c)) return rc;

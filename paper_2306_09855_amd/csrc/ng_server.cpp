@@ -13,6 +13,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <functional>
 #include <memory>
 #include <thread>
 #include <unordered_map>
@@ -69,6 +70,7 @@ struct ng_session {
   uint32_t client_nodes = 0;   // node count as the client sees it (ranges returned at submit)
   std::deque<Request*> queue;  // submitted, not yet admitted, in order
   bool close_submitted = false;
+  uint64_t base_held = 0;      // arena bytes of an empty session (tables)
 };
 
 struct ng_server {
@@ -95,7 +97,70 @@ struct ng_server {
   void run();
   void finish(Request* r, int32_t status, const std::string& msg = "");
   int stage_upload(int k, const std::vector<ng::GenDesc>& descs, ng::GenDesc** d_out, uint64_t* bytes);
+  // Calibrate the collected requests' sessions together (one packed
+  // calibration); if that fails, one by one, where a request that does not
+  // fit stays queued (and joins oom_wait) unless hopeless(session).
+  // Admitted requests leave the queues.  Returns whether any was admitted.
+  bool run_calibrations(const std::vector<Request*>& batch, const std::function<bool(ng_session*)>& hopeless,
+                        std::vector<Request*>& oom_wait);
+  void admit_calibration(Request* r);
+  // r is its session's head request: remove it from the queues
+  void dequeue(Request* r);
 };
+
+void ng_server::dequeue(Request* r) {
+  r->sess->queue.pop_front();
+  arrivals.erase(std::find(arrivals.begin(), arrivals.end(), r));
+}
+
+void ng_server::admit_calibration(Request* r) {
+  ng_ctx* c = r->sess->ctx;
+  r->admit_ns = now_ns(t0);
+  r->n_conns = c->n_conns;
+  dequeue(r);
+  auto box = std::make_shared<EventBox>();
+  if (hipEventCreateWithFlags(&box->ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventRecord(box->ev, streams[r->sess->stream]) != hipSuccess) {
+    finish(r, NG_ERR_DEVICE, "event");
+    return;
+  }
+  r->done_ev = box;
+  inflight.push_back(r);
+  stats.calibrations++;
+}
+
+bool ng_server::run_calibrations(const std::vector<Request*>& batch,
+                                 const std::function<bool(ng_session*)>& hopeless,
+                                 std::vector<Request*>& oom_wait) {
+  // every session's pending connects were flushed to its stream before this
+  if (batch.size() > 1) {
+    std::vector<ng_ctx*> ctxs;
+    for (Request* r : batch) ctxs.push_back(r->sess->ctx);
+    if (calibrate_many(ctxs.data(), (uint32_t)ctxs.size()) == NG_OK) {
+      stats.calibrate_packs++;
+      if (batch.size() > stats.max_sessions_per_pack) stats.max_sessions_per_pack = batch.size();
+      for (Request* r : batch) admit_calibration(r);
+      return true;
+    }
+  }
+  bool any = false;
+  for (Request* r : batch) {
+    const int rc = ng_calibrate(r->sess->ctx);
+    if (rc == NG_ERR_OOM && !hopeless(r->sess)) {  // waits for memory
+      oom_wait.push_back(r);
+      continue;
+    }
+    any = true;
+    if (rc != NG_OK) {
+      r->admit_ns = now_ns(t0);
+      dequeue(r);
+      finish(r, rc, ng_last_error());
+      continue;
+    }
+    admit_calibration(r);
+  }
+  return any;
+}
 
 void ng_server::finish(Request* r, int32_t status, const std::string& msg) {
   r->status = status;
@@ -218,18 +283,15 @@ void ng_server::run() {
     };
     // A request that does not fit waits for memory to come back (another
     // session's release or close).  It fails at once if it would not fit even
-    // with every other session gone, and otherwise when nothing can bring
-    // memory back: the device is idle, no freed memory is pending, no other
-    // request was admitted this round and no other session holds arena memory.
-    const bool idle_device = inflight.empty();
+    // with every other session gone (hopeless).  If no request can move and
+    // every session that could give memory back is itself waiting on the
+    // server (a deadlock), the latest such request fails; see below.
     bool admitted_any = false;
+    std::vector<Request*> oom_wait;
     auto hopeless = [&](ng_session* me) {
-      if (me->ctx->need > arena.size() - std::min(arena.size(), me->ctx->held)) return true;
-      if (!idle_device || admitted_any || arena.deferred_bytes() != 0) return false;
-      for (ng_session* o : sessions)
-        if (o != me && o->ctx && o->ctx->held != 0) return false;
-      return true;
+      return me->ctx->need > arena.size() - std::min(arena.size(), me->ctx->held);
     };
+    std::vector<Request*> cal_batch;
     for (auto it = arrivals.begin(); it != arrivals.end();) {
       Request* r = *it;
       ng_session* s = r->sess;
@@ -254,6 +316,7 @@ void ng_server::run() {
           const int rc = connect_prepare(c, r->src, r->tgt, &r->conn, &r->syn, &d, &n);
           if (rc == NG_ERR_OOM && !hopeless(s)) {
             admitted = false;  // wait for memory to come back
+            oom_wait.push_back(r);
             break;
           }
           r->admit_ns = now_ns(t0);
@@ -271,30 +334,12 @@ void ng_server::run() {
           }
           break;
         }
-        case REQ_CALIBRATE: {
-          flush(k);  // the session's pending connects run first on its stream
-          const int rc = ng_calibrate(c);
-          if (rc == NG_ERR_OOM && !hopeless(s)) {
-            admitted = false;
-            break;
-          }
-          r->admit_ns = now_ns(t0);
-          if (rc != NG_OK) {
-            finish(r, rc, ng_last_error());
-            break;
-          }
-          r->n_conns = c->n_conns;
-          auto box = std::make_shared<EventBox>();
-          if (hipEventCreateWithFlags(&box->ev, hipEventDisableTiming) != hipSuccess ||
-              hipEventRecord(box->ev, streams[k]) != hipSuccess) {
-            finish(r, NG_ERR_DEVICE, "event");
-            break;
-          }
-          r->done_ev = box;
-          inflight.push_back(r);
-          stats.calibrations++;
+        case REQ_CALIBRATE:
+          // collected: the calibrations of this round run together below; the
+          // session's later requests wait for the next round
+          cal_batch.push_back(r);
+          admitted = false;
           break;
-        }
         case REQ_CLOSE: {
           flush(k);
           r->admit_ns = now_ns(t0);
@@ -318,6 +363,25 @@ void ng_server::run() {
       }
     }
     for (int k = 0; k < ns; ++k) flush(k);
+    if (!cal_batch.empty() && run_calibrations(cal_batch, hopeless, oom_wait)) admitted_any = true;
+    if (!oom_wait.empty() && !admitted_any && inflight.empty() && arena.deferred_bytes() == 0) {
+      // Nothing runs and nothing is pending release.  Memory can still come
+      // back from a session that holds connections and has no request queued
+      // (its client may close it); if there is none, break the deadlock by
+      // failing the latest waiting request.
+      bool can_wait = false;
+      for (ng_session* o : sessions)
+        if (o->ctx && o->ctx->held > o->base_held && o->queue.empty()) can_wait = true;
+      if (!can_wait) {
+        Request* victim = oom_wait[0];
+        for (Request* r : oom_wait)
+          if (r->ticket > victim->ticket) victim = r;
+        victim->admit_ns = now_ns(t0);
+        dequeue(victim);
+        finish(victim, NG_ERR_OOM, "arena exhausted: every session holding memory waits for more");
+        admitted_any = true;
+      }
+    }
     progress = admitted_any || inflight.size() != inflight_before;
     if (stop && !progress && inflight.empty() && arena.deferred_bytes() == 0) {
       // shutting down with requests that can never be admitted
@@ -399,6 +463,7 @@ int ng_session_open(ng_server* s, uint64_t seed, ng_session** out) {
   ng_session* ss = new ng_session();
   ss->server = s;
   ss->ctx = c;
+  ss->base_held = c->held;
   ss->stream = k;
   s->sessions.push_back(ss);
   s->stats.sessions_opened++;

@@ -19,7 +19,7 @@ def arena_bytes_for(n_syn: int, n_nodes: int, max_delay: int = 63, block_size: i
     store = 14 * block_size * blocks                 # creation-order blocks
     sorted_store = store                             # calibrated blocks
     scratch = 2 * 12 * n_syn                         # two key/payload buffers (3+ passes)
-    status = 8 * (1 << radix_bits) * (n_syn // 4096 + 1)   # look-back words per tile and digit
+    status = 8 * (1 << radix_bits) * (n_syn // 4096 + 1)   # digit counts and tables (upper bound)
     index = 4 * (n_nodes + 1) * 3 + 4 * (min(n_syn, n_nodes * max_delay) + 1) + 4 * (n_syn // 4096 + 8)
     total = int((store + sorted_store + scratch + status + index) * slack) + (64 << 20)
     return (total + 4095) // 4096 * 4096
@@ -106,6 +106,12 @@ class Network:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def calibrate_many(nets) -> None:
+    """Calibrate several networks in shared launches (ng_calibrate_many); the
+    first network's stream runs them and its arena holds the shared scratch."""
+    ng.ng_calibrate_many([n.ctx for n in nets])
 
 
 class Graph:

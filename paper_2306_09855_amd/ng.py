@@ -89,7 +89,7 @@ class ng_ticket_info(ctypes.Structure):
 class ng_server_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in ("submitted", "launches", "packed_calls", "max_calls_per_launch",
                                                 "calibrations", "sessions_opened", "peak_arena_bytes",
-                                                "arena_used_bytes")]
+                                                "arena_used_bytes", "calibrate_packs", "max_sessions_per_pack")]
 
 
 _lib = None
@@ -113,6 +113,7 @@ def lib():
             "ng_connect_batch": ([vp, u32, P(ng_range), P(ng_range), P(ng_conn_spec), P(ng_syn_spec),
                                   P(u64)], ctypes.c_int),
             "ng_calibrate": ([vp], ctypes.c_int),
+            "ng_calibrate_many": ([P(vp), ctypes.c_uint32], ctypes.c_int),
             "ng_sync": ([vp], ctypes.c_int),
             "ng_get_connections": ([vp, P(ng_conn_view)], ctypes.c_int),
             "ng_copy_connections": ([vp, u64, u64, vp, vp, vp, vp], ctypes.c_int),
@@ -251,6 +252,11 @@ def ng_connect_batch(ctx, srcs, tgts, conns, syns):
 
 def ng_calibrate(ctx) -> None:
     _check(lib().ng_calibrate(ctx))
+
+
+def ng_calibrate_many(ctxs) -> None:
+    arr = (ctypes.c_void_p * len(ctxs))(*ctxs)
+    _check(lib().ng_calibrate_many(arr, len(ctxs)))
 
 
 def ng_sync(ctx) -> None:

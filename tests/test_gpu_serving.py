@@ -108,29 +108,33 @@ def test_served_equals_alone_and_oracle():
 
 
 def test_admission_waits_for_memory():
-    # two sessions that cannot be resident together: the second one's
-    # connects wait until the first session closes, then complete
-    wl = W.two_pop_indegree(scale=1.0)       # 1e5 synapses = 2 blocks of 2^16
-    need = arena_bytes_for(wl.n_syn, wl.n_nodes, wl.max_delay, B)
-    srv, arena, streams = _server(int(need * 0.75), n_streams=2)
+    # Session a (1e5 synapses) peaks near 5.2 MB while it calibrates and then
+    # holds about 2 MB.  Session b's one Connect needs 7 blocks of 2^16
+    # connections (6.4 MB): in a 7.5 MB arena it waits until a closes, then
+    # runs.  b's calibration would need another 6.4 MB of sorted blocks plus
+    # scratch, more than the arena can ever give it, so it fails at once.
+    wl = W.two_pop_indegree(scale=1.0)
+    srv, arena, streams = _server(7_500_000 // 256 * 256, n_streams=2)
     a = ng.ng_session_open(srv, 1)
     b = ng.ng_session_open(srv, 2)
     ta = [ng.ng_submit_create_nodes(a, n)[1] for n in wl.populations]
     ta += [ng.ng_submit_connect(a, *ng.call_args(c)) for c in wl.calls]
     ta.append(ng.ng_submit_calibrate(a))
-    tb = [ng.ng_submit_create_nodes(b, n)[1] for n in wl.populations]
-    tb += [ng.ng_submit_connect(b, *ng.call_args(c)) for c in wl.calls]
+    tb0 = ng.ng_submit_create_nodes(b, 2000)[1]
+    tb = ng.ng_submit_connect(b, ng.ng_range(0, 2000), ng.ng_range(0, 2000),
+                              ng.conn_spec("fixed_total_number", 400_000),
+                              ng.syn_spec(("const", 1.0), ("const", 1.0)))
     for t in ta:
         assert ng.ng_wait(srv, t).status == 0
+    assert ng.ng_wait(srv, tb0).status == 0
     # b's connect cannot fit while a holds its connections
     with pytest.raises(ng.NGError) as e:
-        ng.ng_wait(srv, tb[-1], timeout_ns=200_000_000)
+        ng.ng_wait(srv, tb, timeout_ns=200_000_000)
     assert e.value.status == ng.NG_ERR_STATE
     ng.ng_wait(srv, ng.ng_submit_close(a))
-    for t in tb:
-        assert ng.ng_wait(srv, t).status == 0
-    t = ng.ng_submit_calibrate(b)
-    assert ng.ng_wait(srv, t).status == 0
+    info = ng.ng_wait(srv, tb)
+    assert info.status == 0 and info.n_conns == 400_000
+    assert ng.ng_wait(srv, ng.ng_submit_calibrate(b)).status == ng.NG_ERR_OOM
     ng.ng_server_destroy(srv)
 
 
