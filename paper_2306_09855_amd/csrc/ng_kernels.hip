@@ -162,30 +162,67 @@ __device__ __forceinline__ void gen_quad(const GenDesc& d, uint32_t g, uint32_t 
   }
 }
 
+// Address spaces.  Pointers read from descriptors and block tables are
+// generic to the compiler, but every one of them addresses device memory:
+// saying so makes loads and stores take the global path instead of the flat
+// one (a flat access also counts against the LDS counter, so every LDS wait
+// would wait for it).  Descriptor tables are read through the constant path,
+// with uniform indices, so they land in scalar registers.
+#define NG_GLOBAL __attribute__((address_space(1)))
+#define NG_CONST __attribute__((address_space(4)))
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+template <class T>
+__device__ __forceinline__ NG_GLOBAL T* G(T* p) { return (NG_GLOBAL T*)p; }
+// element i of a read-only table (scalar loads when i is uniform)
+template <class T>
+__device__ __forceinline__ T C(const T* p, uint64_t i) { return ((const NG_CONST T*)p)[i]; }
+// a descriptor struct from a read-only table, word by word through the
+// constant path (i uniform)
+template <class T>
+__device__ __forceinline__ T C_struct(const T* p, uint32_t i) {
+  static_assert(sizeof(T) % 4 == 0, "descriptor size");
+  T out;
+  const NG_CONST uint32_t* w = (const NG_CONST uint32_t*)(p + i);
+  uint32_t* o = reinterpret_cast<uint32_t*>(&out);
+#pragma unroll
+  for (unsigned k = 0; k < sizeof(T) / 4; ++k) o[k] = w[k];
+  return out;
+}
+__device__ __forceinline__ void st_u32x4(void* p, uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+  *(NG_GLOBAL u32x4*)p = u32x4{a, b, c, d};
+}
+__device__ __forceinline__ void st_u32x2(void* p, uint32_t a, uint32_t b) { *(NG_GLOBAL u32x2*)p = u32x2{a, b}; }
+__device__ __forceinline__ uint2 ld_u32x2(const void* p) {
+  const u32x2 v = *(const NG_GLOBAL u32x2*)p;
+  return make_uint2(v.x, v.y);
+}
+
 // Block layout: src u32[B] | tgt u32[B] | w f32[B] | delay i16[B]
 __device__ __forceinline__ void store_one(char* const* __restrict__ blocks, int log2B, uint64_t p,
                                           uint32_t s, uint32_t t, float w, int32_t dl) {
   const uint64_t B = 1ull << log2B;
-  char* base = blocks[p >> log2B];
+  char* base = G(blocks)[p >> log2B];
   const uint64_t o = p & (B - 1);
-  reinterpret_cast<uint32_t*>(base)[o] = s;
-  reinterpret_cast<uint32_t*>(base + 4 * B)[o] = t;
-  reinterpret_cast<float*>(base + 8 * B)[o] = w;
-  reinterpret_cast<int16_t*>(base + 12 * B)[o] = (int16_t)dl;
+  G(reinterpret_cast<uint32_t*>(base))[o] = s;
+  G(reinterpret_cast<uint32_t*>(base + 4 * B))[o] = t;
+  G(reinterpret_cast<float*>(base + 8 * B))[o] = w;
+  G(reinterpret_cast<int16_t*>(base + 12 * B))[o] = (int16_t)dl;
 }
 
 __device__ __forceinline__ void store_quad(char* const* __restrict__ blocks, int log2B, uint64_t p0,
                                            uint32_t nvalid, const Quad& q) {
   if (nvalid == 4 && (p0 & 3) == 0) {
     const uint64_t B = 1ull << log2B;
-    char* base = blocks[p0 >> log2B];
+    char* base = G(blocks)[p0 >> log2B];
     const uint64_t o = p0 & (B - 1);
-    *reinterpret_cast<uint4*>(base + 4 * o) = make_uint4(q.s[0], q.s[1], q.s[2], q.s[3]);
-    *reinterpret_cast<uint4*>(base + 4 * B + 4 * o) = make_uint4(q.t[0], q.t[1], q.t[2], q.t[3]);
-    *reinterpret_cast<float4*>(base + 8 * B + 4 * o) = make_float4(q.w[0], q.w[1], q.w[2], q.w[3]);
+    st_u32x4(base + 4 * o, q.s[0], q.s[1], q.s[2], q.s[3]);
+    st_u32x4(base + 4 * B + 4 * o, q.t[0], q.t[1], q.t[2], q.t[3]);
+    st_u32x4(base + 8 * B + 4 * o, __float_as_uint(q.w[0]), __float_as_uint(q.w[1]), __float_as_uint(q.w[2]),
+             __float_as_uint(q.w[3]));
     const uint32_t d01 = ((uint32_t)q.d[0] & 0xFFFFu) | ((uint32_t)q.d[1] << 16);
     const uint32_t d23 = ((uint32_t)q.d[2] & 0xFFFFu) | ((uint32_t)q.d[3] << 16);
-    *reinterpret_cast<uint2*>(base + 12 * B + 2 * o) = make_uint2(d01, d23);
+    st_u32x2(base + 12 * B + 2 * o, d01, d23);
   } else {
 #pragma unroll
     for (int r = 0; r < 4; ++r)
@@ -234,7 +271,7 @@ __global__ __launch_bounds__(kGenThreads) void k_generate_batch(const GenDesc* _
       if (descs[mid].group0 <= gg) lo = mid; else hi = mid - 1;
     }
     const GenDesc d = descs[lo];
-    const uint32_t key0 = d.key[0], key1 = d.key[1];
+    const uint32_t key0 = G(d.key)[0], key1 = G(d.key)[1];
     const uint32_t g = (uint32_t)(gg - d.group0);
     Quad q;
     if (d.d_kind == D_CONST) gen_any<false>(d, g, key0, key1, q);
@@ -317,7 +354,8 @@ __device__ __forceinline__ int range_index(const SortPack& pk) {
 // The segment a global range belongs to (uniform across the workgroup).
 __device__ __forceinline__ SortSeg sort_seg(const SortPack& pk, uint32_t gr) {
   if (pk.n_segs == 1) return pk.one;
-  return pk.segs[pk.seg_of_range[gr]];
+  const uint32_t k = __builtin_amdgcn_readfirstlane(C(pk.seg_of_range, gr));
+  return C_struct(pk.segs, k);
 }
 
 // Blocked SoA source of one tile: a tile spans at most two blocks.
@@ -329,29 +367,18 @@ struct TileSrc {
 __device__ __forceinline__ TileSrc tile_src(const SortIO& io, uint64_t base, uint32_t cnt) {
   TileSrc t;
   t.first_block = base >> io.log2B;
-  t.blk[0] = io.in_blocks[t.first_block];
+  t.blk[0] = C(io.in_blocks, t.first_block);
   const uint64_t last = (base + cnt - 1) >> io.log2B;  // cnt >= 1
-  t.blk[1] = last != t.first_block ? io.in_blocks[t.first_block + 1] : t.blk[0];
+  t.blk[1] = last != t.first_block ? C(io.in_blocks, t.first_block + 1) : t.blk[0];
   return t;
-}
-
-__device__ __forceinline__ void load_blocked(const SortIO& io, const TileSrc& t, uint64_t j, uint32_t& key,
-                                             uint2& pay) {
-  const uint64_t B = 1ull << io.log2B;
-  const char* blk = t.blk[(j >> io.log2B) != t.first_block];
-  const uint64_t o = j & (B - 1);
-  key = (reinterpret_cast<const uint32_t*>(blk)[o] << io.dbits) |
-        (uint16_t) reinterpret_cast<const int16_t*>(blk + 12 * B)[o];
-  pay = make_uint2(reinterpret_cast<const uint32_t*>(blk + 4 * B)[o],
-                   reinterpret_cast<const uint32_t*>(blk + 8 * B)[o]);
 }
 
 __device__ __forceinline__ uint32_t load_blocked_key(const SortIO& io, const TileSrc& t, uint64_t j) {
   const uint64_t B = 1ull << io.log2B;
   const char* blk = t.blk[(j >> io.log2B) != t.first_block];
   const uint64_t o = j & (B - 1);
-  return (reinterpret_cast<const uint32_t*>(blk)[o] << io.dbits) |
-         (uint16_t) reinterpret_cast<const int16_t*>(blk + 12 * B)[o];
+  return (G(reinterpret_cast<const uint32_t*>(blk))[o] << io.dbits) |
+         (uint16_t)G(reinterpret_cast<const int16_t*>(blk + 12 * B))[o];
 }
 
 template <int RB, bool IN_BLOCKED>
@@ -382,7 +409,7 @@ __global__ __launch_bounds__(kSortThreads) void k_upsweep(SortPack pk, uint32_t*
 #pragma unroll
       for (int k = 0; k < kItems; ++k) {
         const uint32_t lj = k * kSortThreads + threadIdx.x;
-        key[k] = lj < cnt ? io.in_keys[base + lj] : 0u;
+        key[k] = lj < cnt ? G(io.in_keys)[base + lj] : 0u;
       }
     }
 #pragma unroll
@@ -402,41 +429,77 @@ struct SortLds {
   uint32_t* tmp;                    // [kSortWaves]
 };
 
-// One tile of a digit pass.  FULL: all kTile records present (no predicates).
-// RB bounds the digit width; digits are masked to nbits, so the ballots for
-// bits nbits..RB-1 see all-zero bits and leave the peer masks unchanged.
-template <int RB, bool IN_BLOCKED, bool OUT_BLOCKED, bool FULL>
-__device__ __forceinline__ void sort_tile(const SortIO& io, uint64_t base, uint32_t cnt, uint32_t shift,
-                                          uint32_t nbits, const SortLds& L) {
-  constexpr int NB = 1 << RB;
-  const uint32_t nd = 1u << nbits, mask = nd - 1;
+// Records of one tile into registers: wave w owns tile records
+// [w*kItems*64, (w+1)*kItems*64), 64 consecutive records per item slot.
+template <bool IN_BLOCKED, bool FULL>
+__device__ __forceinline__ void load_keys(const SortIO& io, uint64_t base, uint32_t cnt, uint32_t (&key)[kItems]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const uint64_t B = 1ull << io.log2B;
-
-  // wave w owns tile records [w*kItems*64, (w+1)*kItems*64), ranked in batches of 64
-  uint32_t key[kItems];
-  uint2 pay[kItems];
   if constexpr (IN_BLOCKED) {
     const TileSrc ts = tile_src(io, base, cnt);
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
       const uint32_t lj = (uint32_t)(wave * kItems * 64 + k * 64 + lane);
-      if (FULL || lj < cnt) load_blocked(io, ts, base + lj, key[k], pay[k]);
-      else { key[k] = 0; pay[k] = make_uint2(0, 0); }
+      key[k] = (FULL || lj < cnt) ? load_blocked_key(io, ts, base + lj) : 0u;
     }
   } else {
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
       const uint32_t lj = (uint32_t)(wave * kItems * 64 + k * 64 + lane);
+      key[k] = (FULL || lj < cnt) ? G(io.in_keys)[base + lj] : 0u;
+    }
+  }
+}
+
+template <bool IN_BLOCKED, bool FULL>
+__device__ __forceinline__ void load_pays(const SortIO& io, uint64_t base, uint32_t cnt, uint2 (&pay)[kItems]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t B = 1ull << io.log2B;
+  if constexpr (IN_BLOCKED) {
+    const TileSrc ts = tile_src(io, base, cnt);
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      const uint32_t lj = (uint32_t)(wave * kItems * 64 + k * 64 + lane);
       if (FULL || lj < cnt) {
-        key[k] = io.in_keys[base + lj];
-        pay[k] = io.in_pay[base + lj];
+        const uint64_t j = base + lj;
+        const char* blk = ts.blk[(j >> io.log2B) != ts.first_block];
+        const uint64_t o = j & (B - 1);
+        pay[k] = make_uint2(G(reinterpret_cast<const uint32_t*>(blk + 4 * B))[o],
+                            G(reinterpret_cast<const uint32_t*>(blk + 8 * B))[o]);
       } else {
-        key[k] = 0;
         pay[k] = make_uint2(0, 0);
       }
     }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      const uint32_t lj = (uint32_t)(wave * kItems * 64 + k * 64 + lane);
+      pay[k] = (FULL || lj < cnt) ? ld_u32x2(io.in_pay + base + lj) : make_uint2(0, 0);
+    }
   }
+}
+
+template <bool IN_BLOCKED>
+__device__ __forceinline__ void load_keys_any(const SortIO& io, uint64_t base, uint32_t cnt, uint32_t (&key)[kItems]) {
+  if (cnt == kTile) load_keys<IN_BLOCKED, true>(io, base, cnt, key);
+  else load_keys<IN_BLOCKED, false>(io, base, cnt, key);
+}
+
+// One tile of a digit pass, its keys already in registers.  FULL: all kTile
+// records present (no predicates).  RB bounds the digit width; digits are
+// masked to nbits, so the ballots for bits nbits..RB-1 see all-zero bits and
+// leave the peer masks unchanged.  The payloads load at the start and are
+// needed only after ranking; once they are staged in LDS, the keys of the
+// next tile (next_cnt > 0) load while this tile's payloads are stored.
+template <int RB, bool IN_BLOCKED, bool OUT_BLOCKED, bool FULL>
+__device__ __forceinline__ void sort_tile(const SortIO& io, uint64_t base, uint32_t cnt, uint32_t shift,
+                                          uint32_t nbits, const SortLds& L, uint32_t (&key)[kItems],
+                                          uint64_t next_base, uint32_t next_cnt) {
+  constexpr int NB = 1 << RB;
+  const uint32_t nd = 1u << nbits, mask = nd - 1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t B = 1ull << io.log2B;
+  uint2 pay[kItems];
+  load_pays<IN_BLOCKED, FULL>(io, base, cnt, pay);
 
   // stable rank of each record among the earlier records of its digit
   uint32_t pos[kItems];
@@ -510,12 +573,12 @@ __device__ __forceinline__ void sort_tile(const SortIO& io, uint64_t base, uint3
       const uint32_t dg = (kk >> shift) & mask;
       dest[k] = L.run[dg] + (lp - L.start[dg]);
       if constexpr (OUT_BLOCKED) {
-        char* blk = io.out_blocks[dest[k] >> io.log2B];
+        char* blk = G(io.out_blocks)[dest[k] >> io.log2B];
         const uint64_t o = dest[k] & (B - 1);
-        reinterpret_cast<uint32_t*>(blk)[o] = kk >> io.dbits;
-        reinterpret_cast<int16_t*>(blk + 12 * B)[o] = (int16_t)(kk & dmask);
+        G(reinterpret_cast<uint32_t*>(blk))[o] = kk >> io.dbits;
+        G(reinterpret_cast<int16_t*>(blk + 12 * B))[o] = (int16_t)(kk & dmask);
       } else {
-        io.out_keys[dest[k]] = kk;
+        G(io.out_keys)[dest[k]] = kk;
       }
     }
   }
@@ -532,18 +595,19 @@ __device__ __forceinline__ void sort_tile(const SortIO& io, uint64_t base, uint3
     for (int v = 0; v < kSortWaves; ++v) L.wh[v * NB + d] = 0;
   }
   lds_barrier();
+  if (next_cnt) load_keys_any<IN_BLOCKED>(io, next_base, next_cnt, key);
 #pragma unroll
   for (int k = 0; k < kItems; ++k) {
     const uint32_t lp = (uint32_t)(k * kSortThreads + threadIdx.x);
     if (FULL || lp < cnt) {
       const uint2 pp = L.buf[lp];
       if constexpr (OUT_BLOCKED) {
-        char* blk = io.out_blocks[dest[k] >> io.log2B];
+        char* blk = G(io.out_blocks)[dest[k] >> io.log2B];
         const uint64_t o = dest[k] & (B - 1);
-        reinterpret_cast<uint32_t*>(blk + 4 * B)[o] = pp.x;
-        reinterpret_cast<uint32_t*>(blk + 8 * B)[o] = pp.y;
+        G(reinterpret_cast<uint32_t*>(blk + 4 * B))[o] = pp.x;
+        G(reinterpret_cast<uint32_t*>(blk + 8 * B))[o] = pp.y;
       } else {
-        io.out_pay[dest[k]] = pp;
+        st_u32x2(io.out_pay + dest[k], pp.x, pp.y);
       }
     }
   }
@@ -572,10 +636,16 @@ __global__ __launch_bounds__(kSortThreads) void k_downsweep(SortPack pk, const u
   lds_barrier();
   const uint64_t start = (uint64_t)r * sg.tiles_per_range * kTile;
   const uint64_t end = min(start + (uint64_t)sg.tiles_per_range * kTile, sg.n);
+  uint32_t key[kItems];
+  if (start < end) load_keys_any<IN_BLOCKED>(sg.io, start, (uint32_t)min((uint64_t)kTile, end - start), key);
   for (uint64_t base = start; base < end; base += kTile) {
     const uint32_t cnt = (uint32_t)min((uint64_t)kTile, end - base);
-    if (cnt == kTile) sort_tile<RB, IN_BLOCKED, OUT_BLOCKED, true>(sg.io, base, cnt, shift, nbits, L);
-    else sort_tile<RB, IN_BLOCKED, OUT_BLOCKED, false>(sg.io, base, cnt, shift, nbits, L);
+    const uint64_t next = base + kTile;
+    const uint32_t next_cnt = next < end ? (uint32_t)min((uint64_t)kTile, end - next) : 0u;
+    if (cnt == kTile)
+      sort_tile<RB, IN_BLOCKED, OUT_BLOCKED, true>(sg.io, base, cnt, shift, nbits, L, key, next, next_cnt);
+    else
+      sort_tile<RB, IN_BLOCKED, OUT_BLOCKED, false>(sg.io, base, cnt, shift, nbits, L, key, next, next_cnt);
   }
 }
 
@@ -664,15 +734,16 @@ constexpr int kGiTile = kThreads * kGiItems;  // 8,192 positions = 256 bitmap wo
 
 __device__ __forceinline__ uint64_t group_key(char* const* __restrict__ blocks, int log2B, uint64_t j) {
   const uint64_t B = 1ull << log2B;
-  const char* blk = blocks[j >> log2B];
+  const char* blk = G(blocks)[j >> log2B];
   const uint64_t o = j & (B - 1);
-  return ((uint64_t) reinterpret_cast<const uint32_t*>(blk)[o] << 16) |
-         (uint16_t) reinterpret_cast<const int16_t*>(blk + 12 * B)[o];
+  return ((uint64_t)G(reinterpret_cast<const uint32_t*>(blk))[o] << 16) |
+         (uint16_t)G(reinterpret_cast<const int16_t*>(blk + 12 * B))[o];
 }
 
 __device__ __forceinline__ GiSeg gi_seg(const GiPack& pk, const uint32_t* table, uint32_t i) {
   if (pk.n_segs == 1) return pk.one;
-  return pk.segs[table[i]];
+  const uint32_t k = __builtin_amdgcn_readfirstlane(C(table, i));
+  return C_struct(pk.segs, k);
 }
 
 __global__ __launch_bounds__(kThreads) void k_group_flags(GiPack pk, uint32_t* __restrict__ tile_flags) {
@@ -681,13 +752,13 @@ __global__ __launch_bounds__(kThreads) void k_group_flags(GiPack pk, uint32_t* _
   const int log2B = pk.log2B;
   const uint64_t n = sg.n;
   char* const* blocks = sg.blocks;
-  uint32_t* bitmap = sg.bitmap;
+  NG_GLOBAL uint32_t* bitmap = G(sg.bitmap);
   const uint64_t base = (uint64_t)(blockIdx.x - sg.tile0) * kGiTile;
   const uint64_t B = 1ull << log2B;
-  const char* blk = blocks[base >> log2B];  // kGiTile divides the block size
+  const char* blk = C(blocks, base >> log2B);  // kGiTile divides the block size
   const uint64_t o0 = base & (B - 1);
-  const uint32_t* src = reinterpret_cast<const uint32_t*>(blk) + o0;
-  const int16_t* del = reinterpret_cast<const int16_t*>(blk + 12 * B) + o0;
+  const NG_GLOBAL uint32_t* src = G(reinterpret_cast<const uint32_t*>(blk)) + o0;
+  const NG_GLOBAL int16_t* del = G(reinterpret_cast<const int16_t*>(blk + 12 * B)) + o0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t c = 0;
 #pragma unroll 8
@@ -722,7 +793,7 @@ __global__ __launch_bounds__(kThreads) void k_group_write(GiPack pk, const uint3
   const uint64_t n = sg.n;
   const uint64_t wbase = (uint64_t)(blockIdx.x - sg.tile0) * kThreads + threadIdx.x;  // bitmap word
   const uint64_t j0 = wbase << 5;
-  uint32_t bits = j0 < n ? sg.bitmap[wbase] : 0u;
+  uint32_t bits = j0 < n ? G(sg.bitmap)[wbase] : 0u;
   if (j0 < n && n - j0 < 32) bits &= (1u << (n - j0)) - 1;
   uint32_t total;
   uint32_t g = tile_base[blockIdx.x] - tile_base[sg.tile0] +
@@ -731,8 +802,8 @@ __global__ __launch_bounds__(kThreads) void k_group_write(GiPack pk, const uint3
     const int b = __ffs(bits) - 1;
     bits &= bits - 1;
     const uint64_t j = j0 + b;
-    sg.group_start[g] = (uint32_t)j;
-    sg.group_src[g] = (uint32_t)(group_key(sg.blocks, pk.log2B, j) >> 16);
+    G(sg.group_start)[g] = (uint32_t)j;
+    G(sg.group_src)[g] = (uint32_t)(group_key(sg.blocks, pk.log2B, j) >> 16);
     ++g;
   }
 }
@@ -742,20 +813,20 @@ __global__ __launch_bounds__(kThreads) void k_group_write(GiPack pk, const uint3
 __global__ __launch_bounds__(kThreads) void k_group_ptr(GiPack pk, const uint32_t* __restrict__ tile_base) {
   const GiSeg sg = gi_seg(pk, pk.seg_of_ptr_block, blockIdx.x);
   const uint32_t lb = blockIdx.x - sg.ptr_block0;
-  const uint32_t G = tile_base[sg.tile0 + sg.n_tiles] - tile_base[sg.tile0];
+  const uint32_t ng = tile_base[sg.tile0 + sg.n_tiles] - tile_base[sg.tile0];  // G
   if (lb == 0 && threadIdx.x == 0) {
-    *sg.n_groups = G;
-    sg.group_start[G] = (uint32_t)sg.n;  // group_start[G] = n closes the last group
+    *G(sg.n_groups) = ng;
+    G(sg.group_start)[ng] = (uint32_t)sg.n;  // group_start[G] = n closes the last group
   }
-  const uint32_t* group_src = sg.group_src;
+  const NG_GLOBAL uint32_t* group_src = G(sg.group_src);
   for (uint64_t i = (uint64_t)lb * kThreads + threadIdx.x; i <= sg.n_nodes;
        i += (uint64_t)sg.n_ptr_blocks * kThreads) {
-    uint32_t lo = 0, hi = G;  // first g with group_src[g] >= i
+    uint32_t lo = 0, hi = ng;  // first g with group_src[g] >= i
     while (lo < hi) {
       const uint32_t mid = lo + ((hi - lo) >> 1);
       if (group_src[mid] < i) lo = mid + 1; else hi = mid;
     }
-    sg.group_ptr[i] = lo;
+    G(sg.group_ptr)[i] = lo;
   }
 }
 
