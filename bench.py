@@ -88,13 +88,15 @@ def cpu_baseline(sample_syn: int) -> dict:
 
 
 def _events(trace):
+    """(time, episode, kind, call, marshalled call arguments), by arrival time."""
+    from paper_2306_09855_amd import ng
     ev = []
     for ei, ep in enumerate(trace):
-        ev.append((ep.times[0], ei, "create", None))
+        ev.append((ep.times[0], ei, "create", None, None))
         for j, c in enumerate(ep.calls):
-            ev.append((ep.times[1 + j], ei, "connect", c))
-        ev.append((ep.times[-2], ei, "calibrate", None))
-        ev.append((ep.times[-1], ei, "close", None))
+            ev.append((ep.times[1 + j], ei, "connect", c, ng.call_args(c)))
+        ev.append((ep.times[-2], ei, "calibrate", None, None))
+        ev.append((ep.times[-1], ei, "close", None, None))
     ev.sort(key=lambda e: (e[0], e[1]))
     return ev
 
@@ -122,18 +124,20 @@ def serve_run(trace, n_streams, arena_bytes, block_size):
     srv = ng.ng_server_create(ng.ng_server_config(block_size, 0.1, 0, 0, 0), arena, arena_bytes,
                               [s.cuda_stream for s in streams])
     sessions, tickets = {}, []
+    events = _events(trace)
     t0 = time.perf_counter()
-    for (t, ei, kind, c) in _events(trace):
+    for (t, ei, kind, c, args) in events:
         _wait_until(t0 + t)
         if kind == "create":
             sessions[ei] = ng.ng_session_open(srv, trace[ei].seed)
             tickets.append((ng.ng_submit_create_nodes(sessions[ei], trace[ei].n_nodes)[1], kind, 0))
         elif kind == "connect":
-            tickets.append((ng.ng_submit_connect(sessions[ei], *ng.call_args(c)), kind, c.n_syn()))
+            tickets.append((ng.ng_submit_connect(sessions[ei], *args), kind, c.n_syn()))
         elif kind == "calibrate":
             tickets.append((ng.ng_submit_calibrate(sessions[ei]), kind, 0))
         else:
             tickets.append((ng.ng_submit_close(sessions[ei]), kind, 0))
+    submit_s = time.perf_counter() - t0
     lat, first, last, syn, bad = [], None, 0, 0, 0
     for (tk, kind, n) in tickets:
         info = ng.ng_wait(srv, tk)
@@ -152,34 +156,37 @@ def serve_run(trace, n_streams, arena_bytes, block_size):
             "connect_p50_ms": _pct(lat, 50), "connect_p99_ms": _pct(lat, 99), "failed": bad,
             "launches": stats["launches"], "calls_per_launch": round(stats["packed_calls"] / max(stats["launches"], 1), 2),
             "calibrate_packs": stats["calibrate_packs"], "max_sessions_per_pack": stats["max_sessions_per_pack"],
+            "client_submit_s": round(submit_s, 4), "scheduler_busy_s": round(stats["scheduler_busy_ns"] / 1e9, 4),
+            "scheduler_launch_s": round(stats["host_launch_ns"] / 1e9, 4),
+            "scheduler_calibrate_s": round(stats["host_calibrate_ns"] / 1e9, 4),
             "peak_arena_GiB": round(stats["peak_arena_bytes"] / 2**30, 2)}
 
 
-def plain_run(trace, block_size):
-    """The same trace served one request at a time, each synchronized (FIFO)."""
+def plain_run(trace, block_size, pool):
+    """The same trace served one request at a time, each synchronized (FIFO).
+    pool: arena tensors by size, reused across episodes and runs."""
     import torch
     from paper_2306_09855_amd import ng
     from paper_2306_09855_amd.network import arena_bytes_for
     stream = torch.cuda.Stream()
-    pool = {}   # arena tensors by size, reused across episodes
     ctxs, arenas, lat, syn = {}, {}, [], 0
+    events = _events(trace)
     t0 = time.perf_counter()
     first = last = None
-    for (t, ei, kind, c) in _events(trace):
+    for (t, ei, kind, c, args) in events:
         arrival = t0 + t
         _wait_until(arrival)
         ep = trace[ei]
         if kind == "create":
             need = arena_bytes_for(ep.n_syn, ep.n_nodes, 63, block_size, 9)
             size = 1 << max(24, (need - 1).bit_length())
-            a = pool.pop(size, None)
-            if a is None:
-                a = ng.arena_for(size)
+            free = pool.setdefault(size, [])
+            a = free.pop() if free else ng.arena_for(size)
             arenas[ei] = a
             ctxs[ei] = ng.ng_create(ng.ng_config(block_size, ep.seed, 0.1, 0), a, size, stream.cuda_stream)
             ng.ng_create_nodes(ctxs[ei], ep.n_nodes)
         elif kind == "connect":
-            ng.ng_connect(ctxs[ei], *ng.call_args(c))
+            ng.ng_connect(ctxs[ei], *args)
             ng.ng_sync(ctxs[ei])
             syn += c.n_syn()
         elif kind == "calibrate":
@@ -188,18 +195,16 @@ def plain_run(trace, block_size):
         else:
             ng.ng_destroy(ctxs.pop(ei))
             a = arenas.pop(ei)
-            pool[a.numel()] = a
+            pool[a.numel()].append(a)
         done = time.perf_counter()
         first = arrival if first is None else min(first, arrival)
         last = done
         if kind == "connect":
             lat.append((done - arrival) * 1e3)
-    for c in ctxs.values():
+    for ei, c in ctxs.items():
         ng.ng_destroy(c)
-    ctxs.clear()
-    arenas.clear()
-    pool.clear()
-    torch.cuda.empty_cache()
+        a = arenas.pop(ei)
+        pool[a.numel()].append(a)
     span = last - first
     return {"synapses": syn, "seconds": round(span, 4), "synapses_per_s": syn / span,
             "connect_p50_ms": _pct(lat, 50), "connect_p99_ms": _pct(lat, 99)}
@@ -214,28 +219,34 @@ def serving_bench(n_streams=4, block_size=1 << 20, loads=(0.5, 1.0, 2.0, 4.0), b
     sweep: Poisson arrivals (32 clients x sweep_episodes sessions, about 10,000
     requests) at each load x the plain path's request capacity: p50/p99
     Connect latency (arrival to device completion) and synapses/s of both."""
+    import torch
     from paper_2306_09855_amd import workloads as W
+    pool = {}
     warm = W.serving_trace(n_slots=8, episodes_per_slot=1, burst=True, gen_seed=6)
-    plain_run(warm, block_size)
     serve_run(warm, n_streams, arena_bytes, block_size)
     burst = W.serving_trace(episodes_per_slot=burst_episodes, burst=True)
     n_req = sum(len(e.calls) + 3 for e in burst)
     total = sum(e.n_syn for e in burst)
     log(f"serving: backlog of {len(burst)} sessions, {n_req} requests, {total:.3g} synapses")
-    plain_cap = plain_run(burst, block_size)
+    plain_cap = plain_run(burst, block_size, pool)
     served_cap = serve_run(burst, n_streams, arena_bytes, block_size)
     log(f"serving: backlog plain {plain_cap['seconds']} s, served {served_cap['seconds']} s")
     plain_rate = n_req / plain_cap["seconds"]
+    # the plain path holds one arena per open session: allocate them untimed,
+    # at the highest load (the most sessions open at once)
+    plain_run(W.serving_trace(episodes_per_slot=sweep_episodes, rate=max(loads) * plain_rate), block_size, pool)
     sweep = []
     for load in loads:
         timed = W.serving_trace(episodes_per_slot=sweep_episodes, rate=load * plain_rate)
         n_t = sum(len(e.calls) + 3 for e in timed)
-        p = plain_run(timed, block_size)
+        p = plain_run(timed, block_size, pool)
         sv = serve_run(timed, n_streams, arena_bytes, block_size)
         sweep.append({"load_vs_plain_capacity": load, "rate_req_per_s": round(load * plain_rate, 1),
                       "requests": n_t, "plain": p, "served": sv})
         log(f"serving: load {load}: {n_t} requests, connect p50/p99 plain {p['connect_p50_ms']:.3g}/"
             f"{p['connect_p99_ms']:.3g} ms, served {sv['connect_p50_ms']:.3g}/{sv['connect_p99_ms']:.3g} ms")
+    pool.clear()
+    torch.cuda.empty_cache()
     return {"clients": 32, "streams": n_streams, "block_size": block_size, "arena_GiB": arena_bytes / 2**30,
             "backlog": {"sessions": len(burst), "requests": n_req, "synapses": total,
                         "served": served_cap, "plain": plain_cap,

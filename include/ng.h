@@ -277,6 +277,9 @@ typedef struct {
   uint64_t sessions_opened, peak_arena_bytes, arena_used_bytes;
   uint64_t calibrate_packs;        /* calibrations of several sessions run together */
   uint64_t max_sessions_per_pack;
+  uint64_t scheduler_busy_ns;      /* scheduler thread time outside its waits */
+  uint64_t host_launch_ns;         /* of which: planning and launching packed generation */
+  uint64_t host_calibrate_ns;      /* of which: planning and launching calibrations */
 } ng_server_stats;
 int ng_server_create(const ng_server_config* cfg, void* arena, uint64_t arena_bytes,
                      void* const* streams, int n_streams, ng_server** out);
@@ -296,7 +299,7 @@ int ng_submit_close(ng_session* session, uint64_t* ticket);
  * NG_ERR_STATE: still running (the ticket stays valid). */
 int ng_wait(ng_server* server, uint64_t ticket, int64_t timeout_ns, ng_ticket_info* out);
 /* The session's context, for ng_get_connections / ng_copy_*; only while the
- * session has no request pending. */
+ * session has no request unfinished (NG_ERR_STATE otherwise). */
 int ng_session_context(ng_session* session, ng_ctx** out);
 int ng_server_get_stats(ng_server* server, ng_server_stats* out);
 

@@ -351,6 +351,25 @@ __device__ __forceinline__ int range_index(const SortPack& pk) {
   return r < pk.total_ranges ? (int)r : -1;
 }
 
+// Tiles of one range in 32-bit uniform arithmetic (a segment holds < 2^32
+// records): n_full full tiles from `start`, then a partial tile of `tail`
+// records if the range holds the segment's ragged end.  Deriving the tile
+// counts once per range keeps 64-bit min/compare selects out of the tile
+// loops.
+struct RangeTiles {
+  uint32_t start, n_full, tail;
+};
+__device__ __forceinline__ RangeTiles range_tiles(const SortSeg& sg, uint32_t r) {
+  RangeTiles t;
+  const uint32_t tpr = sg.tiles_per_range;
+  t.start = r * tpr * (uint32_t)kTile;  // r < n_ranges, so start < n
+  const uint32_t rem = (uint32_t)sg.n - t.start;
+  const uint32_t whole = rem / (uint32_t)kTile;
+  t.n_full = whole < tpr ? whole : tpr;
+  t.tail = whole < tpr ? rem - whole * (uint32_t)kTile : 0u;
+  return t;
+}
+
 // The segment a global range belongs to (uniform across the workgroup).
 __device__ __forceinline__ SortSeg sort_seg(const SortPack& pk, uint32_t gr) {
   if (pk.n_segs == 1) return pk.one;
@@ -393,10 +412,47 @@ __global__ __launch_bounds__(kSortThreads) void k_upsweep(SortPack pk, uint32_t*
   const uint32_t nd = 1u << sg.nbits, mask = nd - 1;
   for (uint32_t d = threadIdx.x; d < nd; d += kSortThreads) hist[d] = 0;
   __syncthreads();
-  const uint64_t start = (uint64_t)r * sg.tiles_per_range * kTile;
-  const uint64_t end = min(start + (uint64_t)sg.tiles_per_range * kTile, sg.n);
-  for (uint64_t base = start; base < end; base += kTile) {
-    const uint32_t cnt = (uint32_t)min((uint64_t)kTile, end - base);
+  const RangeTiles rt = range_tiles(sg, r);
+  for (uint32_t t = 0; t < rt.n_full; ++t) {
+    const uint64_t base = rt.start + t * (uint32_t)kTile;
+    const uint32_t cnt = kTile;
+    uint32_t key[kItems];
+    // A full tile with 16-byte loads: 4 consecutive records per load (the
+    // order of records does not matter to a histogram).  base is a
+    // multiple of 4 records and so is every block size, so a group of 4
+    // never straddles two blocks and every load is aligned.
+    static_assert(kItems % 4 == 0, "vector loads of 4 records");
+    if constexpr (IN_BLOCKED) {
+      const TileSrc ts = tile_src(io, base, cnt);
+      const uint64_t B = 1ull << io.log2B;
+#pragma unroll
+      for (int v = 0; v < kItems / 4; ++v) {
+        const uint64_t j = base + 4ull * (v * kSortThreads + threadIdx.x);
+        const char* blk = ts.blk[(j >> io.log2B) != ts.first_block];
+        const uint64_t o = j & (B - 1);
+        const u32x4 s4 = *(const NG_GLOBAL u32x4*)(blk + 4 * o);
+        const u32x2 d4 = *(const NG_GLOBAL u32x2*)(blk + 12 * B + 2 * o);
+        key[4 * v + 0] = (s4.x << io.dbits) | (d4.x & 0xFFFFu);
+        key[4 * v + 1] = (s4.y << io.dbits) | (d4.x >> 16);
+        key[4 * v + 2] = (s4.z << io.dbits) | (d4.y & 0xFFFFu);
+        key[4 * v + 3] = (s4.w << io.dbits) | (d4.y >> 16);
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < kItems / 4; ++v) {
+        const u32x4 k4 = *(const NG_GLOBAL u32x4*)(io.in_keys + base + 4ull * (v * kSortThreads + threadIdx.x));
+        key[4 * v + 0] = k4.x;
+        key[4 * v + 1] = k4.y;
+        key[4 * v + 2] = k4.z;
+        key[4 * v + 3] = k4.w;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) atomicAdd(&hist[(key[k] >> shift) & mask], 1u);
+  }
+  if (rt.tail) {  // the ragged last tile of the segment
+    const uint64_t base = rt.start + rt.n_full * (uint32_t)kTile;
+    const uint32_t cnt = rt.tail;
     uint32_t key[kItems];
     if constexpr (IN_BLOCKED) {
       const TileSrc ts = tile_src(io, base, cnt);
@@ -634,19 +690,19 @@ __global__ __launch_bounds__(kSortThreads) void k_downsweep(SortPack pk, const u
     for (int v = 0; v < kSortWaves; ++v) s_wh[v * NB + d] = 0;
   }
   lds_barrier();
-  const uint64_t start = (uint64_t)r * sg.tiles_per_range * kTile;
-  const uint64_t end = min(start + (uint64_t)sg.tiles_per_range * kTile, sg.n);
+  const RangeTiles rt = range_tiles(sg, r);
   uint32_t key[kItems];
-  if (start < end) load_keys_any<IN_BLOCKED>(sg.io, start, (uint32_t)min((uint64_t)kTile, end - start), key);
-  for (uint64_t base = start; base < end; base += kTile) {
-    const uint32_t cnt = (uint32_t)min((uint64_t)kTile, end - base);
-    const uint64_t next = base + kTile;
-    const uint32_t next_cnt = next < end ? (uint32_t)min((uint64_t)kTile, end - next) : 0u;
-    if (cnt == kTile)
-      sort_tile<RB, IN_BLOCKED, OUT_BLOCKED, true>(sg.io, base, cnt, shift, nbits, L, key, next, next_cnt);
-    else
-      sort_tile<RB, IN_BLOCKED, OUT_BLOCKED, false>(sg.io, base, cnt, shift, nbits, L, key, next, next_cnt);
+  if (rt.n_full) load_keys<IN_BLOCKED, true>(sg.io, rt.start, kTile, key);
+  else load_keys<IN_BLOCKED, false>(sg.io, rt.start, rt.tail, key);
+  for (uint32_t t = 0; t < rt.n_full; ++t) {
+    const uint32_t base = rt.start + t * (uint32_t)kTile;
+    const uint32_t next_cnt = t + 1 < rt.n_full ? (uint32_t)kTile : rt.tail;
+    sort_tile<RB, IN_BLOCKED, OUT_BLOCKED, true>(sg.io, base, kTile, shift, nbits, L, key, base + (uint32_t)kTile,
+                                                 next_cnt);
   }
+  if (rt.tail)
+    sort_tile<RB, IN_BLOCKED, OUT_BLOCKED, false>(sg.io, rt.start + rt.n_full * (uint32_t)kTile, rt.tail, shift,
+                                                  nbits, L, key, 0, 0u);
 }
 
 // ---------------------------------------------------------------------------

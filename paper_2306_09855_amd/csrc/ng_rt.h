@@ -5,7 +5,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <functional>
 #include <cstdint>
+#include <deque>
 #include <map>
 #include <mutex>
 #include <string>
@@ -22,13 +24,17 @@ constexpr uint64_t kAlign = 256;
 
 // First-fit sub-allocator over the caller's arena (host bookkeeping only).
 // Thread-safe.  A context that owns its arena frees immediately (reuse is
-// ordered by its single stream); an arena shared by contexts on several
-// streams gets frees through release_after(), which holds the range until an
-// event recorded after its last use has completed.
+// ordered by its single stream).  An arena shared by contexts on several
+// streams takes frees through release_after(stream, ranges, event): the
+// ranges come back once the event, recorded on that stream after their last
+// use, has completed.  Events of one stream complete in order, so only the
+// oldest pending release of each stream is ever queried.
 class Arena {
  public:
+  using Ranges = std::vector<std::pair<char*, uint64_t>>;
   ~Arena() {
-    for (auto& d : deferred_) (void)hipEventDestroy(d.ev);
+    for (auto& kv : deferred_)
+      for (auto& d : kv.second) (void)hipEventDestroy(d.ev);
   }
   void init(char* base, uint64_t size) {
     base_ = base;
@@ -38,8 +44,41 @@ class Arena {
   }
   char* alloc(uint64_t bytes) {
     std::lock_guard<std::mutex> lk(mu_);
-    reclaim_locked();
     bytes = round_up(bytes ? bytes : 1);
+    char* p = first_fit_locked(bytes);
+    if (!p && deferred_bytes_) {
+      reclaim_locked();
+      p = first_fit_locked(bytes);
+    }
+    return p;
+  }
+  void release(char* p, uint64_t bytes) {
+    std::lock_guard<std::mutex> lk(mu_);
+    release_locked(p, bytes);
+  }
+  // release the ranges once `ev` (recorded on `stream` after their last use)
+  // has completed; takes the event
+  void release_after(hipStream_t stream, Ranges&& ranges, hipEvent_t ev) {
+    std::lock_guard<std::mutex> lk(mu_);
+    uint64_t b = 0;
+    for (auto& r : ranges) b += round_up(r.second ? r.second : 1);
+    deferred_[stream].push_back({std::move(ranges), ev, b});
+    deferred_bytes_ += b;
+  }
+  uint64_t deferred_bytes() {
+    std::lock_guard<std::mutex> lk(mu_);
+    reclaim_locked();
+    return deferred_bytes_;
+  }
+  uint64_t size() const { return size_; }
+
+ private:
+  struct Deferred {
+    Ranges ranges;
+    hipEvent_t ev;
+    uint64_t bytes;
+  };
+  char* first_fit_locked(uint64_t bytes) {
     for (auto it = free_.begin(); it != free_.end(); ++it) {
       if (it->second >= bytes) {
         const uint64_t off = it->first, sz = it->second;
@@ -52,42 +91,16 @@ class Arena {
     }
     return nullptr;
   }
-  void release(char* p, uint64_t bytes) {
-    std::lock_guard<std::mutex> lk(mu_);
-    release_locked(p, bytes);
-  }
-  // release once `ev` (recorded after the last use) has completed; takes the event
-  void release_after(char* p, uint64_t bytes, hipEvent_t ev) {
-    if (!p) return;
-    std::lock_guard<std::mutex> lk(mu_);
-    deferred_.push_back({p, bytes, ev});
-  }
-  uint64_t deferred_bytes() {
-    std::lock_guard<std::mutex> lk(mu_);
-    reclaim_locked();
-    uint64_t b = 0;
-    for (auto& d : deferred_) b += round_up(d.bytes ? d.bytes : 1);
-    return b;
-  }
-  uint64_t size() const { return size_; }
-
- private:
-  struct Deferred {
-    char* p;
-    uint64_t bytes;
-    hipEvent_t ev;
-  };
   void reclaim_locked() {
-    size_t k = 0;
-    for (size_t i = 0; i < deferred_.size(); ++i) {
-      if (hipEventQuery(deferred_[i].ev) == hipSuccess) {
-        release_locked(deferred_[i].p, deferred_[i].bytes);
-        (void)hipEventDestroy(deferred_[i].ev);
-      } else {
-        deferred_[k++] = deferred_[i];
+    for (auto& kv : deferred_) {
+      auto& q = kv.second;
+      while (!q.empty() && hipEventQuery(q.front().ev) == hipSuccess) {
+        for (auto& r : q.front().ranges) release_locked(r.first, r.second);
+        (void)hipEventDestroy(q.front().ev);
+        deferred_bytes_ -= q.front().bytes;
+        q.pop_front();
       }
     }
-    deferred_.resize(k);
   }
   void release_locked(char* p, uint64_t bytes) {
     if (!p) return;
@@ -127,7 +140,8 @@ class Arena {
   std::map<uint64_t, uint64_t> free_;
   uint64_t used_ = 0, peak_ = 0;
   std::mutex mu_;
-  std::vector<Deferred> deferred_;
+  std::map<hipStream_t, std::deque<Deferred>> deferred_;
+  uint64_t deferred_bytes_ = 0;
 };
 
 
@@ -155,6 +169,7 @@ struct ng_ctx {
   ngrt::Arena own_arena;
   ngrt::Arena* arena = &own_arena;  // a server's shared arena for sessions
   bool shared_arena = false;        // frees wait for this context's stream
+  ngrt::Arena::Ranges pending_frees;  // shared arena: freed, not yet handed back
   uint64_t held = 0;                // arena bytes this context holds
   uint64_t need = 0;                // bytes the last NG_ERR_OOM asked for
 
@@ -252,9 +267,13 @@ int mutable_state(ng_ctx* c);
 int not_capturing(ng_ctx* c);
 int reserve_blocks(ng_ctx* c, uint64_t n_new);
 void release_index(ng_ctx* c);
-// Return memory to the context's arena (deferred past the stream's pending
-// work when the arena is shared).
+// Return memory to the context's arena.  With a shared arena the range is
+// collected and handed back by ctx_flush_frees, behind one event recorded on
+// the context's stream after everything enqueued so far.
 void ctx_free(ng_ctx* c, char* p, uint64_t bytes);
+void ctx_flush_frees(ng_ctx* c);
+// Undo an allocation that no enqueued work has used (rollback): at once.
+void ctx_unalloc(ng_ctx* c, char* p, uint64_t bytes);
 // A context over a shared arena on `stream` (server sessions).
 int ctx_init(const ng_config* cfg, Arena* shared, char* base, uint64_t bytes, hipStream_t stream,
              ng_ctx** out);
@@ -269,10 +288,13 @@ int connect_prepare(ng_ctx* c, ng_range src, ng_range tgt, const ng_conn_spec* c
 // through the graph's own pinned region while capturing, else through the
 // context's pinned staging buffer (reused once its last upload completed).
 int stage_upload(ng_ctx* c, void* d_dst, const void* src, uint64_t bytes);
+// Copies host bytes to device memory, stream-ordered on the given stream.
+using Uploader = std::function<int(hipStream_t, void* d_dst, const void* src, uint64_t bytes)>;
 // Calibrate n distinct contexts with one sequence of launches on the first
 // one's stream (each context is one segment of the sorts); the others'
-// streams are ordered before and after with events.
-int calibrate_many(ng_ctx* const* cs, uint32_t n);
+// streams are ordered before and after with events.  Descriptor tables go up
+// through `upload` if given, else through the first context's staging.
+int calibrate_many(ng_ctx* const* cs, uint32_t n, const Uploader* upload = nullptr);
 // NG_OK if every descriptor names a block table and a key (checked on the host
 // before any batched launch).
 int check_descs(const std::vector<ng::GenDesc>& descs);

@@ -193,6 +193,7 @@ int enter(ng_ctx* c) {
   if (c->sticky != NG_OK) return fail(c->sticky, "%s", c->sticky_msg.c_str());
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return dev_fail(c, e, "hipSetDevice");
+  if (!c->capturing) ctx_flush_frees(c);  // frees left by an earlier call
   return NG_OK;
 }
 
@@ -239,7 +240,7 @@ int reserve_blocks(ng_ctx* c, uint64_t n_new) {
   for (uint64_t b = 0; b < nb; ++b) {
     char* p = ctx_alloc(c, ng::kBytesPerConn * c->B);
     if (!p) {
-      for (char* q : fresh) ctx_free(c, q, ng::kBytesPerConn * c->B);
+      for (char* q : fresh) ctx_unalloc(c, q, ng::kBytesPerConn * c->B);
       c->need = nb * Arena::round_up(ng::kBytesPerConn * c->B);
       return fail(NG_ERR_OOM, "arena cannot hold %llu more blocks of %llu connections",
                   (unsigned long long)nb, (unsigned long long)c->B);
@@ -290,16 +291,28 @@ void ctx_free(ng_ctx* c, char* p, uint64_t bytes) {
     c->arena->release(p, bytes);
     return;
   }
+  c->pending_frees.emplace_back(p, bytes);
+}
+
+void ctx_unalloc(ng_ctx* c, char* p, uint64_t bytes) {
+  if (!p) return;
+  c->held -= Arena::round_up(bytes ? bytes : 1);
+  c->arena->release(p, bytes);
+}
+
+void ctx_flush_frees(ng_ctx* c) {
+  if (c->pending_frees.empty()) return;
   hipEvent_t ev = nullptr;
   if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess &&
       hipEventRecord(ev, c->stream) == hipSuccess) {
-    c->arena->release_after(p, bytes, ev);
+    c->arena->release_after(c->stream, std::move(c->pending_frees), ev);
   } else {
     // cannot order the release: wait for the stream instead
     if (ev) (void)hipEventDestroy(ev);
     (void)hipStreamSynchronize(c->stream);
-    c->arena->release(p, bytes);
+    for (auto& r : c->pending_frees) c->arena->release(r.first, r.second);
   }
+  c->pending_frees.clear();
 }
 
 // Common construction: an own arena over [base, base + bytes), or a shared one.
@@ -366,12 +379,14 @@ void ctx_destroy_release(ng_ctx* c) {
   release_index(c);
   for (int t = 0; t < 2; ++t) ctx_free(c, (char*)c->d_tab[t], 8ull * c->tab_cap);
   ctx_free(c, (char*)c->d_scalars, 64);
+  ctx_flush_frees(c);
   ctx_host_release(c);
   delete c;
 }
 
 int connect_prepare(ng_ctx* c, ng_range src, ng_range tgt, const ng_conn_spec* conn,
                     const ng_syn_spec* syn, ng::GenDesc* out, uint64_t* out_n) {
+  if (!c->capturing) ctx_flush_frees(c);  // make this context's frees reusable
   Plan p;
   if (int rc = plan_call(c->n_nodes, src, tgt, conn, syn, c->cfg.h_ms, &p)) return rc;
   if (c->next_cid == 0xFFFFFFFFu) return fail(NG_ERR_TOO_LARGE, "connect call ids exhausted");
@@ -493,8 +508,8 @@ int cal_alloc(CalSeg& g) {
   g.gstart = g.gptr ? (uint32_t*)ctx_alloc(c, g.gs_bytes) : nullptr;
   if (!as.ok || !g.gptr || !g.gstart) {
     as.release_all();
-    ctx_free(c, (char*)g.gptr, g.gp_bytes);
-    ctx_free(c, (char*)g.gstart, g.gs_bytes);
+    ctx_unalloc(c, (char*)g.gptr, g.gp_bytes);
+    ctx_unalloc(c, (char*)g.gstart, g.gs_bytes);
     g.gptr = g.gstart = nullptr;
     g.nblocks.clear();
     c->need = as.asked + Arena::round_up(g.gp_bytes) + Arena::round_up(g.gs_bytes);
@@ -507,8 +522,8 @@ int cal_alloc(CalSeg& g) {
 void cal_release(CalSeg& g) {
   if (!g.as) return;
   g.as->release_all();
-  ctx_free(g.c, (char*)g.gptr, g.gp_bytes);
-  ctx_free(g.c, (char*)g.gstart, g.gs_bytes);
+  ctx_unalloc(g.c, (char*)g.gptr, g.gp_bytes);
+  ctx_unalloc(g.c, (char*)g.gstart, g.gs_bytes);
   g.gptr = g.gstart = nullptr;
   g.nblocks.clear();
   g.as.reset();
@@ -541,7 +556,7 @@ uint64_t align256(uint64_t x) { return (x + 255) / 256 * 256; }
 
 }  // namespace
 
-int calibrate_many(ng_ctx* const* cs, uint32_t n) {
+int calibrate_many(ng_ctx* const* cs, uint32_t n, const Uploader* upload) {
   if (n == 0) return NG_OK;
   if (!cs) return fail(NG_ERR_INVALID_ARG, "null context array");
   for (uint32_t i = 0; i < n; ++i) {
@@ -723,15 +738,24 @@ int calibrate_many(ng_ctx* const* cs, uint32_t n) {
 
   // launches, all on the first context's stream
   hipStream_t s = c0->stream;
-  auto run = [&]() -> int {
-    if (multi) {
-      for (auto& g : segs)
-        if (g.c->stream != s) {
-          NG_HIP(c0, hipEventRecord(g.c->order_ev, g.c->stream), "event");
-          NG_HIP(c0, hipStreamWaitEvent(s, g.c->order_ev, 0), "stream wait");
-        }
-      if (int rc = stage_upload(c0, d_tables, h_tables.data(), tables)) return rc;
+  if (multi) {
+    // the other streams' pending work (the segments' connects) comes first
+    int rc = NG_OK;
+    for (auto& g : segs)
+      if (rc == NG_OK && g.c->stream != s &&
+          (hipEventRecord(g.c->order_ev, g.c->stream) != hipSuccess ||
+           hipStreamWaitEvent(s, g.c->order_ev, 0) != hipSuccess))
+        rc = dev_fail(c0, hipErrorUnknown, "stream ordering");
+    if (rc == NG_OK)
+      rc = upload ? (*upload)(s, d_tables, h_tables.data(), tables)
+                  : stage_upload(c0, d_tables, h_tables.data(), tables);
+    if (rc != NG_OK) {  // nothing has used the new buffers yet
+      shared.release_all();
+      for (auto& g : segs) cal_release(g);
+      return rc == NG_ERR_DEVICE || rc == NG_ERR_OOM ? rc : fail(rc, "packed calibration upload failed");
     }
+  }
+  auto run = [&]() -> int {
     for (auto& g : segs) NG_HIP(c0, set_table(g.c->d_tab[g.nxt], 0, g.nblocks, 0, s), "block table");
     for (auto& pl : launches)
       for (int p = 0; p < pl.passes; ++p) {
@@ -777,6 +801,8 @@ int calibrate_many(ng_ctx* const* cs, uint32_t n) {
     c->calibrated = true;
   }
   for (auto& it : shared.items) ctx_free(c0, it.first, it.second);
+  if (!c0->capturing)
+    for (auto& g : segs) ctx_flush_frees(g.c);
   return NG_OK;
 }
 
@@ -887,17 +913,17 @@ int ng_connect_batch(ng_ctx* c, uint32_t n_calls, const ng_range* src, const ng_
     if (!d_descs) return fail(NG_ERR_OOM, "arena cannot hold the call descriptors");
   }
   if (int rc = reserve_blocks(c, total)) {
-    ctx_free(c, d_descs, desc_bytes);
+    ctx_unalloc(c, d_descs, desc_bytes);
     return rc;
   }
   for (auto& d : descs) d.blocks = c->d_tab[c->cur];
   if (int rc = check_descs(descs)) {
-    ctx_free(c, d_descs, desc_bytes);
+    ctx_unalloc(c, d_descs, desc_bytes);
     return rc;
   }
   if (!descs.empty()) {
     if (int rc = stage_upload(c, d_descs, descs.data(), desc_bytes)) {
-      ctx_free(c, d_descs, desc_bytes);
+      ctx_unalloc(c, d_descs, desc_bytes);
       return rc;
     }
   }
@@ -906,6 +932,7 @@ int ng_connect_batch(ng_ctx* c, uint32_t n_calls, const ng_range* src, const ng_
               ng::launch_generate_batch((const ng::GenDesc*)d_descs, (uint32_t)descs.size(), groups,
                                         c->log2B, c->stream));
     ctx_free(c, d_descs, desc_bytes);  // stream-ordered reuse is safe
+    if (!c->capturing) ctx_flush_frees(c);
     c->calibrated = false;
   }
   c->next_cid += n_calls;

@@ -7,6 +7,13 @@
 // different sessions overlaps on the device.  Every request carries its
 // arrival, admission and completion times (host steady clock).
 //
+// Locking: the API side (submit, open, wait, stats) touches only the shared
+// part of the server under `mu` for a few instructions.  The scheduler takes
+// the new submissions at the start of a round, does all device work on
+// private state without the lock, and publishes the requests it finished
+// (and its counters) under the lock at the end of the round, so a client is
+// never held up by the scheduler's device calls.
+//
 // Arithmetic is unchanged: a session's result equals the same calls issued on
 // a context of its own (same seed, same call order).
 #include <chrono>
@@ -50,7 +57,6 @@ struct Request {
   int32_t status = NG_OK;
   uint64_t n_conns = 0;
   std::string msg;
-  std::shared_ptr<EventBox> done_ev;
   bool done = false;
 };
 
@@ -68,34 +74,58 @@ struct ng_session {
   ng_ctx* ctx = nullptr;
   int stream = 0;
   uint32_t client_nodes = 0;   // node count as the client sees it (ranges returned at submit)
-  std::deque<Request*> queue;  // submitted, not yet admitted, in order
-  bool close_submitted = false;
+  std::deque<Request*> queue;  // scheduler: taken over, not yet admitted, in order
+  bool close_submitted = false;  // under mu
+  uint32_t pending = 0;          // under mu: submitted and not yet finished
+  uint64_t blocked_round = 0;    // scheduler: head request must wait in this round
   uint64_t base_held = 0;      // arena bytes of an empty session (tables)
 };
 
 struct ng_server {
   ng_server_config cfg{};
   int log2B = 24;
-  Arena arena;
-  std::vector<ng_session*> sessions;  // open sessions
+  Arena arena;  // thread-safe on its own
   std::vector<hipStream_t> streams;
   std::vector<std::vector<Stage>> stages;
   int device = 0;
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
 
+  // shared with the API side, under mu
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::thread thr;
   bool stop = false;
-  bool new_arrivals = false;
   uint64_t next_ticket = 1;
-  std::deque<Request*> arrivals;                  // global arrival order
+  std::vector<Request*> incoming;                 // submitted, not yet taken by the scheduler
+  std::vector<ng_session*> new_sessions;          // opened, not yet taken by the scheduler
   std::unordered_map<uint64_t, Request*> tickets;  // not yet collected by ng_wait
-  std::vector<Request*> inflight;
   ng_server_stats stats{};
 
+  // scheduler thread only
+  std::vector<ng_session*> sessions;  // open sessions
+  std::deque<Request*> arrivals;      // global arrival order, not yet admitted
+  // launched requests, per stream in launch order: the events of a stream
+  // complete in order, so only the oldest group of each is queried
+  struct Group {
+    std::shared_ptr<EventBox> ev;
+    std::vector<Request*> reqs;
+  };
+  std::vector<std::deque<Group>> inflight;
+  size_t n_inflight = 0;
+  uint64_t round = 0;                 // scheduling rounds (blocked-session marks)
+  std::vector<Request*> finished;     // finished this round, published under mu
+  std::vector<ng_session*> closed;    // deleted once all their requests are published
+  ng_server_stats sched{};            // scheduler-owned counters
+
   void run();
+  // Record a request's result; it becomes visible to ng_wait when published.
   void finish(Request* r, int32_t status, const std::string& msg = "");
+  // Under mu: make this round's finished requests and counters visible.
+  void publish();
+  // Copy host bytes to device memory on stream k through the stream's pinned
+  // stages (allocated once, reused once their last copy ran; the scheduler
+  // never frees pinned memory, which would wait for the whole device).
+  int upload(int k, void* d, const void* src, uint64_t nb);
   int stage_upload(int k, const std::vector<ng::GenDesc>& descs, ng::GenDesc** d_out, uint64_t* bytes);
   // Calibrate the collected requests' sessions together (one packed
   // calibration); if that fails, one by one, where a request that does not
@@ -124,9 +154,9 @@ void ng_server::admit_calibration(Request* r) {
     finish(r, NG_ERR_DEVICE, "event");
     return;
   }
-  r->done_ev = box;
-  inflight.push_back(r);
-  stats.calibrations++;
+  inflight[r->sess->stream].push_back({box, {r}});
+  n_inflight++;
+  sched.calibrations++;
 }
 
 bool ng_server::run_calibrations(const std::vector<Request*>& batch,
@@ -136,9 +166,14 @@ bool ng_server::run_calibrations(const std::vector<Request*>& batch,
   if (batch.size() > 1) {
     std::vector<ng_ctx*> ctxs;
     for (Request* r : batch) ctxs.push_back(r->sess->ctx);
-    if (calibrate_many(ctxs.data(), (uint32_t)ctxs.size()) == NG_OK) {
-      stats.calibrate_packs++;
-      if (batch.size() > stats.max_sessions_per_pack) stats.max_sessions_per_pack = batch.size();
+    const Uploader up = [&](hipStream_t st, void* d, const void* src, uint64_t nb) {
+      for (size_t k = 0; k < streams.size(); ++k)
+        if (streams[k] == st) return upload((int)k, d, src, nb);
+      return (int)NG_ERR_STATE;
+    };
+    if (calibrate_many(ctxs.data(), (uint32_t)ctxs.size(), &up) == NG_OK) {
+      sched.calibrate_packs++;
+      if (batch.size() > sched.max_sessions_per_pack) sched.max_sessions_per_pack = batch.size();
       for (Request* r : batch) admit_calibration(r);
       return true;
     }
@@ -165,17 +200,41 @@ bool ng_server::run_calibrations(const std::vector<Request*>& batch,
 void ng_server::finish(Request* r, int32_t status, const std::string& msg) {
   r->status = status;
   r->msg = msg;
-  r->done = true;
   r->done_ns = now_ns(t0);
-  cv_done.notify_all();
+  finished.push_back(r);
+}
+
+void ng_server::publish() {
+  for (Request* r : finished) {
+    r->sess->pending--;
+    r->done = true;  // from here on ng_wait may delete r
+  }
+  const bool any = !finished.empty();
+  finished.clear();
+  for (size_t i = 0; i < closed.size();) {
+    if (closed[i]->pending == 0) {
+      delete closed[i];
+      closed[i] = closed.back();
+      closed.pop_back();
+    } else {
+      ++i;
+    }
+  }
+  stats.launches = sched.launches;
+  stats.packed_calls = sched.packed_calls;
+  stats.max_calls_per_launch = sched.max_calls_per_launch;
+  stats.calibrations = sched.calibrations;
+  stats.peak_arena_bytes = sched.peak_arena_bytes;
+  stats.calibrate_packs = sched.calibrate_packs;
+  stats.max_sessions_per_pack = sched.max_sessions_per_pack;
+  stats.scheduler_busy_ns = sched.scheduler_busy_ns;
+  stats.host_launch_ns = sched.host_launch_ns;
+  stats.host_calibrate_ns = sched.host_calibrate_ns;
+  if (any) cv_done.notify_all();
 }
 
 // Copy descriptors to the device through a pinned stage of stream k.
-int ng_server::stage_upload(int k, const std::vector<ng::GenDesc>& descs, ng::GenDesc** d_out,
-                            uint64_t* bytes) {
-  const uint64_t nb = descs.size() * sizeof(ng::GenDesc);
-  char* d = arena.alloc(nb);
-  if (!d) return NG_ERR_OOM;
+int ng_server::upload(int k, void* d, const void* src, uint64_t nb) {
   Stage* st = nullptr;
   for (auto& s : stages[k])
     if (s.cap >= nb && (!s.busy || hipEventQuery(s.busy->ev) == hipSuccess)) {
@@ -185,23 +244,29 @@ int ng_server::stage_upload(int k, const std::vector<ng::GenDesc>& descs, ng::Ge
   if (!st) {
     Stage s;
     s.cap = std::max<uint64_t>(nb, 1 << 16);
-    if (hipHostMalloc((void**)&s.p, s.cap, hipHostMallocDefault) != hipSuccess) {
-      arena.release(d, nb);
-      return NG_ERR_DEVICE;
-    }
+    if (hipHostMalloc((void**)&s.p, s.cap, hipHostMallocDefault) != hipSuccess) return NG_ERR_DEVICE;
     stages[k].push_back(s);
     st = &stages[k].back();
   }
-  memcpy(st->p, descs.data(), nb);
-  if (hipMemcpyAsync(d, st->p, nb, hipMemcpyHostToDevice, streams[k]) != hipSuccess) {
-    arena.release(d, nb);
-    return NG_ERR_DEVICE;
-  }
+  memcpy(st->p, src, nb);
+  if (hipMemcpyAsync(d, st->p, nb, hipMemcpyHostToDevice, streams[k]) != hipSuccess) return NG_ERR_DEVICE;
   auto box = std::make_shared<EventBox>();
   if (hipEventCreateWithFlags(&box->ev, hipEventDisableTiming) != hipSuccess ||
       hipEventRecord(box->ev, streams[k]) != hipSuccess)
     return NG_ERR_DEVICE;
   st->busy = box;
+  return NG_OK;
+}
+
+int ng_server::stage_upload(int k, const std::vector<ng::GenDesc>& descs, ng::GenDesc** d_out,
+                            uint64_t* bytes) {
+  const uint64_t nb = descs.size() * sizeof(ng::GenDesc);
+  char* d = arena.alloc(nb);
+  if (!d) return NG_ERR_OOM;
+  if (int rc = upload(k, d, descs.data(), nb)) {
+    arena.release(d, nb);
+    return rc;
+  }
   *d_out = (ng::GenDesc*)d;
   *bytes = nb;
   return NG_OK;
@@ -210,42 +275,52 @@ int ng_server::stage_upload(int k, const std::vector<ng::GenDesc>& descs, ng::Ge
 void ng_server::run() {
   (void)hipSetDevice(device);
   const int ns = (int)streams.size();
-  std::unique_lock<std::mutex> lk(mu);
   bool progress = true;
   for (;;) {
-    // Sleep until something can change: new requests, or (polling every 20 us)
-    // device work or memory releases still pending.
-    const bool pending = !inflight.empty() || arena.deferred_bytes() != 0;
-    if (!pending && !progress)
-      cv_work.wait(lk, [&] { return stop || new_arrivals; });
-    else if (pending)
-      cv_work.wait_for(lk, std::chrono::microseconds(20), [&] { return stop || new_arrivals; });
-    new_arrivals = false;
-    if (stop && arrivals.empty() && inflight.empty()) break;
-    const size_t inflight_before = inflight.size();
+    bool stopping;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      publish();
+      // Sleep until something can change: new requests, or (polling every
+      // 20 us) device work or memory releases still pending.
+      auto news = [&] { return stop || !incoming.empty() || !new_sessions.empty(); };
+      const bool pending = n_inflight != 0 || arena.deferred_bytes() != 0;
+      if (!pending && !progress)
+        cv_work.wait(lk, news);
+      else if (pending)
+        cv_work.wait_for(lk, std::chrono::microseconds(20), news);
+      for (ng_session* ss : new_sessions) sessions.push_back(ss);
+      new_sessions.clear();
+      for (Request* r : incoming) {
+        arrivals.push_back(r);
+        r->sess->queue.push_back(r);
+      }
+      incoming.clear();
+      stopping = stop;
+    }
+    if (stopping && arrivals.empty() && n_inflight == 0) break;
+    const auto busy0 = std::chrono::steady_clock::now();
+    ++round;
 
     // completions
-    for (size_t i = 0; i < inflight.size();) {
-      Request* r = inflight[i];
-      if (hipEventQuery(r->done_ev->ev) == hipSuccess) {
-        finish(r, NG_OK);
-        inflight[i] = inflight.back();
-        inflight.pop_back();
-      } else {
-        ++i;
+    size_t completed = 0;
+    for (auto& q : inflight) {
+      while (!q.empty() && hipEventQuery(q.front().ev->ev) == hipSuccess) {
+        for (Request* r : q.front().reqs) finish(r, NG_OK);
+        completed += q.front().reqs.size();
+        q.pop_front();
       }
     }
+    n_inflight -= completed;
 
     // admission, in arrival order; a session whose head request must wait
     // blocks its later requests (per-session order is kept)
     std::vector<std::vector<ng::GenDesc>> descs(ns);
     std::vector<std::vector<Request*>> packed(ns);
-    std::vector<ng_session*> blocked;
-    auto is_blocked = [&](ng_session* s) {
-      return std::find(blocked.begin(), blocked.end(), s) != blocked.end();
-    };
+    auto is_blocked = [&](ng_session* s) { return s->blocked_round == round; };
     auto flush = [&](int k) {
       if (descs[k].empty()) return;
+      const auto f0 = std::chrono::steady_clock::now();
       uint64_t groups = 0;
       for (auto& d : descs[k]) {
         d.group0 = groups;
@@ -265,21 +340,21 @@ void ng_server::run() {
         hipEvent_t fe = nullptr;  // descriptors return to the arena after the launch
         if (hipEventCreateWithFlags(&fe, hipEventDisableTiming) == hipSuccess &&
             hipEventRecord(fe, streams[k]) == hipSuccess)
-          arena.release_after((char*)d_descs, nb, fe);
-        stats.launches++;
-        stats.packed_calls += descs[k].size();
-        if (descs[k].size() > stats.max_calls_per_launch) stats.max_calls_per_launch = descs[k].size();
+          arena.release_after(streams[k], {{(char*)d_descs, nb}}, fe);
+        sched.launches++;
+        sched.packed_calls += descs[k].size();
+        if (descs[k].size() > sched.max_calls_per_launch) sched.max_calls_per_launch = descs[k].size();
       }
-      for (Request* r : packed[k]) {
-        if (rc != NG_OK || e != hipSuccess) {
-          finish(r, NG_ERR_DEVICE, "packed generation launch failed");
-        } else {
-          r->done_ev = box;
-          inflight.push_back(r);
-        }
+      if (rc != NG_OK || e != hipSuccess) {
+        for (Request* r : packed[k]) finish(r, NG_ERR_DEVICE, "packed generation launch failed");
+      } else {
+        inflight[k].push_back({box, packed[k]});
+        n_inflight += packed[k].size();
       }
       descs[k].clear();
       packed[k].clear();
+      sched.host_launch_ns += (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+                                  std::chrono::steady_clock::now() - f0).count();
     };
     // A request that does not fit waits for memory to come back (another
     // session's release or close).  It fails at once if it would not fit even
@@ -350,7 +425,7 @@ void ng_server::run() {
         }
       }
       if (!admitted) {
-        blocked.push_back(s);
+        s->blocked_round = round;
         ++it;
         continue;
       }
@@ -359,12 +434,17 @@ void ng_server::run() {
       it = arrivals.erase(it);
       if (r->kind == REQ_CLOSE) {
         sessions.erase(std::find(sessions.begin(), sessions.end(), s));
-        delete s;
+        closed.push_back(s);  // deleted once its requests are published
       }
     }
     for (int k = 0; k < ns; ++k) flush(k);
-    if (!cal_batch.empty() && run_calibrations(cal_batch, hopeless, oom_wait)) admitted_any = true;
-    if (!oom_wait.empty() && !admitted_any && inflight.empty() && arena.deferred_bytes() == 0) {
+    if (!cal_batch.empty()) {
+      const auto c0 = std::chrono::steady_clock::now();
+      if (run_calibrations(cal_batch, hopeless, oom_wait)) admitted_any = true;
+      sched.host_calibrate_ns += (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+                                     std::chrono::steady_clock::now() - c0).count();
+    }
+    if (!oom_wait.empty() && !admitted_any && n_inflight == 0 && arena.deferred_bytes() == 0) {
       // Nothing runs and nothing is pending release.  Memory can still come
       // back from a session that holds connections and has no request queued
       // (its client may close it); if there is none, break the deadlock by
@@ -382,8 +462,8 @@ void ng_server::run() {
         admitted_any = true;
       }
     }
-    progress = admitted_any || inflight.size() != inflight_before;
-    if (stop && !progress && inflight.empty() && arena.deferred_bytes() == 0) {
+    progress = admitted_any || completed != 0;
+    if (stopping && !progress && n_inflight == 0 && arena.deferred_bytes() == 0) {
       // shutting down with requests that can never be admitted
       for (Request* r : arrivals) {
         r->admit_ns = now_ns(t0);
@@ -394,8 +474,12 @@ void ng_server::run() {
       break;
     }
     const uint64_t used = arena.used();
-    if (used > stats.peak_arena_bytes) stats.peak_arena_bytes = used;
+    if (used > sched.peak_arena_bytes) sched.peak_arena_bytes = used;
+    sched.scheduler_busy_ns += (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+                                   std::chrono::steady_clock::now() - busy0).count();
   }
+  std::lock_guard<std::mutex> lk(mu);
+  publish();
 }
 
 extern "C" {
@@ -412,6 +496,7 @@ int ng_server_create(const ng_server_config* cfg, void* arena, uint64_t arena_by
   s->arena.init((char*)arena, arena_bytes);
   for (int i = 0; i < n_streams; ++i) s->streams.push_back((hipStream_t)streams[i]);
   s->stages.resize(n_streams);
+  s->inflight.resize(n_streams);
   const uint64_t B = cfg->block_size ? cfg->block_size : (1ull << 24);
   if (B & (B - 1) || B < (1ull << 16) || B > (1ull << 30)) {
     delete s;
@@ -437,10 +522,13 @@ int ng_server_destroy(ng_server* s) {
   s->thr.join();
   (void)hipSetDevice(s->device);
   for (hipStream_t st : s->streams) (void)hipStreamSynchronize(st);
-  for (ng_session* ss : s->sessions) {  // sessions never closed
-    ctx_destroy_release(ss->ctx);
-    delete ss;
+  for (auto* list : {&s->sessions, &s->new_sessions}) {  // sessions never closed
+    for (ng_session* ss : *list) {
+      ctx_destroy_release(ss->ctx);
+      delete ss;
+    }
   }
+  for (ng_session* ss : s->closed) delete ss;
   for (auto& kv : s->tickets) delete kv.second;
   for (auto& v : s->stages)
     for (auto& st : v) (void)hipHostFree(st.p);
@@ -465,7 +553,7 @@ int ng_session_open(ng_server* s, uint64_t seed, ng_session** out) {
   ss->ctx = c;
   ss->base_held = c->held;
   ss->stream = k;
-  s->sessions.push_back(ss);
+  s->new_sessions.push_back(ss);
   s->stats.sessions_opened++;
   *out = ss;
   return NG_OK;
@@ -483,11 +571,10 @@ static int submit(ng_session* ss, Request* r, uint64_t* ticket) {
     r->sess = ss;
     r->arrival_ns = now_ns(s->t0);
     if (r->kind == REQ_CLOSE) ss->close_submitted = true;
-    s->arrivals.push_back(r);
-    s->new_arrivals = true;
-    ss->queue.push_back(r);
+    s->incoming.push_back(r);
     s->tickets[r->ticket] = r;
     s->stats.submitted++;
+    ss->pending++;
     if (ticket) *ticket = r->ticket;
   }
   s->cv_work.notify_one();
@@ -567,7 +654,7 @@ int ng_wait(ng_server* s, uint64_t ticket, int64_t timeout_ns, ng_ticket_info* o
 int ng_session_context(ng_session* ss, ng_ctx** out) {
   if (!ss || !out) return fail(NG_ERR_INVALID_ARG, "null argument");
   std::lock_guard<std::mutex> lk(ss->server->mu);
-  if (!ss->queue.empty()) return fail(NG_ERR_STATE, "the session has requests not yet admitted");
+  if (ss->pending) return fail(NG_ERR_STATE, "the session has requests not yet finished");
   *out = ss->ctx;
   return NG_OK;
 }

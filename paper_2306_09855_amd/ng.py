@@ -89,7 +89,8 @@ class ng_ticket_info(ctypes.Structure):
 class ng_server_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in ("submitted", "launches", "packed_calls", "max_calls_per_launch",
                                                 "calibrations", "sessions_opened", "peak_arena_bytes",
-                                                "arena_used_bytes", "calibrate_packs", "max_sessions_per_pack")]
+                                                "arena_used_bytes", "calibrate_packs", "max_sessions_per_pack",
+                                                "scheduler_busy_ns", "host_launch_ns", "host_calibrate_ns")]
 
 
 _lib = None
