@@ -477,8 +477,8 @@ __global__ __launch_bounds__(kSortThreads) void k_upsweep(SortPack pk, uint32_t*
 }
 
 struct SortLds {
-  uint2* buf;                       // kTile staging words
-  uint32_t* key;                    // the same buffer seen as 32-bit words
+  uint32_t* key;                    // [kTile] keys staged by digit
+  uint2* pay;                       // [kTile] payloads staged by digit (LDS holds both: 120 KB)
   uint32_t* wh;                     // [kSortWaves][NB]: per-wave digit counts, then prefixes
   uint32_t* start;                  // [NB + 1] tile-local digit starts
   uint32_t* run;                    // [NB] next global position per digit
@@ -540,22 +540,21 @@ __device__ __forceinline__ void load_keys_any(const SortIO& io, uint64_t base, u
   else load_keys<IN_BLOCKED, false>(io, base, cnt, key);
 }
 
-// One tile of a digit pass, its keys already in registers.  FULL: all kTile
-// records present (no predicates).  RB bounds the digit width; digits are
-// masked to nbits, so the ballots for bits nbits..RB-1 see all-zero bits and
-// leave the peer masks unchanged.  The payloads load at the start and are
-// needed only after ranking; once they are staged in LDS, the keys of the
-// next tile (next_cnt > 0) load while this tile's payloads are stored.
+// One tile of a digit pass, its records in registers (the payloads possibly
+// still arriving).  FULL: all kTile records present (no predicates).  RB
+// bounds the digit width; digits are masked to nbits, so the ballots for bits
+// nbits..RB-1 see all-zero bits and leave the peer masks unchanged.  Keys are
+// staged by digit and stored, then payloads (the key registers are free by
+// then, so the keys of the next tile (next_cnt > 0) load while this tile's
+// payloads are stored).
 template <int RB, bool IN_BLOCKED, bool OUT_BLOCKED, bool FULL>
 __device__ __forceinline__ void sort_tile(const SortIO& io, uint64_t base, uint32_t cnt, uint32_t shift,
                                           uint32_t nbits, const SortLds& L, uint32_t (&key)[kItems],
-                                          uint64_t next_base, uint32_t next_cnt) {
+                                          uint2 (&pay)[kItems], uint64_t next_base, uint32_t next_cnt) {
   constexpr int NB = 1 << RB;
   const uint32_t nd = 1u << nbits, mask = nd - 1;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint64_t B = 1ull << io.log2B;
-  uint2 pay[kItems];
-  load_pays<IN_BLOCKED, FULL>(io, base, cnt, pay);
 
   // stable rank of each record among the earlier records of its digit
   uint32_t pos[kItems];
@@ -643,7 +642,7 @@ __device__ __forceinline__ void sort_tile(const SortIO& io, uint64_t base, uint3
 #pragma unroll
   for (int k = 0; k < kItems; ++k) {
     const uint32_t lj = (uint32_t)(wave * kItems * 64 + k * 64 + lane);
-    if (FULL || lj < cnt) L.buf[pos[k]] = pay[k];
+    if (FULL || lj < cnt) L.pay[pos[k]] = pay[k];
   }
   for (uint32_t d = threadIdx.x; d < nd; d += kSortThreads) {
     L.run[d] += L.start[d + 1] - L.start[d];
@@ -656,7 +655,7 @@ __device__ __forceinline__ void sort_tile(const SortIO& io, uint64_t base, uint3
   for (int k = 0; k < kItems; ++k) {
     const uint32_t lp = (uint32_t)(k * kSortThreads + threadIdx.x);
     if (FULL || lp < cnt) {
-      const uint2 pp = L.buf[lp];
+      const uint2 pp = L.pay[lp];
       if constexpr (OUT_BLOCKED) {
         char* blk = G(io.out_blocks)[dest[k] >> io.log2B];
         const uint64_t o = dest[k] & (B - 1);
@@ -673,12 +672,13 @@ __device__ __forceinline__ void sort_tile(const SortIO& io, uint64_t base, uint3
 template <int RB, bool IN_BLOCKED, bool OUT_BLOCKED>
 __global__ __launch_bounds__(kSortThreads) void k_downsweep(SortPack pk, const uint32_t* __restrict__ offsets) {
   constexpr int NB = 1 << RB;
-  __shared__ uint2 s_buf[kTile];
+  __shared__ uint32_t s_key[kTile];
+  __shared__ uint2 s_pay[kTile];
   __shared__ uint32_t s_wh[kSortWaves * NB];
   __shared__ uint32_t s_start[NB + 1];
   __shared__ uint32_t s_run[NB];
   __shared__ uint32_t s_tmp[kSortWaves];
-  const SortLds L{s_buf, reinterpret_cast<uint32_t*>(s_buf), s_wh, s_start, s_run, s_tmp};
+  const SortLds L{s_key, s_pay, s_wh, s_start, s_run, s_tmp};
   const int gr = range_index(pk);
   if (gr < 0) return;
   const SortSeg sg = sort_seg(pk, (uint32_t)gr);
@@ -691,18 +691,24 @@ __global__ __launch_bounds__(kSortThreads) void k_downsweep(SortPack pk, const u
   }
   lds_barrier();
   const RangeTiles rt = range_tiles(sg, r);
+  // the keys of each tile are loaded while the tile before it stores its
+  // payloads; the payloads load at the start of their tile and are first
+  // needed after the ranking
   uint32_t key[kItems];
-  if (rt.n_full) load_keys<IN_BLOCKED, true>(sg.io, rt.start, kTile, key);
-  else load_keys<IN_BLOCKED, false>(sg.io, rt.start, rt.tail, key);
+  uint2 pay[kItems];
+  load_keys_any<IN_BLOCKED>(sg.io, rt.start, rt.n_full ? (uint32_t)kTile : rt.tail, key);
   for (uint32_t t = 0; t < rt.n_full; ++t) {
     const uint32_t base = rt.start + t * (uint32_t)kTile;
     const uint32_t next_cnt = t + 1 < rt.n_full ? (uint32_t)kTile : rt.tail;
-    sort_tile<RB, IN_BLOCKED, OUT_BLOCKED, true>(sg.io, base, kTile, shift, nbits, L, key, base + (uint32_t)kTile,
-                                                 next_cnt);
+    load_pays<IN_BLOCKED, true>(sg.io, base, kTile, pay);
+    sort_tile<RB, IN_BLOCKED, OUT_BLOCKED, true>(sg.io, base, kTile, shift, nbits, L, key, pay,
+                                                 base + (uint32_t)kTile, next_cnt);
   }
-  if (rt.tail)
-    sort_tile<RB, IN_BLOCKED, OUT_BLOCKED, false>(sg.io, rt.start + rt.n_full * (uint32_t)kTile, rt.tail, shift,
-                                                  nbits, L, key, 0, 0u);
+  if (rt.tail) {
+    const uint32_t base = rt.start + rt.n_full * (uint32_t)kTile;
+    load_pays<IN_BLOCKED, false>(sg.io, base, rt.tail, pay);
+    sort_tile<RB, IN_BLOCKED, OUT_BLOCKED, false>(sg.io, base, rt.tail, shift, nbits, L, key, pay, 0, 0u);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -806,10 +812,10 @@ __global__ __launch_bounds__(kThreads) void k_group_flags(GiPack pk, uint32_t* _
   __shared__ uint32_t s_tmp[kWaves];
   const GiSeg sg = gi_seg(pk, pk.seg_of_tile, blockIdx.x);
   const int log2B = pk.log2B;
-  const uint64_t n = sg.n;
+  const uint32_t n = (uint32_t)sg.n;  // a segment holds < 2^32 connections
   char* const* blocks = sg.blocks;
   NG_GLOBAL uint32_t* bitmap = G(sg.bitmap);
-  const uint64_t base = (uint64_t)(blockIdx.x - sg.tile0) * kGiTile;
+  const uint32_t base = (blockIdx.x - sg.tile0) * (uint32_t)kGiTile;
   const uint64_t B = 1ull << log2B;
   const char* blk = C(blocks, base >> log2B);  // kGiTile divides the block size
   const uint64_t o0 = base & (B - 1);
@@ -817,25 +823,60 @@ __global__ __launch_bounds__(kThreads) void k_group_flags(GiPack pk, uint32_t* _
   const NG_GLOBAL int16_t* del = G(reinterpret_cast<const int16_t*>(blk + 12 * B)) + o0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t c = 0;
+  if (n - base >= (uint32_t)kGiTile) {
+    // A full tile: each lane takes 4 consecutive positions per item with
+    // 16-byte (source) and 8-byte (delay) loads; the position before a
+    // lane's first is the last of the lane below (a shuffle), or for lane 0
+    // one more load.  A bitmap word is the flags of 8 lanes, gathered by
+    // three xor-shuffles.
+    static_assert(kGiItems % 4 == 0, "4 positions per lane");
+#pragma unroll 2
+    for (int v = 0; v < kGiItems / 4; ++v) {
+      const uint32_t lj = 4u * (uint32_t)(v * kThreads + threadIdx.x);
+      const u32x4 s4 = *(const NG_GLOBAL u32x4*)(src + lj);
+      const u32x2 d4 = *(const NG_GLOBAL u32x2*)(del + lj);
+      const uint32_t d0 = d4.x & 0xFFFFu, d1 = d4.x >> 16, d2 = d4.y & 0xFFFFu, d3 = d4.y >> 16;
+      uint32_t ps = __shfl_up(s4.w, 1), pd = __shfl_up(d3, 1);
+      if (lane == 0) {
+        const uint32_t j = base + lj;
+        if (j > 0) {
+          const uint64_t k = group_key(blocks, log2B, j - 1);
+          ps = (uint32_t)(k >> 16);
+          pd = (uint32_t)(k & 0xFFFFu);
+        } else {
+          ps = ~s4.x;  // position 0 opens a group
+        }
+      }
+      const uint32_t nib = ((s4.x != ps) | (d0 != pd) ? 1u : 0u) | ((s4.y != s4.x) | (d1 != d0) ? 2u : 0u) |
+                           ((s4.z != s4.y) | (d2 != d1) ? 4u : 0u) | ((s4.w != s4.z) | (d3 != d2) ? 8u : 0u);
+      c += (uint32_t)__popc(nib);
+      uint32_t w = nib << (4 * (lane & 7));
+      w |= __shfl_xor(w, 1);
+      w |= __shfl_xor(w, 2);
+      w |= __shfl_xor(w, 4);
+      if ((lane & 7) == 0) bitmap[(base + lj) >> 5] = w;
+    }
+  } else {
 #pragma unroll 8
-  for (int k = 0; k < kGiItems; ++k) {
-    const uint32_t lj = k * kThreads + threadIdx.x;  // 64 consecutive positions per wave
-    const uint64_t j = base + lj;
-    bool f = false;
-    if (j < n) {
-      const uint64_t key = ((uint64_t)src[lj] << 16) | (uint16_t)del[lj];
-      uint64_t prev;
-      if (lj > 0) prev = ((uint64_t)src[lj - 1] << 16) | (uint16_t)del[lj - 1];
-      else prev = j > 0 ? group_key(blocks, log2B, j - 1) : ~0ull;
-      f = key != prev;
+    for (int k = 0; k < kGiItems; ++k) {
+      const uint32_t lj = k * kThreads + threadIdx.x;  // 64 consecutive positions per wave
+      const uint32_t j = base + lj;
+      bool f = false;
+      if (j < n) {
+        const uint64_t key = ((uint64_t)src[lj] << 16) | (uint16_t)del[lj];
+        uint64_t prev;
+        if (lj > 0) prev = ((uint64_t)src[lj - 1] << 16) | (uint16_t)del[lj - 1];
+        else prev = j > 0 ? group_key(blocks, log2B, j - 1) : ~0ull;
+        f = key != prev;
+      }
+      const uint64_t m = __ballot(f);
+      if (lane == 0) {
+        const uint32_t w = (base + k * kThreads + wave * 64) >> 5;  // two bitmap words
+        if ((w << 5) < n) bitmap[w] = (uint32_t)m;
+        if (((w + 1) << 5) < n) bitmap[w + 1] = (uint32_t)(m >> 32);
+      }
+      c += f ? 1u : 0u;
     }
-    const uint64_t m = __ballot(f);
-    if (lane == 0) {
-      const uint64_t w = (base + k * kThreads + wave * 64) >> 5;  // two bitmap words
-      if ((w << 5) < n) bitmap[w] = (uint32_t)m;
-      if (((w + 1) << 5) < n) bitmap[w + 1] = (uint32_t)(m >> 32);
-    }
-    c += f ? 1u : 0u;
   }
   uint32_t total;
   block_exclusive_scan(c, s_tmp, &total);
