@@ -210,23 +210,82 @@ __device__ __forceinline__ void store_one(char* const* __restrict__ blocks, int 
   G(reinterpret_cast<int16_t*>(base + 12 * B))[o] = (int16_t)dl;
 }
 
+// The aligned 4-record chunk that starts s records into this lane's quad:
+// [a[4-s..3], b[0..3-s]] (1 <= s <= 3), selected by value (a select between
+// array elements would put the arrays in scratch memory).
+struct Chunk4 {
+  uint32_t v[4];
+};
+__device__ __forceinline__ Chunk4 chunk_of(const uint32_t (&a)[4], const uint32_t (&b)[4], uint32_t s) {
+  const uint32_t a1 = a[1], a2 = a[2], a3 = a[3], b0 = b[0], b1 = b[1], b2 = b[2];
+  Chunk4 c;
+  c.v[0] = s == 1 ? a3 : (s == 2 ? a2 : a1);
+  c.v[1] = s == 1 ? b0 : (s == 2 ? a3 : a2);
+  c.v[2] = s == 1 ? b1 : (s == 2 ? b0 : a3);
+  c.v[3] = s == 1 ? b2 : (s == 2 ? b1 : b0);
+  return c;
+}
+
+// Store the quad of records p0..p0+nvalid-1.  A quad whose first position is
+// a multiple of 4 goes out as 16-byte (8-byte for delays) stores.  A call
+// whose first position is not leaves every quad misaligned by s = p0 mod 4;
+// then each lane stores the aligned chunk that starts inside its quad,
+// completed with the first 4-s records of the lane above (a shuffle), when
+// that lane holds the next records of the same block table.  Records no
+// aligned chunk covers (a wave's or a call's edges) go out one by one.  Every
+// active lane of the wave must call this together.
 __device__ __forceinline__ void store_quad(char* const* __restrict__ blocks, int log2B, uint64_t p0,
                                            uint32_t nvalid, const Quad& q) {
-  if (nvalid == 4 && (p0 & 3) == 0) {
-    const uint64_t B = 1ull << log2B;
+  const uint64_t B = 1ull << log2B;
+  const int lane = threadIdx.x & 63;
+  const uint64_t active = __ballot(1);
+  const uint32_t s = (uint32_t)p0 & 3u;
+  uint32_t w[4], dl[4], sn[4], tn[4], wn[4], dn[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    w[r] = __float_as_uint(q.w[r]);
+    dl[r] = (uint32_t)q.d[r] & 0xFFFFu;
+    sn[r] = __shfl_down(q.s[r], 1);
+    tn[r] = __shfl_down(q.t[r], 1);
+    wn[r] = __shfl_down(w[r], 1);
+    dn[r] = __shfl_down(dl[r], 1);
+  }
+  const uint64_t p0n = ((uint64_t)__shfl_down((uint32_t)(p0 >> 32), 1) << 32) | __shfl_down((uint32_t)p0, 1);
+  const uint32_t nvn = __shfl_down(nvalid, 1);
+  const uint64_t tab = (uint64_t)blocks;
+  const uint64_t tabn = ((uint64_t)__shfl_down((uint32_t)(tab >> 32), 1) << 32) | __shfl_down((uint32_t)tab, 1);
+  const bool next_active = lane < 63 && ((active >> ((lane + 1) & 63)) & 1ull);
+  const bool chunk = s != 0 && next_active && p0n == p0 + 4 && tabn == tab && nvalid == 4 && nvn >= 4 - s;
+  const bool head_done = __shfl_up(chunk ? 1u : 0u, 1) != 0u && lane > 0 && ((active >> ((lane - 1) & 63)) & 1ull);
+
+  if (s == 0 && nvalid == 4) {
     char* base = G(blocks)[p0 >> log2B];
     const uint64_t o = p0 & (B - 1);
     st_u32x4(base + 4 * o, q.s[0], q.s[1], q.s[2], q.s[3]);
     st_u32x4(base + 4 * B + 4 * o, q.t[0], q.t[1], q.t[2], q.t[3]);
-    st_u32x4(base + 8 * B + 4 * o, __float_as_uint(q.w[0]), __float_as_uint(q.w[1]), __float_as_uint(q.w[2]),
-             __float_as_uint(q.w[3]));
-    const uint32_t d01 = ((uint32_t)q.d[0] & 0xFFFFu) | ((uint32_t)q.d[1] << 16);
-    const uint32_t d23 = ((uint32_t)q.d[2] & 0xFFFFu) | ((uint32_t)q.d[3] << 16);
-    st_u32x2(base + 12 * B + 2 * o, d01, d23);
-  } else {
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-      if ((uint32_t)r < nvalid) store_one(blocks, log2B, p0 + r, q.s[r], q.t[r], q.w[r], q.d[r]);
+    st_u32x4(base + 8 * B + 4 * o, w[0], w[1], w[2], w[3]);
+    st_u32x2(base + 12 * B + 2 * o, dl[0] | (dl[1] << 16), dl[2] | (dl[3] << 16));
+    return;
+  }
+  const uint32_t head = s == 0 ? 4u : 4u - s;  // records before the first aligned chunk boundary
+  auto single = [&](uint32_t r, uint32_t sv, uint32_t tv, float wv, int32_t dv) {
+    const bool covered = r < head ? head_done : chunk;
+    if (r < nvalid && !covered) store_one(blocks, log2B, p0 + r, sv, tv, wv, dv);
+  };
+  single(0, q.s[0], q.t[0], q.w[0], q.d[0]);
+  single(1, q.s[1], q.t[1], q.w[1], q.d[1]);
+  single(2, q.s[2], q.t[2], q.w[2], q.d[2]);
+  single(3, q.s[3], q.t[3], q.w[3], q.d[3]);
+  if (chunk) {
+    const uint64_t pc = p0 + 4 - s;  // a multiple of 4: one block holds the chunk
+    char* base = G(blocks)[pc >> log2B];
+    const uint64_t o = pc & (B - 1);
+    const Chunk4 cs = chunk_of(q.s, sn, s), ct = chunk_of(q.t, tn, s), cw = chunk_of(w, wn, s),
+                 cd = chunk_of(dl, dn, s);
+    st_u32x4(base + 4 * o, cs.v[0], cs.v[1], cs.v[2], cs.v[3]);
+    st_u32x4(base + 4 * B + 4 * o, ct.v[0], ct.v[1], ct.v[2], ct.v[3]);
+    st_u32x4(base + 8 * B + 4 * o, cw.v[0], cw.v[1], cw.v[2], cw.v[3]);
+    st_u32x2(base + 12 * B + 2 * o, cd.v[0] | (cd.v[1] << 16), cd.v[2] | (cd.v[3] << 16));
   }
 }
 
