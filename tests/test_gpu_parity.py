@@ -132,6 +132,33 @@ def test_edge_cases():
         assert gp.tolist() == [0, 1] and gs.tolist() == [0, 1]
 
 
+@pytest.mark.parametrize("batched", [False, True])
+def test_misaligned_calls(batched):
+    # Calls of every size mod 4 leave every start position mod 4 in turn, so
+    # generation stores aligned chunks assembled across lanes, across calls
+    # (batched) and around wave and call edges; the calls cross several
+    # 2^16-connection blocks.
+    rng = np.random.default_rng(77)
+    n = 3000
+    calls = []
+    for i in range(60):
+        size = int(rng.integers(1, 9)) if i % 3 else int(rng.integers(3000, 9000))
+        rule = ("fixed_total_number", "fixed_indegree", "one_to_one", "all_to_all", "fixed_outdegree")[i % 5]
+        if rule == "fixed_total_number":
+            calls.append(W.Call(rule, (0, n), (0, n), size))
+        elif rule == "fixed_indegree":
+            calls.append(W.Call(rule, (0, n), (int(rng.integers(0, n - 3)), 3), size))
+        elif rule == "fixed_outdegree":
+            calls.append(W.Call(rule, (int(rng.integers(0, n - 2)), 2), (0, n), size))
+        elif rule == "one_to_one":
+            k = min(size, n)
+            calls.append(W.Call(rule, (0, k), (n - k, k)))
+        else:
+            calls.append(W.Call(rule, (0, min(size, n)), (0, 1 + i % 7)))
+    wl = W.Workload("misaligned", 4321, [n], calls)
+    _check_all(wl, block_size=1 << 16, batched=batched)
+
+
 def test_connect_after_calibrate():
     # calibrate; connect more; calibrate == one calibration at the end
     wl = W.microcircuit(scale=0.02)
