@@ -108,6 +108,14 @@ hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, uint64_t n, 
 // tab[first + k] = ptrs[k] for k < count <= 8
 hipError_t launch_set_ptrs(char** tab, uint32_t first, uint32_t count, const uint64_t* ptrs,
                            hipStream_t s);
+// Block-table entries of several contexts in one launch: e[i].tab[e[i].idx] = e[i].ptr.
+struct TabEntry {
+  char** tab;
+  char* ptr;
+  uint32_t idx;
+  uint32_t pad;
+};
+hipError_t launch_set_entries(const TabEntry* d_entries, uint32_t n, hipStream_t s);
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, uint64_t n, hipStream_t s);
 

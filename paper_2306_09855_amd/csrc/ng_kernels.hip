@@ -317,26 +317,52 @@ __device__ __forceinline__ void gen_any(const GenDesc& d, uint32_t g, uint32_t k
   }
 }
 
-// Batched form: a grid-stride loop over the 4-synapse groups of all calls;
-// each lane finds its call by binary search over the calls' first groups.
+// Batched form: a grid-stride loop over the 4-synapse groups of all calls.
+// A wave covers 64 consecutive groups; it finds the call of its first group
+// once (scalar loads) and, when all 64 lie in that call -- nearly always --
+// runs with the descriptor in scalar registers and a uniform rule.  A wave
+// that straddles calls looks each lane's call up by binary search.
 __global__ __launch_bounds__(kGenThreads) void k_generate_batch(const GenDesc* __restrict__ descs,
                                                                 uint32_t n_calls, uint64_t total_groups,
                                                                 int log2B) {
-  for (uint64_t gg = (uint64_t)blockIdx.x * kGenThreads + threadIdx.x; gg < total_groups;
-       gg += (uint64_t)gridDim.x * kGenThreads) {
-    uint32_t lo = 0, hi = n_calls - 1;
-    while (lo < hi) {  // last call with group0 <= gg
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform by construction
+  for (uint64_t wbase = (uint64_t)blockIdx.x * kGenThreads + 64u * wave; wbase < total_groups;
+       wbase += (uint64_t)gridDim.x * kGenThreads) {
+    const uint64_t gg = wbase + lane;
+    const uint64_t wlast = min(wbase + 63, total_groups - 1);
+    uint32_t lo = 0, hi = n_calls - 1;  // last call with group0 <= wbase (uniform)
+    while (lo < hi) {
       const uint32_t mid = (lo + hi + 1) >> 1;
-      if (descs[mid].group0 <= gg) lo = mid; else hi = mid - 1;
+      if (C(&descs[mid].group0, 0) <= wbase) lo = mid; else hi = mid - 1;
     }
-    const GenDesc d = descs[lo];
-    const uint32_t key0 = G(d.key)[0], key1 = G(d.key)[1];
-    const uint32_t g = (uint32_t)(gg - d.group0);
-    Quad q;
-    if (d.d_kind == D_CONST) gen_any<false>(d, g, key0, key1, q);
-    else gen_any<true>(d, g, key0, key1, q);
-    const uint32_t i0 = g << 2;
-    store_quad(d.blocks, log2B, d.pos0 + i0, min(4u, d.n_new - i0), q);
+    const bool one_call = lo + 1 >= n_calls || C(&descs[lo + 1].group0, 0) > wlast;
+    if (one_call) {
+      const GenDesc d = C_struct(descs, lo);
+      if (gg < total_groups) {
+        const uint32_t key0 = C(d.key, 0), key1 = C(d.key, 1);
+        const uint32_t g = (uint32_t)(gg - d.group0);
+        Quad q;
+        if (d.d_kind == D_CONST) gen_any<false>(d, g, key0, key1, q);
+        else gen_any<true>(d, g, key0, key1, q);
+        const uint32_t i0 = g << 2;
+        store_quad(d.blocks, log2B, d.pos0 + i0, min(4u, d.n_new - i0), q);
+      }
+    } else if (gg < total_groups) {
+      uint32_t l = lo, h = n_calls - 1;  // this lane's call
+      while (l < h) {
+        const uint32_t mid = (l + h + 1) >> 1;
+        if (descs[mid].group0 <= gg) l = mid; else h = mid - 1;
+      }
+      const GenDesc d = descs[l];
+      const uint32_t key0 = G(d.key)[0], key1 = G(d.key)[1];
+      const uint32_t g = (uint32_t)(gg - d.group0);
+      Quad q;
+      if (d.d_kind == D_CONST) gen_any<false>(d, g, key0, key1, q);
+      else gen_any<true>(d, g, key0, key1, q);
+      const uint32_t i0 = g << 2;
+      store_quad(d.blocks, log2B, d.pos0 + i0, min(4u, d.n_new - i0), q);
+    }
   }
 }
 
@@ -828,6 +854,14 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(const uint32_t* in, uint
   }
 }
 
+__global__ __launch_bounds__(256) void k_set_entries(const TabEntry* __restrict__ e, uint32_t n) {
+  const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) {
+    const TabEntry t = e[i];
+    G(t.tab)[t.idx] = t.ptr;
+  }
+}
+
 __global__ void k_set_ptrs(char** tab, uint32_t first, uint32_t count, uint64_t p0, uint64_t p1,
                            uint64_t p2, uint64_t p3, uint64_t p4, uint64_t p5, uint64_t p6,
                            uint64_t p7) {
@@ -943,24 +977,68 @@ __global__ __launch_bounds__(kThreads) void k_group_flags(GiPack pk, uint32_t* _
 }
 
 // group_start[g]: first connection of group g; group_src[g]: its source.
+// Each wave takes 2,048 consecutive positions, one bitmap word per lane, and
+// writes its groups in one of two orders. Sparse groups go lane by lane:
+// each lane walks its own word's bits, as many rounds as the largest word
+// count; a round's addresses are consecutive only where lanes hold one group
+// each. Dense groups go 64 positions at a time, the flagged lanes taking
+// consecutive group numbers: one fully coalesced round per 64 positions that
+// hold a group. A lane-by-lane round is priced at four of those.
 __global__ __launch_bounds__(kThreads) void k_group_write(GiPack pk, const uint32_t* __restrict__ tile_base) {
-  __shared__ uint32_t s_tmp[kWaves];
+  static_assert(kGiTile == kWaves * 64 * 32, "one bitmap word per lane");
+  __shared__ uint32_t s_cnt[kWaves];
   const GiSeg sg = gi_seg(pk, pk.seg_of_tile, blockIdx.x);
-  const uint64_t n = sg.n;
-  const uint64_t wbase = (uint64_t)(blockIdx.x - sg.tile0) * kThreads + threadIdx.x;  // bitmap word
-  const uint64_t j0 = wbase << 5;
-  uint32_t bits = j0 < n ? G(sg.bitmap)[wbase] : 0u;
-  if (j0 < n && n - j0 < 32) bits &= (1u << (n - j0)) - 1;
-  uint32_t total;
-  uint32_t g = tile_base[blockIdx.x] - tile_base[sg.tile0] +
-               block_exclusive_scan((uint32_t)__popc(bits), s_tmp, &total);
-  while (bits) {
-    const int b = __ffs(bits) - 1;
-    bits &= bits - 1;
-    const uint64_t j = j0 + b;
-    G(sg.group_start)[g] = (uint32_t)j;
-    G(sg.group_src)[g] = (uint32_t)(group_key(sg.blocks, pk.log2B, j) >> 16);
-    ++g;
+  const uint32_t n = (uint32_t)sg.n;
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t base = (blockIdx.x - sg.tile0) * (uint32_t)kGiTile;
+  const uint32_t wi = ((base + wave * 2048u) >> 5) + lane;  // this lane's bitmap word
+  uint32_t bits = 0;
+  if (wi * 32u < n) {
+    bits = G(sg.bitmap)[wi];
+    if (n - wi * 32u < 32u) bits &= (1u << (n - wi * 32u)) - 1u;
+  }
+  const uint32_t pc = (uint32_t)__popc(bits);
+  uint32_t incl = pc, mx = pc;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(incl, o);
+    if (lane >= (uint32_t)o) incl += t;
+    mx = max(mx, (uint32_t)__shfl_xor(mx, o));
+  }
+  if (lane == 63) s_cnt[wave] = incl;
+  __syncthreads();
+  uint32_t g = tile_base[blockIdx.x] - tile_base[sg.tile0];
+  for (uint32_t w = 0; w < wave; ++w) g += s_cnt[w];
+  const uint64_t B = 1ull << pk.log2B;
+  const char* blk = C(sg.blocks, base >> pk.log2B);  // kGiTile divides the block size
+  const NG_GLOBAL uint32_t* src = G(reinterpret_cast<const uint32_t*>(blk)) + (base & (B - 1)) + wave * 2048u;
+  NG_GLOBAL uint32_t* gstart = G(sg.group_start);
+  NG_GLOBAL uint32_t* gsrc = G(sg.group_src);
+  const uint32_t p0 = base + wave * 2048u;  // first position of this wave
+  const uint64_t nz = __ballot(bits != 0);
+  uint64_t chunks = (nz | (nz >> 1)) & 0x5555555555555555ull;  // bit 2i: positions 64i.. hold a group
+  if (4u * __builtin_amdgcn_readfirstlane(mx) <= (uint32_t)__popcll(chunks)) {
+    uint32_t gl = g + incl - pc;
+    while (bits) {
+      const uint32_t j = 32u * lane + (uint32_t)(__ffs(bits) - 1);
+      bits &= bits - 1;
+      gstart[gl] = p0 + j;
+      gsrc[gl] = src[j];
+      ++gl;
+    }
+    return;
+  }
+  while (chunks) {
+    const uint32_t i = (uint32_t)(__ffsll((unsigned long long)chunks) - 1) >> 1;
+    chunks &= chunks - 1;
+    const uint32_t lo = __builtin_amdgcn_readlane(bits, 2 * i), hi = __builtin_amdgcn_readlane(bits, 2 * i + 1);
+    const uint64_t m = ((uint64_t)hi << 32) | lo;
+    if ((m >> lane) & 1ull) {
+      const uint32_t below = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
+      gstart[g + below] = p0 + 64u * i + lane;
+      gsrc[g + below] = src[64u * i + lane];
+    }
+    g += (uint32_t)__popcll(m);
   }
 }
 
@@ -1087,6 +1165,12 @@ hipError_t launch_set_ptrs(char** tab, uint32_t first, uint32_t count, const uin
                            hipStream_t s) {
   hipLaunchKernelGGL(k_set_ptrs, dim3(1), dim3(64), 0, s, tab, first, count, v[0], v[1], v[2], v[3],
                      v[4], v[5], v[6], v[7]);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_entries(const TabEntry* d_entries, uint32_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_set_entries, dim3((n + 255) / 256), dim3(256), 0, s, d_entries, n);
   return hipGetLastError();
 }
 

@@ -61,7 +61,8 @@ class Arena {
   void release_after(hipStream_t stream, Ranges&& ranges, hipEvent_t ev) {
     std::lock_guard<std::mutex> lk(mu_);
     uint64_t b = 0;
-    for (auto& r : ranges) b += round_up(r.second ? r.second : 1);
+    for (auto& r : ranges)
+      if (r.first) b += round_up(r.second ? r.second : 1);
     deferred_[stream].push_back({std::move(ranges), ev, b});
     deferred_bytes_ += b;
   }
@@ -181,6 +182,7 @@ struct ng_ctx {
   std::vector<char*> blocks;      // current storage, host copy of the device table
   char** d_tab[2] = {nullptr, nullptr};
   int cur = 0;                    // d_tab[cur] describes `blocks`
+  uint32_t tab_synced = 0;        // leading entries of d_tab[cur] written on the device
   uint32_t tab_cap = 0;
 
   bool calibrated = false;
@@ -266,6 +268,12 @@ hipError_t set_seed(ng_ctx* c, uint64_t seed);
 int mutable_state(ng_ctx* c);
 int not_capturing(ng_ctx* c);
 int reserve_blocks(ng_ctx* c, uint64_t n_new);
+// Write the block-table entries not yet on the device (kernel arguments, on
+// the context's stream); every launch that reads d_tab[cur] comes after.
+int sync_table(ng_ctx* c);
+// Hand the unwritten entries to a caller that writes many contexts' entries
+// in one launch (marks them written).
+void take_table_entries(ng_ctx* c, std::vector<ng::TabEntry>& out);
 void release_index(ng_ctx* c);
 // Return memory to the context's arena.  With a shared arena the range is
 // collected and handed back by ctx_flush_frees, behind one event recorded on

@@ -247,10 +247,22 @@ int reserve_blocks(ng_ctx* c, uint64_t n_new) {
     }
     fresh.push_back(p);
   }
-  const uint32_t first = (uint32_t)c->blocks.size();
-  for (char* p : fresh) c->blocks.push_back(p);
-  if (!fresh.empty()) NG_HIP(c, set_table(c->d_tab[c->cur], first, c->blocks, first, c->stream), "block table");
+  for (char* p : fresh) c->blocks.push_back(p);  // written to the device table by sync_table
   return NG_OK;
+}
+
+int sync_table(ng_ctx* c) {
+  if (c->tab_synced < c->blocks.size()) {
+    NG_HIP(c, set_table(c->d_tab[c->cur], c->tab_synced, c->blocks, c->tab_synced, c->stream), "block table");
+    c->tab_synced = (uint32_t)c->blocks.size();
+  }
+  return NG_OK;
+}
+
+void take_table_entries(ng_ctx* c, std::vector<ng::TabEntry>& out) {
+  for (uint32_t i = c->tab_synced; i < c->blocks.size(); ++i)
+    out.push_back(ng::TabEntry{c->d_tab[c->cur], c->blocks[i], i, 0});
+  c->tab_synced = (uint32_t)c->blocks.size();
 }
 
 void release_index(ng_ctx* c) {
@@ -607,6 +619,11 @@ int calibrate_many(ng_ctx* const* cs, uint32_t n, const Uploader* upload) {
   if (total_tiles >= 0xFFFFFFFFull || total_ptr_blocks >= 0xFFFFFFFFull)
     return fail(NG_ERR_TOO_LARGE, "too many index tiles");
   tables += align256(sizeof(ng::GiSeg) * segs.size()) + align256(4 * total_tiles) + align256(4 * total_ptr_blocks);
+  // block-table entries, written by one launch: the unwritten ones of each
+  // current table (pass 0 reads it) and every one of each new table
+  uint64_t n_entries = 0;
+  for (auto& g : segs) n_entries += (g.c->blocks.size() - g.c->tab_synced) + (g.N + g.c->B - 1) / g.c->B;
+  tables += align256(sizeof(ng::TabEntry) * n_entries);
   if (!multi) tables = 0;
 
   // allocation: per-context buffers, then the shared scratch from the first
@@ -735,6 +752,21 @@ int calibrate_many(ng_ctx* const* cs, uint32_t n, const Uploader* upload) {
     gp.total_ptr_blocks = pb0;
     gp.log2B = c0->log2B;
   }
+  const ng::TabEntry* d_entries = nullptr;
+  std::vector<uint32_t> synced_before;
+  for (auto& g : segs) synced_before.push_back(g.c->tab_synced);
+  if (multi) {
+    std::vector<ng::TabEntry> entries;
+    for (auto& g : segs) {
+      take_table_entries(g.c, entries);
+      for (uint32_t b = 0; b < g.nblocks.size(); ++b)
+        entries.push_back(ng::TabEntry{g.c->d_tab[g.nxt], g.nblocks[b], b, 0});
+    }
+    memcpy(h_tables.data() + toff, entries.data(), sizeof(ng::TabEntry) * entries.size());
+    d_entries = reinterpret_cast<const ng::TabEntry*>(d_tables + toff);
+    toff += align256(sizeof(ng::TabEntry) * entries.size());
+    n_entries = entries.size();
+  }
 
   // launches, all on the first context's stream
   hipStream_t s = c0->stream;
@@ -751,12 +783,18 @@ int calibrate_many(ng_ctx* const* cs, uint32_t n, const Uploader* upload) {
                   : stage_upload(c0, d_tables, h_tables.data(), tables);
     if (rc != NG_OK) {  // nothing has used the new buffers yet
       shared.release_all();
+      for (size_t k = 0; k < segs.size(); ++k) segs[k].c->tab_synced = synced_before[k];
       for (auto& g : segs) cal_release(g);
       return rc == NG_ERR_DEVICE || rc == NG_ERR_OOM ? rc : fail(rc, "packed calibration upload failed");
     }
   }
   auto run = [&]() -> int {
-    for (auto& g : segs) NG_HIP(c0, set_table(g.c->d_tab[g.nxt], 0, g.nblocks, 0, s), "block table");
+    if (multi) {
+      NG_HIP(c0, ng::launch_set_entries(d_entries, (uint32_t)n_entries, s), "block tables");
+    } else {
+      if (int rc = sync_table(c0)) return rc;
+      NG_HIP(c0, set_table(c0->d_tab[segs[0].nxt], 0, segs[0].nblocks, 0, s), "block table");
+    }
     for (auto& pl : launches)
       for (int p = 0; p < pl.passes; ++p) {
         NG_LAUNCH(c0, "upsweep", ng::launch_upsweep(pl.pass[p], counts, s));
@@ -792,6 +830,7 @@ int calibrate_many(ng_ctx* const* cs, uint32_t n, const Uploader* upload) {
     const size_t nblk = g.nblocks.size();
     for (size_t i = nblk; i < g.as->items.size(); ++i) ctx_free(c, g.as->items[i].first, g.as->items[i].second);
     c->blocks = g.nblocks;
+    c->tab_synced = (uint32_t)g.nblocks.size();  // the new table was written above
     c->cur = g.nxt;
     c->d_group_ptr = g.gptr;
     c->group_ptr_bytes = g.gp_bytes;
@@ -869,6 +908,7 @@ int ng_connect(ng_ctx* c, ng_range src, ng_range tgt, const ng_conn_spec* conn, 
   ng::GenDesc d;
   uint64_t n = 0;
   if (int rc = connect_prepare(c, src, tgt, conn, syn, &d, &n)) return rc;
+  if (int rc = sync_table(c)) return rc;
   if (n) NG_LAUNCH(c, "generate", ng::launch_generate(d, key_ptr(c), c->d_tab[c->cur], c->log2B, c->stream));
   if (out_cid) *out_cid = d.cid;
   if (out_first) *out_first = d.pos0;
@@ -927,6 +967,7 @@ int ng_connect_batch(ng_ctx* c, uint32_t n_calls, const ng_range* src, const ng_
       return rc;
     }
   }
+  if (int rc = sync_table(c)) return rc;
   if (!descs.empty()) {
     NG_LAUNCH(c, "generate_batch",
               ng::launch_generate_batch((const ng::GenDesc*)d_descs, (uint32_t)descs.size(), groups,
@@ -960,6 +1001,7 @@ int ng_reset(ng_ctx* c) {
   if (int rc = mutable_state(c)) return rc;
   for (char* b : c->blocks) ctx_free(c, b, ng::kBytesPerConn * c->B);
   c->blocks.clear();
+  c->tab_synced = 0;
   release_index(c);
   c->n_nodes = 0;
   c->next_cid = 0;

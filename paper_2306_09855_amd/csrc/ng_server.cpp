@@ -329,21 +329,59 @@ void ng_server::run() {
       ng::GenDesc* d_descs = nullptr;
       uint64_t nb = 0;
       int rc = check_descs(descs[k]);
-      if (rc == NG_OK) rc = stage_upload(k, descs[k], &d_descs, &nb);
+      // the sessions' new block-table entries, all written by one launch
+      // (or, without arena room for the list, by each context's own)
+      std::vector<ng::TabEntry> entries;
+      std::vector<std::pair<ng_ctx*, uint32_t>> synced;
+      for (Request* r : packed[k]) {
+        ng_ctx* c = r->sess->ctx;
+        if (c->tab_synced < c->blocks.size()) {
+          synced.emplace_back(c, c->tab_synced);
+          take_table_entries(c, entries);
+        }
+      }
+      char* d_ent = nullptr;
+      const uint64_t ne = entries.size() * sizeof(ng::TabEntry);
       hipError_t e = hipSuccess;
+      if (rc == NG_OK && !entries.empty()) {
+        d_ent = arena.alloc(ne);
+        if (!d_ent) {
+          for (auto& cs : synced) cs.first->tab_synced = cs.second;
+          for (auto& cs : synced)
+            if (rc == NG_OK) rc = sync_table(cs.first);
+        } else if ((rc = upload(k, d_ent, entries.data(), ne)) != NG_OK) {
+          for (auto& cs : synced) cs.first->tab_synced = cs.second;  // not written
+          arena.release(d_ent, ne);
+          d_ent = nullptr;
+        } else {
+          e = ng::launch_set_entries((const ng::TabEntry*)d_ent, (uint32_t)entries.size(), streams[k]);
+        }
+      }
+      if (rc == NG_OK && e == hipSuccess) rc = stage_upload(k, descs[k], &d_descs, &nb);
       std::shared_ptr<EventBox> box;
-      if (rc == NG_OK) {
+      if (rc == NG_OK && e == hipSuccess) {
         e = ng::launch_generate_batch(d_descs, (uint32_t)descs[k].size(), groups, log2B, streams[k]);
         box = std::make_shared<EventBox>();
         if (e == hipSuccess) e = hipEventCreateWithFlags(&box->ev, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventRecord(box->ev, streams[k]);
-        hipEvent_t fe = nullptr;  // descriptors return to the arena after the launch
-        if (hipEventCreateWithFlags(&fe, hipEventDisableTiming) == hipSuccess &&
-            hipEventRecord(fe, streams[k]) == hipSuccess)
-          arena.release_after(streams[k], {{(char*)d_descs, nb}}, fe);
         sched.launches++;
         sched.packed_calls += descs[k].size();
         if (descs[k].size() > sched.max_calls_per_launch) sched.max_calls_per_launch = descs[k].size();
+      }
+      if (d_descs || d_ent) {  // descriptors and entries return to the arena after the launches
+        hipEvent_t fe = nullptr;
+        if (hipEventCreateWithFlags(&fe, hipEventDisableTiming) == hipSuccess &&
+            hipEventRecord(fe, streams[k]) == hipSuccess) {
+          Arena::Ranges rs;
+          if (d_descs) rs.emplace_back((char*)d_descs, nb);
+          if (d_ent) rs.emplace_back(d_ent, ne);
+          arena.release_after(streams[k], std::move(rs), fe);
+        } else {
+          if (fe) (void)hipEventDestroy(fe);
+          (void)hipStreamSynchronize(streams[k]);
+          if (d_descs) arena.release((char*)d_descs, nb);
+          if (d_ent) arena.release(d_ent, ne);
+        }
       }
       if (rc != NG_OK || e != hipSuccess) {
         for (Request* r : packed[k]) finish(r, NG_ERR_DEVICE, "packed generation launch failed");
