@@ -193,6 +193,11 @@ __device__ __forceinline__ void st_u32x4(void* p, uint32_t a, uint32_t b, uint32
   *(NG_GLOBAL u32x4*)p = u32x4{a, b, c, d};
 }
 __device__ __forceinline__ void st_u32x2(void* p, uint32_t a, uint32_t b) { *(NG_GLOBAL u32x2*)p = u32x2{a, b}; }
+// Stores marked streaming (non-temporal): for lines a store fills completely.
+__device__ __forceinline__ void st_u32_nt(void* p, uint32_t a) { __builtin_nontemporal_store(a, (NG_GLOBAL uint32_t*)p); }
+__device__ __forceinline__ void st_u32x2_nt(void* p, uint32_t a, uint32_t b) {
+  __builtin_nontemporal_store(u32x2{a, b}, (NG_GLOBAL u32x2*)p);
+}
 __device__ __forceinline__ uint2 ld_u32x2(const void* p) {
   const u32x2 v = *(const NG_GLOBAL u32x2*)p;
   return make_uint2(v.x, v.y);
@@ -410,8 +415,9 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s
 //   upsweep    range r counts the digits of its records
 //   scan       exclusive scan of the digit-major count matrix -> offsets
 //   downsweep  range r walks its tiles in order: stable wave64 ballot ranks,
-//              LDS staging by digit (keys, then payloads, through one
-//              buffer), runs of equal digits stored to consecutive positions.
+//              LDS staging by digit (keys, then payloads, each in its own
+//              buffer), runs of equal digits stored to consecutive positions;
+//              stores that fill whole 128-byte lines are marked streaming.
 // Tiles are large (10,240 records, 512 threads) because the cost of a pass
 // is set by the length of the runs each tile writes per digit.  Ranges are
 // XCD-aware: workgroup w runs on XCD w % 8, and each XCD owns a contiguous
@@ -564,11 +570,26 @@ __global__ __launch_bounds__(kSortThreads) void k_upsweep(SortPack pk, uint32_t*
 struct SortLds {
   uint32_t* key;                    // [kTile] keys staged by digit
   uint2* pay;                       // [kTile] payloads staged by digit (LDS holds both: 120 KB)
-  uint32_t* wh;                     // [kSortWaves][NB]: per-wave digit counts, then prefixes
-  uint32_t* start;                  // [NB + 1] tile-local digit starts
+  uint32_t* wh;                     // [kSortWaves][NB]: per-wave digit counts, then each wave's
+                                    // first tile position per digit
+  uint4* dig;                       // [NB] per digit: x = global position of its first record
+                                    // in the tile minus its tile position (mod 2^32); [y, y + z):
+                                    // the global positions whose 128-byte key line the tile's
+                                    // run fills completely
   uint32_t* run;                    // [NB] next global position per digit
   uint32_t* tmp;                    // [kSortWaves]
+  uint32_t* sink;                   // [kSortThreads]: counting adds of lanes that lead no digit
+  char** blk;                       // [kLdsBlocks]: output block table when it fits, else null
 };
+
+constexpr int kLdsBlocks = 512;  // output blocks whose pointers the last pass keeps in LDS
+
+// Output block of a sorted position (last pass): from the LDS copy of the
+// table when there is one, so that the lookup does not wait behind the
+// tile's outstanding global loads.
+__device__ __forceinline__ char* out_block(const SortIO& io, const SortLds& L, uint32_t dest) {
+  return L.blk ? L.blk[dest >> io.log2B] : G(io.out_blocks)[dest >> io.log2B];
+}
 
 // Records of one tile into registers: wave w owns tile records
 // [w*kItems*64, (w+1)*kItems*64), 64 consecutive records per item slot.
@@ -625,6 +646,27 @@ __device__ __forceinline__ void load_keys_any(const SortIO& io, uint64_t base, u
   else load_keys<IN_BLOCKED, false>(io, base, cnt, key);
 }
 
+// Store of one payload to its sorted position: streaming where the run fills
+// the 128-byte line, cached otherwise.
+template <bool OUT_BLOCKED>
+__device__ __forceinline__ void store_pay(const SortIO& io, const SortLds& L, uint32_t dest, bool in, uint2 pp) {
+  if constexpr (OUT_BLOCKED) {
+    const uint64_t B = 1ull << io.log2B;
+    char* blk = out_block(io, L, dest);
+    const uint64_t o = dest & (B - 1);
+    if (in) {
+      st_u32_nt(blk + 4 * B + 4 * o, pp.x);
+      st_u32_nt(blk + 8 * B + 4 * o, pp.y);
+    } else {
+      G(reinterpret_cast<uint32_t*>(blk + 4 * B))[o] = pp.x;
+      G(reinterpret_cast<uint32_t*>(blk + 8 * B))[o] = pp.y;
+    }
+  } else {
+    if (in) st_u32x2_nt(io.out_pay + dest, pp.x, pp.y);
+    else st_u32x2(io.out_pay + dest, pp.x, pp.y);
+  }
+}
+
 // One tile of a digit pass, its records in registers (the payloads possibly
 // still arriving).  FULL: all kTile records present (no predicates).  RB
 // bounds the digit width; digits are masked to nbits, so the ballots for bits
@@ -632,63 +674,90 @@ __device__ __forceinline__ void load_keys_any(const SortIO& io, uint64_t base, u
 // staged by digit and stored, then payloads (the key registers are free by
 // then, so the keys of the next tile (next_cnt > 0) load while this tile's
 // payloads are stored).
+//
+// Ranking: for each item slot, the lanes holding the same digit (peers) come
+// from one ballot per digit bit; a record's rank is the number of records of
+// its digit in the wave's earlier slots plus its peers in lower lanes.  The
+// lowest peer adds the slot's count to the wave's digit counter with an LDS
+// atomic (the other lanes add to a private word), and the value it gets back
+// reaches its peers through a lane permute a few slots later, so no slot
+// waits on the one before it.
 template <int RB, bool IN_BLOCKED, bool OUT_BLOCKED, bool FULL>
 __device__ __forceinline__ void sort_tile(const SortIO& io, uint64_t base, uint32_t cnt, uint32_t shift,
                                           uint32_t nbits, const SortLds& L, uint32_t (&key)[kItems],
                                           uint2 (&pay)[kItems], uint64_t next_base, uint32_t next_cnt) {
   constexpr int NB = 1 << RB;
+  constexpr int kLag = 4;  // slots between a counter add and the permute of its result
   const uint32_t nd = 1u << nbits, mask = nd - 1;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint64_t B = 1ull << io.log2B;
 
-  // stable rank of each record among the earlier records of its digit
-  uint32_t pos[kItems];
+  uint32_t pos[kItems];  // rank: (peers below) | (lowest peer's lane << 8), then the rank itself
+  uint32_t prv[kItems];  // counter value returned to the lowest peer
 #pragma unroll
-  for (int k = 0; k < kItems; ++k) {
-    const uint32_t lj = (uint32_t)(wave * kItems * 64 + k * 64 + lane);
-    const bool valid = FULL || lj < cnt;
-    const uint32_t dg = (key[k] >> shift) & mask;
-    uint64_t peers = FULL ? ~0ull : __ballot(valid);
+  for (int k = 0; k < kItems + kLag; ++k) {
+    if (k < kItems) {
+      const uint32_t lj = (uint32_t)(wave * kItems * 64 + k * 64 + lane);
+      const bool valid = FULL || lj < cnt;
+      const uint32_t dg = (key[k] >> shift) & mask;
+      uint32_t plo = ~0u, phi = ~0u;
+      if (!FULL) {
+        const uint64_t v = __ballot(valid);
+        plo = (uint32_t)v;
+        phi = (uint32_t)(v >> 32);
+      }
 #pragma unroll
-    for (int b = 0; b < RB; ++b) {
-      const bool bit = (dg >> b) & 1u;
-      const uint64_t m = __ballot(bit);
-      peers &= bit ? m : ~m;
+      for (int b = 0; b < RB; ++b) {
+        const uint32_t sb = (uint32_t)((int32_t)(dg << (31 - b)) >> 31);  // bit b, all ones or zero
+        const uint64_t m = __ballot(sb != 0u);
+        plo &= ~((uint32_t)m ^ sb);
+        phi &= ~((uint32_t)(m >> 32) ^ sb);
+      }
+      const uint32_t below = __builtin_amdgcn_mbcnt_hi(phi, __builtin_amdgcn_mbcnt_lo(plo, 0u));
+      const uint32_t tot = (uint32_t)__popc(plo) + (uint32_t)__popc(phi);
+      // lowest peer (bit 63 keeps the operand nonzero; a valid lane is its own peer)
+      const uint32_t lead = (uint32_t)__builtin_ctzll(((uint64_t)phi << 32) | plo | (1ull << 63));
+      uint32_t* ctr = (valid && below == 0) ? &L.wh[wave * NB + dg] : &L.sink[threadIdx.x];
+      prv[k] = atomicAdd(ctr, tot);
+      pos[k] = below | (lead << 8);
     }
-    const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(peers >> 32),
-                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
-    const uint32_t tot = (uint32_t)__popcll(peers);
-    uint32_t prev = 0;
-    if (valid) prev = L.wh[wave * NB + dg];
-    if (valid && below == 0) L.wh[wave * NB + dg] = prev + tot;
-    pos[k] = prev + below;
+    if (k >= kLag) {
+      const int q = k - kLag;
+      const uint32_t prev = (uint32_t)__builtin_amdgcn_ds_bpermute((int)((pos[q] >> 8) << 2), (int)prv[q]);
+      pos[q] = prev + (pos[q] & 0xFFu);
+    }
+    __builtin_amdgcn_sched_barrier(0);  // keep the lag: no permute moves up to its add
   }
   lds_barrier();
 
-  // per digit: prefixes over waves and the tile count
-  for (uint32_t d = threadIdx.x; d < nd; d += kSortThreads) {
-    uint32_t acc = 0;
+  // thread d: digit d's counts over the waves become each wave's first tile
+  // position; the tile's digit starts are an exclusive scan of the totals
+  {
+    const uint32_t d = threadIdx.x;  // NB <= kSortThreads
+    uint32_t c[kSortWaves];
+    uint32_t tot = 0;
 #pragma unroll
     for (int v = 0; v < kSortWaves; ++v) {
-      const uint32_t c = L.wh[v * NB + d];
-      L.wh[v * NB + d] = acc;
-      acc += c;
+      c[v] = d < nd ? L.wh[v * NB + d] : 0u;
+      const uint32_t t = c[v];
+      c[v] = tot;
+      tot += t;
     }
-    L.start[d] = acc;
-  }
-  lds_barrier();
-  {  // tile-local digit starts: exclusive scan of the tile counts
-    const uint32_t d = threadIdx.x;  // NB <= kSortThreads
-    const uint32_t local = d < nd ? L.start[d] : 0u;
-    const uint32_t inc = wave_inclusive_scan(local);
+    const uint32_t inc = wave_inclusive_scan(tot);
     if (lane == 63) L.tmp[wave] = inc;
     lds_barrier();
-    uint32_t run = inc - local;
+    uint32_t start = inc - tot;
 #pragma unroll
     for (int w = 0; w < kSortWaves; ++w)
-      if (w < wave) run += L.tmp[w];
-    if (d < nd) L.start[d] = run;
-    if (threadIdx.x == 0) L.start[nd] = cnt;
+      if (w < wave) start += L.tmp[w];
+    if (d < nd) {
+#pragma unroll
+      for (int v = 0; v < kSortWaves; ++v) L.wh[v * NB + d] = start + c[v];
+      const uint32_t r = L.run[d];
+      const uint32_t lo = (r + 31u) & ~31u, hi = (r + tot) & ~31u;
+      L.dig[d] = make_uint4(r - start, lo, hi > lo ? hi - lo : 0u, 0u);
+      L.run[d] = r + tot;
+    }
   }
   lds_barrier();
 
@@ -698,39 +767,47 @@ __device__ __forceinline__ void sort_tile(const SortIO& io, uint64_t base, uint3
     const uint32_t lj = (uint32_t)(wave * kItems * 64 + k * 64 + lane);
     if (FULL || lj < cnt) {
       const uint32_t dg = (key[k] >> shift) & mask;
-      pos[k] += L.start[dg] + L.wh[wave * NB + dg];
+      pos[k] += L.wh[wave * NB + dg];
       L.key[pos[k]] = key[k];
     }
   }
   lds_barrier();
+  // Records whose 128-byte lines the run fills are stored streaming; the
+  // partial lines at a run's ends stay cached, so that the neighbouring
+  // tile's run can complete them in L2 before they reach HBM.
   const uint32_t dmask = (1u << io.dbits) - 1;
   uint32_t dest[kItems];
+  uint32_t inner = 0;  // bit k: record k lies in a completely filled line
 #pragma unroll
   for (int k = 0; k < kItems; ++k) {
     const uint32_t lp = (uint32_t)(k * kSortThreads + threadIdx.x);
     if (FULL || lp < cnt) {
       const uint32_t kk = L.key[lp];
       const uint32_t dg = (kk >> shift) & mask;
-      dest[k] = L.run[dg] + (lp - L.start[dg]);
+      const uint4 di = L.dig[dg];
+      dest[k] = di.x + lp;
+      const bool in = dest[k] - di.y < di.z;
+      inner |= (uint32_t)in << k;
       if constexpr (OUT_BLOCKED) {
-        char* blk = G(io.out_blocks)[dest[k] >> io.log2B];
+        char* blk = out_block(io, L, dest[k]);
         const uint64_t o = dest[k] & (B - 1);
-        G(reinterpret_cast<uint32_t*>(blk))[o] = kk >> io.dbits;
+        if (in) st_u32_nt(blk + 4 * o, kk >> io.dbits);
+        else G(reinterpret_cast<uint32_t*>(blk))[o] = kk >> io.dbits;
         G(reinterpret_cast<int16_t*>(blk + 12 * B))[o] = (int16_t)(kk & dmask);
       } else {
-        G(io.out_keys)[dest[k]] = kk;
+        if (in) st_u32_nt(io.out_keys + dest[k], kk);
+        else G(io.out_keys)[dest[k]] = kk;
       }
     }
   }
-  lds_barrier();
-  // phase 2: payloads through the same buffer
+  // phase 2: payloads through their own buffer (the counters are free again
+  // once every wave has read its positions above)
 #pragma unroll
   for (int k = 0; k < kItems; ++k) {
     const uint32_t lj = (uint32_t)(wave * kItems * 64 + k * 64 + lane);
     if (FULL || lj < cnt) L.pay[pos[k]] = pay[k];
   }
   for (uint32_t d = threadIdx.x; d < nd; d += kSortThreads) {
-    L.run[d] += L.start[d + 1] - L.start[d];
 #pragma unroll
     for (int v = 0; v < kSortWaves; ++v) L.wh[v * NB + d] = 0;
   }
@@ -739,19 +816,9 @@ __device__ __forceinline__ void sort_tile(const SortIO& io, uint64_t base, uint3
 #pragma unroll
   for (int k = 0; k < kItems; ++k) {
     const uint32_t lp = (uint32_t)(k * kSortThreads + threadIdx.x);
-    if (FULL || lp < cnt) {
-      const uint2 pp = L.pay[lp];
-      if constexpr (OUT_BLOCKED) {
-        char* blk = G(io.out_blocks)[dest[k] >> io.log2B];
-        const uint64_t o = dest[k] & (B - 1);
-        G(reinterpret_cast<uint32_t*>(blk + 4 * B))[o] = pp.x;
-        G(reinterpret_cast<uint32_t*>(blk + 8 * B))[o] = pp.y;
-      } else {
-        st_u32x2(io.out_pay + dest[k], pp.x, pp.y);
-      }
-    }
+    if (FULL || lp < cnt) store_pay<OUT_BLOCKED>(io, L, dest[k], (inner >> k) & 1u, L.pay[lp]);
   }
-  lds_barrier();  // the buffer is reused by the next tile
+  lds_barrier();  // the buffers are reused by the next tile
 }
 
 template <int RB, bool IN_BLOCKED, bool OUT_BLOCKED>
@@ -760,15 +827,21 @@ __global__ __launch_bounds__(kSortThreads) void k_downsweep(SortPack pk, const u
   __shared__ uint32_t s_key[kTile];
   __shared__ uint2 s_pay[kTile];
   __shared__ uint32_t s_wh[kSortWaves * NB];
-  __shared__ uint32_t s_start[NB + 1];
+  __shared__ uint4 s_dig[NB];
   __shared__ uint32_t s_run[NB];
   __shared__ uint32_t s_tmp[kSortWaves];
-  const SortLds L{s_key, s_pay, s_wh, s_start, s_run, s_tmp};
+  __shared__ uint32_t s_sink[kSortThreads];
+  __shared__ char* s_blk[OUT_BLOCKED ? kLdsBlocks : 1];
   const int gr = range_index(pk);
   if (gr < 0) return;
   const SortSeg sg = sort_seg(pk, (uint32_t)gr);
   const uint32_t r = (uint32_t)gr - sg.range0, shift = sg.shift, nbits = sg.nbits;
   const uint32_t nd = 1u << nbits;
+  const uint32_t n_out_blocks = (uint32_t)((sg.n + (1ull << sg.io.log2B) - 1) >> sg.io.log2B);
+  const bool lds_tab = OUT_BLOCKED && n_out_blocks <= (uint32_t)kLdsBlocks;
+  if (lds_tab)
+    for (uint32_t b = threadIdx.x; b < n_out_blocks; b += kSortThreads) s_blk[b] = G(sg.io.out_blocks)[b];
+  const SortLds L{s_key, s_pay, s_wh, s_dig, s_run, s_tmp, s_sink, lds_tab ? s_blk : nullptr};
   for (uint32_t d = threadIdx.x; d < nd; d += kSortThreads) {
     s_run[d] = offsets[sg.cbase + (uint64_t)d * sg.n_ranges + r] - sg.base;
 #pragma unroll

@@ -88,3 +88,22 @@ def test_group_index_full(microcircuit_full):
     ptr = torch.zeros(wl.n_nodes + 1, dtype=torch.int64, device="cuda")
     ptr[1:] = torch.cumsum(per_src, 0)
     assert torch.equal(torch.from_numpy(gp.astype(np.int64)).cuda(), ptr)
+
+
+def test_many_output_blocks_stable_sort():
+    # 4e7 synapses in blocks of 2^16 records: 611 output blocks, more than the
+    # last sort pass keeps in LDS, so it reads the device block table instead
+    wl = W.microcircuit(total=40_000_000)
+    B = 1 << 16
+    assert -(-wl.n_syn // B) > 512
+    with Network(wl.seed, wl.h, B, arena_bytes_for(wl.n_syn, wl.n_nodes, wl.max_delay, B)) as net:
+        net.build(wl, calibrate=False)
+        created = net.fetch(device=True)
+        net.calibrate()
+        out = net.fetch(device=True)
+    dbits = int(wl.max_delay).bit_length()
+    key_c = (created["src"].to(torch.int64) << dbits) | created["delay"].to(torch.int64)
+    _, order = torch.sort(key_c, stable=True)
+    for k in ("src", "tgt", "delay"):
+        assert torch.equal(created[k][order], out[k]), k
+    assert torch.equal(created["w"][order].view(torch.int32), out["w"].view(torch.int32))
