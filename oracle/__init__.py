@@ -91,6 +91,10 @@ def lib():
         L.ora_connect.restype = ctypes.c_int
         L.ora_calibrate.argtypes = [u64, u32, vp, vp, vp, vp, vp, P(u64)]
         L.ora_calibrate.restype = ctypes.c_int
+        L.ora_copass_partition.argtypes = [u32, vp, vp, u64, vp, P(u64)]
+        L.ora_copass_partition.restype = ctypes.c_int
+        L.ora_copass_block_sort.argtypes = [u64, u64, vp, vp]
+        L.ora_copass_block_sort.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -213,3 +217,33 @@ def build_network(seed: int, h: float, n_nodes: int, calls, first_connect_id: in
     return dict(src=src, tgt=tgt, w=w, delay=d, perm=perm,
                 s_src=src[perm], s_tgt=tgt[perm], s_w=w[perm], s_delay=d[perm],
                 group_ptr=gptr, group_start=gstart)
+
+
+# --- COPASS block sort (Appendix A) -------------------------------------------
+def copass_partition(subarrays, m: int):
+    """Left-partition sizes m_i of sorted subarrays for a total of m.
+
+    Returns (m_i array, path, iterations): path 1 = threshold found, 2 = all
+    brackets of width <= 1, 0 = trivial m."""
+    subs = [np.ascontiguousarray(a, dtype=np.uint64) for a in subarrays]
+    k = len(subs)
+    off = np.zeros(k + 1, np.uint64)
+    off[1:] = np.cumsum([a.size for a in subs])
+    vals = np.concatenate(subs) if k else np.zeros(0, np.uint64)
+    vals = np.ascontiguousarray(vals, dtype=np.uint64)
+    out = np.zeros(max(k, 1), np.uint64)
+    it = ctypes.c_uint64()
+    path = lib().ora_copass_partition(k, _ptr(vals), _ptr(off), m, _ptr(out), ctypes.byref(it))
+    if path < 0:
+        raise ValueError("bad partition input")
+    return out[:k].astype(np.int64), int(path), int(it.value)
+
+
+def copass_block_sort(vals, block: int, pay=None):
+    """In-place COPASS block sort of vals (u64) in blocks of `block`; pay is
+    permuted alongside (default: the original positions)."""
+    v = np.array(vals, dtype=np.uint64, copy=True)
+    p = np.arange(v.size, dtype=np.uint64) if pay is None else np.array(pay, dtype=np.uint64, copy=True)
+    if lib().ora_copass_block_sort(v.size, block, _ptr(v), _ptr(p)) != 0:
+        raise ValueError("bad block sort input")
+    return v, p

@@ -276,3 +276,221 @@ int ora_calibrate(uint64_t n, uint32_t n_nodes, const uint32_t* src, const int32
   free(items);
   return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* COPASS (Appendix A).                                                     */
+
+/* number of elements of the sorted range a[lo..hi) that are <= t (le = 1) or
+ * < t (le = 0), plus lo: the counts of the paper restricted to a bracket
+ * that already holds the answer */
+static uint64_t count_upto(const uint64_t* a, uint64_t lo, uint64_t hi, uint64_t t, int le) {
+  while (lo < hi) {
+    const uint64_t mid = lo + (hi - lo) / 2;
+    if (le ? a[mid] <= t : a[mid] < t) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+typedef struct {
+  uint64_t v;
+  uint32_t i;
+} copass_cand;
+
+static int cmp_cand(const void* a, const void* b) {
+  const copass_cand* x = (const copass_cand*)a;
+  const copass_cand* y = (const copass_cand*)b;
+  if (x->v != y->v) return x->v < y->v ? -1 : 1;
+  if (x->i != y->i) return x->i < y->i ? -1 : 1;
+  return 0;
+}
+
+int ora_copass_partition(uint32_t k, const uint64_t* vals, const uint64_t* off, uint64_t m,
+                         uint64_t* m_out, uint64_t* iterations) {
+  if (iterations) *iterations = 0;
+  uint64_t total = 0;
+  for (uint32_t i = 0; i < k; i++) {
+    if (off[i + 1] < off[i]) return -1;
+    total += off[i + 1] - off[i];
+  }
+  if (m > total) return -1;
+  if (m == 0 || m == total) {
+    for (uint32_t i = 0; i < k; i++) m_out[i] = m == 0 ? 0 : off[i + 1] - off[i];
+    return 0;
+  }
+  /* bracket [ubar_m_i, bar_m_i] per subarray: ubar_m counts elements <= the
+   * lower threshold, bar_m those < the upper one; initially the thresholds
+   * lie below the minimum and above the maximum, so the brackets are [0, N_i] */
+  uint64_t* lo = (uint64_t*)malloc((k ? k : 1) * sizeof(uint64_t));
+  uint64_t* hi = (uint64_t*)malloc((k ? k : 1) * sizeof(uint64_t));
+  uint64_t* mu_lo = (uint64_t*)malloc((k ? k : 1) * sizeof(uint64_t));
+  uint64_t* mu_hi = (uint64_t*)malloc((k ? k : 1) * sizeof(uint64_t));
+  if (!lo || !hi || !mu_lo || !mu_hi) {
+    free(lo); free(hi); free(mu_lo); free(mu_hi);
+    return -1;
+  }
+  for (uint32_t i = 0; i < k; i++) {
+    lo[i] = 0;
+    hi[i] = off[i + 1] - off[i];
+  }
+  int result = -1;
+  uint64_t iter = 0;
+  for (;;) {
+    /* the widest bracket; stop when every bracket has width <= 1 */
+    uint32_t l = 0;
+    for (uint32_t i = 1; i < k; i++)
+      if (hi[i] - lo[i] > hi[l] - lo[l]) l = i;
+    if (hi[l] - lo[l] <= 1) break;
+    iter++;
+    /* trial threshold: the middle element of that bracket */
+    const uint64_t mt = (lo[l] + hi[l]) / 2;
+    const uint64_t t = vals[off[l] + mt];
+    uint64_t s_lo = 0, s_hi = 0;
+    for (uint32_t i = 0; i < k; i++) {
+      const uint64_t* a = vals + off[i];
+      mu_hi[i] = count_upto(a, lo[i], hi[i], t, 1);  /* #{S_ij <= t} */
+      mu_lo[i] = count_upto(a, lo[i], mu_hi[i], t, 0);  /* #{S_ij < t} */
+      s_lo += mu_lo[i];
+      s_hi += mu_hi[i];
+    }
+    if (s_lo <= m && m <= s_hi) {
+      /* t is the threshold: the elements equal to t, [mu_lo_i, mu_hi_i) in
+       * each subarray, fill the remaining d = m - sum mu_lo, subarray by
+       * subarray in ascending i */
+      uint64_t d = m - s_lo;
+      for (uint32_t i = 0; i < k; i++) {
+        const uint64_t take = d < mu_hi[i] - mu_lo[i] ? d : mu_hi[i] - mu_lo[i];
+        m_out[i] = mu_lo[i] + take;
+        d -= take;
+      }
+      result = 1;
+      break;
+    }
+    if (m < s_lo) {
+      for (uint32_t i = 0; i < k; i++) hi[i] = mu_lo[i];  /* upper threshold := t */
+    } else {
+      for (uint32_t i = 0; i < k; i++) lo[i] = mu_hi[i];  /* lower threshold := t */
+    }
+  }
+  if (result < 0) {
+    /* every bracket has width <= 1: the subarrays with width one offer their
+     * element ubar_m_i; the d = m - sum ubar_m smallest offers, ordered by
+     * (value, i), go to the left partitions */
+    copass_cand* c = (copass_cand*)malloc((k ? k : 1) * sizeof(copass_cand));
+    if (c) {
+      uint32_t nc = 0;
+      uint64_t s = 0;
+      for (uint32_t i = 0; i < k; i++) {
+        s += lo[i];
+        m_out[i] = lo[i];
+        if (hi[i] == lo[i] + 1) {
+          c[nc].v = vals[off[i] + lo[i]];
+          c[nc].i = i;
+          nc++;
+        }
+      }
+      qsort(c, nc, sizeof(copass_cand), cmp_cand);
+      const uint64_t d = m - s;
+      for (uint64_t j = 0; j < d && j < nc; j++) m_out[c[j].i] += 1;
+      free(c);
+      result = 2;
+    }
+  }
+  if (iterations) *iterations = iter;
+  free(lo); free(hi); free(mu_lo); free(mu_hi);
+  return result;
+}
+
+typedef struct {
+  uint64_t v, p;
+  uint64_t pos;
+} copass_item;
+
+static int cmp_copass_item(const void* a, const void* b) {
+  const copass_item* x = (const copass_item*)a;
+  const copass_item* y = (const copass_item*)b;
+  if (x->v != y->v) return x->v < y->v ? -1 : 1;
+  if (x->pos != y->pos) return x->pos < y->pos ? -1 : 1;
+  return 0;
+}
+
+/* the underlying sort: stable, by value, of vals/pay[a..a+len) */
+static int stable_sort_range(uint64_t* vals, uint64_t* pay, uint64_t a, uint64_t len) {
+  copass_item* it = (copass_item*)malloc((len ? len : 1) * sizeof(copass_item));
+  if (!it) return -1;
+  for (uint64_t j = 0; j < len; j++) {
+    it[j].v = vals[a + j];
+    it[j].p = pay[a + j];
+    it[j].pos = j;
+  }
+  qsort(it, len, sizeof(copass_item), cmp_copass_item);
+  for (uint64_t j = 0; j < len; j++) {
+    vals[a + j] = it[j].v;
+    pay[a + j] = it[j].p;
+  }
+  free(it);
+  return 0;
+}
+
+int ora_copass_block_sort(uint64_t n, uint64_t B, uint64_t* vals, uint64_t* pay) {
+  if (B == 0) return -1;
+  const uint64_t nb = (n + B - 1) / B;
+  if (nb > 0xFFFFFFFFull) return -1;
+  const uint32_t k = (uint32_t)nb;
+  if (k == 0) return 0;
+  /* (B) every block sorted */
+  for (uint32_t i = 0; i < k; i++) {
+    const uint64_t a = (uint64_t)i * B, len = a + B <= n ? B : n - a;
+    if (stable_sort_range(vals, pay, a, len)) return -1;
+  }
+  /* subarray i occupies [start_i, start_i + len_i) of the remaining region */
+  uint64_t* start = (uint64_t*)malloc(k * sizeof(uint64_t));
+  uint64_t* len = (uint64_t*)malloc(k * sizeof(uint64_t));
+  uint64_t* off = (uint64_t*)malloc((k + 1) * sizeof(uint64_t));
+  uint64_t* mi = (uint64_t*)malloc(k * sizeof(uint64_t));
+  uint64_t* aux_v = (uint64_t*)malloc(B * sizeof(uint64_t));
+  uint64_t* aux_p = (uint64_t*)malloc(B * sizeof(uint64_t));
+  uint64_t* sub = (uint64_t*)malloc((n ? n : 1) * sizeof(uint64_t));
+  int rc = (start && len && off && mi && aux_v && aux_p && sub) ? 0 : -1;
+  for (uint32_t i = 0; i < k && rc == 0; i++) {
+    start[i] = (uint64_t)i * B;
+    len[i] = start[i] + B <= n ? B : n - start[i];
+  }
+  for (uint32_t b = 0; b < k && rc == 0; b++) {
+    const uint64_t first = (uint64_t)b * B, m = first + B <= n ? B : n - first;
+    /* the partition reads the subarrays as one concatenated sorted list each */
+    off[0] = 0;
+    for (uint32_t i = 0; i < k; i++) {
+      memcpy(sub + off[i], vals + start[i], len[i] * sizeof(uint64_t));
+      off[i + 1] = off[i] + len[i];
+    }
+    if (ora_copass_partition(k, sub, off, m, mi, NULL) < 0) {
+      rc = -1;
+      break;
+    }
+    /* (D) left partitions, in subarray order, to the auxiliary array */
+    uint64_t q = 0;
+    for (uint32_t i = 0; i < k; i++) {
+      memcpy(aux_v + q, vals + start[i], mi[i] * sizeof(uint64_t));
+      memcpy(aux_p + q, pay + start[i], mi[i] * sizeof(uint64_t));
+      q += mi[i];
+    }
+    /* (E) right partitions shifted to the end of the array, last first, so
+     * that block b is free; then the auxiliary array goes to block b */
+    uint64_t end = n;
+    for (uint32_t i = k; i-- > 0;) {
+      const uint64_t r = len[i] - mi[i];
+      memmove(vals + end - r, vals + start[i] + mi[i], r * sizeof(uint64_t));
+      memmove(pay + end - r, pay + start[i] + mi[i], r * sizeof(uint64_t));
+      end -= r;
+      start[i] = end;
+      len[i] = r;
+    }
+    memcpy(vals + first, aux_v, m * sizeof(uint64_t));
+    memcpy(pay + first, aux_p, m * sizeof(uint64_t));
+    /* (F) block b sorted */
+    if (stable_sort_range(vals, pay, first, m)) rc = -1;
+  }
+  free(start); free(len); free(off); free(mi); free(aux_v); free(aux_p); free(sub);
+  return rc;
+}

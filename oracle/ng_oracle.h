@@ -16,7 +16,9 @@
  *     (Sec. 2.1, last paragraph),
  *   - calibration: ordering by source (first key) and delay (second key),
  *     connection-group boundaries, group counts G_i and their cumulative sum
- *     p_i of Eq. (14) (Sec. 2.2).
+ *     p_i of Eq. (14) (Sec. 2.2),
+ *   - the COPASS block sort and its partition of sorted subarrays
+ *     (Appendix A), which sorts the block array in place.
  *
  * The random draws follow one frozen contract (the paper uses an unspecified
  * cuRAND generator and states that a change of generator preserves the
@@ -90,6 +92,31 @@ int ora_connect(uint64_t seed, float h, uint32_t connect_id, const ora_call* cal
 int ora_calibrate(uint64_t n, uint32_t n_nodes, const uint32_t* src, const int32_t* delay,
                   uint64_t* perm, uint32_t* group_ptr, uint32_t* group_start,
                   uint64_t* n_groups);
+
+/* COPASS partition (Appendix A, "The COPASS partition algorithm" and its two
+ * last steps).  k subarrays, each sorted ascending, are given concatenated:
+ * subarray i is vals[off[i] .. off[i+1]).  For 0 < m < total size it finds
+ * left-partition sizes m_i with sum m_i = m such that every left element is
+ * <= every right element.  Readings (the paper is silent or garbled here):
+ * the candidate of the brackets-of-width-one step is element ubar_m_i
+ * (0-based); its candidates are ordered by (value, i); the equal-to-t
+ * elements of the other last step go to the subarrays in ascending i.
+ * Returns 1 if the search ended with t found (last step "case 2"), 2 if it
+ * ended with all brackets of width <= 1 (last step "case 1"), 0 if m is 0
+ * or the total size (trivial), -1 on bad input.  *iterations (may be null)
+ * receives the number of threshold iterations. */
+int ora_copass_partition(uint32_t k, const uint64_t* vals, const uint64_t* off, uint64_t m,
+                         uint64_t* m_out, uint64_t* iterations);
+
+/* COPASS block sort (Appendix A, "The COPASS block-sort algorithm"): sorts n
+ * values in place, keeping blocks of size B (the last one may be shorter),
+ * with auxiliary storage of one block.  Each block is first sorted with a
+ * stable sort; then block b = 0, 1, ... is extracted: the COPASS partition of
+ * the remaining sorted subarrays with m = size of block b, left partitions
+ * copied to the auxiliary array, right partitions shifted to the end, the
+ * auxiliary array copied to block b and sorted.  pay[] is permuted alongside
+ * vals[] (e.g. the creation index).  Returns 0, or -1 on bad input. */
+int ora_copass_block_sort(uint64_t n, uint64_t B, uint64_t* vals, uint64_t* pay);
 
 #ifdef __cplusplus
 }
