@@ -202,6 +202,25 @@ int ng_copy_group_index(ng_ctx* ctx, uint32_t* group_ptr, uint32_t* group_start)
  * speed does. */
 int ng_set_tuning(ng_ctx* ctx, int radix_bits, uint32_t sort_ranges);
 
+/* Calibration algorithm of a context; the calibrated arrays and group index
+ * are the same with either (stable order by (source, delay), Sec. 2.2).
+ *   NG_CALIB_RADIX (default): stable LSD radix sort of all connections into
+ *     a second block set (peak scratch ~ 38 bytes per connection).
+ *   NG_CALIB_COPASS: the COPASS in-place block sort of Appendix A.  Each
+ *     block is sorted, then block b = 0, 1, ... is filled with the next
+ *     block-size smallest connections: a threshold partition of the sorted
+ *     remainders, the left partitions gathered into an auxiliary array, the
+ *     right partitions shifted toward the end, the auxiliary array sorted
+ *     into block b.  The connections stay in their blocks; scratch is about
+ *     36 bytes times the block size plus the group index arrays, at the cost
+ *     of moving the remaining connections once per block.  Each block's
+ *     partition sizes are read back to the host, so a COPASS calibration
+ *     synchronizes and cannot be captured (NG_ERR_UNSUPPORTED); in
+ *     ng_calibrate_many such contexts are calibrated one by one.
+ * Returns NG_OK, or NG_ERR_INVALID_ARG for another value. */
+enum { NG_CALIB_RADIX = 0, NG_CALIB_COPASS = 1 };
+int ng_set_calibration(ng_ctx* ctx, int algorithm);
+
 /* Arena bytes in use now, at peak, and the largest free extent. */
 int ng_memory_stats(ng_ctx* ctx, uint64_t* used, uint64_t* peak, uint64_t* largest_free);
 

@@ -117,6 +117,46 @@ struct TabEntry {
 };
 hipError_t launch_set_entries(const TabEntry* d_entries, uint32_t n, hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// COPASS in-place block sort (Appendix A).
+// Record positions index the block array: position p lives in block p >> log2B.
+struct BlockView {
+  char* const* blocks;  // device block table
+  int log2B;
+  uint32_t dbits;       // key = src << dbits | delay
+};
+// One piece of a copy list: len records from position src to position dst;
+// pre = records of the list's pieces before this one.
+struct CopySeg {
+  uint32_t src, dst, len, pre;
+};
+struct CopyList {
+  const CopySeg* segs;  // device array, pre ascending
+  uint32_t n_segs;
+  uint32_t total;       // sum of len
+};
+// Copies the listed records between the block array and packed arrays
+// (key u32, payload = (tgt, weight bits)); to_packed: block array -> packed.
+hipError_t launch_copass_copy(const BlockView& v, const CopyList& l, bool to_packed, uint32_t* keys, uint2* pay,
+                              hipStream_t s);
+// Partition of k sorted subarrays (subarray i: positions [start[i],
+// start[i]+len[i]) of the block array) for a total of m, 0 < m < sum len:
+// m_out[i] = size of the left partition of subarray i.  lo, hi, mu_lo, mu_hi:
+// k words of scratch each.  status[0] = last step taken (1 threshold found,
+// 2 brackets of width one), status[1] = iterations, status[2] = 1 if the
+// iteration bound was hit.  One workgroup.
+struct CopassPart {
+  BlockView v;
+  const uint32_t* start;
+  const uint32_t* len;
+  uint32_t k;
+  uint32_t m;
+  uint32_t *lo, *hi, *mu_lo, *mu_hi;
+  uint32_t* m_out;
+  uint32_t* status;
+};
+hipError_t launch_copass_partition(const CopassPart& p, hipStream_t s);
+
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, uint64_t n, hipStream_t s);
 
 // Connection-group index over sorted blocked SoA (Sec. 2.2, Eq. (14)), for

@@ -1162,6 +1162,253 @@ hipError_t downsweep_rb(const SortPack& pk, const uint32_t* offsets, hipStream_t
   return hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------------------
+// COPASS in-place block sort (Appendix A): the copies of left partitions to
+// the auxiliary array and of right partitions through a bounce buffer, and
+// the partition search.
+// ---------------------------------------------------------------------------
+constexpr int kCopyThreads = 256;
+constexpr int kCopyItems = 8;
+
+__device__ __forceinline__ uint32_t view_key(const BlockView& v, uint32_t p) {
+  const uint64_t B = 1ull << v.log2B;
+  const char* blk = G(v.blocks)[p >> v.log2B];
+  const uint64_t o = p & (B - 1);
+  return (G(reinterpret_cast<const uint32_t*>(blk))[o] << v.dbits) |
+         (uint32_t)(uint16_t)G(reinterpret_cast<const int16_t*>(blk + 12 * B))[o];
+}
+
+// Each workgroup copies kCopyThreads * kCopyItems consecutive records of the
+// list; a record finds its piece by walking forward from the piece of the
+// workgroup's first record (pieces are long, so the walk is short).
+template <bool TO_PACKED>
+__global__ __launch_bounds__(kCopyThreads) void k_copass_copy(BlockView v, CopyList l, uint32_t* __restrict__ keys,
+                                                              uint2* __restrict__ pay) {
+  const uint64_t B = 1ull << v.log2B;
+  const uint64_t per = kCopyThreads * kCopyItems;
+  for (uint64_t base = blockIdx.x * per; base < l.total; base += gridDim.x * per) {
+    uint32_t a = 0, b = l.n_segs;  // last piece with pre <= base
+    while (b - a > 1) {
+      const uint32_t mid = (a + b) / 2;
+      if (G(l.segs)[mid].pre <= base) a = mid;
+      else b = mid;
+    }
+    const uint32_t s0 = __builtin_amdgcn_readfirstlane(a);
+#pragma unroll
+    for (int j = 0; j < kCopyItems; ++j) {
+      const uint64_t r = base + j * kCopyThreads + threadIdx.x;
+      if (r >= l.total) break;
+      uint32_t sg = s0;
+      while (sg + 1 < l.n_segs && G(l.segs)[sg + 1].pre <= r) ++sg;
+      const u32x4 sq = *(const NG_GLOBAL u32x4*)(const void*)(l.segs + sg);  // (src, dst, len, pre)
+      const CopySeg cs{sq.x, sq.y, sq.z, sq.w};
+      const uint32_t o = (uint32_t)r - cs.pre;
+      if constexpr (TO_PACKED) {
+        const uint32_t p = cs.src + o;
+        const char* blk = G(v.blocks)[p >> v.log2B];
+        const uint64_t q = p & (B - 1);
+        const uint32_t src = G(reinterpret_cast<const uint32_t*>(blk))[q];
+        const uint32_t tgt = G(reinterpret_cast<const uint32_t*>(blk + 4 * B))[q];
+        const uint32_t w = G(reinterpret_cast<const uint32_t*>(blk + 8 * B))[q];
+        const uint32_t d = (uint32_t)(uint16_t)G(reinterpret_cast<const int16_t*>(blk + 12 * B))[q];
+        G(keys)[cs.dst + o] = (src << v.dbits) | d;
+        st_u32x2(pay + cs.dst + o, tgt, w);
+      } else {
+        const uint32_t kk = G(keys)[cs.src + o];
+        const uint2 pp = ld_u32x2(pay + cs.src + o);
+        const uint32_t p = cs.dst + o;
+        char* blk = G(v.blocks)[p >> v.log2B];
+        const uint64_t q = p & (B - 1);
+        G(reinterpret_cast<uint32_t*>(blk))[q] = kk >> v.dbits;
+        G(reinterpret_cast<uint32_t*>(blk + 4 * B))[q] = pp.x;
+        G(reinterpret_cast<uint32_t*>(blk + 8 * B))[q] = pp.y;
+        G(reinterpret_cast<int16_t*>(blk + 12 * B))[q] = (int16_t)(kk & ((1u << v.dbits) - 1u));
+      }
+    }
+  }
+}
+
+constexpr int kPartThreads = 1024;
+constexpr int kPartWaves = kPartThreads / 64;
+
+__device__ __forceinline__ uint64_t part_sum(uint64_t x, uint64_t* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+  __syncthreads();
+  uint64_t t = 0;
+#pragma unroll
+  for (int w = 0; w < kPartWaves; ++w) t += red[w];
+  return t;
+}
+
+// exclusive prefix of x over the threads in order
+__device__ __forceinline__ uint64_t part_excl(uint64_t x, uint64_t* red) {
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint64_t inc = x;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint64_t n = __shfl_up(inc, o);
+    if (lane >= (uint32_t)o) inc += n;
+  }
+  __syncthreads();
+  if (lane == 63) red[wave] = inc;
+  __syncthreads();
+  uint64_t before = 0;
+  for (uint32_t w = 0; w < wave; ++w) before += red[w];
+  return before + inc - x;
+}
+
+// number of keys of subarray (at position st) with index in [a, b) that are
+// <= t (le) or < t (!le), plus a; the answer is known to lie in [a, b]
+__device__ __forceinline__ uint32_t part_count(const BlockView& v, uint32_t st, uint32_t a, uint32_t b, uint32_t t,
+                                               bool le) {
+  while (a < b) {
+    const uint32_t mid = a + (b - a) / 2;
+    const uint32_t x = view_key(v, st + mid);
+    if (le ? x <= t : x < t) a = mid + 1;
+    else b = mid;
+  }
+  return a;
+}
+
+// The partition search of the appendix.  Brackets [lo_i, hi_i]: lo_i counts
+// the keys <= the lower threshold, hi_i those < the upper one.  Each round
+// bisects the widest bracket (lowest i on ties), takes its middle key as the
+// trial threshold t and counts every subarray's keys < t and <= t; if m lies
+// between the sums, t is the threshold, else the bracket side that keeps m
+// inside moves to t.  When every bracket has width <= 1, the subarrays of
+// width one offer their next key and the smallest offers, by (key, i), fill
+// the rest.  Thread t owns the subarrays [t*C, (t+1)*C).
+__global__ __launch_bounds__(kPartThreads) void k_copass_partition(CopassPart p) {
+  __shared__ uint64_t red[kPartWaves];
+  __shared__ uint32_t s_w[kPartWaves], s_i[kPartWaves];
+  const uint32_t k = p.k, m = p.m;
+  const uint32_t C = (k + kPartThreads - 1) / kPartThreads;
+  const uint32_t i0 = min(threadIdx.x * C, k), i1 = min(i0 + C, k);
+  for (uint32_t i = i0; i < i1; ++i) {
+    p.lo[i] = 0;
+    p.hi[i] = p.len[i];
+  }
+  const uint32_t cap = 33u * (k + 1u);  // each round shrinks one bracket of < 2^32 to at most half
+  uint32_t iter = 0, path = 0, err = 0;
+  for (;;) {
+    uint32_t bw = 0, bi = 0;
+    for (uint32_t i = i0; i < i1; ++i) {
+      const uint32_t w = p.hi[i] - p.lo[i];
+      if (w > bw) {
+        bw = w;
+        bi = i;
+      }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const uint32_t ow = __shfl_xor(bw, o), oi = __shfl_xor(bi, o);
+      if (ow > bw || (ow == bw && oi < bi)) {
+        bw = ow;
+        bi = oi;
+      }
+    }
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+      s_w[threadIdx.x >> 6] = bw;
+      s_i[threadIdx.x >> 6] = bi;
+    }
+    __syncthreads();
+    bw = s_w[0];
+    bi = s_i[0];
+    for (int w = 1; w < kPartWaves; ++w)
+      if (s_w[w] > bw || (s_w[w] == bw && s_i[w] < bi)) {
+        bw = s_w[w];
+        bi = s_i[w];
+      }
+    if (bw <= 1) break;
+    if (++iter > cap) {
+      err = 1;
+      break;
+    }
+    const uint32_t t = view_key(p.v, p.start[bi] + (p.lo[bi] + p.hi[bi]) / 2);
+    uint64_t slo = 0, shi = 0;
+    for (uint32_t i = i0; i < i1; ++i) {
+      const uint32_t mh = part_count(p.v, p.start[i], p.lo[i], p.hi[i], t, true);
+      const uint32_t ml = part_count(p.v, p.start[i], p.lo[i], mh, t, false);
+      p.mu_hi[i] = mh;
+      p.mu_lo[i] = ml;
+      slo += ml;
+      shi += mh;
+    }
+    slo = part_sum(slo, red);
+    shi = part_sum(shi, red);
+    if (slo <= m && m <= shi) {
+      // t is the threshold: the keys equal to t fill d = m - sum mu_lo,
+      // subarray by subarray in ascending i
+      const uint64_t d = m - slo;
+      uint64_t mine = 0;
+      for (uint32_t i = i0; i < i1; ++i) mine += p.mu_hi[i] - p.mu_lo[i];
+      uint64_t pre = part_excl(mine, red);
+      for (uint32_t i = i0; i < i1; ++i) {
+        const uint64_t cnt = p.mu_hi[i] - p.mu_lo[i];
+        const uint64_t take = pre >= d ? 0 : (d - pre < cnt ? d - pre : cnt);
+        p.m_out[i] = p.mu_lo[i] + (uint32_t)take;
+        pre += cnt;
+      }
+      path = 1;
+      break;
+    }
+    if (m < slo) {
+      for (uint32_t i = i0; i < i1; ++i) p.hi[i] = p.mu_lo[i];
+    } else {
+      for (uint32_t i = i0; i < i1; ++i) p.lo[i] = p.mu_hi[i];
+    }
+  }
+  if (!path && !err) {
+    // brackets of width <= 1: offers of the width-one subarrays (their keys
+    // kept in mu_lo); the d smallest by (key, i) go left
+    uint64_t s = 0;
+    for (uint32_t i = i0; i < i1; ++i) {
+      s += p.lo[i];
+      if (p.hi[i] == p.lo[i] + 1) p.mu_lo[i] = view_key(p.v, p.start[i] + p.lo[i]);
+    }
+    s = part_sum(s, red);
+    const uint64_t d = m - s;
+    // smallest key V with #{offers <= V} >= d
+    uint32_t va = 0, vb = 0xFFFFFFFFu;
+    while (va < vb) {
+      const uint32_t mid = va + (vb - va) / 2;
+      uint64_t c = 0;
+      for (uint32_t i = i0; i < i1; ++i) c += (p.hi[i] == p.lo[i] + 1 && p.mu_lo[i] <= mid) ? 1u : 0u;
+      c = part_sum(c, red);
+      if (c >= d) vb = mid;
+      else va = mid + 1;
+    }
+    uint64_t less = 0, eq = 0;
+    for (uint32_t i = i0; i < i1; ++i)
+      if (p.hi[i] == p.lo[i] + 1) {
+        less += p.mu_lo[i] < va ? 1u : 0u;
+        eq += p.mu_lo[i] == va ? 1u : 0u;
+      }
+    less = part_sum(less, red);
+    const uint64_t need = d - less;  // offers equal to V that go left, lowest i first
+    uint64_t pre = part_excl(eq, red);
+    for (uint32_t i = i0; i < i1; ++i) {
+      uint32_t add = 0;
+      if (p.hi[i] == p.lo[i] + 1) {
+        if (p.mu_lo[i] < va) add = 1;
+        else if (p.mu_lo[i] == va) add = pre++ < need ? 1u : 0u;
+      }
+      p.m_out[i] = p.lo[i] + add;
+    }
+    path = 2;
+  }
+  if (threadIdx.x == 0) {
+    p.status[0] = path;
+    p.status[1] = iter;
+    p.status[2] = err;
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1238,6 +1485,23 @@ hipError_t launch_set_ptrs(char** tab, uint32_t first, uint32_t count, const uin
                            hipStream_t s) {
   hipLaunchKernelGGL(k_set_ptrs, dim3(1), dim3(64), 0, s, tab, first, count, v[0], v[1], v[2], v[3],
                      v[4], v[5], v[6], v[7]);
+  return hipGetLastError();
+}
+
+hipError_t launch_copass_copy(const BlockView& v, const CopyList& l, bool to_packed, uint32_t* keys, uint2* pay,
+                              hipStream_t s) {
+  if (l.total == 0) return hipSuccess;
+  const uint32_t per = kCopyThreads * kCopyItems;
+  const uint32_t grid = std::min<uint32_t>((l.total + per - 1) / per, 4096u);
+  if (to_packed)
+    hipLaunchKernelGGL(k_copass_copy<true>, dim3(grid), dim3(kCopyThreads), 0, s, v, l, keys, pay);
+  else
+    hipLaunchKernelGGL(k_copass_copy<false>, dim3(grid), dim3(kCopyThreads), 0, s, v, l, keys, pay);
+  return hipGetLastError();
+}
+
+hipError_t launch_copass_partition(const CopassPart& p, hipStream_t s) {
+  hipLaunchKernelGGL(k_copass_partition, dim3(1), dim3(kPartThreads), 0, s, p);
   return hipGetLastError();
 }
 

@@ -195,6 +195,7 @@ struct ng_ctx {
 
   int radix_bits = 9;  // widest digit: the fewest passes
   uint32_t sort_ranges = 1024;  // static ranges (= workgroups) of each sort pass
+  int calib_mode = 0;           // NG_CALIB_RADIX or NG_CALIB_COPASS
   int sticky = NG_OK;
   std::string sticky_msg;
 

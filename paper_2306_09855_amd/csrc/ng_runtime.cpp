@@ -566,6 +566,272 @@ ng::SortSeg sort_seg(const CalSeg& g, int p) {
 
 uint64_t align256(uint64_t x) { return (x + 255) / 256 * 256; }
 
+// COPASS in-place block sort (Appendix A) of one context, then the group
+// index.  The connections stay in their blocks.  Scratch: the auxiliary
+// array and one or two sort buffers of one block each (packed key + payload,
+// 12 bytes per record; the first sort buffer doubles as the bounce buffer of
+// the shifts), the sort counts, the partition's per-subarray words and the
+// copy lists.
+int calibrate_copass(ng_ctx* c) {
+  if (c->capturing) return fail(NG_ERR_UNSUPPORTED, "a COPASS calibration reads partition sizes back; it cannot be captured");
+  CalSeg g;
+  g.c = c;
+  if (int rc = cal_plan(g)) return rc;
+  const uint64_t N = g.N, B = c->B;
+  const uint32_t k = (uint32_t)((N + B - 1) / B);
+  const uint64_t A = std::max<uint64_t>(1, std::min<uint64_t>(B, N));  // the largest block
+  const int P = g.passes;
+  const uint64_t tile = ng::sort_tile_size();
+  const uint64_t blk_tiles = (A + tile - 1) / tile;
+  // a sort of n <= A records uses ceil(tiles / ceil(tiles / sort_ranges)) <= min(sort_ranges, tiles) ranges
+  const uint64_t max_ranges = std::max<uint64_t>(1, std::min<uint64_t>(c->sort_ranges, blk_tiles));
+  uint32_t maxbits = 0;
+  for (int p = 0; p < P; ++p) maxbits = std::max(maxbits, g.nbits[p]);
+  const uint64_t counts_n = ((uint64_t)1 << maxbits) * max_ranges;
+  const uint64_t seg_cap = 5ull * k + 8;  // copy pieces of one step
+
+  AllocSet as(c);
+  uint32_t* aux_k = (uint32_t*)as.get(4 * A);
+  uint2* aux_p = (uint2*)as.get(8 * A);
+  uint32_t* s_k[2] = {nullptr, nullptr};
+  uint2* s_p[2] = {nullptr, nullptr};
+  for (int t = 0; t < (P >= 3 ? 2 : 1); ++t) {
+    s_k[t] = (uint32_t*)as.get(4 * A);
+    s_p[t] = (uint2*)as.get(8 * A);
+  }
+  uint32_t* counts = (uint32_t*)as.get(4 * counts_n);
+  const uint64_t tmp_words = std::max(ng::scan_tmp_words(counts_n), ng::scan_tmp_words(g.gi_tiles));
+  uint32_t* scan_tmp = (uint32_t*)as.get(4 * tmp_words);
+  uint32_t* part = (uint32_t*)as.get(4 * (7ull * std::max<uint32_t>(k, 1) + 4));
+  ng::CopySeg* d_lists = (ng::CopySeg*)as.get(sizeof(ng::CopySeg) * seg_cap);
+  uint32_t* tile_flags = (uint32_t*)as.get(4 * (g.gi_tiles + 1));
+  g.group_src = (uint32_t*)as.get(4 * g.gcap);
+  g.bitmap = (uint32_t*)as.get(4 * ((N + 31) / 32 + 1));
+  g.gp_bytes = 4 * (g.nn + 1ull);
+  g.gs_bytes = 4 * g.gcap;
+  release_index(c);
+  c->calibrated = false;
+  g.gptr = (uint32_t*)ctx_alloc(c, g.gp_bytes);
+  g.gstart = g.gptr ? (uint32_t*)ctx_alloc(c, g.gs_bytes) : nullptr;
+  if (!as.ok || !g.gptr || !g.gstart) {
+    as.release_all();
+    ctx_unalloc(c, (char*)g.gptr, g.gp_bytes);
+    ctx_unalloc(c, (char*)g.gstart, g.gs_bytes);
+    c->need = as.asked + Arena::round_up(g.gp_bytes) + Arena::round_up(g.gs_bytes);
+    return fail(NG_ERR_OOM, "arena cannot hold the COPASS scratch (block of %llu)", (unsigned long long)A);
+  }
+  uint32_t* d_start = part;
+  uint32_t* d_len = part + k;
+  uint32_t* d_lo = part + 2ull * k;
+  uint32_t* d_hi = part + 3ull * k;
+  uint32_t* d_mulo = part + 4ull * k;
+  uint32_t* d_muhi = part + 5ull * k;
+  uint32_t* d_mout = part + 6ull * k;
+  uint32_t* d_status = part + 7ull * k;
+  hipStream_t s = c->stream;
+  char** tab = c->d_tab[c->cur];
+  const ng::BlockView view{tab, c->log2B, (uint32_t)g.dbits};
+
+  auto run = [&]() -> int {
+    if (int rc = sync_table(c)) return rc;
+    // sort the packed records aux[0, n) into block b
+    auto sort_into = [&](uint32_t b, uint32_t n) -> int {
+      const uint64_t tiles = (n + tile - 1) / tile;
+      const uint32_t tpr = (uint32_t)std::max<uint64_t>(1, (tiles + c->sort_ranges - 1) / c->sort_ranges);
+      const uint32_t nr = (uint32_t)((tiles + tpr - 1) / tpr);
+      for (int p = 0; p < P; ++p) {
+        ng::SortSeg sg{};
+        sg.io.log2B = c->log2B;
+        sg.io.dbits = (uint32_t)g.dbits;
+        if (p == 0) {
+          sg.io.in_keys = aux_k;
+          sg.io.in_pay = aux_p;
+        } else {
+          sg.io.in_keys = s_k[(p - 1) & 1];
+          sg.io.in_pay = s_p[(p - 1) & 1];
+        }
+        if (p == P - 1) {
+          sg.io.out_blocks = tab + b;
+        } else {
+          sg.io.out_keys = s_k[p & 1];
+          sg.io.out_pay = s_p[p & 1];
+        }
+        sg.n = n;
+        sg.shift = g.shift[p];
+        sg.nbits = g.nbits[p];
+        sg.tiles_per_range = tpr;
+        sg.n_ranges = nr;
+        ng::SortPack pk{};
+        pk.one = sg;
+        pk.n_segs = 1;
+        pk.total_ranges = nr;
+        pk.ranges_per_xcd = (nr + 7) / 8;
+        pk.max_nbits = sg.nbits;
+        NG_LAUNCH(c, "upsweep", ng::launch_upsweep(pk, counts, s));
+        NG_LAUNCH(c, "scan", ng::launch_exclusive_scan(counts, counts, ((uint64_t)1 << sg.nbits) * nr, scan_tmp,
+                                                        nullptr, s));
+        NG_LAUNCH(c, "downsweep", ng::launch_downsweep(pk, counts, s));
+      }
+      return NG_OK;
+    };
+    auto block_len = [&](uint32_t b) -> uint32_t {
+      const uint64_t a = (uint64_t)b * B;
+      return (uint32_t)std::min<uint64_t>(B, N - a);
+    };
+    std::vector<ng::CopySeg> lists;
+    // (B) every block sorted: packed into the auxiliary array, sorted back
+    for (uint32_t b = 0; b < k; ++b) lists.push_back(ng::CopySeg{(uint32_t)((uint64_t)b * B), 0, block_len(b), 0});
+    if (k) {
+      if (int rc = stage_upload(c, d_lists, lists.data(), sizeof(ng::CopySeg) * lists.size())) return rc;
+    }
+    for (uint32_t b = 0; b < k; ++b) {
+      NG_LAUNCH(c, "copass_copy", ng::launch_copass_copy(view, ng::CopyList{d_lists + b, 1, block_len(b)}, true,
+                                                          aux_k, aux_p, s));
+      if (int rc = sort_into(b, block_len(b))) return rc;
+    }
+    // the remaining region holds k sorted subarrays; block b = 0, 1, ... is
+    // extracted in turn
+    std::vector<uint32_t> start(k), len(k), mi(k), st(4);
+    for (uint32_t i = 0; i < k; ++i) {
+      start[i] = (uint32_t)((uint64_t)i * B);
+      len[i] = block_len(i);
+    }
+    for (uint32_t b = 0; b < k; ++b) {
+      const uint32_t first = (uint32_t)((uint64_t)b * B), m = block_len(b);
+      const uint64_t remaining = N - first;
+      if (m < remaining) {
+        std::vector<uint32_t> sl(2ull * k);
+        std::copy(start.begin(), start.end(), sl.begin());
+        std::copy(len.begin(), len.end(), sl.begin() + k);
+        if (int rc = stage_upload(c, d_start, sl.data(), 8ull * k)) return rc;
+        ng::CopassPart pp{view, d_start, d_len, k, m, d_lo, d_hi, d_mulo, d_muhi, d_mout, d_status};
+        NG_LAUNCH(c, "copass_partition", ng::launch_copass_partition(pp, s));
+        NG_HIP(c, hipMemcpyAsync(mi.data(), d_mout, 4ull * k, hipMemcpyDeviceToHost, s), "partition sizes");
+        NG_HIP(c, hipMemcpyAsync(st.data(), d_status, 12, hipMemcpyDeviceToHost, s), "partition status");
+        NG_HIP(c, hipStreamSynchronize(s), "partition");
+        uint64_t sum = 0;
+        bool bad = st[2] != 0 || (st[0] != 1 && st[0] != 2);
+        for (uint32_t i = 0; i < k && !bad; ++i) {
+          bad = mi[i] > len[i];
+          sum += mi[i];
+        }
+        if (bad || sum != m) return dev_fail(c, hipErrorUnknown, "COPASS partition did not converge");
+      } else {
+        mi = len;
+      }
+      lists.clear();
+      // (D) left partitions to the auxiliary array
+      uint32_t q = 0;
+      for (uint32_t i = 0; i < k; ++i)
+        if (mi[i]) {
+          lists.push_back(ng::CopySeg{start[i], q, mi[i], q});
+          q += mi[i];
+        }
+      const uint32_t n_gather = (uint32_t)lists.size();
+      // (E) right partitions shifted to the end, last subarray last: new
+      // positions, and the moves of those that shift
+      std::vector<uint32_t> nstart(k), nlen(k);
+      uint64_t e = N;
+      for (uint32_t i = k; i-- > 0;) {
+        nlen[i] = len[i] - mi[i];
+        e -= nlen[i];
+        nstart[i] = (uint32_t)e;
+      }
+      struct Move {
+        uint32_t src, dst, len;
+      };
+      std::vector<Move> moves;
+      for (uint32_t i = 0; i < k; ++i)
+        if (nlen[i] && start[i] + mi[i] != nstart[i]) moves.push_back(Move{start[i] + mi[i], nstart[i], nlen[i]});
+      // chunks of at most one block, from the end: each is read into the
+      // bounce buffer, then written; the sources of lower chunks lie below
+      // the chunk, so no chunk overwrites what a later one reads
+      struct Chunk {
+        uint32_t off, n, total;
+      };
+      std::vector<Chunk> chunks;
+      uint64_t ce = N;
+      const uint64_t lo_end = (uint64_t)first + m;
+      while (ce > lo_end && !moves.empty()) {
+        const uint64_t cs = ce > lo_end + A ? ce - A : lo_end;
+        const uint32_t off = (uint32_t)lists.size();
+        uint32_t pre = 0;
+        for (const Move& mv : moves) {
+          const uint64_t a = std::max<uint64_t>(mv.dst, cs), z = std::min<uint64_t>((uint64_t)mv.dst + mv.len, ce);
+          if (a >= z) continue;
+          lists.push_back(ng::CopySeg{(uint32_t)(mv.src + (a - mv.dst)), (uint32_t)(a - cs), (uint32_t)(z - a), pre});
+          pre += (uint32_t)(z - a);
+        }
+        const uint32_t npiece = (uint32_t)lists.size() - off;
+        for (uint32_t j = 0; j < npiece; ++j) {
+          const ng::CopySeg& r = lists[off + j];
+          lists.push_back(ng::CopySeg{r.dst, (uint32_t)(cs + r.dst), r.len, r.pre});
+        }
+        if (npiece) chunks.push_back(Chunk{off, npiece, pre});
+        ce = cs;
+      }
+      if (lists.size() > seg_cap) return fail(NG_ERR_STATE, "COPASS copy list overflow");
+      if (!lists.empty())
+        if (int rc = stage_upload(c, d_lists, lists.data(), sizeof(ng::CopySeg) * lists.size())) return rc;
+      NG_LAUNCH(c, "copass_copy", ng::launch_copass_copy(view, ng::CopyList{d_lists, n_gather, m}, true, aux_k,
+                                                          aux_p, s));
+      for (const Chunk& ch : chunks) {
+        NG_LAUNCH(c, "copass_copy", ng::launch_copass_copy(view, ng::CopyList{d_lists + ch.off, ch.n, ch.total},
+                                                            true, s_k[0], s_p[0], s));
+        NG_LAUNCH(c, "copass_copy", ng::launch_copass_copy(view, ng::CopyList{d_lists + ch.off + ch.n, ch.n,
+                                                                               ch.total},
+                                                            false, s_k[0], s_p[0], s));
+      }
+      // (F) the auxiliary array sorted into block b
+      if (int rc = sort_into(b, m)) return rc;
+      start = nstart;
+      len = nlen;
+    }
+    // group index over the sorted blocks
+    ng::GiPack gp{};
+    ng::GiSeg gs{};
+    gs.blocks = tab;
+    gs.n = N;
+    gs.bitmap = g.bitmap;
+    gs.group_start = g.gstart;
+    gs.group_src = g.group_src;
+    gs.group_ptr = g.gptr;
+    gs.n_groups = c->d_scalars;
+    gs.tile0 = 0;
+    gs.n_tiles = (uint32_t)g.gi_tiles;
+    gs.n_nodes = g.nn;
+    gs.ptr_block0 = 0;
+    gs.n_ptr_blocks = ng::gi_ptr_blocks(g.nn);
+    gp.one = gs;
+    gp.n_segs = 1;
+    gp.total_tiles = gs.n_tiles;
+    gp.total_ptr_blocks = gs.n_ptr_blocks;
+    gp.log2B = c->log2B;
+    NG_LAUNCH(c, "group_flags", ng::launch_group_flags(gp, tile_flags, s));
+    NG_LAUNCH(c, "scan", ng::launch_exclusive_scan(tile_flags, tile_flags, g.gi_tiles, scan_tmp,
+                                                    tile_flags + g.gi_tiles, s));
+    NG_LAUNCH(c, "group_write", ng::launch_group_write(gp, tile_flags, s));
+    NG_LAUNCH(c, "group_ptr", ng::launch_group_ptr(gp, tile_flags, s));
+    return NG_OK;
+  };
+  if (int rc = run()) {
+    // scratch stays with the context's deferred frees; device state unknown
+    for (auto& it : as.items) ctx_free(c, it.first, it.second);
+    ctx_free(c, (char*)g.gptr, g.gp_bytes);
+    ctx_free(c, (char*)g.gstart, g.gs_bytes);
+    return rc;
+  }
+  for (auto& it : as.items) ctx_free(c, it.first, it.second);
+  c->d_group_ptr = g.gptr;
+  c->group_ptr_bytes = g.gp_bytes;
+  c->d_group_start = g.gstart;
+  c->group_start_bytes = g.gs_bytes;
+  c->gi_nodes = g.nn;
+  c->calibrated = true;
+  ctx_flush_frees(c);
+  return NG_OK;
+}
+
 }  // namespace
 
 int calibrate_many(ng_ctx* const* cs, uint32_t n, const Uploader* upload) {
@@ -582,6 +848,12 @@ int calibrate_many(ng_ctx* const* cs, uint32_t n, const Uploader* upload) {
       if (cs[i]->log2B != cs[0]->log2B) return fail(NG_ERR_INVALID_ARG, "contexts with different block sizes");
     }
   }
+  // contexts in COPASS mode, one by one
+  for (uint32_t i = 0; i < n; ++i)
+    if (!cs[i]->calibrated && cs[i]->calib_mode == NG_CALIB_COPASS) {
+      if (hipSetDevice(cs[i]->device) != hipSuccess) return fail(NG_ERR_DEVICE, "hipSetDevice");
+      if (int rc = calibrate_copass(cs[i])) return rc;
+    }
   std::vector<CalSeg> segs;
   for (uint32_t i = 0; i < n; ++i)
     if (!cs[i]->calibrated) {
@@ -989,6 +1261,14 @@ int ng_set_tuning(ng_ctx* c, int radix_bits, uint32_t sort_ranges) {
   if (sort_ranges < 1 || sort_ranges > (1u << 20)) return fail(NG_ERR_INVALID_ARG, "sort_ranges in [1, 2^20]");
   c->radix_bits = radix_bits;
   c->sort_ranges = sort_ranges;
+  return NG_OK;
+}
+
+int ng_set_calibration(ng_ctx* c, int algorithm) {
+  if (!c) return fail(NG_ERR_INVALID_ARG, "null context");
+  if (algorithm != NG_CALIB_RADIX && algorithm != NG_CALIB_COPASS)
+    return fail(NG_ERR_INVALID_ARG, "unknown calibration algorithm %d", algorithm);
+  c->calib_mode = algorithm;
   return NG_OK;
 }
 

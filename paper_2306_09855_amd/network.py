@@ -56,6 +56,10 @@ class Network:
     def tune(self, radix_bits: int, sort_ranges: int = 1024):
         ng.ng_set_tuning(self.ctx, radix_bits, sort_ranges)
 
+    def set_calibration(self, algorithm: str):
+        """"radix" (default) or "copass": the in-place block sort of the appendix."""
+        ng.ng_set_calibration(self.ctx, algorithm)
+
     def build(self, workload, batched: bool = False, calibrate: bool = True):
         for n in workload.populations:
             self.create(n)

@@ -120,6 +120,7 @@ def lib():
             "ng_copy_connections": ([vp, u64, u64, vp, vp, vp, vp], ctypes.c_int),
             "ng_copy_group_index": ([vp, vp, vp], ctypes.c_int),
             "ng_set_tuning": ([vp, ctypes.c_int, u32], ctypes.c_int),
+            "ng_set_calibration": ([vp, ctypes.c_int], ctypes.c_int),
             "ng_memory_stats": ([vp, P(u64), P(u64), P(u64)], ctypes.c_int),
             "ng_reset": ([vp], ctypes.c_int),
             "ng_enable_timing": ([vp, ctypes.c_int], ctypes.c_int),
@@ -315,6 +316,15 @@ def ng_graph_destroy(graph) -> None:
 
 def ng_set_tuning(ctx, radix_bits: int, sort_ranges: int = 1024) -> None:
     _check(lib().ng_set_tuning(ctx, radix_bits, sort_ranges))
+
+
+NG_CALIB_RADIX, NG_CALIB_COPASS = 0, 1
+CALIBRATIONS = {"radix": NG_CALIB_RADIX, "copass": NG_CALIB_COPASS}
+
+
+def ng_set_calibration(ctx, algorithm) -> None:
+    """Calibration algorithm: "radix" (default) or "copass" (in-place block sort)."""
+    _check(lib().ng_set_calibration(ctx, CALIBRATIONS.get(algorithm, algorithm)))
 
 
 def ng_memory_stats(ctx):

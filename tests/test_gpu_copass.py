@@ -1,0 +1,135 @@
+"""GPU parity of the COPASS in-place block sort (Appendix A), through the C ABI.
+
+The COPASS calibration must give exactly the arrays of the stable order (the
+readings of the appendix's tie cases make the result unique), so it is checked
+against the CPU oracle element by element like the radix path, on layouts with
+many blocks, a ragged last block, one block, and heavy key ties; against the
+radix path bit for bit at a larger size; and for its memory saving.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2306_09855_amd import workloads as W
+from parity import check_calibrated, check_creation_order
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2306_09855_amd import ng  # noqa: E402
+from paper_2306_09855_amd.network import Network, arena_bytes_for  # noqa: E402
+
+B16 = 1 << 16
+
+
+def _run(wl, block_size, mode, arena=None):
+    arena = arena or arena_bytes_for(wl.n_syn, wl.n_nodes, wl.max_delay, block_size)
+    with Network(wl.seed, wl.h, block_size, arena) as net:
+        net.set_calibration(mode)
+        net.build(wl, calibrate=False)
+        created = net.fetch()
+        net.calibrate()
+        out = net.fetch()
+        gp, gs = net.group_index()
+    return created, out, gp, gs
+
+
+def _ftn(n_src, n_tgt, total, delay=("uniform_int", 1, 20), seed=7):
+    calls = [W.Call("fixed_total_number", (0, n_src), (n_src, n_tgt), total, ("normal", 0.5, 0.05), delay)]
+    return W.Workload("copass_ftn", seed, [n_src, n_tgt], calls)
+
+
+CASES = {
+    # 16 blocks of 2^16, the last one ragged
+    "microcircuit_16_blocks": lambda: W.microcircuit(total=1_000_000),
+    # exactly 5 full blocks
+    "five_full_blocks": lambda: _ftn(3000, 3000, 5 * B16),
+    # fewer connections than one block
+    "one_block": lambda: _ftn(400, 400, 50_000),
+    # three sources and one delay: a few keys shared by ~10^5 connections each
+    "heavy_ties": lambda: _ftn(3, 50, 7 * B16 + 123, delay=("const", 1.0)),
+    # several calls of different rules
+    "mixed_rules": lambda: W.two_pop_mixed(scale=0.05),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_copass_matches_oracle(name):
+    wl = CASES[name]()
+    ref = oracle.build_network(wl.seed, wl.h, wl.n_nodes, wl.calls)
+    created, out, gp, gs = _run(wl, B16, "copass")
+    check_creation_order(created, ref, wl.calls)
+    check_calibrated(out, gp, gs, ref, wl.calls)
+
+
+def test_copass_equals_radix_bitwise():
+    wl = W.microcircuit(total=6_000_000)
+    B = 1 << 18  # 23 blocks
+    _, a, gpa, gsa = _run(wl, B, "radix")
+    _, b, gpb, gsb = _run(wl, B, "copass")
+    for k in ("src", "tgt", "delay"):
+        assert np.array_equal(a[k], b[k]), k
+    assert np.array_equal(a["w"].view(np.int32), b["w"].view(np.int32))
+    assert np.array_equal(gpa, gpb) and np.array_equal(gsa, gsb)
+
+
+def test_copass_peak_memory_below_radix():
+    wl = W.microcircuit(total=4_000_000)
+    B = 1 << 18
+    peaks = {}
+    for mode in ("radix", "copass"):
+        with Network(wl.seed, wl.h, B, arena_bytes_for(wl.n_syn, wl.n_nodes, wl.max_delay, B)) as net:
+            net.set_calibration(mode)
+            net.build(wl, calibrate=False)
+            net.calibrate()
+            net.fetch(0, 1)
+            peaks[mode] = net.memory_stats()[1]
+    data = 14 * (-(-wl.n_syn // B)) * B
+    # both build the group index: group_start and group sources (4 bytes per
+    # possible group each), the flag bitmap, group_ptr
+    gcap = min(wl.n_syn, wl.n_nodes * wl.max_delay) + 1
+    index = 8 * gcap + wl.n_syn // 8 + 4 * (wl.n_nodes + 1)
+    # radix: a second block set and two ping-pong copies; COPASS: three
+    # one-block buffers of 12 bytes per record on top of the blocks
+    assert peaks["radix"] > data + index + 30 * wl.n_syn
+    assert peaks["copass"] < data + index + 36 * B + (1 << 20)
+
+
+def test_copass_empty_and_capture():
+    with Network(1, 0.1, B16, 64 << 20) as net:
+        net.set_calibration("copass")
+        net.calibrate()  # no connections
+        assert net.fetch(0, 0)["src"].size == 0
+    wl = _ftn(100, 100, 10_000)
+    stream = torch.cuda.Stream()  # capture needs a stream of its own
+    with Network(wl.seed, wl.h, B16, 64 << 20, stream=stream.cuda_stream) as net:
+        net.set_calibration("copass")
+        net.build(wl, calibrate=False)
+        ng.ng_graph_begin(net.ctx)
+        with pytest.raises(ng.NGError) as e:
+            net.calibrate()
+        ng.ng_graph_destroy(ng.ng_graph_end(net.ctx))
+        assert e.value.status == ng.NG_ERR_UNSUPPORTED
+
+
+def test_copass_in_packed_call():
+    # ng_calibrate_many with one COPASS and one radix context
+    wa, wb = _ftn(500, 500, 200_000, seed=1), _ftn(700, 300, 150_000, seed=2)
+    refs = [oracle.build_network(w.seed, w.h, w.n_nodes, w.calls) for w in (wa, wb)]
+    nets = [Network(w.seed, w.h, B16, 64 << 20) for w in (wa, wb)]
+    try:
+        nets[0].set_calibration("copass")
+        for n, w in zip(nets, (wa, wb)):
+            n.build(w, calibrate=False)
+        from paper_2306_09855_amd.network import calibrate_many
+        calibrate_many(nets)
+        for n, w, ref in zip(nets, (wa, wb), refs):
+            out = n.fetch()
+            gp, gs = n.group_index()
+            check_calibrated(out, gp, gs, ref, w.calls)
+    finally:
+        for n in nets:
+            n.close()
