@@ -254,6 +254,61 @@ def serving_bench(n_streams=4, block_size=1 << 20, loads=(0.5, 1.0, 2.0, 4.0), b
             "sweep": sweep}
 
 
+def copass_bench(wl, block_size: int, steps: int, warmup: int, radix_bits: int, sort_ranges: int) -> dict:
+    """The same build with the COPASS in-place block sort as calibration:
+    time per step, per-kernel times, the copies' bandwidth and peak arena use."""
+    import torch
+    from paper_2306_09855_amd import ng
+    from paper_2306_09855_amd.network import Network, arena_bytes_for
+
+    arena = arena_bytes_for(wl.n_syn, wl.n_nodes, wl.max_delay, block_size, 9)
+    side = torch.cuda.Stream()
+    net = Network(wl.seed, wl.h, block_size, arena, stream=side.cuda_stream)
+    net.tune(radix_bits, sort_ranges)
+    net.set_calibration("copass")
+    ctx = net.ctx
+    calls = [ng.call_args(c) for c in wl.calls]
+
+    def step():
+        ng.ng_reset(ctx)
+        for n in wl.populations:
+            ng.ng_create_nodes(ctx, n)
+        for a in calls:
+            ng.ng_connect(ctx, *a)
+        ng.ng_calibrate(ctx)
+
+    for _ in range(warmup):
+        step()
+    ng.ng_sync(ctx)
+    ng.ng_enable_timing(ctx, True)
+    ng.ng_read_timing(ctx, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    ng.ng_sync(ctx)
+    t1 = time.perf_counter()
+    kernels = ng.ng_read_timing(ctx, reset=True, records=True)
+    ng.ng_enable_timing(ctx, False)
+    peak = net.memory_stats()[1]
+    net.close()
+    ms = 1e3 * (t1 - t0) / steps
+    per = {}
+    for name, (launches, total_ms, recs) in kernels.items():
+        k_ms = total_ms / steps
+        gbps = None
+        if name == "copass_copy" and k_ms > 0:
+            gbps = round(26.0 * recs / steps / (k_ms / 1e3) / 1e9, 1)  # read 14 + write 12 bytes, or 12 + 14
+        per[name] = {"launches_per_step": launches / steps, "ms_per_step": round(k_ms, 4), "GBps_algorithmic": gbps}
+        if name == "copass_copy":
+            per[name]["records_per_step"] = recs / steps
+    gen_ms = per.get("generate", {}).get("ms_per_step", 0.0)
+    return {"ms_per_step": round(ms, 3), "synapses_per_s": wl.n_syn / (ms / 1e3),
+            "calibrate_device_ms": round(sum(v["ms_per_step"] for v in per.values()) - gen_ms, 3),
+            "block_size": block_size, "blocks": -(-wl.n_syn // block_size),
+            "peak_arena_GiB": round(peak / 2**30, 3), "kernels": per}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -270,6 +325,8 @@ def main() -> int:
     ap.add_argument("--block-size", type=int, default=1 << 24)
     ap.add_argument("--cpu-sample", type=float, default=6e7, help="synapses of the oracle sample; 0 skips")
     ap.add_argument("--total", type=float, default=3.0e8)
+    ap.add_argument("--copass", type=int, default=1,
+                    help="also time the COPASS in-place calibration on the same build (plain form)")
     ap.add_argument("--serve", type=int, default=1,
                     help="also run the serving trace (32 sessions; p50/p99 Connect latency); 0 skips")
     ap.add_argument("--copy-probe", type=float, default=0,
@@ -418,9 +475,17 @@ def main() -> int:
         "roofline": roofline,
         "kernels": per_kernel,
     }
+    radix_peak = net.memory_stats()[1]
     net.close()
     del net
     torch.cuda.empty_cache()
+    if args.copass and args.form == "plain":
+        cp = copass_bench(wl, args.block_size, max(1, min(args.steps, 3)), 1, args.radix_bits, args.sort_ranges)
+        cp["radix_peak_arena_GiB"] = round(radix_peak / 2**30, 3)
+        log(f"copass: {cp['ms_per_step']} ms/step, peak arena {cp['peak_arena_GiB']} GiB "
+            f"(radix {cp['radix_peak_arena_GiB']} GiB)")
+        result["copass"] = cp
+        torch.cuda.empty_cache()
     if args.serve:
         sv = serving_bench()
         result["serving"] = sv

@@ -230,11 +230,14 @@ int ng_reset(ng_ctx* ctx);
 
 /* Per-kernel device time: with timing on, every kernel launch of the context
  * is bracketed by HIP events on its stream.  ng_read_timing synchronizes and
- * reports, per kernel name, the number of launches and the summed time. */
+ * reports, per kernel name, the number of launches, the summed time and the
+ * records the launches processed where a kernel reports them (the COPASS
+ * copies: records copied), else 0. */
 typedef struct {
   char name[24];
   uint64_t launches;
   double total_ms;
+  uint64_t records;
 } ng_kernel_time;
 int ng_enable_timing(ng_ctx* ctx, int on);
 int ng_read_timing(ng_ctx* ctx, ng_kernel_time* out, int capacity, int* count, int reset);

@@ -203,11 +203,16 @@ struct ng_ctx {
   struct Timed {
     const char* name;
     hipEvent_t a, b;
+    uint64_t records;
+  };
+  struct TimeAcc {
+    double ms = 0;
+    uint64_t launches = 0, records = 0;
   };
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
   std::vector<Timed> pending;
-  std::map<std::string, std::pair<double, uint64_t>> timing_acc;
+  std::map<std::string, TimeAcc> timing_acc;
 
   // graph capture: while capturing, nothing may synchronize; descriptors go
   // to a pinned region the graph owns.  A context with live graphs is frozen.
@@ -319,7 +324,7 @@ void connect_commit(ng_ctx* c, const ng::GenDesc& d, int32_t max_delay);
   } while (0)
 
 // Launch `expr` on the context stream; with timing on, bracket it by events.
-#define NG_LAUNCH(ctx, name, expr)                                              \
+#define NG_LAUNCH_N(ctx, name, recs, expr)                                      \
   do {                                                                          \
     hipEvent_t a_ = nullptr;                                                    \
     if ((ctx)->timing && (a_ = take_event(ctx)) != nullptr)                     \
@@ -330,9 +335,10 @@ void connect_commit(ng_ctx* c, const ng::GenDesc& d, int32_t max_delay);
       hipEvent_t b_ = take_event(ctx);                                          \
       if (b_) {                                                                 \
         (void)hipEventRecord(b_, (ctx)->stream);                                \
-        (ctx)->pending.push_back({name, a_, b_});                               \
+        (ctx)->pending.push_back({name, a_, b_, (uint64_t)(recs)});             \
       } else {                                                                  \
         (ctx)->ev_pool.push_back(a_);                                           \
       }                                                                         \
     }                                                                           \
   } while (0)
+#define NG_LAUNCH(ctx, name, expr) NG_LAUNCH_N(ctx, name, 0, expr)

@@ -179,8 +179,9 @@ void collect_timing(ng_ctx* c) {
     float ms = 0;
     if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
       auto& acc = c->timing_acc[t.name];
-      acc.first += ms;
-      acc.second += 1;
+      acc.ms += ms;
+      acc.launches += 1;
+      acc.records += t.records;
     }
     c->ev_pool.push_back(t.a);
     c->ev_pool.push_back(t.b);
@@ -685,8 +686,8 @@ int calibrate_copass(ng_ctx* c) {
       if (int rc = stage_upload(c, d_lists, lists.data(), sizeof(ng::CopySeg) * lists.size())) return rc;
     }
     for (uint32_t b = 0; b < k; ++b) {
-      NG_LAUNCH(c, "copass_copy", ng::launch_copass_copy(view, ng::CopyList{d_lists + b, 1, block_len(b)}, true,
-                                                          aux_k, aux_p, s));
+      NG_LAUNCH_N(c, "copass_copy", block_len(b),
+                  ng::launch_copass_copy(view, ng::CopyList{d_lists + b, 1, block_len(b)}, true, aux_k, aux_p, s));
       if (int rc = sort_into(b, block_len(b))) return rc;
     }
     // the remaining region holds k sorted subarrays; block b = 0, 1, ... is
@@ -773,14 +774,15 @@ int calibrate_copass(ng_ctx* c) {
       if (lists.size() > seg_cap) return fail(NG_ERR_STATE, "COPASS copy list overflow");
       if (!lists.empty())
         if (int rc = stage_upload(c, d_lists, lists.data(), sizeof(ng::CopySeg) * lists.size())) return rc;
-      NG_LAUNCH(c, "copass_copy", ng::launch_copass_copy(view, ng::CopyList{d_lists, n_gather, m}, true, aux_k,
-                                                          aux_p, s));
+      NG_LAUNCH_N(c, "copass_copy", m,
+                  ng::launch_copass_copy(view, ng::CopyList{d_lists, n_gather, m}, true, aux_k, aux_p, s));
       for (const Chunk& ch : chunks) {
-        NG_LAUNCH(c, "copass_copy", ng::launch_copass_copy(view, ng::CopyList{d_lists + ch.off, ch.n, ch.total},
-                                                            true, s_k[0], s_p[0], s));
-        NG_LAUNCH(c, "copass_copy", ng::launch_copass_copy(view, ng::CopyList{d_lists + ch.off + ch.n, ch.n,
-                                                                               ch.total},
-                                                            false, s_k[0], s_p[0], s));
+        NG_LAUNCH_N(c, "copass_copy", ch.total,
+                    ng::launch_copass_copy(view, ng::CopyList{d_lists + ch.off, ch.n, ch.total}, true, s_k[0],
+                                           s_p[0], s));
+        NG_LAUNCH_N(c, "copass_copy", ch.total,
+                    ng::launch_copass_copy(view, ng::CopyList{d_lists + ch.off + ch.n, ch.n, ch.total}, false,
+                                           s_k[0], s_p[0], s));
       }
       // (F) the auxiliary array sorted into block b
       if (int rc = sort_into(b, m)) return rc;
@@ -1393,8 +1395,9 @@ int ng_read_timing(ng_ctx* c, ng_kernel_time* out, int capacity, int* count, int
     if (out && n < capacity) {
       memset(&out[n], 0, sizeof(out[n]));
       strncpy(out[n].name, kv.first.c_str(), sizeof(out[n].name) - 1);
-      out[n].launches = kv.second.second;
-      out[n].total_ms = kv.second.first;
+      out[n].launches = kv.second.launches;
+      out[n].total_ms = kv.second.ms;
+      out[n].records = kv.second.records;
     }
     ++n;
   }

@@ -73,7 +73,8 @@ class ng_conn_view(ctypes.Structure):
 
 
 class ng_kernel_time(ctypes.Structure):
-    _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double)]
+    _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double),
+                ("records", ctypes.c_uint64)]
 
 
 class ng_server_config(ctypes.Structure):
@@ -287,13 +288,18 @@ def ng_enable_timing(ctx, on: bool = True) -> None:
     _check(lib().ng_enable_timing(ctx, 1 if on else 0))
 
 
-def ng_read_timing(ctx, reset: bool = True) -> dict:
-    """{kernel name: (launches, total ms)} of the timed launches so far."""
+def ng_read_timing(ctx, reset: bool = True, records: bool = False) -> dict:
+    """{kernel name: (launches, total ms)} of the timed launches so far;
+    with records=True, (launches, total ms, records processed)."""
     cap = 64
     arr = (ng_kernel_time * cap)()
     n = ctypes.c_int()
     _check(lib().ng_read_timing(ctx, arr, cap, ctypes.byref(n), 1 if reset else 0))
-    return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms)) for i in range(min(n.value, cap))}
+    rng = range(min(n.value, cap))
+    if records:
+        return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms), int(arr[i].records))
+                for i in rng}
+    return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms)) for i in rng}
 
 
 def ng_graph_begin(ctx, staging_bytes: int = 0) -> None:

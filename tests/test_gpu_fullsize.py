@@ -107,3 +107,21 @@ def test_many_output_blocks_stable_sort():
     for k in ("src", "tgt", "delay"):
         assert torch.equal(created[k][order], out[k]), k
     assert torch.equal(created["w"][order].view(torch.int32), out["w"].view(torch.int32))
+
+
+def test_full_size_copass_equals_radix(microcircuit_full):
+    # the COPASS in-place block sort (18 blocks of 2^24) gives the radix
+    # path's arrays and group index bit for bit
+    wl, _, out, gp, gs = microcircuit_full
+    net = Network(wl.seed, wl.h, 0, arena_bytes_for(wl.n_syn, wl.n_nodes, wl.max_delay))
+    try:
+        net.set_calibration("copass")
+        net.build(wl)
+        cp = net.fetch(device=True)
+        gp2, gs2 = net.group_index()
+    finally:
+        net.close()
+    for k in ("src", "tgt", "delay"):
+        assert torch.equal(cp[k], out[k]), k
+    assert torch.equal(cp["w"].view(torch.int32), out["w"].view(torch.int32))
+    assert np.array_equal(gp2, gp) and np.array_equal(gs2, gs)
