@@ -49,6 +49,8 @@ class _Call(ctypes.Structure):
         ("k_or_n", ctypes.c_uint64),
         ("w_kind", ctypes.c_int32), ("w_a", ctypes.c_double), ("w_b", ctypes.c_double),
         ("d_kind", ctypes.c_int32), ("d_a", ctypes.c_double), ("d_b", ctypes.c_double),
+        ("src_idx", ctypes.c_void_p), ("tgt_idx", ctypes.c_void_p),
+        ("w_arr", ctypes.c_void_p), ("d_arr", ctypes.c_void_p),
     ]
 
 
@@ -104,11 +106,28 @@ def _ptr(a: np.ndarray):
 
 
 def to_struct(call) -> _Call:
+    """Call -> ora_call.  Optional attributes src_idx / tgt_idx (node arrays;
+    then src / tgt give (0, array length)) and w_arr / d_arr (per-connection
+    weights, delays in ms) are passed as arrays; the struct keeps them alive."""
     wk, wa, wb = (tuple(call.weight) + (0.0, 0.0))[:3]
     dk, da, db = (tuple(call.delay) + (0.0, 0.0))[:3]
-    return _Call(RULES[call.rule], int(call.src[0]), int(call.src[1]),
-                 int(call.tgt[0]), int(call.tgt[1]), int(call.k_or_n),
-                 KINDS[wk], float(wa), float(wb), KINDS[dk], float(da), float(db))
+    keep = []
+
+    def arr(name, dt):
+        a = getattr(call, name, None)
+        if a is None:
+            return None
+        a = np.ascontiguousarray(a, dtype=dt)
+        keep.append(a)
+        return a.ctypes.data
+
+    st = _Call(RULES[call.rule], int(call.src[0]), int(call.src[1]),
+               int(call.tgt[0]), int(call.tgt[1]), int(call.k_or_n),
+               KINDS[wk], float(wa), float(wb), KINDS[dk], float(da), float(db),
+               arr("src_idx", np.uint32), arr("tgt_idx", np.uint32),
+               arr("w_arr", np.float32), arr("d_arr", np.float32))
+    st._keep = keep
+    return st
 
 
 # --- elementary pieces --------------------------------------------------------

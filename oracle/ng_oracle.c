@@ -119,7 +119,7 @@ int64_t ora_count(const ora_call* c) {
   }
 }
 
-static int delay_is_random(const ora_call* c) { return c->d_kind != ORA_CONST; }
+static int delay_is_random(const ora_call* c) { return c->d_arr == NULL && c->d_kind != ORA_CONST; }
 
 int ora_words_per_synapse(const ora_call* c) {
   int draws = 0;
@@ -163,10 +163,13 @@ int ora_synapse(uint64_t seed, float h, uint32_t cid, const ora_call* c, uint64_
     default:
       return -1;
   }
-  *src = c->s0 + (uint32_t)s_off;
-  *tgt = c->t0 + (uint32_t)t_off;
+  /* explicit node arrays: the formulas give the array position */
+  *src = c->src_idx ? c->src_idx[s_off] : c->s0 + (uint32_t)s_off;
+  *tgt = c->tgt_idx ? c->tgt_idx[t_off] : c->t0 + (uint32_t)t_off;
 
-  switch (c->d_kind) {
+  if (c->d_arr) {
+    *delay = ora_delay_steps(c->d_arr[i], h);
+  } else switch (c->d_kind) {
     case ORA_CONST:
       *delay = ora_delay_steps((float)c->d_a, h);
       break;
@@ -182,6 +185,10 @@ int ora_synapse(uint64_t seed, float h, uint32_t cid, const ora_call* c, uint64_
       return -1;
   }
 
+  if (c->w_arr) {
+    *w = (double)c->w_arr[i];
+    return 0;
+  }
   switch (c->w_kind) {
     case ORA_CONST:
       *w = c->w_a;

@@ -53,6 +53,16 @@ typedef struct {
   uint64_t k_or_n;      /* K for in/out-degree, total for fixed_total_number */
   int32_t w_kind;  double w_a, w_b;   /* CONST a | NORMAL(mean a, sd b) | UNIFORM [a,b) */
   int32_t d_kind;  double d_a, d_b;   /* CONST a ms | UNIFORM_INT {a..b} steps | UNIFORM [a,b) ms */
+  /* Sec. 2.1, last paragraphs: node groups given as arrays, and weights or
+   * delays given per connection.  NULL = not used.  With src_idx the rule's
+   * source formula (taken with s0 = 0) gives the position in src_idx of the
+   * source node (ns = array length); likewise tgt_idx.  w_arr[i] is the
+   * weight of synapse i of the call; d_arr[i] its delay in ms, converted to
+   * steps like a constant delay.  A delay given by an array is not random. */
+  const uint32_t* src_idx;
+  const uint32_t* tgt_idx;
+  const float* w_arr;
+  const float* d_arr;
 } ora_call;
 
 /* Philox4x32-10 block function */
