@@ -309,6 +309,68 @@ def copass_bench(wl, block_size: int, steps: int, warmup: int, radix_bits: int, 
             "peak_arena_GiB": round(peak / 2**30, 3), "kernels": per}
 
 
+def arrays_bench(wl, block_size: int, steps: int, warmup: int, radix_bits: int, sort_ranges: int) -> dict:
+    """The same build with every call's source group given as an index array
+    (a random permutation of its population) and per-connection weights and
+    delays (ng_connect_groups): time per step and the bandwidth of the pass
+    that applies the arrays."""
+    import numpy as np
+    import torch
+    from paper_2306_09855_amd import ng
+    from paper_2306_09855_amd.network import Network, arena_bytes_for
+
+    arena = arena_bytes_for(wl.n_syn, wl.n_nodes, wl.max_delay, block_size, 9)
+    side = torch.cuda.Stream()
+    net = Network(wl.seed, wl.h, block_size, arena, stream=side.cuda_stream)
+    net.tune(radix_bits, sort_ranges)
+    ctx = net.ctx
+    g = torch.Generator(device="cuda").manual_seed(1)
+    args = []
+    for c in wl.calls:
+        s0, ns = c.src
+        idx = (torch.randperm(ns, device="cuda", generator=g) + s0).to(torch.int32)
+        n = c.n_syn()
+        w = torch.randn(n, device="cuda", generator=g) * 0.05 + 0.5
+        d = torch.rand(n, device="cuda", generator=g) * 3.0  # ms: 1..30 steps at h = 0.1
+        args.append((ng.group(idx), ng.group(c.tgt), ng.conn_spec(c.rule, c.k_or_n),
+                     ng.syn_spec(c.weight, c.delay), w, d, idx))
+    torch.cuda.synchronize()
+
+    def step():
+        ng.ng_reset(ctx)
+        for n in wl.populations:
+            ng.ng_create_nodes(ctx, n)
+        for a in args:
+            ng.ng_connect_groups(ctx, *a[:4], a[4], a[5])
+        ng.ng_calibrate(ctx)
+
+    for _ in range(warmup):
+        step()
+    ng.ng_sync(ctx)
+    ng.ng_enable_timing(ctx, True)
+    ng.ng_read_timing(ctx, reset=True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    ng.ng_sync(ctx)
+    t1 = time.perf_counter()
+    kernels = ng.ng_read_timing(ctx, reset=True)
+    ng.ng_enable_timing(ctx, False)
+    net.close()
+    ms = 1e3 * (t1 - t0) / steps
+    # per connection: source position read 4 + index read 4 + source write 4,
+    # weight read 4 + write 4, delay read 4 + write 2
+    ab = 26.0 * wl.n_syn
+    per = {}
+    for name, (launches, total_ms) in kernels.items():
+        k_ms = total_ms / steps
+        per[name] = {"launches_per_step": launches / steps, "ms_per_step": round(k_ms, 4),
+                     "GBps_algorithmic": round(ab / (k_ms / 1e3) / 1e9, 1) if name == "apply_arrays" and k_ms else None}
+    return {"ms_per_step": round(ms, 3), "synapses_per_s": wl.n_syn / (ms / 1e3),
+            "arrays": "source index arrays (permuted populations), per-connection weights and delays",
+            "apply_bytes_per_connection": 26, "kernels": per}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -325,6 +387,8 @@ def main() -> int:
     ap.add_argument("--block-size", type=int, default=1 << 24)
     ap.add_argument("--cpu-sample", type=float, default=6e7, help="synapses of the oracle sample; 0 skips")
     ap.add_argument("--total", type=float, default=3.0e8)
+    ap.add_argument("--arrays", type=int, default=1,
+                    help="also time the build with index arrays and per-connection weights/delays")
     ap.add_argument("--copass", type=int, default=1,
                     help="also time the COPASS in-place calibration on the same build (plain form)")
     ap.add_argument("--serve", type=int, default=1,
@@ -485,6 +549,11 @@ def main() -> int:
         log(f"copass: {cp['ms_per_step']} ms/step, peak arena {cp['peak_arena_GiB']} GiB "
             f"(radix {cp['radix_peak_arena_GiB']} GiB)")
         result["copass"] = cp
+        torch.cuda.empty_cache()
+    if args.arrays and args.form == "plain" and wl.name == "microcircuit":
+        ar = arrays_bench(wl, args.block_size, max(1, min(args.steps, 3)), 1, args.radix_bits, args.sort_ranges)
+        log(f"arrays: {ar['ms_per_step']} ms/step")
+        result["arrays"] = ar
         torch.cuda.empty_cache()
     if args.serve:
         sv = serving_bench()

@@ -152,6 +152,38 @@ int ng_connect(ng_ctx* ctx, ng_range src, ng_range tgt, const ng_conn_spec* conn
                const ng_syn_spec* syn, uint32_t* out_connect_id, uint64_t* out_first,
                uint64_t* out_n);
 
+/* A node group (Sec. 2.1): the consecutive indices [first, first + n) when
+ * idx is NULL; else the n node indices idx[0..n) (device memory, u32, each
+ * below the node count, repeats allowed) and first must be 0. */
+typedef struct {
+  uint32_t first, n;
+  const uint32_t* idx;
+} ng_group;
+
+/* A Connect call whose node groups may be index arrays and whose weights or
+ * delays may be given per connection (Sec. 2.1, last paragraphs).  Same as
+ * ng_connect, except:
+ *   - a group with an index array takes its node indices from the array, at
+ *     the positions the rule's formulas give (the formulas taken from 0);
+ *   - weights != NULL: weights[i] (device, f32, one per connection of the
+ *     call, creation order) is the weight of connection i; syn->weight is
+ *     ignored and no weight words are drawn;
+ *   - delays_ms != NULL: delays_ms[i] (device, f32, ms) is the delay of
+ *     connection i, converted to steps like a constant delay (divided by the
+ *     resolution in fp32, rounded to nearest even, at least one step);
+ *     syn->delay is ignored and the connection draws no delay word, so its
+ *     source and target draws are those of a constant-delay call.
+ * The random words of everything else are those of ng_connect.  With any
+ * array the call first checks the arrays on the device (indices below the
+ * node count; delays finite and at most 32767 steps) and synchronizes:
+ * NG_ERR_INVALID_ARG if a check fails (nothing changed), NG_ERR_STATE under
+ * graph capture, NG_ERR_UNSUPPORTED with allow_autapses = 0.  The arrays must
+ * stay valid until the context's stream has run the call's generation.  With
+ * no array it is ng_connect. */
+int ng_connect_groups(ng_ctx* ctx, ng_group src, ng_group tgt, const ng_conn_spec* conn,
+                      const ng_syn_spec* syn, const float* weights, const float* delays_ms,
+                      uint32_t* out_connect_id, uint64_t* out_first, uint64_t* out_n);
+
 /* Many Connect calls at once, with results identical to issuing them one by
  * one with ng_connect in array order: one generation kernel for all of them.
  * out_first (may be NULL) receives each call's first connection index. */

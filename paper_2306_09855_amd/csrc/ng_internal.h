@@ -118,6 +118,25 @@ struct TabEntry {
 hipError_t launch_set_entries(const TabEntry* d_entries, uint32_t n, hipStream_t s);
 
 // ---------------------------------------------------------------------------
+// Node groups as index arrays and per-connection weights / delays (Sec. 2.1).
+// check: out[0] = largest source index, out[1] = largest target index,
+// out[2] = bits of the largest delay in ms (negative delays count as 0),
+// out[3] = 1 if a delay is NaN (out must hold zeros on entry).  apply: rewrites the
+// call's n connections from creation position pos0 on.
+struct CallArrays {
+  const uint32_t* src_idx;  // ns entries, or null
+  uint32_t ns;
+  const uint32_t* tgt_idx;  // nt entries, or null
+  uint32_t nt;
+  const float* w;           // n entries, or null
+  const float* d_ms;        // n entries, or null
+  uint32_t n;
+  float h;
+};
+hipError_t launch_check_arrays(const CallArrays& a, uint32_t* out, hipStream_t s);
+hipError_t launch_apply_arrays(const CallArrays& a, char* const* blocks, int log2B, uint64_t pos0, hipStream_t s);
+
+// ---------------------------------------------------------------------------
 // COPASS in-place block sort (Appendix A).
 // Record positions index the block array: position p lives in block p >> log2B.
 struct BlockView {

@@ -1164,6 +1164,81 @@ hipError_t downsweep_rb(const SortPack& pk, const uint32_t* offsets, hipStream_t
 
 
 // ---------------------------------------------------------------------------
+// Node groups as index arrays and per-connection weights and delays
+// (Sec. 2.1): generation runs with the groups as position ranges from 0 and
+// constant weights / delays, then one pass maps positions through the arrays
+// and stores the per-connection values.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float ms_to_steps(float ms, float h) {
+  const float steps = rintf(__fdiv_rn(ms, h));  // as the generation kernel's ms path
+  return steps < 1.0f ? 1.0f : steps;
+}
+
+__global__ __launch_bounds__(256) void k_check_arrays(CallArrays a, uint32_t* out) {
+  constexpr int U = 8;  // independent loads in flight per thread and round
+  uint32_t ms = 0, mt = 0, md = 0, bad = 0;
+  const uint64_t n = max(max(a.ns, a.nt), a.n);
+  const uint64_t stride = (uint64_t)gridDim.x * 256;
+  for (uint64_t j0 = blockIdx.x * 256ull + threadIdx.x; j0 < n; j0 += U * stride) {
+    uint32_t vs[U], vt[U];
+    float vd[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint64_t j = j0 + u * stride;
+      vs[u] = a.src_idx && j < a.ns ? G(a.src_idx)[j] : 0u;
+      vt[u] = a.tgt_idx && j < a.nt ? G(a.tgt_idx)[j] : 0u;
+      vd[u] = a.d_ms && j < a.n ? G(a.d_ms)[j] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      ms = max(ms, vs[u]);
+      mt = max(mt, vt[u]);
+      // the step count is monotone in the delay: the largest delay in ms
+      // (bits of a non-negative float order like the float) is converted once
+      if (vd[u] != vd[u]) bad = 1;
+      else md = max(md, __float_as_uint(fmaxf(vd[u], 0.0f)));
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    ms = max(ms, (uint32_t)__shfl_xor(ms, o));
+    mt = max(mt, (uint32_t)__shfl_xor(mt, o));
+    md = max(md, (uint32_t)__shfl_xor(md, o));
+    bad |= (uint32_t)__shfl_xor(bad, o);
+  }
+  // one atomic per workgroup and word: the four words are shared by the whole grid
+  __shared__ uint32_t red[4][4];
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = ms;
+    red[1][threadIdx.x >> 6] = mt;
+    red[2][threadIdx.x >> 6] = md;
+    red[3][threadIdx.x >> 6] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    uint32_t v = red[threadIdx.x][0];
+    for (int w = 1; w < 4; ++w) v = threadIdx.x == 3 ? (v | red[3][w]) : max(v, red[threadIdx.x][w]);
+    if (threadIdx.x == 3) atomicOr(out + 3, v);
+    else atomicMax(out + threadIdx.x, v);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_apply_arrays(CallArrays a, char* const* blocks, int log2B, uint64_t pos0) {
+  const uint64_t B = 1ull << log2B;
+  for (uint64_t j = blockIdx.x * 256ull + threadIdx.x; j < a.n; j += gridDim.x * 256ull) {
+    const uint64_t p = pos0 + j;
+    char* blk = G(blocks)[p >> log2B];
+    const uint64_t o = p & (B - 1);
+    NG_GLOBAL uint32_t* src = G(reinterpret_cast<uint32_t*>(blk));
+    NG_GLOBAL uint32_t* tgt = G(reinterpret_cast<uint32_t*>(blk + 4 * B));
+    if (a.src_idx) src[o] = G(a.src_idx)[src[o]];  // the generated value is a position < ns
+    if (a.tgt_idx) tgt[o] = G(a.tgt_idx)[tgt[o]];
+    if (a.w) G(reinterpret_cast<float*>(blk + 8 * B))[o] = G(a.w)[j];
+    if (a.d_ms) G(reinterpret_cast<int16_t*>(blk + 12 * B))[o] = (int16_t)ms_to_steps(G(a.d_ms)[j], a.h);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // COPASS in-place block sort (Appendix A): the copies of left partitions to
 // the auxiliary array and of right partitions through a bounce buffer, and
 // the partition search.
@@ -1485,6 +1560,22 @@ hipError_t launch_set_ptrs(char** tab, uint32_t first, uint32_t count, const uin
                            hipStream_t s) {
   hipLaunchKernelGGL(k_set_ptrs, dim3(1), dim3(64), 0, s, tab, first, count, v[0], v[1], v[2], v[3],
                      v[4], v[5], v[6], v[7]);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_arrays(const CallArrays& a, uint32_t* out, hipStream_t s) {
+  const uint32_t n = std::max(std::max(a.ns, a.nt), a.n);
+  if (n == 0) return hipSuccess;
+  // each workgroup ends in one atomic per word; all of them share the four words
+  const uint32_t grid = std::min<uint32_t>((n + 2047) / 2048, 512u);
+  hipLaunchKernelGGL(k_check_arrays, dim3(grid), dim3(256), 0, s, a, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_apply_arrays(const CallArrays& a, char* const* blocks, int log2B, uint64_t pos0, hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  const uint32_t grid = std::min<uint32_t>((a.n + 255) / 256, 8192u);
+  hipLaunchKernelGGL(k_apply_arrays, dim3(grid), dim3(256), 0, s, a, blocks, log2B, pos0);
   return hipGetLastError();
 }
 

@@ -298,6 +298,8 @@ void ctx_destroy_release(ng_ctx* c);
 // descriptor carries the block table and key of this context.
 int connect_prepare(ng_ctx* c, ng_range src, ng_range tgt, const ng_conn_spec* conn,
                     const ng_syn_spec* syn, ng::GenDesc* out, uint64_t* out_n);
+int connect_prepare_limit(ng_ctx* c, uint32_t node_limit, ng_range src, ng_range tgt, const ng_conn_spec* conn,
+                          const ng_syn_spec* syn, ng::GenDesc* out, uint64_t* out_n);
 // Upload `bytes` of host data to device memory on the context's stream:
 // through the graph's own pinned region while capturing, else through the
 // context's pinned staging buffer (reused once its last upload completed).

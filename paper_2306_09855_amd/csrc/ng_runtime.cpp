@@ -399,9 +399,16 @@ void ctx_destroy_release(ng_ctx* c) {
 
 int connect_prepare(ng_ctx* c, ng_range src, ng_range tgt, const ng_conn_spec* conn,
                     const ng_syn_spec* syn, ng::GenDesc* out, uint64_t* out_n) {
+  return connect_prepare_limit(c, c->n_nodes, src, tgt, conn, syn, out, out_n);
+}
+
+// node_limit bounds the ranges; a group given by an index array is planned as
+// the position range [0, n), which the node count does not bound
+int connect_prepare_limit(ng_ctx* c, uint32_t node_limit, ng_range src, ng_range tgt, const ng_conn_spec* conn,
+                          const ng_syn_spec* syn, ng::GenDesc* out, uint64_t* out_n) {
   if (!c->capturing) ctx_flush_frees(c);  // make this context's frees reusable
   Plan p;
-  if (int rc = plan_call(c->n_nodes, src, tgt, conn, syn, c->cfg.h_ms, &p)) return rc;
+  if (int rc = plan_call(node_limit, src, tgt, conn, syn, c->cfg.h_ms, &p)) return rc;
   if (c->next_cid == 0xFFFFFFFFu) return fail(NG_ERR_TOO_LARGE, "connect call ids exhausted");
   if (c->n_conns + p.n_new > 0xFFFFFFFFull)
     return fail(NG_ERR_TOO_LARGE, "a context holds at most 2^32-1 connections");
@@ -1188,6 +1195,71 @@ int ng_connect(ng_ctx* c, ng_range src, ng_range tgt, const ng_conn_spec* conn, 
   if (out_first) *out_first = d.pos0;
   if (out_n) *out_n = n;
   connect_commit(c, d, d.max_delay);
+  return NG_OK;
+}
+
+int ng_connect_groups(ng_ctx* c, ng_group src, ng_group tgt, const ng_conn_spec* conn, const ng_syn_spec* syn,
+                      const float* weights, const float* delays_ms, uint32_t* out_cid, uint64_t* out_first,
+                      uint64_t* out_n) {
+  const ng_range rs{src.first, src.n}, rt{tgt.first, tgt.n};
+  if (!src.idx && !tgt.idx && !weights && !delays_ms) return ng_connect(c, rs, rt, conn, syn, out_cid, out_first, out_n);
+  if (int rc = enter(c)) return rc;
+  if (int rc = mutable_state(c)) return rc;
+  if (int rc = not_capturing(c)) return rc;
+  if (!conn || !syn) return fail(NG_ERR_INVALID_ARG, "null connection or synapse spec");
+  if ((src.idx && src.first) || (tgt.idx && tgt.first))
+    return fail(NG_ERR_INVALID_ARG, "a group given by an index array needs first = 0");
+  if ((src.idx || tgt.idx) && !conn->allow_autapses)
+    return fail(NG_ERR_UNSUPPORTED, "allow_autapses = 0 is not implemented for index arrays");
+  // ranges of the groups without arrays are node ranges
+  if ((!src.idx && (uint64_t)src.first + src.n > c->n_nodes) || (!tgt.idx && (uint64_t)tgt.first + tgt.n > c->n_nodes))
+    return fail(NG_ERR_INVALID_ARG, "node range exceeds the %u created nodes", c->n_nodes);
+  ng_syn_spec sy = *syn;
+  if (weights) sy.weight = ng_param{NG_CONST, 0, 0.0, 0.0};
+  if (delays_ms) sy.delay = ng_param{NG_CONST, 0, (double)c->cfg.h_ms, 0.0};  // one step; replaced below
+  // plan without side effects, to size the arrays
+  Plan pl;
+  if (int rc = plan_call(0xFFFFFFFFu, rs, rt, conn, &sy, c->cfg.h_ms, &pl)) return rc;
+  ng::CallArrays ca{};
+  ca.src_idx = src.idx;
+  ca.ns = src.idx ? src.n : 0;
+  ca.tgt_idx = tgt.idx;
+  ca.nt = tgt.idx ? tgt.n : 0;
+  ca.w = weights;
+  ca.d_ms = delays_ms;
+  ca.n = (uint32_t)pl.n_new;
+  ca.h = c->cfg.h_ms;
+  // the arrays are checked on the device before anything changes
+  uint32_t chk[4] = {0, 0, 0, 0};
+  uint32_t* d_chk = c->d_scalars + 8;
+  NG_LAUNCH(c, "fill", ng::launch_fill_u32(d_chk, 0u, 4, c->stream));
+  NG_LAUNCH(c, "check_arrays", ng::launch_check_arrays(ca, d_chk, c->stream));
+  NG_HIP(c, hipMemcpyAsync(chk, d_chk, sizeof(chk), hipMemcpyDeviceToHost, c->stream), "array check");
+  NG_HIP(c, hipStreamSynchronize(c->stream), "array check");
+  if (src.idx && src.n && chk[0] >= c->n_nodes)
+    return fail(NG_ERR_INVALID_ARG, "source index %u is not below the %u created nodes", chk[0], c->n_nodes);
+  if (tgt.idx && tgt.n && chk[1] >= c->n_nodes)
+    return fail(NG_ERR_INVALID_ARG, "target index %u is not below the %u created nodes", chk[1], c->n_nodes);
+  int64_t max_steps = 1;
+  if (delays_ms && pl.n_new) {
+    float max_ms;
+    memcpy(&max_ms, &chk[2], 4);
+    max_steps = delay_steps_f32(max_ms, c->cfg.h_ms);  // the conversion is monotone in the delay
+    if (chk[3] || max_steps > 32767) return fail(NG_ERR_INVALID_ARG, "a delay is not finite or exceeds 32767 steps");
+  }
+  const ng_range ps{src.idx ? 0u : src.first, src.n}, pt{tgt.idx ? 0u : tgt.first, tgt.n};
+  ng::GenDesc d;
+  uint64_t n = 0;
+  if (int rc = connect_prepare_limit(c, 0xFFFFFFFFu, ps, pt, conn, &sy, &d, &n)) return rc;
+  if (int rc = sync_table(c)) return rc;
+  if (n) {
+    NG_LAUNCH(c, "generate", ng::launch_generate(d, key_ptr(c), c->d_tab[c->cur], c->log2B, c->stream));
+    NG_LAUNCH(c, "apply_arrays", ng::launch_apply_arrays(ca, c->d_tab[c->cur], c->log2B, d.pos0, c->stream));
+  }
+  if (out_cid) *out_cid = d.cid;
+  if (out_first) *out_first = d.pos0;
+  if (out_n) *out_n = n;
+  connect_commit(c, d, delays_ms ? (int32_t)max_steps : d.max_delay);
   return NG_OK;
 }
 

@@ -56,6 +56,13 @@ class Network:
     def tune(self, radix_bits: int, sort_ranges: int = 1024):
         ng.ng_set_tuning(self.ctx, radix_bits, sort_ranges)
 
+    def connect_groups(self, call, src, tgt, weights=None, delays_ms=None):
+        """A Connect call whose groups may be index tensors (device, int32) and whose weights
+        / delays (ms) may be per-connection device tensors (float32); the rule, K/N and
+        distributions come from `call`."""
+        return ng.ng_connect_groups(self.ctx, ng.group(src), ng.group(tgt), ng.conn_spec(call.rule, call.k_or_n),
+                                    ng.syn_spec(call.weight, call.delay), weights, delays_ms)
+
     def set_calibration(self, algorithm: str):
         """"radix" (default) or "copass": the in-place block sort of the appendix."""
         ng.ng_set_calibration(self.ctx, algorithm)

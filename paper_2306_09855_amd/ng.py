@@ -59,6 +59,11 @@ class ng_syn_spec(ctypes.Structure):
     _fields_ = [("weight", ng_param), ("delay", ng_param)]
 
 
+class ng_group(ctypes.Structure):
+    """Node group: the range [first, first + n) when idx is NULL, else n indices at idx (device)."""
+    _fields_ = [("first", ctypes.c_uint32), ("n", ctypes.c_uint32), ("idx", ctypes.c_void_p)]
+
+
 class ng_config(ctypes.Structure):
     _fields_ = [("block_size", ctypes.c_uint64), ("seed", ctypes.c_uint64),
                 ("h_ms", ctypes.c_float), ("reserved", ctypes.c_int32)]
@@ -112,6 +117,8 @@ def lib():
             "ng_create_nodes": ([vp, u32, P(ng_range)], ctypes.c_int),
             "ng_connect": ([vp, ng_range, ng_range, P(ng_conn_spec), P(ng_syn_spec), P(u32), P(u64),
                             P(u64)], ctypes.c_int),
+            "ng_connect_groups": ([vp, ng_group, ng_group, P(ng_conn_spec), P(ng_syn_spec), vp, vp, P(u32),
+                                   P(u64), P(u64)], ctypes.c_int),
             "ng_connect_batch": ([vp, u32, P(ng_range), P(ng_range), P(ng_conn_spec), P(ng_syn_spec),
                                   P(u64)], ctypes.c_int),
             "ng_calibrate": ([vp], ctypes.c_int),
@@ -233,6 +240,16 @@ def ng_create_nodes(ctx, n: int) -> ng_range:
     r = ng_range()
     _check(lib().ng_create_nodes(ctx, n, ctypes.byref(r)))
     return r
+
+
+def ng_connect_groups(ctx, src: ng_group, tgt: ng_group, conn: ng_conn_spec, syn: ng_syn_spec,
+                      weights=None, delays_ms=None):
+    """ng_connect with node groups as index arrays and/or per-connection weights and delays
+    (device pointers, as int addresses)."""
+    cid, first, n = ctypes.c_uint32(), ctypes.c_uint64(), ctypes.c_uint64()
+    _check(lib().ng_connect_groups(ctx, src, tgt, ctypes.byref(conn), ctypes.byref(syn), _vp(weights),
+                                   _vp(delays_ms), ctypes.byref(cid), ctypes.byref(first), ctypes.byref(n)))
+    return int(cid.value), int(first.value), int(n.value)
 
 
 def ng_connect(ctx, src: ng_range, tgt: ng_range, conn: ng_conn_spec, syn: ng_syn_spec):
@@ -408,3 +425,14 @@ def arena_for(nbytes: int, device: str = "cuda") -> torch.Tensor:
 
 def current_stream() -> int:
     return torch.cuda.current_stream().cuda_stream
+
+
+def group(g) -> ng_group:
+    """ng_group from (first, n), or from a device tensor of node indices."""
+    if isinstance(g, ng_group):
+        return g
+    if isinstance(g, torch.Tensor):
+        if not g.is_cuda or g.dtype not in (torch.int32, torch.uint32) or not g.is_contiguous():
+            raise ValueError("index arrays are contiguous 32-bit device tensors")
+        return ng_group(0, g.numel(), g.data_ptr())
+    return ng_group(int(g[0]), int(g[1]), None)
