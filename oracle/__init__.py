@@ -93,6 +93,8 @@ def lib():
         L.ora_connect.restype = ctypes.c_int
         L.ora_calibrate.argtypes = [u64, u32, vp, vp, vp, vp, vp, P(u64)]
         L.ora_calibrate.restype = ctypes.c_int
+        L.ora_deliver.argtypes = [u32, vp, vp, vp, vp, vp, u32, vp, vp, vp, vp]
+        L.ora_deliver.restype = ctypes.c_int
         L.ora_copass_partition.argtypes = [u32, vp, vp, u64, vp, P(u64)]
         L.ora_copass_partition.restype = ctypes.c_int
         L.ora_copass_block_sort.argtypes = [u64, u64, vp, vp]
@@ -266,3 +268,26 @@ def copass_block_sort(vals, block: int, pay=None):
     if lib().ora_copass_block_sort(v.size, block, _ptr(v), _ptr(p)) != 0:
         raise ValueError("bad block sort input")
     return v, p
+
+
+# --- spike buffer and delivery (Sec. 2.3) --------------------------------------
+def deliver(n_nodes: int, net: dict, spikes):
+    """Input (fp64, [n_steps, n_nodes]) delivered by the calibrated network
+    `net` (as build_network returns) for `spikes`: a list over steps of
+    (nodes, multiplicities) arrays, a node at most once per step."""
+    off = np.zeros(len(spikes) + 1, np.uint64)
+    off[1:] = np.cumsum([len(n) for n, _ in spikes])
+    nodes = np.ascontiguousarray(np.concatenate([np.asarray(n, np.uint32) for n, _ in spikes])
+                                 if spikes else np.zeros(0, np.uint32), dtype=np.uint32)
+    mult = np.ascontiguousarray(np.concatenate([np.asarray(m, np.uint32) for _, m in spikes])
+                                if spikes else np.zeros(0, np.uint32), dtype=np.uint32)
+    tgt = np.ascontiguousarray(net["s_tgt"], dtype=np.uint32)
+    w = np.ascontiguousarray(net["s_w"], dtype=np.float64)
+    d = np.ascontiguousarray(net["s_delay"], dtype=np.int32)
+    gp = np.ascontiguousarray(net["group_ptr"], dtype=np.uint32)
+    gs = np.ascontiguousarray(net["group_start"], dtype=np.uint32)
+    out = np.zeros((len(spikes), n_nodes), np.float64)
+    if lib().ora_deliver(n_nodes, _ptr(gp), _ptr(gs), _ptr(tgt), _ptr(w), _ptr(d), len(spikes), _ptr(off),
+                         _ptr(nodes), _ptr(mult), _ptr(out)) != 0:
+        raise ValueError("bad spikes")
+    return out

@@ -501,3 +501,67 @@ int ora_copass_block_sort(uint64_t n, uint64_t B, uint64_t* vals, uint64_t* pay)
   free(start); free(len); free(off); free(mi); free(aux_v); free(aux_p); free(sub);
   return rc;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Spike buffer and delivery (Sec. 2.3).                                    */
+
+typedef struct {
+  uint32_t time, group, mult;
+} ora_spike;
+
+int ora_deliver(uint32_t n_nodes, const uint32_t* group_ptr, const uint32_t* group_start,
+                const uint32_t* tgt, const double* w, const int32_t* delay, uint32_t n_steps,
+                const uint64_t* spk_off, const uint32_t* spk_node, const uint32_t* spk_mult, double* input) {
+  /* a queue per node; a spike stays at most (largest delay) steps, plus the
+   * step it was emitted in */
+  int32_t dmax = 1;
+  const uint64_t n_groups = group_ptr[n_nodes];
+  for (uint64_t g = 0; g < n_groups; g++)
+    if (delay[group_start[g]] > dmax) dmax = delay[group_start[g]];
+  const uint64_t cap = (uint64_t)dmax + 1;
+  ora_spike* q = (ora_spike*)malloc((n_nodes ? n_nodes : 1) * cap * sizeof(ora_spike));
+  uint64_t* head = (uint64_t*)calloc(n_nodes ? n_nodes : 1, sizeof(uint64_t));
+  uint64_t* cnt = (uint64_t*)calloc(n_nodes ? n_nodes : 1, sizeof(uint64_t));
+  if (!q || !head || !cnt) {
+    free(q); free(head); free(cnt);
+    return -1;
+  }
+  int rc = 0;
+  for (uint32_t s = 0; s < n_steps && rc == 0; s++) {
+    double* in = input + (uint64_t)s * n_nodes;
+    for (uint32_t t = 0; t < n_nodes; t++) in[t] = 0.0;
+    /* the spike array of this step, delivered as it is filled */
+    for (uint32_t i = 0; i < n_nodes; i++) {
+      for (uint64_t e = 0; e < cnt[i]; e++) {
+        ora_spike* sp = &q[(uint64_t)i * cap + (head[i] + e) % cap];
+        sp->time += 1;
+        const uint64_t g = group_ptr[i] + sp->group;
+        if ((int32_t)sp->time == delay[group_start[g]]) {
+          for (uint64_t j = group_start[g]; j < group_start[g + 1]; j++) in[tgt[j]] += w[j] * sp->mult;
+          sp->group += 1;
+        }
+      }
+      /* spikes past the node's last group leave from the front (they are the oldest) */
+      while (cnt[i] > 0 && q[(uint64_t)i * cap + head[i]].group == group_ptr[i + 1] - group_ptr[i]) {
+        head[i] = (head[i] + 1) % cap;
+        cnt[i]--;
+      }
+    }
+    /* spikes emitted this step */
+    for (uint64_t e = spk_off[s]; e < spk_off[s + 1]; e++) {
+      const uint32_t i = spk_node[e];
+      if (i >= n_nodes || cnt[i] >= cap) {
+        rc = -1;
+        break;
+      }
+      if (group_ptr[i + 1] == group_ptr[i]) continue;  /* no outgoing connections */
+      ora_spike* sp = &q[(uint64_t)i * cap + (head[i] + cnt[i]) % cap];
+      sp->time = 0;
+      sp->group = 0;
+      sp->mult = spk_mult[e];
+      cnt[i]++;
+    }
+  }
+  free(q); free(head); free(cnt);
+  return rc;
+}

@@ -103,6 +103,24 @@ int ora_calibrate(uint64_t n, uint32_t n_nodes, const uint32_t* src, const int32
                   uint64_t* perm, uint32_t* group_ptr, uint32_t* group_start,
                   uint64_t* n_groups);
 
+/* Spike buffer and delivery (Sec. 2.3): the consumer of the calibrated
+ * arrays.  Each node keeps a queue of spikes (time index, connection-group
+ * index, multiplicity).  At each step every queued spike's time index grows
+ * by one; a spike whose time index equals the delay of its current group is
+ * put in the spike array and moves on to the node's next group (groups of a
+ * node are in ascending delay), and leaves the queue after the last group;
+ * then the spikes the nodes emit this step join their queues with time and
+ * group index zero.  Every connection of every group in the spike array
+ * adds weight x multiplicity to its target's input of this step.
+ * Inputs: the calibrated arrays (tgt, w, delay in sorted order), group_ptr
+ * (n_nodes + 1) and group_start (G + 1) as ora_calibrate gives them; steps
+ * of spikes: spikes of step s are spk_node[spk_off[s] .. spk_off[s+1]) with
+ * multiplicities spk_mult[...] (a node at most once per step).  Output:
+ * input[s * n_nodes + t] (fp64) for s < n_steps.  Returns 0 or -1. */
+int ora_deliver(uint32_t n_nodes, const uint32_t* group_ptr, const uint32_t* group_start,
+                const uint32_t* tgt, const double* w, const int32_t* delay, uint32_t n_steps,
+                const uint64_t* spk_off, const uint32_t* spk_node, const uint32_t* spk_mult, double* input);
+
 /* COPASS partition (Appendix A, "The COPASS partition algorithm" and its two
  * last steps).  k subarrays, each sorted ascending, are given concatenated:
  * subarray i is vals[off[i] .. off[i+1]).  For 0 < m < total size it finds
