@@ -234,6 +234,29 @@ int ng_copy_group_index(ng_ctx* ctx, uint32_t* group_ptr, uint32_t* group_start)
  * speed does. */
 int ng_set_tuning(ng_ctx* ctx, int radix_bits, uint32_t sort_ranges);
 
+/* Spike buffers and delivery (Sec. 2.3), the consumer of the calibrated
+ * connections.  ng_spikes_init (after calibration; synchronizes) gives every
+ * node a queue of spikes -- (time index, connection-group index,
+ * multiplicity), room for the largest delay plus one -- and empties them.
+ * ng_spikes_step runs one simulation step on the context's stream: every
+ * queued spike's time index grows by one; a spike whose time index equals
+ * the delay of its current group (the node's groups in ascending delay) puts
+ * that group in the spike array and moves to the next group, and leaves
+ * after the last; every connection of every group in the spike array adds
+ * weight x multiplicity to input[target] (device f32 array of n_nodes
+ * entries, accumulated with atomics: the order of the additions, and so the
+ * rounding, varies between runs; the caller clears it when it wants); then
+ * nodes[0..n) (device u32, each at most once per step) emit spikes of
+ * multiplicity mult[k] (device u32; NULL: 1) with time and group index zero.
+ * A connection of delay d thus delivers d steps after its source emitted.
+ * Spikes given with a node index not below the node count, or a node twice
+ * in one step, are dropped; the next ng_sync returns NG_ERR_INVALID_ARG
+ * once for them.  The buffers hold 20 bytes per node and queue slot, 12 per
+ * node and 2 per group, and are released with the group index (a new
+ * calibration, ng_reset).  NG_ERR_STATE before calibration / init. */
+int ng_spikes_init(ng_ctx* ctx);
+int ng_spikes_step(ng_ctx* ctx, const uint32_t* nodes, const uint32_t* mult, uint32_t n, float* input);
+
 /* Calibration algorithm of a context; the calibrated arrays and group index
  * are the same with either (stable order by (source, delay), Sec. 2.2).
  *   NG_CALIB_RADIX (default): stable LSD radix sort of all connections into

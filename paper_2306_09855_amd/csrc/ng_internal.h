@@ -118,6 +118,29 @@ struct TabEntry {
 hipError_t launch_set_entries(const TabEntry* d_entries, uint32_t n, hipStream_t s);
 
 // ---------------------------------------------------------------------------
+// Spike buffers and delivery (Sec. 2.3) over the calibrated connections.
+struct SpikeState {
+  uint32_t *time, *group, *mult;  // [n_nodes * cap] queue slots per node
+  uint32_t *head, *count;         // [n_nodes]
+  uint32_t* stamp;                // [n_nodes] last step a node emitted in
+  uint2* entries;                 // [n_nodes * cap] spike array: (global group, multiplicity)
+  uint32_t* n_entries;            // entries of the current step
+  uint32_t* err;                  // bit 1: a node emitted into a full queue; bit 2: a node index out of range
+  int16_t* gdelay;                // [G] delay of each group
+  const uint32_t* group_ptr;      // [n_nodes + 1]
+  const uint32_t* group_start;    // [G + 1]
+  char* const* blocks;            // calibrated connections
+  int log2B;
+  uint32_t n_nodes, cap;
+};
+// group delays, empty queues
+hipError_t launch_spikes_init(const SpikeState& st, uint64_t n_groups, hipStream_t s);
+// one step: queued spikes advance, the reached groups are delivered
+// (input[t] += w * multiplicity), then nodes[0..n) emit
+hipError_t launch_spikes_step(const SpikeState& st, const uint32_t* nodes, const uint32_t* mult, uint32_t n,
+                              float* input, uint32_t step, hipStream_t s);
+
+// ---------------------------------------------------------------------------
 // Node groups as index arrays and per-connection weights / delays (Sec. 2.1).
 // check: out[0] = largest source index, out[1] = largest target index,
 // out[2] = bits of the largest delay in ms (negative delays count as 0),

@@ -1164,6 +1164,126 @@ hipError_t downsweep_rb(const SortPack& pk, const uint32_t* offsets, hipStream_t
 
 
 // ---------------------------------------------------------------------------
+// Spike buffers and delivery (Sec. 2.3).  Each node holds a ring of `cap`
+// spike slots (time index, group index within the node, multiplicity).  A
+// step advances every queued spike; a spike whose time index reaches its
+// group's delay enters the spike array and moves to the next group (a node's
+// groups are in ascending delay); finished spikes leave the front of the
+// ring.  Delivery gives one wave to each spike-array entry, a lane to each of
+// the group's connections.  Then the emitting nodes push new spikes.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_spikes_init(SpikeState st, uint64_t n_groups) {
+  const uint64_t B = 1ull << st.log2B;
+  const uint64_t n = max((uint64_t)st.n_nodes, n_groups);
+  for (uint64_t j = blockIdx.x * 256ull + threadIdx.x; j < n; j += gridDim.x * 256ull) {
+    if (j < n_groups) {
+      const uint32_t p = G(st.group_start)[j];
+      const char* blk = G(st.blocks)[p >> st.log2B];
+      G(st.gdelay)[j] = G(reinterpret_cast<const int16_t*>(blk + 12 * B))[p & (B - 1)];
+    }
+    if (j < st.n_nodes) {
+      G(st.head)[j] = 0;
+      G(st.count)[j] = 0;
+      G(st.stamp)[j] = 0xFFFFFFFFu;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_spikes_advance(SpikeState st) {
+  const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+  const uint32_t lane = threadIdx.x & 63;
+  uint32_t cnt = 0, h = 0, base = 0, gi = 0;
+  if (i < st.n_nodes) {
+    cnt = G(st.count)[i];
+    h = G(st.head)[i];
+    base = G(st.group_ptr)[i];
+    gi = G(st.group_ptr)[i + 1] - base;
+  }
+  const uint64_t q0 = (uint64_t)i * st.cap;
+  // time indices grow by one; count the spikes that reach their group's delay
+  uint32_t hits = 0;
+  for (uint32_t e = 0; e < cnt; ++e) {
+    const uint64_t sl = q0 + (h + e) % st.cap;
+    const uint32_t t = G(st.time)[sl] + 1;
+    G(st.time)[sl] = t;
+    if ((int32_t)t == G(st.gdelay)[base + G(st.group)[sl]]) ++hits;
+  }
+  // one counter update per wave
+  uint32_t incl = hits;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t v = __shfl_up(incl, o);
+    if (lane >= (uint32_t)o) incl += v;
+  }
+  const uint32_t wave_total = __shfl(incl, 63);
+  uint32_t first = 0;
+  if (lane == 63 && wave_total) first = atomicAdd(st.n_entries, wave_total);
+  uint32_t pos = __shfl(first, 63) + incl - hits;
+  for (uint32_t e = 0; e < cnt && hits; ++e) {
+    const uint64_t sl = q0 + (h + e) % st.cap;
+    const uint32_t g = G(st.group)[sl];
+    if ((int32_t)G(st.time)[sl] == G(st.gdelay)[base + g]) {
+      st_u32x2(st.entries + pos++, base + g, G(st.mult)[sl]);
+      G(st.group)[sl] = g + 1;
+    }
+  }
+  // the oldest spikes finish first
+  while (cnt && G(st.group)[q0 + h] == gi) {
+    h = h + 1 == st.cap ? 0 : h + 1;
+    --cnt;
+  }
+  if (i < st.n_nodes) {
+    G(st.head)[i] = h;
+    G(st.count)[i] = cnt;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_spikes_deliver(SpikeState st, float* __restrict__ input) {
+  const uint64_t B = 1ull << st.log2B;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t n_e = __builtin_amdgcn_readfirstlane(G(st.n_entries)[0]);
+  const uint32_t waves = gridDim.x * 4;
+  for (uint32_t e = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6)); e < n_e; e += waves) {
+    const uint2 en = ld_u32x2(st.entries + e);
+    const uint32_t a = G(st.group_start)[en.x], b = G(st.group_start)[en.x + 1];
+    const float m = (float)en.y;
+    for (uint32_t j = a + lane; j < b; j += 64) {
+      const char* blk = G(st.blocks)[j >> st.log2B];
+      const uint64_t o = j & (B - 1);
+      const uint32_t t = G(reinterpret_cast<const uint32_t*>(blk + 4 * B))[o];
+      const float w = G(reinterpret_cast<const float*>(blk + 8 * B))[o];
+      unsafeAtomicAdd(input + t, w * m);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_spikes_push(SpikeState st, const uint32_t* __restrict__ nodes,
+                                                     const uint32_t* __restrict__ mult, uint32_t n, uint32_t step) {
+  for (uint64_t k = blockIdx.x * 256ull + threadIdx.x; k < n; k += gridDim.x * 256ull) {
+    const uint32_t i = G(nodes)[k];
+    if (i >= st.n_nodes) {
+      atomicOr(st.err, 4u);
+      continue;
+    }
+    if (atomicExch(st.stamp + i, step) == step) {  // the node already emitted in this step
+      atomicOr(st.err, 2u);
+      continue;
+    }
+    if (G(st.group_ptr)[i + 1] == G(st.group_ptr)[i]) continue;  // no outgoing connections
+    const uint32_t c = atomicAdd(st.count + i, 1u);
+    if (c >= st.cap) {  // cannot happen with one spike per node and step; never write past the ring
+      atomicSub(st.count + i, 1u);
+      atomicOr(st.err, 2u);
+      continue;
+    }
+    const uint64_t sl = (uint64_t)i * st.cap + (G(st.head)[i] + c) % st.cap;
+    G(st.time)[sl] = 0;
+    G(st.group)[sl] = 0;
+    G(st.mult)[sl] = mult ? G(mult)[k] : 1u;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Node groups as index arrays and per-connection weights and delays
 // (Sec. 2.1): generation runs with the groups as position ranges from 0 and
 // constant weights / delays, then one pass maps positions through the arrays
@@ -1561,6 +1681,32 @@ hipError_t launch_set_ptrs(char** tab, uint32_t first, uint32_t count, const uin
   hipLaunchKernelGGL(k_set_ptrs, dim3(1), dim3(64), 0, s, tab, first, count, v[0], v[1], v[2], v[3],
                      v[4], v[5], v[6], v[7]);
   return hipGetLastError();
+}
+
+hipError_t launch_spikes_init(const SpikeState& st, uint64_t n_groups, hipStream_t s) {
+  const uint64_t n = std::max<uint64_t>(st.n_nodes, n_groups);
+  if (n == 0) return hipSuccess;
+  const uint32_t grid = (uint32_t)std::min<uint64_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_spikes_init, dim3(grid), dim3(256), 0, s, st, n_groups);
+  return hipGetLastError();
+}
+
+hipError_t launch_spikes_step(const SpikeState& st, const uint32_t* nodes, const uint32_t* mult, uint32_t n,
+                              float* input, uint32_t step, hipStream_t s) {
+  hipError_t e = launch_fill_u32(st.n_entries, 0u, 1, s);
+  if (e != hipSuccess) return e;
+  if (st.n_nodes) {
+    hipLaunchKernelGGL(k_spikes_advance, dim3((st.n_nodes + 255) / 256), dim3(256), 0, s, st);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_spikes_deliver, dim3(2048), dim3(256), 0, s, st, input);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (n) {
+    hipLaunchKernelGGL(k_spikes_push, dim3(std::min<uint32_t>((n + 255) / 256, 4096u)), dim3(256), 0, s, st, nodes,
+                       mult, n, step);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 hipError_t launch_check_arrays(const CallArrays& a, uint32_t* out, hipStream_t s) {

@@ -190,6 +190,11 @@ struct ng_ctx {
   uint64_t group_ptr_bytes = 0;
   uint32_t* d_group_start = nullptr;
   uint64_t group_start_bytes = 0;
+  // spike buffers over the calibrated connections (one allocation; released with the index)
+  char* d_spikes = nullptr;
+  uint64_t spikes_bytes = 0;
+  ng::SpikeState spikes{};
+  uint32_t spike_step = 0;  // steps since ng_spikes_init (stamps the emitting nodes)
   uint32_t* d_scalars = nullptr;  // [0] = G
   uint32_t gi_nodes = 0;          // n_nodes the index was built for
 

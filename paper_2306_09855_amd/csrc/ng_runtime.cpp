@@ -271,6 +271,9 @@ void release_index(ng_ctx* c) {
   ctx_free(c, (char*)c->d_group_start, c->group_start_bytes);
   c->d_group_ptr = c->d_group_start = nullptr;
   c->group_ptr_bytes = c->group_start_bytes = 0;
+  ctx_free(c, c->d_spikes, c->spikes_bytes);  // the spike buffers walk the index
+  c->d_spikes = nullptr;
+  c->spikes_bytes = 0;
 }
 
 int check_descs(const std::vector<ng::GenDesc>& descs) {
@@ -1338,6 +1341,62 @@ int ng_set_tuning(ng_ctx* c, int radix_bits, uint32_t sort_ranges) {
   return NG_OK;
 }
 
+int ng_spikes_init(ng_ctx* c) {
+  if (int rc = enter(c)) return rc;
+  if (int rc = not_capturing(c)) return rc;
+  if (!c->calibrated || !c->d_group_ptr) return fail(NG_ERR_STATE, "spike buffers need a calibrated context");
+  NG_HIP(c, hipStreamSynchronize(c->stream), "spike init");
+  uint32_t G = 0;
+  NG_HIP(c, hipMemcpy(&G, c->d_scalars, 4, hipMemcpyDeviceToHost), "group count");
+  const uint64_t N = c->gi_nodes, cap = (uint64_t)std::max<int32_t>(c->max_delay, 1) + 1;
+  // time, group, multiplicity and spike-array slots per node, head, count, group delays
+  const uint64_t slots = N * cap;
+  const uint64_t off_entries = align256(3 * 4 * slots + 3 * 4 * N);
+  const uint64_t off_gd = off_entries + align256(8 * slots);
+  const uint64_t bytes = off_gd + align256(2 * (uint64_t)G + 2);
+  ctx_free(c, c->d_spikes, c->spikes_bytes);
+  c->d_spikes = nullptr;
+  c->spikes_bytes = 0;
+  char* m = ctx_alloc(c, bytes);
+  if (!m) {
+    c->need = Arena::round_up(bytes);
+    return fail(NG_ERR_OOM, "arena cannot hold the spike buffers (%llu bytes)", (unsigned long long)bytes);
+  }
+  c->d_spikes = m;
+  c->spikes_bytes = bytes;
+  ng::SpikeState& st = c->spikes;
+  st.time = (uint32_t*)m;
+  st.group = st.time + slots;
+  st.mult = st.group + slots;
+  st.head = st.mult + slots;
+  st.count = st.head + N;
+  st.stamp = st.count + N;
+  st.entries = (uint2*)(m + off_entries);
+  st.gdelay = (int16_t*)(m + off_gd);
+  st.n_entries = c->d_scalars + 12;
+  st.err = c->d_scalars + 2;
+  st.group_ptr = c->d_group_ptr;
+  st.group_start = c->d_group_start;
+  st.blocks = c->d_tab[c->cur];
+  st.log2B = c->log2B;
+  st.n_nodes = (uint32_t)N;
+  st.cap = (uint32_t)cap;
+  c->spike_step = 0;
+  NG_LAUNCH(c, "spikes_init", ng::launch_spikes_init(st, G, c->stream));
+  return NG_OK;
+}
+
+int ng_spikes_step(ng_ctx* c, const uint32_t* nodes, const uint32_t* mult, uint32_t n, float* input) {
+  if (int rc = enter(c)) return rc;
+  if (!c->calibrated || !c->d_spikes) return fail(NG_ERR_STATE, "ng_spikes_init first (after calibration)");
+  if ((n && !nodes) || !input) return fail(NG_ERR_INVALID_ARG, "null spike or input array");
+  // stamps tell a node's second spike in one step apart; 0xFFFFFFFF marks "never"
+  if (c->spike_step == 0xFFFFFFFEu) return fail(NG_ERR_STATE, "step count exhausted; ng_spikes_init again");
+  NG_LAUNCH(c, "spikes_step", ng::launch_spikes_step(c->spikes, nodes, mult, n, input, c->spike_step, c->stream));
+  c->spike_step++;
+  return NG_OK;
+}
+
 int ng_set_calibration(ng_ctx* c, int algorithm) {
   if (!c) return fail(NG_ERR_INVALID_ARG, "null context");
   if (algorithm != NG_CALIB_RADIX && algorithm != NG_CALIB_COPASS)
@@ -1484,10 +1543,10 @@ int ng_sync(ng_ctx* c) {
   NG_HIP(c, hipStreamSynchronize(c->stream), "kernel execution");
   uint32_t err = 0;
   NG_HIP(c, hipMemcpy(&err, c->d_scalars + 2, 4, hipMemcpyDeviceToHost), "read error word");
-  if (err) {
-    c->sticky = NG_ERR_DEVICE;
-    c->sticky_msg = "a sort look-back wait exceeded its spin limit";
-    return fail(NG_ERR_DEVICE, "%s", c->sticky_msg.c_str());
+  if (err) {  // spike input the steps since the last check dropped (not sticky)
+    NG_HIP(c, hipMemset(c->d_scalars + 2, 0, 4), "clear error word");
+    return fail(NG_ERR_INVALID_ARG, "spike input dropped:%s%s", (err & 2) ? " a node emitted twice in one step" : "",
+                (err & 4) ? " a node index not below the node count" : "");
   }
   return NG_OK;
 }

@@ -63,6 +63,15 @@ class Network:
         return ng.ng_connect_groups(self.ctx, ng.group(src), ng.group(tgt), ng.conn_spec(call.rule, call.k_or_n),
                                     ng.syn_spec(call.weight, call.delay), weights, delays_ms)
 
+    def spikes_init(self):
+        ng.ng_spikes_init(self.ctx)
+
+    def spikes_step(self, nodes, input, mult=None):
+        """One simulation step (Sec. 2.3): nodes (device int32/uint32 tensor) emit after the
+        queued spikes are delivered into input (device float32 tensor, accumulated)."""
+        n = 0 if nodes is None else nodes.numel()
+        ng.ng_spikes_step(self.ctx, nodes if n else None, mult, n, input)
+
     def set_calibration(self, algorithm: str):
         """"radix" (default) or "copass": the in-place block sort of the appendix."""
         ng.ng_set_calibration(self.ctx, algorithm)

@@ -129,6 +129,8 @@ def lib():
             "ng_copy_group_index": ([vp, vp, vp], ctypes.c_int),
             "ng_set_tuning": ([vp, ctypes.c_int, u32], ctypes.c_int),
             "ng_set_calibration": ([vp, ctypes.c_int], ctypes.c_int),
+            "ng_spikes_init": ([vp], ctypes.c_int),
+            "ng_spikes_step": ([vp, vp, vp, u32, vp], ctypes.c_int),
             "ng_memory_stats": ([vp, P(u64), P(u64), P(u64)], ctypes.c_int),
             "ng_reset": ([vp], ctypes.c_int),
             "ng_enable_timing": ([vp, ctypes.c_int], ctypes.c_int),
@@ -436,3 +438,13 @@ def group(g) -> ng_group:
             raise ValueError("index arrays are contiguous 32-bit device tensors")
         return ng_group(0, g.numel(), g.data_ptr())
     return ng_group(int(g[0]), int(g[1]), None)
+
+
+def ng_spikes_init(ctx) -> None:
+    """Spike buffers over the calibrated connections (Sec. 2.3); synchronizes."""
+    _check(lib().ng_spikes_init(ctx))
+
+
+def ng_spikes_step(ctx, nodes, mult, n: int, input) -> None:
+    """One step: queued spikes advance and deliver input[t] += w * m; then nodes emit."""
+    _check(lib().ng_spikes_step(ctx, _vp(nodes), _vp(mult), n, _vp(input)))

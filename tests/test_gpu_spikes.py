@@ -1,0 +1,118 @@
+"""GPU parity of the spike buffers and delivery (Sec. 2.3), the consumer of
+the calibrated connections, through the C ABI, against the CPU oracle.
+
+The GPU accumulates input in fp32 with atomics, so the order of additions
+varies.  Bound per target and step: each delivered term w*m carries the
+weight parity bound 1e-6 (|base| + |w - base|) m, and each of the k
+additions rounds once, at most 2^-24 of the running sum's magnitude, so
+|gpu - oracle| <= 1e-6 * sum (|base| + |w - base|) m + (k + 1) 2^-24 sum |w| m.
+The sums and k come from the oracle with the weights replaced."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2306_09855_amd import workloads as W
+from parity import per_record_base
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2306_09855_amd import ng  # noqa: E402
+from paper_2306_09855_amd.network import Network, arena_bytes_for  # noqa: E402
+
+
+def _spikes(rng, n_nodes, n_steps, p, always=()):
+    out = []
+    for _ in range(n_steps):
+        nodes = np.union1d(np.nonzero(rng.random(n_nodes) < p)[0], np.asarray(always, np.int64))
+        out.append((nodes.astype(np.uint32), rng.integers(1, 4, nodes.size).astype(np.uint32)))
+    return out
+
+
+def _gpu(wl, n_nodes, spikes, block_size=1 << 16):
+    with Network(wl.seed, wl.h, block_size, arena_bytes_for(wl.n_syn, n_nodes, wl.max_delay, block_size) + (64 << 20)) as net:
+        net.create(n_nodes)
+        for c in wl.calls:
+            net.connect(c)
+        net.calibrate()
+        net.spikes_init()
+        inp = torch.zeros(n_nodes, dtype=torch.float32, device="cuda")
+        out = np.zeros((len(spikes), n_nodes), np.float32)
+        for s, (nodes, mult) in enumerate(spikes):
+            inp.zero_()
+            net.spikes_step(torch.from_numpy(nodes.astype(np.int32)).cuda(), inp,
+                            torch.from_numpy(mult.astype(np.int32)).cuda())
+            out[s] = inp.cpu().numpy()
+        ng.ng_sync(net.ctx)
+    return out
+
+
+def _check(wl, n_nodes, spikes):
+    ref = oracle.build_network(wl.seed, wl.h, n_nodes, wl.calls)
+    want = oracle.deliver(n_nodes, ref, spikes)
+    base = per_record_base(wl.calls, ref["perm"])
+    bound_w = dict(ref, s_w=np.abs(base) + np.abs(ref["s_w"] - base))
+    s_bound = oracle.deliver(n_nodes, bound_w, spikes)
+    s_abs = oracle.deliver(n_nodes, dict(ref, s_w=np.abs(ref["s_w"])), spikes)
+    ones = [(n, np.ones_like(m)) for n, m in spikes]
+    k = oracle.deliver(n_nodes, dict(ref, s_w=np.ones_like(ref["s_w"])), ones)
+    got = _gpu(wl, n_nodes, spikes)
+    tol = 1e-6 * s_bound + (k + 1) * 2.0 ** -24 * s_abs
+    err = np.abs(got.astype(np.float64) - want)
+    bad = np.argwhere(err > tol)
+    assert bad.size == 0, f"{len(bad)} inputs outside the bound; first {bad[0]}: gpu {got[tuple(bad[0])]} " \
+                          f"ref {want[tuple(bad[0])]} tol {tol[tuple(bad[0])]}"
+    assert np.abs(want).max() > 0
+
+
+def test_delivery_small_network():
+    calls = [
+        W.Call("fixed_total_number", (0, 40), (40, 60), 3000, ("normal", 0.5, 0.2), ("uniform_int", 1, 20)),
+        W.Call("fixed_indegree", (40, 60), (0, 40), 7, ("uniform", -1.0, 1.0), ("uniform_int", 1, 5)),
+        W.Call("all_to_all", (90, 5), (0, 100), 0, ("const", 0.25), ("const", 1.3)),
+    ]
+    wl = W.Workload("spikes_small", 11, [120], calls)
+    spikes = _spikes(np.random.default_rng(1), 120, 80, 0.1, always=(3, 45, 92, 110))
+    _check(wl, 120, spikes)
+
+
+def test_delivery_microcircuit_scaled():
+    wl = W.microcircuit(scale=0.05)
+    spikes = _spikes(np.random.default_rng(2), wl.n_nodes, 60, 0.01)
+    _check(wl, wl.n_nodes, spikes)
+
+
+def test_spike_errors_and_lifetime():
+    wl = W.Workload("spk", 3, [50], [W.Call("all_to_all", (0, 50), (0, 50), 0, ("const", 1.0), ("const", 0.2))])
+    with Network(3, 0.1, 1 << 16, 64 << 20) as net:
+        net.create(50)
+        net.connect(wl.calls[0])
+        inp = torch.zeros(50, dtype=torch.float32, device="cuda")
+        with pytest.raises(ng.NGError) as e:
+            net.spikes_step(None, inp)
+        assert e.value.status == ng.NG_ERR_STATE  # not calibrated
+        net.calibrate()
+        with pytest.raises(ng.NGError) as e:
+            net.spikes_step(None, inp)
+        assert e.value.status == ng.NG_ERR_STATE  # buffers not initialised
+        net.spikes_init()
+        for nodes in ([4, 4], [50]):  # a node twice in one step; a node out of range
+            net.spikes_step(torch.tensor(nodes, dtype=torch.int32, device="cuda"), inp)
+            with pytest.raises(ng.NGError) as e:
+                ng.ng_sync(net.ctx)
+            assert e.value.status == ng.NG_ERR_INVALID_ARG
+            ng.ng_sync(net.ctx)  # reported once
+        # the accepted spike of node 4 arrives two steps later at all 50 targets
+        inp.zero_()
+        net.spikes_step(None, inp)
+        net.spikes_step(None, inp)
+        assert torch.all(inp == 1.0)
+        # a new calibration releases the buffers
+        net.connect(wl.calls[0])
+        net.calibrate()
+        with pytest.raises(ng.NGError) as e:
+            net.spikes_step(None, inp)
+        assert e.value.status == ng.NG_ERR_STATE
