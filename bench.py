@@ -371,6 +371,52 @@ def arrays_bench(wl, block_size: int, steps: int, warmup: int, radix_bits: int, 
             "apply_bytes_per_connection": 26, "kernels": per}
 
 
+def delivery_bench(wl, block_size: int, rate_per_step: float = 1e-3, warm_steps: int = 100,
+                   steps: int = 500) -> dict:
+    """Spike buffers and delivery over the calibrated network: random spike
+    trains with `rate_per_step` spikes per node and step (10 Hz at 0.1 ms),
+    `warm_steps` steps to fill the queues, then `steps` timed steps."""
+    import numpy as np
+    import torch
+    from paper_2306_09855_amd import ng
+    from paper_2306_09855_amd.network import Network, arena_bytes_for
+
+    arena = arena_bytes_for(wl.n_syn, wl.n_nodes, wl.max_delay, block_size, 9) + (512 << 20)
+    side = torch.cuda.Stream()
+    net = Network(wl.seed, wl.h, block_size, arena, stream=side.cuda_stream)
+    net.build(wl)
+    net.spikes_init()
+    gp, gs = net.group_index()
+    outdeg = gs[gp[1:].astype(np.int64)].astype(np.int64) - gs[gp[:-1].astype(np.int64)].astype(np.int64)
+    rng = np.random.default_rng(7)
+    trains = [np.nonzero(rng.random(wl.n_nodes) < rate_per_step)[0] for _ in range(warm_steps + steps)]
+    dev = [torch.from_numpy(t.astype(np.int32)).cuda() for t in trains]
+    inp = torch.zeros(wl.n_nodes, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    ctx = net.ctx
+    for t in range(warm_steps):
+        ng.ng_spikes_step(ctx, dev[t], None, dev[t].numel(), inp)
+    ng.ng_sync(ctx)
+    ng.ng_enable_timing(ctx, True)
+    ng.ng_read_timing(ctx, reset=True)
+    t0 = time.perf_counter()
+    for t in range(warm_steps, warm_steps + steps):
+        ng.ng_spikes_step(ctx, dev[t], None, dev[t].numel(), inp)
+    ng.ng_sync(ctx)
+    t1 = time.perf_counter()
+    kernels = ng.ng_read_timing(ctx, reset=True)
+    ng.ng_enable_timing(ctx, False)
+    net.close()
+    emitted = sum(int(outdeg[t].sum()) for t in trains[warm_steps:])
+    wall = t1 - t0
+    dev_ms = kernels.get("spikes_step", (steps, 0.0))[1]
+    return {"steps": steps, "spikes_per_step": round(sum(len(t) for t in trains[warm_steps:]) / steps, 1),
+            "us_per_step": round(1e6 * wall / steps, 2), "device_us_per_step": round(1e3 * dev_ms / steps, 2),
+            "connections_delivered_per_s": emitted / wall,
+            "delivered_note": "out-degree of the spikes emitted in the timed steps",
+            "GBps_algorithmic": round(8.0 * emitted / (dev_ms / 1e3) / 1e9, 1) if dev_ms else None}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -387,6 +433,8 @@ def main() -> int:
     ap.add_argument("--block-size", type=int, default=1 << 24)
     ap.add_argument("--cpu-sample", type=float, default=6e7, help="synapses of the oracle sample; 0 skips")
     ap.add_argument("--total", type=float, default=3.0e8)
+    ap.add_argument("--delivery", type=int, default=1,
+                    help="also time spike delivery (Sec. 2.3) over the calibrated network")
     ap.add_argument("--arrays", type=int, default=1,
                     help="also time the build with index arrays and per-connection weights/delays")
     ap.add_argument("--copass", type=int, default=1,
@@ -554,6 +602,11 @@ def main() -> int:
         ar = arrays_bench(wl, args.block_size, max(1, min(args.steps, 3)), 1, args.radix_bits, args.sort_ranges)
         log(f"arrays: {ar['ms_per_step']} ms/step")
         result["arrays"] = ar
+        torch.cuda.empty_cache()
+    if args.delivery and args.form == "plain" and wl.name == "microcircuit":
+        dl = delivery_bench(wl, args.block_size)
+        log(f"delivery: {dl['us_per_step']} us/step, {dl['connections_delivered_per_s']:.3g} connections/s")
+        result["delivery"] = dl
         torch.cuda.empty_cache()
     if args.serve:
         sv = serving_bench()
