@@ -49,9 +49,16 @@ def algorithmic_bytes(kernel: str, n_syn: int, passes: int) -> float | None:
 
 
 def kernels_fingerprint() -> str:
+    """Hash of the radix-sort section of the kernel source (the counters are
+    taken on the sort kernels; other sections do not change them)."""
     import hashlib
     with open(os.path.join(ROOT, "paper_2306_09855_amd", "csrc", "ng_kernels.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+        src = f.read()
+    a = src.find(b"// Radix sort: reduce-then-scan")
+    b = src.find(b"// Device-wide exclusive scan")
+    if a < 0 or b < a:
+        raise RuntimeError("radix-sort section markers not found in ng_kernels.hip")
+    return hashlib.sha256(src[a:b]).hexdigest()[:16]
 
 
 def measured_traffic(kernel: str, workload: str):
