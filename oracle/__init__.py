@@ -51,6 +51,7 @@ class _Call(ctypes.Structure):
         ("d_kind", ctypes.c_int32), ("d_a", ctypes.c_double), ("d_b", ctypes.c_double),
         ("src_idx", ctypes.c_void_p), ("tgt_idx", ctypes.c_void_p),
         ("w_arr", ctypes.c_void_p), ("d_arr", ctypes.c_void_p),
+        ("allow_autapses", ctypes.c_int32),
     ]
 
 
@@ -127,7 +128,8 @@ def to_struct(call) -> _Call:
                int(call.tgt[0]), int(call.tgt[1]), int(call.k_or_n),
                KINDS[wk], float(wa), float(wb), KINDS[dk], float(da), float(db),
                arr("src_idx", np.uint32), arr("tgt_idx", np.uint32),
-               arr("w_arr", np.float32), arr("d_arr", np.float32))
+               arr("w_arr", np.float32), arr("d_arr", np.float32),
+               int(getattr(call, "allow_autapses", 1)))
     st._keep = keep
     return st
 

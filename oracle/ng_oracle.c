@@ -96,23 +96,39 @@ int32_t ora_uniform_ms_delay(uint32_t x, double lo, double hi, float h) {
 /* ---------------------------------------------------------------------- */
 /* Connection rules, Sec. 2.1 Eqs. (4)-(13)                                */
 /* ---------------------------------------------------------------------- */
+/* number of nodes in both ranges */
+static uint64_t overlap(const ora_call* c) {
+  const uint64_t a = c->s0 > c->t0 ? c->s0 : c->t0;
+  const uint64_t b0 = (uint64_t)c->s0 + c->ns, b1 = (uint64_t)c->t0 + c->nt;
+  const uint64_t b = b0 < b1 ? b0 : b1;
+  return b > a ? b - a : 0;
+}
+
+static int no_self(const ora_call* c) { return !c->allow_autapses && !c->src_idx && !c->tgt_idx; }
+
 int64_t ora_count(const ora_call* c) {
   if ((uint64_t)c->s0 + c->ns > 0xFFFFFFFFull || (uint64_t)c->t0 + c->nt > 0xFFFFFFFFull)
     return -1;
+  if (!c->allow_autapses && (c->src_idx || c->tgt_idx)) return -1;
+  const int ns_ = no_self(c);
   switch (c->rule) {
     case ORA_ONE_TO_ONE: /* N_new = N_sources = N_targets */
       if (c->ns != c->nt) return -1;
+      if (ns_ && c->s0 == c->t0) return 0;  /* every pair would be an autapse */
       return (int64_t)c->ns;
-    case ORA_ALL_TO_ALL: /* N_new = N_sources * N_targets */
-      return (int64_t)c->ns * (int64_t)c->nt;
+    case ORA_ALL_TO_ALL: /* N_new = N_sources * N_targets (minus the pairs s == t) */
+      return (int64_t)c->ns * (int64_t)c->nt - (ns_ ? (int64_t)overlap(c) : 0);
     case ORA_FIXED_OUTDEGREE: /* N_new = N_sources * K, random targets need N_t > 0 */
       if (c->nt == 0 && c->ns > 0 && c->k_or_n > 0) return -1;
+      if (ns_ && c->nt == 1 && overlap(c) && c->k_or_n > 0) return -1;  /* a source with no other target */
       return (int64_t)c->ns * (int64_t)c->k_or_n;
     case ORA_FIXED_INDEGREE: /* N_new = N_targets * K, random sources need N_s > 0 */
       if (c->ns == 0 && c->nt > 0 && c->k_or_n > 0) return -1;
+      if (ns_ && c->ns == 1 && overlap(c) && c->k_or_n > 0) return -1;  /* a target with no other source */
       return (int64_t)c->nt * (int64_t)c->k_or_n;
     case ORA_FIXED_TOTAL_NUMBER: /* N_new given */
       if ((c->ns == 0 || c->nt == 0) && c->k_or_n > 0) return -1;
+      if (ns_ && (uint64_t)c->ns * c->nt == overlap(c) && c->k_or_n > 0) return -1;  /* only autapses */
       return (int64_t)c->k_or_n;
     default:
       return -1;
@@ -141,24 +157,66 @@ int ora_synapse(uint64_t seed, float h, uint32_t cid, const ora_call* c, uint64_
       t_off = i;
       break;
     case ORA_ALL_TO_ALL: /* Eqs. (6)-(7) */
-      s_off = i / c->nt;
-      t_off = i % c->nt;
+      if (!no_self(c)) {
+        s_off = i / c->nt;
+        t_off = i % c->nt;
+      } else {
+        /* walk the rows: row a has N_t targets, minus one if its source is a target */
+        uint64_t rem = i, a = 0;
+        for (;; a++) {
+          const uint64_t s = c->s0 + a;
+          const int in_t = s >= c->t0 && s < (uint64_t)c->t0 + c->nt;
+          const uint64_t len = c->nt - (in_t ? 1 : 0);
+          if (rem < len) {
+            t_off = rem;
+            if (in_t && c->t0 + t_off >= s) t_off++;  /* skip t == s */
+            break;
+          }
+          rem -= len;
+        }
+        s_off = a;
+      }
       break;
     case ORA_FIXED_OUTDEGREE: /* Eqs. (8)-(9) */
       s_off = i / k;
-      t_off = ora_rand_below(ora_word(seed, cid, 0, q), c->nt);
+      {
+        const uint64_t s = c->s0 + s_off;
+        const int in_t = no_self(c) && s >= c->t0 && s < (uint64_t)c->t0 + c->nt;
+        t_off = ora_rand_below(ora_word(seed, cid, 0, q), c->nt - (in_t ? 1 : 0));
+        if (in_t && t_off >= s - c->t0) t_off++;
+      }
       q++;
       break;
     case ORA_FIXED_INDEGREE: /* Eqs. (10)-(11) */
-      s_off = ora_rand_below(ora_word(seed, cid, 0, q), c->ns);
-      q++;
       t_off = i / k;
+      {
+        const uint64_t t = c->t0 + t_off;
+        const int in_s = no_self(c) && t >= c->s0 && t < (uint64_t)c->s0 + c->ns;
+        s_off = ora_rand_below(ora_word(seed, cid, 0, q), c->ns - (in_s ? 1 : 0));
+        if (in_s && s_off >= t - c->s0) s_off++;
+      }
+      q++;
       break;
     case ORA_FIXED_TOTAL_NUMBER: /* Eqs. (12)-(13): source draw, then target draw */
       s_off = ora_rand_below(ora_word(seed, cid, 0, q), c->ns);
       q++;
       t_off = ora_rand_below(ora_word(seed, cid, 0, q), c->nt);
       q++;
+      if (no_self(c)) {
+        for (uint32_t a = 1; c->s0 + s_off == c->t0 + t_off; a++) {
+          const uint32_t st = 65536u + (a <= 64 ? a : 64);
+          s_off = ora_rand_below(ora_word(seed, cid, st, 2 * i), c->ns);
+          if (a < 64) {
+            t_off = ora_rand_below(ora_word(seed, cid, st, 2 * i + 1), c->nt);
+          } else {  /* last attempt: a target other than the source */
+            const uint64_t s = c->s0 + s_off;
+            const int in_t = s >= c->t0 && s < (uint64_t)c->t0 + c->nt;
+            t_off = ora_rand_below(ora_word(seed, cid, st, 2 * i + 1), c->nt - (in_t ? 1 : 0));
+            if (in_t && t_off >= s - c->t0) t_off++;
+            break;
+          }
+        }
+      }
       break;
     default:
       return -1;

@@ -63,6 +63,21 @@ typedef struct {
   const uint32_t* tgt_idx;
   const float* w_arr;
   const float* d_arr;
+  /* 0: no connection from a node to itself (Discussion: a flag the paper
+   * names as future work).  Ranges only.  Definitions:
+   *   one_to_one       the pairs with s != t (none if s0 == t0);
+   *   all_to_all       the pairs with s != t, row by row (row s has N_t or
+   *                    N_t - 1 targets), targets ascending;
+   *   fixed_indegree   a target inside the source range draws from the other
+   *                    N_s - 1 sources: r = rand(N_s - 1) from its usual word,
+   *                    then r + 1 if r >= the target's position in the range;
+   *   fixed_outdegree  the same with sources and targets exchanged;
+   *   fixed_total_number  attempt 0 draws (s, t) from the usual words; while
+   *                    s == t, attempt a >= 1 draws both from words 2i, 2i+1
+   *                    of stream 65536 + a; after 64 attempts the target is
+   *                    drawn from the other N_t - 1 targets as for
+   *                    fixed_outdegree, from attempt 64's target word. */
+  int32_t allow_autapses;
 } ora_call;
 
 /* Philox4x32-10 block function */
