@@ -64,7 +64,18 @@ typedef struct {
   uint32_t first, n;
 } ng_range;
 
-/* Connection rules of Sec. 2.1, autapses and multapses allowed. */
+/* Connection rules of Sec. 2.1, multapses allowed.  With allow_autapses = 0
+ * (a flag the paper names as future work, Discussion) no connection joins a
+ * node to itself:
+ *   one_to_one       no connections if the ranges start at the same node;
+ *   all_to_all       the pairs s != t, row by row, targets ascending;
+ *   fixed_indegree   a target inside the source range draws from the other
+ *                    N_s - 1 sources (rand(N_s - 1) from its usual word, the
+ *                    target's own position skipped); fixed_outdegree likewise;
+ *   fixed_total_number  a drawn pair with s == t is redrawn from words 2i,
+ *                    2i+1 of stream 65536 + a for attempt a = 1, 2, ...; the
+ *                    64th attempt draws the target among the others.
+ * Calls that could only make autapses fail with NG_ERR_INVALID_ARG. */
 typedef enum {
   NG_ONE_TO_ONE = 0,         /* Eqs. (4)-(5): N_new = N_s = N_t         */
   NG_ALL_TO_ALL = 1,         /* Eqs. (6)-(7): N_new = N_s * N_t         */
@@ -75,7 +86,7 @@ typedef enum {
 
 typedef struct {
   int32_t rule;            /* ng_rule */
-  int32_t allow_autapses;  /* must be 1, or the ranges must not overlap */
+  int32_t allow_autapses;  /* 0: no connection from a node to itself (below) */
   int32_t allow_multapses; /* must be 1 (the paper's rules allow multapses) */
   int32_t reserved;
   uint64_t k_or_n;         /* K for in/out-degree, N for fixed_total_number */

@@ -31,6 +31,8 @@ struct GenDesc {
   uint32_t d_range;  // D_UNIFORM_INT: hi - lo + 1
   float d_ms_lo, d_ms_width, h;  // D_UNIFORM_MS
   int32_t max_delay; // largest delay this call can produce (host bookkeeping)
+  uint32_t no_self;  // no connection from a node to itself, and the ranges overlap
+  uint32_t a_lo, a_hi;  // all_to_all without autapses: source positions whose node is a target
   uint64_t group0;   // batched form: index of this call's first 4-synapse group
   char* const* blocks;        // batched form: block table of the call's context
   const uint32_t* key;        // batched form: Philox key of the call's context

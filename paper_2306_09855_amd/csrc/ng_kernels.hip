@@ -79,7 +79,69 @@ __device__ __forceinline__ void gen_quad(const GenDesc& d, uint32_t g, uint32_t 
     philox_block((uint64_t)g * W0 + m, d.cid, 0u, key0, key1, &x[4 * m]);
 
   // source / target indices, Eqs. (4)-(13)
-  if constexpr (RULE == R_ONE_TO_ONE) {
+  if (d.no_self && RULE != R_ONE_TO_ONE) {
+    // no connection from a node to itself (the ranges overlap)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const uint32_t i = i0 + r;
+      if constexpr (RULE == R_ALL_TO_ALL) {
+        // rows before the overlap have N_t targets, rows of sources that are
+        // targets N_t - 1 (their own node skipped), rows after it N_t
+        const uint64_t p1 = (uint64_t)d.a_lo * d.nt;
+        const uint32_t l2 = d.nt > 1 ? d.nt - 1 : 1;
+        const uint64_t p2 = p1 + (uint64_t)(d.a_hi - d.a_lo) * (d.nt - 1);
+        uint32_t a, b;
+        if (i < p1) {
+          a = i / d.nt;
+          b = i - a * d.nt;
+        } else if (i < p2) {
+          const uint32_t j = (uint32_t)(i - p1);
+          a = d.a_lo + j / l2;
+          b = j - (a - d.a_lo) * l2;
+          if (d.t0 + b >= d.s0 + a) ++b;  // skip t == s
+        } else {
+          const uint32_t j = (uint32_t)(i - p2);
+          a = d.a_hi + j / d.nt;
+          b = j - (a - d.a_hi) * d.nt;
+        }
+        q.s[r] = d.s0 + a;
+        q.t[r] = d.t0 + b;
+      } else if constexpr (RULE == R_OUTDEG) {
+        const uint32_t s = d.s0 + i / d.k;
+        const bool in_t = s - d.t0 < d.nt;  // s in [t0, t0 + nt)
+        uint32_t b = rand_below(x[r * W0], d.nt - (in_t ? 1u : 0u));
+        if (in_t && b >= s - d.t0) ++b;
+        q.s[r] = s;
+        q.t[r] = d.t0 + b;
+      } else if constexpr (RULE == R_INDEG) {
+        const uint32_t t = d.t0 + i / d.k;
+        const bool in_s = t - d.s0 < d.ns;
+        uint32_t a = rand_below(x[r * W0], d.ns - (in_s ? 1u : 0u));
+        if (in_s && a >= t - d.s0) ++a;
+        q.s[r] = d.s0 + a;
+        q.t[r] = t;
+      } else {  // R_TOTAL: redraw autapses from attempt streams 65536 + a, words 2i and 2i+1
+        uint32_t a = rand_below(x[r * W0], d.ns), b = rand_below(x[r * W0 + 1], d.nt);
+        for (uint32_t att = 1; d.s0 + a == d.t0 + b; ++att) {
+          uint32_t y[4];
+          philox_block(i >> 1, d.cid, 65536u + att, key0, key1, y);
+          const uint32_t ys = y[(i & 1u) * 2], yt = y[(i & 1u) * 2 + 1];
+          a = rand_below(ys, d.ns);
+          if (att < 64) {
+            b = rand_below(yt, d.nt);
+          } else {  // the last attempt draws a target other than the source
+            const uint32_t s = d.s0 + a;
+            const bool in_t = s - d.t0 < d.nt;
+            b = rand_below(yt, d.nt - (in_t ? 1u : 0u));
+            if (in_t && b >= s - d.t0) ++b;
+            break;
+          }
+        }
+        q.s[r] = d.s0 + a;
+        q.t[r] = d.t0 + b;
+      }
+    }
+  } else if constexpr (RULE == R_ONE_TO_ONE) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       q.s[r] = d.s0 + i0 + r;

@@ -59,34 +59,40 @@ int plan_call(uint32_t n_nodes, ng_range src, ng_range tgt, const ng_conn_spec* 
                 src.first, src.n, tgt.first, tgt.n, n_nodes);
   if (!conn->allow_multapses)
     return fail(NG_ERR_UNSUPPORTED, "allow_multapses = 0 is not implemented (the rules allow multapses)");
-  if (!conn->allow_autapses) {
-    const bool overlap = src.n && tgt.n && src.first < tgt.first + tgt.n && tgt.first < src.first + src.n;
-    if (overlap)
-      return fail(NG_ERR_UNSUPPORTED, "allow_autapses = 0 with overlapping ranges is not implemented");
-  }
   const uint64_t ns = src.n, nt = tgt.n, k = conn->k_or_n;
+  // allow_autapses = 0 matters only where the ranges share nodes
+  const uint64_t ov_lo = std::max<uint64_t>(src.first, tgt.first);
+  const uint64_t ov_hi = std::min<uint64_t>((uint64_t)src.first + ns, (uint64_t)tgt.first + nt);
+  const uint64_t ov = ov_hi > ov_lo ? ov_hi - ov_lo : 0;
+  const bool no_self = !conn->allow_autapses && ov > 0;
   uint64_t n = 0;
   switch (conn->rule) {
     case NG_ONE_TO_ONE:
       if (ns != nt) return fail(NG_ERR_INVALID_ARG, "one_to_one needs equal ranges (%llu vs %llu)",
                                 (unsigned long long)ns, (unsigned long long)nt);
-      n = ns;
+      n = (no_self && src.first == tgt.first) ? 0 : ns;  // with s0 != t0 no pair is s == t
       break;
-    case NG_ALL_TO_ALL: n = ns * nt; break;
+    case NG_ALL_TO_ALL: n = ns * nt - (no_self ? ov : 0); break;
     case NG_FIXED_INDEGREE:
       if (k > 0xFFFFFFFFull) return fail(NG_ERR_TOO_LARGE, "K too large");
       n = nt * k;
       if (n && ns == 0) return fail(NG_ERR_INVALID_ARG, "fixed_indegree needs a non-empty source range");
+      if (n && no_self && ns == 1)
+        return fail(NG_ERR_INVALID_ARG, "fixed_indegree without autapses: a target has no other source");
       break;
     case NG_FIXED_OUTDEGREE:
       if (k > 0xFFFFFFFFull) return fail(NG_ERR_TOO_LARGE, "K too large");
       n = ns * k;
       if (n && nt == 0) return fail(NG_ERR_INVALID_ARG, "fixed_outdegree needs a non-empty target range");
+      if (n && no_self && nt == 1)
+        return fail(NG_ERR_INVALID_ARG, "fixed_outdegree without autapses: a source has no other target");
       break;
     case NG_FIXED_TOTAL_NUMBER:
       n = k;
       if (n && (ns == 0 || nt == 0))
         return fail(NG_ERR_INVALID_ARG, "fixed_total_number needs non-empty ranges");
+      if (n && no_self && ns * nt == ov)
+        return fail(NG_ERR_INVALID_ARG, "fixed_total_number without autapses: every pair is an autapse");
       break;
     default: return fail(NG_ERR_INVALID_ARG, "unknown rule %d", conn->rule);
   }
@@ -101,6 +107,11 @@ int plan_call(uint32_t n_nodes, ng_range src, ng_range tgt, const ng_conn_spec* 
   d.t0 = tgt.first;
   d.nt = tgt.n;
   d.h = h;
+  if (no_self && conn->rule != NG_ONE_TO_ONE) {
+    d.no_self = 1;
+    d.a_lo = (uint32_t)(ov_lo - src.first);  // source positions whose node is also a target
+    d.a_hi = (uint32_t)(ov_hi - src.first);
+  }
 
   const ng_param& w = syn->weight;
   if (!std::isfinite(w.a) || !std::isfinite(w.b)) return fail(NG_ERR_INVALID_ARG, "non-finite weight parameter");

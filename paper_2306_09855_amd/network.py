@@ -60,7 +60,8 @@ class Network:
         """A Connect call whose groups may be index tensors (device, int32) and whose weights
         / delays (ms) may be per-connection device tensors (float32); the rule, K/N and
         distributions come from `call`."""
-        return ng.ng_connect_groups(self.ctx, ng.group(src), ng.group(tgt), ng.conn_spec(call.rule, call.k_or_n),
+        conn = ng.conn_spec(call.rule, call.k_or_n, allow_autapses=int(getattr(call, "allow_autapses", 1)))
+        return ng.ng_connect_groups(self.ctx, ng.group(src), ng.group(tgt), conn,
                                     ng.syn_spec(call.weight, call.delay), weights, delays_ms)
 
     def spikes_init(self):

@@ -203,7 +203,8 @@ def syn_spec(weight, delay) -> ng_syn_spec:
 
 def call_args(call):
     """(src range, tgt range, conn spec, syn spec) of a workloads.Call."""
-    return (ng_range(*call.src), ng_range(*call.tgt), conn_spec(call.rule, call.k_or_n),
+    return (ng_range(*call.src), ng_range(*call.tgt),
+            conn_spec(call.rule, call.k_or_n, allow_autapses=int(getattr(call, "allow_autapses", 1))),
             syn_spec(call.weight, call.delay))
 
 

@@ -106,11 +106,19 @@ def test_spec_errors(L):
 def test_autapse_multapse_flags(L):
     spec = ng.conn_spec("fixed_indegree", 3, allow_autapses=0)
     syn = ng.syn_spec(("const", 1.0), ("const", 1.0))
-    # disjoint ranges: autapses cannot occur, accepted
+    # disjoint ranges: autapses cannot occur
     assert ng.ng_plan_count(10, ng.ng_range(0, 5), ng.ng_range(5, 5), spec, syn, 0.1) == 15
-    with pytest.raises(ng.NGError) as e:
-        ng.ng_plan_count(10, ng.ng_range(0, 5), ng.ng_range(3, 5), spec, syn, 0.1)
-    assert e.value.status == ng.NG_ERR_UNSUPPORTED
+    # overlapping ranges: counts without the self-pairs
+    assert ng.ng_plan_count(10, ng.ng_range(0, 5), ng.ng_range(3, 5), spec, syn, 0.1) == 15
+    no_self = lambda rule, k=0: ng.conn_spec(rule, k, allow_autapses=0)  # noqa: E731
+    assert ng.ng_plan_count(10, ng.ng_range(0, 5), ng.ng_range(3, 5), no_self("all_to_all"), syn, 0.1) == 23
+    assert ng.ng_plan_count(10, ng.ng_range(2, 5), ng.ng_range(2, 5), no_self("one_to_one"), syn, 0.1) == 0
+    assert ng.ng_plan_count(10, ng.ng_range(2, 5), ng.ng_range(3, 5), no_self("one_to_one"), syn, 0.1) == 5
+    for rule, src, tgt in [("fixed_indegree", (4, 1), (3, 5)), ("fixed_outdegree", (3, 5), (4, 1)),
+                           ("fixed_total_number", (4, 1), (4, 1))]:
+        with pytest.raises(ng.NGError) as e:  # only autapses possible
+            ng.ng_plan_count(10, ng.ng_range(*src), ng.ng_range(*tgt), no_self(rule, 3), syn, 0.1)
+        assert e.value.status == ng.NG_ERR_INVALID_ARG
     with pytest.raises(ng.NGError) as e:
         ng.ng_plan_count(10, ng.ng_range(0, 5), ng.ng_range(5, 5),
                          ng.conn_spec("fixed_indegree", 3, allow_multapses=0), syn, 0.1)
