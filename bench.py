@@ -378,6 +378,53 @@ def arrays_bench(wl, block_size: int, steps: int, warmup: int, radix_bits: int, 
             "apply_bytes_per_connection": 26, "kernels": per}
 
 
+def no_autapse_bench(wl, block_size: int, steps: int, warmup: int, radix_bits: int, sort_ranges: int) -> dict:
+    """The same build with allow_autapses = 0 on every call: the calls whose
+    source and target populations are the same draw without self-pairs."""
+    import types
+    import torch
+    from paper_2306_09855_amd import ng
+    from paper_2306_09855_amd.network import Network, arena_bytes_for
+
+    arena = arena_bytes_for(wl.n_syn, wl.n_nodes, wl.max_delay, block_size, 9)
+    side = torch.cuda.Stream()
+    net = Network(wl.seed, wl.h, block_size, arena, stream=side.cuda_stream)
+    net.tune(radix_bits, sort_ranges)
+    ctx = net.ctx
+    calls = [ng.call_args(types.SimpleNamespace(rule=c.rule, src=c.src, tgt=c.tgt, k_or_n=c.k_or_n,
+                                                weight=c.weight, delay=c.delay, allow_autapses=0))
+             for c in wl.calls]
+    overlapping = sum(1 for c in wl.calls if c.src[0] < c.tgt[0] + c.tgt[1] and c.tgt[0] < c.src[0] + c.src[1])
+
+    def step():
+        ng.ng_reset(ctx)
+        for n in wl.populations:
+            ng.ng_create_nodes(ctx, n)
+        for a in calls:
+            ng.ng_connect(ctx, *a)
+        ng.ng_calibrate(ctx)
+
+    for _ in range(warmup):
+        step()
+    ng.ng_sync(ctx)
+    ng.ng_enable_timing(ctx, True)
+    ng.ng_read_timing(ctx, reset=True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    ng.ng_sync(ctx)
+    t1 = time.perf_counter()
+    kernels = ng.ng_read_timing(ctx, reset=True)
+    ng.ng_enable_timing(ctx, False)
+    n_conns = ng.ng_get_connections(ctx).n_conns
+    net.close()
+    ms = 1e3 * (t1 - t0) / steps
+    gen = kernels.get("generate", (0, 0.0))
+    return {"ms_per_step": round(ms, 3), "synapses": n_conns, "synapses_per_s": n_conns / (ms / 1e3),
+            "calls_with_overlapping_ranges": overlapping,
+            "generate_ms_per_step": round(gen[1] / steps, 4)}
+
+
 def delivery_bench(wl, block_size: int, rate_per_step: float = 1e-3, warm_steps: int = 100,
                    steps: int = 500) -> dict:
     """Spike buffers and delivery over the calibrated network: random spike
@@ -440,6 +487,8 @@ def main() -> int:
     ap.add_argument("--block-size", type=int, default=1 << 24)
     ap.add_argument("--cpu-sample", type=float, default=6e7, help="synapses of the oracle sample; 0 skips")
     ap.add_argument("--total", type=float, default=3.0e8)
+    ap.add_argument("--no-autapses", type=int, default=1,
+                    help="also time the build with allow_autapses = 0 on every call")
     ap.add_argument("--delivery", type=int, default=1,
                     help="also time spike delivery (Sec. 2.3) over the calibrated network")
     ap.add_argument("--arrays", type=int, default=1,
@@ -609,6 +658,11 @@ def main() -> int:
         ar = arrays_bench(wl, args.block_size, max(1, min(args.steps, 3)), 1, args.radix_bits, args.sort_ranges)
         log(f"arrays: {ar['ms_per_step']} ms/step")
         result["arrays"] = ar
+        torch.cuda.empty_cache()
+    if args.no_autapses and args.form == "plain" and wl.name == "microcircuit":
+        na = no_autapse_bench(wl, args.block_size, max(1, min(args.steps, 3)), 1, args.radix_bits, args.sort_ranges)
+        log(f"no autapses: {na['ms_per_step']} ms/step, generate {na['generate_ms_per_step']} ms")
+        result["no_autapses"] = na
         torch.cuda.empty_cache()
     if args.delivery and args.form == "plain" and wl.name == "microcircuit":
         dl = delivery_bench(wl, args.block_size)
