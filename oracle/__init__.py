@@ -28,6 +28,7 @@ RULES = {
     "fixed_indegree": 2,
     "fixed_outdegree": 3,
     "fixed_total_number": 4,
+    "pairwise_bernoulli": 5,
 }
 KINDS = {"const": 0, "normal": 1, "uniform_int": 2, "uniform": 3}
 
@@ -52,6 +53,7 @@ class _Call(ctypes.Structure):
         ("src_idx", ctypes.c_void_p), ("tgt_idx", ctypes.c_void_p),
         ("w_arr", ctypes.c_void_p), ("d_arr", ctypes.c_void_p),
         ("allow_autapses", ctypes.c_int32),
+        ("p", ctypes.c_double),
     ]
 
 
@@ -83,6 +85,8 @@ def lib():
         L.ora_delay_steps.restype = i32
         L.ora_uniform_ms_delay.argtypes = [u32, f64, f64, f32]
         L.ora_uniform_ms_delay.restype = i32
+        L.ora_count_pairwise.argtypes = [u64, u32, P(_Call)]
+        L.ora_count_pairwise.restype = ctypes.c_int64
         L.ora_count.argtypes = [P(_Call)]
         L.ora_count.restype = ctypes.c_int64
         L.ora_words_per_synapse.argtypes = [P(_Call)]
@@ -129,7 +133,7 @@ def to_struct(call) -> _Call:
                KINDS[wk], float(wa), float(wb), KINDS[dk], float(da), float(db),
                arr("src_idx", np.uint32), arr("tgt_idx", np.uint32),
                arr("w_arr", np.float32), arr("d_arr", np.float32),
-               int(getattr(call, "allow_autapses", 1)))
+               int(getattr(call, "allow_autapses", 1)), float(getattr(call, "p", 0.0)))
     st._keep = keep
     return st
 
@@ -174,6 +178,11 @@ def count(call) -> int:
     return int(lib().ora_count(ctypes.byref(to_struct(call))))
 
 
+def count_pairwise(seed: int, connect_id: int, call) -> int:
+    """Connections of a call of any rule (pairwise_bernoulli's depend on the draws)."""
+    return int(lib().ora_count_pairwise(seed, connect_id, ctypes.byref(to_struct(call))))
+
+
 def words_per_synapse(call) -> int:
     return int(lib().ora_words_per_synapse(ctypes.byref(to_struct(call))))
 
@@ -192,7 +201,7 @@ def synapse(seed: int, h: float, connect_id: int, call, i: int):
 def connect(seed: int, h: float, connect_id: int, call):
     """All synapses of one Connect call in creation order: (src, tgt, w fp64, delay)."""
     st = to_struct(call)
-    n = int(lib().ora_count(ctypes.byref(st)))
+    n = int(lib().ora_count_pairwise(seed, connect_id, ctypes.byref(st)))
     if n < 0:
         raise ValueError("invalid call")
     src = np.empty(n, np.uint32)

@@ -106,6 +106,13 @@ static uint64_t overlap(const ora_call* c) {
 
 static int no_self(const ora_call* c) { return !c->allow_autapses && !c->src_idx && !c->tgt_idx; }
 
+/* pairwise_bernoulli: is pair (a, b) a connection */
+static uint64_t pb_threshold(const ora_call* c) { return (uint64_t)floor(c->p * 4294967296.0); }
+static int pb_pair(uint64_t seed, uint32_t cid, const ora_call* c, uint64_t a, uint64_t b) {
+  if (no_self(c) && c->s0 + a == c->t0 + b) return 0;
+  return (uint64_t)ora_word(seed, cid, 0, a * c->nt + b) < pb_threshold(c);
+}
+
 int64_t ora_count(const ora_call* c) {
   if ((uint64_t)c->s0 + c->ns > 0xFFFFFFFFull || (uint64_t)c->t0 + c->nt > 0xFFFFFFFFull)
     return -1;
@@ -135,6 +142,16 @@ int64_t ora_count(const ora_call* c) {
   }
 }
 
+/* pairwise_bernoulli needs the seed and call id to count */
+int64_t ora_count_pairwise(uint64_t seed, uint32_t cid, const ora_call* c) {
+  if (c->rule != ORA_PAIRWISE_BERNOULLI) return ora_count(c);
+  if (!(c->p >= 0.0 && c->p <= 1.0) || c->src_idx || c->tgt_idx) return -1;
+  int64_t n = 0;
+  for (uint64_t a = 0; a < c->ns; a++)
+    for (uint64_t b = 0; b < c->nt; b++) n += pb_pair(seed, cid, c, a, b);
+  return n;
+}
+
 static int delay_is_random(const ora_call* c) { return c->d_arr == NULL && c->d_kind != ORA_CONST; }
 
 int ora_words_per_synapse(const ora_call* c) {
@@ -145,8 +162,23 @@ int ora_words_per_synapse(const ora_call* c) {
   return draws;
 }
 
+static int weight_and_delay(uint64_t seed, float h, uint32_t cid, const ora_call* c, uint64_t i, uint32_t dstream,
+                            uint64_t q, double* w, int32_t* delay);
+
 int ora_synapse(uint64_t seed, float h, uint32_t cid, const ora_call* c, uint64_t i,
                 uint32_t* src, uint32_t* tgt, double* w, int32_t* delay) {
+  if (c->rule == ORA_PAIRWISE_BERNOULLI) {
+    /* connection i is the i-th pair, in row order, that is a connection */
+    uint64_t seen = 0;
+    for (uint64_t a = 0; a < c->ns; a++)
+      for (uint64_t b = 0; b < c->nt; b++)
+        if (pb_pair(seed, cid, c, a, b) && seen++ == i) {
+          *src = c->s0 + (uint32_t)a;
+          *tgt = c->t0 + (uint32_t)b;
+          return weight_and_delay(seed, h, cid, c, i, 2, i, w, delay);
+        }
+    return -1;
+  }
   uint64_t w0 = (uint64_t)ora_words_per_synapse(c);
   uint64_t q = i * w0; /* first stream-0 word of synapse i */
   uint64_t k = c->k_or_n;
@@ -224,7 +256,13 @@ int ora_synapse(uint64_t seed, float h, uint32_t cid, const ora_call* c, uint64_
   /* explicit node arrays: the formulas give the array position */
   *src = c->src_idx ? c->src_idx[s_off] : c->s0 + (uint32_t)s_off;
   *tgt = c->tgt_idx ? c->tgt_idx[t_off] : c->t0 + (uint32_t)t_off;
+  return weight_and_delay(seed, h, cid, c, i, 0, q, w, delay);
+}
 
+/* delay of synapse i from word q of stream dstream (if random), weight from
+ * words 2i, 2i+1 of stream 1 (if random) */
+static int weight_and_delay(uint64_t seed, float h, uint32_t cid, const ora_call* c, uint64_t i, uint32_t dstream,
+                            uint64_t q, double* w, int32_t* delay) {
   if (c->d_arr) {
     *delay = ora_delay_steps(c->d_arr[i], h);
   } else switch (c->d_kind) {
@@ -233,11 +271,11 @@ int ora_synapse(uint64_t seed, float h, uint32_t cid, const ora_call* c, uint64_
       break;
     case ORA_UNIFORM_INT: { /* integer steps lo..hi */
       uint32_t lo = (uint32_t)c->d_a, hi = (uint32_t)c->d_b;
-      *delay = (int32_t)(lo + ora_rand_below(ora_word(seed, cid, 0, q), hi - lo + 1));
+      *delay = (int32_t)(lo + ora_rand_below(ora_word(seed, cid, dstream, q), hi - lo + 1));
       break;
     }
     case ORA_UNIFORM:
-      *delay = ora_uniform_ms_delay(ora_word(seed, cid, 0, q), c->d_a, c->d_b, h);
+      *delay = ora_uniform_ms_delay(ora_word(seed, cid, dstream, q), c->d_a, c->d_b, h);
       break;
     default:
       return -1;
@@ -266,6 +304,19 @@ int ora_synapse(uint64_t seed, float h, uint32_t cid, const ora_call* c, uint64_
 
 int ora_connect(uint64_t seed, float h, uint32_t cid, const ora_call* c, uint32_t* src,
                 uint32_t* tgt, double* w, int32_t* delay) {
+  if (c->rule == ORA_PAIRWISE_BERNOULLI) {  /* one walk over the pairs */
+    if (!(c->p >= 0.0 && c->p <= 1.0) || c->src_idx || c->tgt_idx) return -1;
+    uint64_t j = 0;
+    for (uint64_t a = 0; a < c->ns; a++)
+      for (uint64_t b = 0; b < c->nt; b++)
+        if (pb_pair(seed, cid, c, a, b)) {
+          src[j] = c->s0 + (uint32_t)a;
+          tgt[j] = c->t0 + (uint32_t)b;
+          if (weight_and_delay(seed, h, cid, c, j, 2, j, &w[j], &delay[j])) return -1;
+          j++;
+        }
+    return 0;
+  }
   int64_t n = ora_count(c);
   if (n < 0) return -1;
   for (int64_t i = 0; i < n; i++)

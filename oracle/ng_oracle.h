@@ -41,7 +41,7 @@ extern "C" {
 #endif
 
 enum { ORA_ONE_TO_ONE = 0, ORA_ALL_TO_ALL = 1, ORA_FIXED_INDEGREE = 2,
-       ORA_FIXED_OUTDEGREE = 3, ORA_FIXED_TOTAL_NUMBER = 4 };
+       ORA_FIXED_OUTDEGREE = 3, ORA_FIXED_TOTAL_NUMBER = 4, ORA_PAIRWISE_BERNOULLI = 5 };
 
 /* distribution kinds of a weight or delay specification */
 enum { ORA_CONST = 0, ORA_NORMAL = 1, ORA_UNIFORM_INT = 2, ORA_UNIFORM = 3 };
@@ -78,6 +78,13 @@ typedef struct {
    *                    drawn from the other N_t - 1 targets as for
    *                    fixed_outdegree, from attempt 64's target word. */
   int32_t allow_autapses;
+  /* pairwise_bernoulli (named as missing in the Discussion): every pair
+   * (s, t), rows of sources in order, targets ascending, is a connection
+   * when word (a * N_t + b) of stream 0 is below floor(p * 2^32) (a, b: the
+   * positions of s and t; self-pairs never with allow_autapses = 0); the
+   * connections are numbered in that order; connection j draws its delay
+   * from word j of stream 2 and its weight from words 2j, 2j+1 of stream 1. */
+  double p;
 } ora_call;
 
 /* Philox4x32-10 block function */
@@ -97,6 +104,8 @@ int32_t ora_uniform_ms_delay(uint32_t x, double lo, double hi, float h);
 
 /* number of connections a call creates, or -1 if the call is invalid */
 int64_t ora_count(const ora_call* call);
+/* count of any rule; pairwise_bernoulli's depends on the seed and call id */
+int64_t ora_count_pairwise(uint64_t seed, uint32_t connect_id, const ora_call* call);
 /* stream-0 words a synapse consumes */
 int ora_words_per_synapse(const ora_call* call);
 
