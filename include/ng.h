@@ -81,7 +81,8 @@ typedef enum {
   NG_ALL_TO_ALL = 1,         /* Eqs. (6)-(7): N_new = N_s * N_t         */
   NG_FIXED_INDEGREE = 2,     /* Eqs. (10)-(11): N_new = N_t * K          */
   NG_FIXED_OUTDEGREE = 3,    /* Eqs. (8)-(9): N_new = N_s * K           */
-  NG_FIXED_TOTAL_NUMBER = 4  /* Eqs. (12)-(13): N_new = N                */
+  NG_FIXED_TOTAL_NUMBER = 4, /* Eqs. (12)-(13): N_new = N                */
+  NG_PAIRWISE_BERNOULLI = 5  /* each pair with probability p (below)     */
 } ng_rule;
 
 typedef struct {
@@ -90,7 +91,21 @@ typedef struct {
   int32_t allow_multapses; /* must be 1 (the paper's rules allow multapses) */
   int32_t reserved;
   uint64_t k_or_n;         /* K for in/out-degree, N for fixed_total_number */
+  double p;                /* pairwise_bernoulli: connection probability in [0, 1] */
 } ng_conn_spec;
+
+/* pairwise_bernoulli (the Discussion names it as missing: the number of
+ * connections is not known before they are drawn).  Pair (s, t) -- rows of
+ * sources in order, targets ascending, positions a and b in the ranges --
+ * is a connection when word a * N_t + b of stream 0 is below
+ * floor(p * 2^32); with allow_autapses = 0 a self-pair never is.  The
+ * connections are numbered in pair order; connection j draws its delay from
+ * word j of stream 2 and its weight from words 2j, 2j+1 of stream 1.  Only
+ * ng_connect takes it: a counting pass over the pairs gives the exact number
+ * of connections, the host reads it (ng_connect synchronizes for this rule;
+ * NG_ERR_STATE under capture), reserves exactly that many, and a second pass
+ * writes them (never a multapse, so allow_multapses is ignored).  The
+ * batched, array and served forms return NG_ERR_UNSUPPORTED. */
 
 /* Weight and delay specifications (Sec. 2.1, last paragraph). */
 typedef enum {

@@ -33,6 +33,7 @@ struct GenDesc {
   int32_t max_delay; // largest delay this call can produce (host bookkeeping)
   uint32_t no_self;  // no connection from a node to itself, and the ranges overlap
   uint32_t a_lo, a_hi;  // all_to_all without autapses: source positions whose node is a target
+  uint64_t p_thr;       // pairwise_bernoulli: a pair connects when its word is below this
   uint64_t group0;   // batched form: index of this call's first 4-synapse group
   char* const* blocks;        // batched form: block table of the call's context
   const uint32_t* key;        // batched form: Philox key of the call's context
@@ -118,6 +119,16 @@ struct TabEntry {
   uint32_t pad;
 };
 hipError_t launch_set_entries(const TabEntry* d_entries, uint32_t n, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// pairwise_bernoulli: pairs (rows of sources, targets ascending) in units of
+// kPbUnit consecutive targets of one row.  count: counts[u] = connections of
+// unit u.  write: the connections of unit u from creation position
+// d.pos0 + offsets[u] on, in pair order.
+constexpr uint32_t kPbUnit = 4096;
+hipError_t launch_pb_count(const GenDesc& d, const uint32_t* d_key, uint32_t* counts, hipStream_t s);
+hipError_t launch_pb_write(const GenDesc& d, const uint32_t* d_key, const uint32_t* offsets, char* const* blocks,
+                           int log2B, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Spike buffers and delivery (Sec. 2.3) over the calibrated connections.

@@ -66,6 +66,29 @@ struct Quad {
   int32_t d[4];
 };
 
+// Random delay from one word (Sec. 2.1): integer steps, or ms -> steps with a
+// one-step minimum.
+__device__ __forceinline__ int32_t delay_from_word(const GenDesc& d, uint32_t xd) {
+  if (d.d_kind == D_UNIFORM_INT) return (int32_t)(d.d_lo + rand_below(xd, d.d_range));
+  const float u = (float)(xd >> 8) * kInv2p24;
+  const float ms = __fmaf_rn(d.d_ms_width, u, d.d_ms_lo);
+  const float steps = rintf(__fdiv_rn(ms, d.h));
+  return steps < 1.0f ? 1 : (int32_t)steps;
+}
+
+// Random weight from its two stream-1 words: Box-Muller (cosine branch) or uniform.
+__device__ __forceinline__ float weight_from_words(const GenDesc& d, uint32_t y0, uint32_t y1) {
+  if (d.w_kind == W_NORMAL) {
+    const float u1 = (float)((y0 >> 8) + 1u) * kInv2p24;  // (0, 1]
+    const float u2 = (float)(y1 >> 8) * kInv2p24;         // [0, 1)
+    const float rad = __fsqrt_rn(-2.0f * logf(u1));
+    const float z = rad * cospif(2.0f * u2);
+    return __fmaf_rn(d.w_b, z, d.w_a);
+  }
+  const float u = (float)(y0 >> 8) * kInv2p24;
+  return __fmaf_rn(d.w_b, u, d.w_a);
+}
+
 // Synapses i0..i0+3 of one call (i0 = 4g).  W0 = stream-0 words per synapse.
 template <int RULE, bool DRAND>
 __device__ __forceinline__ void gen_quad(const GenDesc& d, uint32_t g, uint32_t key0, uint32_t key1,
@@ -183,15 +206,7 @@ __device__ __forceinline__ void gen_quad(const GenDesc& d, uint32_t g, uint32_t 
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     if constexpr (DRAND) {
-      const uint32_t xd = x[r * W0 + NIDX];
-      if (d.d_kind == D_UNIFORM_INT) {
-        q.d[r] = (int32_t)(d.d_lo + rand_below(xd, d.d_range));
-      } else {
-        const float u = (float)(xd >> 8) * kInv2p24;
-        const float ms = __fmaf_rn(d.d_ms_width, u, d.d_ms_lo);
-        const float steps = rintf(__fdiv_rn(ms, d.h));
-        q.d[r] = steps < 1.0f ? 1 : (int32_t)steps;
-      }
+      q.d[r] = delay_from_word(d, x[r * W0 + NIDX]);
     } else {
       q.d[r] = d.d_const;
     }
@@ -205,22 +220,8 @@ __device__ __forceinline__ void gen_quad(const GenDesc& d, uint32_t g, uint32_t 
     uint32_t y[8];
     philox_block(2ull * g, d.cid, 1u, key0, key1, &y[0]);
     philox_block(2ull * g + 1, d.cid, 1u, key0, key1, &y[4]);
-    if (d.w_kind == W_NORMAL) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const float u1 = (float)((y[2 * r] >> 8) + 1u) * kInv2p24;  // (0, 1]
-        const float u2 = (float)(y[2 * r + 1] >> 8) * kInv2p24;     // [0, 1)
-        const float rad = __fsqrt_rn(-2.0f * logf(u1));
-        const float z = rad * cospif(2.0f * u2);
-        q.w[r] = __fmaf_rn(d.w_b, z, d.w_a);
-      }
-    } else {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const float u = (float)(y[2 * r] >> 8) * kInv2p24;
-        q.w[r] = __fmaf_rn(d.w_b, u, d.w_a);
-      }
-    }
+    for (int r = 0; r < 4; ++r) q.w[r] = weight_from_words(d, y[2 * r], y[2 * r + 1]);
   }
 }
 
@@ -1226,6 +1227,97 @@ hipError_t downsweep_rb(const SortPack& pk, const uint32_t* offsets, hipStream_t
 
 
 // ---------------------------------------------------------------------------
+// pairwise_bernoulli: pair (a, b) connects when word a*N_t + b of stream 0 is
+// below p * 2^32 (never a self-pair when those are prohibited).  A workgroup
+// takes one unit of kPbUnit targets of one row, 16 consecutive pairs per
+// thread; the counting pass and the writing pass evaluate the same words.
+// ---------------------------------------------------------------------------
+constexpr int kPbThreads = 256;
+constexpr int kPbPer = kPbUnit / kPbThreads;  // 16 pairs per thread
+
+__device__ __forceinline__ uint32_t pb_bits(const GenDesc& d, uint32_t a, uint32_t b0, uint32_t key0,
+                                            uint32_t key1) {
+  // bit k: pair (a, b0 + k) connects, for the pairs of this thread inside the row
+  uint32_t bits = 0;
+  uint64_t blk = ~0ull;
+  uint32_t w4[4] = {0, 0, 0, 0};
+  for (int k = 0; k < kPbPer; ++k) {
+    const uint32_t b = b0 + k;
+    if (b >= d.nt) break;
+    const uint64_t q = (uint64_t)a * d.nt + b;
+    if ((q >> 2) != blk) {
+      blk = q >> 2;
+      philox_block(blk, d.cid, 0u, key0, key1, w4);
+    }
+    const uint32_t x = w4[0] * ((q & 3) == 0) + w4[1] * ((q & 3) == 1) + w4[2] * ((q & 3) == 2) + w4[3] * ((q & 3) == 3);
+    const bool self = d.no_self && d.s0 + a == d.t0 + b;
+    if (!self && (uint64_t)x < d.p_thr) bits |= 1u << k;
+  }
+  return bits;
+}
+
+__global__ __launch_bounds__(kPbThreads) void k_pb_count(GenDesc d, const uint32_t* __restrict__ key,
+                                                         uint32_t* __restrict__ counts) {
+  __shared__ uint32_t s_tmp[kPbThreads / 64];
+  const uint32_t key0 = C(key, 0), key1 = C(key, 1);
+  const uint32_t upr = (d.nt + kPbUnit - 1) / kPbUnit;
+  const uint64_t units = (uint64_t)d.ns * upr;
+  for (uint64_t u = blockIdx.x; u < units; u += gridDim.x) {
+    const uint32_t a = (uint32_t)(u / upr), c = (uint32_t)(u - (uint64_t)a * upr);
+    const uint32_t bits = pb_bits(d, a, c * kPbUnit + threadIdx.x * kPbPer, key0, key1);
+    uint32_t total;
+    (void)block_exclusive_scan((uint32_t)__popc(bits), s_tmp, &total);
+    if (threadIdx.x == 0) counts[u] = total;
+    __syncthreads();  // s_tmp is reused by the next unit
+  }
+}
+
+__global__ __launch_bounds__(kPbThreads) void k_pb_write(GenDesc d, const uint32_t* __restrict__ key,
+                                                         const uint32_t* __restrict__ offsets,
+                                                         char* const* __restrict__ blocks, int log2B) {
+  __shared__ uint32_t s_tmp[kPbThreads / 64];
+  const uint32_t key0 = C(key, 0), key1 = C(key, 1);
+  const uint64_t B = 1ull << log2B;
+  const uint32_t upr = (d.nt + kPbUnit - 1) / kPbUnit;
+  const uint64_t units = (uint64_t)d.ns * upr;
+  for (uint64_t u = blockIdx.x; u < units; u += gridDim.x) {
+    const uint32_t a = (uint32_t)(u / upr), c = (uint32_t)(u - (uint64_t)a * upr);
+    const uint32_t b0 = c * kPbUnit + threadIdx.x * kPbPer;
+    uint32_t bits = pb_bits(d, a, b0, key0, key1);
+    uint32_t total;
+    uint32_t j = offsets[u] + block_exclusive_scan((uint32_t)__popc(bits), s_tmp, &total);
+    while (bits) {
+      const uint32_t k = (uint32_t)(__ffs(bits) - 1);
+      bits &= bits - 1;
+      // connection j of the call: delay from word j of stream 2, weight from
+      // words 2j, 2j+1 of stream 1
+      int32_t dl = d.d_const;
+      if (d.d_kind != D_CONST) {
+        uint32_t w4[4];
+        philox_block(j >> 2, d.cid, 2u, key0, key1, w4);
+        const uint32_t x = w4[0] * ((j & 3) == 0) + w4[1] * ((j & 3) == 1) + w4[2] * ((j & 3) == 2) + w4[3] * ((j & 3) == 3);
+        dl = delay_from_word(d, x);
+      }
+      float w = d.w_a;
+      if (d.w_kind != W_CONST) {
+        uint32_t y[4];
+        philox_block(j >> 1, d.cid, 1u, key0, key1, y);
+        w = weight_from_words(d, (j & 1) ? y[2] : y[0], (j & 1) ? y[3] : y[1]);
+      }
+      const uint64_t p = d.pos0 + j;
+      char* blk = G(blocks)[p >> log2B];
+      const uint64_t o = p & (B - 1);
+      G(reinterpret_cast<uint32_t*>(blk))[o] = d.s0 + a;
+      G(reinterpret_cast<uint32_t*>(blk + 4 * B))[o] = d.t0 + b0 + k;
+      G(reinterpret_cast<float*>(blk + 8 * B))[o] = w;
+      G(reinterpret_cast<int16_t*>(blk + 12 * B))[o] = (int16_t)dl;
+      ++j;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Spike buffers and delivery (Sec. 2.3).  Each node holds a ring of `cap`
 // spike slots (time index, group index within the node, multiplicity).  A
 // step advances every queued spike; a spike whose time index reaches its
@@ -1742,6 +1834,23 @@ hipError_t launch_set_ptrs(char** tab, uint32_t first, uint32_t count, const uin
                            hipStream_t s) {
   hipLaunchKernelGGL(k_set_ptrs, dim3(1), dim3(64), 0, s, tab, first, count, v[0], v[1], v[2], v[3],
                      v[4], v[5], v[6], v[7]);
+  return hipGetLastError();
+}
+
+hipError_t launch_pb_count(const GenDesc& d, const uint32_t* d_key, uint32_t* counts, hipStream_t s) {
+  const uint64_t units = (uint64_t)d.ns * ((d.nt + kPbUnit - 1) / kPbUnit);
+  if (units == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pb_count, dim3((uint32_t)std::min<uint64_t>(units, 65536)), dim3(kPbThreads), 0, s, d, d_key,
+                     counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_pb_write(const GenDesc& d, const uint32_t* d_key, const uint32_t* offsets, char* const* blocks,
+                           int log2B, hipStream_t s) {
+  const uint64_t units = (uint64_t)d.ns * ((d.nt + kPbUnit - 1) / kPbUnit);
+  if (units == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pb_write, dim3((uint32_t)std::min<uint64_t>(units, 65536)), dim3(kPbThreads), 0, s, d, d_key,
+                     offsets, blocks, log2B);
   return hipGetLastError();
 }
 

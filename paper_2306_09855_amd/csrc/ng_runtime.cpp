@@ -94,6 +94,8 @@ int plan_call(uint32_t n_nodes, ng_range src, ng_range tgt, const ng_conn_spec* 
       if (n && no_self && ns * nt == ov)
         return fail(NG_ERR_INVALID_ARG, "fixed_total_number without autapses: every pair is an autapse");
       break;
+    case NG_PAIRWISE_BERNOULLI:
+      return fail(NG_ERR_UNSUPPORTED, "pairwise_bernoulli is taken only by ng_connect (its count needs a device pass)");
     default: return fail(NG_ERR_INVALID_ARG, "unknown rule %d", conn->rule);
   }
   if (n > 0xFFFFFFFFull) return fail(NG_ERR_TOO_LARGE, "a call may create at most 2^32-1 connections");
@@ -1196,10 +1198,74 @@ int ng_create_nodes(ng_ctx* c, uint32_t n, ng_range* out) {
   return NG_OK;
 }
 
+// pairwise_bernoulli: count the connections on the device, read the total,
+// reserve exactly that many, write them.  All-or-nothing.
+static int connect_pairwise(ng_ctx* c, ng_range src, ng_range tgt, const ng_conn_spec* conn,
+                            const ng_syn_spec* syn, uint32_t* out_cid, uint64_t* out_first, uint64_t* out_n) {
+  if (int rc = not_capturing(c)) return rc;
+  if (!(conn->p >= 0.0 && conn->p <= 1.0)) return fail(NG_ERR_INVALID_ARG, "pairwise_bernoulli needs 0 <= p <= 1");
+  // the unit counts are scanned in 32 bits: fewer than 2^32 pairs bound every count
+  if ((uint64_t)src.n * tgt.n > 0xFFFFFFFFull)
+    return fail(NG_ERR_TOO_LARGE, "pairwise_bernoulli takes at most 2^32-1 source-target pairs per call");
+  if (!c->capturing) ctx_flush_frees(c);
+  // ranges, weight and delay as for all_to_all (no connection is made here)
+  ng_conn_spec a2a = *conn;
+  a2a.rule = NG_ALL_TO_ALL;
+  a2a.allow_multapses = 1;
+  Plan pl;
+  if (int rc = plan_call(c->n_nodes, src, tgt, &a2a, syn, c->cfg.h_ms, &pl)) return rc;
+  if (c->next_cid == 0xFFFFFFFFu) return fail(NG_ERR_TOO_LARGE, "connect call ids exhausted");
+  ng::GenDesc d = pl.d;
+  d.rule = NG_PAIRWISE_BERNOULLI;
+  d.p_thr = (uint64_t)std::floor(conn->p * 4294967296.0);
+  d.cid = c->next_cid;
+  d.no_self = !conn->allow_autapses;
+  const uint64_t units = (uint64_t)src.n * ((tgt.n + ng::kPbUnit - 1) / ng::kPbUnit);
+  uint64_t n = 0;
+  uint32_t* counts = nullptr;
+  uint64_t cbytes = 0;
+  if (units) {
+    cbytes = 4 * (units + 1);
+    const uint64_t tbytes = 4 * ng::scan_tmp_words(units);
+    counts = (uint32_t*)ctx_alloc(c, cbytes + tbytes);
+    if (!counts) {
+      c->need = Arena::round_up(cbytes + tbytes);
+      return fail(NG_ERR_OOM, "arena cannot hold the pair counts");
+    }
+    cbytes += tbytes;
+    uint32_t* tmp = counts + units + 1;
+    NG_LAUNCH(c, "pb_count", ng::launch_pb_count(d, key_ptr(c), counts, c->stream));
+    NG_LAUNCH(c, "scan", ng::launch_exclusive_scan(counts, counts, units, tmp, counts + units, c->stream));
+    uint32_t total = 0;
+    NG_HIP(c, hipMemcpyAsync(&total, counts + units, 4, hipMemcpyDeviceToHost, c->stream), "pair count");
+    NG_HIP(c, hipStreamSynchronize(c->stream), "pair count");
+    n = total;
+  }
+  if (c->n_conns + n > 0xFFFFFFFFull) {
+    ctx_unalloc(c, (char*)counts, cbytes);
+    return fail(NG_ERR_TOO_LARGE, "a context holds at most 2^32-1 connections");
+  }
+  if (int rc = reserve_blocks(c, n)) {
+    ctx_unalloc(c, (char*)counts, cbytes);
+    return rc;
+  }
+  d.n_new = (uint32_t)n;
+  d.pos0 = c->n_conns;
+  if (int rc = sync_table(c)) return rc;
+  if (n) NG_LAUNCH(c, "pb_write", ng::launch_pb_write(d, key_ptr(c), counts, c->d_tab[c->cur], c->log2B, c->stream));
+  ctx_free(c, (char*)counts, cbytes);
+  if (out_cid) *out_cid = d.cid;
+  if (out_first) *out_first = d.pos0;
+  if (out_n) *out_n = n;
+  connect_commit(c, d, pl.max_delay);
+  return NG_OK;
+}
+
 int ng_connect(ng_ctx* c, ng_range src, ng_range tgt, const ng_conn_spec* conn, const ng_syn_spec* syn,
                uint32_t* out_cid, uint64_t* out_first, uint64_t* out_n) {
   if (int rc = enter(c)) return rc;
   if (int rc = mutable_state(c)) return rc;
+  if (conn && conn->rule == NG_PAIRWISE_BERNOULLI) return connect_pairwise(c, src, tgt, conn, syn, out_cid, out_first, out_n);
   ng::GenDesc d;
   uint64_t n = 0;
   if (int rc = connect_prepare(c, src, tgt, conn, syn, &d, &n)) return rc;

@@ -24,12 +24,13 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "ng.h")
 NG_OK, NG_ERR_INVALID_ARG, NG_ERR_OOM, NG_ERR_UNSUPPORTED = 0, -1, -2, -3
 NG_ERR_STATE, NG_ERR_TOO_LARGE, NG_ERR_DEVICE = -4, -5, -6
 
-NG_ONE_TO_ONE, NG_ALL_TO_ALL, NG_FIXED_INDEGREE, NG_FIXED_OUTDEGREE, NG_FIXED_TOTAL_NUMBER = range(5)
+(NG_ONE_TO_ONE, NG_ALL_TO_ALL, NG_FIXED_INDEGREE, NG_FIXED_OUTDEGREE, NG_FIXED_TOTAL_NUMBER,
+ NG_PAIRWISE_BERNOULLI) = range(6)
 NG_CONST, NG_NORMAL, NG_UNIFORM_INT, NG_UNIFORM = range(4)
 
 RULE_CODES = {"one_to_one": NG_ONE_TO_ONE, "all_to_all": NG_ALL_TO_ALL,
               "fixed_indegree": NG_FIXED_INDEGREE, "fixed_outdegree": NG_FIXED_OUTDEGREE,
-              "fixed_total_number": NG_FIXED_TOTAL_NUMBER}
+              "fixed_total_number": NG_FIXED_TOTAL_NUMBER, "pairwise_bernoulli": NG_PAIRWISE_BERNOULLI}
 DIST_CODES = {"const": NG_CONST, "normal": NG_NORMAL, "uniform_int": NG_UNIFORM_INT,
               "uniform": NG_UNIFORM}
 
@@ -47,7 +48,7 @@ class ng_range(ctypes.Structure):
 class ng_conn_spec(ctypes.Structure):
     _fields_ = [("rule", ctypes.c_int32), ("allow_autapses", ctypes.c_int32),
                 ("allow_multapses", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("k_or_n", ctypes.c_uint64)]
+                ("k_or_n", ctypes.c_uint64), ("p", ctypes.c_double)]
 
 
 class ng_param(ctypes.Structure):
@@ -188,8 +189,9 @@ def _vp(x) -> ctypes.c_void_p:
 
 
 # --- marshalling of workload descriptions ----------------------------------
-def conn_spec(rule: str, k_or_n: int = 0, allow_autapses: int = 1, allow_multapses: int = 1) -> ng_conn_spec:
-    return ng_conn_spec(RULE_CODES[rule], allow_autapses, allow_multapses, 0, int(k_or_n))
+def conn_spec(rule: str, k_or_n: int = 0, allow_autapses: int = 1, allow_multapses: int = 1,
+              p: float = 0.0) -> ng_conn_spec:
+    return ng_conn_spec(RULE_CODES[rule], allow_autapses, allow_multapses, 0, int(k_or_n), float(p))
 
 
 def param(spec) -> ng_param:
@@ -204,7 +206,8 @@ def syn_spec(weight, delay) -> ng_syn_spec:
 def call_args(call):
     """(src range, tgt range, conn spec, syn spec) of a workloads.Call."""
     return (ng_range(*call.src), ng_range(*call.tgt),
-            conn_spec(call.rule, call.k_or_n, allow_autapses=int(getattr(call, "allow_autapses", 1))),
+            conn_spec(call.rule, call.k_or_n, allow_autapses=int(getattr(call, "allow_autapses", 1)),
+                      p=float(getattr(call, "p", 0.0))),
             syn_spec(call.weight, call.delay))
 
 

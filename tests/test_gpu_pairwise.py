@@ -1,0 +1,87 @@
+"""GPU parity of pairwise_bernoulli (the Discussion names it as missing;
+counted on the device, allocated exactly, then written), through the C ABI,
+against the CPU oracle: creation order and calibrated arrays element by
+element; p = 0 and p = 1; rows longer than one 4,096-pair unit; self-pairs
+prohibited; mixed with other rules; and the error paths."""
+from types import SimpleNamespace
+
+import numpy as np
+import pytest
+
+import oracle
+from parity import check_calibrated, check_creation_order
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2306_09855_amd import ng  # noqa: E402
+from paper_2306_09855_amd.network import Network  # noqa: E402
+
+N_NODES = 12_000
+
+
+def _pb(p, src, tgt, allow=1, w=("normal", 0.5, 0.05), d=("uniform_int", 1, 25)):
+    c = SimpleNamespace(rule="pairwise_bernoulli", src=src, tgt=tgt, k_or_n=0, weight=w, delay=d,
+                        allow_autapses=allow, p=p)
+    return c
+
+
+def _other(rule, src, tgt, k, w=("normal", -0.5, 0.05), d=("uniform", 0.1, 3.0)):
+    return SimpleNamespace(rule=rule, src=src, tgt=tgt, k_or_n=k, weight=w, delay=d)
+
+
+def _counts(calls, seed):
+    return [oracle.count_pairwise(seed, cid, c) for cid, c in enumerate(calls)]
+
+
+def _check(calls, seed=77):
+    ns = _counts(calls, seed)
+    for c, n in zip(calls, ns):
+        c.n_syn = (lambda n: lambda: n)(n)
+    ref = oracle.build_network(seed, 0.1, N_NODES, calls)
+    with Network(seed, 0.1, 1 << 16, 512 << 20) as net:
+        net.create(N_NODES)
+        got_n = [net.connect(c)[2] for c in calls]
+        created = net.fetch()
+        net.calibrate()
+        out = net.fetch()
+        gp, gs = net.group_index()
+    assert got_n == ns
+    check_creation_order(created, ref, calls)
+    check_calibrated(out, gp, gs, ref, calls)
+
+
+CASES = {
+    "p0": [_pb(0.0, (0, 100), (100, 100))],
+    "p1_is_all_to_all": [_pb(1.0, (0, 40), (30, 70))],
+    "long_rows": [_pb(0.05, (0, 30), (1000, 10_000))],  # 3 units per row, the last partial
+    "no_autapses": [_pb(0.3, (0, 300), (200, 300), allow=0)],
+    "ms_delays_uniform_weights": [_pb(0.2, (500, 200), (0, 5000), w=("uniform", -1.0, 1.0),
+                                      d=("uniform", 0.05, 2.5))],
+    "mixed": [_other("fixed_total_number", (0, 400), (400, 400), 30_000), _pb(0.1, (400, 400), (0, 700)),
+              _other("fixed_indegree", (0, 100), (100, 50), 17)],
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_pairwise_matches_oracle(name):
+    _check(CASES[name])
+
+
+def test_pairwise_errors_change_nothing():
+    with Network(1, 0.1, 1 << 16, 4 << 20) as net:  # an arena too small for 1e6 connections
+        net.create(2000)
+        for bad, status in [(_pb(1.5, (0, 10), (0, 10)), ng.NG_ERR_INVALID_ARG),
+                            (_pb(0.5, (0, 10), (1995, 10)), ng.NG_ERR_INVALID_ARG),
+                            (_pb(1.0, (0, 1000), (1000, 1000)), ng.NG_ERR_OOM)]:
+            with pytest.raises(ng.NGError) as e:
+                net.connect(bad)
+            assert e.value.status == status
+        assert net.view().n_conns == 0
+        assert net.connect(_pb(0.5, (0, 10), (0, 10)))[0] == 0  # first call id still free
+        with pytest.raises(ng.NGError) as e:
+            net.connect_batch([_pb(0.5, (0, 10), (0, 10))])
+        assert e.value.status == ng.NG_ERR_UNSUPPORTED
