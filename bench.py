@@ -425,6 +425,53 @@ def no_autapse_bench(wl, block_size: int, steps: int, warmup: int, radix_bits: i
             "generate_ms_per_step": round(gen[1] / steps, 4)}
 
 
+def pairwise_bench(wl, block_size: int, steps: int, warmup: int, radix_bits: int, sort_ranges: int,
+                   n_tgt: int = 50_000, p: float = 0.0777) -> dict:
+    """One pairwise_bernoulli call from all nodes of the workload to the
+    first n_tgt of them (~3e8 connections), calibrated: counting pass,
+    exact reservation, writing pass, sort and index."""
+    import torch
+    from paper_2306_09855_amd import ng
+    from paper_2306_09855_amd.network import Network, arena_bytes_for
+
+    n_exp = int(wl.n_nodes * n_tgt * p)
+    arena = arena_bytes_for(int(n_exp * 1.01), wl.n_nodes, wl.max_delay, block_size, 9) + (64 << 20)
+    side = torch.cuda.Stream()
+    net = Network(wl.seed, wl.h, block_size, arena, stream=side.cuda_stream)
+    net.tune(radix_bits, sort_ranges)
+    ctx = net.ctx
+    conn = ng.conn_spec("pairwise_bernoulli", 0, p=p)
+    syn = ng.syn_spec(("normal", 0.5, 0.05), ("uniform_int", 1, 30))
+    n = 0
+
+    def step():
+        nonlocal n
+        ng.ng_reset(ctx)
+        ng.ng_create_nodes(ctx, wl.n_nodes)
+        n = ng.ng_connect(ctx, ng.ng_range(0, wl.n_nodes), ng.ng_range(0, n_tgt), conn, syn)[2]
+        ng.ng_calibrate(ctx)
+
+    for _ in range(warmup):
+        step()
+    ng.ng_sync(ctx)
+    ng.ng_enable_timing(ctx, True)
+    ng.ng_read_timing(ctx, reset=True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    ng.ng_sync(ctx)
+    t1 = time.perf_counter()
+    kernels = ng.ng_read_timing(ctx, reset=True)
+    ng.ng_enable_timing(ctx, False)
+    net.close()
+    ms = 1e3 * (t1 - t0) / steps
+    per = {k: round(v[1] / steps, 4) for k, v in kernels.items()}
+    pairs = wl.n_nodes * n_tgt
+    return {"pairs": pairs, "p": p, "connections": n, "ms_per_step": round(ms, 3),
+            "synapses_per_s": n / (ms / 1e3), "pairs_per_s_counting": pairs / (per.get("pb_count", 0) / 1e3)
+            if per.get("pb_count") else None, "kernels_ms_per_step": per}
+
+
 def delivery_bench(wl, block_size: int, rate_per_step: float = 1e-3, warm_steps: int = 100,
                    steps: int = 500) -> dict:
     """Spike buffers and delivery over the calibrated network: random spike
@@ -489,6 +536,8 @@ def main() -> int:
     ap.add_argument("--total", type=float, default=3.0e8)
     ap.add_argument("--no-autapses", type=int, default=1,
                     help="also time the build with allow_autapses = 0 on every call")
+    ap.add_argument("--pairwise", type=int, default=1,
+                    help="also time a ~3e8-connection pairwise_bernoulli build")
     ap.add_argument("--delivery", type=int, default=1,
                     help="also time spike delivery (Sec. 2.3) over the calibrated network")
     ap.add_argument("--arrays", type=int, default=1,
@@ -663,6 +712,11 @@ def main() -> int:
         na = no_autapse_bench(wl, args.block_size, max(1, min(args.steps, 3)), 1, args.radix_bits, args.sort_ranges)
         log(f"no autapses: {na['ms_per_step']} ms/step, generate {na['generate_ms_per_step']} ms")
         result["no_autapses"] = na
+        torch.cuda.empty_cache()
+    if args.pairwise and args.form == "plain" and wl.name == "microcircuit":
+        pb = pairwise_bench(wl, args.block_size, max(1, min(args.steps, 3)), 1, args.radix_bits, args.sort_ranges)
+        log(f"pairwise_bernoulli: {pb['ms_per_step']} ms/step, {pb['connections']} connections")
+        result["pairwise_bernoulli"] = pb
         torch.cuda.empty_cache()
     if args.delivery and args.form == "plain" and wl.name == "microcircuit":
         dl = delivery_bench(wl, args.block_size)
