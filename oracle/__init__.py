@@ -54,6 +54,7 @@ class _Call(ctypes.Structure):
         ("w_arr", ctypes.c_void_p), ("d_arr", ctypes.c_void_p),
         ("allow_autapses", ctypes.c_int32),
         ("p", ctypes.c_double),
+        ("allow_multapses", ctypes.c_int32),
     ]
 
 
@@ -133,7 +134,8 @@ def to_struct(call) -> _Call:
                KINDS[wk], float(wa), float(wb), KINDS[dk], float(da), float(db),
                arr("src_idx", np.uint32), arr("tgt_idx", np.uint32),
                arr("w_arr", np.float32), arr("d_arr", np.float32),
-               int(getattr(call, "allow_autapses", 1)), float(getattr(call, "p", 0.0)))
+               int(getattr(call, "allow_autapses", 1)), float(getattr(call, "p", 0.0)),
+               int(getattr(call, "allow_multapses", 1)))
     st._keep = keep
     return st
 

@@ -106,6 +106,55 @@ static uint64_t overlap(const ora_call* c) {
 
 static int no_self(const ora_call* c) { return !c->allow_autapses && !c->src_idx && !c->tgt_idx; }
 
+/* permutation of [0, m) for multapse-free draws: Feistel network, cycle walk */
+static uint64_t feistel(uint64_t seed, uint32_t cid, uint32_t u, int h, uint64_t x) {
+  const uint64_t mask = (h >= 64) ? ~0ull : ((1ull << h) - 1);
+  uint64_t l = x >> h, r = x & mask;
+  for (uint32_t round = 0; round < 4; round++) {
+    uint32_t ctr[4] = {(uint32_t)r, u, cid, 131072u + round}, key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)}, out[4];
+    ora_philox4x32_10(ctr, key, out);
+    const uint64_t f = (uint64_t)out[0] & mask;
+    const uint64_t nl = r, nr = l ^ f;
+    l = nl;
+    r = nr;
+  }
+  return (l << h) | r;
+}
+
+static uint64_t permute(uint64_t seed, uint32_t cid, uint32_t u, uint64_t m, uint64_t x) {
+  int bits = 2;
+  while (bits < 64 && (1ull << bits) < m) bits++;
+  if (bits & 1) bits++;
+  uint64_t y = feistel(seed, cid, u, bits / 2, x);
+  while (y >= m) y = feistel(seed, cid, u, bits / 2, y);
+  return y;
+}
+
+static int no_multi(const ora_call* c) { return !c->allow_multapses; }
+
+/* pair index k in all_to_all order (without self-pairs when prohibited) */
+static void a2a_pair(const ora_call* c, uint64_t k, uint64_t* s_off, uint64_t* t_off) {
+  if (!no_self(c)) {
+    *s_off = k / c->nt;
+    *t_off = k % c->nt;
+    return;
+  }
+  uint64_t rem = k, a = 0;
+  for (;; a++) {
+    const uint64_t s = c->s0 + a;
+    const int in_t = s >= c->t0 && s < (uint64_t)c->t0 + c->nt;
+    const uint64_t len = c->nt - (in_t ? 1 : 0);
+    if (rem < len) {
+      uint64_t t = rem;
+      if (in_t && c->t0 + t >= s) t++;
+      *s_off = a;
+      *t_off = t;
+      return;
+    }
+    rem -= len;
+  }
+}
+
 /* pairwise_bernoulli: is pair (a, b) a connection */
 static uint64_t pb_threshold(const ora_call* c) { return (uint64_t)floor(c->p * 4294967296.0); }
 static int pb_pair(uint64_t seed, uint32_t cid, const ora_call* c, uint64_t a, uint64_t b) {
@@ -116,7 +165,7 @@ static int pb_pair(uint64_t seed, uint32_t cid, const ora_call* c, uint64_t a, u
 int64_t ora_count(const ora_call* c) {
   if ((uint64_t)c->s0 + c->ns > 0xFFFFFFFFull || (uint64_t)c->t0 + c->nt > 0xFFFFFFFFull)
     return -1;
-  if (!c->allow_autapses && (c->src_idx || c->tgt_idx)) return -1;
+  if ((!c->allow_autapses || !c->allow_multapses) && (c->src_idx || c->tgt_idx)) return -1;
   const int ns_ = no_self(c);
   switch (c->rule) {
     case ORA_ONE_TO_ONE: /* N_new = N_sources = N_targets */
@@ -127,15 +176,18 @@ int64_t ora_count(const ora_call* c) {
       return (int64_t)c->ns * (int64_t)c->nt - (ns_ ? (int64_t)overlap(c) : 0);
     case ORA_FIXED_OUTDEGREE: /* N_new = N_sources * K, random targets need N_t > 0 */
       if (c->nt == 0 && c->ns > 0 && c->k_or_n > 0) return -1;
+      if (no_multi(c) && c->ns && c->k_or_n > (uint64_t)c->nt - (ns_ && overlap(c) ? 1 : 0)) return -1;
       if (ns_ && c->nt == 1 && overlap(c) && c->k_or_n > 0) return -1;  /* a source with no other target */
       return (int64_t)c->ns * (int64_t)c->k_or_n;
     case ORA_FIXED_INDEGREE: /* N_new = N_targets * K, random sources need N_s > 0 */
       if (c->ns == 0 && c->nt > 0 && c->k_or_n > 0) return -1;
+      if (no_multi(c) && c->nt && c->k_or_n > (uint64_t)c->ns - (ns_ && overlap(c) ? 1 : 0)) return -1;
       if (ns_ && c->ns == 1 && overlap(c) && c->k_or_n > 0) return -1;  /* a target with no other source */
       return (int64_t)c->nt * (int64_t)c->k_or_n;
     case ORA_FIXED_TOTAL_NUMBER: /* N_new given */
       if ((c->ns == 0 || c->nt == 0) && c->k_or_n > 0) return -1;
       if (ns_ && (uint64_t)c->ns * c->nt == overlap(c) && c->k_or_n > 0) return -1;  /* only autapses */
+      if (no_multi(c) && c->k_or_n > (uint64_t)c->ns * c->nt - (ns_ ? overlap(c) : 0)) return -1;
       return (int64_t)c->k_or_n;
     default:
       return -1;
@@ -156,6 +208,9 @@ static int delay_is_random(const ora_call* c) { return c->d_arr == NULL && c->d_
 
 int ora_words_per_synapse(const ora_call* c) {
   int draws = 0;
+  if (no_multi(c) && (c->rule == ORA_FIXED_INDEGREE || c->rule == ORA_FIXED_OUTDEGREE ||
+                      c->rule == ORA_FIXED_TOTAL_NUMBER))
+    return delay_is_random(c) ? 1 : 0; /* the permutation draws no stream-0 word */
   if (c->rule == ORA_FIXED_INDEGREE || c->rule == ORA_FIXED_TOTAL_NUMBER) draws++; /* source */
   if (c->rule == ORA_FIXED_OUTDEGREE || c->rule == ORA_FIXED_TOTAL_NUMBER) draws++; /* target */
   if (delay_is_random(c)) draws++;
@@ -183,6 +238,33 @@ int ora_synapse(uint64_t seed, float h, uint32_t cid, const ora_call* c, uint64_
   uint64_t q = i * w0; /* first stream-0 word of synapse i */
   uint64_t k = c->k_or_n;
   uint64_t s_off = 0, t_off = 0;
+  if (no_multi(c) && c->rule == ORA_FIXED_INDEGREE) {
+    t_off = i / k;
+    const uint64_t t = c->t0 + t_off;
+    const int in_s = no_self(c) && t >= c->s0 && t < (uint64_t)c->s0 + c->ns;
+    s_off = permute(seed, cid, (uint32_t)t, c->ns - (in_s ? 1 : 0), i % k);
+    if (in_s && s_off >= t - c->s0) s_off++;
+    *src = c->s0 + (uint32_t)s_off;
+    *tgt = (uint32_t)t;
+    return weight_and_delay(seed, h, cid, c, i, 0, q, w, delay);
+  }
+  if (no_multi(c) && c->rule == ORA_FIXED_OUTDEGREE) {
+    s_off = i / k;
+    const uint64_t s = c->s0 + s_off;
+    const int in_t = no_self(c) && s >= c->t0 && s < (uint64_t)c->t0 + c->nt;
+    t_off = permute(seed, cid, (uint32_t)s, c->nt - (in_t ? 1 : 0), i % k);
+    if (in_t && t_off >= s - c->t0) t_off++;
+    *src = (uint32_t)s;
+    *tgt = c->t0 + (uint32_t)t_off;
+    return weight_and_delay(seed, h, cid, c, i, 0, q, w, delay);
+  }
+  if (no_multi(c) && c->rule == ORA_FIXED_TOTAL_NUMBER) {
+    const uint64_t pairs = (uint64_t)c->ns * c->nt - (no_self(c) ? overlap(c) : 0);
+    a2a_pair(c, permute(seed, cid, 0, pairs, i), &s_off, &t_off);
+    *src = c->s0 + (uint32_t)s_off;
+    *tgt = c->t0 + (uint32_t)t_off;
+    return weight_and_delay(seed, h, cid, c, i, 0, q, w, delay);
+  }
   switch (c->rule) {
     case ORA_ONE_TO_ONE: /* Eqs. (4)-(5) */
       s_off = i;

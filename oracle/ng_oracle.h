@@ -85,6 +85,18 @@ typedef struct {
    * connections are numbered in that order; connection j draws its delay
    * from word j of stream 2 and its weight from words 2j, 2j+1 of stream 1. */
   double p;
+  /* 0: no two connections join the same pair (sampling without
+   * replacement; Discussion: future work).  Defined with a pseudorandom
+   * permutation pi_u of [0, M): a 4-round Feistel network on the smallest
+   * even number of bits 2h >= 2 with 2^(2h) >= M, round r mapping (L, R) to
+   * (R, L ^ (word 0 of Philox(ctr = (R, u, c, 131072 + r)) mod 2^h)), walked
+   * until the value falls below M.  fixed_indegree: target t gets the sources
+   * at positions pi_t(0..K-1) of its candidates (the source range, or the
+   * range without t, skip-self as above); fixed_outdegree likewise;
+   * fixed_total_number: synapse i is the pair of index pi_0(i) in the
+   * all_to_all order (without the self-pairs when those are prohibited).
+   * The index draws use no stream-0 word: synapse i's delay is word i. */
+  int32_t allow_multapses;
 } ora_call;
 
 /* Philox4x32-10 block function */
