@@ -75,7 +75,19 @@ typedef struct {
  *   fixed_total_number  a drawn pair with s == t is redrawn from words 2i,
  *                    2i+1 of stream 65536 + a for attempt a = 1, 2, ...; the
  *                    64th attempt draws the target among the others.
- * Calls that could only make autapses fail with NG_ERR_INVALID_ARG. */
+ * Calls that could only make autapses fail with NG_ERR_INVALID_ARG.
+ * With allow_multapses = 0 (also named as future work) no two connections
+ * join the same pair.  one_to_one and all_to_all never repeat a pair.
+ * fixed_indegree: target t takes the sources at positions pi_t(0..K-1) of
+ * its candidates (the source range, without t when autapses are
+ * prohibited), pi_t a permutation of [0, M) keyed by the call and t: a
+ * 4-round Feistel network on the smallest even width 2h >= 2 with
+ * 2^(2h) >= M, round r mapping (L, R) to (R, L ^ (word 0 of
+ * Philox(ctr = (R, t, call, 131072 + r)) mod 2^h)), reapplied until the value
+ * is below M.  fixed_outdegree likewise with sources and targets exchanged.
+ * fixed_total_number: synapse i is the pair of index pi_0(i) in the
+ * all_to_all order.  These draws use no stream-0 word (synapse i's delay is
+ * word i).  K or N above the distinct candidates is NG_ERR_INVALID_ARG. */
 typedef enum {
   NG_ONE_TO_ONE = 0,         /* Eqs. (4)-(5): N_new = N_s = N_t         */
   NG_ALL_TO_ALL = 1,         /* Eqs. (6)-(7): N_new = N_s * N_t         */
@@ -88,7 +100,7 @@ typedef enum {
 typedef struct {
   int32_t rule;            /* ng_rule */
   int32_t allow_autapses;  /* 0: no connection from a node to itself (below) */
-  int32_t allow_multapses; /* must be 1 (the paper's rules allow multapses) */
+  int32_t allow_multapses; /* 0: no two connections join the same pair (below) */
   int32_t reserved;
   uint64_t k_or_n;         /* K for in/out-degree, N for fixed_total_number */
   double p;                /* pairwise_bernoulli: connection probability in [0, 1] */

@@ -16,6 +16,12 @@ enum : uint32_t { W_CONST = 0, W_NORMAL = 1, W_UNIFORM = 3 };
 enum : uint32_t { D_CONST = 0, D_UNIFORM_INT = 2, D_UNIFORM_MS = 3 };
 
 // One planned Connect call, as the generation kernels consume it.
+// Generation rule codes beyond ng_rule's: the multapse-free draws (a keyed
+// permutation instead of independent draws; no stream-0 index words).
+constexpr uint32_t kRuleIndegDistinct = 8;
+constexpr uint32_t kRuleOutdegDistinct = 9;
+constexpr uint32_t kRuleTotalDistinct = 10;
+
 struct GenDesc {
   uint64_t pos0;     // creation position of synapse 0 (global connection index)
   uint32_t n_new;    // synapses in this call (< 2^32)
@@ -34,6 +40,7 @@ struct GenDesc {
   uint32_t no_self;  // no connection from a node to itself, and the ranges overlap
   uint32_t a_lo, a_hi;  // all_to_all without autapses: source positions whose node is a target
   uint64_t p_thr;       // pairwise_bernoulli: a pair connects when its word is below this
+  uint64_t n_pairs;     // fixed_total_number without multapses: candidate pairs
   uint64_t group0;   // batched form: index of this call's first 4-synapse group
   char* const* blocks;        // batched form: block table of the call's context
   const uint32_t* key;        // batched form: Philox key of the call's context

@@ -53,10 +53,41 @@ __device__ __forceinline__ uint32_t rand_below(uint32_t x, uint32_t n) { return 
 
 constexpr float kInv2p24 = 5.9604644775390625e-08f;  // 2^-24
 
-enum { R_ONE_TO_ONE = 0, R_ALL_TO_ALL = 1, R_INDEG = 2, R_OUTDEG = 3, R_TOTAL = 4 };
+enum { R_ONE_TO_ONE = 0, R_ALL_TO_ALL = 1, R_INDEG = 2, R_OUTDEG = 3, R_TOTAL = 4,
+       R_INDEG_D = kRuleIndegDistinct, R_OUTDEG_D = kRuleOutdegDistinct, R_TOTAL_D = kRuleTotalDistinct };
+
+// Distinct draws (no multapses): x -> pi(x), a permutation of [0, m) keyed by
+// (call, node u): a 4-round Feistel network on 2h bits (the smallest even
+// width with 2^(2h) >= m, at least 2), whose round r maps (L, R) to
+// (R, L ^ (word 0 of Philox(R, u, call, 131072 + r) mod 2^h)), applied again
+// until the value falls below m (the cycle through x returns below m).
+__device__ __forceinline__ uint64_t feistel4(uint64_t x, int h, uint32_t u, uint32_t cid, uint32_t key0,
+                                             uint32_t key1) {
+  const uint64_t mask = (1ull << h) - 1;
+  uint64_t l = x >> h, r = x & mask;
+#pragma unroll
+  for (uint32_t round = 0; round < 4; ++round) {
+    uint32_t out[4];
+    philox10((uint32_t)r, u, cid, 131072u + round, key0, key1, out);
+    const uint64_t f = (uint64_t)out[0] & mask;
+    const uint64_t nl = r;
+    r = l ^ f;
+    l = nl;
+  }
+  return (l << h) | r;
+}
+
+__device__ __forceinline__ uint64_t permute_below(uint64_t x, uint64_t m, uint32_t u, uint32_t cid, uint32_t key0,
+                                                  uint32_t key1) {
+  int bits = m <= 4 ? 2 : 64 - __clzll((long long)(m - 1));
+  bits += bits & 1;
+  uint64_t y = feistel4(x, bits / 2, u, cid, key0, key1);
+  while (y >= m) y = feistel4(y, bits / 2, u, cid, key0, key1);
+  return y;
+}
 
 template <int RULE>
-struct RuleDraws {
+struct RuleDraws {  // stream-0 index words per synapse (the distinct draws use none)
   static constexpr int value = RULE == R_TOTAL ? 2 : (RULE == R_INDEG || RULE == R_OUTDEG) ? 1 : 0;
 };
 
@@ -102,7 +133,53 @@ __device__ __forceinline__ void gen_quad(const GenDesc& d, uint32_t g, uint32_t 
     philox_block((uint64_t)g * W0 + m, d.cid, 0u, key0, key1, &x[4 * m]);
 
   // source / target indices, Eqs. (4)-(13)
-  if (d.no_self && RULE != R_ONE_TO_ONE) {
+  if constexpr (RULE == R_INDEG_D || RULE == R_OUTDEG_D || RULE == R_TOTAL_D) {
+    // no multapses: positions from a permutation keyed by the fixed node
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const uint32_t i = i0 + r;
+      if constexpr (RULE == R_INDEG_D) {
+        const uint32_t t = d.t0 + i / d.k;
+        const bool in_s = d.no_self && t - d.s0 < d.ns;
+        uint32_t a = (uint32_t)permute_below(i % d.k, d.ns - (in_s ? 1u : 0u), t, d.cid, key0, key1);
+        if (in_s && a >= t - d.s0) ++a;
+        q.s[r] = d.s0 + a;
+        q.t[r] = t;
+      } else if constexpr (RULE == R_OUTDEG_D) {
+        const uint32_t s = d.s0 + i / d.k;
+        const bool in_t = d.no_self && s - d.t0 < d.nt;
+        uint32_t b = (uint32_t)permute_below(i % d.k, d.nt - (in_t ? 1u : 0u), s, d.cid, key0, key1);
+        if (in_t && b >= s - d.t0) ++b;
+        q.s[r] = s;
+        q.t[r] = d.t0 + b;
+      } else {
+        // pair index in all_to_all order (without the self-pairs when prohibited)
+        const uint64_t k = permute_below(i, d.n_pairs, 0u, d.cid, key0, key1);
+        uint64_t a, b;
+        if (!d.no_self) {
+          a = k / d.nt;
+          b = k - a * d.nt;
+        } else {
+          const uint64_t p1 = (uint64_t)d.a_lo * d.nt;
+          const uint64_t p2 = p1 + (uint64_t)(d.a_hi - d.a_lo) * (d.nt - 1);
+          if (k < p1) {
+            a = k / d.nt;
+            b = k - a * d.nt;
+          } else if (k < p2) {
+            const uint64_t l2 = d.nt > 1 ? d.nt - 1 : 1;
+            a = d.a_lo + (k - p1) / l2;
+            b = (k - p1) - (a - d.a_lo) * l2;
+            if (d.t0 + b >= d.s0 + a) ++b;
+          } else {
+            a = d.a_hi + (k - p2) / d.nt;
+            b = (k - p2) - (a - d.a_hi) * d.nt;
+          }
+        }
+        q.s[r] = d.s0 + (uint32_t)a;
+        q.t[r] = d.t0 + (uint32_t)b;
+      }
+    }
+  } else if (d.no_self && RULE != R_ONE_TO_ONE) {
     // no connection from a node to itself (the ranges overlap)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -381,6 +458,9 @@ __device__ __forceinline__ void gen_any(const GenDesc& d, uint32_t g, uint32_t k
     case R_ALL_TO_ALL: gen_quad<R_ALL_TO_ALL, DRAND>(d, g, key0, key1, q); break;
     case R_INDEG: gen_quad<R_INDEG, DRAND>(d, g, key0, key1, q); break;
     case R_OUTDEG: gen_quad<R_OUTDEG, DRAND>(d, g, key0, key1, q); break;
+    case R_INDEG_D: gen_quad<R_INDEG_D, DRAND>(d, g, key0, key1, q); break;
+    case R_OUTDEG_D: gen_quad<R_OUTDEG_D, DRAND>(d, g, key0, key1, q); break;
+    case R_TOTAL_D: gen_quad<R_TOTAL_D, DRAND>(d, g, key0, key1, q); break;
     default: gen_quad<R_TOTAL, DRAND>(d, g, key0, key1, q); break;
   }
 }
@@ -1787,6 +1867,9 @@ hipError_t launch_generate(const GenDesc& d, const uint32_t* d_key, char* const*
     case R_INDEG: gen_launch<R_INDEG>(d, d_key, d_blocks, log2B, grid, s); break;
     case R_OUTDEG: gen_launch<R_OUTDEG>(d, d_key, d_blocks, log2B, grid, s); break;
     case R_TOTAL: gen_launch<R_TOTAL>(d, d_key, d_blocks, log2B, grid, s); break;
+    case R_INDEG_D: gen_launch<R_INDEG_D>(d, d_key, d_blocks, log2B, grid, s); break;
+    case R_OUTDEG_D: gen_launch<R_OUTDEG_D>(d, d_key, d_blocks, log2B, grid, s); break;
+    case R_TOTAL_D: gen_launch<R_TOTAL_D>(d, d_key, d_blocks, log2B, grid, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -57,8 +57,6 @@ int plan_call(uint32_t n_nodes, ng_range src, ng_range tgt, const ng_conn_spec* 
   if ((uint64_t)src.first + src.n > n_nodes || (uint64_t)tgt.first + tgt.n > n_nodes)
     return fail(NG_ERR_INVALID_ARG, "node range [%u,+%u) or [%u,+%u) exceeds the %u created nodes",
                 src.first, src.n, tgt.first, tgt.n, n_nodes);
-  if (!conn->allow_multapses)
-    return fail(NG_ERR_UNSUPPORTED, "allow_multapses = 0 is not implemented (the rules allow multapses)");
   const uint64_t ns = src.n, nt = tgt.n, k = conn->k_or_n;
   // allow_autapses = 0 matters only where the ranges share nodes
   const uint64_t ov_lo = std::max<uint64_t>(src.first, tgt.first);
@@ -79,6 +77,8 @@ int plan_call(uint32_t n_nodes, ng_range src, ng_range tgt, const ng_conn_spec* 
       if (n && ns == 0) return fail(NG_ERR_INVALID_ARG, "fixed_indegree needs a non-empty source range");
       if (n && no_self && ns == 1)
         return fail(NG_ERR_INVALID_ARG, "fixed_indegree without autapses: a target has no other source");
+      if (n && !conn->allow_multapses && k > ns - (no_self ? 1 : 0))
+        return fail(NG_ERR_INVALID_ARG, "fixed_indegree without multapses: K exceeds the distinct sources");
       break;
     case NG_FIXED_OUTDEGREE:
       if (k > 0xFFFFFFFFull) return fail(NG_ERR_TOO_LARGE, "K too large");
@@ -86,6 +86,8 @@ int plan_call(uint32_t n_nodes, ng_range src, ng_range tgt, const ng_conn_spec* 
       if (n && nt == 0) return fail(NG_ERR_INVALID_ARG, "fixed_outdegree needs a non-empty target range");
       if (n && no_self && nt == 1)
         return fail(NG_ERR_INVALID_ARG, "fixed_outdegree without autapses: a source has no other target");
+      if (n && !conn->allow_multapses && k > nt - (no_self ? 1 : 0))
+        return fail(NG_ERR_INVALID_ARG, "fixed_outdegree without multapses: K exceeds the distinct targets");
       break;
     case NG_FIXED_TOTAL_NUMBER:
       n = k;
@@ -93,6 +95,8 @@ int plan_call(uint32_t n_nodes, ng_range src, ng_range tgt, const ng_conn_spec* 
         return fail(NG_ERR_INVALID_ARG, "fixed_total_number needs non-empty ranges");
       if (n && no_self && ns * nt == ov)
         return fail(NG_ERR_INVALID_ARG, "fixed_total_number without autapses: every pair is an autapse");
+      if (n && !conn->allow_multapses && n > ns * nt - (no_self ? ov : 0))
+        return fail(NG_ERR_INVALID_ARG, "fixed_total_number without multapses: N exceeds the distinct pairs");
       break;
     case NG_PAIRWISE_BERNOULLI:
       return fail(NG_ERR_UNSUPPORTED, "pairwise_bernoulli is taken only by ng_connect (its count needs a device pass)");
@@ -113,6 +117,14 @@ int plan_call(uint32_t n_nodes, ng_range src, ng_range tgt, const ng_conn_spec* 
     d.no_self = 1;
     d.a_lo = (uint32_t)(ov_lo - src.first);  // source positions whose node is also a target
     d.a_hi = (uint32_t)(ov_hi - src.first);
+  }
+  if (!conn->allow_multapses && n) {  // distinct draws: a keyed permutation per call or node
+    if (conn->rule == NG_FIXED_INDEGREE) d.rule = ng::kRuleIndegDistinct;
+    if (conn->rule == NG_FIXED_OUTDEGREE) d.rule = ng::kRuleOutdegDistinct;
+    if (conn->rule == NG_FIXED_TOTAL_NUMBER) {
+      d.rule = ng::kRuleTotalDistinct;
+      d.n_pairs = ns * nt - (no_self ? ov : 0);
+    }
   }
 
   const ng_param& w = syn->weight;
@@ -1289,8 +1301,8 @@ int ng_connect_groups(ng_ctx* c, ng_group src, ng_group tgt, const ng_conn_spec*
   if (!conn || !syn) return fail(NG_ERR_INVALID_ARG, "null connection or synapse spec");
   if ((src.idx && src.first) || (tgt.idx && tgt.first))
     return fail(NG_ERR_INVALID_ARG, "a group given by an index array needs first = 0");
-  if ((src.idx || tgt.idx) && !conn->allow_autapses)
-    return fail(NG_ERR_UNSUPPORTED, "allow_autapses = 0 is not implemented for index arrays");
+  if ((src.idx || tgt.idx) && (!conn->allow_autapses || !conn->allow_multapses))
+    return fail(NG_ERR_UNSUPPORTED, "allow_autapses = 0 or allow_multapses = 0 is not implemented for index arrays");
   // ranges of the groups without arrays are node ranges
   if ((!src.idx && (uint64_t)src.first + src.n > c->n_nodes) || (!tgt.idx && (uint64_t)tgt.first + tgt.n > c->n_nodes))
     return fail(NG_ERR_INVALID_ARG, "node range exceeds the %u created nodes", c->n_nodes);

@@ -207,7 +207,7 @@ def call_args(call):
     """(src range, tgt range, conn spec, syn spec) of a workloads.Call."""
     return (ng_range(*call.src), ng_range(*call.tgt),
             conn_spec(call.rule, call.k_or_n, allow_autapses=int(getattr(call, "allow_autapses", 1)),
-                      p=float(getattr(call, "p", 0.0))),
+                      allow_multapses=int(getattr(call, "allow_multapses", 1)), p=float(getattr(call, "p", 0.0))),
             syn_spec(call.weight, call.delay))
 
 

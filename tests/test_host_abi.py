@@ -119,10 +119,17 @@ def test_autapse_multapse_flags(L):
         with pytest.raises(ng.NGError) as e:  # only autapses possible
             ng.ng_plan_count(10, ng.ng_range(*src), ng.ng_range(*tgt), no_self(rule, 3), syn, 0.1)
         assert e.value.status == ng.NG_ERR_INVALID_ARG
-    with pytest.raises(ng.NGError) as e:
-        ng.ng_plan_count(10, ng.ng_range(0, 5), ng.ng_range(5, 5),
-                         ng.conn_spec("fixed_indegree", 3, allow_multapses=0), syn, 0.1)
-    assert e.value.status == ng.NG_ERR_UNSUPPORTED
+    # no multapses: distinct draws, at most as many as the candidates
+    assert ng.ng_plan_count(10, ng.ng_range(0, 5), ng.ng_range(5, 5),
+                            ng.conn_spec("fixed_indegree", 3, allow_multapses=0), syn, 0.1) == 15
+    for rule, k, src, tgt in [("fixed_indegree", 6, (0, 5), (5, 5)), ("fixed_outdegree", 6, (0, 5), (5, 5)),
+                              ("fixed_total_number", 26, (0, 5), (5, 5)),
+                              ("fixed_indegree", 5, (0, 5), (0, 5))]:  # without autapses: 4 candidates
+        with pytest.raises(ng.NGError) as e:
+            ng.ng_plan_count(10, ng.ng_range(*src), ng.ng_range(*tgt),
+                             ng.conn_spec(rule, k, allow_autapses=0 if src == tgt else 1, allow_multapses=0),
+                             syn, 0.1)
+        assert e.value.status == ng.NG_ERR_INVALID_ARG, rule
 
 
 def test_arena_for_sizes():
