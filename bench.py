@@ -378,9 +378,11 @@ def arrays_bench(wl, block_size: int, steps: int, warmup: int, radix_bits: int, 
             "apply_bytes_per_connection": 26, "kernels": per}
 
 
-def no_autapse_bench(wl, block_size: int, steps: int, warmup: int, radix_bits: int, sort_ranges: int) -> dict:
-    """The same build with allow_autapses = 0 on every call: the calls whose
-    source and target populations are the same draw without self-pairs."""
+def no_autapse_bench(wl, block_size: int, steps: int, warmup: int, radix_bits: int, sort_ranges: int,
+                     multapses: int = 1) -> dict:
+    """The same build with allow_autapses = 0 on every call (the calls whose
+    source and target populations are the same draw without self-pairs);
+    with multapses = 0 also without repeated pairs (keyed permutations)."""
     import types
     import torch
     from paper_2306_09855_amd import ng
@@ -392,7 +394,8 @@ def no_autapse_bench(wl, block_size: int, steps: int, warmup: int, radix_bits: i
     net.tune(radix_bits, sort_ranges)
     ctx = net.ctx
     calls = [ng.call_args(types.SimpleNamespace(rule=c.rule, src=c.src, tgt=c.tgt, k_or_n=c.k_or_n,
-                                                weight=c.weight, delay=c.delay, allow_autapses=0))
+                                                weight=c.weight, delay=c.delay, allow_autapses=0,
+                                                allow_multapses=multapses))
              for c in wl.calls]
     overlapping = sum(1 for c in wl.calls if c.src[0] < c.tgt[0] + c.tgt[1] and c.tgt[0] < c.src[0] + c.src[1])
 
@@ -712,6 +715,10 @@ def main() -> int:
         na = no_autapse_bench(wl, args.block_size, max(1, min(args.steps, 3)), 1, args.radix_bits, args.sort_ranges)
         log(f"no autapses: {na['ms_per_step']} ms/step, generate {na['generate_ms_per_step']} ms")
         result["no_autapses"] = na
+        nm = no_autapse_bench(wl, args.block_size, max(1, min(args.steps, 3)), 1, args.radix_bits, args.sort_ranges,
+                              multapses=0)
+        log(f"no autapses, no multapses: {nm['ms_per_step']} ms/step, generate {nm['generate_ms_per_step']} ms")
+        result["no_autapses_no_multapses"] = nm
         torch.cuda.empty_cache()
     if args.pairwise and args.form == "plain" and wl.name == "microcircuit":
         pb = pairwise_bench(wl, args.block_size, max(1, min(args.steps, 3)), 1, args.radix_bits, args.sort_ranges)
