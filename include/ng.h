@@ -291,7 +291,8 @@ int ng_set_tuning(ng_ctx* ctx, int radix_bits, uint32_t sort_ranges);
  * in one step, are dropped; the next ng_sync returns NG_ERR_INVALID_ARG
  * once for them.  The buffers hold 20 bytes per node and queue slot, 12 per
  * node and 2 per group, and are released with the group index (a new
- * calibration, ng_reset).  NG_ERR_STATE before calibration / init. */
+ * calibration, ng_reset).  NG_ERR_STATE before calibration / init and
+ * under graph capture (every step numbers the spikes it takes in). */
 int ng_spikes_init(ng_ctx* ctx);
 int ng_spikes_step(ng_ctx* ctx, const uint32_t* nodes, const uint32_t* mult, uint32_t n, float* input);
 

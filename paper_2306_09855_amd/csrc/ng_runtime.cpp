@@ -1477,6 +1477,7 @@ int ng_spikes_init(ng_ctx* c) {
 
 int ng_spikes_step(ng_ctx* c, const uint32_t* nodes, const uint32_t* mult, uint32_t n, float* input) {
   if (int rc = enter(c)) return rc;
+  if (int rc = not_capturing(c)) return rc;  // each step stamps the emitting nodes with its own number
   if (!c->calibrated || !c->d_spikes) return fail(NG_ERR_STATE, "ng_spikes_init first (after calibration)");
   if ((n && !nodes) || !input) return fail(NG_ERR_INVALID_ARG, "null spike or input array");
   // stamps tell a node's second spike in one step apart; 0xFFFFFFFF marks "never"
