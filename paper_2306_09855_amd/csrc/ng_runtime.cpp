@@ -732,7 +732,7 @@ int calibrate_copass(ng_ctx* c) {
       start[i] = (uint32_t)((uint64_t)i * B);
       len[i] = block_len(i);
     }
-    for (uint32_t b = 0; b < k; ++b) {
+    for (uint32_t b = 0; b < (k > 1 ? k : 0); ++b) {  // one block: sorted above
       const uint32_t first = (uint32_t)((uint64_t)b * B), m = block_len(b);
       const uint64_t remaining = N - first;
       if (m < remaining) {
@@ -792,7 +792,11 @@ int calibrate_copass(ng_ctx* c) {
         const uint64_t cs = ce > lo_end + A ? ce - A : lo_end;
         const uint32_t off = (uint32_t)lists.size();
         uint32_t pre = 0;
-        for (const Move& mv : moves) {
+        // the moves are disjoint and ascending: those meeting [cs, ce) are a contiguous run
+        const auto first_mv = std::partition_point(moves.begin(), moves.end(),
+                                                   [&](const Move& mv) { return (uint64_t)mv.dst + mv.len <= cs; });
+        for (auto it = first_mv; it != moves.end() && it->dst < ce; ++it) {
+          const Move& mv = *it;
           const uint64_t a = std::max<uint64_t>(mv.dst, cs), z = std::min<uint64_t>((uint64_t)mv.dst + mv.len, ce);
           if (a >= z) continue;
           lists.push_back(ng::CopySeg{(uint32_t)(mv.src + (a - mv.dst)), (uint32_t)(a - cs), (uint32_t)(z - a), pre});
@@ -806,7 +810,7 @@ int calibrate_copass(ng_ctx* c) {
         if (npiece) chunks.push_back(Chunk{off, npiece, pre});
         ce = cs;
       }
-      if (lists.size() > seg_cap) return fail(NG_ERR_STATE, "COPASS copy list overflow");
+      if (lists.size() > seg_cap) return dev_fail(c, hipErrorUnknown, "COPASS copy list overflow");
       if (!lists.empty())
         if (int rc = stage_upload(c, d_lists, lists.data(), sizeof(ng::CopySeg) * lists.size())) return rc;
       NG_LAUNCH_N(c, "copass_copy", m,
