@@ -21,14 +21,19 @@ constexpr uint32_t kPhiloxMul1 = 0xCD9E8D57u;
 constexpr uint32_t kWeyl0 = 0x9E3779B9u;
 constexpr uint32_t kWeyl1 = 0xBB67AE85u;
 
+// a ^ b ^ c in one gfx950 three-input bit operation (truth table 0x96)
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ void philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                          uint32_t k0, uint32_t k1, uint32_t* out) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     const uint64_t a = (uint64_t)c0 * kPhiloxMul0;
     const uint64_t b = (uint64_t)c2 * kPhiloxMul1;
-    const uint32_t n0 = (uint32_t)(b >> 32) ^ c1 ^ k0;
-    const uint32_t n2 = (uint32_t)(a >> 32) ^ c3 ^ k1;
+    const uint32_t n0 = xor3((uint32_t)(b >> 32), c1, k0);
+    const uint32_t n2 = xor3((uint32_t)(a >> 32), c3, k1);
     c1 = (uint32_t)b;
     c3 = (uint32_t)a;
     c0 = n0;
