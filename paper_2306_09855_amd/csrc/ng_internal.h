@@ -130,12 +130,15 @@ hipError_t launch_set_entries(const TabEntry* d_entries, uint32_t n, hipStream_t
 // ---------------------------------------------------------------------------
 // pairwise_bernoulli: pairs (rows of sources, targets ascending) in units of
 // kPbUnit consecutive targets of one row.  count: counts[u] = connections of
-// unit u.  write: the connections of unit u from creation position
-// d.pos0 + offsets[u] on, in pair order.
+// unit u, and, when bits is not null, the decisions (16 per thread, one u16
+// per 16 pairs: kPbUnit / 8 bytes per unit).  write: the connections of unit
+// u from creation position d.pos0 + offsets[u] on, in pair order, from the
+// stored decisions when bits is not null, else evaluated again.
 constexpr uint32_t kPbUnit = 4096;
-hipError_t launch_pb_count(const GenDesc& d, const uint32_t* d_key, uint32_t* counts, hipStream_t s);
-hipError_t launch_pb_write(const GenDesc& d, const uint32_t* d_key, const uint32_t* offsets, char* const* blocks,
-                           int log2B, hipStream_t s);
+hipError_t launch_pb_count(const GenDesc& d, const uint32_t* d_key, uint32_t* counts, uint16_t* bits,
+                           hipStream_t s);
+hipError_t launch_pb_write(const GenDesc& d, const uint32_t* d_key, const uint32_t* offsets, const uint16_t* bits,
+                           char* const* blocks, int log2B, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Spike buffers and delivery (Sec. 2.3) over the calibrated connections.

@@ -1342,7 +1342,7 @@ __device__ __forceinline__ uint32_t pb_bits(const GenDesc& d, uint32_t a, uint32
 }
 
 __global__ __launch_bounds__(kPbThreads) void k_pb_count(GenDesc d, const uint32_t* __restrict__ key,
-                                                         uint32_t* __restrict__ counts) {
+                                                         uint32_t* __restrict__ counts, uint16_t* __restrict__ dbits) {
   __shared__ uint32_t s_tmp[kPbThreads / 64];
   const uint32_t key0 = C(key, 0), key1 = C(key, 1);
   const uint32_t upr = (d.nt + kPbUnit - 1) / kPbUnit;
@@ -1350,6 +1350,7 @@ __global__ __launch_bounds__(kPbThreads) void k_pb_count(GenDesc d, const uint32
   for (uint64_t u = blockIdx.x; u < units; u += gridDim.x) {
     const uint32_t a = (uint32_t)(u / upr), c = (uint32_t)(u - (uint64_t)a * upr);
     const uint32_t bits = pb_bits(d, a, c * kPbUnit + threadIdx.x * kPbPer, key0, key1);
+    if (dbits) G(dbits)[u * kPbThreads + threadIdx.x] = (uint16_t)bits;
     uint32_t total;
     (void)block_exclusive_scan((uint32_t)__popc(bits), s_tmp, &total);
     if (threadIdx.x == 0) counts[u] = total;
@@ -1359,6 +1360,7 @@ __global__ __launch_bounds__(kPbThreads) void k_pb_count(GenDesc d, const uint32
 
 __global__ __launch_bounds__(kPbThreads) void k_pb_write(GenDesc d, const uint32_t* __restrict__ key,
                                                          const uint32_t* __restrict__ offsets,
+                                                         const uint16_t* __restrict__ dbits,
                                                          char* const* __restrict__ blocks, int log2B) {
   __shared__ uint32_t s_tmp[kPbThreads / 64];
   const uint32_t key0 = C(key, 0), key1 = C(key, 1);
@@ -1368,7 +1370,7 @@ __global__ __launch_bounds__(kPbThreads) void k_pb_write(GenDesc d, const uint32
   for (uint64_t u = blockIdx.x; u < units; u += gridDim.x) {
     const uint32_t a = (uint32_t)(u / upr), c = (uint32_t)(u - (uint64_t)a * upr);
     const uint32_t b0 = c * kPbUnit + threadIdx.x * kPbPer;
-    uint32_t bits = pb_bits(d, a, b0, key0, key1);
+    uint32_t bits = dbits ? (uint32_t)G(dbits)[u * kPbThreads + threadIdx.x] : pb_bits(d, a, b0, key0, key1);
     uint32_t total;
     uint32_t j = offsets[u] + block_exclusive_scan((uint32_t)__popc(bits), s_tmp, &total);
     while (bits) {
@@ -1925,20 +1927,21 @@ hipError_t launch_set_ptrs(char** tab, uint32_t first, uint32_t count, const uin
   return hipGetLastError();
 }
 
-hipError_t launch_pb_count(const GenDesc& d, const uint32_t* d_key, uint32_t* counts, hipStream_t s) {
+hipError_t launch_pb_count(const GenDesc& d, const uint32_t* d_key, uint32_t* counts, uint16_t* bits,
+                           hipStream_t s) {
   const uint64_t units = (uint64_t)d.ns * ((d.nt + kPbUnit - 1) / kPbUnit);
   if (units == 0) return hipSuccess;
   hipLaunchKernelGGL(k_pb_count, dim3((uint32_t)std::min<uint64_t>(units, 65536)), dim3(kPbThreads), 0, s, d, d_key,
-                     counts);
+                     counts, bits);
   return hipGetLastError();
 }
 
-hipError_t launch_pb_write(const GenDesc& d, const uint32_t* d_key, const uint32_t* offsets, char* const* blocks,
-                           int log2B, hipStream_t s) {
+hipError_t launch_pb_write(const GenDesc& d, const uint32_t* d_key, const uint32_t* offsets, const uint16_t* bits,
+                           char* const* blocks, int log2B, hipStream_t s) {
   const uint64_t units = (uint64_t)d.ns * ((d.nt + kPbUnit - 1) / kPbUnit);
   if (units == 0) return hipSuccess;
   hipLaunchKernelGGL(k_pb_write, dim3((uint32_t)std::min<uint64_t>(units, 65536)), dim3(kPbThreads), 0, s, d, d_key,
-                     offsets, blocks, log2B);
+                     offsets, bits, blocks, log2B);
   return hipGetLastError();
 }
 

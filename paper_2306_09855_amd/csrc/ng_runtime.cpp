@@ -1239,7 +1239,8 @@ static int connect_pairwise(ng_ctx* c, ng_range src, ng_range tgt, const ng_conn
   const uint64_t units = (uint64_t)src.n * ((tgt.n + ng::kPbUnit - 1) / ng::kPbUnit);
   uint64_t n = 0;
   uint32_t* counts = nullptr;
-  uint64_t cbytes = 0;
+  uint64_t cbytes = 0, bits_bytes = 0;
+  uint16_t* bits = nullptr;
   if (units) {
     cbytes = 4 * (units + 1);
     const uint64_t tbytes = 4 * ng::scan_tmp_words(units);
@@ -1250,7 +1251,12 @@ static int connect_pairwise(ng_ctx* c, ng_range src, ng_range tgt, const ng_conn
     }
     cbytes += tbytes;
     uint32_t* tmp = counts + units + 1;
-    NG_LAUNCH(c, "pb_count", ng::launch_pb_count(d, key_ptr(c), counts, c->stream));
+    // the decisions of the counting pass, kept for the writing pass when the
+    // arena has room (one bit per pair), else evaluated again
+    bits_bytes = units * (ng::kPbUnit / 8);
+    bits = (uint16_t*)ctx_alloc(c, bits_bytes);
+    if (!bits) bits_bytes = 0;
+    NG_LAUNCH(c, "pb_count", ng::launch_pb_count(d, key_ptr(c), counts, bits, c->stream));
     NG_LAUNCH(c, "scan", ng::launch_exclusive_scan(counts, counts, units, tmp, counts + units, c->stream));
     uint32_t total = 0;
     NG_HIP(c, hipMemcpyAsync(&total, counts + units, 4, hipMemcpyDeviceToHost, c->stream), "pair count");
@@ -1259,17 +1265,28 @@ static int connect_pairwise(ng_ctx* c, ng_range src, ng_range tgt, const ng_conn
   }
   if (c->n_conns + n > 0xFFFFFFFFull) {
     ctx_unalloc(c, (char*)counts, cbytes);
+    ctx_unalloc(c, (char*)bits, bits_bytes);
     return fail(NG_ERR_TOO_LARGE, "a context holds at most 2^32-1 connections");
   }
   if (int rc = reserve_blocks(c, n)) {
-    ctx_unalloc(c, (char*)counts, cbytes);
-    return rc;
+    if (bits) {  // the decisions can be evaluated again: give their room to the blocks
+      ctx_unalloc(c, (char*)bits, bits_bytes);
+      bits = nullptr;
+      bits_bytes = 0;
+      rc = reserve_blocks(c, n);
+    }
+    if (rc) {
+      ctx_unalloc(c, (char*)counts, cbytes);
+      return rc;
+    }
   }
   d.n_new = (uint32_t)n;
   d.pos0 = c->n_conns;
   if (int rc = sync_table(c)) return rc;
-  if (n) NG_LAUNCH(c, "pb_write", ng::launch_pb_write(d, key_ptr(c), counts, c->d_tab[c->cur], c->log2B, c->stream));
+  if (n)
+    NG_LAUNCH(c, "pb_write", ng::launch_pb_write(d, key_ptr(c), counts, bits, c->d_tab[c->cur], c->log2B, c->stream));
   ctx_free(c, (char*)counts, cbytes);
+  ctx_free(c, (char*)bits, bits_bytes);
   if (out_cid) *out_cid = d.cid;
   if (out_first) *out_first = d.pos0;
   if (out_n) *out_n = n;

@@ -85,3 +85,19 @@ def test_pairwise_errors_change_nothing():
         with pytest.raises(ng.NGError) as e:
             net.connect_batch([_pb(0.5, (0, 10), (0, 10))])
         assert e.value.status == ng.NG_ERR_UNSUPPORTED
+
+
+def test_pairwise_without_room_for_the_decisions():
+    # 2,000 x 4,096 pairs: the counting pass keeps 1 MB of decisions; the
+    # arena then has no room for the one block of connections, so the
+    # decisions are dropped and the writing pass evaluates the pairs again
+    call = _pb(0.0075, (0, 2000), (2000, 4096))
+    n = oracle.count_pairwise(5, 0, call)
+    assert 0 < n < (1 << 16)
+    call.n_syn = lambda: n
+    ref = oracle.build_network(5, 0.1, 6200, [call])
+    with Network(5, 0.1, 1 << 16, 1_100_000) as net:
+        net.create(6200)
+        assert net.connect(call)[2] == n
+        created = net.fetch()
+    check_creation_order(created, ref, [call])
