@@ -81,10 +81,12 @@ typedef struct {
  * fixed_indegree: target t takes the sources at positions pi_t(0..K-1) of
  * its candidates (the source range, without t when autapses are
  * prohibited), pi_t a permutation of [0, M) keyed by the call and t: a
- * 4-round Feistel network on the smallest even width 2h >= 2 with
- * 2^(2h) >= M, round r mapping (L, R) to (R, L ^ (word 0 of
- * Philox(ctr = (R, t, call, 131072 + r)) mod 2^h)), reapplied until the value
- * is below M.  fixed_outdegree likewise with sources and targets exchanged.
+ * 4-round Feistel network on n bits, the smallest n >= 2 with 2^n >= M,
+ * reapplied until the value is below M: the value is L * 2^nb + R (R the low
+ * nb = n - floor(n/2) bits), rounds 0 and 2 set L ^= lowbias32(R ^ k_r) mod
+ * 2^(n - nb), rounds 1 and 3 set R ^= lowbias32(L ^ k_r) mod 2^nb, with
+ * k_0..k_3 the words of Philox(ctr = (t, 0, call, 131072)) and lowbias32
+ * the integer hash of C. Wellons (2018).  fixed_outdegree likewise with sources and targets exchanged.
  * fixed_total_number: synapse i is the pair of index pi_0(i) in the
  * all_to_all order.  These draws use no stream-0 word (synapse i's delay is
  * word i).  K or N above the distinct candidates is NG_ERR_INVALID_ARG. */

@@ -106,27 +106,41 @@ static uint64_t overlap(const ora_call* c) {
 
 static int no_self(const ora_call* c) { return !c->allow_autapses && !c->src_idx && !c->tgt_idx; }
 
-/* permutation of [0, m) for multapse-free draws: Feistel network, cycle walk */
-static uint64_t feistel(uint64_t seed, uint32_t cid, uint32_t u, int h, uint64_t x) {
-  const uint64_t mask = (h >= 64) ? ~0ull : ((1ull << h) - 1);
-  uint64_t l = x >> h, r = x & mask;
-  for (uint32_t round = 0; round < 4; round++) {
-    uint32_t ctr[4] = {(uint32_t)r, u, cid, 131072u + round}, key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)}, out[4];
-    ora_philox4x32_10(ctr, key, out);
-    const uint64_t f = (uint64_t)out[0] & mask;
-    const uint64_t nl = r, nr = l ^ f;
-    l = nl;
-    r = nr;
-  }
-  return (l << h) | r;
+/* permutation of [0, m) for multapse-free draws: a 4-round Feistel network on
+ * n bits (the smallest n >= 2 with 2^n >= m), walked until the value falls
+ * below m.  x = L * 2^nb + R with R the low nb = n - floor(n/2) bits and L
+ * the high na = floor(n/2) bits; rounds 0 and 2 set L ^= F_r(R) mod 2^na,
+ * rounds 1 and 3 set R ^= F_r(L) mod 2^nb, F_r(v) = lowbias32(v ^ k_r) with
+ * lowbias32 the integer hash of C. Wellons ("Prospecting for Hash
+ * Functions", 2018) and k_0..k_3 the words of Philox(ctr = (u, 0, cid,
+ * 131072)). */
+static uint32_t lowbias32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+static uint64_t feistel(const uint32_t k[4], int na, int nb, uint64_t x) {
+  const uint64_t mask_a = (1ull << na) - 1, mask_b = (1ull << nb) - 1;
+  uint64_t left = x >> nb, right = x & mask_b;
+  left ^= (uint64_t)lowbias32((uint32_t)right ^ k[0]) & mask_a;
+  right ^= (uint64_t)lowbias32((uint32_t)left ^ k[1]) & mask_b;
+  left ^= (uint64_t)lowbias32((uint32_t)right ^ k[2]) & mask_a;
+  right ^= (uint64_t)lowbias32((uint32_t)left ^ k[3]) & mask_b;
+  return (left << nb) | right;
 }
 
 static uint64_t permute(uint64_t seed, uint32_t cid, uint32_t u, uint64_t m, uint64_t x) {
-  int bits = 2;
-  while (bits < 64 && (1ull << bits) < m) bits++;
-  if (bits & 1) bits++;
-  uint64_t y = feistel(seed, cid, u, bits / 2, x);
-  while (y >= m) y = feistel(seed, cid, u, bits / 2, y);
+  int n = 2;
+  while (n < 64 && (1ull << n) < m) n++;
+  const int na = n / 2, nb = n - na;
+  uint32_t ctr[4] = {u, 0, cid, 131072u}, key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)}, k[4];
+  ora_philox4x32_10(ctr, key, k);
+  uint64_t y = feistel(k, na, nb, x);
+  while (y >= m) y = feistel(k, na, nb, y);
   return y;
 }
 

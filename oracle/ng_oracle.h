@@ -87,10 +87,14 @@ typedef struct {
   double p;
   /* 0: no two connections join the same pair (sampling without
    * replacement; Discussion: future work).  Defined with a pseudorandom
-   * permutation pi_u of [0, M): a 4-round Feistel network on the smallest
-   * even number of bits 2h >= 2 with 2^(2h) >= M, round r mapping (L, R) to
-   * (R, L ^ (word 0 of Philox(ctr = (R, u, c, 131072 + r)) mod 2^h)), walked
-   * until the value falls below M.  fixed_indegree: target t gets the sources
+   * permutation pi_u of [0, M): a 4-round Feistel network on n bits, the
+   * smallest n >= 2 with 2^n >= M, walked until the value falls below M; the
+   * value is L * 2^nb + R (R the low nb = n - floor(n/2) bits), rounds 0 and
+   * 2 set L ^= lowbias32(R ^ k_r) mod 2^(n - nb), rounds 1 and 3 set
+   * R ^= lowbias32(L ^ k_r) mod 2^nb, with k_0..k_3 the words of
+   * Philox(ctr = (u, 0, c, 131072)) and lowbias32 the integer hash of
+   * C. Wellons (2018).
+   * fixed_indegree: target t gets the sources
    * at positions pi_t(0..K-1) of its candidates (the source range, or the
    * range without t, skip-self as above); fixed_outdegree likewise;
    * fixed_total_number: synapse i is the pair of index pi_0(i) in the

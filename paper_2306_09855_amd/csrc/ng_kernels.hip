@@ -62,32 +62,45 @@ enum { R_ONE_TO_ONE = 0, R_ALL_TO_ALL = 1, R_INDEG = 2, R_OUTDEG = 3, R_TOTAL = 
        R_INDEG_D = kRuleIndegDistinct, R_OUTDEG_D = kRuleOutdegDistinct, R_TOTAL_D = kRuleTotalDistinct };
 
 // Distinct draws (no multapses): x -> pi(x), a permutation of [0, m) keyed by
-// (call, node u): a 4-round Feistel network on 2h bits (the smallest even
-// width with 2^(2h) >= m, at least 2), whose round r maps (L, R) to
-// (R, L ^ (word 0 of Philox(R, u, call, 131072 + r) mod 2^h)), applied again
-// until the value falls below m (the cycle through x returns below m).
-__device__ __forceinline__ uint64_t feistel4(uint64_t x, int h, uint32_t u, uint32_t cid, uint32_t key0,
-                                             uint32_t key1) {
-  const uint64_t mask = (1ull << h) - 1;
-  uint64_t l = x >> h, r = x & mask;
-#pragma unroll
-  for (uint32_t round = 0; round < 4; ++round) {
-    uint32_t out[4];
-    philox10((uint32_t)r, u, cid, 131072u + round, key0, key1, out);
-    const uint64_t f = (uint64_t)out[0] & mask;
-    const uint64_t nl = r;
-    r = l ^ f;
-    l = nl;
-  }
-  return (l << h) | r;
+// (call, node u).  A 4-round Feistel network on n bits, the smallest n >= 2
+// with 2^n >= m, applied again until the value falls below m (the cycle
+// through x returns below m; at most 2m values are visited per cycle step,
+// so about 2 steps on average).  x = L * 2^nb + R, R the low nb = n -
+// floor(n/2) bits, L the high na = floor(n/2) bits; rounds 0 and 2 set
+// L ^= F_r(R) mod 2^na, rounds 1 and 3 R ^= F_r(L) mod 2^nb, with
+// F_r(v) = lowbias32(v ^ k_r), lowbias32 the integer hash of C. Wellons
+// (2018) and k_0..k_3 the words of Philox(u, 0, call, 131072).  Both halves
+// fit 32 bits, so the rounds are 32-bit arithmetic.
+__device__ __forceinline__ uint32_t lowbias32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
 }
 
-__device__ __forceinline__ uint64_t permute_below(uint64_t x, uint64_t m, uint32_t u, uint32_t cid, uint32_t key0,
-                                                  uint32_t key1) {
-  int bits = m <= 4 ? 2 : 64 - __clzll((long long)(m - 1));
-  bits += bits & 1;
-  uint64_t y = feistel4(x, bits / 2, u, cid, key0, key1);
-  while (y >= m) y = feistel4(y, bits / 2, u, cid, key0, key1);
+struct PermKeys {
+  uint32_t k[4];
+};
+
+__device__ __forceinline__ void perm_keys(PermKeys& p, uint32_t u, uint32_t cid, uint32_t key0, uint32_t key1) {
+  philox10(u, 0u, cid, 131072u, key0, key1, p.k);
+}
+
+__device__ __forceinline__ uint64_t permute_below(uint64_t x, uint64_t m, const PermKeys& p) {
+  const int n = m <= 4 ? 2 : 64 - __clzll((long long)(m - 1));
+  const int na = n >> 1, nb = n - na;
+  const uint32_t mask_a = (uint32_t)((1ull << na) - 1), mask_b = (uint32_t)((1ull << nb) - 1);
+  uint64_t y = x;
+  do {
+    uint32_t l = (uint32_t)(y >> nb), r = (uint32_t)y & mask_b;
+    l ^= lowbias32(r ^ p.k[0]) & mask_a;
+    r ^= lowbias32(l ^ p.k[1]) & mask_b;
+    l ^= lowbias32(r ^ p.k[2]) & mask_a;
+    r ^= lowbias32(l ^ p.k[3]) & mask_b;
+    y = ((uint64_t)l << nb) | r;
+  } while (y >= m);
   return y;
 }
 
@@ -139,27 +152,44 @@ __device__ __forceinline__ void gen_quad(const GenDesc& d, uint32_t g, uint32_t 
 
   // source / target indices, Eqs. (4)-(13)
   if constexpr (RULE == R_INDEG_D || RULE == R_OUTDEG_D || RULE == R_TOTAL_D) {
-    // no multapses: positions from a permutation keyed by the fixed node
+    // no multapses: positions from a permutation keyed by the fixed node;
+    // the node's keys are drawn once per quad unless the quad crosses nodes
+    PermKeys pk;
+    uint32_t node = 0, pos = 0;
+    if constexpr (RULE == R_TOTAL_D) {
+      perm_keys(pk, 0u, d.cid, key0, key1);
+    } else {
+      node = i0 / d.k;
+      pos = i0 - node * d.k;
+      perm_keys(pk, (RULE == R_INDEG_D ? d.t0 : d.s0) + node, d.cid, key0, key1);
+    }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const uint32_t i = i0 + r;
+      if constexpr (RULE != R_TOTAL_D) {
+        if (r > 0 && ++pos == d.k) {
+          pos = 0;
+          ++node;
+          perm_keys(pk, (RULE == R_INDEG_D ? d.t0 : d.s0) + node, d.cid, key0, key1);
+        }
+      }
       if constexpr (RULE == R_INDEG_D) {
-        const uint32_t t = d.t0 + i / d.k;
+        const uint32_t t = d.t0 + node;
         const bool in_s = d.no_self && t - d.s0 < d.ns;
-        uint32_t a = (uint32_t)permute_below(i % d.k, d.ns - (in_s ? 1u : 0u), t, d.cid, key0, key1);
+        uint32_t a = (uint32_t)permute_below(pos, d.ns - (in_s ? 1u : 0u), pk);
         if (in_s && a >= t - d.s0) ++a;
         q.s[r] = d.s0 + a;
         q.t[r] = t;
       } else if constexpr (RULE == R_OUTDEG_D) {
-        const uint32_t s = d.s0 + i / d.k;
+        const uint32_t s = d.s0 + node;
         const bool in_t = d.no_self && s - d.t0 < d.nt;
-        uint32_t b = (uint32_t)permute_below(i % d.k, d.nt - (in_t ? 1u : 0u), s, d.cid, key0, key1);
+        uint32_t b = (uint32_t)permute_below(pos, d.nt - (in_t ? 1u : 0u), pk);
         if (in_t && b >= s - d.t0) ++b;
         q.s[r] = s;
         q.t[r] = d.t0 + b;
       } else {
         // pair index in all_to_all order (without the self-pairs when prohibited)
-        const uint64_t k = permute_below(i, d.n_pairs, 0u, d.cid, key0, key1);
+        const uint64_t k = permute_below(i, d.n_pairs, pk);
         uint64_t a, b;
         if (!d.no_self) {
           a = k / d.nt;
@@ -1161,8 +1191,8 @@ __global__ __launch_bounds__(kThreads) void k_group_flags(GiPack pk, uint32_t* _
           ps = ~s4.x;  // position 0 opens a group
         }
       }
-      const uint32_t nib = ((s4.x != ps) | (d0 != pd) ? 1u : 0u) | ((s4.y != s4.x) | (d1 != d0) ? 2u : 0u) |
-                           ((s4.z != s4.y) | (d2 != d1) ? 4u : 0u) | ((s4.w != s4.z) | (d3 != d2) ? 8u : 0u);
+      const uint32_t nib = (((s4.x != ps) | (d0 != pd)) ? 1u : 0u) | (((s4.y != s4.x) | (d1 != d0)) ? 2u : 0u) |
+                           (((s4.z != s4.y) | (d2 != d1)) ? 4u : 0u) | (((s4.w != s4.z) | (d3 != d2)) ? 8u : 0u);
       c += (uint32_t)__popc(nib);
       uint32_t w = nib << (4 * (lane & 7));
       w |= __shfl_xor(w, 1);
