@@ -33,10 +33,11 @@
  *   counter (q/4 mod 2^32, q/4 >> 32, c, s).  Stream 0 holds index and delay
  *   draws: synapse i of a call uses words i*w0 .. i*w0+w0-1 in the order
  *   [source draw][target draw][delay draw], each present only if random
- *   (w0 = number of random draws).  Stream 1 holds weight draws: words 2i and
- *   2i+1 of synapse i.  rand(N) = floor(x * N / 2^32) for a word x.
- *   Normal weights: Box-Muller, cosine branch, u1 = (y0>>8 + 1)/2^24,
- *   u2 = (y1>>8)/2^24, computed in fp32 and stored as fp32.
+ *   (w0 = number of random draws).  Stream 1 holds weight draws: normal
+ *   weights of synapses 2j and 2j+1 are the cosine and sine outputs of
+ *   Box-Muller on words y0 = 2j, y1 = 2j+1, u1 = (y0>>8 + 1)/2^24,
+ *   u2 = (y1>>8)/2^24; a uniform weight of synapse i takes word i.  Computed
+ *   in fp32 and stored as fp32.  rand(N) = floor(x * N / 2^32) for a word x.
  */
 #ifndef NG_H
 #define NG_H
@@ -114,7 +115,7 @@ typedef struct {
  * is a connection when word a * N_t + b of stream 0 is below
  * floor(p * 2^32); with allow_autapses = 0 a self-pair never is.  The
  * connections are numbered in pair order; connection j draws its delay from
- * word j of stream 2 and its weight from words 2j, 2j+1 of stream 1.  Only
+ * word j of stream 2 and its weight from stream 1 as synapse j would.  Only
  * ng_connect takes it: a counting pass over the pairs gives the exact number
  * of connections, the host reads it (ng_connect synchronizes for this rule;
  * NG_ERR_STATE under capture), reserves exactly that many, and a second pass

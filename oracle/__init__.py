@@ -80,6 +80,8 @@ def lib():
         L.ora_rand_below_batch.restype = None
         L.ora_normal_weight.argtypes = [u32, u32, f64, f64]
         L.ora_normal_weight.restype = f64
+        L.ora_normal_weight2.argtypes = [u32, u32, ctypes.c_int, f64, f64]
+        L.ora_normal_weight2.restype = f64
         L.ora_uniform_weight.argtypes = [u32, f64, f64]
         L.ora_uniform_weight.restype = f64
         L.ora_delay_steps.argtypes = [f32, f32]
@@ -160,8 +162,11 @@ def rand_below(x, n: int) -> np.ndarray:
     return out
 
 
-def normal_weight(y0: int, y1: int, mean: float, sd: float) -> float:
-    return float(lib().ora_normal_weight(y0, y1, mean, sd))
+def normal_weight(y0: int, y1: int, mean: float, sd: float, branch: int = 0) -> float:
+    """Box-Muller on the words (y0, y1): branch 0 the cosine output, 1 the sine output."""
+    if branch == 0:
+        return float(lib().ora_normal_weight(y0, y1, mean, sd))
+    return float(lib().ora_normal_weight2(y0, y1, branch, mean, sd))
 
 
 def uniform_weight(y0: int, lo: float, hi: float) -> float:

@@ -64,13 +64,20 @@ void ora_rand_below_batch(const uint32_t* x, uint64_t count, uint32_t n, uint32_
 static double unit_open0(uint32_t y) { return ((double)(y >> 8) + 1.0) * (1.0 / 16777216.0); }
 static double unit_open1(uint32_t y) { return (double)(y >> 8) * (1.0 / 16777216.0); }
 
-/* Normal weight: Box-Muller, cosine branch, evaluated in fp64. */
-double ora_normal_weight(uint32_t y0, uint32_t y1, double mean, double sd) {
+/* Normal weights: Box-Muller on one pair of words, evaluated in fp64;
+ * branch 0 is the cosine, branch 1 the sine (the two outputs are independent
+ * standard normals). */
+double ora_normal_weight2(uint32_t y0, uint32_t y1, int branch, double mean, double sd) {
   const double two_pi = 6.283185307179586476925286766559;
   double u1 = unit_open0(y0);
   double u2 = unit_open1(y1);
-  double z = sqrt(-2.0 * log(u1)) * cos(two_pi * u2);
+  double r = sqrt(-2.0 * log(u1));
+  double z = branch ? r * sin(two_pi * u2) : r * cos(two_pi * u2);
   return mean + sd * z;
+}
+
+double ora_normal_weight(uint32_t y0, uint32_t y1, double mean, double sd) {
+  return ora_normal_weight2(y0, y1, 0, mean, sd);
 }
 
 double ora_uniform_weight(uint32_t y0, double lo, double hi) {
@@ -355,8 +362,10 @@ int ora_synapse(uint64_t seed, float h, uint32_t cid, const ora_call* c, uint64_
   return weight_and_delay(seed, h, cid, c, i, 0, q, w, delay);
 }
 
-/* delay of synapse i from word q of stream dstream (if random), weight from
- * words 2i, 2i+1 of stream 1 (if random) */
+/* delay of synapse i from word q of stream dstream (if random); a random
+ * weight from stream 1: normal weights of synapses 2j and 2j+1 are the cosine
+ * and sine outputs of the Box-Muller pair on words 2j, 2j+1; a uniform
+ * weight takes word i */
 static int weight_and_delay(uint64_t seed, float h, uint32_t cid, const ora_call* c, uint64_t i, uint32_t dstream,
                             uint64_t q, double* w, int32_t* delay) {
   if (c->d_arr) {
@@ -385,12 +394,14 @@ static int weight_and_delay(uint64_t seed, float h, uint32_t cid, const ora_call
     case ORA_CONST:
       *w = c->w_a;
       break;
-    case ORA_NORMAL:
-      *w = ora_normal_weight(ora_word(seed, cid, 1, 2 * i), ora_word(seed, cid, 1, 2 * i + 1),
-                             c->w_a, c->w_b);
+    case ORA_NORMAL: {
+      const uint64_t j = i >> 1;
+      *w = ora_normal_weight2(ora_word(seed, cid, 1, 2 * j), ora_word(seed, cid, 1, 2 * j + 1), (int)(i & 1),
+                              c->w_a, c->w_b);
       break;
+    }
     case ORA_UNIFORM:
-      *w = ora_uniform_weight(ora_word(seed, cid, 1, 2 * i), c->w_a, c->w_b);
+      *w = ora_uniform_weight(ora_word(seed, cid, 1, i), c->w_a, c->w_b);
       break;
     default:
       return -1;

@@ -83,7 +83,7 @@ typedef struct {
    * when word (a * N_t + b) of stream 0 is below floor(p * 2^32) (a, b: the
    * positions of s and t; self-pairs never with allow_autapses = 0); the
    * connections are numbered in that order; connection j draws its delay
-   * from word j of stream 2 and its weight from words 2j, 2j+1 of stream 1. */
+   * from word j of stream 2 and its weight from stream 1 as synapse j would. */
   double p;
   /* 0: no two connections join the same pair (sampling without
    * replacement; Discussion: future work).  Defined with a pseudorandom
@@ -112,6 +112,8 @@ uint32_t ora_rand_below(uint32_t x, uint32_t n);
 void ora_rand_below_batch(const uint32_t* x, uint64_t count, uint32_t n, uint32_t* out);
 /* weight transforms from stream-1 words */
 double ora_normal_weight(uint32_t y0, uint32_t y1, double mean, double sd);
+/* branch 0: cosine output (ora_normal_weight), 1: sine output */
+double ora_normal_weight2(uint32_t y0, uint32_t y1, int branch, double mean, double sd);
 double ora_uniform_weight(uint32_t y0, double lo, double hi);
 /* delay in ms -> integer steps (fp32), minimum one step */
 int32_t ora_delay_steps(float d_ms, float h);

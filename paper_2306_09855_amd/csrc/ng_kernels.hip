@@ -125,17 +125,34 @@ __device__ __forceinline__ int32_t delay_from_word(const GenDesc& d, uint32_t xd
   return steps < 1.0f ? 1 : (int32_t)steps;
 }
 
-// Random weight from its two stream-1 words: Box-Muller (cosine branch) or uniform.
-__device__ __forceinline__ float weight_from_words(const GenDesc& d, uint32_t y0, uint32_t y1) {
+// Random weights from stream 1.  Normal: synapses 2j and 2j+1 take the cosine
+// and sine outputs of Box-Muller on words 2j, 2j+1; uniform: synapse i takes
+// word i.
+__device__ __forceinline__ void normal_pair(const GenDesc& d, uint32_t y0, uint32_t y1, float& w_cos,
+                                            float& w_sin) {
+  const float u1 = (float)((y0 >> 8) + 1u) * kInv2p24;  // (0, 1]
+  const float u2 = (float)(y1 >> 8) * kInv2p24;         // [0, 1)
+  const float rad = __fsqrt_rn(-2.0f * logf(u1));
+  float sn, cs;
+  sincospif(2.0f * u2, &sn, &cs);
+  w_cos = __fmaf_rn(d.w_b, rad * cs, d.w_a);
+  w_sin = __fmaf_rn(d.w_b, rad * sn, d.w_a);
+}
+
+__device__ __forceinline__ float uniform_weight(const GenDesc& d, uint32_t y) {
+  return __fmaf_rn(d.w_b, (float)(y >> 8) * kInv2p24, d.w_a);
+}
+
+// Weight of connection j from the stream-1 block holding words 4(j/4)..4(j/4)+3.
+__device__ __forceinline__ float weight_of(const GenDesc& d, const uint32_t (&y)[4], uint32_t j) {
   if (d.w_kind == W_NORMAL) {
-    const float u1 = (float)((y0 >> 8) + 1u) * kInv2p24;  // (0, 1]
-    const float u2 = (float)(y1 >> 8) * kInv2p24;         // [0, 1)
-    const float rad = __fsqrt_rn(-2.0f * logf(u1));
-    const float z = rad * cospif(2.0f * u2);
-    return __fmaf_rn(d.w_b, z, d.w_a);
+    float wc, ws;
+    const bool hi = (j & 2u) != 0;  // selects, not a dynamic register index
+    normal_pair(d, hi ? y[2] : y[0], hi ? y[3] : y[1], wc, ws);
+    return (j & 1u) ? ws : wc;
   }
-  const float u = (float)(y0 >> 8) * kInv2p24;
-  return __fmaf_rn(d.w_b, u, d.w_a);
+  const uint32_t lo = (j & 1u) ? y[1] : y[0], hi = (j & 1u) ? y[3] : y[2];
+  return uniform_weight(d, (j & 2u) ? hi : lo);
 }
 
 // Synapses i0..i0+3 of one call (i0 = 4g).  W0 = stream-0 words per synapse.
@@ -324,16 +341,20 @@ __device__ __forceinline__ void gen_quad(const GenDesc& d, uint32_t g, uint32_t 
     }
   }
 
-  // weights from stream 1, words 2i and 2i+1
+  // weights from stream 1, block g (words 4g..4g+3)
   if (d.w_kind == W_CONST) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) q.w[r] = d.w_a;
   } else {
-    uint32_t y[8];
-    philox_block(2ull * g, d.cid, 1u, key0, key1, &y[0]);
-    philox_block(2ull * g + 1, d.cid, 1u, key0, key1, &y[4]);
+    uint32_t y[4];
+    philox_block(g, d.cid, 1u, key0, key1, y);
+    if (d.w_kind == W_NORMAL) {
+      normal_pair(d, y[0], y[1], q.w[0], q.w[1]);
+      normal_pair(d, y[2], y[3], q.w[2], q.w[3]);
+    } else {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) q.w[r] = weight_from_words(d, y[2 * r], y[2 * r + 1]);
+      for (int r = 0; r < 4; ++r) q.w[r] = uniform_weight(d, y[r]);
+    }
   }
 }
 
@@ -1407,7 +1428,7 @@ __global__ __launch_bounds__(kPbThreads) void k_pb_write(GenDesc d, const uint32
       const uint32_t k = (uint32_t)(__ffs(bits) - 1);
       bits &= bits - 1;
       // connection j of the call: delay from word j of stream 2, weight from
-      // words 2j, 2j+1 of stream 1
+      // stream 1 as synapse j of a generated call
       int32_t dl = d.d_const;
       if (d.d_kind != D_CONST) {
         uint32_t w4[4];
@@ -1418,8 +1439,8 @@ __global__ __launch_bounds__(kPbThreads) void k_pb_write(GenDesc d, const uint32
       float w = d.w_a;
       if (d.w_kind != W_CONST) {
         uint32_t y[4];
-        philox_block(j >> 1, d.cid, 1u, key0, key1, y);
-        w = weight_from_words(d, (j & 1) ? y[2] : y[0], (j & 1) ? y[3] : y[1]);
+        philox_block(j >> 2, d.cid, 1u, key0, key1, y);
+        w = weight_of(d, y, j);
       }
       const uint64_t p = d.pos0 + j;
       char* blk = G(blocks)[p >> log2B];

@@ -6,7 +6,7 @@ Discussion; defined here with per-pair decisions from the word streams):
 * the number of connections is binomial(N_s N_t, p) (z test over seeds);
 * targets and delays uniform (chi-square);
 * connection j has the weight of synapse j of an all_to_all call with the
-  same call id and weight law (weights are words 2j, 2j+1 of stream 1);
+  same call id and weight law (weights are stream 1 of synapse j);
 * the oracle's one-synapse path agrees with its whole-call path.
 """
 from types import SimpleNamespace

@@ -7,6 +7,7 @@
 * Weight transforms: closed-form special cases and distribution tests.
 * ms -> step delay conversion (Sec. 2.1): hand-checkable cases, ties to even.
 """
+import math
 import os
 import shutil
 import subprocess
@@ -125,12 +126,38 @@ def test_normal_special_cases():
     assert oracle.normal_weight(y0, 1 << 29, -0.5, 0.05) == pytest.approx(-0.5 + 0.05 * z, rel=1e-15)
 
 
+def test_normal_sine_branch_special_cases():
+    y0 = _y_for_u1(1 << 22)          # u1 = 1/4, radius 2 sqrt(ln 2)
+    assert oracle.normal_weight(y0, 0, 0.0, 1.0, branch=1) == 0.0                                      # u2 = 0
+    assert oracle.normal_weight(y0, 1 << 30, 0.0, 1.0, branch=1) == pytest.approx(SQRT_LN2_X2, rel=1e-15)   # 1/4
+    assert oracle.normal_weight(y0, 3 << 30, 0.0, 1.0, branch=1) == pytest.approx(-SQRT_LN2_X2, rel=1e-15)  # 3/4
+    assert oracle.normal_weight(y0, 1 << 29, 0.0, 1.0, branch=1) == pytest.approx(SQRT_2LN2, rel=1e-15)     # 1/8
+    assert oracle.normal_weight(y0, 5 << 29, 0.0, 1.0, branch=1) == pytest.approx(-SQRT_2LN2, rel=1e-15)    # 5/8
+    for y1 in (0, 123 << 8, 0xFFFFFFFF):
+        assert oracle.normal_weight(0xFFFFFFFF, y1, 0.5, 0.05, branch=1) == 0.5
+
+
+def test_normal_pair_radius():
+    # both outputs of one pair lie on the circle of radius sqrt(-2 ln u1)
+    for i in range(200):
+        y0, y1 = oracle.word(3, 1, 1, 2 * i), oracle.word(3, 1, 1, 2 * i + 1)
+        zc = oracle.normal_weight(y0, y1, 0.0, 1.0)
+        zs = oracle.normal_weight(y0, y1, 0.0, 1.0, branch=1)
+        u1 = ((y0 >> 8) + 1) * 2.0**-24
+        assert zc * zc + zs * zs == pytest.approx(-2.0 * math.log(u1), rel=1e-12, abs=1e-300)
+
+
 def test_normal_distribution():
     n = 100_000
     ws = np.array([oracle.normal_weight(oracle.word(7, 2, 1, 2 * i), oracle.word(7, 2, 1, 2 * i + 1),
                                         0.5, 0.05) for i in range(n)])
     assert stats.kstest(ws, "norm", args=(0.5, 0.05)).pvalue > 1e-4
     assert abs(ws.mean() - 0.5) < 4 * 0.05 / np.sqrt(n)
+    wsin = np.array([oracle.normal_weight(oracle.word(7, 2, 1, 2 * i), oracle.word(7, 2, 1, 2 * i + 1),
+                                          0.5, 0.05, branch=1) for i in range(n)])
+    assert stats.kstest(wsin, "norm", args=(0.5, 0.05)).pvalue > 1e-4
+    # the two outputs of a pair are independent: uncorrelated across pairs
+    assert abs(np.corrcoef(ws, wsin)[0, 1]) < 4 / np.sqrt(n)
     # variance: (n-1) s^2 / sigma^2 ~ chi2(n-1)
     chi = (n - 1) * ws.var(ddof=1) / 0.05**2
     assert stats.chi2.sf(chi, n - 1) > 1e-4 and stats.chi2.cdf(chi, n - 1) > 1e-4
@@ -140,7 +167,7 @@ def test_uniform_weight():
     assert oracle.uniform_weight(0, -1.0, 3.0) == -1.0
     assert oracle.uniform_weight(0xFFFFFFFF, -1.0, 3.0) == 3.0 - 4.0 * 2.0**-24
     assert oracle.uniform_weight(1 << 31, -1.0, 3.0) == 1.0
-    ws = np.array([oracle.uniform_weight(oracle.word(5, 0, 1, 2 * i), 2.0, 4.0) for i in range(50_000)])
+    ws = np.array([oracle.uniform_weight(oracle.word(5, 0, 1, i), 2.0, 4.0) for i in range(50_000)])
     assert stats.kstest(ws, "uniform", args=(2.0, 2.0)).pvalue > 1e-4
 
 

@@ -103,6 +103,20 @@ def test_weights_normal_per_call():
     assert stats.kstest(w, "norm", args=(-0.5, 0.05)).pvalue > ALPHA
 
 
+def test_normal_weights_pair_up():
+    # synapses 2j and 2j+1 are the cosine and sine outputs of one Box-Muller pair (words 2j,
+    # 2j+1 of stream 1), so they lie on the circle of radius sqrt(-2 ln u1); an odd last
+    # synapse is its pair's cosine output
+    n = 1001
+    _, _, w, _ = _conn(Call("fixed_total_number", (0, 10), (0, 10), n, ("normal", 0.0, 1.0)), cid=4)
+    w = np.asarray(w, np.float64)
+    for j in range(n // 2):
+        u1 = ((oracle.word(SEED, 4, 1, 2 * j) >> 8) + 1) * 2.0**-24
+        assert w[2 * j] ** 2 + w[2 * j + 1] ** 2 == pytest.approx(-2.0 * np.log(u1), rel=1e-6, abs=1e-12)
+    y0, y1 = oracle.word(SEED, 4, 1, 1000), oracle.word(SEED, 4, 1, 1001)
+    assert w[1000] == pytest.approx(oracle.normal_weight(y0, y1, 0.0, 1.0), rel=1e-6)
+
+
 def test_streams_are_distinct_across_calls_and_seeds():
     c = Call("fixed_total_number", (0, 1000), (0, 1000), 1000)
     a = _conn(c, cid=0)
