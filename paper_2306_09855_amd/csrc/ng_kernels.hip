@@ -143,18 +143,6 @@ __device__ __forceinline__ float uniform_weight(const GenDesc& d, uint32_t y) {
   return __fmaf_rn(d.w_b, (float)(y >> 8) * kInv2p24, d.w_a);
 }
 
-// Weight of connection j from the stream-1 block holding words 4(j/4)..4(j/4)+3.
-__device__ __forceinline__ float weight_of(const GenDesc& d, const uint32_t (&y)[4], uint32_t j) {
-  if (d.w_kind == W_NORMAL) {
-    float wc, ws;
-    const bool hi = (j & 2u) != 0;  // selects, not a dynamic register index
-    normal_pair(d, hi ? y[2] : y[0], hi ? y[3] : y[1], wc, ws);
-    return (j & 1u) ? ws : wc;
-  }
-  const uint32_t lo = (j & 1u) ? y[1] : y[0], hi = (j & 1u) ? y[3] : y[2];
-  return uniform_weight(d, (j & 2u) ? hi : lo);
-}
-
 // Synapses i0..i0+3 of one call (i0 = 4g).  W0 = stream-0 words per synapse.
 template <int RULE, bool DRAND>
 __device__ __forceinline__ void gen_quad(const GenDesc& d, uint32_t g, uint32_t key0, uint32_t key1,
@@ -1409,49 +1397,105 @@ __global__ __launch_bounds__(kPbThreads) void k_pb_count(GenDesc d, const uint32
   }
 }
 
+// Writing pass.  The unit's connections are numbered j = offsets[u] + l,
+// l = 0..total-1 in pair order; their target offsets are staged in LDS, then
+// each lane takes an aligned quad of connection indices: one stream-2 block
+// gives the quad's delays and one stream-1 block its weights (the draws of
+// synapses 4q..4q+3 of a generated call), so a block is evaluated once per
+// four connections instead of once per connection.  A unit's connections
+// span at most two blocks (a block holds >= 2^16 connections), whose
+// addresses are read once per unit; the next unit's decisions and offset
+// load while this unit is written.  A quad that is whole, inside one block
+// and 4-aligned there is written with vector stores.
 __global__ __launch_bounds__(kPbThreads) void k_pb_write(GenDesc d, const uint32_t* __restrict__ key,
                                                          const uint32_t* __restrict__ offsets,
                                                          const uint16_t* __restrict__ dbits,
                                                          char* const* __restrict__ blocks, int log2B) {
   __shared__ uint32_t s_tmp[kPbThreads / 64];
+  __shared__ uint16_t s_b[kPbUnit];  // target offset within the unit of local connection l
   const uint32_t key0 = C(key, 0), key1 = C(key, 1);
   const uint64_t B = 1ull << log2B;
   const uint32_t upr = (d.nt + kPbUnit - 1) / kPbUnit;
   const uint64_t units = (uint64_t)d.ns * upr;
-  for (uint64_t u = blockIdx.x; u < units; u += gridDim.x) {
+  uint64_t u = blockIdx.x;
+  uint32_t bits_next = 0, off_next = 0;
+  if (u < units) {
+    if (dbits) bits_next = G(dbits)[u * kPbThreads + threadIdx.x];
+    off_next = offsets[u];
+  }
+  for (; u < units; u += gridDim.x) {
     const uint32_t a = (uint32_t)(u / upr), c = (uint32_t)(u - (uint64_t)a * upr);
-    const uint32_t b0 = c * kPbUnit + threadIdx.x * kPbPer;
-    uint32_t bits = dbits ? (uint32_t)G(dbits)[u * kPbThreads + threadIdx.x] : pb_bits(d, a, b0, key0, key1);
+    uint32_t bits = dbits ? bits_next : pb_bits(d, a, c * kPbUnit + threadIdx.x * kPbPer, key0, key1);
+    const uint64_t j0 = off_next;
+    const uint64_t un = u + gridDim.x;
+    if (un < units) {
+      if (dbits) bits_next = G(dbits)[un * kPbThreads + threadIdx.x];
+      off_next = offsets[un];
+    }
     uint32_t total;
-    uint32_t j = offsets[u] + block_exclusive_scan((uint32_t)__popc(bits), s_tmp, &total);
+    uint32_t l = block_exclusive_scan((uint32_t)__popc(bits), s_tmp, &total);
     while (bits) {
       const uint32_t k = (uint32_t)(__ffs(bits) - 1);
       bits &= bits - 1;
-      // connection j of the call: delay from word j of stream 2, weight from
-      // stream 1 as synapse j of a generated call
-      int32_t dl = d.d_const;
-      if (d.d_kind != D_CONST) {
-        uint32_t w4[4];
-        philox_block(j >> 2, d.cid, 2u, key0, key1, w4);
-        const uint32_t x = w4[0] * ((j & 3) == 0) + w4[1] * ((j & 3) == 1) + w4[2] * ((j & 3) == 2) + w4[3] * ((j & 3) == 3);
-        dl = delay_from_word(d, x);
-      }
-      float w = d.w_a;
-      if (d.w_kind != W_CONST) {
-        uint32_t y[4];
-        philox_block(j >> 2, d.cid, 1u, key0, key1, y);
-        w = weight_of(d, y, j);
-      }
-      const uint64_t p = d.pos0 + j;
-      char* blk = G(blocks)[p >> log2B];
-      const uint64_t o = p & (B - 1);
-      G(reinterpret_cast<uint32_t*>(blk))[o] = d.s0 + a;
-      G(reinterpret_cast<uint32_t*>(blk + 4 * B))[o] = d.t0 + b0 + k;
-      G(reinterpret_cast<float*>(blk + 8 * B))[o] = w;
-      G(reinterpret_cast<int16_t*>(blk + 12 * B))[o] = (int16_t)dl;
-      ++j;
+      s_b[l++] = (uint16_t)(threadIdx.x * kPbPer + k);
     }
     __syncthreads();
+    if (total) {
+      const uint64_t j1 = j0 + total;  // this unit's connections [j0, j1)
+      const uint64_t q0 = j0 >> 2, nq = ((j1 - 1) >> 2) - q0 + 1;
+      const uint32_t src = d.s0 + a, tgt0 = d.t0 + c * kPbUnit;
+      const uint64_t bA = (d.pos0 + j0) >> log2B, bZ = (d.pos0 + j1 - 1) >> log2B;  // bZ <= bA + 1
+      char* const blkA = G(blocks)[bA];
+      char* const blkZ = bZ != bA ? G(blocks)[bZ] : blkA;
+      for (uint64_t qi = threadIdx.x; qi < nq; qi += kPbThreads) {
+        const uint64_t q = q0 + qi;
+        uint32_t xd[4] = {0, 0, 0, 0}, y[4] = {0, 0, 0, 0};
+        if (d.d_kind != D_CONST) philox_block(q, d.cid, 2u, key0, key1, xd);
+        float w[4] = {d.w_a, d.w_a, d.w_a, d.w_a};
+        if (d.w_kind != W_CONST) {
+          philox_block(q, d.cid, 1u, key0, key1, y);
+          if (d.w_kind == W_NORMAL) {
+            normal_pair(d, y[0], y[1], w[0], w[1]);
+            normal_pair(d, y[2], y[3], w[2], w[3]);
+          } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) w[r] = uniform_weight(d, y[r]);
+          }
+        }
+        int32_t dl[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dl[r] = d.d_kind != D_CONST ? delay_from_word(d, xd[r]) : d.d_const;
+        const uint64_t p4 = d.pos0 + 4 * q;
+        const bool whole = 4 * q >= j0 && 4 * q + 3 < j1;
+        if (whole && (p4 & 3) == 0) {
+          // p4 is 4-aligned and a block holds a multiple of 4, so the quad is in one block
+          char* blk = (p4 >> log2B) == bA ? blkA : blkZ;
+          const uint64_t o = p4 & (B - 1);
+          const uint32_t lq = (uint32_t)(4 * q - j0);
+          *(NG_GLOBAL u32x4*)(blk + 4 * o) = u32x4{src, src, src, src};
+          *(NG_GLOBAL u32x4*)(blk + 4 * B + 4 * o) =
+              u32x4{tgt0 + s_b[lq], tgt0 + s_b[lq + 1], tgt0 + s_b[lq + 2], tgt0 + s_b[lq + 3]};
+          *(NG_GLOBAL u32x4*)(blk + 8 * B + 4 * o) =
+              u32x4{__float_as_uint(w[0]), __float_as_uint(w[1]), __float_as_uint(w[2]), __float_as_uint(w[3])};
+          *(NG_GLOBAL u32x2*)(blk + 12 * B + 2 * o) =
+              u32x2{((uint32_t)dl[0] & 0xFFFFu) | ((uint32_t)dl[1] << 16), ((uint32_t)dl[2] & 0xFFFFu) | ((uint32_t)dl[3] << 16)};
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const uint64_t j = 4 * q + r;
+            if (j < j0 || j >= j1) continue;
+            const uint64_t p = d.pos0 + j;
+            char* blk = (p >> log2B) == bA ? blkA : blkZ;
+            const uint64_t o = p & (B - 1);
+            G(reinterpret_cast<uint32_t*>(blk))[o] = src;
+            G(reinterpret_cast<uint32_t*>(blk + 4 * B))[o] = tgt0 + s_b[j - j0];
+            G(reinterpret_cast<float*>(blk + 8 * B))[o] = w[r];
+            G(reinterpret_cast<int16_t*>(blk + 12 * B))[o] = (int16_t)dl[r];
+          }
+        }
+      }
+    }
+    __syncthreads();  // s_b and s_tmp are reused by the next unit
   }
 }
 

@@ -63,6 +63,8 @@ CASES = {
                                       d=("uniform", 0.05, 2.5))],
     "mixed": [_other("fixed_total_number", (0, 400), (400, 400), 30_000), _pb(0.1, (400, 400), (0, 700)),
               _other("fixed_indegree", (0, 100), (100, 50), 17)],
+    # 21 connections first: the pairwise call starts at a position that is not a multiple of 4
+    "unaligned_start": [_other("fixed_indegree", (0, 100), (100, 3), 7), _pb(0.15, (0, 300), (0, 2000))],
 }
 
 
