@@ -1793,16 +1793,26 @@ __device__ __forceinline__ uint64_t part_excl(uint64_t x, uint64_t* red) {
 }
 
 // number of keys of subarray (at position st) with index in [a, b) that are
-// <= t (le) or < t (!le), plus a; the answer is known to lie in [a, b]
+// <= t (le) or < t (!le), plus a; the answer is known to lie in [a, b] and
+// the keys ascend.  One wave, all lanes active with the same arguments: each
+// step probes 64 evenly spaced keys and keeps the slice between the last
+// probe that passes and the first that fails (a 65-ary search: a bracket of
+// 2^24 keys takes 4 steps and a final probe of <= 64 keys).
 __device__ __forceinline__ uint32_t part_count(const BlockView& v, uint32_t st, uint32_t a, uint32_t b, uint32_t t,
                                                bool le) {
-  while (a < b) {
-    const uint32_t mid = a + (b - a) / 2;
-    const uint32_t x = view_key(v, st + mid);
-    if (le ? x <= t : x < t) a = mid + 1;
-    else b = mid;
+  const uint32_t lane = threadIdx.x & 63;
+  while (b - a > 64) {
+    const uint64_t span = b - a;  // >= 65: the probes a + floor(span (j+1) / 65) ascend strictly inside (a, b)
+    const uint32_t x = view_key(v, st + a + (uint32_t)(span * (lane + 1) / 65));
+    const uint32_t c = (uint32_t)__popcll(__ballot(le ? x <= t : x < t));  // the passing probes are 0..c-1
+    const uint32_t na = c ? a + (uint32_t)(span * c / 65) + 1 : a;
+    const uint32_t nb = c < 64 ? a + (uint32_t)(span * (c + 1) / 65) : b;
+    a = na;
+    b = nb;
   }
-  return a;
+  const bool in = lane < b - a;
+  const uint32_t x = in ? view_key(v, st + a + lane) : 0u;
+  return a + (uint32_t)__popcll(__ballot(in && (le ? x <= t : x < t)));
 }
 
 // The partition search of the appendix.  Brackets [lo_i, hi_i]: lo_i counts
@@ -1812,7 +1822,8 @@ __device__ __forceinline__ uint32_t part_count(const BlockView& v, uint32_t st, 
 // between the sums, t is the threshold, else the bracket side that keeps m
 // inside moves to t.  When every bracket has width <= 1, the subarrays of
 // width one offer their next key and the smallest offers, by (key, i), fill
-// the rest.  Thread t owns the subarrays [t*C, (t+1)*C).
+// the rest.  Thread t owns the brackets of subarrays [t*C, (t+1)*C); the
+// counting searches of a round are spread over the waves.
 __global__ __launch_bounds__(kPartThreads) void k_copass_partition(CopassPart p) {
   __shared__ uint64_t red[kPartWaves];
   __shared__ uint32_t s_w[kPartWaves], s_i[kPartWaves];
@@ -1861,14 +1872,22 @@ __global__ __launch_bounds__(kPartThreads) void k_copass_partition(CopassPart p)
       break;
     }
     const uint32_t t = view_key(p.v, p.start[bi] + (p.lo[bi] + p.hi[bi]) / 2);
+    // counts at t: wave w searches subarrays w, w + kPartWaves, ... (the
+    // brackets were last written before the barriers above)
+    for (uint32_t i = threadIdx.x >> 6; i < k; i += kPartWaves) {
+      const uint32_t st = p.start[i], lo = p.lo[i], hi = p.hi[i];
+      const uint32_t mh = part_count(p.v, st, lo, hi, t, true);
+      const uint32_t ml = part_count(p.v, st, lo, mh, t, false);
+      if ((threadIdx.x & 63) == 0) {
+        p.mu_hi[i] = mh;
+        p.mu_lo[i] = ml;
+      }
+    }
+    __syncthreads();
     uint64_t slo = 0, shi = 0;
     for (uint32_t i = i0; i < i1; ++i) {
-      const uint32_t mh = part_count(p.v, p.start[i], p.lo[i], p.hi[i], t, true);
-      const uint32_t ml = part_count(p.v, p.start[i], p.lo[i], mh, t, false);
-      p.mu_hi[i] = mh;
-      p.mu_lo[i] = ml;
-      slo += ml;
-      shi += mh;
+      slo += p.mu_lo[i];
+      shi += p.mu_hi[i];
     }
     slo = part_sum(slo, red);
     shi = part_sum(shi, red);
