@@ -365,17 +365,17 @@ def arrays_bench(wl, block_size: int, steps: int, warmup: int, radix_bits: int, 
     ng.ng_enable_timing(ctx, False)
     net.close()
     ms = 1e3 * (t1 - t0) / steps
-    # per connection: source position read 4 + index read 4 + source write 4,
-    # weight read 4 + write 4, delay read 4 + write 2
+    # generation per connection: the 14-byte record written, the source index,
+    # weight and delay (ms) read from the arrays
     ab = 26.0 * wl.n_syn
     per = {}
     for name, (launches, total_ms) in kernels.items():
         k_ms = total_ms / steps
         per[name] = {"launches_per_step": launches / steps, "ms_per_step": round(k_ms, 4),
-                     "GBps_algorithmic": round(ab / (k_ms / 1e3) / 1e9, 1) if name == "apply_arrays" and k_ms else None}
+                     "GBps_algorithmic": round(ab / (k_ms / 1e3) / 1e9, 1) if name == "generate" and k_ms else None}
     return {"ms_per_step": round(ms, 3), "synapses_per_s": wl.n_syn / (ms / 1e3),
             "arrays": "source index arrays (permuted populations), per-connection weights and delays",
-            "apply_bytes_per_connection": 26, "kernels": per}
+            "generate_bytes_per_connection": 26, "kernels": per}
 
 
 def no_autapse_bench(wl, block_size: int, steps: int, warmup: int, radix_bits: int, sort_ranges: int,

@@ -44,6 +44,13 @@ struct GenDesc {
   uint64_t group0;   // batched form: index of this call's first 4-synapse group
   char* const* blocks;        // batched form: block table of the call's context
   const uint32_t* key;        // batched form: Philox key of the call's context
+  // node groups as index arrays and per-connection values (plain form only):
+  // a generated source (target) position p becomes src_idx[p] (tgt_idx[p]);
+  // synapse i takes weight w_arr[i] and the delay d_ms_arr[i] ms in steps
+  const uint32_t* src_idx = nullptr;
+  const uint32_t* tgt_idx = nullptr;
+  const float* w_arr = nullptr;
+  const float* d_ms_arr = nullptr;
 };
 
 // --- generation -----------------------------------------------------------
@@ -165,10 +172,12 @@ hipError_t launch_spikes_step(const SpikeState& st, const uint32_t* nodes, const
 
 // ---------------------------------------------------------------------------
 // Node groups as index arrays and per-connection weights / delays (Sec. 2.1).
-// check: out[0] = largest source index, out[1] = largest target index,
-// out[2] = bits of the largest delay in ms (negative delays count as 0),
-// out[3] = 1 if a delay is NaN (out must hold zeros on entry).  apply: rewrites the
-// call's n connections from creation position pos0 on.
+// check: the low words of out[0] = largest source index, out[1] = largest
+// target index, out[2] = bits of the largest delay in ms (negative delays
+// count as 0), out[3] = 1 if a delay is NaN; every workgroup raises each
+// out[w] to at least (epoch << 32 | its value), so out must hold values of
+// smaller epochs on entry.  Generation then applies the arrays
+// (GenDesc::src_idx, tgt_idx, w_arr, d_ms_arr).
 struct CallArrays {
   const uint32_t* src_idx;  // ns entries, or null
   uint32_t ns;
@@ -179,8 +188,7 @@ struct CallArrays {
   uint32_t n;
   float h;
 };
-hipError_t launch_check_arrays(const CallArrays& a, uint32_t* out, hipStream_t s);
-hipError_t launch_apply_arrays(const CallArrays& a, char* const* blocks, int log2B, uint64_t pos0, hipStream_t s);
+hipError_t launch_check_arrays(const CallArrays& a, uint64_t* out, uint32_t epoch, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // COPASS in-place block sort (Appendix A).

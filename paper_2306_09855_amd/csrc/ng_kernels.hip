@@ -125,6 +125,12 @@ __device__ __forceinline__ int32_t delay_from_word(const GenDesc& d, uint32_t xd
   return steps < 1.0f ? 1 : (int32_t)steps;
 }
 
+// A delay given in ms as integer steps (Sec. 2.1), at least one step.
+__device__ __forceinline__ float ms_to_steps(float ms, float h) {
+  const float steps = rintf(__fdiv_rn(ms, h));  // as the generation kernel's ms path
+  return steps < 1.0f ? 1.0f : steps;
+}
+
 // Random weights from stream 1.  Normal: synapses 2j and 2j+1 take the cosine
 // and sine outputs of Box-Muller on words 2j, 2j+1; uniform: synapse i takes
 // word i.
@@ -478,6 +484,42 @@ __device__ __forceinline__ void store_quad(char* const* __restrict__ blocks, int
   }
 }
 
+// Index arrays and per-connection values of synapses i0..i0+3 (those below
+// n_new): generated positions become the nodes the arrays name.
+__device__ __forceinline__ void apply_arrays(const GenDesc& d, uint32_t i0, Quad& q) {
+  if (i0 + 3 < d.n_new && (((uintptr_t)d.w_arr | (uintptr_t)d.d_ms_arr) & 15) == 0) {
+    // a whole quad and 16-byte aligned values: one vector load per array
+    if (d.w_arr) {
+      const u32x4 w4 = *(const NG_GLOBAL u32x4*)(const void*)(d.w_arr + i0);
+      q.w[0] = __uint_as_float(w4.x);
+      q.w[1] = __uint_as_float(w4.y);
+      q.w[2] = __uint_as_float(w4.z);
+      q.w[3] = __uint_as_float(w4.w);
+    }
+    if (d.d_ms_arr) {
+      const u32x4 d4 = *(const NG_GLOBAL u32x4*)(const void*)(d.d_ms_arr + i0);
+      q.d[0] = (int32_t)ms_to_steps(__uint_as_float(d4.x), d.h);
+      q.d[1] = (int32_t)ms_to_steps(__uint_as_float(d4.y), d.h);
+      q.d[2] = (int32_t)ms_to_steps(__uint_as_float(d4.z), d.h);
+      q.d[3] = (int32_t)ms_to_steps(__uint_as_float(d4.w), d.h);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (d.src_idx) q.s[r] = G(d.src_idx)[q.s[r]];  // the generated value is a position < ns
+      if (d.tgt_idx) q.t[r] = G(d.tgt_idx)[q.t[r]];
+    }
+    return;
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    if (i0 + r >= d.n_new) break;
+    if (d.src_idx) q.s[r] = G(d.src_idx)[q.s[r]];
+    if (d.tgt_idx) q.t[r] = G(d.tgt_idx)[q.t[r]];
+    if (d.w_arr) q.w[r] = G(d.w_arr)[i0 + r];
+    if (d.d_ms_arr) q.d[r] = (int32_t)ms_to_steps(G(d.d_ms_arr)[i0 + r], d.h);
+  }
+}
+
 constexpr int kGenThreads = 256;
 
 template <int RULE, bool DRAND>
@@ -490,6 +532,7 @@ __global__ __launch_bounds__(kGenThreads) void k_generate(GenDesc d, const uint3
     Quad q;
     gen_quad<RULE, DRAND>(d, g, key0, key1, q);
     const uint32_t i0 = g << 2;
+    if (d.src_idx || d.tgt_idx || d.w_arr || d.d_ms_arr) apply_arrays(d, i0, q);
     store_quad(blocks, log2B, d.pos0 + i0, min(4u, d.n_new - i0), q);
   }
 }
@@ -1621,16 +1664,13 @@ __global__ __launch_bounds__(256) void k_spikes_push(SpikeState st, const uint32
 
 // ---------------------------------------------------------------------------
 // Node groups as index arrays and per-connection weights and delays
-// (Sec. 2.1): generation runs with the groups as position ranges from 0 and
-// constant weights / delays, then one pass maps positions through the arrays
-// and stores the per-connection values.
+// (Sec. 2.1): before a call changes anything, one pass finds the largest
+// source and target index, the largest delay (its fp32 bits, delays being
+// non-negative) and whether a delay is not finite.  Generation then runs with
+// the groups as position ranges from 0 and maps each synapse through the
+// arrays as it stores it.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float ms_to_steps(float ms, float h) {
-  const float steps = rintf(__fdiv_rn(ms, h));  // as the generation kernel's ms path
-  return steps < 1.0f ? 1.0f : steps;
-}
-
-__global__ __launch_bounds__(256) void k_check_arrays(CallArrays a, uint32_t* out) {
+__global__ __launch_bounds__(256) void k_check_arrays(CallArrays a, unsigned long long* out, uint32_t epoch) {
   constexpr int U = 8;  // independent loads in flight per thread and round
   uint32_t ms = 0, mt = 0, md = 0, bad = 0;
   const uint64_t n = max(max(a.ns, a.nt), a.n);
@@ -1674,25 +1714,11 @@ __global__ __launch_bounds__(256) void k_check_arrays(CallArrays a, uint32_t* ou
   if (threadIdx.x < 4) {
     uint32_t v = red[threadIdx.x][0];
     for (int w = 1; w < 4; ++w) v = threadIdx.x == 3 ? (v | red[3][w]) : max(v, red[threadIdx.x][w]);
-    if (threadIdx.x == 3) atomicOr(out + 3, v);
-    else atomicMax(out + threadIdx.x, v);
+    // the epoch in the high word: values left by earlier calls are smaller
+    atomicMax(out + threadIdx.x, ((unsigned long long)epoch << 32) | v);
   }
 }
 
-__global__ __launch_bounds__(256) void k_apply_arrays(CallArrays a, char* const* blocks, int log2B, uint64_t pos0) {
-  const uint64_t B = 1ull << log2B;
-  for (uint64_t j = blockIdx.x * 256ull + threadIdx.x; j < a.n; j += gridDim.x * 256ull) {
-    const uint64_t p = pos0 + j;
-    char* blk = G(blocks)[p >> log2B];
-    const uint64_t o = p & (B - 1);
-    NG_GLOBAL uint32_t* src = G(reinterpret_cast<uint32_t*>(blk));
-    NG_GLOBAL uint32_t* tgt = G(reinterpret_cast<uint32_t*>(blk + 4 * B));
-    if (a.src_idx) src[o] = G(a.src_idx)[src[o]];  // the generated value is a position < ns
-    if (a.tgt_idx) tgt[o] = G(a.tgt_idx)[tgt[o]];
-    if (a.w) G(reinterpret_cast<float*>(blk + 8 * B))[o] = G(a.w)[j];
-    if (a.d_ms) G(reinterpret_cast<int16_t*>(blk + 12 * B))[o] = (int16_t)ms_to_steps(G(a.d_ms)[j], a.h);
-  }
-}
 
 // ---------------------------------------------------------------------------
 // COPASS in-place block sort (Appendix A): the copies of left partitions to
@@ -2085,21 +2111,16 @@ hipError_t launch_spikes_step(const SpikeState& st, const uint32_t* nodes, const
   return e;
 }
 
-hipError_t launch_check_arrays(const CallArrays& a, uint32_t* out, hipStream_t s) {
+hipError_t launch_check_arrays(const CallArrays& a, uint64_t* out, uint32_t epoch, hipStream_t s) {
   const uint32_t n = std::max(std::max(a.ns, a.nt), a.n);
   if (n == 0) return hipSuccess;
   // each workgroup ends in one atomic per word; all of them share the four words
   const uint32_t grid = std::min<uint32_t>((n + 2047) / 2048, 512u);
-  hipLaunchKernelGGL(k_check_arrays, dim3(grid), dim3(256), 0, s, a, out);
+  hipLaunchKernelGGL(k_check_arrays, dim3(grid), dim3(256), 0, s, a, reinterpret_cast<unsigned long long*>(out),
+                     epoch);
   return hipGetLastError();
 }
 
-hipError_t launch_apply_arrays(const CallArrays& a, char* const* blocks, int log2B, uint64_t pos0, hipStream_t s) {
-  if (a.n == 0) return hipSuccess;
-  const uint32_t grid = std::min<uint32_t>((a.n + 255) / 256, 8192u);
-  hipLaunchKernelGGL(k_apply_arrays, dim3(grid), dim3(256), 0, s, a, blocks, log2B, pos0);
-  return hipGetLastError();
-}
 
 hipError_t launch_copass_copy(const BlockView& v, const CopyList& l, bool to_packed, uint32_t* keys, uint2* pay,
                               hipStream_t s) {

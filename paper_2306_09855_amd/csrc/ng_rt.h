@@ -21,6 +21,8 @@ namespace ngrt {
 int fail(int code, const char* fmt, ...);
 
 constexpr uint64_t kAlign = 256;
+constexpr uint64_t kScalarBytes = 128;  // a context's device words (ng_ctx::d_scalars)
+constexpr uint32_t kCheckWord = 16;     // d_scalars[16..23]: the array check's four u64 results
 
 // First-fit sub-allocator over the caller's arena (host bookkeeping only).
 // Thread-safe.  A context that owns its arena frees immediately (reuse is
@@ -195,7 +197,11 @@ struct ng_ctx {
   uint64_t spikes_bytes = 0;
   ng::SpikeState spikes{};
   uint32_t spike_step = 0;  // steps since ng_spikes_init (stamps the emitting nodes)
-  uint32_t* d_scalars = nullptr;  // [0] = G
+  // device words: [0] = G, [2] = spike error word, [4..5] = Philox key,
+  // [12] = spike-array entries, [16..23] = array check results (4 x u64)
+  uint32_t* d_scalars = nullptr;
+  uint32_t check_epoch = 0;       // ng_connect_groups calls checked so far (mod 2^32)
+  uint64_t* h_chk = nullptr;      // pinned copy of the array check results
   uint32_t gi_nodes = 0;          // n_nodes the index was built for
 
   int radix_bits = 9;  // widest digit: the fewest passes

@@ -311,6 +311,8 @@ int check_descs(const std::vector<ng::GenDesc>& descs) {
 void ctx_host_release(ng_ctx* c) {
   if (c->h_stage) (void)hipHostFree(c->h_stage);
   c->h_stage = nullptr;
+  if (c->h_chk) (void)hipHostFree(c->h_chk);
+  c->h_chk = nullptr;
   if (c->stage_done) (void)hipEventDestroy(c->stage_done);
   if (c->order_ev) (void)hipEventDestroy(c->order_ev);
   c->stage_done = c->order_ev = nullptr;
@@ -384,11 +386,11 @@ int ctx_init(const ng_config* cfg, Arena* shared, char* base, uint64_t bytes, hi
   }
   c->tab_cap = (uint32_t)std::min<uint64_t>(bytes / (ng::kBytesPerConn * B) + 2, 1u << 20);
   for (int t = 0; t < 2; ++t) c->d_tab[t] = (char**)ctx_alloc(c, 8ull * c->tab_cap);
-  c->d_scalars = (uint32_t*)ctx_alloc(c, 64);
+  c->d_scalars = (uint32_t*)ctx_alloc(c, kScalarBytes);
   if (!c->d_tab[0] || !c->d_tab[1] || !c->d_scalars) {
     for (int t = 0; t < 2; ++t)
       if (c->d_tab[t]) c->arena->release((char*)c->d_tab[t], 8ull * c->tab_cap);
-    if (c->d_scalars) c->arena->release((char*)c->d_scalars, 64);
+    if (c->d_scalars) c->arena->release((char*)c->d_scalars, kScalarBytes);
     delete c;
     return fail(NG_ERR_OOM, "arena too small");
   }
@@ -398,7 +400,7 @@ int ctx_init(const ng_config* cfg, Arena* shared, char* base, uint64_t bytes, hi
     delete c;
     return fail(NG_ERR_DEVICE, "hipEventCreate failed");
   }
-  if (ng::launch_fill_u32(c->d_scalars, 0u, 16, c->stream) != hipSuccess ||
+  if (ng::launch_fill_u32(c->d_scalars, 0u, kScalarBytes / 4, c->stream) != hipSuccess ||
       set_seed(c, c->cfg.seed) != hipSuccess) {
     ctx_host_release(c);
     delete c;
@@ -419,7 +421,7 @@ void ctx_destroy_release(ng_ctx* c) {
   c->blocks.clear();
   release_index(c);
   for (int t = 0; t < 2; ++t) ctx_free(c, (char*)c->d_tab[t], 8ull * c->tab_cap);
-  ctx_free(c, (char*)c->d_scalars, 64);
+  ctx_free(c, (char*)c->d_scalars, kScalarBytes);
   ctx_flush_frees(c);
   ctx_host_release(c);
   delete c;
@@ -1342,13 +1344,22 @@ int ng_connect_groups(ng_ctx* c, ng_group src, ng_group tgt, const ng_conn_spec*
   ca.d_ms = delays_ms;
   ca.n = (uint32_t)pl.n_new;
   ca.h = c->cfg.h_ms;
-  // the arrays are checked on the device before anything changes
-  uint32_t chk[4] = {0, 0, 0, 0};
-  uint32_t* d_chk = c->d_scalars + 8;
-  NG_LAUNCH(c, "fill", ng::launch_fill_u32(d_chk, 0u, 4, c->stream));
-  NG_LAUNCH(c, "check_arrays", ng::launch_check_arrays(ca, d_chk, c->stream));
-  NG_HIP(c, hipMemcpyAsync(chk, d_chk, sizeof(chk), hipMemcpyDeviceToHost, c->stream), "array check");
+  // the arrays are checked on the device before anything changes; the four
+  // results carry this call's epoch in their high words, so the maxima of
+  // earlier calls lose without a clearing pass (the words start at zero and
+  // are cleared again when the epoch wraps)
+  if (!c->h_chk) NG_HIP(c, hipHostMalloc((void**)&c->h_chk, 4 * sizeof(uint64_t), hipHostMallocDefault), "hipHostMalloc");
+  uint64_t* d_chk = reinterpret_cast<uint64_t*>(c->d_scalars + kCheckWord);
+  if (++c->check_epoch == 0) {
+    NG_LAUNCH(c, "fill", ng::launch_fill_u32(c->d_scalars + kCheckWord, 0u, 8, c->stream));
+    c->check_epoch = 1;
+  }
+  NG_LAUNCH(c, "check_arrays", ng::launch_check_arrays(ca, d_chk, c->check_epoch, c->stream));
+  NG_HIP(c, hipMemcpyAsync(c->h_chk, d_chk, 4 * sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream), "array check");
   NG_HIP(c, hipStreamSynchronize(c->stream), "array check");
+  uint32_t chk[4];
+  for (int w = 0; w < 4; ++w)  // no launch (no entries): no result of this epoch
+    chk[w] = (uint32_t)(c->h_chk[w] >> 32) == c->check_epoch ? (uint32_t)c->h_chk[w] : 0u;
   if (src.idx && src.n && chk[0] >= c->n_nodes)
     return fail(NG_ERR_INVALID_ARG, "source index %u is not below the %u created nodes", chk[0], c->n_nodes);
   if (tgt.idx && tgt.n && chk[1] >= c->n_nodes)
@@ -1365,10 +1376,12 @@ int ng_connect_groups(ng_ctx* c, ng_group src, ng_group tgt, const ng_conn_spec*
   uint64_t n = 0;
   if (int rc = connect_prepare_limit(c, 0xFFFFFFFFu, ps, pt, conn, &sy, &d, &n)) return rc;
   if (int rc = sync_table(c)) return rc;
-  if (n) {
-    NG_LAUNCH(c, "generate", ng::launch_generate(d, key_ptr(c), c->d_tab[c->cur], c->log2B, c->stream));
-    NG_LAUNCH(c, "apply_arrays", ng::launch_apply_arrays(ca, c->d_tab[c->cur], c->log2B, d.pos0, c->stream));
-  }
+  // generation maps each synapse through the arrays as it stores it
+  d.src_idx = src.idx;
+  d.tgt_idx = tgt.idx;
+  d.w_arr = weights;
+  d.d_ms_arr = delays_ms;
+  if (n) NG_LAUNCH(c, "generate", ng::launch_generate(d, key_ptr(c), c->d_tab[c->cur], c->log2B, c->stream));
   if (out_cid) *out_cid = d.cid;
   if (out_first) *out_first = d.pos0;
   if (out_n) *out_n = n;

@@ -89,6 +89,21 @@ def test_weight_and_delay_arrays(rule, ns, nt, k):
     _check(5, [(c, {"w_t": _dev(w, torch.float32), "d_t": _dev(d, torch.float32)})])
 
 
+def test_value_arrays_not_16_byte_aligned():
+    # views one element into a larger tensor: the per-connection values are read one by one
+    base = _call("fixed_indegree", 23, (0, 300), (300, 200))
+    n = oracle.count(base)
+    rng = np.random.default_rng(3)
+    w = rng.normal(0.0, 1.0, n).astype(np.float32)
+    d = (rng.random(n) * 4.0).astype(np.float32)
+    w_big = _dev(np.concatenate([[7.0], w]).astype(np.float32), torch.float32)
+    d_big = _dev(np.concatenate([[7.0], d]).astype(np.float32), torch.float32)
+    w_t, d_t = w_big[1:], d_big[1:]
+    assert w_t.data_ptr() % 16 != 0 and d_t.data_ptr() % 16 != 0
+    c = _call("fixed_indegree", 23, (0, 300), (300, 200), w_arr=w, d_arr=d)
+    _check(8, [(c, {"w_t": w_t, "d_t": d_t})])
+
+
 def test_array_calls_among_range_calls():
     rng = np.random.default_rng(9)
     sidx = rng.integers(0, N_NODES, 250).astype(np.uint32)
