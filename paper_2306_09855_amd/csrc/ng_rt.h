@@ -201,7 +201,8 @@ struct ng_ctx {
   // [12] = spike-array entries, [16..23] = array check results (4 x u64)
   uint32_t* d_scalars = nullptr;
   uint32_t check_epoch = 0;       // ng_connect_groups calls checked so far (mod 2^32)
-  uint64_t* h_chk = nullptr;      // pinned copy of the array check results
+  uint32_t* h_words = nullptr;    // pinned host words for small device-to-host reads
+  uint64_t h_words_cap = 0;       // words
   uint32_t gi_nodes = 0;          // n_nodes the index was built for
 
   int radix_bits = 9;  // widest digit: the fewest passes
@@ -315,6 +316,9 @@ int connect_prepare_limit(ng_ctx* c, uint32_t node_limit, ng_range src, ng_range
 // through the graph's own pinned region while capturing, else through the
 // context's pinned staging buffer (reused once its last upload completed).
 int stage_upload(ng_ctx* c, void* d_dst, const void* src, uint64_t bytes);
+// Pinned host buffer of at least n words for a device-to-host read that is
+// synchronized before the next one; null (with the error set) on failure.
+uint32_t* host_words(ng_ctx* c, uint64_t n);
 // Copies host bytes to device memory, stream-ordered on the given stream.
 using Uploader = std::function<int(hipStream_t, void* d_dst, const void* src, uint64_t bytes)>;
 // Calibrate n distinct contexts with one sequence of launches on the first

@@ -311,8 +311,9 @@ int check_descs(const std::vector<ng::GenDesc>& descs) {
 void ctx_host_release(ng_ctx* c) {
   if (c->h_stage) (void)hipHostFree(c->h_stage);
   c->h_stage = nullptr;
-  if (c->h_chk) (void)hipHostFree(c->h_chk);
-  c->h_chk = nullptr;
+  if (c->h_words) (void)hipHostFree(c->h_words);
+  c->h_words = nullptr;
+  c->h_words_cap = 0;
   if (c->stage_done) (void)hipEventDestroy(c->stage_done);
   if (c->order_ev) (void)hipEventDestroy(c->order_ev);
   c->stage_done = c->order_ev = nullptr;
@@ -451,6 +452,24 @@ int connect_prepare_limit(ng_ctx* c, uint32_t node_limit, ng_range src, ng_range
   *out = p.d;
   if (out_n) *out_n = p.n_new;
   return NG_OK;
+}
+
+// Pinned host words for the small results the host reads back (kept, and
+// grown when needed, until the context is released); every read is followed
+// by a stream synchronization before the next one.
+uint32_t* host_words(ng_ctx* c, uint64_t n) {
+  if (c->h_words_cap < n) {
+    if (c->h_words) (void)hipHostFree(c->h_words);
+    c->h_words = nullptr;
+    c->h_words_cap = 0;
+    if (hipHostMalloc((void**)&c->h_words, 4 * n, hipHostMallocDefault) != hipSuccess) {
+      c->h_words = nullptr;
+      fail(NG_ERR_DEVICE, "hipHostMalloc of %llu bytes failed", (unsigned long long)(4 * n));
+      return nullptr;
+    }
+    c->h_words_cap = n;
+  }
+  return c->h_words;
 }
 
 int stage_upload(ng_ctx* c, void* d_dst, const void* src, uint64_t bytes) {
@@ -744,9 +763,13 @@ int calibrate_copass(ng_ctx* c) {
         if (int rc = stage_upload(c, d_start, sl.data(), 8ull * k)) return rc;
         ng::CopassPart pp{view, d_start, d_len, k, m, d_lo, d_hi, d_mulo, d_muhi, d_mout, d_status};
         NG_LAUNCH(c, "copass_partition", ng::launch_copass_partition(pp, s));
-        NG_HIP(c, hipMemcpyAsync(mi.data(), d_mout, 4ull * k, hipMemcpyDeviceToHost, s), "partition sizes");
-        NG_HIP(c, hipMemcpyAsync(st.data(), d_status, 12, hipMemcpyDeviceToHost, s), "partition status");
+        uint32_t* h = host_words(c, (uint64_t)k + 3);
+        if (!h) return NG_ERR_DEVICE;
+        NG_HIP(c, hipMemcpyAsync(h, d_mout, 4ull * k, hipMemcpyDeviceToHost, s), "partition sizes");
+        NG_HIP(c, hipMemcpyAsync(h + k, d_status, 12, hipMemcpyDeviceToHost, s), "partition status");
         NG_HIP(c, hipStreamSynchronize(s), "partition");
+        std::copy(h, h + k, mi.begin());
+        std::copy(h + k, h + k + 3, st.begin());
         uint64_t sum = 0;
         bool bad = st[2] != 0 || (st[0] != 1 && st[0] != 2);
         for (uint32_t i = 0; i < k && !bad; ++i) {
@@ -1260,10 +1283,15 @@ static int connect_pairwise(ng_ctx* c, ng_range src, ng_range tgt, const ng_conn
     if (!bits) bits_bytes = 0;
     NG_LAUNCH(c, "pb_count", ng::launch_pb_count(d, key_ptr(c), counts, bits, c->stream));
     NG_LAUNCH(c, "scan", ng::launch_exclusive_scan(counts, counts, units, tmp, counts + units, c->stream));
-    uint32_t total = 0;
-    NG_HIP(c, hipMemcpyAsync(&total, counts + units, 4, hipMemcpyDeviceToHost, c->stream), "pair count");
+    uint32_t* h = host_words(c, 1);
+    if (!h) {  // the counting pass may still run: stream-ordered frees
+      ctx_free(c, (char*)counts, cbytes);
+      ctx_free(c, (char*)bits, bits_bytes);
+      return NG_ERR_DEVICE;
+    }
+    NG_HIP(c, hipMemcpyAsync(h, counts + units, 4, hipMemcpyDeviceToHost, c->stream), "pair count");
     NG_HIP(c, hipStreamSynchronize(c->stream), "pair count");
-    n = total;
+    n = h[0];
   }
   if (c->n_conns + n > 0xFFFFFFFFull) {
     ctx_unalloc(c, (char*)counts, cbytes);
@@ -1348,18 +1376,19 @@ int ng_connect_groups(ng_ctx* c, ng_group src, ng_group tgt, const ng_conn_spec*
   // results carry this call's epoch in their high words, so the maxima of
   // earlier calls lose without a clearing pass (the words start at zero and
   // are cleared again when the epoch wraps)
-  if (!c->h_chk) NG_HIP(c, hipHostMalloc((void**)&c->h_chk, 4 * sizeof(uint64_t), hipHostMallocDefault), "hipHostMalloc");
+  uint32_t* h = host_words(c, 8);
+  if (!h) return NG_ERR_DEVICE;
   uint64_t* d_chk = reinterpret_cast<uint64_t*>(c->d_scalars + kCheckWord);
   if (++c->check_epoch == 0) {
     NG_LAUNCH(c, "fill", ng::launch_fill_u32(c->d_scalars + kCheckWord, 0u, 8, c->stream));
     c->check_epoch = 1;
   }
   NG_LAUNCH(c, "check_arrays", ng::launch_check_arrays(ca, d_chk, c->check_epoch, c->stream));
-  NG_HIP(c, hipMemcpyAsync(c->h_chk, d_chk, 4 * sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream), "array check");
+  NG_HIP(c, hipMemcpyAsync(h, d_chk, 4 * sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream), "array check");
   NG_HIP(c, hipStreamSynchronize(c->stream), "array check");
   uint32_t chk[4];
-  for (int w = 0; w < 4; ++w)  // no launch (no entries): no result of this epoch
-    chk[w] = (uint32_t)(c->h_chk[w] >> 32) == c->check_epoch ? (uint32_t)c->h_chk[w] : 0u;
+  for (int w = 0; w < 4; ++w)  // (low, high) words; no launch (no entries): no result of this epoch
+    chk[w] = h[2 * w + 1] == c->check_epoch ? h[2 * w] : 0u;
   if (src.idx && src.n && chk[0] >= c->n_nodes)
     return fail(NG_ERR_INVALID_ARG, "source index %u is not below the %u created nodes", chk[0], c->n_nodes);
   if (tgt.idx && tgt.n && chk[1] >= c->n_nodes)
