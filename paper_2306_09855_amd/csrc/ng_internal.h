@@ -154,7 +154,7 @@ struct SpikeState {
   uint32_t *head, *count;         // [n_nodes]
   uint32_t* stamp;                // [n_nodes] last step a node emitted in
   uint2* entries;                 // [n_nodes * cap] spike array: (global group, multiplicity)
-  uint32_t* n_entries;            // entries of the current step
+  uint32_t* n_entries;            // [2]: entries of the steps of even and odd number
   uint32_t* err;                  // bit 1: a node emitted into a full queue; bit 2: a node index out of range
   int16_t* gdelay;                // [G] delay of each group
   const uint32_t* group_ptr;      // [n_nodes + 1]

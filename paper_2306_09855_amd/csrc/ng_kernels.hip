@@ -1568,9 +1568,13 @@ __global__ __launch_bounds__(256) void k_spikes_init(SpikeState st, uint64_t n_g
   }
 }
 
-__global__ __launch_bounds__(256) void k_spikes_advance(SpikeState st) {
+// The spike-array entries of step k are counted in n_entries[k & 1]; the
+// advance of step k clears the other word for step k + 1 (its last reader, the
+// delivery of step k - 1, has finished), so no launch clears the counter.
+__global__ __launch_bounds__(256) void k_spikes_advance(SpikeState st, uint32_t step) {
   const uint32_t i = blockIdx.x * 256 + threadIdx.x;
   const uint32_t lane = threadIdx.x & 63;
+  if (i == 0) G(st.n_entries)[(step + 1) & 1] = 0;
   uint32_t cnt = 0, h = 0, base = 0, gi = 0;
   if (i < st.n_nodes) {
     cnt = G(st.count)[i];
@@ -1596,7 +1600,7 @@ __global__ __launch_bounds__(256) void k_spikes_advance(SpikeState st) {
   }
   const uint32_t wave_total = __shfl(incl, 63);
   uint32_t first = 0;
-  if (lane == 63 && wave_total) first = atomicAdd(st.n_entries, wave_total);
+  if (lane == 63 && wave_total) first = atomicAdd(st.n_entries + (step & 1), wave_total);
   uint32_t pos = __shfl(first, 63) + incl - hits;
   for (uint32_t e = 0; e < cnt && hits; ++e) {
     const uint64_t sl = q0 + (h + e) % st.cap;
@@ -1617,10 +1621,10 @@ __global__ __launch_bounds__(256) void k_spikes_advance(SpikeState st) {
   }
 }
 
-__global__ __launch_bounds__(256) void k_spikes_deliver(SpikeState st, float* __restrict__ input) {
+__global__ __launch_bounds__(256) void k_spikes_deliver(SpikeState st, float* __restrict__ input, uint32_t step) {
   const uint64_t B = 1ull << st.log2B;
   const uint32_t lane = threadIdx.x & 63;
-  const uint32_t n_e = __builtin_amdgcn_readfirstlane(G(st.n_entries)[0]);
+  const uint32_t n_e = __builtin_amdgcn_readfirstlane(G(st.n_entries)[step & 1]);
   const uint32_t waves = gridDim.x * 4;
   for (uint32_t e = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6)); e < n_e; e += waves) {
     const uint2 en = ld_u32x2(st.entries + e);
@@ -2086,6 +2090,8 @@ hipError_t launch_pb_write(const GenDesc& d, const uint32_t* d_key, const uint32
 }
 
 hipError_t launch_spikes_init(const SpikeState& st, uint64_t n_groups, hipStream_t s) {
+  hipError_t e = launch_fill_u32(st.n_entries, 0u, 2, s);  // both step parities' entry counters
+  if (e != hipSuccess) return e;
   const uint64_t n = std::max<uint64_t>(st.n_nodes, n_groups);
   if (n == 0) return hipSuccess;
   const uint32_t grid = (uint32_t)std::min<uint64_t>((n + 255) / 256, 8192);
@@ -2095,12 +2101,11 @@ hipError_t launch_spikes_init(const SpikeState& st, uint64_t n_groups, hipStream
 
 hipError_t launch_spikes_step(const SpikeState& st, const uint32_t* nodes, const uint32_t* mult, uint32_t n,
                               float* input, uint32_t step, hipStream_t s) {
-  hipError_t e = launch_fill_u32(st.n_entries, 0u, 1, s);
-  if (e != hipSuccess) return e;
+  hipError_t e = hipSuccess;
   if (st.n_nodes) {
-    hipLaunchKernelGGL(k_spikes_advance, dim3((st.n_nodes + 255) / 256), dim3(256), 0, s, st);
+    hipLaunchKernelGGL(k_spikes_advance, dim3((st.n_nodes + 255) / 256), dim3(256), 0, s, st, step);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_spikes_deliver, dim3(2048), dim3(256), 0, s, st, input);
+    hipLaunchKernelGGL(k_spikes_deliver, dim3(2048), dim3(256), 0, s, st, input, step);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (n) {

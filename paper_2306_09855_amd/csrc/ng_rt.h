@@ -198,7 +198,8 @@ struct ng_ctx {
   ng::SpikeState spikes{};
   uint32_t spike_step = 0;  // steps since ng_spikes_init (stamps the emitting nodes)
   // device words: [0] = G, [2] = spike error word, [4..5] = Philox key,
-  // [12] = spike-array entries, [16..23] = array check results (4 x u64)
+  // [12..13] = spike-array entries (even, odd steps), [16..23] = array check
+  // results (4 x u64)
   uint32_t* d_scalars = nullptr;
   uint32_t check_epoch = 0;       // ng_connect_groups calls checked so far (mod 2^32)
   uint32_t* h_words = nullptr;    // pinned host words for small device-to-host reads
