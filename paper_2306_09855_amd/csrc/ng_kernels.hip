@@ -1630,8 +1630,12 @@ __global__ __launch_bounds__(256) void k_spikes_deliver(SpikeState st, float* __
     const uint2 en = ld_u32x2(st.entries + e);
     const uint32_t a = G(st.group_start)[en.x], b = G(st.group_start)[en.x + 1];
     const float m = (float)en.y;
+    // the group's connections are consecutive: the block of its first one is
+    // read once per entry, any other block only where the group reaches it
+    const uint32_t ba = a >> st.log2B;
+    const char* const blk_a = G(st.blocks)[ba];
     for (uint32_t j = a + lane; j < b; j += 64) {
-      const char* blk = G(st.blocks)[j >> st.log2B];
+      const char* blk = (j >> st.log2B) == ba ? blk_a : G(st.blocks)[j >> st.log2B];
       const uint64_t o = j & (B - 1);
       const uint32_t t = G(reinterpret_cast<const uint32_t*>(blk + 4 * B))[o];
       const float w = G(reinterpret_cast<const float*>(blk + 8 * B))[o];
