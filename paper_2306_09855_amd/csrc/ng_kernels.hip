@@ -1571,9 +1571,13 @@ __global__ __launch_bounds__(256) void k_spikes_init(SpikeState st, uint64_t n_g
 // The spike-array entries of step k are counted in n_entries[k & 1]; the
 // advance of step k clears the other word for step k + 1 (its last reader, the
 // delivery of step k - 1, has finished), so no launch clears the counter.
-__global__ __launch_bounds__(256) void k_spikes_advance(SpikeState st, uint32_t step) {
-  const uint32_t i = blockIdx.x * 256 + threadIdx.x;
-  const uint32_t lane = threadIdx.x & 63;
+constexpr int kAdvThreads = 1024;
+
+__global__ __launch_bounds__(kAdvThreads) void k_spikes_advance(SpikeState st, uint32_t step) {
+  constexpr uint32_t kFast = 4;  // queued spikes a node keeps in registers
+  __shared__ uint32_t s_wave[kAdvThreads / 64 + 1];
+  const uint32_t i = blockIdx.x * kAdvThreads + threadIdx.x;
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (i == 0) G(st.n_entries)[(step + 1) & 1] = 0;
   uint32_t cnt = 0, h = 0, base = 0, gi = 0;
   if (i < st.n_nodes) {
@@ -1583,37 +1587,89 @@ __global__ __launch_bounds__(256) void k_spikes_advance(SpikeState st, uint32_t 
     gi = G(st.group_ptr)[i + 1] - base;
   }
   const uint64_t q0 = (uint64_t)i * st.cap;
-  // time indices grow by one; count the spikes that reach their group's delay
-  uint32_t hits = 0;
-  for (uint32_t e = 0; e < cnt; ++e) {
-    const uint64_t sl = q0 + (h + e) % st.cap;
-    const uint32_t t = G(st.time)[sl] + 1;
-    G(st.time)[sl] = t;
-    if ((int32_t)t == G(st.gdelay)[base + G(st.group)[sl]]) ++hits;
+  // time indices grow by one; count the spikes that reach their group's delay.
+  // Up to kFast spikes (almost every node at biological rates) are read once
+  // and kept in registers; a longer queue is walked in global memory.
+  const bool fast = cnt <= kFast;
+  uint32_t sl[kFast], t[kFast], g[kFast];
+  uint32_t hit_mask = 0, hits = 0;
+  if (fast) {
+    uint32_t r = h;
+#pragma unroll
+    for (uint32_t e = 0; e < kFast; ++e) {
+      sl[e] = r;
+      r = r + 1 == st.cap ? 0 : r + 1;
+      t[e] = 0;
+      g[e] = 0;
+      if (e < cnt) {
+        t[e] = G(st.time)[q0 + sl[e]] + 1;
+        g[e] = G(st.group)[q0 + sl[e]];
+      }
+    }
+#pragma unroll
+    for (uint32_t e = 0; e < kFast; ++e)
+      if (e < cnt && (int32_t)t[e] == G(st.gdelay)[base + g[e]]) hit_mask |= 1u << e;
+    hits = (uint32_t)__popc(hit_mask);
+  } else {
+    for (uint32_t e = 0; e < cnt; ++e) {
+      const uint64_t q = q0 + (h + e) % st.cap;
+      const uint32_t tt = G(st.time)[q] + 1;
+      G(st.time)[q] = tt;
+      if ((int32_t)tt == G(st.gdelay)[base + G(st.group)[q]]) ++hits;
+    }
   }
-  // one counter update per wave
+  // one counter update per workgroup (the grid's updates of one word serialize)
   uint32_t incl = hits;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
     const uint32_t v = __shfl_up(incl, o);
     if (lane >= (uint32_t)o) incl += v;
   }
-  const uint32_t wave_total = __shfl(incl, 63);
-  uint32_t first = 0;
-  if (lane == 63 && wave_total) first = atomicAdd(st.n_entries + (step & 1), wave_total);
-  uint32_t pos = __shfl(first, 63) + incl - hits;
-  for (uint32_t e = 0; e < cnt && hits; ++e) {
-    const uint64_t sl = q0 + (h + e) % st.cap;
-    const uint32_t g = G(st.group)[sl];
-    if ((int32_t)G(st.time)[sl] == G(st.gdelay)[base + g]) {
-      st_u32x2(st.entries + pos++, base + g, G(st.mult)[sl]);
-      G(st.group)[sl] = g + 1;
+  if (lane == 63) s_wave[wave] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int w = 0; w < kAdvThreads / 64; ++w) {
+      const uint32_t c = s_wave[w];
+      s_wave[w] = run;
+      run += c;
     }
+    s_wave[kAdvThreads / 64] = run ? atomicAdd(st.n_entries + (step & 1), run) : 0u;
   }
-  // the oldest spikes finish first
-  while (cnt && G(st.group)[q0 + h] == gi) {
-    h = h + 1 == st.cap ? 0 : h + 1;
-    --cnt;
+  __syncthreads();
+  uint32_t pos = s_wave[kAdvThreads / 64] + s_wave[wave] + incl - hits;
+  if (fast) {
+#pragma unroll
+    for (uint32_t e = 0; e < kFast; ++e) {
+      if (e >= cnt) break;
+      const uint64_t q = q0 + sl[e];
+      G(st.time)[q] = t[e];
+      if ((hit_mask >> e) & 1u) {
+        st_u32x2(st.entries + pos++, base + g[e], G(st.mult)[q]);
+        G(st.group)[q] = ++g[e];
+      }
+    }
+    // the oldest spikes finish first (a node's spikes pass the same delays in
+    // emission order): drop the finished ones from the front
+    uint32_t fin = 0;
+#pragma unroll
+    for (uint32_t e = 0; e < kFast; ++e)
+      if (e < cnt && fin == e && g[e] == gi) ++fin;
+    if (fin) h = sl[fin - 1] + 1 == st.cap ? 0 : sl[fin - 1] + 1;
+    cnt -= fin;
+  } else {
+    for (uint32_t e = 0; e < cnt && hits; ++e) {
+      const uint64_t q = q0 + (h + e) % st.cap;
+      const uint32_t gg = G(st.group)[q];
+      if ((int32_t)G(st.time)[q] == G(st.gdelay)[base + gg]) {
+        st_u32x2(st.entries + pos++, base + gg, G(st.mult)[q]);
+        G(st.group)[q] = gg + 1;
+      }
+    }
+    while (cnt && G(st.group)[q0 + h] == gi) {
+      h = h + 1 == st.cap ? 0 : h + 1;
+      --cnt;
+    }
   }
   if (i < st.n_nodes) {
     G(st.head)[i] = h;
@@ -2107,7 +2163,8 @@ hipError_t launch_spikes_step(const SpikeState& st, const uint32_t* nodes, const
                               float* input, uint32_t step, hipStream_t s) {
   hipError_t e = hipSuccess;
   if (st.n_nodes) {
-    hipLaunchKernelGGL(k_spikes_advance, dim3((st.n_nodes + 255) / 256), dim3(256), 0, s, st, step);
+    hipLaunchKernelGGL(k_spikes_advance, dim3((st.n_nodes + kAdvThreads - 1) / kAdvThreads), dim3(kAdvThreads), 0, s,
+                       st, step);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_spikes_deliver, dim3(2048), dim3(256), 0, s, st, input, step);
     if ((e = hipGetLastError()) != hipSuccess) return e;
