@@ -90,6 +90,10 @@ def lib():
         L.ora_uniform_ms_delay.restype = i32
         L.ora_count_pairwise.argtypes = [u64, u32, P(_Call)]
         L.ora_count_pairwise.restype = ctypes.c_int64
+        L.ora_pairwise_row.argtypes = [u64, u32, P(_Call), u32, ctypes.c_void_p]
+        L.ora_pairwise_row.restype = ctypes.c_int64
+        L.ora_pairwise_values.argtypes = [u64, f32, u32, P(_Call), u64, P(f64), P(i32)]
+        L.ora_pairwise_values.restype = ctypes.c_int
         L.ora_count.argtypes = [P(_Call)]
         L.ora_count.restype = ctypes.c_int64
         L.ora_words_per_synapse.argtypes = [P(_Call)]
@@ -188,6 +192,25 @@ def count(call) -> int:
 def count_pairwise(seed: int, connect_id: int, call) -> int:
     """Connections of a call of any rule (pairwise_bernoulli's depend on the draws)."""
     return int(lib().ora_count_pairwise(seed, connect_id, ctypes.byref(to_struct(call))))
+
+
+def pairwise_row(seed: int, connect_id: int, call, a: int) -> np.ndarray:
+    """pairwise_bernoulli: the connecting target offsets of source offset a, ascending."""
+    st = to_struct(call)
+    out = np.empty(max(int(st.nt), 1), np.uint32)
+    n = int(lib().ora_pairwise_row(seed, connect_id, ctypes.byref(st), a, _ptr(out)))
+    if n < 0:
+        raise ValueError("bad pairwise_bernoulli call or row")
+    return out[:n].copy()
+
+
+def pairwise_values(seed: int, h: float, connect_id: int, call, j: int):
+    """pairwise_bernoulli: (weight, delay in steps) of connection j."""
+    w, d = ctypes.c_double(), ctypes.c_int32()
+    if lib().ora_pairwise_values(seed, h, connect_id, ctypes.byref(to_struct(call)), j, ctypes.byref(w),
+                                 ctypes.byref(d)):
+        raise ValueError("bad pairwise_bernoulli call")
+    return float(w.value), int(d.value)
 
 
 def words_per_synapse(call) -> int:

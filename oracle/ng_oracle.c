@@ -225,6 +225,16 @@ int64_t ora_count_pairwise(uint64_t seed, uint32_t cid, const ora_call* c) {
   return n;
 }
 
+/* pairwise_bernoulli, one row: the target offsets b of source offset a that
+ * connect, ascending (out holds nt entries); returns their number or -1 */
+int64_t ora_pairwise_row(uint64_t seed, uint32_t cid, const ora_call* c, uint32_t a, uint32_t* out) {
+  if (c->rule != ORA_PAIRWISE_BERNOULLI || !(c->p >= 0.0 && c->p <= 1.0) || a >= c->ns) return -1;
+  int64_t n = 0;
+  for (uint64_t b = 0; b < c->nt; b++)
+    if (pb_pair(seed, cid, c, a, b)) out[n++] = (uint32_t)b;
+  return n;
+}
+
 static int delay_is_random(const ora_call* c) { return c->d_arr == NULL && c->d_kind != ORA_CONST; }
 
 int ora_words_per_synapse(const ora_call* c) {
@@ -407,6 +417,14 @@ static int weight_and_delay(uint64_t seed, float h, uint32_t cid, const ora_call
       return -1;
   }
   return 0;
+}
+
+/* pairwise_bernoulli: weight and delay of connection j (they depend on j
+ * only: delay word j of stream 2, weight as synapse j of stream 1) */
+int ora_pairwise_values(uint64_t seed, float h, uint32_t cid, const ora_call* c, uint64_t j, double* w,
+                        int32_t* delay) {
+  if (c->rule != ORA_PAIRWISE_BERNOULLI) return -1;
+  return weight_and_delay(seed, h, cid, c, j, 2, j, w, delay);
 }
 
 int ora_connect(uint64_t seed, float h, uint32_t cid, const ora_call* c, uint32_t* src,

@@ -124,6 +124,12 @@ int32_t ora_uniform_ms_delay(uint32_t x, double lo, double hi, float h);
 int64_t ora_count(const ora_call* call);
 /* count of any rule; pairwise_bernoulli's depends on the seed and call id */
 int64_t ora_count_pairwise(uint64_t seed, uint32_t connect_id, const ora_call* call);
+/* pairwise_bernoulli, sampled checks of large calls: the connecting target
+ * offsets of source offset a, ascending, into out (nt entries; returns their
+ * number, -1 on a bad call), and the weight and delay of connection j */
+int64_t ora_pairwise_row(uint64_t seed, uint32_t connect_id, const ora_call* call, uint32_t a, uint32_t* out);
+int ora_pairwise_values(uint64_t seed, float h, uint32_t connect_id, const ora_call* call, uint64_t j,
+                        double* w, int32_t* delay);
 /* stream-0 words a synapse consumes */
 int ora_words_per_synapse(const ora_call* call);
 

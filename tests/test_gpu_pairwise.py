@@ -103,3 +103,54 @@ def test_pairwise_without_room_for_the_decisions():
         assert net.connect(call)[2] == n
         created = net.fetch()
     check_creation_order(created, ref, [call])
+
+
+def test_pairwise_full_size_sampled():
+    """The benchmark's call at full size (all 77,169 microcircuit nodes to the first 50,000,
+    p = 0.0777: 3.86e9 pairs, ~3.0e8 connections, blocks of 2^24, the bench's sort schedule):
+    sampled source rows against the oracle's row decisions, bit for bit, with their delays and
+    weights by connection index; after calibration, each sampled source's run is its creation
+    run stably sorted by delay and the group index marks the delay changes."""
+    from paper_2306_09855_amd import workloads as W
+    from paper_2306_09855_amd.network import arena_bytes_for
+    from parity import check_equal, check_weights
+
+    wl = W.microcircuit()
+    n_tgt, p, B = 50_000, 0.0777, 1 << 24
+    call = _pb(p, (0, wl.n_nodes), (0, n_tgt), w=("normal", 0.5, 0.05), d=("uniform_int", 1, 30))
+    arena = arena_bytes_for(int(wl.n_nodes * n_tgt * p * 1.01), wl.n_nodes, wl.max_delay, B, 9) + (64 << 20)
+    rng = np.random.default_rng(7)
+    rows = np.unique(np.concatenate([[0, 1, 12_345, 49_999, 50_000, wl.n_nodes - 1],
+                                     rng.integers(0, wl.n_nodes, 18)]))
+    with Network(wl.seed, wl.h, B, arena) as net:
+        net.tune(9, 1024)
+        net.create(wl.n_nodes)
+        cid, first, n = net.connect(call)
+        assert first == 0 and abs(n - wl.n_nodes * n_tgt * p) < 6 * np.sqrt(wl.n_nodes * n_tgt * p)
+        dev = net.fetch(device=True)
+        lo = torch.searchsorted(dev["src"], torch.from_numpy(rows.astype(np.int32)).cuda()).cpu().numpy()
+        hi = torch.searchsorted(dev["src"], torch.from_numpy(rows.astype(np.int32)).cuda(), right=True).cpu().numpy()
+        created = {}
+        for a, l, h in zip(rows, lo, hi):
+            want = oracle.pairwise_row(wl.seed, cid, call, int(a))
+            t = dev["tgt"][l:h].cpu().numpy()
+            check_equal(t, want, f"targets of source {a}")
+            w = dev["w"][l:h].cpu().numpy()
+            d = dev["delay"][l:h].cpu().numpy()
+            ref = [oracle.pairwise_values(wl.seed, wl.h, cid, call, int(j)) for j in range(l, h)]
+            check_equal(d, [r[1] for r in ref], f"delays of source {a}")
+            check_weights(w, np.array([r[0] for r in ref]), np.full(h - l, 0.5), f"weights of source {a}")
+            created[int(a)] = (t, w, d)
+        del dev
+        net.calibrate()
+        out = net.fetch(device=True)
+        gp, gs = net.group_index()
+        for a in rows:
+            t, w, d = created[int(a)]
+            l = int(torch.searchsorted(out["src"], torch.tensor([int(a)], dtype=torch.int32, device="cuda")).item())
+            order = np.argsort(d, kind="stable")  # the run of a, stably sorted by delay
+            check_equal(out["tgt"][l:l + t.size].cpu().numpy(), t[order], f"sorted targets of source {a}")
+            check_equal(out["delay"][l:l + t.size].cpu().numpy(), d[order], f"sorted delays of source {a}")
+            assert np.array_equal(out["w"][l:l + t.size].cpu().numpy(), w[order])
+            starts = l + np.concatenate([[0], np.nonzero(np.diff(d[order]))[0] + 1]) if t.size else np.zeros(0)
+            check_equal(gs[gp[a]:gp[a + 1]], starts, f"group starts of source {a}")

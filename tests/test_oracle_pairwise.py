@@ -63,3 +63,21 @@ def test_one_synapse_path_agrees():
     s, t, w, d = oracle.connect(4, 0.1, 3, c)
     for i in range(0, s.size, 7):
         assert oracle.synapse(4, 0.1, 3, c, i) == (int(s[i]), int(t[i]), float(w[i]), int(d[i]))
+
+
+@pytest.mark.parametrize("allow", [1, 0])
+def test_row_and_value_paths_agree(allow):
+    # the sampled-check helpers against the whole-call walk, and p = 1 / p = 0 rows in closed form
+    c = _call(0.15, allow=allow, src=(0, 60), tgt=(20, 70), d=("uniform", 0.1, 2.0))
+    s, t, w, d = oracle.connect(6, 0.1, 2, c)
+    for a in range(60):
+        run = np.nonzero(s == a)[0]
+        assert np.array_equal(oracle.pairwise_row(6, 2, c, a), (t[run] - 20).astype(np.uint32))
+    for j in range(0, s.size, 5):
+        assert oracle.pairwise_values(6, 0.1, 2, c, j) == (float(w[j]), int(d[j]))
+    full = oracle.pairwise_row(6, 2, _call(1.0, allow=allow, src=(0, 60), tgt=(20, 70)), 25)
+    want = np.arange(70, dtype=np.uint32)
+    if not allow:
+        want = want[want != 25 - 20]  # source 25 is target offset 5
+    assert np.array_equal(full, want)
+    assert oracle.pairwise_row(6, 2, _call(0.0, allow=allow, src=(0, 60), tgt=(20, 70)), 25).size == 0
