@@ -125,3 +125,57 @@ def test_full_size_copass_equals_radix(microcircuit_full):
         assert torch.equal(cp[k], out[k]), k
     assert torch.equal(cp["w"].view(torch.int32), out["w"].view(torch.int32))
     assert np.array_equal(gp2, gp) and np.array_equal(gs2, gs)
+
+
+def test_no_autapses_no_multapses_full_size():
+    """The microcircuit with allow_autapses = 0 and allow_multapses = 0 on all 64 calls, at
+    full size in the benchmark's configuration (blocks of 2^24, 9-bit widest digit, 1,024
+    ranges): sampled synapses of every call recomputed by the oracle one at a time; every
+    call's pairs distinct and none a self-pair; the calibrated arrays a stable sort of the
+    created ones."""
+    from types import SimpleNamespace
+
+    wl = W.microcircuit()
+    calls = []
+    for c in wl.calls:
+        nc = SimpleNamespace(rule=c.rule, src=c.src, tgt=c.tgt, k_or_n=c.k_or_n, weight=c.weight, delay=c.delay,
+                             allow_autapses=0, allow_multapses=0)
+        nc.n_syn = (lambda x: (lambda: oracle.count(x)))(nc)
+        calls.append(nc)
+    B = 1 << 24
+    net = Network(wl.seed, wl.h, B, arena_bytes_for(wl.n_syn, wl.n_nodes, wl.max_delay, B, 9))
+    try:
+        net.tune(9, 1024)
+        for n in wl.populations:
+            net.create(n)
+        firsts = [net.connect(c)[1] for c in calls]
+        created = net.fetch(device=True)
+        rng = np.random.default_rng(11)
+        picks = []
+        for ci, c in enumerate(calls):
+            n = c.n_syn()
+            picks += [(ci, 0), (ci, n - 1)] + [(ci, int(i)) for i in rng.integers(0, n, 40)]
+        pos = np.array([firsts[ci] + i for ci, i in picks], dtype=np.int64)
+        ref = np.array([oracle.synapse(wl.seed, wl.h, ci, calls[ci], i) for ci, i in picks], dtype=object)
+        idx = torch.from_numpy(pos).cuda()
+        check_equal(created["src"][idx].cpu().numpy().view(np.uint32), ref[:, 0].astype(np.int64), "src")
+        check_equal(created["tgt"][idx].cpu().numpy().view(np.uint32), ref[:, 1].astype(np.int64), "tgt")
+        check_equal(created["delay"][idx].cpu().numpy(), ref[:, 3].astype(np.int64), "delay")
+        base = np.array([calls[ci].weight[1] for ci, _ in picks])
+        check_weights(created["w"][idx].cpu().numpy(), ref[:, 2].astype(np.float64), base, "w")
+        src = created["src"].to(torch.int64)
+        tgt = created["tgt"].to(torch.int64)
+        assert bool((src != tgt).all())
+        for ci, c in enumerate(calls):
+            a, b = firsts[ci], firsts[ci] + c.n_syn()
+            pairs = src[a:b] * wl.n_nodes + tgt[a:b]
+            assert torch.unique(pairs).numel() == b - a, f"call {ci}: a repeated pair"
+        key = src * 65536 + created["delay"].to(torch.int64)  # delays are below 2^15
+        order = torch.sort(key, stable=True).indices
+        net.calibrate()
+        out = net.fetch(device=True)
+        for name in ("src", "tgt", "w", "delay"):
+            assert torch.equal(out[name], created[name][order]), f"sorted {name}"
+    finally:
+        net.close()
+        torch.cuda.empty_cache()
