@@ -319,8 +319,8 @@ def copass_bench(wl, block_size: int, steps: int, warmup: int, radix_bits: int, 
 def arrays_bench(wl, block_size: int, steps: int, warmup: int, radix_bits: int, sort_ranges: int) -> dict:
     """The same build with every call's source group given as an index array
     (a random permutation of its population) and per-connection weights and
-    delays (ng_connect_groups): time per step and the bandwidth of the pass
-    that applies the arrays."""
+    delays (ng_connect_groups): time per step and the bandwidth of the
+    generation that maps each synapse through the arrays."""
     import numpy as np
     import torch
     from paper_2306_09855_amd import ng

@@ -179,3 +179,56 @@ def test_no_autapses_no_multapses_full_size():
     finally:
         net.close()
         torch.cuda.empty_cache()
+
+
+def test_node_and_value_arrays_full_size():
+    """The benchmark's arrays build at full size: every call's source group an index array (a
+    random permutation of its population), weights and delays (ms) per connection from device
+    arrays, blocks of 2^24; sampled synapses of every call recomputed by the oracle with the
+    same arrays; the calibrated arrays a stable sort of the created ones."""
+    from types import SimpleNamespace
+
+    wl = W.microcircuit()
+    rng = np.random.default_rng(5)
+    B = 1 << 24
+    net = Network(wl.seed, wl.h, B, arena_bytes_for(wl.n_syn, wl.n_nodes, wl.max_delay, B, 9))
+    try:
+        net.tune(9, 1024)
+        for n in wl.populations:
+            net.create(n)
+        calls, firsts, keep = [], [], []
+        for c in wl.calls:
+            s0, ns = c.src
+            nc = SimpleNamespace(rule=c.rule, src=(0, ns), tgt=c.tgt, k_or_n=c.k_or_n, weight=c.weight,
+                                 delay=c.delay)
+            n = oracle.count(nc)
+            nc.src_idx = (s0 + rng.permutation(ns)).astype(np.uint32)
+            nc.w_arr = rng.normal(0.5, 0.05, n).astype(np.float32)
+            nc.d_arr = (rng.random(n) * 3.0).astype(np.float32)  # 1..30 steps at h = 0.1 ms
+            dev = [torch.from_numpy(a.view(np.int32) if a.dtype == np.uint32 else a).cuda()
+                   for a in (nc.src_idx, nc.w_arr, nc.d_arr)]
+            keep.append(dev)  # valid until the generation has run
+            firsts.append(net.connect_groups(nc, dev[0], c.tgt, dev[1], dev[2])[1])
+            calls.append(nc)
+        torch.cuda.synchronize()
+        created = net.fetch(device=True)
+        picks = []
+        for ci, c in enumerate(calls):
+            n = c.w_arr.size
+            picks += [(ci, 0), (ci, n - 1)] + [(ci, int(i)) for i in rng.integers(0, n, 40)]
+        pos = np.array([firsts[ci] + i for ci, i in picks], dtype=np.int64)
+        ref = np.array([oracle.synapse(wl.seed, wl.h, ci, calls[ci], i) for ci, i in picks], dtype=object)
+        idx = torch.from_numpy(pos).cuda()
+        check_equal(created["src"][idx].cpu().numpy().view(np.uint32), ref[:, 0].astype(np.int64), "src")
+        check_equal(created["tgt"][idx].cpu().numpy().view(np.uint32), ref[:, 1].astype(np.int64), "tgt")
+        check_equal(created["delay"][idx].cpu().numpy(), ref[:, 3].astype(np.int64), "delay")
+        assert np.array_equal(created["w"][idx].cpu().numpy().astype(np.float64), ref[:, 2].astype(np.float64))
+        key = created["src"].to(torch.int64) * 65536 + created["delay"].to(torch.int64)  # delays below 2^15
+        order = torch.sort(key, stable=True).indices
+        net.calibrate()
+        out = net.fetch(device=True)
+        for name in ("src", "tgt", "w", "delay"):
+            assert torch.equal(out[name], created[name][order]), f"sorted {name}"
+    finally:
+        net.close()
+        torch.cuda.empty_cache()
