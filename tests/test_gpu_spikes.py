@@ -116,3 +116,48 @@ def test_spike_errors_and_lifetime():
         with pytest.raises(ng.NGError) as e:
             net.spikes_step(None, inp)
         assert e.value.status == ng.NG_ERR_STATE
+
+
+def test_delivery_full_size_conservation():
+    """The calibrated 3.0e8-synapse microcircuit (the benchmark's build): 60 steps of random
+    spikes with multiplicities, then enough silent steps for every queued spike to reach its
+    last group.  Property that holds at any size (the oracle cannot rebuild 3e8 synapses in
+    test time; the build itself is checked against it by the full-size tests): each target's
+    accumulated input equals the sum over its connections of weight x the multiplicity its
+    source emitted, evaluated in fp64 with plain tensor ops; the bound covers fp32 atomic
+    accumulation (one rounding per add and per product)."""
+    wl = W.microcircuit()
+    N = wl.n_nodes
+    with Network(wl.seed, wl.h, 0, arena_bytes_for(wl.n_syn, N, wl.max_delay)) as net:
+        net.build(wl)
+        net.spikes_init()
+        rng = np.random.default_rng(9)
+        inp = torch.zeros(N, dtype=torch.float32, device="cuda")
+        emitted = np.zeros(N, np.float64)  # total multiplicity per node
+        events = np.zeros(N, np.float64)   # steps in which the node emitted
+        for s in range(60 + wl.max_delay + 2):
+            if s < 60:
+                nodes = np.nonzero(rng.random(N) < 0.01)[0]
+                mult = rng.integers(1, 4, nodes.size)
+                emitted[nodes] += mult
+                events[nodes] += 1
+                net.spikes_step(torch.from_numpy(nodes.astype(np.int32)).cuda(), inp,
+                                torch.from_numpy(mult.astype(np.int32)).cuda())
+            else:
+                net.spikes_step(None, inp)
+        ng.ng_sync(net.ctx)
+        out = net.fetch(device=True)
+        src, tgt = out["src"].long(), out["tgt"].long()
+        c = torch.from_numpy(emitted).cuda()[src]
+        terms = out["w"].double() * c
+        want = torch.zeros(N, dtype=torch.float64, device="cuda").index_add_(0, tgt, terms)
+        mag = torch.zeros(N, dtype=torch.float64, device="cuda").index_add_(0, tgt, terms.abs())
+        # one fp32 add per connection and emission, each rounding the sum, and one rounding of
+        # each weight x multiplicity product
+        adds = torch.zeros(N, dtype=torch.float64, device="cuda").index_add_(
+            0, tgt, torch.from_numpy(events).cuda()[src])
+        tol = (2 * adds + 1) * 2.0 ** -24 * mag + 1e-30
+        err = (inp.double() - want).abs()
+        assert float(mag.sum()) > 0
+        bad = torch.nonzero(err > tol)
+        assert bad.numel() == 0, f"{bad.numel()} targets outside the bound; first {int(bad[0])}"
