@@ -646,6 +646,9 @@ int calibrate_copass(ng_ctx* c) {
   for (int p = 0; p < P; ++p) maxbits = std::max(maxbits, g.nbits[p]);
   const uint64_t counts_n = ((uint64_t)1 << maxbits) * max_ranges;
   const uint64_t seg_cap = 5ull * k + 8;  // copy pieces of one step
+  // the partition results are read back through pinned words: had before
+  // anything moves, so that failing to get them changes nothing
+  if (k > 1 && !host_words(c, (uint64_t)k + 3)) return NG_ERR_DEVICE;
 
   AllocSet as(c);
   uint32_t* aux_k = (uint32_t*)as.get(4 * A);
@@ -763,8 +766,7 @@ int calibrate_copass(ng_ctx* c) {
         if (int rc = stage_upload(c, d_start, sl.data(), 8ull * k)) return rc;
         ng::CopassPart pp{view, d_start, d_len, k, m, d_lo, d_hi, d_mulo, d_muhi, d_mout, d_status};
         NG_LAUNCH(c, "copass_partition", ng::launch_copass_partition(pp, s));
-        uint32_t* h = host_words(c, (uint64_t)k + 3);
-        if (!h) return NG_ERR_DEVICE;
+        uint32_t* h = c->h_words;  // k + 3 words, held since the calibration began
         NG_HIP(c, hipMemcpyAsync(h, d_mout, 4ull * k, hipMemcpyDeviceToHost, s), "partition sizes");
         NG_HIP(c, hipMemcpyAsync(h + k, d_status, 12, hipMemcpyDeviceToHost, s), "partition status");
         NG_HIP(c, hipStreamSynchronize(s), "partition");
@@ -1267,6 +1269,8 @@ static int connect_pairwise(ng_ctx* c, ng_range src, ng_range tgt, const ng_conn
   uint64_t cbytes = 0, bits_bytes = 0;
   uint16_t* bits = nullptr;
   if (units) {
+    // the count is read back through pinned words: had before any launch
+    if (!host_words(c, 1)) return NG_ERR_DEVICE;
     cbytes = 4 * (units + 1);
     const uint64_t tbytes = 4 * ng::scan_tmp_words(units);
     counts = (uint32_t*)ctx_alloc(c, cbytes + tbytes);
@@ -1283,12 +1287,7 @@ static int connect_pairwise(ng_ctx* c, ng_range src, ng_range tgt, const ng_conn
     if (!bits) bits_bytes = 0;
     NG_LAUNCH(c, "pb_count", ng::launch_pb_count(d, key_ptr(c), counts, bits, c->stream));
     NG_LAUNCH(c, "scan", ng::launch_exclusive_scan(counts, counts, units, tmp, counts + units, c->stream));
-    uint32_t* h = host_words(c, 1);
-    if (!h) {  // the counting pass may still run: stream-ordered frees
-      ctx_free(c, (char*)counts, cbytes);
-      ctx_free(c, (char*)bits, bits_bytes);
-      return NG_ERR_DEVICE;
-    }
+    uint32_t* h = c->h_words;  // held since before the counting pass
     NG_HIP(c, hipMemcpyAsync(h, counts + units, 4, hipMemcpyDeviceToHost, c->stream), "pair count");
     NG_HIP(c, hipStreamSynchronize(c->stream), "pair count");
     n = h[0];
