@@ -88,6 +88,7 @@ __device__ __forceinline__ void perm_keys(PermKeys& p, uint32_t u, uint32_t cid,
   philox10(u, 0u, cid, 131072u, key0, key1, p.k);
 }
 
+// x must be below m (the walk from x returns below m only then).
 __device__ __forceinline__ uint64_t permute_below(uint64_t x, uint64_t m, const PermKeys& p) {
   const int n = m <= 4 ? 2 : 64 - __clzll((long long)(m - 1));
   const int na = n >> 1, nb = n - na;
@@ -200,7 +201,10 @@ __device__ __forceinline__ void gen_quad(const GenDesc& d, uint32_t g, uint32_t 
         q.t[r] = d.t0 + b;
       } else {
         // pair index in all_to_all order (without the self-pairs when prohibited)
-        const uint64_t k = permute_below(i, d.n_pairs, pk);
+        // a lane past the call's end (its result is not stored) walks from 0:
+        // the walk from x ends only for x below n_pairs, and i may not be
+        // when the call takes nearly every pair
+        const uint64_t k = permute_below(i < d.n_new ? i : 0u, d.n_pairs, pk);
         uint64_t a, b;
         if (!d.no_self) {
           a = k / d.nt;

@@ -39,6 +39,11 @@ CASES = {
     "total": [_call("fixed_total_number", (0, 300), (300, 200), 40_000)],
     "total_all_pairs_no_autapses": [_call("fixed_total_number", (0, 40), (20, 40), 40 * 40 - 20, autapses=0)],
     "total_wide_pair_space": [_call("fixed_total_number", (0, 100_000), (0, 60_000), 50_000)],  # 6e9 pairs
+    # every pair, or all but one, with a count that is not a multiple of 4: the lanes past the
+    # call's end must not walk from an index outside the pair space
+    "total_all_pairs_ragged": [_call("fixed_total_number", (0, 7), (100, 9), 63)],
+    "total_all_but_one_ragged": [_call("fixed_total_number", (0, 7), (100, 9), 62)],
+    "total_all_pairs_no_autapses_ragged": [_call("fixed_total_number", (0, 7), (3, 9), 59, autapses=0)],
 }
 
 
