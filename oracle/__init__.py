@@ -36,7 +36,7 @@ KINDS = {"const": 0, "normal": 1, "uniform_int": 2, "uniform": 3}
 def build() -> str:
     """Compile the oracle with gcc (contraction off so fp32 steps are exact IEEE ops)."""
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
-           "-fno-fast-math", "-Wall", "-o", _LIB + ".tmp", _SRC, "-lm"]
+           "-fno-fast-math", "-fopenmp", "-Wall", "-o", _LIB + ".tmp", _SRC, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(_LIB + ".tmp", _LIB)
     return _LIB
@@ -70,6 +70,12 @@ def lib():
         u32, u64, i32, f32, f64 = (ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32,
                                    ctypes.c_float, ctypes.c_double)
         P = ctypes.POINTER
+        L.ora_set_threads.argtypes = [ctypes.c_int]
+        L.ora_set_threads.restype = None
+        L.ora_get_threads.argtypes = []
+        L.ora_get_threads.restype = ctypes.c_int
+        L.ora_lowbias32.argtypes = [u32]
+        L.ora_lowbias32.restype = u32
         L.ora_philox4x32_10.argtypes = [P(u32), P(u32), P(u32)]
         L.ora_philox4x32_10.restype = None
         L.ora_word.argtypes = [u64, u32, u32, u64]
@@ -146,6 +152,32 @@ def to_struct(call) -> _Call:
     return st
 
 
+def set_threads(n: int) -> None:
+    """Threads of the generation and calibration loops: 1 is the single-thread
+    reference mode, n > 1 the timed mode (the same bytes)."""
+    lib().ora_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(lib().ora_get_threads())
+
+
+class threads:
+    """Context manager: run the enclosed oracle calls with n threads."""
+
+    def __init__(self, n: int):
+        self.n = int(n)
+
+    def __enter__(self):
+        self.prev = get_threads()
+        set_threads(self.n)
+        return self
+
+    def __exit__(self, *exc):
+        set_threads(self.prev)
+        return False
+
+
 # --- elementary pieces --------------------------------------------------------
 def philox(ctr, key):
     c = (ctypes.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
@@ -153,6 +185,10 @@ def philox(ctr, key):
     o = (ctypes.c_uint32 * 4)()
     lib().ora_philox4x32_10(c, k, o)
     return [int(v) for v in o]
+
+
+def lowbias32(x: int) -> int:
+    return int(lib().ora_lowbias32(int(x) & 0xFFFFFFFF))
 
 
 def word(seed: int, c: int, s: int, q: int) -> int:

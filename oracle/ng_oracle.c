@@ -11,6 +11,17 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads of the timed mode (1 = the single-thread reference mode).  Each
+ * synapse is a function of (seed, call, index) alone and the calibration
+ * order is total, so every thread count gives the same bytes. */
+static int g_threads = 1;
+
+void ora_set_threads(int n) { g_threads = n < 1 ? 1 : n; }
+int ora_get_threads(void) { return g_threads; }
 
 /* ---------------------------------------------------------------------- */
 /* Philox4x32-10, Salmon et al. SC'11: 10 rounds of the S-box built from    */
@@ -121,7 +132,9 @@ static int no_self(const ora_call* c) { return !c->allow_autapses && !c->src_idx
  * lowbias32 the integer hash of C. Wellons ("Prospecting for Hash
  * Functions", 2018) and k_0..k_3 the words of Philox(ctr = (u, 0, cid,
  * 131072)). */
-static uint32_t lowbias32(uint32_t x) {
+uint32_t ora_lowbias32(uint32_t x);
+static uint32_t lowbias32(uint32_t x) { return ora_lowbias32(x); }
+uint32_t ora_lowbias32(uint32_t x) {
   x ^= x >> 16;
   x *= 0x7feb352du;
   x ^= x >> 15;
@@ -140,7 +153,10 @@ static uint64_t feistel(const uint32_t k[4], int na, int nb, uint64_t x) {
   return (left << nb) | right;
 }
 
-static uint64_t permute(uint64_t seed, uint32_t cid, uint32_t u, uint64_t m, uint64_t x) {
+/* The walk from x ends only for x < m (x's cycle then returns below m):
+ * x >= m is a caller's error and gives -1. */
+static int permute(uint64_t seed, uint32_t cid, uint32_t u, uint64_t m, uint64_t x, uint64_t* out) {
+  if (x >= m) return -1;
   int n = 2;
   while (n < 64 && (1ull << n) < m) n++;
   const int na = n / 2, nb = n - na;
@@ -148,7 +164,8 @@ static uint64_t permute(uint64_t seed, uint32_t cid, uint32_t u, uint64_t m, uin
   ora_philox4x32_10(ctr, key, k);
   uint64_t y = feistel(k, na, nb, x);
   while (y >= m) y = feistel(k, na, nb, y);
-  return y;
+  *out = y;
+  return 0;
 }
 
 static int no_multi(const ora_call* c) { return !c->allow_multapses; }
@@ -273,7 +290,7 @@ int ora_synapse(uint64_t seed, float h, uint32_t cid, const ora_call* c, uint64_
     t_off = i / k;
     const uint64_t t = c->t0 + t_off;
     const int in_s = no_self(c) && t >= c->s0 && t < (uint64_t)c->s0 + c->ns;
-    s_off = permute(seed, cid, (uint32_t)t, c->ns - (in_s ? 1 : 0), i % k);
+    if (permute(seed, cid, (uint32_t)t, c->ns - (in_s ? 1 : 0), i % k, &s_off)) return -1;
     if (in_s && s_off >= t - c->s0) s_off++;
     *src = c->s0 + (uint32_t)s_off;
     *tgt = (uint32_t)t;
@@ -283,7 +300,7 @@ int ora_synapse(uint64_t seed, float h, uint32_t cid, const ora_call* c, uint64_
     s_off = i / k;
     const uint64_t s = c->s0 + s_off;
     const int in_t = no_self(c) && s >= c->t0 && s < (uint64_t)c->t0 + c->nt;
-    t_off = permute(seed, cid, (uint32_t)s, c->nt - (in_t ? 1 : 0), i % k);
+    if (permute(seed, cid, (uint32_t)s, c->nt - (in_t ? 1 : 0), i % k, &t_off)) return -1;
     if (in_t && t_off >= s - c->t0) t_off++;
     *src = (uint32_t)s;
     *tgt = c->t0 + (uint32_t)t_off;
@@ -291,7 +308,9 @@ int ora_synapse(uint64_t seed, float h, uint32_t cid, const ora_call* c, uint64_
   }
   if (no_multi(c) && c->rule == ORA_FIXED_TOTAL_NUMBER) {
     const uint64_t pairs = (uint64_t)c->ns * c->nt - (no_self(c) ? overlap(c) : 0);
-    a2a_pair(c, permute(seed, cid, 0, pairs, i), &s_off, &t_off);
+    uint64_t pair;
+    if (permute(seed, cid, 0, pairs, i, &pair)) return -1;
+    a2a_pair(c, pair, &s_off, &t_off);
     *src = c->s0 + (uint32_t)s_off;
     *tgt = c->t0 + (uint32_t)t_off;
     return weight_and_delay(seed, h, cid, c, i, 0, q, w, delay);
@@ -444,10 +463,11 @@ int ora_connect(uint64_t seed, float h, uint32_t cid, const ora_call* c, uint32_
   }
   int64_t n = ora_count(c);
   if (n < 0) return -1;
+  int bad = 0;
+#pragma omp parallel for num_threads(g_threads) schedule(static) reduction(| : bad) if (g_threads > 1)
   for (int64_t i = 0; i < n; i++)
-    if (ora_synapse(seed, h, cid, c, (uint64_t)i, &src[i], &tgt[i], &w[i], &delay[i]) != 0)
-      return -1;
-  return 0;
+    if (ora_synapse(seed, h, cid, c, (uint64_t)i, &src[i], &tgt[i], &w[i], &delay[i]) != 0) bad = 1;
+  return bad ? -1 : 0;
 }
 
 /* ---------------------------------------------------------------------- */
@@ -470,6 +490,91 @@ static int cmp_item(const void* a, const void* b) {
   return 0;
 }
 
+/* bucket of x among the sorted splitters: how many of them precede x */
+static uint32_t bucket_of(const sort_item* spl, uint32_t nspl, const sort_item* x) {
+  uint32_t lo = 0, hi = nspl;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (cmp_item(&spl[mid], x) < 0) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+/* Sorts *items by the total order of cmp_item.  One thread: qsort.  Timed
+ * mode: a sample sort -- splitters from a regular sample, every thread counts
+ * and then moves its share of the items into the buckets, each bucket is
+ * sorted with qsort.  Both give the one sorted sequence (the order is
+ * total).  *items may be replaced by a new array.  Returns 0 or -1. */
+static int sort_items(sort_item** pitems, uint64_t n) {
+  sort_item* items = *pitems;
+  const int T = g_threads;
+  if (T <= 1 || n < (1u << 16)) {
+    qsort(items, n, sizeof(sort_item), cmp_item);
+    return 0;
+  }
+  const uint32_t nb = 8u * (uint32_t)T, nspl = nb - 1, ns = 64u * nb;
+  sort_item* sample = (sort_item*)malloc(ns * sizeof(sort_item));
+  sort_item* out = (sort_item*)malloc(n * sizeof(sort_item));
+  uint64_t* counts = (uint64_t*)calloc((size_t)T * nb, sizeof(uint64_t));
+  uint64_t* bstart = (uint64_t*)malloc((nb + 1) * sizeof(uint64_t));
+  if (!sample || !out || !counts || !bstart) {
+    free(sample);
+    free(out);
+    free(counts);
+    free(bstart);
+    return -1;
+  }
+  for (uint32_t k = 0; k < ns; k++) sample[k] = items[(uint64_t)k * n / ns];
+  qsort(sample, ns, sizeof(sort_item), cmp_item);
+  sort_item* spl = (sort_item*)malloc(nspl * sizeof(sort_item));
+  if (!spl) {
+    free(sample);
+    free(out);
+    free(counts);
+    free(bstart);
+    return -1;
+  }
+  for (uint32_t b = 0; b < nspl; b++) spl[b] = sample[(uint64_t)(b + 1) * ns / nb];
+  free(sample);
+#pragma omp parallel num_threads(T)
+  {
+#ifdef _OPENMP
+    const int t = omp_get_thread_num();
+#else
+    const int t = 0;
+#endif
+    const uint64_t lo = (uint64_t)t * n / T, hi = (uint64_t)(t + 1) * n / T;
+    uint64_t* cnt = counts + (size_t)t * nb;
+    for (uint64_t j = lo; j < hi; j++) cnt[bucket_of(spl, nspl, &items[j])]++;
+#pragma omp barrier
+#pragma omp single
+    {
+      uint64_t acc = 0;
+      for (uint32_t b = 0; b < nb; b++) {
+        bstart[b] = acc;
+        for (int u = 0; u < T; u++) {
+          const uint64_t c = counts[(size_t)u * nb + b];
+          counts[(size_t)u * nb + b] = acc;
+          acc += c;
+        }
+      }
+      bstart[nb] = acc;
+    }
+    for (uint64_t j = lo; j < hi; j++) out[cnt[bucket_of(spl, nspl, &items[j])]++] = items[j];
+#pragma omp barrier
+#pragma omp for schedule(dynamic, 1)
+    for (uint32_t b = 0; b < nb; b++)
+      qsort(out + bstart[b], bstart[b + 1] - bstart[b], sizeof(sort_item), cmp_item);
+  }
+  free(spl);
+  free(counts);
+  free(bstart);
+  free(items);
+  *pitems = out;
+  return 0;
+}
+
 int ora_calibrate(uint64_t n, uint32_t n_nodes, const uint32_t* src, const int32_t* delay,
                   uint64_t* perm, uint32_t* group_ptr, uint32_t* group_start,
                   uint64_t* n_groups) {
@@ -483,7 +588,10 @@ int ora_calibrate(uint64_t n, uint32_t n_nodes, const uint32_t* src, const int32
     items[j].delay = delay[j];
     items[j].idx = j;
   }
-  qsort(items, n, sizeof(sort_item), cmp_item);
+  if (sort_items(&items, n) != 0) {
+    free(items);
+    return -1;
+  }
   for (uint64_t j = 0; j < n; j++) perm[j] = items[j].idx;
 
   /* A connection starts a group when its source or its delay differs from

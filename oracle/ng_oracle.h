@@ -103,6 +103,17 @@ typedef struct {
   int32_t allow_multapses;
 } ora_call;
 
+/* Threads of the generation and calibration loops.  1 (the default) is the
+ * single-thread reference mode; n > 1 is the timed mode (OpenMP over
+ * synapse indices, a sample sort for calibration), which gives the same
+ * bytes. */
+void ora_set_threads(int n);
+int ora_get_threads(void);
+
+/* the 32-bit integer hash "lowbias32" of C. Wellons (2018), used by the
+ * permutation of the multapse-free draws */
+uint32_t ora_lowbias32(uint32_t x);
+
 /* Philox4x32-10 block function */
 void ora_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 /* word q of stream s of connect call c */

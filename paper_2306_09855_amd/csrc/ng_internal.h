@@ -44,6 +44,7 @@ struct GenDesc {
   uint64_t group0;   // batched form: index of this call's first 4-synapse group
   char* const* blocks;        // batched form: block table of the call's context
   const uint32_t* key;        // batched form: Philox key of the call's context
+  uint32_t* err;              // the context's generation error word (bits: see permute_below)
   // node groups as index arrays and per-connection values (plain form only):
   // a generated source (target) position p becomes src_idx[p] (tgt_idx[p]);
   // synapse i takes weight w_arr[i] and the delay d_ms_arr[i] ms in steps

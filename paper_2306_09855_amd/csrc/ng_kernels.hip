@@ -88,12 +88,24 @@ __device__ __forceinline__ void perm_keys(PermKeys& p, uint32_t u, uint32_t cid,
   philox10(u, 0u, cid, 131072u, key0, key1, p.k);
 }
 
-// x must be below m (the walk from x returns below m only then).
-__device__ __forceinline__ uint64_t permute_below(uint64_t x, uint64_t m, const PermKeys& p) {
+// The walk from x returns below m only for x below m; it then takes at most
+// 2^n - m + 1 steps, and more than kWalkCap steps only after kWalkCap
+// consecutive cycle values at or above m, each of which has probability
+// below one half.  Both conditions are checked: x >= m (a caller's bug) sets
+// bit 0 and a walk that reaches the cap sets bit 1 of the call's error word,
+// which the host reports as a sticky device error; the value is then 0, and
+// every walk ends.
+constexpr uint32_t kWalkCap = 4096;
+__device__ __forceinline__ uint64_t permute_below(uint64_t x, uint64_t m, const PermKeys& p, uint32_t* err) {
+  if (x >= m) {
+    atomicOr(err, 1u);
+    return 0;
+  }
   const int n = m <= 4 ? 2 : 64 - __clzll((long long)(m - 1));
   const int na = n >> 1, nb = n - na;
   const uint32_t mask_a = (uint32_t)((1ull << na) - 1), mask_b = (uint32_t)((1ull << nb) - 1);
   uint64_t y = x;
+  uint32_t steps = 0;
   do {
     uint32_t l = (uint32_t)(y >> nb), r = (uint32_t)y & mask_b;
     l ^= lowbias32(r ^ p.k[0]) & mask_a;
@@ -101,7 +113,11 @@ __device__ __forceinline__ uint64_t permute_below(uint64_t x, uint64_t m, const 
     l ^= lowbias32(r ^ p.k[2]) & mask_a;
     r ^= lowbias32(l ^ p.k[3]) & mask_b;
     y = ((uint64_t)l << nb) | r;
-  } while (y >= m);
+  } while (y >= m && ++steps < kWalkCap);
+  if (y >= m) {
+    atomicOr(err, 2u);
+    return 0;
+  }
   return y;
 }
 
@@ -188,14 +204,14 @@ __device__ __forceinline__ void gen_quad(const GenDesc& d, uint32_t g, uint32_t 
       if constexpr (RULE == R_INDEG_D) {
         const uint32_t t = d.t0 + node;
         const bool in_s = d.no_self && t - d.s0 < d.ns;
-        uint32_t a = (uint32_t)permute_below(pos, d.ns - (in_s ? 1u : 0u), pk);
+        uint32_t a = (uint32_t)permute_below(pos, d.ns - (in_s ? 1u : 0u), pk, d.err);
         if (in_s && a >= t - d.s0) ++a;
         q.s[r] = d.s0 + a;
         q.t[r] = t;
       } else if constexpr (RULE == R_OUTDEG_D) {
         const uint32_t s = d.s0 + node;
         const bool in_t = d.no_self && s - d.t0 < d.nt;
-        uint32_t b = (uint32_t)permute_below(pos, d.nt - (in_t ? 1u : 0u), pk);
+        uint32_t b = (uint32_t)permute_below(pos, d.nt - (in_t ? 1u : 0u), pk, d.err);
         if (in_t && b >= s - d.t0) ++b;
         q.s[r] = s;
         q.t[r] = d.t0 + b;
@@ -204,7 +220,7 @@ __device__ __forceinline__ void gen_quad(const GenDesc& d, uint32_t g, uint32_t 
         // a lane past the call's end (its result is not stored) walks from 0:
         // the walk from x ends only for x below n_pairs, and i may not be
         // when the call takes nearly every pair
-        const uint64_t k = permute_below(i < d.n_new ? i : 0u, d.n_pairs, pk);
+        const uint64_t k = permute_below(i < d.n_new ? i : 0u, d.n_pairs, pk, d.err);
         uint64_t a, b;
         if (!d.no_self) {
           a = k / d.nt;

@@ -283,6 +283,7 @@ int enter(ng_ctx* c);
 hipError_t set_table(char** tab, uint32_t first, const std::vector<char*>& ptrs, uint32_t from,
                      hipStream_t s);
 uint32_t* key_ptr(ng_ctx* c);
+uint32_t* gen_err_ptr(ng_ctx* c);
 hipError_t set_seed(ng_ctx* c, uint64_t seed);
 int mutable_state(ng_ctx* c);
 int not_capturing(ng_ctx* c);

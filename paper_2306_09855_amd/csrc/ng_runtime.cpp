@@ -241,6 +241,10 @@ hipError_t set_table(char** tab, uint32_t first, const std::vector<char*>& ptrs,
 // graph can be replayed with another seed.
 uint32_t* key_ptr(ng_ctx* c) { return c->d_scalars + 4; }
 
+// Generation error word (d_scalars[3], sticky): bit 0 a permutation walk
+// started at or above its bound, bit 1 a walk reached its step cap.
+uint32_t* gen_err_ptr(ng_ctx* c) { return c->d_scalars + 3; }
+
 hipError_t set_seed(ng_ctx* c, uint64_t seed) {
   return ng::launch_set_ptrs(reinterpret_cast<char**>(key_ptr(c)), 0, 1, &seed, c->stream);
 }
@@ -303,7 +307,8 @@ void release_index(ng_ctx* c) {
 
 int check_descs(const std::vector<ng::GenDesc>& descs) {
   for (const auto& d : descs)
-    if (!d.blocks || !d.key) return fail(NG_ERR_STATE, "internal: a generation descriptor has no block table or key");
+    if (!d.blocks || !d.key || !d.err)
+      return fail(NG_ERR_STATE, "internal: a generation descriptor has no block table, key or error word");
   return NG_OK;
 }
 
@@ -448,6 +453,7 @@ int connect_prepare_limit(ng_ctx* c, uint32_t node_limit, ng_range src, ng_range
   p.d.cid = c->next_cid;
   p.d.blocks = c->d_tab[c->cur];
   p.d.key = key_ptr(c);
+  p.d.err = gen_err_ptr(c);
   p.d.max_delay = p.max_delay;
   *out = p.d;
   if (out_n) *out_n = p.n_new;
@@ -1438,6 +1444,7 @@ int ng_connect_batch(ng_ctx* c, uint32_t n_calls, const ng_range* src, const ng_
     p.d.cid = c->next_cid + i;
     p.d.group0 = groups;
     p.d.key = key_ptr(c);
+    p.d.err = gen_err_ptr(c);
     pos += p.n_new;
     groups += (p.n_new + 3) / 4;
     maxd = std::max(maxd, p.max_delay);
@@ -1693,8 +1700,16 @@ int ng_sync(ng_ctx* c) {
   if (int rc = enter(c)) return rc;
   if (int rc = not_capturing(c)) return rc;
   NG_HIP(c, hipStreamSynchronize(c->stream), "kernel execution");
-  uint32_t err = 0;
-  NG_HIP(c, hipMemcpy(&err, c->d_scalars + 2, 4, hipMemcpyDeviceToHost), "read error word");
+  uint32_t words[2] = {0, 0};
+  NG_HIP(c, hipMemcpy(words, c->d_scalars + 2, 8, hipMemcpyDeviceToHost), "read error words");
+  if (words[1]) {  // generation: the connections of some call are not valid
+    c->sticky = NG_ERR_DEVICE;
+    c->sticky_msg = std::string("generation error:") +
+                    ((words[1] & 1u) ? " a permutation walk started at or above its bound" : "") +
+                    ((words[1] & 2u) ? " a permutation walk reached its step cap" : "");
+    return fail(NG_ERR_DEVICE, "%s", c->sticky_msg.c_str());
+  }
+  const uint32_t err = words[0];
   if (err) {  // spike input the steps since the last check dropped (not sticky)
     NG_HIP(c, hipMemset(c->d_scalars + 2, 0, 4), "clear error word");
     return fail(NG_ERR_INVALID_ARG, "spike input dropped:%s%s", (err & 2) ? " a node emitted twice in one step" : "",
