@@ -62,6 +62,16 @@ uint32_t ora_word(uint64_t seed, uint32_t c, uint32_t s, uint64_t q) {
   return out[q & 3];
 }
 
+/* The word streams of a call (stream numbers): every random quantity of
+ * synapse i is word i of its own stream (pairwise_bernoulli: the decision
+ * of pair q is word q of stream 0, and connection j takes the delay and
+ * weight words of synapse j). */
+#define ST_SRC 0u    /* source draws (fixed_indegree, fixed_total_number) */
+#define ST_PAIR 0u   /* pairwise_bernoulli decisions */
+#define ST_W 1u      /* weights */
+#define ST_TGT 2u    /* target draws (fixed_outdegree, fixed_total_number) */
+#define ST_DELAY 3u  /* delays */
+
 /* rand(N) of Sec. 2.1: a uniform integer in [0, N); fixed-point product. */
 uint32_t ora_rand_below(uint32_t x, uint32_t n) {
   return (uint32_t)(((uint64_t)x * (uint64_t)n) >> 32);
@@ -197,7 +207,7 @@ static void a2a_pair(const ora_call* c, uint64_t k, uint64_t* s_off, uint64_t* t
 static uint64_t pb_threshold(const ora_call* c) { return (uint64_t)floor(c->p * 4294967296.0); }
 static int pb_pair(uint64_t seed, uint32_t cid, const ora_call* c, uint64_t a, uint64_t b) {
   if (no_self(c) && c->s0 + a == c->t0 + b) return 0;
-  return (uint64_t)ora_word(seed, cid, 0, a * c->nt + b) < pb_threshold(c);
+  return (uint64_t)ora_word(seed, cid, ST_PAIR, a * c->nt + b) < pb_threshold(c);
 }
 
 int64_t ora_count(const ora_call* c) {
@@ -258,15 +268,15 @@ int ora_words_per_synapse(const ora_call* c) {
   int draws = 0;
   if (no_multi(c) && (c->rule == ORA_FIXED_INDEGREE || c->rule == ORA_FIXED_OUTDEGREE ||
                       c->rule == ORA_FIXED_TOTAL_NUMBER))
-    return delay_is_random(c) ? 1 : 0; /* the permutation draws no stream-0 word */
+    return delay_is_random(c) ? 1 : 0; /* the permutation draws no source or target word */
   if (c->rule == ORA_FIXED_INDEGREE || c->rule == ORA_FIXED_TOTAL_NUMBER) draws++; /* source */
   if (c->rule == ORA_FIXED_OUTDEGREE || c->rule == ORA_FIXED_TOTAL_NUMBER) draws++; /* target */
   if (delay_is_random(c)) draws++;
   return draws;
 }
 
-static int weight_and_delay(uint64_t seed, float h, uint32_t cid, const ora_call* c, uint64_t i, uint32_t dstream,
-                            uint64_t q, double* w, int32_t* delay);
+static int weight_and_delay(uint64_t seed, float h, uint32_t cid, const ora_call* c, uint64_t i, double* w,
+                            int32_t* delay);
 
 int ora_synapse(uint64_t seed, float h, uint32_t cid, const ora_call* c, uint64_t i,
                 uint32_t* src, uint32_t* tgt, double* w, int32_t* delay) {
@@ -278,12 +288,10 @@ int ora_synapse(uint64_t seed, float h, uint32_t cid, const ora_call* c, uint64_
         if (pb_pair(seed, cid, c, a, b) && seen++ == i) {
           *src = c->s0 + (uint32_t)a;
           *tgt = c->t0 + (uint32_t)b;
-          return weight_and_delay(seed, h, cid, c, i, 2, i, w, delay);
+          return weight_and_delay(seed, h, cid, c, i, w, delay);
         }
     return -1;
   }
-  uint64_t w0 = (uint64_t)ora_words_per_synapse(c);
-  uint64_t q = i * w0; /* first stream-0 word of synapse i */
   uint64_t k = c->k_or_n;
   uint64_t s_off = 0, t_off = 0;
   if (no_multi(c) && c->rule == ORA_FIXED_INDEGREE) {
@@ -294,7 +302,7 @@ int ora_synapse(uint64_t seed, float h, uint32_t cid, const ora_call* c, uint64_
     if (in_s && s_off >= t - c->s0) s_off++;
     *src = c->s0 + (uint32_t)s_off;
     *tgt = (uint32_t)t;
-    return weight_and_delay(seed, h, cid, c, i, 0, q, w, delay);
+    return weight_and_delay(seed, h, cid, c, i, w, delay);
   }
   if (no_multi(c) && c->rule == ORA_FIXED_OUTDEGREE) {
     s_off = i / k;
@@ -304,7 +312,7 @@ int ora_synapse(uint64_t seed, float h, uint32_t cid, const ora_call* c, uint64_
     if (in_t && t_off >= s - c->t0) t_off++;
     *src = (uint32_t)s;
     *tgt = c->t0 + (uint32_t)t_off;
-    return weight_and_delay(seed, h, cid, c, i, 0, q, w, delay);
+    return weight_and_delay(seed, h, cid, c, i, w, delay);
   }
   if (no_multi(c) && c->rule == ORA_FIXED_TOTAL_NUMBER) {
     const uint64_t pairs = (uint64_t)c->ns * c->nt - (no_self(c) ? overlap(c) : 0);
@@ -313,7 +321,7 @@ int ora_synapse(uint64_t seed, float h, uint32_t cid, const ora_call* c, uint64_
     a2a_pair(c, pair, &s_off, &t_off);
     *src = c->s0 + (uint32_t)s_off;
     *tgt = c->t0 + (uint32_t)t_off;
-    return weight_and_delay(seed, h, cid, c, i, 0, q, w, delay);
+    return weight_and_delay(seed, h, cid, c, i, w, delay);
   }
   switch (c->rule) {
     case ORA_ONE_TO_ONE: /* Eqs. (4)-(5) */
@@ -346,26 +354,22 @@ int ora_synapse(uint64_t seed, float h, uint32_t cid, const ora_call* c, uint64_
       {
         const uint64_t s = c->s0 + s_off;
         const int in_t = no_self(c) && s >= c->t0 && s < (uint64_t)c->t0 + c->nt;
-        t_off = ora_rand_below(ora_word(seed, cid, 0, q), c->nt - (in_t ? 1 : 0));
+        t_off = ora_rand_below(ora_word(seed, cid, ST_TGT, i), c->nt - (in_t ? 1 : 0));
         if (in_t && t_off >= s - c->t0) t_off++;
       }
-      q++;
       break;
     case ORA_FIXED_INDEGREE: /* Eqs. (10)-(11) */
       t_off = i / k;
       {
         const uint64_t t = c->t0 + t_off;
         const int in_s = no_self(c) && t >= c->s0 && t < (uint64_t)c->s0 + c->ns;
-        s_off = ora_rand_below(ora_word(seed, cid, 0, q), c->ns - (in_s ? 1 : 0));
+        s_off = ora_rand_below(ora_word(seed, cid, ST_SRC, i), c->ns - (in_s ? 1 : 0));
         if (in_s && s_off >= t - c->s0) s_off++;
       }
-      q++;
       break;
-    case ORA_FIXED_TOTAL_NUMBER: /* Eqs. (12)-(13): source draw, then target draw */
-      s_off = ora_rand_below(ora_word(seed, cid, 0, q), c->ns);
-      q++;
-      t_off = ora_rand_below(ora_word(seed, cid, 0, q), c->nt);
-      q++;
+    case ORA_FIXED_TOTAL_NUMBER: /* Eqs. (12)-(13): a source draw and a target draw */
+      s_off = ora_rand_below(ora_word(seed, cid, ST_SRC, i), c->ns);
+      t_off = ora_rand_below(ora_word(seed, cid, ST_TGT, i), c->nt);
       if (no_self(c)) {
         for (uint32_t a = 1; c->s0 + s_off == c->t0 + t_off; a++) {
           const uint32_t st = 65536u + (a <= 64 ? a : 64);
@@ -388,15 +392,15 @@ int ora_synapse(uint64_t seed, float h, uint32_t cid, const ora_call* c, uint64_
   /* explicit node arrays: the formulas give the array position */
   *src = c->src_idx ? c->src_idx[s_off] : c->s0 + (uint32_t)s_off;
   *tgt = c->tgt_idx ? c->tgt_idx[t_off] : c->t0 + (uint32_t)t_off;
-  return weight_and_delay(seed, h, cid, c, i, 0, q, w, delay);
+  return weight_and_delay(seed, h, cid, c, i, w, delay);
 }
 
-/* delay of synapse i from word q of stream dstream (if random); a random
- * weight from stream 1: normal weights of synapses 2j and 2j+1 are the cosine
- * and sine outputs of the Box-Muller pair on words 2j, 2j+1; a uniform
- * weight takes word i */
-static int weight_and_delay(uint64_t seed, float h, uint32_t cid, const ora_call* c, uint64_t i, uint32_t dstream,
-                            uint64_t q, double* w, int32_t* delay) {
+/* delay of synapse i from word i of the delay stream (if random); a random
+ * weight from the weight stream: normal weights of synapses 2j and 2j+1 are
+ * the cosine and sine outputs of the Box-Muller pair on words 2j, 2j+1; a
+ * uniform weight takes word i */
+static int weight_and_delay(uint64_t seed, float h, uint32_t cid, const ora_call* c, uint64_t i, double* w,
+                            int32_t* delay) {
   if (c->d_arr) {
     *delay = ora_delay_steps(c->d_arr[i], h);
   } else switch (c->d_kind) {
@@ -405,11 +409,11 @@ static int weight_and_delay(uint64_t seed, float h, uint32_t cid, const ora_call
       break;
     case ORA_UNIFORM_INT: { /* integer steps lo..hi */
       uint32_t lo = (uint32_t)c->d_a, hi = (uint32_t)c->d_b;
-      *delay = (int32_t)(lo + ora_rand_below(ora_word(seed, cid, dstream, q), hi - lo + 1));
+      *delay = (int32_t)(lo + ora_rand_below(ora_word(seed, cid, ST_DELAY, i), hi - lo + 1));
       break;
     }
     case ORA_UNIFORM:
-      *delay = ora_uniform_ms_delay(ora_word(seed, cid, dstream, q), c->d_a, c->d_b, h);
+      *delay = ora_uniform_ms_delay(ora_word(seed, cid, ST_DELAY, i), c->d_a, c->d_b, h);
       break;
     default:
       return -1;
@@ -425,12 +429,12 @@ static int weight_and_delay(uint64_t seed, float h, uint32_t cid, const ora_call
       break;
     case ORA_NORMAL: {
       const uint64_t j = i >> 1;
-      *w = ora_normal_weight2(ora_word(seed, cid, 1, 2 * j), ora_word(seed, cid, 1, 2 * j + 1), (int)(i & 1),
+      *w = ora_normal_weight2(ora_word(seed, cid, ST_W, 2 * j), ora_word(seed, cid, ST_W, 2 * j + 1), (int)(i & 1),
                               c->w_a, c->w_b);
       break;
     }
     case ORA_UNIFORM:
-      *w = ora_uniform_weight(ora_word(seed, cid, 1, i), c->w_a, c->w_b);
+      *w = ora_uniform_weight(ora_word(seed, cid, ST_W, i), c->w_a, c->w_b);
       break;
     default:
       return -1;
@@ -439,11 +443,12 @@ static int weight_and_delay(uint64_t seed, float h, uint32_t cid, const ora_call
 }
 
 /* pairwise_bernoulli: weight and delay of connection j (they depend on j
- * only: delay word j of stream 2, weight as synapse j of stream 1) */
+ * only: as synapse j of any call, delay word j of the delay stream, weight
+ * from the weight stream) */
 int ora_pairwise_values(uint64_t seed, float h, uint32_t cid, const ora_call* c, uint64_t j, double* w,
                         int32_t* delay) {
   if (c->rule != ORA_PAIRWISE_BERNOULLI) return -1;
-  return weight_and_delay(seed, h, cid, c, j, 2, j, w, delay);
+  return weight_and_delay(seed, h, cid, c, j, w, delay);
 }
 
 int ora_connect(uint64_t seed, float h, uint32_t cid, const ora_call* c, uint32_t* src,
@@ -456,7 +461,7 @@ int ora_connect(uint64_t seed, float h, uint32_t cid, const ora_call* c, uint32_
         if (pb_pair(seed, cid, c, a, b)) {
           src[j] = c->s0 + (uint32_t)a;
           tgt[j] = c->t0 + (uint32_t)b;
-          if (weight_and_delay(seed, h, cid, c, j, 2, j, &w[j], &delay[j])) return -1;
+          if (weight_and_delay(seed, h, cid, c, j, &w[j], &delay[j])) return -1;
           j++;
         }
     return 0;

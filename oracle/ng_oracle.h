@@ -25,8 +25,11 @@
  * connectivity only statistically, Sec. 2.7):
  *   Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), key = seed split in two
  *   32-bit halves, word stream W_{c,s}[q] = Philox(ctr = (q/4 low, q/4 high,
- *   c, s))[q mod 4] for connect call c and stream s (0: index and delay draws,
- *   1: weight draws).
+ *   c, s))[q mod 4] for connect call c and stream s.  Synapse i takes word i
+ *   of stream 0 for a source draw, of stream 2 for a target draw, of stream 3
+ *   for its delay; its weight comes from stream 1 (two normal weights per
+ *   pair of words, or word i for a uniform weight).  So the draws of any one
+ *   kind can be evaluated without the others.
  *
  * Floating point: weights are evaluated in double precision (fp64).  The
  * ms-to-step delay conversion decides an integer, so it is evaluated in fp32,
@@ -83,7 +86,7 @@ typedef struct {
    * when word (a * N_t + b) of stream 0 is below floor(p * 2^32) (a, b: the
    * positions of s and t; self-pairs never with allow_autapses = 0); the
    * connections are numbered in that order; connection j draws its delay
-   * from word j of stream 2 and its weight from stream 1 as synapse j would. */
+   * and weight as synapse j of any call would (word j of stream 3, stream 1). */
   double p;
   /* 0: no two connections join the same pair (sampling without
    * replacement; Discussion: future work).  Defined with a pseudorandom
@@ -99,7 +102,8 @@ typedef struct {
    * range without t, skip-self as above); fixed_outdegree likewise;
    * fixed_total_number: synapse i is the pair of index pi_0(i) in the
    * all_to_all order (without the self-pairs when those are prohibited).
-   * The index draws use no stream-0 word: synapse i's delay is word i. */
+   * The permutation draws no source or target word; synapse i's delay is
+   * word i of the delay stream as for any rule. */
   int32_t allow_multapses;
 } ora_call;
 
@@ -128,7 +132,7 @@ double ora_normal_weight2(uint32_t y0, uint32_t y1, int branch, double mean, dou
 double ora_uniform_weight(uint32_t y0, double lo, double hi);
 /* delay in ms -> integer steps (fp32), minimum one step */
 int32_t ora_delay_steps(float d_ms, float h);
-/* uniform ms delay from one stream-0 word, then to steps */
+/* uniform ms delay from one delay word, then to steps */
 int32_t ora_uniform_ms_delay(uint32_t x, double lo, double hi, float h);
 
 /* number of connections a call creates, or -1 if the call is invalid */
@@ -141,7 +145,8 @@ int64_t ora_count_pairwise(uint64_t seed, uint32_t connect_id, const ora_call* c
 int64_t ora_pairwise_row(uint64_t seed, uint32_t connect_id, const ora_call* call, uint32_t a, uint32_t* out);
 int ora_pairwise_values(uint64_t seed, float h, uint32_t connect_id, const ora_call* call, uint64_t j,
                         double* w, int32_t* delay);
-/* stream-0 words a synapse consumes */
+/* random source, target and delay draws of one synapse (one word each, of
+ * their own streams) */
 int ora_words_per_synapse(const ora_call* call);
 
 /* synapse i of connect call `connect_id` */

@@ -6,7 +6,7 @@
   (the formulas give array positions);
 * a weight array leaves sources, targets and delays of the call unchanged
   (weights draw from their own stream) and its values come out exactly;
-* a delay array consumes no stream-0 words: sources and targets equal those of
+* a delay array consumes no delay word: sources and targets equal those of
   the call with a constant delay, and delays that are whole multiples of the
   step, or below one step, come out as those multiples, or as one step.
 """

@@ -9,8 +9,8 @@ in the Discussion), defined with a keyed Feistel permutation walked into
   and without self-pairs);
 * with K < N_s the sources of a target are distinct and, over many targets,
   uniform (chi-square);
-* delays: synapse i's delay is word i of stream 0, the same as an all_to_all
-  call's synapse i with the same call id;
+* delays: synapse i's delay is word i of the delay stream, the same as an
+  all_to_all call's synapse i with the same call id;
 * calls asking for more distinct draws than candidates are rejected.
 """
 from types import SimpleNamespace

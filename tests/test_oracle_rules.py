@@ -129,6 +129,30 @@ def test_streams_are_distinct_across_calls_and_seeds():
         assert np.array_equal(x, y)
 
 
+def test_draws_of_one_kind_are_shared_across_rules():
+    # Each kind of draw has its own stream, indexed by the synapse: calls of
+    # different rules with the same call id, source range, target range and
+    # specs draw the same sources (fixed_indegree and fixed_total_number), the
+    # same targets (fixed_outdegree and fixed_total_number) and the same
+    # delays and weights (every rule).  A word taken at a wrong index or from
+    # the wrong stream breaks one of these equalities.
+    S, T, n = (10, 300), (400, 250), 250 * 12
+    d = ("uniform_int", 1, 17)
+    tot = _conn(Call("fixed_total_number", S, T, n, delay=d), cid=6)
+    ind = _conn(Call("fixed_indegree", S, T, 12, delay=d), cid=6)
+    outd = _conn(Call("fixed_outdegree", S, T, n // 300, delay=d), cid=6)
+    a2a = _conn(Call("all_to_all", (10, 12), T, 0, delay=d), cid=6)
+    assert np.array_equal(tot[0], ind[0])
+    assert np.array_equal(tot[1][: outd[1].size], outd[1])
+    for other in (ind, outd, a2a):
+        m = other[3].size
+        assert np.array_equal(tot[3][:m], other[3]) and np.array_equal(tot[2][:m], other[2])
+    # and a different stream is used for each kind: sources and targets of
+    # fixed_total_number over equal ranges are not the same draws
+    same = _conn(Call("fixed_total_number", (0, 500), (0, 500), 5000, delay=d), cid=6)
+    assert np.mean(same[0] == same[1]) < 0.01
+
+
 def test_synapse_matches_connect():
     c = Call("fixed_indegree", (3, 77), (1000, 50), 13, ("uniform", -1.0, 2.0), ("uniform", 0.5, 3.0))
     src, tgt, w, d = _conn(c, cid=4)
