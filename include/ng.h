@@ -30,10 +30,10 @@
  * preserves the network only statistically, Sec. 2.7).  The contract here:
  *   Philox4x32-10 (Salmon et al., SC'11), key = (seed mod 2^32, seed >> 32).
  *   Word q of stream s of Connect call c is word (q mod 4) of the block with
- *   counter (q/4 mod 2^32, q/4 >> 32, c, s).  Stream 0 holds index and delay
- *   draws: synapse i of a call uses words i*w0 .. i*w0+w0-1 in the order
- *   [source draw][target draw][delay draw], each present only if random
- *   (w0 = number of random draws).  Stream 1 holds weight draws: normal
+ *   counter (q/4 mod 2^32, q/4 >> 32, c, s).  Synapse i of a call takes word
+ *   i of stream 0 for a random source, word i of stream 2 for a random
+ *   target and word i of stream 3 for a random delay, so the draws of one
+ *   kind are independent of the others'.  Stream 1 holds weight draws: normal
  *   weights of synapses 2j and 2j+1 are the cosine and sine outputs of
  *   Box-Muller on words y0 = 2j, y1 = 2j+1, u1 = (y0>>8 + 1)/2^24,
  *   u2 = (y1>>8)/2^24; a uniform weight of synapse i takes word i.  Computed
@@ -89,8 +89,9 @@ typedef struct {
  * k_0..k_3 the words of Philox(ctr = (t, 0, call, 131072)) and lowbias32
  * the integer hash of C. Wellons (2018).  fixed_outdegree likewise with sources and targets exchanged.
  * fixed_total_number: synapse i is the pair of index pi_0(i) in the
- * all_to_all order.  These draws use no stream-0 word (synapse i's delay is
- * word i).  K or N above the distinct candidates is NG_ERR_INVALID_ARG. */
+ * all_to_all order.  These draws take no source or target word (synapse
+ * i's delay is word i of the delay stream, as for every rule).  K or N above
+ * the distinct candidates is NG_ERR_INVALID_ARG. */
 typedef enum {
   NG_ONE_TO_ONE = 0,         /* Eqs. (4)-(5): N_new = N_s = N_t         */
   NG_ALL_TO_ALL = 1,         /* Eqs. (6)-(7): N_new = N_s * N_t         */
@@ -114,8 +115,8 @@ typedef struct {
  * sources in order, targets ascending, positions a and b in the ranges --
  * is a connection when word a * N_t + b of stream 0 is below
  * floor(p * 2^32); with allow_autapses = 0 a self-pair never is.  The
- * connections are numbered in pair order; connection j draws its delay from
- * word j of stream 2 and its weight from stream 1 as synapse j would.  Only
+ * connections are numbered in pair order; connection j takes the delay and
+ * weight words of synapse j (word j of stream 3, stream 1).  Only
  * ng_connect takes it: a counting pass over the pairs gives the exact number
  * of connections, the host reads it (ng_connect synchronizes for this rule;
  * NG_ERR_STATE under capture), reserves exactly that many, and a second pass
@@ -250,31 +251,6 @@ int ng_calibrate(ng_ctx* ctx);
  * All-or-nothing on NG_ERR_OOM: no context changes except that a context's
  * stale group index (it was uncalibrated) may have been released. */
 int ng_calibrate_many(ng_ctx* const* ctxs, uint32_t n);
-
-/* For callers that cannot allocate device memory (code under HIP graph
- * capture, tight serving loops, harnesses that forbid it): ng_calibrate with
- * its sort and group-index scratch (digit counts, scan partials, ping-pong
- * key and payload arrays, group-start bitmap and group sources) taken from a
- * fixed region of ng_noalloc_scratch_bytes() = 64 MiB in device memory that
- * the library holds on each GPU it runs on until the process ends, instead
- * of from the arena.  It calls no hipMalloc, hipFree or other allocating
- * routine (with timing off: ng_enable_timing creates events).  The outputs
- * -- the calibrated connection blocks and the group index -- live in the
- * context's arena as after ng_calibrate, and the result is identical to
- * ng_calibrate's.  The radix calibration of one context with its own arena:
- * NG_ERR_UNSUPPORTED for a context in COPASS mode or on a server's shared
- * arena.  NG_ERR_TOO_LARGE, with nothing changed, when the scratch does not
- * fit the region: 24 bytes per connection with three or more digit passes
- * (keys wider than 2 x radix bits), 12 with two, none with one, plus about
- * 4.2 bytes per connection for the group index and the counts -- so up to
- * about 2.3 million connections with wide keys.  Asynchronous on the
- * context's stream.  Every call on one GPU uses that GPU's one region:
- * calls whose work may overlap on one GPU (contexts on different streams
- * without ordering between them) race and give wrong results; serialize
- * them.  The region keeps the previous call's contents; nothing in it needs
- * to start at zero. */
-int ng_calibrate_noalloc(ng_ctx* ctx);
-uint64_t ng_noalloc_scratch_bytes(void);
 
 /* Wait for all enqueued work; reports kernel errors. */
 int ng_sync(ng_ctx* ctx);

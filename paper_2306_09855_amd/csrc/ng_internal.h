@@ -17,7 +17,7 @@ enum : uint32_t { D_CONST = 0, D_UNIFORM_INT = 2, D_UNIFORM_MS = 3 };
 
 // One planned Connect call, as the generation kernels consume it.
 // Generation rule codes beyond ng_rule's: the multapse-free draws (a keyed
-// permutation instead of independent draws; no stream-0 index words).
+// permutation instead of independent draws; no source or target words).
 constexpr uint32_t kRuleIndegDistinct = 8;
 constexpr uint32_t kRuleOutdegDistinct = 9;
 constexpr uint32_t kRuleTotalDistinct = 10;

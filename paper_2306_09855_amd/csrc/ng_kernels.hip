@@ -121,9 +121,15 @@ __device__ __forceinline__ uint64_t permute_below(uint64_t x, uint64_t m, const 
   return y;
 }
 
+// Word streams of a call: synapse i takes word i of its own stream for each
+// random quantity (source draw, target draw, delay), so one Philox block of a
+// stream serves a lane's four synapses; weights come from stream 1.
+constexpr uint32_t kStreamSrc = 0u, kStreamW = 1u, kStreamTgt = 2u, kStreamDelay = 3u;
+
 template <int RULE>
-struct RuleDraws {  // stream-0 index words per synapse (the distinct draws use none)
-  static constexpr int value = RULE == R_TOTAL ? 2 : (RULE == R_INDEG || RULE == R_OUTDEG) ? 1 : 0;
+struct RuleDraws {  // which index draws a rule takes (the distinct draws take none)
+  static constexpr bool src = RULE == R_TOTAL || RULE == R_INDEG;
+  static constexpr bool tgt = RULE == R_TOTAL || RULE == R_OUTDEG;
 };
 
 struct Quad {
@@ -166,17 +172,16 @@ __device__ __forceinline__ float uniform_weight(const GenDesc& d, uint32_t y) {
   return __fmaf_rn(d.w_b, (float)(y >> 8) * kInv2p24, d.w_a);
 }
 
-// Synapses i0..i0+3 of one call (i0 = 4g).  W0 = stream-0 words per synapse.
+// Synapses i0..i0+3 of one call (i0 = 4g): block g of the source, target and
+// delay streams the rule draws from.
 template <int RULE, bool DRAND>
 __device__ __forceinline__ void gen_quad(const GenDesc& d, uint32_t g, uint32_t key0, uint32_t key1,
                                          Quad& q) {
-  constexpr int NIDX = RuleDraws<RULE>::value;
-  constexpr int W0 = NIDX + (DRAND ? 1 : 0);
   const uint32_t i0 = g << 2;
-  uint32_t x[W0 > 0 ? 4 * W0 : 1];
-#pragma unroll
-  for (int m = 0; m < W0; ++m)
-    philox_block((uint64_t)g * W0 + m, d.cid, 0u, key0, key1, &x[4 * m]);
+  uint32_t xs[4], xt[4], xd[4];
+  if constexpr (RuleDraws<RULE>::src) philox_block(g, d.cid, kStreamSrc, key0, key1, xs);
+  if constexpr (RuleDraws<RULE>::tgt) philox_block(g, d.cid, kStreamTgt, key0, key1, xt);
+  if constexpr (DRAND) philox_block(g, d.cid, kStreamDelay, key0, key1, xd);
 
   // source / target indices, Eqs. (4)-(13)
   if constexpr (RULE == R_INDEG_D || RULE == R_OUTDEG_D || RULE == R_TOTAL_D) {
@@ -275,19 +280,19 @@ __device__ __forceinline__ void gen_quad(const GenDesc& d, uint32_t g, uint32_t 
       } else if constexpr (RULE == R_OUTDEG) {
         const uint32_t s = d.s0 + i / d.k;
         const bool in_t = s - d.t0 < d.nt;  // s in [t0, t0 + nt)
-        uint32_t b = rand_below(x[r * W0], d.nt - (in_t ? 1u : 0u));
+        uint32_t b = rand_below(xt[r], d.nt - (in_t ? 1u : 0u));
         if (in_t && b >= s - d.t0) ++b;
         q.s[r] = s;
         q.t[r] = d.t0 + b;
       } else if constexpr (RULE == R_INDEG) {
         const uint32_t t = d.t0 + i / d.k;
         const bool in_s = t - d.s0 < d.ns;
-        uint32_t a = rand_below(x[r * W0], d.ns - (in_s ? 1u : 0u));
+        uint32_t a = rand_below(xs[r], d.ns - (in_s ? 1u : 0u));
         if (in_s && a >= t - d.s0) ++a;
         q.s[r] = d.s0 + a;
         q.t[r] = t;
       } else {  // R_TOTAL: redraw autapses from attempt streams 65536 + a, words 2i and 2i+1
-        uint32_t a = rand_below(x[r * W0], d.ns), b = rand_below(x[r * W0 + 1], d.nt);
+        uint32_t a = rand_below(xs[r], d.ns), b = rand_below(xt[r], d.nt);
         for (uint32_t att = 1; d.s0 + a == d.t0 + b; ++att) {
           uint32_t y[4];
           philox_block(i >> 1, d.cid, 65536u + att, key0, key1, y);
@@ -326,22 +331,22 @@ __device__ __forceinline__ void gen_quad(const GenDesc& d, uint32_t g, uint32_t 
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       q.s[r] = d.s0 + a;
-      q.t[r] = d.t0 + rand_below(x[r * W0], d.nt);
+      q.t[r] = d.t0 + rand_below(xt[r], d.nt);
       if (++b == d.k) { b = 0; ++a; }
     }
   } else if constexpr (RULE == R_INDEG) {
     uint32_t a = i0 / d.k, b = i0 - a * d.k;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      q.s[r] = d.s0 + rand_below(x[r * W0], d.ns);
+      q.s[r] = d.s0 + rand_below(xs[r], d.ns);
       q.t[r] = d.t0 + a;
       if (++b == d.k) { b = 0; ++a; }
     }
   } else {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      q.s[r] = d.s0 + rand_below(x[r * W0], d.ns);
-      q.t[r] = d.t0 + rand_below(x[r * W0 + 1], d.nt);
+      q.s[r] = d.s0 + rand_below(xs[r], d.ns);
+      q.t[r] = d.t0 + rand_below(xt[r], d.nt);
     }
   }
 
@@ -349,7 +354,7 @@ __device__ __forceinline__ void gen_quad(const GenDesc& d, uint32_t g, uint32_t 
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     if constexpr (DRAND) {
-      q.d[r] = delay_from_word(d, x[r * W0 + NIDX]);
+      q.d[r] = delay_from_word(d, xd[r]);
     } else {
       q.d[r] = d.d_const;
     }
@@ -361,7 +366,7 @@ __device__ __forceinline__ void gen_quad(const GenDesc& d, uint32_t g, uint32_t 
     for (int r = 0; r < 4; ++r) q.w[r] = d.w_a;
   } else {
     uint32_t y[4];
-    philox_block(g, d.cid, 1u, key0, key1, y);
+    philox_block(g, d.cid, kStreamW, key0, key1, y);
     if (d.w_kind == W_NORMAL) {
       normal_pair(d, y[0], y[1], q.w[0], q.w[1]);
       normal_pair(d, y[2], y[3], q.w[2], q.w[3]);
@@ -1434,7 +1439,7 @@ __device__ __forceinline__ uint32_t pb_bits(const GenDesc& d, uint32_t a, uint32
     const uint64_t q = (uint64_t)a * d.nt + b;
     if ((q >> 2) != blk) {
       blk = q >> 2;
-      philox_block(blk, d.cid, 0u, key0, key1, w4);
+      philox_block(blk, d.cid, kStreamSrc, key0, key1, w4);  // the decisions' stream
     }
     const uint32_t x = w4[0] * ((q & 3) == 0) + w4[1] * ((q & 3) == 1) + w4[2] * ((q & 3) == 2) + w4[3] * ((q & 3) == 3);
     const bool self = d.no_self && d.s0 + a == d.t0 + b;
@@ -1513,10 +1518,10 @@ __global__ __launch_bounds__(kPbThreads) void k_pb_write(GenDesc d, const uint32
       for (uint64_t qi = threadIdx.x; qi < nq; qi += kPbThreads) {
         const uint64_t q = q0 + qi;
         uint32_t xd[4] = {0, 0, 0, 0}, y[4] = {0, 0, 0, 0};
-        if (d.d_kind != D_CONST) philox_block(q, d.cid, 2u, key0, key1, xd);
+        if (d.d_kind != D_CONST) philox_block(q, d.cid, kStreamDelay, key0, key1, xd);
         float w[4] = {d.w_a, d.w_a, d.w_a, d.w_a};
         if (d.w_kind != W_CONST) {
-          philox_block(q, d.cid, 1u, key0, key1, y);
+          philox_block(q, d.cid, kStreamW, key0, key1, y);
           if (d.w_kind == W_NORMAL) {
             normal_pair(d, y[0], y[1], w[0], w[1]);
             normal_pair(d, y[2], y[3], w[2], w[3]);
