@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libng.so")
 
-SOURCES = ["ng_runtime.cpp", "ng_server.cpp", "ng_kernels.hip"]
+SOURCES = ["ng_runtime.cpp", "ng_server.cpp", "ng_kernels.hip", "ng_msd.hip"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -136,6 +136,67 @@ struct TabEntry {
 hipError_t launch_set_entries(const TabEntry* d_entries, uint32_t n, hipStream_t s);
 
 // ---------------------------------------------------------------------------
+// Most-significant-digit calibration (Sec. 2.2): the stable sort by key =
+// src << dbits | delay (keybits <= 27) in three digits from the top, key =
+// D1 (b1 bits) | D2 (b2 bits) | D3 (b3 bits), each at most 9 bits:
+//   A  all records, stably by D1, into 2^b1 buckets (reads the creation-order
+//      blocks);
+//   B  each bucket stably by D2 into 2^b2 sub-buckets (skipped when b2 = 0);
+//   C  each sub-bucket sorted by D3 in LDS and written as calibrated blocks,
+//      with its groups (distinct keys) recorded for the group index.
+// Records between passes: "narrow" = a u32 kt = (key mod 2^r) << tbits | tgt
+// (r = the key bits below the digit already applied) plus a u32 weight, when
+// r + tbits <= 32 and tbits < 32; "wide" = the full u32 key, u32 tgt and u32
+// weight.  Buckets, sub-buckets and the ranges of pass B are laid out on the
+// device from the counts, so no value travels back to the host.
+constexpr uint32_t kMsdTile = 10240;      // records per tile of passes A and B
+constexpr uint32_t kMsdMaxDigit = 9;      // widest digit
+constexpr uint32_t kMsdMaxKeyBits = 27;   // 3 x kMsdMaxDigit
+
+struct MsdPlan {
+  uint32_t n;                       // records (n > 0)
+  uint32_t keybits, dbits, tbits;   // tbits: bits of a target index (nodes - 1)
+  uint32_t b1, b2, b3;
+  uint32_t narrow_a, narrow_b;      // formats of the output of A and of B
+  uint32_t tpr;                     // tiles per range (passes A and B)
+  uint32_t ranges_a;                // ranges of pass A
+  uint32_t max_ranges_b;            // ranges of pass B: at most this many
+  uint32_t wgs_c;                   // workgroups of pass C
+  uint32_t n_nodes;
+  int log2B;
+  char* const* in_blocks;           // creation-order blocks
+  char* const* out_blocks;          // calibrated blocks
+  // records after A (= input of B) and after B (= input of C); *_tgt only wide
+  uint32_t *a_key, *a_tgt, *a_w;
+  uint32_t *b_key, *b_tgt, *b_w;
+  uint32_t* cnt_a;                  // [2^b1 * ranges_a] digit-major counts, scanned in place
+  uint32_t* cnt_b;                  // [2^b2 * max_ranges_b] (bucket, digit, range) counts, scanned
+  uint32_t* bstart;                 // [2^b1 + 1] bucket starts
+  uint32_t* rangeb0;                // [2^b1 + 1] first range of pass B of each bucket
+  uint32_t* sbstart;                // [2^(b1+b2) + 1] sub-bucket starts
+  uint32_t* wg_sb0;                 // [wgs_c + 1] first sub-bucket of each workgroup of C
+  uint32_t* gcount;                 // [2^(b1+b2) + 1] groups per sub-bucket, scanned in place
+  uint32_t* gmask;                  // [2^(b1+b2) * mask_words] present D3 values per sub-bucket
+  uint32_t* gslot;                  // [n] local group starts at sub-bucket offsets (scratch)
+  uint32_t mask_words;              // max(1, 2^b3 / 32)
+  uint32_t* group_ptr;              // [n_nodes + 1]
+  uint32_t* group_start;            // [min(n, 2^keybits) + 1]
+  uint32_t* n_groups;               // G (device word)
+};
+
+// Largest sub-bucket that pass C sorts in LDS in one piece (larger ones are
+// sorted in pieces of this size, with a counting pre-pass).
+uint32_t msd_cap(bool narrow);
+hipError_t launch_msd_count_a(const MsdPlan& p, hipStream_t s);
+hipError_t launch_msd_scatter_a(const MsdPlan& p, hipStream_t s);
+hipError_t launch_msd_plan_b(const MsdPlan& p, hipStream_t s);
+hipError_t launch_msd_count_b(const MsdPlan& p, hipStream_t s);
+hipError_t launch_msd_scatter_b(const MsdPlan& p, hipStream_t s);
+hipError_t launch_msd_plan_c(const MsdPlan& p, hipStream_t s);
+hipError_t launch_msd_local_c(const MsdPlan& p, hipStream_t s);
+hipError_t launch_msd_groups(const MsdPlan& p, hipStream_t s);
+
+// ---------------------------------------------------------------------------
 // pairwise_bernoulli: pairs (rows of sources, targets ascending) in units of
 // kPbUnit consecutive targets of one row.  count: counts[u] = connections of
 // unit u, and, when bits is not null, the decisions (16 per thread, one u16
