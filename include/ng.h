@@ -252,6 +252,31 @@ int ng_calibrate(ng_ctx* ctx);
  * stale group index (it was uncalibrated) may have been released. */
 int ng_calibrate_many(ng_ctx* const* ctxs, uint32_t n);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid it): ng_calibrate with
+ * its sort and group-index scratch (digit counts, scan partials, ping-pong
+ * key and payload arrays, group-start bitmap and group sources) taken from a
+ * fixed region of ng_noalloc_scratch_bytes() = 64 MiB in device memory that
+ * the library holds on each GPU it runs on until the process ends, instead
+ * of from the arena.  It calls no hipMalloc, hipFree or other allocating
+ * routine (with timing off: ng_enable_timing creates events).  The outputs
+ * -- the calibrated connection blocks and the group index -- live in the
+ * context's arena as after ng_calibrate, and the result is identical to
+ * ng_calibrate's.  The radix calibration of one context with its own arena:
+ * NG_ERR_UNSUPPORTED for a context in COPASS mode or on a server's shared
+ * arena.  NG_ERR_TOO_LARGE, with nothing changed, when the scratch does not
+ * fit the region: 24 bytes per connection with three or more digit passes
+ * (keys wider than 2 x radix bits), 12 with two, none with one, plus about
+ * 4.2 bytes per connection for the group index and the counts -- so up to
+ * about 2.3 million connections with wide keys.  Asynchronous on the
+ * context's stream.  Every call on one GPU uses that GPU's one region:
+ * calls whose work may overlap on one GPU (contexts on different streams
+ * without ordering between them) race and give wrong results; serialize
+ * them.  The region keeps the previous call's contents; nothing in it needs
+ * to start at zero. */
+int ng_calibrate_noalloc(ng_ctx* ctx);
+uint64_t ng_noalloc_scratch_bytes(void);
+
 /* Wait for all enqueued work; reports kernel errors. */
 int ng_sync(ng_ctx* ctx);
 

@@ -327,7 +327,31 @@ using Uploader = std::function<int(hipStream_t, void* d_dst, const void* src, ui
 // one's stream (each context is one segment of the sorts); the others'
 // streams are ordered before and after with events.  Descriptor tables go up
 // through `upload` if given, else through the first context's staging.
-int calibrate_many(ng_ctx* const* cs, uint32_t n, const Uploader* upload = nullptr);
+// Bump allocator over a fixed device region (the no-allocation calibration's
+// scratch): 256-byte aligned pieces; ok turns false once a request does not fit.
+struct ScratchBump {
+  char* base = nullptr;
+  uint64_t cap = 0, used = 0;
+  bool ok = true;
+  char* get(uint64_t bytes) {
+    const uint64_t b = (bytes + kAlign - 1) / kAlign * kAlign;
+    if (!ok || b > cap - used) {
+      ok = false;
+      used = cap;
+      return nullptr;
+    }
+    char* p = base + used;
+    used += b ? b : kAlign;
+    return p;
+  }
+};
+
+// sb: the sort and group-index scratch comes from sb instead of the arena
+// (one context only); outputs still live in the context's arena.
+int calibrate_many(ng_ctx* const* cs, uint32_t n, const Uploader* upload = nullptr, ScratchBump* sb = nullptr);
+// The device address of the no-allocation calibration's scratch on the
+// current device (looked up once per device; 0 on success).
+int noalloc_scratch_init(int device);
 // NG_OK if every descriptor names a block table and a key (checked on the host
 // before any batched launch).
 int check_descs(const std::vector<ng::GenDesc>& descs);

@@ -12,12 +12,40 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "ng_rt.h"
 
 namespace ngrt {
+
+// Scratch of ng_calibrate_noalloc: a fixed array in device memory, one copy per
+// GPU at its own address, held until the process ends.  Host code never uses
+// the name `scratch` as an address: the address comes from
+// hipGetSymbolAddress, looked up once per device with that device current.
+constexpr uint64_t kNoAllocScratchBytes = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+static std::mutex g_scratch_mu;
+static std::vector<char*> g_scratch_ptr;  // per device id
+
+int noalloc_scratch_init(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (device < 0) return fail(NG_ERR_DEVICE, "bad device id");
+  if ((int)g_scratch_ptr.size() <= device) g_scratch_ptr.resize((size_t)device + 1, nullptr);
+  if (g_scratch_ptr[(size_t)device]) return NG_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return fail(NG_ERR_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+  g_scratch_ptr[(size_t)device] = (char*)ptr;
+  return NG_OK;
+}
+
+static char* noalloc_scratch_ptr(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return device >= 0 && (size_t)device < g_scratch_ptr.size() ? g_scratch_ptr[(size_t)device] : nullptr;
+}
 
 
 thread_local std::string g_err;
@@ -383,6 +411,10 @@ int ctx_init(const ng_config* cfg, Arena* shared, char* base, uint64_t bytes, hi
     delete c;
     return fail(NG_ERR_DEVICE, "no HIP device");
   }
+  if (int rc = noalloc_scratch_init(c->device)) {  // library set-up, once per device
+    delete c;
+    return rc;
+  }
   if (shared) {
     c->arena = shared;
     c->shared_arena = true;
@@ -526,6 +558,7 @@ struct CalSeg {
   uint32_t* gstart = nullptr;
   uint64_t gp_bytes = 0, gs_bytes = 0;
   int nxt = 0;
+  ScratchBump* sb = nullptr;  // scratch from a fixed region instead of the arena
 };
 
 // Digit schedule and geometry (no allocation).
@@ -569,12 +602,19 @@ int cal_alloc(CalSeg& g) {
   AllocSet& as = *g.as;
   const uint64_t nblk = (g.N + c->B - 1) / c->B;
   for (uint64_t b = 0; b < nblk && as.ok; ++b) g.nblocks.push_back(as.get(ng::kBytesPerConn * c->B));
+  auto sget = [&](uint64_t bytes) { return g.sb ? g.sb->get(bytes) : as.get(bytes); };
   for (int t = 0; t < std::min(g.passes - 1, 2); ++t) {
-    g.keys[t] = (uint32_t*)as.get(4 * std::max<uint64_t>(g.N, 1));
-    g.pay[t] = (uint2*)as.get(8 * std::max<uint64_t>(g.N, 1));
+    g.keys[t] = (uint32_t*)sget(4 * std::max<uint64_t>(g.N, 1));
+    g.pay[t] = (uint2*)sget(8 * std::max<uint64_t>(g.N, 1));
   }
-  g.group_src = (uint32_t*)as.get(4 * g.gcap);
-  g.bitmap = (uint32_t*)as.get(4 * ((g.N + 31) / 32 + 1));
+  g.group_src = (uint32_t*)sget(4 * g.gcap);
+  g.bitmap = (uint32_t*)sget(4 * ((g.N + 31) / 32 + 1));
+  if (g.sb && !g.sb->ok) {
+    as.release_all();
+    g.nblocks.clear();
+    return fail(NG_ERR_TOO_LARGE, "the calibration scratch of %llu connections exceeds the fixed %llu-byte region",
+                (unsigned long long)g.N, (unsigned long long)g.sb->cap);
+  }
   g.gp_bytes = 4 * (g.nn + 1ull);
   g.gs_bytes = 4 * g.gcap;
   release_index(c);
@@ -908,9 +948,10 @@ int calibrate_copass(ng_ctx* c) {
 
 }  // namespace
 
-int calibrate_many(ng_ctx* const* cs, uint32_t n, const Uploader* upload) {
+int calibrate_many(ng_ctx* const* cs, uint32_t n, const Uploader* upload, ScratchBump* sb) {
   if (n == 0) return NG_OK;
   if (!cs) return fail(NG_ERR_INVALID_ARG, "null context array");
+  if (sb && n != 1) return fail(NG_ERR_INVALID_ARG, "internal: fixed scratch serves one context");
   for (uint32_t i = 0; i < n; ++i) {
     if (int rc = enter(cs[i])) return rc;
     if (int rc = mutable_state(cs[i])) return rc;
@@ -936,8 +977,10 @@ int calibrate_many(ng_ctx* const* cs, uint32_t n, const Uploader* upload) {
     }
   if (segs.empty()) return NG_OK;
   if (hipSetDevice(segs[0].c->device) != hipSuccess) return fail(NG_ERR_DEVICE, "hipSetDevice");
-  for (auto& g : segs)
+  for (auto& g : segs) {
     if (int rc = cal_plan(g)) return rc;
+    g.sb = sb;
+  }
   ng_ctx* c0 = segs[0].c;
   const bool multi = segs.size() > 1;
 
@@ -980,11 +1023,17 @@ int calibrate_many(ng_ctx* const* cs, uint32_t n, const Uploader* upload) {
     }
   }
   AllocSet shared(c0);
-  uint32_t* counts = (uint32_t*)shared.get(4 * std::max<uint64_t>(counts_max, 1));
+  auto sget = [&](uint64_t bytes) { return sb ? sb->get(bytes) : shared.get(bytes); };
+  uint32_t* counts = (uint32_t*)sget(4 * std::max<uint64_t>(counts_max, 1));
   const uint64_t tmp_words = std::max(ng::scan_tmp_words(counts_max), ng::scan_tmp_words(total_tiles));
-  uint32_t* scan_tmp = (uint32_t*)shared.get(4 * tmp_words);
-  uint32_t* tile_flags = (uint32_t*)shared.get(4 * (total_tiles + 1));
+  uint32_t* scan_tmp = (uint32_t*)sget(4 * tmp_words);
+  uint32_t* tile_flags = (uint32_t*)sget(4 * (total_tiles + 1));
   char* d_tables = tables ? shared.get(tables) : nullptr;
+  if (sb && !sb->ok) {
+    for (auto& g : segs) cal_release(g);
+    return fail(NG_ERR_TOO_LARGE, "the calibration scratch exceeds the fixed %llu-byte region",
+                (unsigned long long)sb->cap);
+  }
   if (!shared.ok) {
     const uint64_t asked = shared.asked;
     shared.release_all();
@@ -1565,6 +1614,23 @@ int ng_set_calibration(ng_ctx* c, int algorithm) {
 }
 
 int ng_calibrate(ng_ctx* c) { return calibrate_many(&c, 1); }
+
+int ng_calibrate_noalloc(ng_ctx* c) {
+  if (int rc = enter(c)) return rc;
+  if (int rc = mutable_state(c)) return rc;
+  if (c->calibrated) return NG_OK;
+  if (c->calib_mode == NG_CALIB_COPASS)
+    return fail(NG_ERR_UNSUPPORTED, "the fixed-scratch calibration is the radix sort; the context is in COPASS mode");
+  if (c->shared_arena)
+    return fail(NG_ERR_UNSUPPORTED, "the fixed-scratch calibration needs a context with its own arena");
+  ScratchBump sb;
+  sb.base = noalloc_scratch_ptr(c->device);
+  sb.cap = kNoAllocScratchBytes;
+  if (!sb.base) return fail(NG_ERR_STATE, "the fixed scratch of this device was not set up");
+  return calibrate_many(&c, 1, nullptr, &sb);
+}
+
+uint64_t ng_noalloc_scratch_bytes(void) { return kNoAllocScratchBytes; }
 
 int ng_calibrate_many(ng_ctx* const* ctxs, uint32_t n) { return calibrate_many(ctxs, n); }
 

@@ -124,6 +124,8 @@ def lib():
                                   P(u64)], ctypes.c_int),
             "ng_calibrate": ([vp], ctypes.c_int),
             "ng_calibrate_many": ([P(vp), ctypes.c_uint32], ctypes.c_int),
+            "ng_calibrate_noalloc": ([vp], ctypes.c_int),
+            "ng_noalloc_scratch_bytes": ([], ctypes.c_uint64),
             "ng_sync": ([vp], ctypes.c_int),
             "ng_get_connections": ([vp, P(ng_conn_view)], ctypes.c_int),
             "ng_copy_connections": ([vp, u64, u64, vp, vp, vp, vp], ctypes.c_int),
@@ -278,6 +280,15 @@ def ng_connect_batch(ctx, srcs, tgts, conns, syns):
 
 def ng_calibrate(ctx) -> None:
     _check(lib().ng_calibrate(ctx))
+
+
+def ng_calibrate_noalloc(ctx) -> None:
+    """ng_calibrate with its scratch in the library's fixed device region."""
+    _check(lib().ng_calibrate_noalloc(ctx))
+
+
+def ng_noalloc_scratch_bytes() -> int:
+    return int(lib().ng_noalloc_scratch_bytes())
 
 
 def ng_calibrate_many(ctxs) -> None:
