@@ -327,8 +327,24 @@ int ng_spikes_step(ng_ctx* ctx, const uint32_t* nodes, const uint32_t* mult, uin
 
 /* Calibration algorithm of a context; the calibrated arrays and group index
  * are the same with either (stable order by (source, delay), Sec. 2.2).
- *   NG_CALIB_RADIX (default): stable LSD radix sort of all connections into
- *     a second block set (peak scratch ~ 38 bytes per connection).
+ *   NG_CALIB_RADIX (default): stable radix sort of all connections into a
+ *     second block set, in the most-significant-digit form (below) when one
+ *     context is calibrated, its keys (source bits + delay bits) fit in 27
+ *     bits and its connections average at least 256 per sub-bucket, else in
+ *     the LSD form.
+ *   NG_CALIB_RADIX_MSD: the most-significant-digit form whenever one context
+ *     with keys of at most 27 bits is calibrated (else LSD): a scatter by
+ *     the top digit, a scatter of each bucket by the second digit, and runs
+ *     of whole sub-buckets sorted by the last digit in on-chip memory and
+ *     written straight into the calibrated blocks with their connection
+ *     groups; the records between passes carry only the key bits not yet
+ *     applied, packed with the target into one word when they fit (peak
+ *     scratch 16-24 bytes per connection).  Packed calibrations
+ *     (ng_calibrate_many with several contexts) and ng_calibrate_noalloc
+ *     always use the LSD form.
+ *   NG_CALIB_RADIX_LSD: stable least-significant-digit radix sort (digit
+ *     passes of at most 9 bits over the whole key, then a group-index pass;
+ *     peak scratch ~ 38 bytes per connection).
  *   NG_CALIB_COPASS: the COPASS in-place block sort of Appendix A.  Each
  *     block is sorted, then block b = 0, 1, ... is filled with the next
  *     block-size smallest connections: a threshold partition of the sorted
@@ -341,7 +357,7 @@ int ng_spikes_step(ng_ctx* ctx, const uint32_t* nodes, const uint32_t* mult, uin
  *     synchronizes and cannot be captured (NG_ERR_UNSUPPORTED); in
  *     ng_calibrate_many such contexts are calibrated one by one.
  * Returns NG_OK, or NG_ERR_INVALID_ARG for another value. */
-enum { NG_CALIB_RADIX = 0, NG_CALIB_COPASS = 1 };
+enum { NG_CALIB_RADIX = 0, NG_CALIB_COPASS = 1, NG_CALIB_RADIX_LSD = 2, NG_CALIB_RADIX_MSD = 3 };
 int ng_set_calibration(ng_ctx* ctx, int algorithm);
 
 /* Arena bytes in use now, at peak, and the largest free extent. */
@@ -457,6 +473,22 @@ const char* ng_last_error(void);
  * size block_size, given n_blocks already allocated (never negative). */
 uint64_t ng_blocks_needed(uint64_t n_conns, uint64_t n_new, uint64_t block_size,
                           uint64_t n_blocks);
+
+/* Digit plan that the default calibration (NG_CALIB_RADIX) takes for one
+ * context of n_conns connections over n_nodes nodes whose delays are at most
+ * max_delay steps, with sort_ranges static ranges per scatter pass (the
+ * ng_set_tuning value, 1024 by default).  out[0] = 2 when the default
+ * calibration takes the most-significant-digit form, 1 when only
+ * NG_CALIB_RADIX_MSD takes it (too few connections per sub-bucket), 0 when
+ * it does not apply (keys wider than 27 bits, n_conns = 0 or >= 2^32; the
+ * rest is then zero); out[1..3] = the widths b1, b2, b3
+ * of the digits from the top (b2 = 0: no second scatter); out[4], out[5] =
+ * 1 when the records after the first / second scatter pack the remaining
+ * key bits and the target into one word; out[6] = workgroups of the
+ * in-LDS pass; out[7] = tiles per range.  Returns NG_OK, or
+ * NG_ERR_INVALID_ARG for a null out or max_delay < 1. */
+int ng_calibration_plan(uint64_t n_conns, uint32_t n_nodes, int32_t max_delay, uint32_t sort_ranges,
+                        uint32_t out[8]);
 
 /* Validate a Connect call against n_nodes existing nodes and return the
  * number of connections it creates (Sec. 2.1). */

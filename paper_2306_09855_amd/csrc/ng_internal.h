@@ -158,6 +158,7 @@ struct MsdPlan {
   uint32_t keybits, dbits, tbits;   // tbits: bits of a target index (nodes - 1)
   uint32_t b1, b2, b3;
   uint32_t narrow_a, narrow_b;      // formats of the output of A and of B
+  uint32_t cbits;                   // packed records entering pass C: key bits held above the target
   uint32_t tpr;                     // tiles per range (passes A and B)
   uint32_t ranges_a;                // ranges of pass A
   uint32_t max_ranges_b;            // ranges of pass B: at most this many
@@ -175,6 +176,9 @@ struct MsdPlan {
   uint32_t* rangeb0;                // [2^b1 + 1] first range of pass B of each bucket
   uint32_t* sbstart;                // [2^(b1+b2) + 1] sub-bucket starts
   uint32_t* wg_sb0;                 // [wgs_c + 1] first sub-bucket of each workgroup of C
+  uint32_t* big_count;              // sub-buckets larger than one LDS load (set by pass C)
+  uint32_t* big_list;               // [max_big] their numbers
+  uint32_t max_big;                 // n / (one load + 1) + 1
   uint32_t* gcount;                 // [2^(b1+b2) + 1] groups per sub-bucket, scanned in place
   uint32_t* gmask;                  // [2^(b1+b2) * mask_words] present D3 values per sub-bucket
   uint32_t* gslot;                  // [n] local group starts at sub-bucket offsets (scratch)
@@ -184,8 +188,9 @@ struct MsdPlan {
   uint32_t* n_groups;               // G (device word)
 };
 
-// Largest sub-bucket that pass C sorts in LDS in one piece (larger ones are
-// sorted in pieces of this size, with a counting pre-pass).
+// Records pass C sorts in LDS at once: runs of whole sub-buckets up to this
+// many records form one tile; a larger sub-bucket is sorted in pieces of
+// this size after a counting pass.
 uint32_t msd_cap(bool narrow);
 hipError_t launch_msd_count_a(const MsdPlan& p, hipStream_t s);
 hipError_t launch_msd_scatter_a(const MsdPlan& p, hipStream_t s);

@@ -35,8 +35,6 @@ constexpr int kMItems = 20;
 static_assert(kMThreads * kMItems == (int)kMsdTile, "tile of passes A and B");
 constexpr int kMNB = 1 << kMsdMaxDigit;  // 512 digit values at most
 static_assert(kMNB == kMThreads, "one thread per digit value");
-constexpr int kCItemsN = 24;  // pass C, narrow records: 12288 per piece
-constexpr int kCItemsW = 20;  // pass C, wide records: 10,240 per piece
 constexpr int kMLdsBlocks = 512;
 
 enum { IN_BLOCKS = 0, IN_NARROW = 1, IN_WIDE = 2 };
@@ -92,20 +90,24 @@ __device__ __forceinline__ void load_blocks(char* const* blocks, int log2B, uint
   const uint32_t b0 = base >> log2B;
   const char* blk0 = C(blocks, b0);
   const char* blk1 = C(blocks, (base + cnt - 1) >> log2B);
+// Each slot's values are selected, not stored on two paths, so that the
+// record arrays stay in registers.
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k) {
     const uint32_t lj = item_index(ITEMS, k);
+    uint32_t kv = 0, tv = 0, wv = 0;
     if (FULL || lj < cnt) {
       const uint32_t j = base + lj;
       const char* blk = (j >> log2B) != b0 ? blk1 : blk0;
       const uint64_t o = j & (B - 1);
       const uint32_t s = G(reinterpret_cast<const uint32_t*>(blk))[o];
-      r.t[k] = G(reinterpret_cast<const uint32_t*>(blk + 4 * B))[o];
-      r.w[k] = G(reinterpret_cast<const uint32_t*>(blk + 8 * B))[o];
-      r.k[k] = (s << dbits) | (uint16_t)G(reinterpret_cast<const int16_t*>(blk + 12 * B))[o];
-    } else {
-      r.k[k] = r.t[k] = r.w[k] = 0;
+      tv = G(reinterpret_cast<const uint32_t*>(blk + 4 * B))[o];
+      wv = G(reinterpret_cast<const uint32_t*>(blk + 8 * B))[o];
+      kv = (s << dbits) | (uint16_t)G(reinterpret_cast<const int16_t*>(blk + 12 * B))[o];
     }
+    r.k[k] = kv;
+    r.t[k] = tv;
+    r.w[k] = wv;
   }
 }
 
@@ -115,14 +117,15 @@ __device__ __forceinline__ void load_arrays(const uint32_t* ik, const uint32_t* 
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k) {
     const uint32_t lj = item_index(ITEMS, k);
+    uint32_t kv = 0, tv = 0, wv = 0;
     if (FULL || lj < cnt) {
-      r.k[k] = G(ik)[base + lj];
-      if constexpr (IN == IN_WIDE) r.t[k] = G(it)[base + lj];
-      r.w[k] = G(iw)[base + lj];
-    } else {
-      r.k[k] = r.w[k] = 0;
-      if constexpr (IN == IN_WIDE) r.t[k] = 0;
+      kv = G(ik)[base + lj];
+      if constexpr (IN == IN_WIDE) tv = G(it)[base + lj];
+      wv = G(iw)[base + lj];
     }
+    r.k[k] = kv;
+    r.t[k] = tv;
+    r.w[k] = wv;
   }
 }
 
@@ -132,12 +135,14 @@ __device__ __forceinline__ void load_arrays(const uint32_t* ik, const uint32_t* 
 // peers in lower lanes.  The lowest peer adds the slot's count to the wave's
 // counter of that digit with one LDS atomic (other lanes add to a private
 // word), and the old value reaches its peers through a lane permute a few
-// slots later, so no slot waits on the one before it.  On return pos[k] is
-// the rank within the wave's records of the digit, and wh[wave][d] holds the
-// wave's count of digit d.
+// slots later, so no slot waits on the one before it.  The digit of a key is
+// ((key >> shift) - base) & mask.  On return pos[k] is the rank within the
+// wave's records of the digit, and wh[wave][d] holds the wave's count of
+// digit d.
 template <int RB, int ITEMS, bool FULL>
 __device__ __forceinline__ void rank_digits(const uint32_t (&key)[ITEMS], uint32_t shift, uint32_t mask, uint32_t cnt,
-                                            uint32_t* wh, uint32_t* sink, uint32_t (&pos)[ITEMS]) {
+                                            uint32_t* wh, uint32_t* sink, uint32_t (&pos)[ITEMS],
+                                            uint32_t base = 0) {
   constexpr int kLag = 4;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t prv[ITEMS];
@@ -148,7 +153,7 @@ __device__ __forceinline__ void rank_digits(const uint32_t (&key)[ITEMS], uint32
     if (k < ITEMS && slot_used(k)) {
       const uint32_t lj = (uint32_t)(wave * ITEMS * 64 + k * 64 + lane);
       const bool valid = FULL || lj < cnt;
-      const uint32_t d = (key[k] >> shift) & mask;
+      const uint32_t d = ((key[k] >> shift) - base) & mask;
       uint32_t plo = ~0u, phi = ~0u;
       if (!FULL) {
         const uint64_t v = __ballot(valid);
@@ -400,7 +405,7 @@ __global__ __launch_bounds__(kMThreads) void k_msd_scatter_b(MsdPlan p) {
   io.shift = (IN == IN_NARROW ? p.tbits : 0u) + p.b3;
   io.mask = nd - 1;
   io.tbits = p.tbits;
-  io.remmask = (1u << p.b3) - 1u;
+  io.remmask = (1u << p.cbits) - 1u;  // packed from full keys: as many low key bits as fit
   const uint64_t cb = ((uint64_t)s_rb0[b] << p.b2) + rl;
   for (uint32_t d = threadIdx.x; d < (uint32_t)kMNB; d += kMThreads) {
     s_run[d] = d < nd ? p.cnt_b[cb + (uint64_t)d * nr] : 0u;
@@ -484,8 +489,34 @@ __global__ __launch_bounds__(kMThreads) void k_msd_count_b(MsdPlan p) {
   const uint32_t shift = (IN == IN_NARROW ? p.tbits : 0u) + p.b3;
   const uint32_t lo = bs + rl * p.tpr * kMsdTile;
   const uint32_t hi = (be - lo) / kMsdTile < p.tpr ? be : lo + p.tpr * kMsdTile;
-  for (uint32_t j = lo + threadIdx.x; j < hi; j += kMThreads)
-    atomicAdd(&hist[(G(p.a_key)[j] >> shift) & (nd - 1)], 1u);
+  // 16-byte loads over the aligned middle (the key array starts 256-byte
+  // aligned), four in flight per thread; single words at the ends
+  const uint32_t a0 = min(hi, (lo + 3u) & ~3u), a1 = max(a0, hi & ~3u);
+  auto add = [&](uint32_t k) { atomicAdd(&hist[(k >> shift) & (nd - 1)], 1u); };
+  if (lo + threadIdx.x < a0) add(G(p.a_key)[lo + threadIdx.x]);
+  if (a1 + threadIdx.x < hi) add(G(p.a_key)[a1 + threadIdx.x]);
+  const NG_GLOBAL u32x4* v = (const NG_GLOBAL u32x4*)(p.a_key + a0);
+  const uint32_t nq = (a1 - a0) / 4;
+  uint32_t q = threadIdx.x;
+  for (; q + 3 * kMThreads < nq; q += 4 * kMThreads) {
+    u32x4 x[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) x[u] = v[q + u * kMThreads];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      add(x[u].x);
+      add(x[u].y);
+      add(x[u].z);
+      add(x[u].w);
+    }
+  }
+  for (; q < nq; q += kMThreads) {
+    const u32x4 x = v[q];
+    add(x.x);
+    add(x.y);
+    add(x.z);
+    add(x.w);
+  }
   __syncthreads();
   const uint64_t cb = ((uint64_t)s_rb0[b] << p.b2) + rl;
   for (uint32_t d = threadIdx.x; d < nd; d += kMThreads) p.cnt_b[cb + (uint64_t)d * nr] = hist[d];
@@ -534,16 +565,25 @@ __global__ __launch_bounds__(256) void k_msd_plan_c(MsdPlan p) {
   if (sb == 0) p.sbstart[nsb] = p.n;
 }
 
+// Group counts and masks of all sub-buckets start at zero; pass C writes
+// those of the sub-buckets that hold records.
+__global__ __launch_bounds__(256) void k_msd_zero(MsdPlan p) {
+  const uint64_t nsb = 1ull << (p.b1 + p.b2);
+  const uint64_t stride = (uint64_t)gridDim.x * 256u;
+  for (uint64_t i = blockIdx.x * 256ull + threadIdx.x; i < nsb; i += stride) G(p.gcount)[i] = 0;
+  for (uint64_t i = blockIdx.x * 256ull + threadIdx.x; i < nsb * p.mask_words; i += stride) G(p.gmask)[i] = 0;
+}
+
 // Workgroup w of pass C takes the sub-buckets whose first record lies in
 // [w * n / wgs, (w + 1) * n / wgs): a split by records.
 __global__ __launch_bounds__(256) void k_msd_split(MsdPlan p) {
   const uint32_t nsb = 1u << (p.b1 + p.b2);
   const uint32_t w = blockIdx.x * 256u + threadIdx.x;
+  if (w == 0) *p.big_count = 0;  // sub-buckets listed by pass C
   if (w > p.wgs_c) return;
-  if (w == p.wgs_c) {
-    p.wg_sb0[w] = nsb;
-    return;
-  }
+  // the last boundary is the first sub-bucket past the records: the empty
+  // sub-buckets above it are never visited (their group counts and masks are
+  // zero from k_msd_zero)
   const uint32_t target = (uint32_t)((uint64_t)w * p.n / p.wgs_c);
   uint32_t lo = 0, hi = nsb;  // first sb with sbstart[sb] >= target
   while (lo < hi) {
@@ -555,33 +595,160 @@ __global__ __launch_bounds__(256) void k_msd_split(MsdPlan p) {
 }
 
 // ---------------------------------------------------------------------------
-// Pass C: each sub-bucket sorted by D3 in LDS, written as calibrated blocks.
+// Pass C: runs of whole sub-buckets sorted in LDS, written as calibrated
+// blocks.
 // ---------------------------------------------------------------------------
+// A tile is a run of consecutive sub-buckets [sb, e) holding at most one
+// LDS load of records, with at most kCMaxSub sub-buckets; sorting it by the
+// combined digit (sub-bucket offset in the run, D3) sorts every sub-bucket by
+// D3, and its sorted order is its final order, so the tile is written to
+// [sbstart[sb], sbstart[e]) as one contiguous run.  A sub-bucket larger than
+// one load is its own tile and is sorted in pieces after a counting pass.
 // Output block of a sorted position: from the LDS copy of the block table
 // when it holds all of them.
 __device__ __forceinline__ char* m_out_block(const MsdPlan& p, char* const* s_blk, uint32_t dest) {
   return s_blk ? s_blk[dest >> p.log2B] : C(p.out_blocks, dest >> p.log2B);
 }
 
-template <int RB, bool NARROW>
-__global__ __launch_bounds__(kMThreads) void k_msd_local_c(MsdPlan p) {
-  constexpr int ITEMS = NARROW ? kCItemsN : kCItemsW;
-  constexpr uint32_t CAP = (uint32_t)(ITEMS * kMThreads);
-  __shared__ uint32_t s_k[CAP];
-  __shared__ uint32_t s_t[NARROW ? 1 : CAP];
-  __shared__ uint32_t s_w[CAP];
-  __shared__ uint32_t s_wh[kMWaves * kMNB];
-  __shared__ uint32_t s_hist[kMNB];  // counts of the sub-bucket per D3 value
-  __shared__ uint32_t s_cur[kMNB];   // next output position per D3 value
-  __shared__ uint32_t s_dx[kMNB];    // output position minus piece position, per D3 value
-  __shared__ uint32_t s_tmp[kMWaves];
-  __shared__ uint32_t s_sink[kMThreads];
+constexpr uint32_t kCTile = kMsdTile;  // records per LDS load
+constexpr uint32_t kCMaxSub = 63;      // sub-buckets per tile: lanes 1..63 test the ends
+
+// Sub-buckets per tile: bounded by the lanes of one wave, by 9-bit combined
+// digits, and for packed records by the sub-bucket bits they hold.
+__host__ __device__ inline uint32_t msd_max_sub(const MsdPlan& p, bool narrow) {
+  uint32_t m = kCMaxSub < (512u >> p.b3) ? kCMaxSub : (512u >> p.b3);
+  if (narrow) {
+    const uint32_t own = 1u << (p.cbits - p.b3);
+    m = m < own ? m : own;
+  }
+  return m;
+}
+
+struct CTile {
+  uint32_t sb, e, r0, r1;  // sub-buckets [sb, e), records [r0, r1); e == sb: no tile left
+};
+
+// The next tile from sub-bucket sb in [sb, sb_end), found by one wave in
+// two steps so that the load's latency can hide behind other work: the
+// probe reads the starts of sub-buckets sb .. sb + lim (lane l: sb +
+// min(l, lim), lim = min(63, sb_end - sb)); the finish takes the longest run
+// of at most m sub-buckets whose records fit one load (sub-bucket starts
+// ascend, so the runs that fit form a prefix of the lanes).  A run that
+// starts with empty sub-buckets becomes a tile of those alone (no records;
+// their group counts and masks are already zero).  Wave 0 only.
+__device__ __forceinline__ uint32_t tile_probe(const MsdPlan& p, uint32_t sb, uint32_t lim) {
+  const uint32_t lane = threadIdx.x & 63;
+  return G(p.sbstart)[sb + min(lane, lim)];
+}
+
+__device__ __forceinline__ CTile tile_finish(uint32_t st, uint32_t sb, uint32_t lim, uint32_t m) {
+  const uint32_t lane = threadIdx.x & 63;
+  CTile t{sb, sb, 0, 0};
+  if (lim == 0) return t;
+  const uint32_t r0 = (uint32_t)__shfl(st, 0);
+  t.r0 = t.r1 = r0;
+  if ((uint32_t)__shfl(st, 1) == r0) {  // empty sub-buckets first
+    t.e = sb + (uint32_t)__popcll(__ballot(lane <= lim && st == r0)) - 1u;
+    return t;
+  }
+  const bool ok = lane <= min(lim, m) && st - r0 <= kCTile;
+  const uint32_t L = (uint32_t)__popcll(__ballot(ok)) - 1u;  // lane 0 always fits
+  const uint32_t Lx = L ? L : 1u;
+  t.e = sb + Lx;
+  t.r1 = (uint32_t)__shfl(st, (int)Lx);
+  return t;
+}
+
+// One predicated form of each step: pass C keeps a single copy of its
+// load and ranking, which keeps its loop within the register file.
+template <bool NARROW>
+__device__ __forceinline__ void load_c(const uint32_t* ik, const uint32_t* it, const uint32_t* iw, uint32_t base,
+                                       uint32_t cnt, Recs<kMItems>& r) {
+  load_arrays<kMItems, NARROW ? IN_NARROW : IN_WIDE, false>(ik, it, iw, base, cnt, r);
+}
+
+__device__ __forceinline__ bool tile_fits(const CTile& t) {
+  return t.e > t.sb && t.r1 > t.r0 && t.r1 - t.r0 <= kCTile;
+}
+
+// The connection groups of a tile of nsub sub-buckets from sba whose records
+// start at r0 (Sec. 2.2): each present combined digit (thread d, h = its
+// record count, 0 past the tile's digits) is a group.  Its start goes to its
+// sub-bucket's offset in gslot, at the group's rank in the sub-bucket; each
+// sub-bucket gets its group count and its mask of present D3 values.  Leaves
+// s_st[d] = the tile position of digit d's first record.  All threads call;
+// ends with a barrier.
+__device__ __forceinline__ void tile_groups(const MsdPlan& p, uint32_t sba, uint32_t nsub, uint32_t r0, uint32_t h,
+                                            uint32_t* s_ex, uint32_t* s_st, uint32_t* s_tmp, uint32_t* s_bal) {
+  const uint32_t d = threadIdx.x, lane = d & 63, wave = d >> 6;
+  const uint32_t b3 = p.b3, m3 = (1u << b3) - 1u, nd = nsub << b3;
+  const bool present = h != 0;
+  uint32_t all, cnt_all;
+  const uint32_t ex = m_block_scan(present ? 1u : 0u, s_tmp, &all);
+  const uint32_t hst = m_block_scan(h, s_tmp, &cnt_all);
+  const uint64_t bal = __ballot(present);
+  s_ex[d] = ex;
+  s_st[d] = hst;
+  if (lane == 0) {
+    s_bal[2 * wave] = (uint32_t)bal;
+    s_bal[2 * wave + 1] = (uint32_t)(bal >> 32);
+  }
+  if (d == 0) s_ex[kMNB] = all;
+  lds_barrier();
+  if (present) {
+    const uint32_t d0 = d & ~m3;  // first digit of its sub-bucket
+    G(p.gslot)[r0 + s_st[d0] + (ex - s_ex[d0])] = r0 + hst;
+  }
+  if (d < nsub) {
+    const uint32_t hi = d + 1 < nsub ? s_ex[(d + 1) << b3] : s_ex[kMNB];
+    G(p.gcount)[sba + d] = hi - s_ex[d << b3];
+  }
+  if (d < nd) {
+    if (b3 >= 5) {
+      if ((d & 31u) == 0) G(p.gmask)[(uint64_t)(sba + (d >> b3)) * p.mask_words + ((d & m3) >> 5)] = s_bal[d >> 5];
+    } else if ((d & m3) == 0) {
+      G(p.gmask)[sba + (d >> b3)] = (s_bal[d >> 5] >> (d & 31u)) & ((1u << (1u << b3)) - 1u);
+    }
+  }
+  lds_barrier();
+}
+
+#define M_C_LDS                                  \
+  __shared__ uint32_t s_k[kCTile];               \
+  __shared__ uint32_t s_t[NARROW ? 1 : kCTile];  \
+  __shared__ uint32_t s_w[kCTile];               \
+  __shared__ uint32_t s_wh[kMWaves * kMNB];      \
+  __shared__ uint32_t s_st[kMNB + 1];            \
+  __shared__ uint32_t s_ex[kMNB + 1];            \
+  __shared__ uint32_t s_tmp[kMWaves];            \
+  __shared__ uint32_t s_sink[kMThreads];         \
+  __shared__ uint32_t s_bal[kMNB / 32];          \
   __shared__ char* s_blk_tab[kMLdsBlocks];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const uint32_t nd = 1u << p.b3, m3 = nd - 1;
-  const uint32_t kshift = NARROW ? p.tbits : 0u;
-  const uint32_t tmask = NARROW ? ((1u << p.tbits) - 1u) : ~0u;
-  const uint32_t dmask = (1u << p.dbits) - 1u;
+
+// Key-field constants of pass C: a record holds the low cbits key bits above
+// its target (packed) or the whole key, so the combined digit of a tile is
+// ((k >> ks) - base) & km with base = (first sub-bucket << b3) & km.
+struct CFields {
+  uint32_t ks, km, msub, tmask, dmask;
+  const uint32_t *ik, *it, *iw;
+};
+
+template <bool NARROW>
+__device__ __forceinline__ CFields c_fields(const MsdPlan& p) {
+  CFields f;
+  f.ks = NARROW ? p.tbits : 0u;
+  f.km = NARROW ? ((1u << p.cbits) - 1u) : ((1u << p.keybits) - 1u);
+  f.msub = msd_max_sub(p, NARROW);
+  f.tmask = NARROW ? ((1u << p.tbits) - 1u) : ~0u;
+  f.dmask = (1u << p.dbits) - 1u;
+  f.ik = p.b2 ? p.b_key : p.a_key;
+  f.it = p.b2 ? p.b_tgt : p.a_tgt;
+  f.iw = p.b2 ? p.b_w : p.a_w;
+  return f;
+}
+
+// Block table in LDS when it fits; clears the per-wave digit counters.
+__device__ __forceinline__ char* const* c_setup(const MsdPlan& p, char** s_blk_tab, uint32_t* s_wh) {
   const uint32_t n_out_blocks = (uint32_t)(((uint64_t)p.n + (1ull << p.log2B) - 1) >> p.log2B);
   char* const* s_blk = n_out_blocks <= (uint32_t)kMLdsBlocks ? s_blk_tab : nullptr;
   if (s_blk)
@@ -590,97 +757,171 @@ __global__ __launch_bounds__(kMThreads) void k_msd_local_c(MsdPlan p) {
 #pragma unroll
     for (int v = 0; v < kMWaves; ++v) s_wh[v * kMNB + d] = 0;
   }
-  const uint32_t* ik = p.b2 ? p.b_key : p.a_key;
-  const uint32_t* it = p.b2 ? p.b_tgt : p.a_tgt;
-  const uint32_t* iw = p.b2 ? p.b_w : p.a_w;
+  return s_blk;
+}
+
+// Records staged in sorted order at [0, cnt) of the LDS arrays go out to
+// their positions: dest = dx[digit] + lp (or r0 + lp when dx is null).
+template <bool NARROW>
+__device__ __forceinline__ void c_store(const MsdPlan& p, const CFields& f, char* const* s_blk, const uint32_t* s_k,
+                                        const uint32_t* s_t, const uint32_t* s_w, uint32_t cnt, uint32_t base,
+                                        uint32_t kb, const uint32_t* dx, uint32_t r0) {
   const uint64_t B = 1ull << p.log2B;
-  const uint32_t sb0 = p.wg_sb0[blockIdx.x], sb1 = p.wg_sb0[blockIdx.x + 1];
+#pragma unroll
+  for (int k = 0; k < kMItems; ++k) {
+    const uint32_t lp = (uint32_t)(k * kMThreads + threadIdx.x);
+    if (lp < cnt) {
+      const uint32_t kk = s_k[lp];
+      const uint32_t dg = ((kk >> f.ks) - base) & f.km;
+      const uint32_t dest = dx ? dx[dg] + lp : r0 + lp;
+      const uint32_t key = kb + dg;
+      char* blk = m_out_block(p, s_blk, dest);
+      const uint64_t o = dest & (B - 1);
+      G(reinterpret_cast<uint32_t*>(blk))[o] = key >> p.dbits;
+      G(reinterpret_cast<uint32_t*>(blk + 4 * B))[o] = NARROW ? (kk & f.tmask) : s_t[lp];
+      G(reinterpret_cast<uint32_t*>(blk + 8 * B))[o] = s_w[lp];
+      G(reinterpret_cast<int16_t*>(blk + 12 * B))[o] = (int16_t)(key & f.dmask);
+    }
+  }
+}
+
+// Records ranked by their combined digit move to their sorted places in LDS.
+template <bool NARROW>
+__device__ __forceinline__ void c_stage(const CFields& f, const Recs<kMItems>& r, const uint32_t (&pos)[kMItems],
+                                        uint32_t cnt, uint32_t base, const uint32_t* s_wh, uint32_t* s_k, uint32_t* s_t,
+                                        uint32_t* s_w) {
+  const int wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < kMItems; ++k) {
+    if (item_index(kMItems, k) < cnt) {
+      const uint32_t dg = ((r.k[k] >> f.ks) - base) & f.km;
+      const uint32_t q = pos[k] + s_wh[wave * kMNB + dg];
+      s_k[q] = r.k[k];
+      if constexpr (!NARROW) s_t[q] = r.t[k];
+      s_w[q] = r.w[k];
+    }
+  }
+}
+
+__device__ __forceinline__ void clear_wh(uint32_t* s_wh) {
+  for (uint32_t e = threadIdx.x; e < (uint32_t)kMNB; e += kMThreads) {
+#pragma unroll
+    for (int v = 0; v < kMWaves; ++v) s_wh[v * kMNB + e] = 0;
+  }
+}
+
+// Tiles of the workgroup's sub-buckets [wg_sb0[w], wg_sb0[w + 1]); the
+// records of the next tile load while a tile is written.  Sub-buckets larger
+// than one load are listed for k_msd_big_c.
+template <int RB, bool NARROW>
+__global__ __launch_bounds__(kMThreads) void k_msd_tiles_c(MsdPlan p) {
+  M_C_LDS
+  __shared__ CTile s_next;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const CFields f = c_fields<NARROW>(p);
+  char* const* s_blk = c_setup(p, s_blk_tab, s_wh);
+  const uint32_t b3 = p.b3;
+  const uint32_t sb0 = p.wg_sb0[blockIdx.x], sb_end = p.wg_sb0[blockIdx.x + 1];
+  if (wave == 0) {
+    const uint32_t lim = min(kCMaxSub, sb_end - sb0);
+    const CTile t = tile_finish(tile_probe(p, sb0, lim), sb0, lim, f.msub);
+    if (lane == 0) s_next = t;
+  }
   lds_barrier();
-  for (uint32_t sb = sb0; sb < sb1; ++sb) {
-    const uint32_t start = p.sbstart[sb], n = p.sbstart[sb + 1] - start;
-    if (n == 0) {  // no records, no groups
-      uint32_t* gm = p.gmask + (uint64_t)sb * p.mask_words;
-      for (uint32_t w = threadIdx.x; w < p.mask_words; w += kMThreads) G(gm)[w] = 0;
-      if (threadIdx.x == 0) G(p.gcount)[sb] = 0;
-      continue;
+  CTile cur = s_next;
+  lds_barrier();  // read by all before wave 0 writes the next one
+  Recs<kMItems> r;
+  // invariant at the top of the loop: loaded == tile_fits(cur), and then r
+  // holds cur's records
+  bool loaded = tile_fits(cur);
+  if (loaded) load_c<NARROW>(f.ik, f.it, f.iw, cur.r0, cur.r1 - cur.r0, r);
+  while (cur.e > cur.sb) {
+    const uint32_t n = cur.r1 - cur.r0;
+    const uint32_t nsub = cur.e - cur.sb;
+    const uint32_t lim = min(kCMaxSub, sb_end - cur.e);
+    uint32_t probe = 0;
+    if (wave == 0) probe = tile_probe(p, cur.e, lim);  // used after the ranking
+    if (n == 0 || n > kCTile) {
+      // empty sub-buckets: nothing to do; one sub-bucket too large for one
+      // load: listed for k_msd_big_c
+      if (n && threadIdx.x == 0) G(p.big_list)[atomicAdd(p.big_count, 1u)] = cur.sb;
+      if (wave == 0) {
+        const CTile t = tile_finish(probe, cur.e, lim, f.msub);
+        if (lane == 0) s_next = t;
+      }
+    } else {
+      const uint32_t base = (cur.sb << b3) & f.km;
+      uint32_t pos[kMItems];
+      rank_digits<RB, kMItems, false>(r.k, f.ks, f.km, n, s_wh, s_sink, pos, base);
+      if (wave == 0) {
+        const CTile t = tile_finish(probe, cur.e, lim, f.msub);
+        if (lane == 0) s_next = t;
+      }
+      lds_barrier();
+      uint32_t st;
+      const uint32_t d = threadIdx.x, nd = nsub << b3;
+      const uint32_t tot = digit_starts(nd, s_wh, s_tmp, &st);
+      tile_groups(p, cur.sb, nsub, cur.r0, d < nd ? tot : 0u, s_ex, s_st, s_tmp, s_bal);
+      c_stage<NARROW>(f, r, pos, n, base, s_wh, s_k, s_t, s_w);
+      lds_barrier();
+      clear_wh(s_wh);
+      const CTile nx = s_next;
+      loaded = tile_fits(nx);
+      if (loaded) load_c<NARROW>(f.ik, f.it, f.iw, nx.r0, nx.r1 - nx.r0, r);
+      c_store<NARROW>(p, f, s_blk, s_k, s_t, s_w, n, base, cur.sb << b3, nullptr, cur.r0);
     }
-    if (n > CAP) {  // counting pre-pass over the whole sub-bucket
-      for (uint32_t d = threadIdx.x; d < (uint32_t)kMNB; d += kMThreads) s_hist[d] = 0;
-      lds_barrier();
-      for (uint32_t j = threadIdx.x; j < n; j += kMThreads)
-        atomicAdd(&s_hist[(G(ik)[start + j] >> kshift) & m3], 1u);
-      lds_barrier();
+    lds_barrier();  // s_next is complete; the tile's LDS is free
+    const CTile nx = s_next;
+    if (!loaded && tile_fits(nx)) {
+      load_c<NARROW>(f.ik, f.it, f.iw, nx.r0, nx.r1 - nx.r0, r);
+      loaded = true;
     }
-    for (uint32_t c0 = 0; c0 < n; c0 += CAP) {
-      const uint32_t cnt = n - c0 < CAP ? n - c0 : CAP;
-      Recs<ITEMS> r;
-      uint32_t pos[ITEMS];
-      load_arrays<ITEMS, NARROW ? IN_NARROW : IN_WIDE, false>(ik, it, iw, start + c0, cnt, r);
-      rank_digits<RB, ITEMS, false>(r.k, kshift, m3, cnt, s_wh, s_sink, pos);
+    cur = nx;
+    lds_barrier();  // read by all before wave 0 writes it again
+  }
+}
+
+// The listed sub-buckets larger than one load: counted by D3, then sorted in
+// pieces of one load, each piece's records of a D3 value following those of
+// the pieces before.
+template <int RB, bool NARROW>
+__global__ __launch_bounds__(kMThreads) void k_msd_big_c(MsdPlan p) {
+  M_C_LDS
+  __shared__ uint32_t s_cur[kMNB];
+  __shared__ uint32_t s_dx[kMNB];
+  const CFields f = c_fields<NARROW>(p);
+  char* const* s_blk = c_setup(p, s_blk_tab, s_wh);
+  const uint32_t b3 = p.b3, nd = 1u << b3, d = threadIdx.x;
+  lds_barrier();
+  for (uint32_t i = blockIdx.x; i < G(p.big_count)[0]; i += gridDim.x) {
+    const uint32_t sb = G(p.big_list)[i];
+    const uint32_t r0 = G(p.sbstart)[sb], n = G(p.sbstart)[sb + 1] - r0;
+    const uint32_t base = (sb << b3) & f.km;
+    for (uint32_t e = d; e < (uint32_t)kMNB; e += kMThreads) s_cur[e] = 0;
+    lds_barrier();
+    for (uint32_t j = d; j < n; j += kMThreads) atomicAdd(&s_cur[((G(f.ik)[r0 + j] >> f.ks) - base) & f.km], 1u);
+    lds_barrier();
+    tile_groups(p, sb, 1u, r0, d < nd ? s_cur[d] : 0u, s_ex, s_st, s_tmp, s_bal);
+    if (d < nd) s_cur[d] = r0 + s_st[d];
+    for (uint32_t c0 = 0; c0 < n; c0 += kCTile) {
+      const uint32_t cnt = n - c0 < kCTile ? n - c0 : kCTile;
+      Recs<kMItems> r;
+      load_c<NARROW>(f.ik, f.it, f.iw, r0 + c0, cnt, r);
+      uint32_t pos[kMItems];
+      rank_digits<RB, kMItems, false>(r.k, f.ks, f.km, cnt, s_wh, s_sink, pos, base);
       lds_barrier();
-      const uint32_t d = threadIdx.x;
       uint32_t st;
       const uint32_t tot = digit_starts(nd, s_wh, s_tmp, &st);
-      if (n <= CAP && d < nd) s_hist[d] = tot;
-      if (c0 == 0) {
-        // the sub-bucket's groups: its present D3 values (Sec. 2.2)
-        lds_barrier();
-        const uint32_t h = d < nd ? s_hist[d] : 0u;
-        uint32_t all;
-        const uint32_t ex = m_block_scan(h, s_tmp, &all);
-        const bool present = h != 0;
-        uint32_t ng;
-        const uint32_t gi = m_block_scan(present ? 1u : 0u, s_tmp, &ng);
-        if (d < nd) s_cur[d] = start + ex;
-        if (present) G(p.gslot)[start + gi] = start + ex;
-        const uint64_t bits = __ballot(present);
-        const uint32_t mw = p.mask_words;
-        uint32_t* gm = p.gmask + (uint64_t)sb * mw;
-        if (lane == 0) {
-          if (2u * (uint32_t)wave < mw) G(gm)[2 * wave] = (uint32_t)bits;
-          if (2u * (uint32_t)wave + 1 < mw) G(gm)[2 * wave + 1] = (uint32_t)(bits >> 32);
-        }
-        if (threadIdx.x == 0) G(p.gcount)[sb] = ng;
-      }
-      lds_barrier();
       if (d < nd) {
-        const uint32_t cur = s_cur[d];
-        s_dx[d] = cur - st;
-        s_cur[d] = cur + tot;
+        const uint32_t cp = s_cur[d];
+        s_dx[d] = cp - st;  // output position minus piece position
+        s_cur[d] = cp + tot;
       }
-#pragma unroll
-      for (int k = 0; k < ITEMS; ++k) {
-        if (item_index(ITEMS, k) < cnt) {
-          const uint32_t q = pos[k] + s_wh[wave * kMNB + ((r.k[k] >> kshift) & m3)];
-          s_k[q] = r.k[k];
-          if constexpr (!NARROW) s_t[q] = r.t[k];
-          s_w[q] = r.w[k];
-        }
-      }
+      lds_barrier();  // every digit's wave starts are in s_wh
+      c_stage<NARROW>(f, r, pos, cnt, base, s_wh, s_k, s_t, s_w);
       lds_barrier();
-      for (uint32_t e = threadIdx.x; e < (uint32_t)kMNB; e += kMThreads) {
-#pragma unroll
-        for (int v = 0; v < kMWaves; ++v) s_wh[v * kMNB + e] = 0;
-      }
-      // Sorted records out: one piece is contiguous per D3 value, and a
-      // sub-bucket that fits in one piece is one contiguous run.
-      const uint32_t sbk = sb << p.b3;
-#pragma unroll
-      for (int k = 0; k < ITEMS; ++k) {
-        const uint32_t lp = (uint32_t)(k * kMThreads + threadIdx.x);
-        if (lp < cnt) {
-          const uint32_t kk = s_k[lp];
-          const uint32_t d3 = (kk >> kshift) & m3;
-          const uint32_t dest = s_dx[d3] + lp;
-          const uint32_t key = sbk | d3;
-          char* blk = m_out_block(p, s_blk, dest);
-          const uint64_t o = dest & (B - 1);
-          G(reinterpret_cast<uint32_t*>(blk))[o] = key >> p.dbits;
-          G(reinterpret_cast<uint32_t*>(blk + 4 * B))[o] = NARROW ? (kk & tmask) : s_t[lp];
-          G(reinterpret_cast<uint32_t*>(blk + 8 * B))[o] = s_w[lp];
-          G(reinterpret_cast<int16_t*>(blk + 12 * B))[o] = (int16_t)(key & dmask);
-        }
-      }
+      clear_wh(s_wh);
+      c_store<NARROW>(p, f, s_blk, s_k, s_t, s_w, cnt, base, sb << b3, s_dx, 0u);
       lds_barrier();
     }
   }
@@ -721,7 +962,7 @@ inline int rb_class(uint32_t bits) { return bits <= 6 ? 6 : (bits <= 8 ? 8 : 9);
 
 }  // namespace
 
-uint32_t msd_cap(bool narrow) { return (uint32_t)((narrow ? kCItemsN : kCItemsW) * kMThreads); }
+uint32_t msd_cap(bool) { return kCTile; }
 
 #define M_RB_SWITCH(bits, F) \
   switch (rb_class(bits)) {  \
@@ -773,15 +1014,26 @@ hipError_t launch_msd_scatter_b(const MsdPlan& p, hipStream_t s) {
 hipError_t launch_msd_plan_c(const MsdPlan& p, hipStream_t s) {
   const uint32_t nsb = 1u << (p.b1 + p.b2);
   if (p.b2) hipLaunchKernelGGL(k_msd_plan_c, dim3((nsb + 255) / 256), dim3(256), 0, s, p);
+  hipLaunchKernelGGL(k_msd_zero, dim3(std::min<uint32_t>((nsb * p.mask_words + 255) / 256, 1024u)), dim3(256), 0, s, p);
   hipLaunchKernelGGL(k_msd_split, dim3((p.wgs_c + 1 + 255) / 256), dim3(256), 0, s, p);
   return hipGetLastError();
 }
 
 hipError_t launch_msd_local_c(const MsdPlan& p, hipStream_t s) {
   const bool narrow = p.b2 ? p.narrow_b : p.narrow_a;
-#define F(RB)                                                                                  \
-  if (narrow) hipLaunchKernelGGL((k_msd_local_c<RB, true>), dim3(p.wgs_c), dim3(kMThreads), 0, s, p); \
-  else hipLaunchKernelGGL((k_msd_local_c<RB, false>), dim3(p.wgs_c), dim3(kMThreads), 0, s, p);
+  // combined digits: sub-bucket offset in the tile above D3
+  const uint32_t nd = msd_max_sub(p, narrow) << p.b3;
+  uint32_t cbits = 0;
+  while ((1u << cbits) < nd) ++cbits;
+  const dim3 big_grid(p.max_big < 256u ? p.max_big : 256u);
+#define F(RB)                                                                                           \
+  if (narrow) hipLaunchKernelGGL((k_msd_tiles_c<RB, true>), dim3(p.wgs_c), dim3(kMThreads), 0, s, p);   \
+  else hipLaunchKernelGGL((k_msd_tiles_c<RB, false>), dim3(p.wgs_c), dim3(kMThreads), 0, s, p);
+  M_RB_SWITCH(cbits, F)
+#undef F
+#define F(RB)                                                                                           \
+  if (narrow) hipLaunchKernelGGL((k_msd_big_c<RB, true>), big_grid, dim3(kMThreads), 0, s, p);          \
+  else hipLaunchKernelGGL((k_msd_big_c<RB, false>), big_grid, dim3(kMThreads), 0, s, p);
   M_RB_SWITCH(p.b3, F)
 #undef F
   return hipGetLastError();

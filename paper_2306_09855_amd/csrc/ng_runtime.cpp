@@ -946,6 +946,168 @@ int calibrate_copass(ng_ctx* c) {
   return NG_OK;
 }
 
+// Digit plan of the most-significant-digit calibration (keys of at most 27
+// bits, see ng_internal.h).  The last digit (pass C, in LDS) is as wide as
+// keeps an average occupied sub-bucket at about half of what one LDS piece
+// holds; the keys only occupy [0, n_nodes << dbits), so that range, not
+// 2^keybits, sets the occupancy.  The remaining bits go to pass A alone when
+// they fit one digit, else are split between A and B so that the occupied
+// values of D1 and the values of D2 balance (both set the run lengths of
+// their scatter).  False if the plan does not apply (the LSD sort runs).
+bool msd_geometry(uint64_t N, uint32_t nn, int dbits, int log2B, uint32_t sort_ranges, ng::MsdPlan& p) {
+  const int sbits = bitwidth(nn > 0 ? nn - 1 : 0);
+  const int K = sbits + dbits;
+  if (N == 0 || N > 0xFFFFFFFFull || K < 2 || K > (int)ng::kMsdMaxKeyBits) return false;
+  const uint32_t tbits = (uint32_t)std::max(1, sbits);
+  const uint64_t keyspace = (uint64_t)nn << dbits;
+  const uint64_t cap = ng::msd_cap(tbits + ng::kMsdMaxDigit <= 32);
+  int b3 = 0;
+  while (b3 < 9 && ((keyspace * (cap / 2)) >> (b3 + 1)) >= N) ++b3;
+  b3 = std::max(b3, std::max(1, K - 18));
+  b3 = std::min(b3, std::min(9, K - 1));
+  const int hb = K - b3;
+  int b1 = hb, b2 = 0;
+  if (hb > 9) {
+    uint64_t best = ~0ull;
+    for (int t = std::max(1, hb - 9); t <= std::min(9, hb - 1); ++t) {
+      const uint64_t occ1 = (keyspace + (1ull << (t + b3)) - 1) >> (t + b3);
+      const uint64_t cost = std::max<uint64_t>(occ1, 1ull << t);
+      if (cost < best) {
+        best = cost;
+        b2 = t;
+      }
+    }
+    b1 = hb - b2;
+  }
+  p = ng::MsdPlan{};
+  p.n = (uint32_t)N;
+  p.keybits = (uint32_t)K;
+  p.dbits = (uint32_t)dbits;
+  p.tbits = tbits;
+  p.b1 = (uint32_t)b1;
+  p.b2 = (uint32_t)b2;
+  p.b3 = (uint32_t)b3;
+  p.narrow_a = (uint32_t)(b2 + b3) + tbits <= 32 ? 1u : 0u;
+  p.narrow_b = (uint32_t)b3 + tbits <= 32 ? 1u : 0u;
+  // packed records entering pass C hold D3 and as many D2 bits as fit
+  p.cbits = (uint32_t)b3;
+  if (b2 && p.narrow_a) p.cbits = (uint32_t)(b2 + b3);
+  else if (b2 && p.narrow_b) p.cbits = std::min<uint32_t>((uint32_t)(b2 + b3), 32u - tbits);
+  const uint64_t tile = ng::kMsdTile;
+  const uint64_t ntiles = (N + tile - 1) / tile;
+  p.tpr = (uint32_t)std::max<uint64_t>(1, (ntiles + sort_ranges - 1) / std::max<uint32_t>(sort_ranges, 1));
+  p.ranges_a = (uint32_t)((ntiles + p.tpr - 1) / p.tpr);
+  // every bucket's ranges start at its first record: at most one partial
+  // range per bucket beyond the full ones
+  p.max_ranges_b = b2 ? (uint32_t)((N + tile * p.tpr - 1) / (tile * p.tpr) + (1ull << b1)) : 0u;
+  // pass C: workgroups of about eight LDS loads of records each
+  const uint64_t piece = ng::msd_cap(b2 ? p.narrow_b : p.narrow_a);
+  p.wgs_c = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(1, (N + 8 * piece - 1) / (8 * piece)), 1u << 20);
+  p.max_big = (uint32_t)(N / (piece + 1) + 1);
+  p.n_nodes = nn;
+  p.log2B = log2B;
+  p.mask_words = std::max<uint32_t>(1, (1u << b3) / 32);
+  return true;
+}
+
+// The default radix calibration takes the most-significant-digit form when
+// the sub-buckets it must visit hold 256 connections on average or more:
+// fewer connections over a wide key leave most sub-buckets empty, and the
+// LSD passes (a few launches over all records) are then cheaper.
+bool msd_pays(const ng::MsdPlan& p) { return (uint64_t)p.n >= (256ull << (p.b1 + p.b2)); }
+
+// Calibration of one context by the most-significant-digit sort: count and
+// scatter by D1 (A), count and scatter each bucket by D2 (B), each
+// sub-bucket sorted by D3 in LDS into the calibrated blocks with its groups
+// (C), then group_start and group_ptr (Eq. (14)).  Every launch size is an
+// upper bound computed on the host; the bucket layout stays on the device.
+int calibrate_msd(CalSeg& g, const ng::MsdPlan& plan) {
+  ng_ctx* c = g.c;
+  ng::MsdPlan p = plan;
+  const uint64_t N = g.N;
+  const uint64_t nb = 1ull << p.b1, nsb = 1ull << (p.b1 + p.b2);
+  AllocSet as(c);
+  const uint64_t nblk = (N + c->B - 1) / c->B;
+  for (uint64_t b = 0; b < nblk && as.ok; ++b) g.nblocks.push_back(as.get(ng::kBytesPerConn * c->B));
+  const uint64_t first_scratch = g.nblocks.size();
+  p.a_key = (uint32_t*)as.get(4 * N);
+  p.a_w = (uint32_t*)as.get(4 * N);
+  p.a_tgt = p.narrow_a ? nullptr : (uint32_t*)as.get(4 * N);
+  if (p.b2) {
+    p.b_key = (uint32_t*)as.get(4 * N);
+    p.b_w = (uint32_t*)as.get(4 * N);
+    p.b_tgt = p.narrow_b ? nullptr : (uint32_t*)as.get(4 * N);
+    p.gslot = p.a_key;  // pass C reads B's records; A's keys are dead by then
+  } else {
+    p.gslot = (uint32_t*)as.get(4 * N);
+  }
+  const uint64_t na = nb * p.ranges_a, nbc = p.b2 ? ((uint64_t)p.max_ranges_b << p.b2) : 0;
+  p.cnt_a = (uint32_t*)as.get(4 * na);
+  p.cnt_b = p.b2 ? (uint32_t*)as.get(4 * nbc) : nullptr;
+  uint32_t* scan_tmp =
+      (uint32_t*)as.get(4 * std::max({ng::scan_tmp_words(na), ng::scan_tmp_words(nbc), ng::scan_tmp_words(nsb)}));
+  p.bstart = (uint32_t*)as.get(4 * (nb + 1));
+  p.rangeb0 = (uint32_t*)as.get(4 * (nb + 1));
+  p.sbstart = (uint32_t*)as.get(4 * (nsb + 1));
+  p.gcount = (uint32_t*)as.get(4 * (nsb + 1));
+  p.gmask = (uint32_t*)as.get(4 * nsb * p.mask_words);
+  p.wg_sb0 = (uint32_t*)as.get(4 * ((uint64_t)p.wgs_c + 1));
+  p.big_count = (uint32_t*)as.get(4);
+  p.big_list = (uint32_t*)as.get(4 * (uint64_t)p.max_big);
+  g.gp_bytes = 4 * (g.nn + 1ull);
+  g.gs_bytes = 4 * g.gcap;
+  release_index(c);
+  c->calibrated = false;
+  g.gptr = (uint32_t*)ctx_alloc(c, g.gp_bytes);
+  g.gstart = g.gptr ? (uint32_t*)ctx_alloc(c, g.gs_bytes) : nullptr;
+  if (!as.ok || !g.gptr || !g.gstart) {
+    as.release_all();
+    ctx_unalloc(c, (char*)g.gptr, g.gp_bytes);
+    ctx_unalloc(c, (char*)g.gstart, g.gs_bytes);
+    g.nblocks.clear();
+    c->need = as.asked + Arena::round_up(g.gp_bytes) + Arena::round_up(g.gs_bytes);
+    return fail(NG_ERR_OOM, "arena cannot hold the calibration buffers (N=%llu)", (unsigned long long)N);
+  }
+  g.nxt = 1 - c->cur;
+  p.in_blocks = c->d_tab[c->cur];
+  p.out_blocks = c->d_tab[g.nxt];
+  p.group_ptr = g.gptr;
+  p.group_start = g.gstart;
+  p.n_groups = c->d_scalars;
+
+  hipStream_t s = c->stream;
+  if (int rc = sync_table(c)) return rc;
+  NG_HIP(c, set_table(c->d_tab[g.nxt], 0, g.nblocks, 0, s), "block table");
+  NG_LAUNCH_N(c, "msd_count_a", N, ng::launch_msd_count_a(p, s));
+  NG_LAUNCH(c, "scan", ng::launch_exclusive_scan(p.cnt_a, p.cnt_a, na, scan_tmp, nullptr, s));
+  NG_LAUNCH_N(c, "msd_scatter_a", N, ng::launch_msd_scatter_a(p, s));
+  NG_LAUNCH(c, "msd_plan", ng::launch_msd_plan_b(p, s));
+  if (p.b2) {
+    NG_LAUNCH_N(c, "msd_count_b", N, ng::launch_msd_count_b(p, s));
+    NG_LAUNCH(c, "scan", ng::launch_exclusive_scan(p.cnt_b, p.cnt_b, nbc, scan_tmp, nullptr, s));
+    NG_LAUNCH_N(c, "msd_scatter_b", N, ng::launch_msd_scatter_b(p, s));
+  }
+  NG_LAUNCH(c, "msd_plan", ng::launch_msd_plan_c(p, s));
+  NG_LAUNCH_N(c, "msd_local_c", N, ng::launch_msd_local_c(p, s));
+  NG_LAUNCH(c, "scan", ng::launch_exclusive_scan(p.gcount, p.gcount, nsb, scan_tmp, p.gcount + nsb, s));
+  NG_LAUNCH(c, "msd_groups", ng::launch_msd_groups(p, s));
+
+  // old storage and scratch return to the arena (ordered after the launches)
+  for (char* b : c->blocks) ctx_free(c, b, ng::kBytesPerConn * c->B);
+  for (size_t i = first_scratch; i < as.items.size(); ++i) ctx_free(c, as.items[i].first, as.items[i].second);
+  c->blocks = g.nblocks;
+  c->tab_synced = (uint32_t)g.nblocks.size();
+  c->cur = g.nxt;
+  c->d_group_ptr = g.gptr;
+  c->group_ptr_bytes = g.gp_bytes;
+  c->d_group_start = g.gstart;
+  c->group_start_bytes = g.gs_bytes;
+  c->gi_nodes = g.nn;
+  c->calibrated = true;
+  if (!c->capturing) ctx_flush_frees(c);
+  return NG_OK;
+}
+
 }  // namespace
 
 int calibrate_many(ng_ctx* const* cs, uint32_t n, const Uploader* upload, ScratchBump* sb) {
@@ -980,6 +1142,16 @@ int calibrate_many(ng_ctx* const* cs, uint32_t n, const Uploader* upload, Scratc
   for (auto& g : segs) {
     if (int rc = cal_plan(g)) return rc;
     g.sb = sb;
+  }
+  // one context with its own scratch: the most-significant-digit sort when
+  // its keys fit
+  if (segs.size() == 1 && !sb &&
+      (segs[0].c->calib_mode == NG_CALIB_RADIX || segs[0].c->calib_mode == NG_CALIB_RADIX_MSD)) {
+    ng::MsdPlan mp;
+    const CalSeg& g = segs[0];
+    if (msd_geometry(g.N, g.nn, g.dbits, g.c->log2B, g.c->sort_ranges, mp) &&
+        (g.c->calib_mode == NG_CALIB_RADIX_MSD || msd_pays(mp)))
+      return calibrate_msd(segs[0], mp);
   }
   ng_ctx* c0 = segs[0].c;
   const bool multi = segs.size() > 1;
@@ -1257,6 +1429,18 @@ extern "C" {
 const char* ng_version(void) { return "ng 0.1 gfx950"; }
 
 const char* ng_last_error(void) { return g_err.c_str(); }
+
+int ng_calibration_plan(uint64_t n_conns, uint32_t n_nodes, int32_t max_delay, uint32_t sort_ranges,
+                        uint32_t out[8]) {
+  if (!out || max_delay < 1) return fail(NG_ERR_INVALID_ARG, "null output or max_delay < 1");
+  for (int i = 0; i < 8; ++i) out[i] = 0;
+  ng::MsdPlan p;
+  if (!msd_geometry(n_conns, n_nodes, bitwidth((uint64_t)max_delay), 24, sort_ranges ? sort_ranges : 1024, p))
+    return NG_OK;
+  const uint32_t v[8] = {msd_pays(p) ? 2u : 1u, p.b1, p.b2, p.b3, p.narrow_a, p.narrow_b, p.wgs_c, p.tpr};
+  for (int i = 0; i < 8; ++i) out[i] = v[i];
+  return NG_OK;
+}
 
 uint64_t ng_blocks_needed(uint64_t n_conns, uint64_t n_new, uint64_t block_size, uint64_t n_blocks) {
   if (block_size == 0) return 0;
@@ -1607,7 +1791,8 @@ int ng_spikes_step(ng_ctx* c, const uint32_t* nodes, const uint32_t* mult, uint3
 
 int ng_set_calibration(ng_ctx* c, int algorithm) {
   if (!c) return fail(NG_ERR_INVALID_ARG, "null context");
-  if (algorithm != NG_CALIB_RADIX && algorithm != NG_CALIB_COPASS)
+  if (algorithm != NG_CALIB_RADIX && algorithm != NG_CALIB_COPASS && algorithm != NG_CALIB_RADIX_LSD &&
+      algorithm != NG_CALIB_RADIX_MSD)
     return fail(NG_ERR_INVALID_ARG, "unknown calibration algorithm %d", algorithm);
   c->calib_mode = algorithm;
   return NG_OK;

@@ -158,6 +158,7 @@ def lib():
             "ng_blocks_needed": ([u64, u64, u64, u64], u64),
             "ng_plan_count": ([u32, ng_range, ng_range, P(ng_conn_spec), P(ng_syn_spec), ctypes.c_float,
                                P(u64)], ctypes.c_int),
+            "ng_calibration_plan": ([u64, u32, i32, u32, P(u32)], ctypes.c_int),
             "ng_version": ([], ctypes.c_char_p),
         }
         for name, (args, res) in sig.items():
@@ -232,6 +233,13 @@ def ng_plan_count(n_nodes: int, src: ng_range, tgt: ng_range, conn: ng_conn_spec
     _check(lib().ng_plan_count(n_nodes, src, tgt, ctypes.byref(conn), ctypes.byref(syn), h_ms,
                                ctypes.byref(out)))
     return int(out.value)
+
+
+def ng_calibration_plan(n_conns: int, n_nodes: int, max_delay: int, sort_ranges: int = 1024) -> dict:
+    out = (ctypes.c_uint32 * 8)()
+    _check(lib().ng_calibration_plan(n_conns, n_nodes, max_delay, sort_ranges, out))
+    keys = ("msd", "b1", "b2", "b3", "narrow_a", "narrow_b", "wgs_c", "tpr")
+    return {k: int(v) for k, v in zip(keys, out)}
 
 
 def ng_create(cfg: ng_config, arena, arena_bytes: int, stream) -> ctypes.c_void_p:
@@ -358,8 +366,9 @@ def ng_set_tuning(ctx, radix_bits: int, sort_ranges: int = 1024) -> None:
     _check(lib().ng_set_tuning(ctx, radix_bits, sort_ranges))
 
 
-NG_CALIB_RADIX, NG_CALIB_COPASS = 0, 1
-CALIBRATIONS = {"radix": NG_CALIB_RADIX, "copass": NG_CALIB_COPASS}
+NG_CALIB_RADIX, NG_CALIB_COPASS, NG_CALIB_RADIX_LSD, NG_CALIB_RADIX_MSD = 0, 1, 2, 3
+CALIBRATIONS = {"radix": NG_CALIB_RADIX, "copass": NG_CALIB_COPASS, "lsd": NG_CALIB_RADIX_LSD,
+                "msd": NG_CALIB_RADIX_MSD}
 
 
 def ng_set_calibration(ctx, algorithm) -> None:

@@ -27,8 +27,9 @@ def _net(wl, block_size=0, arena=None):
                    arena or arena_bytes_for(wl.n_syn, wl.n_nodes, wl.max_delay, block_size or (1 << 24)))
 
 
-def _gpu_run(wl, block_size=0, batched=False, tuning=None):
+def _gpu_run(wl, block_size=0, batched=False, tuning=None, calibration="radix"):
     with _net(wl, block_size) as net:
+        net.set_calibration(calibration)
         if tuning:
             net.tune(*tuning)
         net.build(wl, batched=batched, calibrate=False)
@@ -103,10 +104,11 @@ def test_batch_equals_plain_and_oracle():
 
 @pytest.mark.parametrize("tuning", [(4, 1024), (5, 1), (7, 3), (8, 9), (9, 100000)])
 def test_schedule_invariance(tuning):
-    # digit widths 4..9 (2..5 passes) and range counts (a single range, counts
-    # that are not multiples of 8, more ranges than tiles) give identical results
+    # LSD form: digit widths 4..9 (2..5 passes) and range counts (a single
+    # range, counts that are not multiples of 8, more ranges than tiles) give
+    # identical results
     wl = W.microcircuit(scale=0.02)
-    _check_all(wl, tuning=tuning)
+    _check_all(wl, tuning=tuning, calibration="lsd")
 
 
 def test_edge_cases():

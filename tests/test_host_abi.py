@@ -136,3 +136,35 @@ def test_arena_for_sizes():
     from paper_2306_09855_amd.network import arena_bytes_for
     assert arena_bytes_for(300_000_000, 77169, 30) > 2 * 14 * 300_000_000
     assert arena_bytes_for(0, 1) > 0
+
+
+@pytest.mark.parametrize("n_conns,n_nodes,max_delay", [
+    (300_000_000, 77_169, 30), (100_000, 2_000, 20), (154_000_000, 100_000, 50),
+    (445_000_000, 1_000_000, 63), (2_000_000, 1 << 24, 7), (5, 2, 1), (1 << 20, 1 << 22, 31),
+    (12_345, 3, 32767), (1 << 31, 77_169, 30)])
+def test_calibration_plan(L, n_conns, n_nodes, max_delay):
+    # the digits cover the key exactly (source bits + delay bits, Sec. 2.2),
+    # each at most 9 bits; a record is packed into one word only when the
+    # key bits not yet applied and a target index fit in 32 bits
+    p = ng.ng_calibration_plan(n_conns, n_nodes, max_delay)
+    sbits = max(n_nodes - 1, 0).bit_length()
+    dbits = int(max_delay).bit_length()
+    keybits = sbits + dbits
+    if keybits > 27:
+        assert p["msd"] == 0 and p["b1"] == 0
+        return
+    # the default takes it when the sub-buckets average 256 connections or more
+    assert p["msd"] == (2 if n_conns >= 256 << (p["b1"] + p["b2"]) else 1)
+    assert p["b1"] + p["b2"] + p["b3"] == keybits
+    assert all(1 <= p[k] <= 9 for k in ("b1", "b3")) and 0 <= p["b2"] <= 9
+    tbits = max(sbits, 1)
+    assert p["narrow_a"] == int(p["b2"] + p["b3"] + tbits <= 32)
+    assert p["narrow_b"] == int(p["b3"] + tbits <= 32)
+    assert p["wgs_c"] >= 1 and p["tpr"] >= 1
+
+
+def test_calibration_plan_rejects(L):
+    assert ng.ng_calibration_plan(0, 100, 5)["msd"] == 0
+    assert ng.ng_calibration_plan(1000, 1, 1)["msd"] == 0     # a one-bit key: LSD
+    with pytest.raises(ng.NGError):
+        ng.ng_calibration_plan(1000, 10, 0)
