@@ -3,14 +3,17 @@
 
 A step is one pass of the whole hot path over the microcircuit-shaped
 network (77,169 nodes in 8 populations, 64 fixed_total_number Connect calls,
-3.0e8 synapses): reset the context, create the nodes, issue every Connect
-call (generation kernels), then calibrate (radix-sort passes and the group
-index).  Inputs are the call descriptions; nothing is copied from the host
-inside the timed region.
+3.0e8 synapses): reset the context, set the step's seed (steps cycle through
+seeds 1..10, as the paper's timings average ten seeds), create the nodes,
+issue every Connect call (generation kernels), then calibrate (radix-sort
+passes and the group index).  Inputs are the call descriptions; nothing is
+copied from the host inside the timed region.
 
-Prints one JSON line (rank 0) with the throughput, the roofline of the
-dominant kernel measured with HIP events on the context's stream, and the
-CPU oracle timed on a bounded sample of the same workload.
+Prints one JSON line (rank 0) with the throughput, mean (std) of the step
+time over the seeds, the roofline of the dominant kernel measured with HIP
+events on the context's stream, the same build for the two-population
+network and the 4,096-call batch (plain, batched and graph forms), and the
+CPU oracle timed on the host's cores.
 """
 from __future__ import annotations
 
@@ -34,25 +37,50 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(kernel: str, n_syn: int, passes: int) -> float | None:
-    """Bytes a kernel must move per step (not what it happens to move)."""
-    per = {
-        "generate": 14.0,                 # write src, tgt, w, delay once
-        "generate_batch": 14.0,
-        # per pass: read one record, write one record (14 B SoA at the ends, 12 B key+payload between)
-        "downsweep": 26.0 * 2 + 24.0 * (passes - 2) if passes >= 2 else 28.0,
-        "upsweep": 6.0 + 4.0 * (passes - 1),  # read the keys (src + delay, then key words)
-        "group_flags": 6.0,               # read src + delay
-        "group_write": 6.0,               # read src + delay again
-    }.get(kernel)
+# Bytes the method must move per synapse (the path's 42: the 14-byte record
+# written once by generation, read once and written once sorted by the
+# calibration).  The calibration's 28 bytes are split evenly over the kernels
+# that move every record (the scatter and LDS-sort passes of the sort); the
+# counting, planning and index kernels get none.
+SORT_PASS_KERNELS = ("msd_scatter_a", "msd_scatter_b", "msd_tiles_c", "downsweep")
+GEN_KERNELS = ("generate", "generate_batch")
+
+
+def algorithmic_bytes(kernel: str, n_syn: int, kernels: dict) -> float | None:
+    """Algorithmic bytes of `kernel` per step, given the step's launches
+    (name -> (launches, ms)) so that the sort's share is split over its
+    record-moving launches."""
+    if kernel in GEN_KERNELS:
+        return 14.0 * n_syn
+    if kernel in SORT_PASS_KERNELS:
+        launches = sum(kernels[k][0] for k in SORT_PASS_KERNELS if k in kernels)
+        return 28.0 * n_syn * kernels[kernel][0] / launches
+    return None
+
+
+def moved_bytes(kernel: str, n_syn: int, plan: dict) -> float | None:
+    """Bytes the implementation's kernel reads and writes per step (records
+    of 14 bytes in blocks, 8 bytes packed, 12 bytes unpacked between
+    passes); a diagnostic next to the algorithmic figure."""
+    if not plan or plan.get("msd", 0) != 2:
+        return None
+    a = 8.0 if plan["narrow_a"] else 12.0
+    b = 8.0 if plan["narrow_b"] else 12.0
+    per = {"msd_count_a": 4.0, "msd_scatter_a": 14.0 + a, "msd_count_b": 4.0,
+           "msd_scatter_b": a + b, "msd_tiles_c": (b if plan["b2"] else a) + 14.0}.get(kernel)
     return None if per is None else per * n_syn
 
 
-def kernels_fingerprint() -> str:
-    """Hash of the radix-sort section of the kernel source (the counters are
-    taken on the sort kernels; other sections do not change them)."""
+def kernels_fingerprint(kernel: str) -> str:
+    """Hash of the source that holds `kernel` (the most-significant-digit
+    sort file for its kernels, else the radix-sort section of the kernel
+    file): traffic counters taken on one version do not describe another."""
     import hashlib
-    with open(os.path.join(ROOT, "paper_2306_09855_amd", "csrc", "ng_kernels.hip"), "rb") as f:
+    csrc = os.path.join(ROOT, "paper_2306_09855_amd", "csrc")
+    if kernel.startswith("msd_"):
+        with open(os.path.join(csrc, "ng_msd.hip"), "rb") as f:
+            return hashlib.sha256(f.read()).hexdigest()[:16]
+    with open(os.path.join(csrc, "ng_kernels.hip"), "rb") as f:
         src = f.read()
     a = src.find(b"// Radix sort: reduce-then-scan")
     b = src.find(b"// Device-wide exclusive scan")
@@ -65,7 +93,7 @@ def measured_traffic(kernel: str, workload: str):
     """HBM bytes per launch of `kernel` from the committed counter summary, or
     None if there is none or the kernels changed since it was taken."""
     import glob
-    fp = kernels_fingerprint()
+    fp = kernels_fingerprint(kernel)
     for path in glob.glob(os.path.join(ROOT, "profiles", "*traffic*.md")):
         for line in open(path):
             line = line.strip()
@@ -80,18 +108,42 @@ def measured_traffic(kernel: str, workload: str):
     return None
 
 
-def cpu_baseline(sample_syn: int) -> dict:
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def cpu_baseline(sample_syn: int, one_thread_syn: int) -> dict:
+    """The oracle as it stands, timed on this host: the microcircuit call list
+    scaled to sample_syn synapses on all cores the process may use (its
+    threaded mode, byte-identical to the single-thread mode), and on one core
+    for one_thread_syn synapses.  Generation of every call plus calibration."""
     import oracle
     from paper_2306_09855_amd import workloads as W
-    wl = W.microcircuit(total=sample_syn)
-    log(f"cpu baseline: oracle on {wl.n_syn:.3g} synapses ...")
-    t0 = time.perf_counter()
-    oracle.build_network(wl.seed, wl.h, wl.n_nodes, wl.calls)
-    dt = time.perf_counter() - t0
-    return {"value": wl.n_syn / dt, "unit": "synapses/s", "cores": 1, "kind": "oracle",
-            "seconds": dt, "cpu": platform.processor() or platform.machine(),
+
+    def run(total, threads):
+        wl = W.microcircuit(total=total)
+        with oracle.threads(threads):
+            t0 = time.perf_counter()
+            oracle.build_network(wl.seed, wl.h, wl.n_nodes, wl.calls)
+            dt = time.perf_counter() - t0
+        return wl.n_syn, dt
+
+    cores = max(1, len(os.sched_getaffinity(0)))
+    log(f"cpu baseline: oracle on {sample_syn:.3g} synapses, {cores} threads ...")
+    n_all, t_all = run(sample_syn, cores)
+    log(f"cpu baseline: oracle on {one_thread_syn:.3g} synapses, 1 thread ...")
+    n_one, t_one = run(one_thread_syn, 1)
+    return {"value": n_all / t_all, "unit": "synapses/s", "cores": cores, "kind": "oracle",
+            "seconds": round(t_all, 3), "cpu": cpu_model(), "host_cpus": os.cpu_count(),
             "sample": (f"microcircuit populations (77,169 nodes), 64 fixed_total_number calls scaled to "
-                       f"{wl.n_syn} synapses in total; generation + calibration, single thread")}
+                       f"{n_all} synapses; generation + calibration, {cores} threads"),
+            "single_thread": {"value": n_one / t_one, "seconds": round(t_one, 3), "synapses": n_one}}
 
 
 def _events(trace):
@@ -521,22 +573,110 @@ def delivery_bench(wl, block_size: int, rate_per_step: float = 1e-3, warm_steps:
             "GBps_algorithmic": round(8.0 * emitted / (dev_ms / 1e3) / 1e9, 1) if dev_ms else None}
 
 
+SEEDS = tuple(range(1, 11))  # the paper's timings are means over ten seeds
+
+
+def form_bench(wl, form: str, steps: int, warmup: int, block_size: int) -> dict:
+    """One workload built and calibrated in the plain form (one ng_connect
+    per call), the batched form (one ng_connect_batch) or the graph form (the
+    batched build captured once, replayed with each step's seed); steps cycle
+    through the seeds.  Wall time per step and the device time of the
+    generation and calibration kernels."""
+    import torch
+    from paper_2306_09855_amd import ng
+    from paper_2306_09855_amd.network import Network, arena_bytes_for
+
+    arena = arena_bytes_for(wl.n_syn, wl.n_nodes, wl.max_delay, block_size, 9)
+    side = torch.cuda.Stream()
+    net = Network(wl.seed, wl.h, block_size, arena, stream=side.cuda_stream)
+    ctx = net.ctx
+    calls = [ng.call_args(c) for c in wl.calls]
+    batch = [list(x) for x in zip(*calls)]
+
+    def build():
+        for n in wl.populations:
+            ng.ng_create_nodes(ctx, n)
+        if form == "plain":
+            for a in calls:
+                ng.ng_connect(ctx, *a)
+        else:
+            ng.ng_connect_batch(ctx, *batch)
+        ng.ng_calibrate(ctx)
+
+    graph = None
+    if form == "graph":
+        ng.ng_reset(ctx)
+        ng.ng_graph_begin(ctx)
+        build()
+        graph = ng.ng_graph_end(ctx)
+
+    def step(i):
+        seed = SEEDS[i % len(SEEDS)]
+        if graph is not None:
+            ng.ng_graph_launch(graph, seed)
+        else:
+            ng.ng_reset(ctx)
+            ng.ng_set_seed(ctx, seed)
+            build()
+
+    for i in range(warmup):
+        step(i)
+    ng.ng_sync(ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        step(i)
+    ng.ng_sync(ctx)
+    t1 = time.perf_counter()
+    if graph is not None:
+        ng.ng_graph_destroy(graph)
+    net.close()
+    torch.cuda.empty_cache()
+    ms = 1e3 * (t1 - t0) / steps
+    return {"form": form, "ms_per_step": round(ms, 3), "synapses_per_s": wl.n_syn / (ms / 1e3)}
+
+
+def workload_legs(block_size: int, steps: int) -> dict:
+    """The two-population network (four calls, four rules, 1.54e8 synapses)
+    and the 4,096-call batch (~4.3e8 synapses, mixed rules over 1e6 nodes) in
+    the plain form, and the batch also in the batched and graph forms."""
+    from paper_2306_09855_amd import workloads as W
+    out = {}
+    tp = W.two_pop_mixed()
+    out["two_population"] = {"n_syn": tp.n_syn, "n_calls": len(tp.calls), "n_nodes": tp.n_nodes,
+                             "plain": form_bench(tp, "plain", steps, 1, block_size)}
+    log(f"two-population network: {out['two_population']['plain']['ms_per_step']} ms/step")
+    bm = W.batch_mixed()
+    legs = {f: form_bench(bm, f, steps, 1, block_size) for f in ("plain", "batched", "graph")}
+    for f in ("batched", "graph"):
+        legs[f]["vs_plain"] = round(legs[f]["synapses_per_s"] / legs["plain"]["synapses_per_s"], 2)
+    out["batch_4096"] = {"n_syn": bm.n_syn, "n_calls": len(bm.calls), "n_nodes": bm.n_nodes, **legs}
+    log("batch of 4,096 calls: " + ", ".join(f"{f} {legs[f]['ms_per_step']} ms" for f in legs))
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10, help="timed steps (seeds 1..10 in turn)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="microcircuit", choices=["microcircuit", "batch_mixed"],
                     help="microcircuit: 64 calls, 3.0e8 synapses; batch_mixed: 4,096 uneven calls, ~4.3e8")
     ap.add_argument("--form", default="plain", choices=["plain", "batched", "graph"],
                     help="plain: one ng_connect per call; batched: one ng_connect_batch; "
                          "graph: the batched build captured once and replayed")
+    ap.add_argument("--calibration", default="radix", choices=["radix", "lsd", "msd"],
+                    help="radix: the default form choice; lsd / msd: force one form")
     ap.add_argument("--tune", action="store_true", help="pick the sort schedule with the autotuner first")
-    ap.add_argument("--radix-bits", type=int, default=9, help="widest digit (fewest passes)")
-    ap.add_argument("--sort-ranges", type=int, default=1024, help="static ranges (workgroups) of each sort pass")
+    ap.add_argument("--radix-bits", type=int, default=9, help="widest digit of the LSD form (fewest passes)")
+    ap.add_argument("--sort-ranges", type=int, default=1024, help="static ranges (workgroups) of each scatter pass")
     ap.add_argument("--block-size", type=int, default=1 << 24)
-    ap.add_argument("--cpu-sample", type=float, default=6e7, help="synapses of the oracle sample; 0 skips")
+    ap.add_argument("--cpu-sample", type=float, default=3.0e8,
+                    help="synapses of the oracle run on all cores; 0 skips the CPU baseline")
+    ap.add_argument("--cpu-one-thread", type=float, default=3.0e7, help="synapses of the single-thread oracle run")
     ap.add_argument("--total", type=float, default=3.0e8)
+    ap.add_argument("--legs", type=int, default=1,
+                    help="also time the two-population network and the 4,096-call batch in every form")
     ap.add_argument("--no-autapses", type=int, default=1,
                     help="also time the build with allow_autapses = 0 on every call")
     ap.add_argument("--pairwise", type=int, default=1,
@@ -559,6 +699,7 @@ def main() -> int:
                           "n_gpus": args.gpus}))
         return 2
 
+    import numpy as np
     import torch
     if args.copy_probe:
         n = int(args.copy_probe)
@@ -584,6 +725,7 @@ def main() -> int:
         f"arena {arena / 2**30:.1f} GiB, form {args.form}")
     side = torch.cuda.Stream()  # graphs cannot capture the null stream
     net = Network(wl.seed, wl.h, args.block_size, arena, stream=side.cuda_stream)
+    net.set_calibration(args.calibration)
     if args.tune:
         from paper_2306_09855_amd.autotune import tune
         args.radix_bits, args.sort_ranges = tune(net, wl)
@@ -610,72 +752,88 @@ def main() -> int:
         build()
         graph = ng.ng_graph_end(ctx)
 
-    def step():
+    def step(i):
+        seed = SEEDS[i % len(SEEDS)]
         if graph is not None:
-            ng.ng_graph_launch(graph, wl.seed)
+            ng.ng_graph_launch(graph, seed)
         else:
             ng.ng_reset(ctx)
+            ng.ng_set_seed(ctx, seed)
             build()
 
     for i in range(args.warmup):
-        step()
+        step(i)
         ng.ng_sync(ctx)
         log(f"warmup {i + 1}/{args.warmup} done")
 
     ng.ng_enable_timing(ctx, True)
     ng.ng_read_timing(ctx, reset=True)
     stream = torch.cuda.ExternalStream(net.stream) if net.stream else torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    e0.record(stream)
+    ev[0].record(stream)
     for i in range(args.steps):
-        step()
-    e1.record(stream)
+        step(i)
+        ev[i + 1].record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kernels = ng.ng_read_timing(ctx, reset=True)
     ng.ng_enable_timing(ctx, False)
-    if graph is not None:  # replays carry no per-kernel events: time one eager build instead
+    if graph is not None:  # replays carry no per-kernel events: time eager builds instead
         ng.ng_graph_destroy(graph)
         graph = None
         ng.ng_enable_timing(ctx, True)
-        for _ in range(args.steps):
+        for i in range(args.steps):
             ng.ng_reset(ctx)
+            ng.ng_set_seed(ctx, SEEDS[i % len(SEEDS)])
             build()
         kernels = ng.ng_read_timing(ctx, reset=True)
         ng.ng_enable_timing(ctx, False)
     log(f"timed {args.steps} steps in {t1 - t0:.4f} s")
 
     wall = t1 - t0
-    dev_ms = e0.elapsed_time(e1)
+    step_ms = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)])
+    dev_ms = float(step_ms.sum())
     ms_per_step = 1e3 * wall / args.steps
     value = args.steps * n_syn / wall
 
-    # digit passes the calibration used
+    plan = ng.ng_calibration_plan(n_syn, wl.n_nodes, wl.max_delay, args.sort_ranges)
+    msd = plan["msd"] == 2 and args.calibration != "lsd" or (args.calibration == "msd" and plan["msd"] >= 1)
     dbits = int(wl.max_delay).bit_length()
     sbits = int(wl.n_nodes - 1).bit_length()
-    passes = max(1, -(-(sbits + dbits) // args.radix_bits))
+    lsd_passes = max(1, -(-(sbits + dbits) // args.radix_bits))
     per_kernel = {}
     for name, (launches, total_ms) in kernels.items():
         ms = total_ms / args.steps
-        ab = algorithmic_bytes(name, n_syn, passes)
+        ab = algorithmic_bytes(name, n_syn, kernels)
+        mb = moved_bytes(name, n_syn, plan) if msd else None
         per_kernel[name] = {"launches_per_step": launches / args.steps, "ms_per_step": round(ms, 4),
-                            "GBps_algorithmic": None if ab is None or ms == 0 else round(ab / ms / 1e6, 1)}
+                            "GBps_algorithmic": None if ab is None or ms == 0 else round(ab / ms / 1e6, 1),
+                            "GBps_moved": None if mb is None or ms == 0 else round(mb / ms / 1e6, 1)}
     dom = max(kernels.items(), key=lambda kv: kv[1][1])[0] if kernels else None
     roofline = None
     if dom is not None:
         launches, total_ms = kernels[dom]
-        ab_step = algorithmic_bytes(dom, n_syn, passes)
+        ab_step = algorithmic_bytes(dom, n_syn, kernels)
         if ab_step is not None:
             per_launch_bytes = ab_step * args.steps / launches
             avg_s = total_ms / launches / 1e3
             achieved = per_launch_bytes / avg_s / 1e9
+            mb = moved_bytes(dom, n_syn, plan) if msd else None
             roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                         "traffic": measured_traffic(dom, wl.name),
-                        "bytes_per_launch": per_launch_bytes, "avg_launch_ms": round(avg_s * 1e3, 4)}
+                        "bytes_per_launch": per_launch_bytes, "avg_launch_ms": round(avg_s * 1e3, 4),
+                        "bytes_note": "the method's 28 bytes per synapse of calibration split evenly over the "
+                                      "sort's record-moving launches (14 per synapse for generation)",
+                        "moved_bytes_per_launch": None if mb is None else mb * args.steps / launches}
     path_alg = 42.0 * n_syn  # write each record once, read it and write it sorted once
+    if msd:
+        calib = {"form": "msd", "digits": [plan["b1"], plan["b2"], plan["b3"]],
+                 "packed_after_a": plan["narrow_a"], "packed_after_b": plan["narrow_b"]}
+    else:
+        calib = {"form": "lsd", "radix_bits": args.radix_bits, "passes": lsd_passes}
     result = {
         "metric": METRIC, "value": value, "unit": "synapses/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
@@ -686,10 +844,12 @@ def main() -> int:
                    "n_syn": n_syn,
                    "rule": "fixed_total_number" if wl.name == "microcircuit" else "mixed",
                    "delays": f"uniform_int 1..{wl.max_delay}",
-                   "weights": "normal fp32", "form": args.form,
-                   "block_size": args.block_size, "radix_bits": args.radix_bits, "sort_ranges": args.sort_ranges,
-                   "sort_passes": passes},
+                   "weights": "normal fp32", "form": args.form, "seeds": list(SEEDS),
+                   "block_size": args.block_size, "sort_ranges": args.sort_ranges, "calibration": calib},
         "device_ms_per_step": round(dev_ms / args.steps, 4),
+        "step_ms_over_seeds": {"mean": round(float(step_ms.mean()), 4), "std": round(float(step_ms.std(ddof=1)), 4)
+                               if args.steps > 1 else 0.0, "steps": args.steps,
+                               "note": "device time of each step (HIP events), steps cycling through the seeds"},
         "path_roofline": {"algorithmic_bytes_per_step": path_alg,
                           "frac": round(path_alg / (ms_per_step / 1e3) / (HBM_PEAK_GBS * 1e9), 4)},
         "roofline": roofline,
@@ -699,29 +859,32 @@ def main() -> int:
     net.close()
     del net
     torch.cuda.empty_cache()
+    legs_steps = max(1, min(args.steps, 3))
+    if args.legs and args.form == "plain" and wl.name == "microcircuit":
+        result.update(workload_legs(args.block_size, legs_steps))
     if args.copass and args.form == "plain":
-        cp = copass_bench(wl, args.block_size, max(1, min(args.steps, 3)), 1, args.radix_bits, args.sort_ranges)
+        cp = copass_bench(wl, args.block_size, legs_steps, 1, args.radix_bits, args.sort_ranges)
         cp["radix_peak_arena_GiB"] = round(radix_peak / 2**30, 3)
         log(f"copass: {cp['ms_per_step']} ms/step, peak arena {cp['peak_arena_GiB']} GiB "
             f"(radix {cp['radix_peak_arena_GiB']} GiB)")
         result["copass"] = cp
         torch.cuda.empty_cache()
     if args.arrays and args.form == "plain" and wl.name == "microcircuit":
-        ar = arrays_bench(wl, args.block_size, max(1, min(args.steps, 3)), 1, args.radix_bits, args.sort_ranges)
+        ar = arrays_bench(wl, args.block_size, legs_steps, 1, args.radix_bits, args.sort_ranges)
         log(f"arrays: {ar['ms_per_step']} ms/step")
         result["arrays"] = ar
         torch.cuda.empty_cache()
     if args.no_autapses and args.form == "plain" and wl.name == "microcircuit":
-        na = no_autapse_bench(wl, args.block_size, max(1, min(args.steps, 3)), 1, args.radix_bits, args.sort_ranges)
+        na = no_autapse_bench(wl, args.block_size, legs_steps, 1, args.radix_bits, args.sort_ranges)
         log(f"no autapses: {na['ms_per_step']} ms/step, generate {na['generate_ms_per_step']} ms")
         result["no_autapses"] = na
-        nm = no_autapse_bench(wl, args.block_size, max(1, min(args.steps, 3)), 1, args.radix_bits, args.sort_ranges,
+        nm = no_autapse_bench(wl, args.block_size, legs_steps, 1, args.radix_bits, args.sort_ranges,
                               multapses=0)
         log(f"no autapses, no multapses: {nm['ms_per_step']} ms/step, generate {nm['generate_ms_per_step']} ms")
         result["no_autapses_no_multapses"] = nm
         torch.cuda.empty_cache()
     if args.pairwise and args.form == "plain" and wl.name == "microcircuit":
-        pb = pairwise_bench(wl, args.block_size, max(1, min(args.steps, 3)), 1, args.radix_bits, args.sort_ranges)
+        pb = pairwise_bench(wl, args.block_size, legs_steps, 1, args.radix_bits, args.sort_ranges)
         log(f"pairwise_bernoulli: {pb['ms_per_step']} ms/step, {pb['connections']} connections")
         result["pairwise_bernoulli"] = pb
         torch.cuda.empty_cache()
@@ -738,7 +901,7 @@ def main() -> int:
         result["latency_p99_ms"] = at1["served"]["connect_p99_ms"]
         result["latency_load"] = "Poisson arrivals at the plain path's capacity, served form"
     if args.cpu_sample > 0 and wl.name == "microcircuit":
-        result["cpu_baseline"] = cpu_baseline(int(args.cpu_sample))
+        result["cpu_baseline"] = cpu_baseline(int(args.cpu_sample), int(args.cpu_one_thread))
     print(json.dumps(result))
     return 0
 

@@ -330,8 +330,9 @@ int ng_spikes_step(ng_ctx* ctx, const uint32_t* nodes, const uint32_t* mult, uin
  *   NG_CALIB_RADIX (default): stable radix sort of all connections into a
  *     second block set, in the most-significant-digit form (below) when one
  *     context is calibrated, its keys (source bits + delay bits) fit in 27
- *     bits and its connections average at least 256 per sub-bucket, else in
- *     the LSD form.
+ *     bits, its connections average at least 256 per sub-bucket and at
+ *     least 10 per possible key (n_nodes x 2^delay bits), else in the LSD
+ *     form.
  *   NG_CALIB_RADIX_MSD: the most-significant-digit form whenever one context
  *     with keys of at most 27 bits is calibrated (else LSD): a scatter by
  *     the top digit, a scatter of each bucket by the second digit, and runs
@@ -366,6 +367,14 @@ int ng_memory_stats(ng_ctx* ctx, uint64_t* used, uint64_t* peak, uint64_t* large
 /* Drop all nodes and connections (the context and its arena stay); the
  * next call ids start at 0 again.  Asynchronous: pending work still runs. */
 int ng_reset(ng_ctx* ctx);
+
+/* Seed of the context's Philox key (key = (seed mod 2^32, seed >> 32)),
+ * for a new network on the same context, e.g. the repetitions of one
+ * network over several seeds that the paper's timings average (Sec. 3).
+ * Only on a context that has issued no Connect call since ng_create or
+ * ng_reset, and not under graph capture or with live graphs: NG_ERR_STATE
+ * otherwise.  Stream-ordered on the context's stream. */
+int ng_set_seed(ng_ctx* ctx, uint64_t seed);
 
 /* Per-kernel device time: with timing on, every kernel launch of the context
  * is bracketed by HIP events on its stream.  ng_read_timing synchronizes and
@@ -479,7 +488,8 @@ uint64_t ng_blocks_needed(uint64_t n_conns, uint64_t n_new, uint64_t block_size,
  * max_delay steps, with sort_ranges static ranges per scatter pass (the
  * ng_set_tuning value, 1024 by default).  out[0] = 2 when the default
  * calibration takes the most-significant-digit form, 1 when only
- * NG_CALIB_RADIX_MSD takes it (too few connections per sub-bucket), 0 when
+ * NG_CALIB_RADIX_MSD takes it (too few connections per sub-bucket or per
+ * key), 0 when
  * it does not apply (keys wider than 27 bits, n_conns = 0 or >= 2^32; the
  * rest is then zero); out[1..3] = the widths b1, b2, b3
  * of the digits from the top (b2 = 0: no second scatter); out[4], out[5] =

@@ -198,7 +198,9 @@ hipError_t launch_msd_plan_b(const MsdPlan& p, hipStream_t s);
 hipError_t launch_msd_count_b(const MsdPlan& p, hipStream_t s);
 hipError_t launch_msd_scatter_b(const MsdPlan& p, hipStream_t s);
 hipError_t launch_msd_plan_c(const MsdPlan& p, hipStream_t s);
-hipError_t launch_msd_local_c(const MsdPlan& p, hipStream_t s);
+// pass C: tiles of whole sub-buckets, then the sub-buckets larger than one load
+hipError_t launch_msd_tiles_c(const MsdPlan& p, hipStream_t s);
+hipError_t launch_msd_big_c(const MsdPlan& p, hipStream_t s);
 hipError_t launch_msd_groups(const MsdPlan& p, hipStream_t s);
 
 // ---------------------------------------------------------------------------

@@ -1019,21 +1019,30 @@ hipError_t launch_msd_plan_c(const MsdPlan& p, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_msd_local_c(const MsdPlan& p, hipStream_t s) {
-  const bool narrow = p.b2 ? p.narrow_b : p.narrow_a;
-  // combined digits: sub-bucket offset in the tile above D3
+// Combined-digit width of pass C's tiles: sub-bucket offset above D3.
+static uint32_t c_digit_bits(const MsdPlan& p, bool narrow) {
   const uint32_t nd = msd_max_sub(p, narrow) << p.b3;
-  uint32_t cbits = 0;
-  while ((1u << cbits) < nd) ++cbits;
-  const dim3 big_grid(p.max_big < 256u ? p.max_big : 256u);
+  uint32_t bits = 0;
+  while ((1u << bits) < nd) ++bits;
+  return bits;
+}
+
+hipError_t launch_msd_tiles_c(const MsdPlan& p, hipStream_t s) {
+  const bool narrow = p.b2 ? p.narrow_b : p.narrow_a;
 #define F(RB)                                                                                           \
   if (narrow) hipLaunchKernelGGL((k_msd_tiles_c<RB, true>), dim3(p.wgs_c), dim3(kMThreads), 0, s, p);   \
   else hipLaunchKernelGGL((k_msd_tiles_c<RB, false>), dim3(p.wgs_c), dim3(kMThreads), 0, s, p);
-  M_RB_SWITCH(cbits, F)
+  M_RB_SWITCH(c_digit_bits(p, narrow), F)
 #undef F
-#define F(RB)                                                                                           \
-  if (narrow) hipLaunchKernelGGL((k_msd_big_c<RB, true>), big_grid, dim3(kMThreads), 0, s, p);          \
-  else hipLaunchKernelGGL((k_msd_big_c<RB, false>), big_grid, dim3(kMThreads), 0, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_msd_big_c(const MsdPlan& p, hipStream_t s) {
+  const bool narrow = p.b2 ? p.narrow_b : p.narrow_a;
+  const dim3 grid(p.max_big < 256u ? p.max_big : 256u);
+#define F(RB)                                                                                      \
+  if (narrow) hipLaunchKernelGGL((k_msd_big_c<RB, true>), grid, dim3(kMThreads), 0, s, p);          \
+  else hipLaunchKernelGGL((k_msd_big_c<RB, false>), grid, dim3(kMThreads), 0, s, p);
   M_RB_SWITCH(p.b3, F)
 #undef F
   return hipGetLastError();

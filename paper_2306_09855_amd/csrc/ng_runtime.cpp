@@ -1011,10 +1011,15 @@ bool msd_geometry(uint64_t N, uint32_t nn, int dbits, int log2B, uint32_t sort_r
 }
 
 // The default radix calibration takes the most-significant-digit form when
-// the sub-buckets it must visit hold 256 connections on average or more:
-// fewer connections over a wide key leave most sub-buckets empty, and the
-// LSD passes (a few launches over all records) are then cheaper.
-bool msd_pays(const ng::MsdPlan& p) { return (uint64_t)p.n >= (256ull << (p.b1 + p.b2)); }
+// (1) the sub-buckets it must visit hold 256 connections on average or more
+// (fewer connections over a wide key leave most sub-buckets empty), and (2)
+// the 512 keys that one LDS tile can tell apart hold at least half a tile of
+// connections (n >= 10 connections per occupied key: otherwise pass C sorts
+// nearly empty tiles).  Elsewhere the LSD passes are cheaper.
+bool msd_pays(const ng::MsdPlan& p) {
+  const uint64_t keyspace = (uint64_t)p.n_nodes << p.dbits;
+  return (uint64_t)p.n >= (256ull << (p.b1 + p.b2)) && (uint64_t)p.n * 512 >= keyspace * (ng::kMsdTile / 2);
+}
 
 // Calibration of one context by the most-significant-digit sort: count and
 // scatter by D1 (A), count and scatter each bucket by D2 (B), each
@@ -1088,7 +1093,8 @@ int calibrate_msd(CalSeg& g, const ng::MsdPlan& plan) {
     NG_LAUNCH_N(c, "msd_scatter_b", N, ng::launch_msd_scatter_b(p, s));
   }
   NG_LAUNCH(c, "msd_plan", ng::launch_msd_plan_c(p, s));
-  NG_LAUNCH_N(c, "msd_local_c", N, ng::launch_msd_local_c(p, s));
+  NG_LAUNCH_N(c, "msd_tiles_c", N, ng::launch_msd_tiles_c(p, s));
+  NG_LAUNCH(c, "msd_big_c", ng::launch_msd_big_c(p, s));
   NG_LAUNCH(c, "scan", ng::launch_exclusive_scan(p.gcount, p.gcount, nsb, scan_tmp, p.gcount + nsb, s));
   NG_LAUNCH(c, "msd_groups", ng::launch_msd_groups(p, s));
 
@@ -1818,6 +1824,17 @@ int ng_calibrate_noalloc(ng_ctx* c) {
 uint64_t ng_noalloc_scratch_bytes(void) { return kNoAllocScratchBytes; }
 
 int ng_calibrate_many(ng_ctx* const* ctxs, uint32_t n) { return calibrate_many(ctxs, n); }
+
+int ng_set_seed(ng_ctx* c, uint64_t seed) {
+  if (int rc = enter(c)) return rc;
+  if (int rc = mutable_state(c)) return rc;
+  if (int rc = not_capturing(c)) return rc;
+  if (c->n_conns != 0 || c->next_cid != 0)
+    return fail(NG_ERR_STATE, "the seed can change only on a context without Connect calls (after ng_reset)");
+  NG_HIP(c, set_seed(c, seed), "seed");
+  c->cfg.seed = seed;
+  return NG_OK;
+}
 
 int ng_reset(ng_ctx* c) {
   if (int rc = enter(c)) return rc;

@@ -136,6 +136,7 @@ def lib():
             "ng_spikes_step": ([vp, vp, vp, u32, vp], ctypes.c_int),
             "ng_memory_stats": ([vp, P(u64), P(u64), P(u64)], ctypes.c_int),
             "ng_reset": ([vp], ctypes.c_int),
+            "ng_set_seed": ([vp, u64], ctypes.c_int),
             "ng_enable_timing": ([vp, ctypes.c_int], ctypes.c_int),
             "ng_read_timing": ([vp, P(ng_kernel_time), ctypes.c_int, P(ctypes.c_int), ctypes.c_int],
                                ctypes.c_int),
@@ -324,6 +325,10 @@ def ng_copy_group_index(ctx, group_ptr=None, group_start=None) -> None:
 
 def ng_reset(ctx) -> None:
     _check(lib().ng_reset(ctx))
+
+
+def ng_set_seed(ctx, seed: int) -> None:
+    _check(lib().ng_set_seed(ctx, int(seed)))
 
 
 def ng_enable_timing(ctx, on: bool = True) -> None:

@@ -81,7 +81,7 @@ def test_copass_peak_memory_below_radix():
     wl = W.microcircuit(total=4_000_000)
     B = 1 << 18
     peaks = {}
-    for mode in ("radix", "lsd", "copass"):
+    for mode in ("msd", "lsd", "copass"):
         with Network(wl.seed, wl.h, B, arena_bytes_for(wl.n_syn, wl.n_nodes, wl.max_delay, B)) as net:
             net.set_calibration(mode)
             net.build(wl, calibrate=False)
@@ -94,11 +94,11 @@ def test_copass_peak_memory_below_radix():
     gcap = min(wl.n_syn, wl.n_nodes * wl.max_delay) + 1
     index = 8 * gcap + wl.n_syn // 8 + 4 * (wl.n_nodes + 1)
     # LSD radix: a second block set and two ping-pong copies of 12 bytes per
-    # record; most-significant-digit radix (the default here: 8-byte packed
-    # records): a second block set and two copies of 8 bytes; COPASS: three
-    # one-block buffers of 12 bytes per record on top of the blocks
+    # record; most-significant-digit radix (8-byte packed records here): a
+    # second block set and two copies of 8 bytes; COPASS: three one-block
+    # buffers of 12 bytes per record on top of the blocks
     assert peaks["lsd"] > data + index + 30 * wl.n_syn
-    assert data + 14 * wl.n_syn + 16 * wl.n_syn <= peaks["radix"] < peaks["lsd"]
+    assert data + 14 * wl.n_syn + 16 * wl.n_syn <= peaks["msd"] < peaks["lsd"]
     assert peaks["copass"] < data + index + 36 * B + (1 << 20)
 
 

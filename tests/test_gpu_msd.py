@@ -193,8 +193,9 @@ def _kernels_used(wl, calibration):
 
 def test_default_form_choice():
     # the default radix calibration sorts most-significant digit first when
-    # the sub-buckets average 256 connections or more, else by LSD passes
-    big = W.microcircuit(scale=0.05)
+    # the sub-buckets average 256 connections or more and the possible keys
+    # 10 or more, else by LSD passes
+    big = W.microcircuit(scale=0.1)
     assert _plan(big)["msd"] == 2
     names = _kernels_used(big, "radix")
     assert "msd_scatter_a" in names and "downsweep" not in names
@@ -203,3 +204,6 @@ def test_default_form_choice():
     names = _kernels_used(sparse, "radix")
     assert "downsweep" in names and not any(n.startswith("msd") for n in names)
     assert "downsweep" in _kernels_used(big, "lsd")
+    low_density = W.microcircuit(scale=0.05)  # 6 connections per possible key
+    assert _plan(low_density)["msd"] == 1
+    assert "downsweep" in _kernels_used(low_density, "radix")

@@ -210,3 +210,21 @@ def test_errors_leave_state_unchanged():
     ref = oracle.build_network(wl.seed, wl.h, wl.n_nodes, wl.calls)
     check_equal(out["src"], ref["s_src"], "src")
     check_equal(out["tgt"], ref["s_tgt"], "tgt")
+
+
+def test_set_seed():
+    # a context reset and reseeded builds the network of the new seed; the
+    # seed cannot change once a Connect call was issued
+    wl = W.two_pop_indegree(scale=0.3)
+    with _net(wl) as net:
+        net.build(wl)
+        with pytest.raises(ng.NGError) as e:
+            ng.ng_set_seed(net.ctx, 99)
+        assert e.value.status == ng.NG_ERR_STATE
+        ng.ng_reset(net.ctx)
+        ng.ng_set_seed(net.ctx, 99)
+        net.build(wl)
+        out = net.fetch()
+        gp, gs = net.group_index()
+    ref = oracle.build_network(99, wl.h, wl.n_nodes, wl.calls)
+    check_calibrated(out, gp, gs, ref, wl.calls)
