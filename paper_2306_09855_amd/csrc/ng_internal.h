@@ -149,7 +149,8 @@ hipError_t launch_set_entries(const TabEntry* d_entries, uint32_t n, hipStream_t
 // r + tbits <= 32 and tbits < 32; "wide" = the full u32 key, u32 tgt and u32
 // weight.  Buckets, sub-buckets and the ranges of pass B are laid out on the
 // device from the counts, so no value travels back to the host.
-constexpr uint32_t kMsdTile = 10240;      // records per tile of passes A and B
+constexpr uint32_t kMsdTile = 10240;      // records per tile of passes A and C, and of B with unpacked records
+constexpr uint32_t kMsdTileN = 16384;     // records per tile of B with packed (8-byte) records
 constexpr uint32_t kMsdMaxDigit = 9;      // widest digit
 constexpr uint32_t kMsdMaxKeyBits = 27;   // 3 x kMsdMaxDigit
 
@@ -160,7 +161,9 @@ struct MsdPlan {
   uint32_t narrow_a, narrow_b;      // formats of the output of A and of B
   uint32_t cbits;                   // packed records entering pass C: key bits held above the target
   uint32_t tpr;                     // tiles per range (passes A and B)
+  uint32_t tile_b;                  // records per tile of pass B (kMsdTileN when its input is packed)
   uint32_t ranges_a;                // ranges of pass A
+  uint32_t ranges_b;                // ranges of pass B wanted (spread over the buckets by their tiles)
   uint32_t max_ranges_b;            // ranges of pass B: at most this many
   uint32_t wgs_c;                   // workgroups of pass C
   uint32_t n_nodes;
@@ -174,6 +177,7 @@ struct MsdPlan {
   uint32_t* cnt_b;                  // [2^b2 * max_ranges_b] (bucket, digit, range) counts, scanned
   uint32_t* bstart;                 // [2^b1 + 1] bucket starts
   uint32_t* rangeb0;                // [2^b1 + 1] first range of pass B of each bucket
+  uint32_t* tprb;                   // [2^b1] tiles per range of pass B of each bucket
   uint32_t* sbstart;                // [2^(b1+b2) + 1] sub-bucket starts
   uint32_t* wg_sb0;                 // [wgs_c + 1] first sub-bucket of each workgroup of C
   uint32_t* big_count;              // sub-buckets larger than one LDS load (set by pass C)

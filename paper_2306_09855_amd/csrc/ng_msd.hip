@@ -31,8 +31,10 @@ namespace {
 
 constexpr int kMThreads = 512;
 constexpr int kMWaves = kMThreads / 64;
-constexpr int kMItems = 20;
-static_assert(kMThreads * kMItems == (int)kMsdTile, "tile of passes A and B");
+constexpr int kMItems = 20;                          // tile of pass A and of unpacked records
+constexpr int kMItemsN = (int)kMsdTileN / kMThreads;  // tile of packed records (passes B and C)
+static_assert(kMThreads * kMItems == (int)kMsdTile, "tile of unpacked records");
+static_assert(kMThreads * kMItemsN == (int)kMsdTileN, "tile of packed records");
 constexpr int kMNB = 1 << kMsdMaxDigit;  // 512 digit values at most
 static_assert(kMNB == kMThreads, "one thread per digit value");
 constexpr int kMLdsBlocks = 512;
@@ -136,13 +138,13 @@ __device__ __forceinline__ void load_arrays(const uint32_t* ik, const uint32_t* 
 // counter of that digit with one LDS atomic (other lanes add to a private
 // word), and the old value reaches its peers through a lane permute a few
 // slots later, so no slot waits on the one before it.  The digit of a key is
-// ((key >> shift) - base) & mask.  On return pos[k] is the rank within the
+// ((key >> shift) - base) & mask, below 2^nbits (ballots only for those bits).  On return pos[k] is the rank within the
 // wave's records of the digit, and wh[wave][d] holds the wave's count of
 // digit d.
 template <int RB, int ITEMS, bool FULL>
 __device__ __forceinline__ void rank_digits(const uint32_t (&key)[ITEMS], uint32_t shift, uint32_t mask, uint32_t cnt,
                                             uint32_t* wh, uint32_t* sink, uint32_t (&pos)[ITEMS],
-                                            uint32_t base = 0) {
+                                            uint32_t base = 0, uint32_t nbits = RB) {
   constexpr int kLag = 4;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t prv[ITEMS];
@@ -162,10 +164,12 @@ __device__ __forceinline__ void rank_digits(const uint32_t (&key)[ITEMS], uint32
       }
 #pragma unroll
       for (int b = 0; b < RB; ++b) {
-        const uint32_t sb = (uint32_t)((int32_t)(d << (31 - b)) >> 31);  // bit b, all ones or zero
-        const uint64_t m = __ballot(sb != 0u);
-        plo &= ~((uint32_t)m ^ sb);
-        phi &= ~((uint32_t)(m >> 32) ^ sb);
+        if ((uint32_t)b < nbits) {  // digits are below 2^nbits (a uniform test)
+          const uint32_t sb = (uint32_t)((int32_t)(d << (31 - b)) >> 31);  // bit b, all ones or zero
+          const uint64_t m = __ballot(sb != 0u);
+          plo &= ~((uint32_t)m ^ sb);
+          phi &= ~((uint32_t)(m >> 32) ^ sb);
+        }
       }
       const uint32_t below = __builtin_amdgcn_mbcnt_hi(phi, __builtin_amdgcn_mbcnt_lo(plo, 0u));
       const uint32_t tot = (uint32_t)__popc(plo) + (uint32_t)__popc(phi);
@@ -181,6 +185,24 @@ __device__ __forceinline__ void rank_digits(const uint32_t (&key)[ITEMS], uint32
     }
     __builtin_amdgcn_sched_barrier(0);  // keep the lag: no permute moves up to its add
   }
+}
+
+// m_block_scan without its closing barrier, for callers whose next use of
+// s_tmp comes after another barrier.
+__device__ __forceinline__ uint32_t m_block_scan_open(uint32_t v, uint32_t* s_tmp, uint32_t* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t inc = wave_inclusive_scan(v);
+  if (lane == 63) s_tmp[wave] = inc;
+  lds_barrier();
+  uint32_t off = 0, sum = 0;
+#pragma unroll
+  for (int w = 0; w < kMWaves; ++w) {
+    const uint32_t t = s_tmp[w];
+    if (w < wave) off += t;
+    sum += t;
+  }
+  *total = sum;
+  return off + inc - v;
 }
 
 // Thread d: digit d's counts over the waves become each wave's first tile
@@ -203,6 +225,34 @@ __device__ __forceinline__ uint32_t digit_starts(uint32_t nd, uint32_t* wh, uint
     for (int v = 0; v < kMWaves; ++v) wh[v * kMNB + d] = st + c[v];
   }
   *start = st;
+  return tot;
+}
+
+// digit_starts for pass C, which also needs the present digits: one scan of
+// (count << 10 | present) gives each digit's first tile position (*start)
+// and the number of present digits before it (*ex); *all = the tile's
+// records << 10 | its present digits.  Leaves s_tmp in use (a barrier must
+// come before its next use).
+__device__ __forceinline__ uint32_t digit_starts_present(uint32_t nd, uint32_t* wh, uint32_t* s_tmp,
+                                                         uint32_t* start, uint32_t* ex, uint32_t* all) {
+  const uint32_t d = threadIdx.x;
+  uint32_t c[kMWaves];
+  uint32_t tot = 0;
+#pragma unroll
+  for (int v = 0; v < kMWaves; ++v) {
+    const uint32_t x = d < nd ? wh[v * kMNB + d] : 0u;
+    c[v] = tot;
+    tot += x;
+  }
+  // tot < 2^15 (one load), at most 512 present digits: the fields do not mix
+  const uint32_t sc = m_block_scan_open((tot << 10) | (tot ? 1u : 0u), s_tmp, all);
+  const uint32_t st = sc >> 10;
+  if (d < nd) {
+#pragma unroll
+    for (int v = 0; v < kMWaves; ++v) wh[v * kMNB + d] = st + c[v];
+  }
+  *start = st;
+  *ex = sc & 1023u;
   return tot;
 }
 
@@ -245,13 +295,13 @@ __device__ __forceinline__ void load_tile_any(const PassIO& io, uint32_t base, u
 
 // One tile, its records in registers; next_cnt > 0: the next tile's records
 // load (into r) while this tile's runs are written.
-template <int RB, int IN, bool OUT_NARROW, bool FULL>
-__device__ __forceinline__ void scatter_tile(const PassIO& io, uint32_t cnt, const ScatterLds& L, Recs<kMItems>& r,
+template <int RB, int IN, bool OUT_NARROW, bool FULL, int ITEMS>
+__device__ __forceinline__ void scatter_tile(const PassIO& io, uint32_t cnt, const ScatterLds& L, Recs<ITEMS>& r,
                                              uint32_t next_base, uint32_t next_cnt) {
   constexpr bool HAS_T = IN != IN_NARROW;
   const int wave = threadIdx.x >> 6;
-  uint32_t pos[kMItems];
-  rank_digits<RB, kMItems, FULL>(r.k, io.shift, io.mask, cnt, L.wh, L.sink, pos);
+  uint32_t pos[ITEMS];
+  rank_digits<RB, ITEMS, FULL>(r.k, io.shift, io.mask, cnt, L.wh, L.sink, pos);
   lds_barrier();
   {
     const uint32_t d = threadIdx.x;
@@ -266,8 +316,8 @@ __device__ __forceinline__ void scatter_tile(const PassIO& io, uint32_t cnt, con
   }
   lds_barrier();
 #pragma unroll
-  for (int k = 0; k < kMItems; ++k) {
-    if (FULL || item_index(kMItems, k) < cnt) {
+  for (int k = 0; k < ITEMS; ++k) {
+    if (FULL || item_index(ITEMS, k) < cnt) {
       const uint32_t p = pos[k] + L.wh[wave * kMNB + ((r.k[k] >> io.shift) & io.mask)];
       L.k[p] = r.k[k];
       if constexpr (HAS_T) L.t[p] = r.t[k];
@@ -279,13 +329,13 @@ __device__ __forceinline__ void scatter_tile(const PassIO& io, uint32_t cnt, con
 #pragma unroll
     for (int v = 0; v < kMWaves; ++v) L.wh[v * kMNB + d] = 0;
   }
-  if (next_cnt) load_tile_any<kMItems, IN>(io, next_base, next_cnt, r);
+  if (next_cnt) load_tile_any<ITEMS, IN>(io, next_base, next_cnt, r);
   // Runs of equal digits go to consecutive positions.  Stores of records
   // whose 128-byte lines the run fills are marked streaming; the partial
   // lines at a run's ends stay cached, so that the neighbouring tile's run
   // can complete them in L2 before they reach HBM.
 #pragma unroll
-  for (int k = 0; k < kMItems; ++k) {
+  for (int k = 0; k < ITEMS; ++k) {
     const uint32_t lp = (uint32_t)(k * kMThreads + threadIdx.x);
     if (FULL || lp < cnt) {
       const uint32_t kk = L.k[lp];
@@ -311,29 +361,30 @@ __device__ __forceinline__ void scatter_tile(const PassIO& io, uint32_t cnt, con
 
 // Tiles [t0, t1) of a record span starting at span0 and ending at span1:
 // tile t holds records [span0 + t * tile, min(span0 + (t + 1) * tile, span1)).
-template <int RB, int IN, bool OUT_NARROW>
+template <int RB, int IN, bool OUT_NARROW, int ITEMS>
 __device__ __forceinline__ void scatter_range(const PassIO& io, const ScatterLds& L, uint32_t span0, uint32_t span1,
                                               uint32_t t0, uint32_t t1) {
+  constexpr uint32_t TILE = (uint32_t)(ITEMS * kMThreads);
   if (t0 >= t1) return;
-  Recs<kMItems> r;
+  Recs<ITEMS> r;
   auto tile_cnt = [&](uint32_t t) {
-    const uint32_t b = span0 + t * kMsdTile;
-    return span1 - b < kMsdTile ? span1 - b : kMsdTile;
+    const uint32_t b = span0 + t * TILE;
+    return span1 - b < TILE ? span1 - b : TILE;
   };
-  load_tile_any<kMItems, IN>(io, span0 + t0 * kMsdTile, tile_cnt(t0), r);
+  load_tile_any<ITEMS, IN>(io, span0 + t0 * TILE, tile_cnt(t0), r);
   for (uint32_t t = t0; t < t1; ++t) {
     const uint32_t cnt = tile_cnt(t);
-    const uint32_t nb = t + 1 < t1 ? span0 + (t + 1) * kMsdTile : 0u;
+    const uint32_t nb = t + 1 < t1 ? span0 + (t + 1) * TILE : 0u;
     const uint32_t nc = t + 1 < t1 ? tile_cnt(t + 1) : 0u;
-    if (cnt == kMsdTile) scatter_tile<RB, IN, OUT_NARROW, true>(io, cnt, L, r, nb, nc);
-    else scatter_tile<RB, IN, OUT_NARROW, false>(io, cnt, L, r, nb, nc);
+    if (cnt == TILE) scatter_tile<RB, IN, OUT_NARROW, true, ITEMS>(io, cnt, L, r, nb, nc);
+    else scatter_tile<RB, IN, OUT_NARROW, false, ITEMS>(io, cnt, L, r, nb, nc);
   }
 }
 
-#define M_SCATTER_LDS                                   \
-  __shared__ uint32_t s_k[kMsdTile];                    \
-  __shared__ uint32_t s_t[IN == IN_NARROW ? 1 : kMsdTile]; \
-  __shared__ uint32_t s_w[kMsdTile];                    \
+#define M_SCATTER_LDS(TILE)                             \
+  __shared__ uint32_t s_k[TILE];                        \
+  __shared__ uint32_t s_t[IN == IN_NARROW ? 1 : TILE];  \
+  __shared__ uint32_t s_w[TILE];                        \
   __shared__ uint32_t s_wh[kMWaves * kMNB];             \
   __shared__ uint4 s_dig[kMNB];                         \
   __shared__ uint32_t s_run[kMNB];                      \
@@ -345,7 +396,7 @@ __device__ __forceinline__ void scatter_range(const PassIO& io, const ScatterLds
 template <int RB, bool OUT_NARROW>
 __global__ __launch_bounds__(kMThreads) void k_msd_scatter_a(MsdPlan p) {
   constexpr int IN = IN_BLOCKS;
-  M_SCATTER_LDS
+  M_SCATTER_LDS(kMsdTile)
   const uint32_t r = m_range((p.ranges_a + 7) / 8);
   if (r >= p.ranges_a) return;
   const uint32_t nd = 1u << p.b1;
@@ -368,7 +419,7 @@ __global__ __launch_bounds__(kMThreads) void k_msd_scatter_a(MsdPlan p) {
   lds_barrier();
   const uint32_t ntiles = (p.n + kMsdTile - 1) / kMsdTile;
   const uint32_t t0 = r * p.tpr, t1 = min(t0 + p.tpr, ntiles);
-  scatter_range<RB, IN, OUT_NARROW>(io, L, 0u, p.n, t0, t1);
+  scatter_range<RB, IN, OUT_NARROW, kMItems>(io, L, 0u, p.n, t0, t1);
 }
 
 // Bucket of pass-B range r: the last b with rangeb0[b] <= r (from LDS).
@@ -385,7 +436,8 @@ __device__ __forceinline__ uint32_t bucket_of_range(const uint32_t* s_rb0, uint3
 // Pass B: range r of a bucket by D2.
 template <int RB, int IN, bool OUT_NARROW>
 __global__ __launch_bounds__(kMThreads) void k_msd_scatter_b(MsdPlan p) {
-  M_SCATTER_LDS
+  constexpr int ITEMS = IN == IN_NARROW ? kMItemsN : kMItems;  // the tile is p.tile_b records
+  M_SCATTER_LDS(ITEMS * kMThreads)
   __shared__ uint32_t s_rb0[kMNB + 1];
   const uint32_t nb = 1u << p.b1, nd = 1u << p.b2;
   for (uint32_t b = threadIdx.x; b <= nb; b += kMThreads) s_rb0[b] = p.rangeb0[b];
@@ -413,9 +465,10 @@ __global__ __launch_bounds__(kMThreads) void k_msd_scatter_b(MsdPlan p) {
     for (int v = 0; v < kMWaves; ++v) s_wh[v * kMNB + d] = 0;
   }
   lds_barrier();
-  const uint32_t ntiles = (be - bs + kMsdTile - 1) / kMsdTile;
-  const uint32_t t0 = rl * p.tpr, t1 = min(t0 + p.tpr, ntiles);
-  scatter_range<RB, IN, OUT_NARROW>(io, L, bs, be, t0, t1);
+  const uint32_t ntiles = (be - bs + p.tile_b - 1) / p.tile_b;
+  const uint32_t tpr = p.tprb[b];
+  const uint32_t t0 = rl * tpr, t1 = min(t0 + tpr, ntiles);
+  scatter_range<RB, IN, OUT_NARROW, ITEMS>(io, L, bs, be, t0, t1);
 }
 
 // ---------------------------------------------------------------------------
@@ -487,8 +540,9 @@ __global__ __launch_bounds__(kMThreads) void k_msd_count_b(MsdPlan p) {
   const uint32_t rl = r - s_rb0[b], nr = s_rb0[b + 1] - s_rb0[b];
   const uint32_t bs = p.bstart[b], be = p.bstart[b + 1];
   const uint32_t shift = (IN == IN_NARROW ? p.tbits : 0u) + p.b3;
-  const uint32_t lo = bs + rl * p.tpr * kMsdTile;
-  const uint32_t hi = (be - lo) / kMsdTile < p.tpr ? be : lo + p.tpr * kMsdTile;
+  const uint32_t tpr = p.tprb[b];
+  const uint32_t lo = bs + rl * tpr * p.tile_b;
+  const uint32_t hi = (be - lo) / p.tile_b < tpr ? be : lo + tpr * p.tile_b;
   // 16-byte loads over the aligned middle (the key array starts 256-byte
   // aligned), four in flight per thread; single words at the ends
   const uint32_t a0 = min(hi, (lo + 3u) & ~3u), a1 = max(a0, hi & ~3u);
@@ -526,7 +580,8 @@ __global__ __launch_bounds__(kMThreads) void k_msd_count_b(MsdPlan p) {
 // Start tables.
 // ---------------------------------------------------------------------------
 // Bucket starts from the scanned counts of pass A, and the ranges of pass B
-// (tiles of kMsdTile records from each bucket's start, tpr tiles per range).
+// (tiles of tile_b records from each bucket's start, tprb[b] tiles per range
+// of bucket b).
 // One workgroup, one thread per bucket.  Without pass B the buckets are the
 // sub-buckets.
 __global__ __launch_bounds__(kMThreads) void k_msd_plan_b(MsdPlan p) {
@@ -543,8 +598,19 @@ __global__ __launch_bounds__(kMThreads) void k_msd_plan_b(MsdPlan p) {
     p.bstart[nb] = p.n;
     if (p.b2 == 0) p.sbstart[nb] = p.n;
   }
-  const uint32_t ntiles = (be - bs + kMsdTile - 1) / kMsdTile;
-  const uint32_t nr = (ntiles + p.tpr - 1) / p.tpr;
+  // Every bucket gets ranges in proportion to its tiles, about ranges_b in
+  // all, and its tiles are spread evenly over them, so that all ranges of
+  // pass B hold about the same number of tiles (no short last ranges).
+  const uint32_t ntiles = (be - bs + p.tile_b - 1) / p.tile_b;
+  uint32_t all_tiles;
+  (void)m_block_scan(b < nb ? ntiles : 0u, s_tmp, &all_tiles);
+  uint32_t nr = 0, tpr = 1;
+  if (b < nb && ntiles) {
+    const uint64_t want = ((uint64_t)ntiles * p.ranges_b + all_tiles - 1) / all_tiles;  // >= 1
+    tpr = (uint32_t)((ntiles + want - 1) / want);
+    nr = (ntiles + tpr - 1) / tpr;  // <= want
+  }
+  if (b < nb) p.tprb[b] = tpr;
   uint32_t total;
   const uint32_t ex = m_block_scan(b < nb ? nr : 0u, s_tmp, &total);
   if (b < nb) p.rangeb0[b] = ex;
@@ -610,7 +676,16 @@ __device__ __forceinline__ char* m_out_block(const MsdPlan& p, char* const* s_bl
   return s_blk ? s_blk[dest >> p.log2B] : C(p.out_blocks, dest >> p.log2B);
 }
 
-constexpr uint32_t kCTile = kMsdTile;  // records per LDS load
+// Records per LDS load of pass C: 10,240 for packed and unpacked records.
+// (Measured on the 3e8 microcircuit: 16,384-record tiles spill registers and
+// took 2.46 ms; 6,144-record tiles with two workgroups per CU need a
+// narrower last digit, hence a 9-bit second scatter, and took 2.38 ms plus
+// 0.7 ms more in pass B; 10,240: 2.27 ms.)
+template <bool NARROW>
+struct CSize {
+  static constexpr int ITEMS = kMItems;
+  static constexpr uint32_t TILE = (uint32_t)(ITEMS * kMThreads);
+};
 constexpr uint32_t kCMaxSub = 63;      // sub-buckets per tile: lanes 1..63 test the ends
 
 // Sub-buckets per tile: bounded by the lanes of one wave, by 9-bit combined
@@ -641,7 +716,7 @@ __device__ __forceinline__ uint32_t tile_probe(const MsdPlan& p, uint32_t sb, ui
   return G(p.sbstart)[sb + min(lane, lim)];
 }
 
-__device__ __forceinline__ CTile tile_finish(uint32_t st, uint32_t sb, uint32_t lim, uint32_t m) {
+__device__ __forceinline__ CTile tile_finish(uint32_t st, uint32_t sb, uint32_t lim, uint32_t m, uint32_t cap) {
   const uint32_t lane = threadIdx.x & 63;
   CTile t{sb, sb, 0, 0};
   if (lim == 0) return t;
@@ -651,7 +726,7 @@ __device__ __forceinline__ CTile tile_finish(uint32_t st, uint32_t sb, uint32_t 
     t.e = sb + (uint32_t)__popcll(__ballot(lane <= lim && st == r0)) - 1u;
     return t;
   }
-  const bool ok = lane <= min(lim, m) && st - r0 <= kCTile;
+  const bool ok = lane <= min(lim, m) && st - r0 <= cap;
   const uint32_t L = (uint32_t)__popcll(__ballot(ok)) - 1u;  // lane 0 always fits
   const uint32_t Lx = L ? L : 1u;
   t.e = sb + Lx;
@@ -663,29 +738,29 @@ __device__ __forceinline__ CTile tile_finish(uint32_t st, uint32_t sb, uint32_t 
 // load and ranking, which keeps its loop within the register file.
 template <bool NARROW>
 __device__ __forceinline__ void load_c(const uint32_t* ik, const uint32_t* it, const uint32_t* iw, uint32_t base,
-                                       uint32_t cnt, Recs<kMItems>& r) {
-  load_arrays<kMItems, NARROW ? IN_NARROW : IN_WIDE, false>(ik, it, iw, base, cnt, r);
+                                       uint32_t cnt, Recs<CSize<NARROW>::ITEMS>& r) {
+  load_arrays<CSize<NARROW>::ITEMS, NARROW ? IN_NARROW : IN_WIDE, false>(ik, it, iw, base, cnt, r);
 }
 
+template <bool NARROW>
 __device__ __forceinline__ bool tile_fits(const CTile& t) {
-  return t.e > t.sb && t.r1 > t.r0 && t.r1 - t.r0 <= kCTile;
+  return t.e > t.sb && t.r1 > t.r0 && t.r1 - t.r0 <= CSize<NARROW>::TILE;
 }
 
 // The connection groups of a tile of nsub sub-buckets from sba whose records
 // start at r0 (Sec. 2.2): each present combined digit (thread d, h = its
-// record count, 0 past the tile's digits) is a group.  Its start goes to its
-// sub-bucket's offset in gslot, at the group's rank in the sub-bucket; each
-// sub-bucket gets its group count and its mask of present D3 values.  Leaves
-// s_st[d] = the tile position of digit d's first record.  All threads call;
-// ends with a barrier.
+// record count, 0 past the tile's digits; hst = records and ex = present
+// digits before it, all_present = the tile's present digits) is a group.
+// Its start goes to its sub-bucket's offset in gslot, at the group's rank in
+// the sub-bucket; each sub-bucket gets its group count and its mask of
+// present D3 values.  Uses s_ex, s_st, s_bal; contains one barrier, after
+// which the LDS writes made before the call are visible to all.
 __device__ __forceinline__ void tile_groups(const MsdPlan& p, uint32_t sba, uint32_t nsub, uint32_t r0, uint32_t h,
-                                            uint32_t* s_ex, uint32_t* s_st, uint32_t* s_tmp, uint32_t* s_bal) {
+                                            uint32_t hst, uint32_t ex, uint32_t all_present, uint32_t* s_ex,
+                                            uint32_t* s_st, uint32_t* s_bal) {
   const uint32_t d = threadIdx.x, lane = d & 63, wave = d >> 6;
   const uint32_t b3 = p.b3, m3 = (1u << b3) - 1u, nd = nsub << b3;
   const bool present = h != 0;
-  uint32_t all, cnt_all;
-  const uint32_t ex = m_block_scan(present ? 1u : 0u, s_tmp, &all);
-  const uint32_t hst = m_block_scan(h, s_tmp, &cnt_all);
   const uint64_t bal = __ballot(present);
   s_ex[d] = ex;
   s_st[d] = hst;
@@ -693,7 +768,7 @@ __device__ __forceinline__ void tile_groups(const MsdPlan& p, uint32_t sba, uint
     s_bal[2 * wave] = (uint32_t)bal;
     s_bal[2 * wave + 1] = (uint32_t)(bal >> 32);
   }
-  if (d == 0) s_ex[kMNB] = all;
+  if (d == 0) s_ex[kMNB] = all_present;
   lds_barrier();
   if (present) {
     const uint32_t d0 = d & ~m3;  // first digit of its sub-bucket
@@ -710,13 +785,12 @@ __device__ __forceinline__ void tile_groups(const MsdPlan& p, uint32_t sba, uint
       G(p.gmask)[sba + (d >> b3)] = (s_bal[d >> 5] >> (d & 31u)) & ((1u << (1u << b3)) - 1u);
     }
   }
-  lds_barrier();
 }
 
 #define M_C_LDS                                  \
-  __shared__ uint32_t s_k[kCTile];               \
-  __shared__ uint32_t s_t[NARROW ? 1 : kCTile];  \
-  __shared__ uint32_t s_w[kCTile];               \
+  __shared__ uint32_t s_k[CSize<NARROW>::TILE];              \
+  __shared__ uint32_t s_t[NARROW ? 1 : CSize<NARROW>::TILE]; \
+  __shared__ uint32_t s_w[CSize<NARROW>::TILE];              \
   __shared__ uint32_t s_wh[kMWaves * kMNB];      \
   __shared__ uint32_t s_st[kMNB + 1];            \
   __shared__ uint32_t s_ex[kMNB + 1];            \
@@ -768,7 +842,7 @@ __device__ __forceinline__ void c_store(const MsdPlan& p, const CFields& f, char
                                         uint32_t kb, const uint32_t* dx, uint32_t r0) {
   const uint64_t B = 1ull << p.log2B;
 #pragma unroll
-  for (int k = 0; k < kMItems; ++k) {
+  for (int k = 0; k < CSize<NARROW>::ITEMS; ++k) {
     const uint32_t lp = (uint32_t)(k * kMThreads + threadIdx.x);
     if (lp < cnt) {
       const uint32_t kk = s_k[lp];
@@ -787,13 +861,14 @@ __device__ __forceinline__ void c_store(const MsdPlan& p, const CFields& f, char
 
 // Records ranked by their combined digit move to their sorted places in LDS.
 template <bool NARROW>
-__device__ __forceinline__ void c_stage(const CFields& f, const Recs<kMItems>& r, const uint32_t (&pos)[kMItems],
+__device__ __forceinline__ void c_stage(const CFields& f, const Recs<CSize<NARROW>::ITEMS>& r,
+                                        const uint32_t (&pos)[CSize<NARROW>::ITEMS],
                                         uint32_t cnt, uint32_t base, const uint32_t* s_wh, uint32_t* s_k, uint32_t* s_t,
                                         uint32_t* s_w) {
   const int wave = threadIdx.x >> 6;
 #pragma unroll
-  for (int k = 0; k < kMItems; ++k) {
-    if (item_index(kMItems, k) < cnt) {
+  for (int k = 0; k < CSize<NARROW>::ITEMS; ++k) {
+    if (item_index(CSize<NARROW>::ITEMS, k) < cnt) {
       const uint32_t dg = ((r.k[k] >> f.ks) - base) & f.km;
       const uint32_t q = pos[k] + s_wh[wave * kMNB + dg];
       s_k[q] = r.k[k];
@@ -816,7 +891,7 @@ __device__ __forceinline__ void clear_wh(uint32_t* s_wh) {
 template <int RB, bool NARROW>
 __global__ __launch_bounds__(kMThreads) void k_msd_tiles_c(MsdPlan p) {
   M_C_LDS
-  __shared__ CTile s_next;
+  __shared__ CTile s_next[2];  // by iteration parity: wave 0 writes one while the other is read
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const CFields f = c_fields<NARROW>(p);
   char* const* s_blk = c_setup(p, s_blk_tab, s_wh);
@@ -824,16 +899,18 @@ __global__ __launch_bounds__(kMThreads) void k_msd_tiles_c(MsdPlan p) {
   const uint32_t sb0 = p.wg_sb0[blockIdx.x], sb_end = p.wg_sb0[blockIdx.x + 1];
   if (wave == 0) {
     const uint32_t lim = min(kCMaxSub, sb_end - sb0);
-    const CTile t = tile_finish(tile_probe(p, sb0, lim), sb0, lim, f.msub);
-    if (lane == 0) s_next = t;
+    const CTile t = tile_finish(tile_probe(p, sb0, lim), sb0, lim, f.msub, CSize<NARROW>::TILE);
+    if (lane == 0) s_next[0] = t;
   }
   lds_barrier();
-  CTile cur = s_next;
-  lds_barrier();  // read by all before wave 0 writes the next one
-  Recs<kMItems> r;
+  CTile cur = s_next[0];
+  uint32_t par = 1;  // s_next[par] receives the tile after cur
+  constexpr int ITEMS = CSize<NARROW>::ITEMS;
+  constexpr uint32_t TILE = CSize<NARROW>::TILE;
+  Recs<ITEMS> r;
   // invariant at the top of the loop: loaded == tile_fits(cur), and then r
   // holds cur's records
-  bool loaded = tile_fits(cur);
+  bool loaded = tile_fits<NARROW>(cur);
   if (loaded) load_c<NARROW>(f.ik, f.it, f.iw, cur.r0, cur.r1 - cur.r0, r);
   while (cur.e > cur.sb) {
     const uint32_t n = cur.r1 - cur.r0;
@@ -841,43 +918,46 @@ __global__ __launch_bounds__(kMThreads) void k_msd_tiles_c(MsdPlan p) {
     const uint32_t lim = min(kCMaxSub, sb_end - cur.e);
     uint32_t probe = 0;
     if (wave == 0) probe = tile_probe(p, cur.e, lim);  // used after the ranking
-    if (n == 0 || n > kCTile) {
+    if (n == 0 || n > TILE) {
       // empty sub-buckets: nothing to do; one sub-bucket too large for one
       // load: listed for k_msd_big_c
       if (n && threadIdx.x == 0) G(p.big_list)[atomicAdd(p.big_count, 1u)] = cur.sb;
       if (wave == 0) {
-        const CTile t = tile_finish(probe, cur.e, lim, f.msub);
-        if (lane == 0) s_next = t;
+        const CTile t = tile_finish(probe, cur.e, lim, f.msub, TILE);
+        if (lane == 0) s_next[par] = t;
       }
     } else {
       const uint32_t base = (cur.sb << b3) & f.km;
-      uint32_t pos[kMItems];
-      rank_digits<RB, kMItems, false>(r.k, f.ks, f.km, n, s_wh, s_sink, pos, base);
+      const uint32_t nd = nsub << b3;
+      uint32_t nbits = 1;
+      while ((1u << nbits) < nd) ++nbits;
+      uint32_t pos[ITEMS];
+      rank_digits<RB, ITEMS, false>(r.k, f.ks, f.km, n, s_wh, s_sink, pos, base, nbits);
       if (wave == 0) {
-        const CTile t = tile_finish(probe, cur.e, lim, f.msub);
-        if (lane == 0) s_next = t;
+        const CTile t = tile_finish(probe, cur.e, lim, f.msub, TILE);
+        if (lane == 0) s_next[par] = t;
       }
       lds_barrier();
-      uint32_t st;
-      const uint32_t d = threadIdx.x, nd = nsub << b3;
-      const uint32_t tot = digit_starts(nd, s_wh, s_tmp, &st);
-      tile_groups(p, cur.sb, nsub, cur.r0, d < nd ? tot : 0u, s_ex, s_st, s_tmp, s_bal);
+      uint32_t st, ex, all;
+      const uint32_t d = threadIdx.x;
+      const uint32_t tot = digit_starts_present(nd, s_wh, s_tmp, &st, &ex, &all);
+      tile_groups(p, cur.sb, nsub, cur.r0, d < nd ? tot : 0u, st, ex, all & 1023u, s_ex, s_st, s_bal);
       c_stage<NARROW>(f, r, pos, n, base, s_wh, s_k, s_t, s_w);
       lds_barrier();
       clear_wh(s_wh);
-      const CTile nx = s_next;
-      loaded = tile_fits(nx);
+      const CTile nx = s_next[par];
+      loaded = tile_fits<NARROW>(nx);
       if (loaded) load_c<NARROW>(f.ik, f.it, f.iw, nx.r0, nx.r1 - nx.r0, r);
       c_store<NARROW>(p, f, s_blk, s_k, s_t, s_w, n, base, cur.sb << b3, nullptr, cur.r0);
     }
-    lds_barrier();  // s_next is complete; the tile's LDS is free
-    const CTile nx = s_next;
-    if (!loaded && tile_fits(nx)) {
+    lds_barrier();  // s_next[par] is complete; the tile's LDS is free
+    const CTile nx = s_next[par];
+    if (!loaded && tile_fits<NARROW>(nx)) {
       load_c<NARROW>(f.ik, f.it, f.iw, nx.r0, nx.r1 - nx.r0, r);
       loaded = true;
     }
     cur = nx;
-    lds_barrier();  // read by all before wave 0 writes it again
+    par ^= 1u;  // wave 0 next writes the other slot; this one is read before the next barrier
   }
 }
 
@@ -901,14 +981,22 @@ __global__ __launch_bounds__(kMThreads) void k_msd_big_c(MsdPlan p) {
     lds_barrier();
     for (uint32_t j = d; j < n; j += kMThreads) atomicAdd(&s_cur[((G(f.ik)[r0 + j] >> f.ks) - base) & f.km], 1u);
     lds_barrier();
-    tile_groups(p, sb, 1u, r0, d < nd ? s_cur[d] : 0u, s_ex, s_st, s_tmp, s_bal);
-    if (d < nd) s_cur[d] = r0 + s_st[d];
-    for (uint32_t c0 = 0; c0 < n; c0 += kCTile) {
-      const uint32_t cnt = n - c0 < kCTile ? n - c0 : kCTile;
-      Recs<kMItems> r;
+    {
+      // a large sub-bucket may hold any number of records per digit: two scans
+      const uint32_t h = d < nd ? s_cur[d] : 0u;
+      uint32_t all_rec, all_present;
+      const uint32_t hst = m_block_scan(h, s_tmp, &all_rec);
+      const uint32_t ex = m_block_scan(h ? 1u : 0u, s_tmp, &all_present);
+      tile_groups(p, sb, 1u, r0, h, hst, ex, all_present, s_ex, s_st, s_bal);
+      lds_barrier();
+      if (d < nd) s_cur[d] = r0 + hst;
+    }
+    for (uint32_t c0 = 0; c0 < n; c0 += CSize<NARROW>::TILE) {
+      const uint32_t cnt = n - c0 < CSize<NARROW>::TILE ? n - c0 : CSize<NARROW>::TILE;
+      Recs<CSize<NARROW>::ITEMS> r;
       load_c<NARROW>(f.ik, f.it, f.iw, r0 + c0, cnt, r);
-      uint32_t pos[kMItems];
-      rank_digits<RB, kMItems, false>(r.k, f.ks, f.km, cnt, s_wh, s_sink, pos, base);
+      uint32_t pos[CSize<NARROW>::ITEMS];
+      rank_digits<RB, CSize<NARROW>::ITEMS, false>(r.k, f.ks, f.km, cnt, s_wh, s_sink, pos, base);
       lds_barrier();
       uint32_t st;
       const uint32_t tot = digit_starts(nd, s_wh, s_tmp, &st);
@@ -962,7 +1050,7 @@ inline int rb_class(uint32_t bits) { return bits <= 6 ? 6 : (bits <= 8 ? 8 : 9);
 
 }  // namespace
 
-uint32_t msd_cap(bool) { return kCTile; }
+uint32_t msd_cap(bool) { return kMsdTile; }
 
 #define M_RB_SWITCH(bits, F) \
   switch (rb_class(bits)) {  \

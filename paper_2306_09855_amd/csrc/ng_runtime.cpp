@@ -997,9 +997,10 @@ bool msd_geometry(uint64_t N, uint32_t nn, int dbits, int log2B, uint32_t sort_r
   const uint64_t ntiles = (N + tile - 1) / tile;
   p.tpr = (uint32_t)std::max<uint64_t>(1, (ntiles + sort_ranges - 1) / std::max<uint32_t>(sort_ranges, 1));
   p.ranges_a = (uint32_t)((ntiles + p.tpr - 1) / p.tpr);
-  // every bucket's ranges start at its first record: at most one partial
-  // range per bucket beyond the full ones
-  p.max_ranges_b = b2 ? (uint32_t)((N + tile * p.tpr - 1) / (tile * p.tpr) + (1ull << b1)) : 0u;
+  p.tile_b = p.narrow_a ? ng::kMsdTileN : ng::kMsdTile;
+  // each bucket asks for ceil(its tiles x ranges_b / all tiles) ranges
+  p.ranges_b = std::max<uint32_t>(sort_ranges, 1);
+  p.max_ranges_b = b2 ? (uint32_t)(p.ranges_b + (1ull << b1)) : 0u;
   // pass C: workgroups of about eight LDS loads of records each
   const uint64_t piece = ng::msd_cap(b2 ? p.narrow_b : p.narrow_a);
   p.wgs_c = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(1, (N + 8 * piece - 1) / (8 * piece)), 1u << 20);
@@ -1053,6 +1054,7 @@ int calibrate_msd(CalSeg& g, const ng::MsdPlan& plan) {
       (uint32_t*)as.get(4 * std::max({ng::scan_tmp_words(na), ng::scan_tmp_words(nbc), ng::scan_tmp_words(nsb)}));
   p.bstart = (uint32_t*)as.get(4 * (nb + 1));
   p.rangeb0 = (uint32_t*)as.get(4 * (nb + 1));
+  p.tprb = (uint32_t*)as.get(4 * nb);
   p.sbstart = (uint32_t*)as.get(4 * (nsb + 1));
   p.gcount = (uint32_t*)as.get(4 * (nsb + 1));
   p.gmask = (uint32_t*)as.get(4 * nsb * p.mask_words);
