@@ -474,6 +474,27 @@ __global__ __launch_bounds__(kMThreads) void k_msd_scatter_b(MsdPlan p) {
 // ---------------------------------------------------------------------------
 // Digit counts of the ranges of passes A and B.
 // ---------------------------------------------------------------------------
+// Adds four digits of a lane to an LDS histogram.  When every active lane of
+// the wave holds one digit four times (sorted input: the same address for
+// the whole wave would serialize the adds) the wave adds once; a lane whose
+// four digits agree adds once.
+__device__ __forceinline__ void hist_add4(uint32_t* hist, uint32_t d0, uint32_t d1, uint32_t d2, uint32_t d3) {
+  const bool same = d0 == d1 && d0 == d2 && d0 == d3;
+  const uint32_t first = __builtin_amdgcn_readfirstlane(d0);
+  const uint64_t act = __ballot(1);
+  const uint64_t agree = __ballot(same && d0 == first);
+  if (agree == act) {
+    if ((threadIdx.x & 63u) == (uint32_t)__builtin_ctzll(act)) atomicAdd(&hist[first], 4u * (uint32_t)__popcll(act));
+  } else if (same) {
+    atomicAdd(&hist[d0], 4u);
+  } else {
+    atomicAdd(&hist[d0], 1u);
+    atomicAdd(&hist[d1], 1u);
+    atomicAdd(&hist[d2], 1u);
+    atomicAdd(&hist[d3], 1u);
+  }
+}
+
 // Pass A: D1 of every creation-order record (the delays are read only when
 // D1 reaches into the delay bits).
 template <bool NEED_DELAY>
@@ -510,8 +531,8 @@ __global__ __launch_bounds__(kMThreads) void k_msd_count_a(MsdPlan p) {
         key[1] = (s4.y << p.dbits) | dl[1];
         key[2] = (s4.z << p.dbits) | dl[2];
         key[3] = (s4.w << p.dbits) | dl[3];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) atomicAdd(&hist[(key[e] >> shift) & (nd - 1)], 1u);
+        hist_add4(hist, (key[0] >> shift) & (nd - 1), (key[1] >> shift) & (nd - 1), (key[2] >> shift) & (nd - 1),
+                  (key[3] >> shift) & (nd - 1));
       } else {
         for (uint32_t e = 0; 4 * q + e < cnt; ++e) {
           const uint32_t s = G(reinterpret_cast<const uint32_t*>(blk))[o + e];
@@ -556,20 +577,15 @@ __global__ __launch_bounds__(kMThreads) void k_msd_count_b(MsdPlan p) {
     u32x4 x[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) x[u] = v[q + u * kMThreads];
+    const uint32_t m = nd - 1;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      add(x[u].x);
-      add(x[u].y);
-      add(x[u].z);
-      add(x[u].w);
-    }
+    for (int u = 0; u < 4; ++u)
+      hist_add4(hist, (x[u].x >> shift) & m, (x[u].y >> shift) & m, (x[u].z >> shift) & m, (x[u].w >> shift) & m);
   }
   for (; q < nq; q += kMThreads) {
     const u32x4 x = v[q];
-    add(x.x);
-    add(x.y);
-    add(x.z);
-    add(x.w);
+    const uint32_t m = nd - 1;
+    hist_add4(hist, (x.x >> shift) & m, (x.y >> shift) & m, (x.z >> shift) & m, (x.w >> shift) & m);
   }
   __syncthreads();
   const uint64_t cb = ((uint64_t)s_rb0[b] << p.b2) + rl;
