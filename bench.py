@@ -667,7 +667,8 @@ def main() -> int:
                          "graph: the batched build captured once and replayed")
     ap.add_argument("--calibration", default="radix", choices=["radix", "lsd", "msd"],
                     help="radix: the default form choice; lsd / msd: force one form")
-    ap.add_argument("--tune", action="store_true", help="pick the sort schedule with the autotuner first")
+    ap.add_argument("--tune", type=int, default=1,
+                    help="pick the kernel schedule with the autotuner first (untimed); 0 keeps the default")
     ap.add_argument("--radix-bits", type=int, default=9, help="widest digit of the LSD form (fewest passes)")
     ap.add_argument("--sort-ranges", type=int, default=1024, help="static ranges (workgroups) of each scatter pass")
     ap.add_argument("--block-size", type=int, default=1 << 24)
@@ -725,13 +726,17 @@ def main() -> int:
         f"arena {arena / 2**30:.1f} GiB, form {args.form}")
     side = torch.cuda.Stream()  # graphs cannot capture the null stream
     net = Network(wl.seed, wl.h, args.block_size, arena, stream=side.cuda_stream)
-    net.set_calibration(args.calibration)
-    if args.tune:
-        from paper_2306_09855_amd.autotune import tune
-        args.radix_bits, args.sort_ranges = tune(net, wl)
-        log(f"autotuner: radix_bits={args.radix_bits} sort_ranges={args.sort_ranges}")
-    net.tune(args.radix_bits, args.sort_ranges)
     ctx = net.ctx
+    schedule = {"calibration": args.calibration, "radix_bits": args.radix_bits, "sort_ranges": args.sort_ranges,
+                "msd_tile": 16384, "gen_synapses_per_lane": 4}
+    schedule_source = "default"
+    if args.tune and args.calibration == "radix":
+        from paper_2306_09855_amd.autotune import tune
+        t0 = time.perf_counter()
+        schedule, cached = tune(net, wl, batched=args.form != "plain", use_cache=False)
+        schedule_source = f"autotuner ({time.perf_counter() - t0:.1f} s, untimed)"
+        log(f"autotuner: {schedule}")
+    ng.ng_set_schedule(ctx, schedule)
     calls = [ng.call_args(c) for c in wl.calls]
     batch = [list(x) for x in zip(*calls)]
 
@@ -798,11 +803,12 @@ def main() -> int:
     ms_per_step = 1e3 * wall / args.steps
     value = args.steps * n_syn / wall
 
-    plan = ng.ng_calibration_plan(n_syn, wl.n_nodes, wl.max_delay, args.sort_ranges)
-    msd = plan["msd"] == 2 and args.calibration != "lsd" or (args.calibration == "msd" and plan["msd"] >= 1)
+    plan = ng.ng_calibration_plan(n_syn, wl.n_nodes, wl.max_delay, schedule["sort_ranges"])
+    cal = schedule["calibration"]
+    msd = plan["msd"] == 2 and cal == "radix" or (cal == "msd" and plan["msd"] >= 1)
     dbits = int(wl.max_delay).bit_length()
     sbits = int(wl.n_nodes - 1).bit_length()
-    lsd_passes = max(1, -(-(sbits + dbits) // args.radix_bits))
+    lsd_passes = max(1, -(-(sbits + dbits) // schedule["radix_bits"]))
     per_kernel = {}
     for name, (launches, total_ms) in kernels.items():
         ms = total_ms / args.steps
@@ -833,7 +839,7 @@ def main() -> int:
         calib = {"form": "msd", "digits": [plan["b1"], plan["b2"], plan["b3"]],
                  "packed_after_a": plan["narrow_a"], "packed_after_b": plan["narrow_b"]}
     else:
-        calib = {"form": "lsd", "radix_bits": args.radix_bits, "passes": lsd_passes}
+        calib = {"form": "lsd", "radix_bits": schedule["radix_bits"], "passes": lsd_passes}
     result = {
         "metric": METRIC, "value": value, "unit": "synapses/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
@@ -845,7 +851,8 @@ def main() -> int:
                    "rule": "fixed_total_number" if wl.name == "microcircuit" else "mixed",
                    "delays": f"uniform_int 1..{wl.max_delay}",
                    "weights": "normal fp32", "form": args.form, "seeds": list(SEEDS),
-                   "block_size": args.block_size, "sort_ranges": args.sort_ranges, "calibration": calib},
+                   "block_size": args.block_size, "calibration": calib,
+                   "schedule": schedule, "schedule_source": schedule_source},
         "device_ms_per_step": round(dev_ms / args.steps, 4),
         "step_ms_over_seeds": {"mean": round(float(step_ms.mean()), 4), "std": round(float(step_ms.std(ddof=1)), 4)
                                if args.steps > 1 else 0.0, "steps": args.steps,

@@ -301,6 +301,32 @@ int ng_copy_group_index(ng_ctx* ctx, uint32_t* group_ptr, uint32_t* group_start)
  * speed does. */
 int ng_set_tuning(ng_ctx* ctx, int radix_bits, uint32_t sort_ranges);
 
+/* The whole kernel schedule of a context, for an autotuner (results never
+ * depend on it; speed does):
+ *   calibration            NG_CALIB_RADIX (default), NG_CALIB_RADIX_LSD,
+ *                          NG_CALIB_RADIX_MSD or NG_CALIB_COPASS (as
+ *                          ng_set_calibration);
+ *   radix_bits             widest digit of the LSD form, 4..9 (default 9);
+ *   sort_ranges            static ranges of each scatter pass, 1..2^20
+ *                          (default 1024; as ng_set_tuning);
+ *   msd_tile               records per tile of the most-significant-digit
+ *                          form's second scatter when its records are packed:
+ *                          10240 or 16384 (default);
+ *   gen_synapses_per_lane  synapses each generation lane makes in groups of
+ *                          four: 4 (default), 8, 16 or 32 (fewer
+ *                          workgroups per launch).
+ * ng_set_schedule: NG_ERR_INVALID_ARG (nothing changed) for a value outside
+ * these; ng_get_schedule fills the current values. */
+typedef struct {
+  int32_t calibration;
+  int32_t radix_bits;
+  uint32_t sort_ranges;
+  uint32_t msd_tile;
+  uint32_t gen_synapses_per_lane;
+} ng_schedule;
+int ng_set_schedule(ng_ctx* ctx, const ng_schedule* schedule);
+int ng_get_schedule(ng_ctx* ctx, ng_schedule* schedule);
+
 /* Spike buffers and delivery (Sec. 2.3), the consumer of the calibrated
  * connections.  ng_spikes_init (after calibration; synchronizes) gives every
  * node a queue of spikes -- (time index, connection-group index,

@@ -57,12 +57,14 @@ struct GenDesc {
 // --- generation -----------------------------------------------------------
 // d_key: the Philox key (seed low word, seed high word) in device memory.
 hipError_t launch_generate(const GenDesc& d, const uint32_t* d_key, char* const* d_blocks, int log2B,
-                           hipStream_t s);
+                           hipStream_t s,
+                           uint32_t quads_per_lane = 1);
 // All calls of a batch in one launch; d_descs[n_calls] device array sorted by
 // group0, total_groups = sum of ceil(n_new / 4).  Each descriptor names its
 // own block table and key, so one launch may serve several contexts.
 hipError_t launch_generate_batch(const GenDesc* d_descs, uint32_t n_calls, uint64_t total_groups,
-                                 int log2B, hipStream_t s);
+                                 int log2B, hipStream_t s,
+                                 uint32_t quads_per_lane = 1);
 
 // --- calibration ----------------------------------------------------------
 // Input and output of one digit pass of one segment.

@@ -1516,15 +1516,19 @@ static void gen_launch(const GenDesc& d, const uint32_t* key, char* const* block
     hipLaunchKernelGGL((k_generate<RULE, true>), grid, dim3(kGenThreads), 0, s, d, key, blocks, log2B);
 }
 
-static uint32_t gen_grid(uint64_t groups) {
-  const uint64_t need = (groups + kGenThreads - 1) / kGenThreads;
+// Workgroups of a generation launch: each lane makes about quads_per_lane
+// groups of four synapses (the kernels loop over their groups), at most
+// 16,384 workgroups.
+static uint32_t gen_grid(uint64_t groups, uint32_t quads_per_lane) {
+  const uint64_t per_wg = (uint64_t)kGenThreads * (quads_per_lane ? quads_per_lane : 1);
+  const uint64_t need = (groups + per_wg - 1) / per_wg;
   return (uint32_t)(need < 16384 ? (need ? need : 1) : 16384);
 }
 
 hipError_t launch_generate(const GenDesc& d, const uint32_t* d_key, char* const* d_blocks, int log2B,
-                           hipStream_t s) {
+                           hipStream_t s, uint32_t quads_per_lane) {
   if (d.n_new == 0) return hipSuccess;
-  const dim3 grid(gen_grid(((uint64_t)d.n_new + 3) / 4));
+  const dim3 grid(gen_grid(((uint64_t)d.n_new + 3) / 4, quads_per_lane));
   switch (d.rule) {
     case R_ONE_TO_ONE: gen_launch<R_ONE_TO_ONE>(d, d_key, d_blocks, log2B, grid, s); break;
     case R_ALL_TO_ALL: gen_launch<R_ALL_TO_ALL>(d, d_key, d_blocks, log2B, grid, s); break;
@@ -1540,9 +1544,9 @@ hipError_t launch_generate(const GenDesc& d, const uint32_t* d_key, char* const*
 }
 
 hipError_t launch_generate_batch(const GenDesc* d_descs, uint32_t n_calls, uint64_t total_groups,
-                                 int log2B, hipStream_t s) {
+                                 int log2B, hipStream_t s, uint32_t quads_per_lane) {
   if (n_calls == 0 || total_groups == 0) return hipSuccess;
-  const dim3 grid(gen_grid(total_groups));
+  const dim3 grid(gen_grid(total_groups, quads_per_lane));
   hipLaunchKernelGGL(k_generate_batch, grid, dim3(kGenThreads), 0, s, d_descs, n_calls, total_groups, log2B);
   return hipGetLastError();
 }

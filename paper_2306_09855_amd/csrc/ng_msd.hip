@@ -434,9 +434,8 @@ __device__ __forceinline__ uint32_t bucket_of_range(const uint32_t* s_rb0, uint3
 }
 
 // Pass B: range r of a bucket by D2.
-template <int RB, int IN, bool OUT_NARROW>
-__global__ __launch_bounds__(kMThreads) void k_msd_scatter_b(MsdPlan p) {
-  constexpr int ITEMS = IN == IN_NARROW ? kMItemsN : kMItems;  // the tile is p.tile_b records
+template <int RB, int IN, bool OUT_NARROW, int ITEMS>
+__global__ __launch_bounds__(kMThreads) void k_msd_scatter_b(MsdPlan p) {  // the tile is p.tile_b = ITEMS x 512
   M_SCATTER_LDS(ITEMS * kMThreads)
   __shared__ uint32_t s_rb0[kMNB + 1];
   const uint32_t nb = 1u << p.b1, nd = 1u << p.b2;
@@ -1106,10 +1105,13 @@ hipError_t launch_msd_count_b(const MsdPlan& p, hipStream_t s) {
 
 hipError_t launch_msd_scatter_b(const MsdPlan& p, hipStream_t s) {
   const dim3 grid(8 * ((p.max_ranges_b + 7) / 8));
-#define F(RB)                                                                                                \
-  if (p.narrow_a) hipLaunchKernelGGL((k_msd_scatter_b<RB, IN_NARROW, true>), grid, dim3(kMThreads), 0, s, p); \
-  else if (p.narrow_b) hipLaunchKernelGGL((k_msd_scatter_b<RB, IN_WIDE, true>), grid, dim3(kMThreads), 0, s, p); \
-  else hipLaunchKernelGGL((k_msd_scatter_b<RB, IN_WIDE, false>), grid, dim3(kMThreads), 0, s, p);
+  if (!(p.tile_b == kMsdTile || (p.narrow_a && p.tile_b == kMsdTileN))) return hipErrorInvalidValue;
+#define F(RB)                                                                                                       \
+  if (p.narrow_a && p.tile_b == kMsdTileN)                                                                           \
+    hipLaunchKernelGGL((k_msd_scatter_b<RB, IN_NARROW, true, kMItemsN>), grid, dim3(kMThreads), 0, s, p);            \
+  else if (p.narrow_a) hipLaunchKernelGGL((k_msd_scatter_b<RB, IN_NARROW, true, kMItems>), grid, dim3(kMThreads), 0, s, p); \
+  else if (p.narrow_b) hipLaunchKernelGGL((k_msd_scatter_b<RB, IN_WIDE, true, kMItems>), grid, dim3(kMThreads), 0, s, p);   \
+  else hipLaunchKernelGGL((k_msd_scatter_b<RB, IN_WIDE, false, kMItems>), grid, dim3(kMThreads), 0, s, p);
   M_RB_SWITCH(p.b2, F)
 #undef F
   return hipGetLastError();

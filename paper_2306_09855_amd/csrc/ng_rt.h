@@ -208,7 +208,9 @@ struct ng_ctx {
 
   int radix_bits = 9;  // widest digit: the fewest passes
   uint32_t sort_ranges = 1024;  // static ranges (= workgroups) of each sort pass
-  int calib_mode = 0;           // NG_CALIB_RADIX or NG_CALIB_COPASS
+  int calib_mode = 0;           // NG_CALIB_RADIX, _COPASS, _RADIX_LSD or _RADIX_MSD
+  uint32_t msd_tile = 0;        // records per tile of the MSD second scatter over packed records (0: default)
+  uint32_t gen_quads = 1;       // groups of four synapses per generation lane
   int sticky = NG_OK;
   std::string sticky_msg;
 

@@ -954,7 +954,8 @@ int calibrate_copass(ng_ctx* c) {
 // they fit one digit, else are split between A and B so that the occupied
 // values of D1 and the values of D2 balance (both set the run lengths of
 // their scatter).  False if the plan does not apply (the LSD sort runs).
-bool msd_geometry(uint64_t N, uint32_t nn, int dbits, int log2B, uint32_t sort_ranges, ng::MsdPlan& p) {
+bool msd_geometry(uint64_t N, uint32_t nn, int dbits, int log2B, uint32_t sort_ranges, ng::MsdPlan& p,
+                  uint32_t msd_tile = 0) {
   const int sbits = bitwidth(nn > 0 ? nn - 1 : 0);
   const int K = sbits + dbits;
   if (N == 0 || N > 0xFFFFFFFFull || K < 2 || K > (int)ng::kMsdMaxKeyBits) return false;
@@ -997,7 +998,7 @@ bool msd_geometry(uint64_t N, uint32_t nn, int dbits, int log2B, uint32_t sort_r
   const uint64_t ntiles = (N + tile - 1) / tile;
   p.tpr = (uint32_t)std::max<uint64_t>(1, (ntiles + sort_ranges - 1) / std::max<uint32_t>(sort_ranges, 1));
   p.ranges_a = (uint32_t)((ntiles + p.tpr - 1) / p.tpr);
-  p.tile_b = p.narrow_a ? ng::kMsdTileN : ng::kMsdTile;
+  p.tile_b = p.narrow_a && msd_tile != ng::kMsdTile ? ng::kMsdTileN : ng::kMsdTile;
   // each bucket asks for ceil(its tiles x ranges_b / all tiles) ranges
   p.ranges_b = std::max<uint32_t>(sort_ranges, 1);
   p.max_ranges_b = b2 ? (uint32_t)(p.ranges_b + (1ull << b1)) : 0u;
@@ -1157,7 +1158,7 @@ int calibrate_many(ng_ctx* const* cs, uint32_t n, const Uploader* upload, Scratc
       (segs[0].c->calib_mode == NG_CALIB_RADIX || segs[0].c->calib_mode == NG_CALIB_RADIX_MSD)) {
     ng::MsdPlan mp;
     const CalSeg& g = segs[0];
-    if (msd_geometry(g.N, g.nn, g.dbits, g.c->log2B, g.c->sort_ranges, mp) &&
+    if (msd_geometry(g.N, g.nn, g.dbits, g.c->log2B, g.c->sort_ranges, mp, g.c->msd_tile) &&
         (g.c->calib_mode == NG_CALIB_RADIX_MSD || msd_pays(mp)))
       return calibrate_msd(segs[0], mp);
   }
@@ -1579,7 +1580,7 @@ int ng_connect(ng_ctx* c, ng_range src, ng_range tgt, const ng_conn_spec* conn, 
   uint64_t n = 0;
   if (int rc = connect_prepare(c, src, tgt, conn, syn, &d, &n)) return rc;
   if (int rc = sync_table(c)) return rc;
-  if (n) NG_LAUNCH(c, "generate", ng::launch_generate(d, key_ptr(c), c->d_tab[c->cur], c->log2B, c->stream));
+  if (n) NG_LAUNCH(c, "generate", ng::launch_generate(d, key_ptr(c), c->d_tab[c->cur], c->log2B, c->stream, c->gen_quads));
   if (out_cid) *out_cid = d.cid;
   if (out_first) *out_first = d.pos0;
   if (out_n) *out_n = n;
@@ -1656,7 +1657,7 @@ int ng_connect_groups(ng_ctx* c, ng_group src, ng_group tgt, const ng_conn_spec*
   d.tgt_idx = tgt.idx;
   d.w_arr = weights;
   d.d_ms_arr = delays_ms;
-  if (n) NG_LAUNCH(c, "generate", ng::launch_generate(d, key_ptr(c), c->d_tab[c->cur], c->log2B, c->stream));
+  if (n) NG_LAUNCH(c, "generate", ng::launch_generate(d, key_ptr(c), c->d_tab[c->cur], c->log2B, c->stream, c->gen_quads));
   if (out_cid) *out_cid = d.cid;
   if (out_first) *out_first = d.pos0;
   if (out_n) *out_n = n;
@@ -1719,7 +1720,7 @@ int ng_connect_batch(ng_ctx* c, uint32_t n_calls, const ng_range* src, const ng_
   if (!descs.empty()) {
     NG_LAUNCH(c, "generate_batch",
               ng::launch_generate_batch((const ng::GenDesc*)d_descs, (uint32_t)descs.size(), groups,
-                                        c->log2B, c->stream));
+                                        c->log2B, c->stream, c->gen_quads));
     ctx_free(c, d_descs, desc_bytes);  // stream-ordered reuse is safe
     if (!c->capturing) ctx_flush_frees(c);
     c->calibrated = false;
@@ -1737,6 +1738,37 @@ int ng_set_tuning(ng_ctx* c, int radix_bits, uint32_t sort_ranges) {
   if (sort_ranges < 1 || sort_ranges > (1u << 20)) return fail(NG_ERR_INVALID_ARG, "sort_ranges in [1, 2^20]");
   c->radix_bits = radix_bits;
   c->sort_ranges = sort_ranges;
+  return NG_OK;
+}
+
+int ng_set_schedule(ng_ctx* c, const ng_schedule* sc) {
+  if (!c || !sc) return fail(NG_ERR_INVALID_ARG, "null context or schedule");
+  const int cal = sc->calibration;
+  if (cal != NG_CALIB_RADIX && cal != NG_CALIB_COPASS && cal != NG_CALIB_RADIX_LSD && cal != NG_CALIB_RADIX_MSD)
+    return fail(NG_ERR_INVALID_ARG, "unknown calibration algorithm %d", cal);
+  if (sc->radix_bits < 4 || sc->radix_bits > ng::sort_max_radix_bits())
+    return fail(NG_ERR_INVALID_ARG, "radix_bits must be in [4, %d]", ng::sort_max_radix_bits());
+  if (sc->sort_ranges < 1 || sc->sort_ranges > (1u << 20)) return fail(NG_ERR_INVALID_ARG, "sort_ranges in [1, 2^20]");
+  if (sc->msd_tile != ng::kMsdTile && sc->msd_tile != ng::kMsdTileN)
+    return fail(NG_ERR_INVALID_ARG, "msd_tile must be %u or %u", ng::kMsdTile, ng::kMsdTileN);
+  const uint32_t spl = sc->gen_synapses_per_lane;
+  if (spl != 4 && spl != 8 && spl != 16 && spl != 32)
+    return fail(NG_ERR_INVALID_ARG, "gen_synapses_per_lane must be 4, 8, 16 or 32");
+  c->calib_mode = cal;
+  c->radix_bits = sc->radix_bits;
+  c->sort_ranges = sc->sort_ranges;
+  c->msd_tile = sc->msd_tile;
+  c->gen_quads = spl / 4;
+  return NG_OK;
+}
+
+int ng_get_schedule(ng_ctx* c, ng_schedule* sc) {
+  if (!c || !sc) return fail(NG_ERR_INVALID_ARG, "null context or schedule");
+  sc->calibration = c->calib_mode;
+  sc->radix_bits = c->radix_bits;
+  sc->sort_ranges = c->sort_ranges;
+  sc->msd_tile = c->msd_tile ? c->msd_tile : ng::kMsdTileN;
+  sc->gen_synapses_per_lane = 4 * c->gen_quads;
   return NG_OK;
 }
 

@@ -65,6 +65,11 @@ class ng_group(ctypes.Structure):
     _fields_ = [("first", ctypes.c_uint32), ("n", ctypes.c_uint32), ("idx", ctypes.c_void_p)]
 
 
+class ng_schedule(ctypes.Structure):
+    _fields_ = [("calibration", ctypes.c_int32), ("radix_bits", ctypes.c_int32), ("sort_ranges", ctypes.c_uint32),
+                ("msd_tile", ctypes.c_uint32), ("gen_synapses_per_lane", ctypes.c_uint32)]
+
+
 class ng_config(ctypes.Structure):
     _fields_ = [("block_size", ctypes.c_uint64), ("seed", ctypes.c_uint64),
                 ("h_ms", ctypes.c_float), ("reserved", ctypes.c_int32)]
@@ -132,6 +137,8 @@ def lib():
             "ng_copy_group_index": ([vp, vp, vp], ctypes.c_int),
             "ng_set_tuning": ([vp, ctypes.c_int, u32], ctypes.c_int),
             "ng_set_calibration": ([vp, ctypes.c_int], ctypes.c_int),
+            "ng_set_schedule": ([vp, P(ng_schedule)], ctypes.c_int),
+            "ng_get_schedule": ([vp, P(ng_schedule)], ctypes.c_int),
             "ng_spikes_init": ([vp], ctypes.c_int),
             "ng_spikes_step": ([vp, vp, vp, u32, vp], ctypes.c_int),
             "ng_memory_stats": ([vp, P(u64), P(u64), P(u64)], ctypes.c_int),
@@ -379,6 +386,26 @@ CALIBRATIONS = {"radix": NG_CALIB_RADIX, "copass": NG_CALIB_COPASS, "lsd": NG_CA
 def ng_set_calibration(ctx, algorithm) -> None:
     """Calibration algorithm: "radix" (default) or "copass" (in-place block sort)."""
     _check(lib().ng_set_calibration(ctx, CALIBRATIONS.get(algorithm, algorithm)))
+
+
+SCHEDULE_KEYS = ("calibration", "radix_bits", "sort_ranges", "msd_tile", "gen_synapses_per_lane")
+
+
+def ng_set_schedule(ctx, schedule: dict) -> None:
+    """schedule: the fields of ng_schedule; calibration may be a name of CALIBRATIONS."""
+    cal = schedule["calibration"]
+    sc = ng_schedule(CALIBRATIONS[cal] if isinstance(cal, str) else int(cal), int(schedule["radix_bits"]),
+                     int(schedule["sort_ranges"]), int(schedule["msd_tile"]), int(schedule["gen_synapses_per_lane"]))
+    _check(lib().ng_set_schedule(ctx, ctypes.byref(sc)))
+
+
+def ng_get_schedule(ctx) -> dict:
+    sc = ng_schedule()
+    _check(lib().ng_get_schedule(ctx, ctypes.byref(sc)))
+    names = {v: k for k, v in CALIBRATIONS.items()}
+    out = {k: int(getattr(sc, k)) for k in SCHEDULE_KEYS}
+    out["calibration"] = names.get(out["calibration"], out["calibration"])
+    return out
 
 
 def ng_memory_stats(ctx):

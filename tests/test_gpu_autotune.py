@@ -1,0 +1,76 @@
+"""The autotuner (batched and plain forms): it times the schedule space of
+ng_schedule on the device, caches its choice per device and workload shape,
+reuses the cached choice, and the chosen schedule builds exactly the arrays
+of the default schedule (the schedule changes speed only)."""
+import json
+
+import numpy as np
+import pytest
+
+from paper_2306_09855_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2306_09855_amd import autotune, ng  # noqa: E402
+from paper_2306_09855_amd.network import Network, arena_bytes_for  # noqa: E402
+
+
+def _build(wl, schedule, batched):
+    with Network(wl.seed, wl.h, 0, arena_bytes_for(wl.n_syn, wl.n_nodes, wl.max_delay)) as net:
+        ng.ng_set_schedule(net.ctx, schedule)
+        assert ng.ng_get_schedule(net.ctx)["gen_synapses_per_lane"] == schedule["gen_synapses_per_lane"]
+        net.build(wl, batched=batched)
+        out = net.fetch()
+        gp, gs = net.group_index()
+    return out, gp, gs
+
+
+@pytest.mark.parametrize("batched", [False, True])
+def test_tune_caches_reuses_and_keeps_results(tmp_path, monkeypatch, batched):
+    cache = tmp_path / "ng_autotune.json"
+    monkeypatch.setenv("NG_AUTOTUNE_CACHE", str(cache))
+    wl = W.microcircuit(scale=0.2)  # 1.2e7 synapses: the MSD and LSD forms both apply
+    with Network(wl.seed, wl.h, 0, arena_bytes_for(wl.n_syn, wl.n_nodes, wl.max_delay)) as net:
+        before = ng.ng_get_schedule(net.ctx)
+        choice, cached = autotune.tune(net, wl, batched=batched)
+        assert not cached and set(choice) == set(ng.SCHEDULE_KEYS)
+        assert ng.ng_get_schedule(net.ctx) == before  # the tuner leaves the schedule as it was
+        data = json.loads(cache.read_text())
+        (key, entry), = data.items()
+        assert entry["choice"] == choice
+        # every candidate of the space was timed
+        assert len(entry["calibrate_ms"]) == len(autotune.calibration_candidates(wl))
+        assert set(entry["generate_ms"]) == {str(s) for s in autotune.GEN_SPL}
+        again, cached2 = autotune.tune(net, wl, batched=batched)
+        assert cached2 and again == choice
+    a = _build(wl, autotune.DEFAULT, batched)
+    b = _build(wl, choice, batched)
+    for k in ("src", "tgt", "delay"):
+        assert np.array_equal(a[0][k], b[0][k]), k
+    assert np.array_equal(a[0]["w"].view(np.uint32), b[0]["w"].view(np.uint32))
+    assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+
+
+@pytest.mark.parametrize("spl,tile,cal", [(8, 10240, "msd"), (16, 16384, "lsd"), (32, 16384, "copass")])
+def test_every_schedule_value_gives_the_default_arrays(spl, tile, cal):
+    wl = W.microcircuit(scale=0.2)
+    ref = _build(wl, autotune.DEFAULT, False)
+    got = _build(wl, {**autotune.DEFAULT, "gen_synapses_per_lane": spl, "msd_tile": tile, "calibration": cal}, False)
+    for k in ("src", "tgt", "delay"):
+        assert np.array_equal(ref[0][k], got[0][k]), k
+    assert np.array_equal(ref[0]["w"].view(np.uint32), got[0]["w"].view(np.uint32))
+    assert np.array_equal(ref[1], got[1]) and np.array_equal(ref[2], got[2])
+
+
+def test_invalid_schedule_is_refused():
+    with Network(1, 0.1, 0, 64 << 20) as net:
+        before = ng.ng_get_schedule(net.ctx)
+        for bad in ({"gen_synapses_per_lane": 12}, {"msd_tile": 4096}, {"radix_bits": 10}, {"sort_ranges": 0}):
+            with pytest.raises(ng.NGError) as e:
+                ng.ng_set_schedule(net.ctx, {**autotune.DEFAULT, **bad})
+            assert e.value.status == ng.NG_ERR_INVALID_ARG
+        assert ng.ng_get_schedule(net.ctx) == before
