@@ -308,7 +308,9 @@ int ng_set_tuning(ng_ctx* ctx, int radix_bits, uint32_t sort_ranges);
  *                          ng_set_calibration);
  *   radix_bits             widest digit of the LSD form, 4..9 (default 9);
  *   sort_ranges            static ranges of each scatter pass, 1..2^20
- *                          (default 1024; as ng_set_tuning);
+ *                          (default 1024; as ng_set_tuning; the second
+ *                          scatter of the most-significant-digit form takes
+ *                          twice as many);
  *   msd_tile               records per tile of the most-significant-digit
  *                          form's second scatter when its records are packed:
  *                          10240 or 16384 (default);
