@@ -357,10 +357,10 @@ int ng_spikes_step(ng_ctx* ctx, const uint32_t* nodes, const uint32_t* mult, uin
  * are the same with either (stable order by (source, delay), Sec. 2.2).
  *   NG_CALIB_RADIX (default): stable radix sort of all connections into a
  *     second block set, in the most-significant-digit form (below) when one
- *     context is calibrated, its keys (source bits + delay bits) fit in 27
- *     bits, its connections average at least 256 per sub-bucket and at
- *     least 10 per possible key (n_nodes x 2^delay bits), else in the LSD
- *     form.
+ *     context with at least 2^25 connections is calibrated, its keys
+ *     (source bits + delay bits) fit in 27 bits, its connections average at
+ *     least 256 per sub-bucket and at least 10 per possible key (n_nodes x
+ *     2^delay bits), else in the LSD form.
  *   NG_CALIB_RADIX_MSD: the most-significant-digit form whenever one context
  *     with keys of at most 27 bits is calibrated (else LSD): a scatter by
  *     the top digit, a scatter of each bucket by the second digit, and runs
@@ -516,8 +516,8 @@ uint64_t ng_blocks_needed(uint64_t n_conns, uint64_t n_new, uint64_t block_size,
  * max_delay steps, with sort_ranges static ranges per scatter pass (the
  * ng_set_tuning value, 1024 by default).  out[0] = 2 when the default
  * calibration takes the most-significant-digit form, 1 when only
- * NG_CALIB_RADIX_MSD takes it (too few connections per sub-bucket or per
- * key), 0 when
+ * NG_CALIB_RADIX_MSD takes it (fewer than 2^25 connections, too few per
+ * sub-bucket or per key), 0 when
  * it does not apply (keys wider than 27 bits, n_conns = 0 or >= 2^32; the
  * rest is then zero); out[1..3] = the widths b1, b2, b3
  * of the digits from the top (b2 = 0: no second scatter); out[4], out[5] =

@@ -1030,17 +1030,28 @@ __global__ __launch_bounds__(kMThreads) void k_msd_big_c(MsdPlan p) {
   }
 }
 
-// group_start from the scanned group counts and the local group starts;
+// group_start from the scanned group counts and the local group starts: one
+// wave per sub-bucket copies its groups (up to 2^b3 of them), four
+// sub-buckets per workgroup.  Workgroups past the sub-buckets' build
 // group_ptr (Eq. (14)): the groups of all sources below i are the distinct
 // keys below i << dbits, i.e. the groups of the sub-buckets before the one
 // holding that key plus its present D3 values below the key's.
 __global__ __launch_bounds__(256) void k_msd_groups(MsdPlan p) {
   const uint32_t nsb = 1u << (p.b1 + p.b2);
-  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
-  if (i < nsb) {
-    const uint32_t g0 = p.gcount[i], ng = p.gcount[i + 1] - g0, start = p.sbstart[i];
-    for (uint32_t k = 0; k < ng; ++k) p.group_start[g0 + k] = p.gslot[start + k];
+  const uint32_t copy_blocks = (nsb + 3) / 4;
+  if (blockIdx.x < copy_blocks) {
+    const uint32_t sb = blockIdx.x * 4u + (threadIdx.x >> 6), lane = threadIdx.x & 63u;
+    if (sb < nsb) {
+      const uint32_t g0 = p.gcount[sb], ng = p.gcount[sb + 1] - g0, start = p.sbstart[sb];
+      for (uint32_t k = lane; k < ng; k += 64) p.group_start[g0 + k] = p.gslot[start + k];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      p.group_start[p.gcount[nsb]] = p.n;
+      *p.n_groups = p.gcount[nsb];
+    }
+    return;
   }
+  const uint32_t i = (blockIdx.x - copy_blocks) * 256u + threadIdx.x;
   if (i <= p.n_nodes) {
     uint32_t v = p.gcount[nsb];
     if (i < p.n_nodes) {
@@ -1052,10 +1063,6 @@ __global__ __launch_bounds__(256) void k_msd_groups(MsdPlan p) {
       if (local & 31u) v += (uint32_t)__popc(gm[local >> 5] & ((1u << (local & 31u)) - 1u));
     }
     p.group_ptr[i] = v;
-  }
-  if (i == 0) {
-    p.group_start[p.gcount[nsb]] = p.n;
-    *p.n_groups = p.gcount[nsb];
   }
 }
 
@@ -1156,8 +1163,8 @@ hipError_t launch_msd_big_c(const MsdPlan& p, hipStream_t s) {
 
 hipError_t launch_msd_groups(const MsdPlan& p, hipStream_t s) {
   const uint32_t nsb = 1u << (p.b1 + p.b2);
-  const uint32_t m = std::max(nsb, p.n_nodes + 1);
-  hipLaunchKernelGGL(k_msd_groups, dim3((m + 255) / 256), dim3(256), 0, s, p);
+  const uint32_t blocks = (nsb + 3) / 4 + (p.n_nodes + 1 + 255) / 256;
+  hipLaunchKernelGGL(k_msd_groups, dim3(blocks), dim3(256), 0, s, p);
   return hipGetLastError();
 }
 

@@ -1005,9 +1005,15 @@ bool msd_geometry(uint64_t N, uint32_t nn, int dbits, int log2B, uint32_t sort_r
   // microcircuit's second scatter)
   p.ranges_b = 2 * std::max<uint32_t>(sort_ranges, 1);
   p.max_ranges_b = b2 ? (uint32_t)(p.ranges_b + (1ull << b1)) : 0u;
-  // pass C: workgroups of about eight LDS loads of records each
+  // pass C: workgroups of about eight LDS loads of records each, and at
+  // least 1,024 (four per CU) so that short tiles of few records -- small or
+  // sparse calibrations -- still spread over the chip; no more workgroups
+  // than sub-buckets
   const uint64_t piece = ng::msd_cap(b2 ? p.narrow_b : p.narrow_a);
-  p.wgs_c = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(1, (N + 8 * piece - 1) / (8 * piece)), 1u << 20);
+  const uint64_t nsb = 1ull << (b1 + b2);
+  p.wgs_c = (uint32_t)std::min<uint64_t>(
+      std::max<uint64_t>(1, std::min<uint64_t>(std::max<uint64_t>((N + 8 * piece - 1) / (8 * piece), 1024), nsb)),
+      1u << 20);
   p.max_big = (uint32_t)(N / (piece + 1) + 1);
   p.n_nodes = nn;
   p.log2B = log2B;
@@ -1016,14 +1022,17 @@ bool msd_geometry(uint64_t N, uint32_t nn, int dbits, int log2B, uint32_t sort_r
 }
 
 // The default radix calibration takes the most-significant-digit form when
-// (1) the sub-buckets it must visit hold 256 connections on average or more
-// (fewer connections over a wide key leave most sub-buckets empty), and (2)
-// the 512 keys that one LDS tile can tell apart hold at least half a tile of
-// connections (n >= 10 connections per occupied key: otherwise pass C sorts
-// nearly empty tiles).  Elsewhere the LSD passes are cheaper.
+// (1) there are at least 2^25 connections: below, the LSD passes are faster
+// (measured on MI355X: 0.94 against 1.04 ms at 3e7 connections over 77,169
+// nodes, 2.9 against 2.3 ms at 1e8); (2) the sub-buckets it must visit hold
+// 256 connections on average or more (fewer connections over a wide key
+// leave most sub-buckets empty); and (3) the 512 keys that one LDS tile can
+// tell apart hold at least half a tile of connections (n >= 10 connections
+// per possible key: otherwise pass C sorts nearly empty tiles).
 bool msd_pays(const ng::MsdPlan& p) {
   const uint64_t keyspace = (uint64_t)p.n_nodes << p.dbits;
-  return (uint64_t)p.n >= (256ull << (p.b1 + p.b2)) && (uint64_t)p.n * 512 >= keyspace * (ng::kMsdTile / 2);
+  return p.n >= (1u << 25) && (uint64_t)p.n >= (256ull << (p.b1 + p.b2)) &&
+         (uint64_t)p.n * 512 >= keyspace * (ng::kMsdTile / 2);
 }
 
 // Calibration of one context by the most-significant-digit sort: count and

@@ -192,11 +192,14 @@ def _kernels_used(wl, calibration):
 
 
 def test_default_form_choice():
-    # the default radix calibration sorts most-significant digit first when
-    # the sub-buckets average 256 connections or more and the possible keys
-    # 10 or more, else by LSD passes
-    big = W.microcircuit(scale=0.1)
+    # the default radix calibration sorts most-significant digit first from
+    # 2^25 connections on, when the sub-buckets average 256 connections or
+    # more and the possible keys 10 or more, else by LSD passes
+    big = W.microcircuit(scale=0.35)  # 3.7e7 connections, 42 per possible key
     assert _plan(big)["msd"] == 2
+    small = W.microcircuit(scale=0.1)  # 3e6 connections
+    assert _plan(small)["msd"] == 1
+    assert "downsweep" in _kernels_used(small, "radix")
     names = _kernels_used(big, "radix")
     assert "msd_scatter_a" in names and "downsweep" not in names
     sparse = _ftn("sparse_default", [1 << 20], (0, 1 << 20), (0, 1 << 20), 5_000, ("uniform_int", 1, 63))

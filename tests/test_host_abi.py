@@ -153,10 +153,11 @@ def test_calibration_plan(L, n_conns, n_nodes, max_delay):
     if keybits > 27:
         assert p["msd"] == 0 and p["b1"] == 0
         return
-    # the default takes it when the sub-buckets average 256 connections or
-    # more and the possible keys 10 or more
+    # the default takes it from 2^25 connections on, when the sub-buckets
+    # average 256 connections or more and the possible keys 10 or more
     dense = n_conns * 512 >= (n_nodes << dbits) * 5120
-    assert p["msd"] == (2 if n_conns >= 256 << (p["b1"] + p["b2"]) and dense else 1)
+    big = n_conns >= 1 << 25
+    assert p["msd"] == (2 if big and n_conns >= 256 << (p["b1"] + p["b2"]) and dense else 1)
     assert p["b1"] + p["b2"] + p["b3"] == keybits
     assert all(1 <= p[k] <= 9 for k in ("b1", "b3")) and 0 <= p["b2"] <= 9
     tbits = max(sbits, 1)
