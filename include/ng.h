@@ -492,6 +492,8 @@ int ng_submit_connect(ng_session* session, ng_range src, ng_range tgt, const ng_
 int ng_submit_calibrate(ng_session* session, uint64_t* ticket);
 /* Close after the session's earlier requests; the handle is invalid afterwards. */
 int ng_submit_close(ng_session* session, uint64_t* ticket);
+/* The same, waiting for the close to finish: returns its status. */
+int ng_session_close(ng_session* session);
 /* Wait up to timeout_ns (< 0: forever) for a ticket.  NG_OK: finished, *out
  * filled (out->status is the request's result) and the ticket consumed;
  * NG_ERR_STATE: still running (the ticket stays valid). */

@@ -31,13 +31,25 @@ namespace {
 
 constexpr int kMThreads = 512;
 constexpr int kMWaves = kMThreads / 64;
-constexpr int kMItems = 20;                          // tile of pass A and of unpacked records
+constexpr int kMItems = (int)kMsdTile / kMThreads;   // tile of pass A and of unpacked records
 constexpr int kMItemsN = (int)kMsdTileN / kMThreads;  // tile of packed records (passes B and C)
 static_assert(kMThreads * kMItems == (int)kMsdTile, "tile of unpacked records");
 static_assert(kMThreads * kMItemsN == (int)kMsdTileN, "tile of packed records");
 constexpr int kMNB = 1 << kMsdMaxDigit;  // 512 digit values at most
-static_assert(kMNB == kMThreads, "one thread per digit value");
+static_assert(kMThreads >= kMNB, "one thread per digit value");
+static_assert(kMWaves % 2 == 0, "wave counters come in pairs");
 constexpr int kMLdsBlocks = 512;
+
+// Per-wave digit counters in LDS: waves 2v and 2v + 1 share the words
+// wh[v][d], wave 2v in the low and wave 2v + 1 in the high 16 bits.  A
+// wave's count of one digit in a tile is at most 64 x 32 records, and a
+// tile position at most 16,384, so neither half carries into the other.
+constexpr int kMWhWords = kMWaves / 2 * kMNB;
+__device__ __forceinline__ uint32_t wh_at(int wave, uint32_t d) { return (uint32_t)(wave >> 1) * kMNB + d; }
+__device__ __forceinline__ uint32_t wh_shift(int wave) { return (uint32_t)(wave & 1) * 16u; }
+__device__ __forceinline__ uint32_t wh_get(const uint32_t* wh, int wave, uint32_t d) {
+  return (wh[wh_at(wave, d)] >> wh_shift(wave)) & 0xFFFFu;
+}
 
 enum { IN_BLOCKS = 0, IN_NARROW = 1, IN_WIDE = 2 };
 
@@ -138,9 +150,10 @@ __device__ __forceinline__ void load_arrays(const uint32_t* ik, const uint32_t* 
 // counter of that digit with one LDS atomic (other lanes add to a private
 // word), and the old value reaches its peers through a lane permute a few
 // slots later, so no slot waits on the one before it.  The digit of a key is
-// ((key >> shift) - base) & mask, below 2^nbits (ballots only for those bits).  On return pos[k] is the rank within the
-// wave's records of the digit, and wh[wave][d] holds the wave's count of
-// digit d.
+// ((key >> shift) - base) & mask, below 2^nbits (ballots only for those
+// bits).  On return pos[k] is the rank within the wave's records of the
+// digit, and the wave's half of wh[wave / 2][d] holds its count of digit d.
+// Lanes that add nothing add to their word of sink[64].
 template <int RB, int ITEMS, bool FULL>
 __device__ __forceinline__ void rank_digits(const uint32_t (&key)[ITEMS], uint32_t shift, uint32_t mask, uint32_t cnt,
                                             uint32_t* wh, uint32_t* sink, uint32_t (&pos)[ITEMS],
@@ -174,14 +187,14 @@ __device__ __forceinline__ void rank_digits(const uint32_t (&key)[ITEMS], uint32
       const uint32_t below = __builtin_amdgcn_mbcnt_hi(phi, __builtin_amdgcn_mbcnt_lo(plo, 0u));
       const uint32_t tot = (uint32_t)__popc(plo) + (uint32_t)__popc(phi);
       const uint32_t lead = (uint32_t)__builtin_ctzll(((uint64_t)phi << 32) | plo | (1ull << 63));
-      uint32_t* ctr = (valid && below == 0) ? &wh[wave * kMNB + d] : &sink[threadIdx.x];
-      prv[k] = atomicAdd(ctr, tot);
+      uint32_t* ctr = (valid && below == 0) ? &wh[wh_at(wave, d)] : &sink[lane];
+      prv[k] = atomicAdd(ctr, tot << wh_shift(wave));
       pos[k] = below | (lead << 8);
     }
     if (k >= kLag && slot_used(k - kLag)) {
       const int q = k - kLag;
       const uint32_t prev = (uint32_t)__builtin_amdgcn_ds_bpermute((int)((pos[q] >> 8) << 2), (int)prv[q]);
-      pos[q] = prev + (pos[q] & 0xFFu);
+      pos[q] = ((prev >> wh_shift(wave)) & 0xFFFFu) + (pos[q] & 0xFFu);
     }
     __builtin_amdgcn_sched_barrier(0);  // keep the lag: no permute moves up to its add
   }
@@ -207,14 +220,15 @@ __device__ __forceinline__ uint32_t m_block_scan_open(uint32_t v, uint32_t* s_tm
 
 // Thread d: digit d's counts over the waves become each wave's first tile
 // position of that digit; returns the digit's count in the tile and sets
-// *start to its first tile position.  Leaves wh[wave][d] = tile position.
+// *start to its first tile position.  Leaves each wave's half of
+// wh[wave / 2][d] = that tile position.
 __device__ __forceinline__ uint32_t digit_starts(uint32_t nd, uint32_t* wh, uint32_t* s_tmp, uint32_t* start) {
   const uint32_t d = threadIdx.x;
   uint32_t c[kMWaves];
   uint32_t tot = 0;
 #pragma unroll
   for (int v = 0; v < kMWaves; ++v) {
-    const uint32_t x = d < nd ? wh[v * kMNB + d] : 0u;
+    const uint32_t x = d < nd ? wh_get(wh, v, d) : 0u;
     c[v] = tot;
     tot += x;
   }
@@ -222,7 +236,7 @@ __device__ __forceinline__ uint32_t digit_starts(uint32_t nd, uint32_t* wh, uint
   const uint32_t st = m_block_scan(tot, s_tmp, &all);
   if (d < nd) {
 #pragma unroll
-    for (int v = 0; v < kMWaves; ++v) wh[v * kMNB + d] = st + c[v];
+    for (int v = 0; v < kMWaves; v += 2) wh[wh_at(v, d)] = (st + c[v]) | ((st + c[v + 1]) << 16);
   }
   *start = st;
   return tot;
@@ -240,7 +254,7 @@ __device__ __forceinline__ uint32_t digit_starts_present(uint32_t nd, uint32_t* 
   uint32_t tot = 0;
 #pragma unroll
   for (int v = 0; v < kMWaves; ++v) {
-    const uint32_t x = d < nd ? wh[v * kMNB + d] : 0u;
+    const uint32_t x = d < nd ? wh_get(wh, v, d) : 0u;
     c[v] = tot;
     tot += x;
   }
@@ -249,7 +263,7 @@ __device__ __forceinline__ uint32_t digit_starts_present(uint32_t nd, uint32_t* 
   const uint32_t st = sc >> 10;
   if (d < nd) {
 #pragma unroll
-    for (int v = 0; v < kMWaves; ++v) wh[v * kMNB + d] = st + c[v];
+    for (int v = 0; v < kMWaves; v += 2) wh[wh_at(v, d)] = (st + c[v]) | ((st + c[v + 1]) << 16);
   }
   *start = st;
   *ex = sc & 1023u;
@@ -272,13 +286,13 @@ struct PassIO {
 
 struct ScatterLds {
   uint32_t *k, *t, *w;   // [kMsdTile] staged records
-  uint32_t* wh;          // [kMWaves][kMNB]
+  uint32_t* wh;          // [kMWaves / 2][kMNB], two waves per word
   uint4* dig;            // [kMNB]: x = global position of the digit's first record minus its
                          // tile position (mod 2^32); [y, y + z): positions whose 128-byte line
                          // the tile's run fills completely
   uint32_t* run;         // [kMNB] next global position per digit
   uint32_t* tmp;         // [kMWaves]
-  uint32_t* sink;        // [kMThreads]
+  uint32_t* sink;        // [64]
 };
 
 template <int ITEMS, int IN, bool FULL>
@@ -318,7 +332,7 @@ __device__ __forceinline__ void scatter_tile(const PassIO& io, uint32_t cnt, con
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k) {
     if (FULL || item_index(ITEMS, k) < cnt) {
-      const uint32_t p = pos[k] + L.wh[wave * kMNB + ((r.k[k] >> io.shift) & io.mask)];
+      const uint32_t p = pos[k] + wh_get(L.wh, wave, (r.k[k] >> io.shift) & io.mask);
       L.k[p] = r.k[k];
       if constexpr (HAS_T) L.t[p] = r.t[k];
       L.w[p] = r.w[k];
@@ -327,7 +341,7 @@ __device__ __forceinline__ void scatter_tile(const PassIO& io, uint32_t cnt, con
   lds_barrier();
   for (uint32_t d = threadIdx.x; d < (uint32_t)kMNB; d += kMThreads) {
 #pragma unroll
-    for (int v = 0; v < kMWaves; ++v) L.wh[v * kMNB + d] = 0;
+    for (int v = 0; v < kMWaves / 2; ++v) L.wh[v * kMNB + d] = 0;
   }
   if (next_cnt) load_tile_any<ITEMS, IN>(io, next_base, next_cnt, r);
   // Runs of equal digits go to consecutive positions.  Stores of records
@@ -385,11 +399,11 @@ __device__ __forceinline__ void scatter_range(const PassIO& io, const ScatterLds
   __shared__ uint32_t s_k[TILE];                        \
   __shared__ uint32_t s_t[IN == IN_NARROW ? 1 : TILE];  \
   __shared__ uint32_t s_w[TILE];                        \
-  __shared__ uint32_t s_wh[kMWaves * kMNB];             \
+  __shared__ uint32_t s_wh[kMWhWords];                  \
   __shared__ uint4 s_dig[kMNB];                         \
   __shared__ uint32_t s_run[kMNB];                      \
   __shared__ uint32_t s_tmp[kMWaves];                   \
-  __shared__ uint32_t s_sink[kMThreads];                \
+  __shared__ uint32_t s_sink[64];                       \
   const ScatterLds L{s_k, s_t, s_w, s_wh, s_dig, s_run, s_tmp, s_sink};
 
 // Pass A: range r of the creation-order records by D1.
@@ -414,7 +428,7 @@ __global__ __launch_bounds__(kMThreads) void k_msd_scatter_a(MsdPlan p) {
   for (uint32_t d = threadIdx.x; d < (uint32_t)kMNB; d += kMThreads) {
     s_run[d] = d < nd ? p.cnt_a[(uint64_t)d * p.ranges_a + r] : 0u;
 #pragma unroll
-    for (int v = 0; v < kMWaves; ++v) s_wh[v * kMNB + d] = 0;
+    for (int v = 0; v < kMWaves / 2; ++v) s_wh[v * kMNB + d] = 0;
   }
   lds_barrier();
   const uint32_t ntiles = (p.n + kMsdTile - 1) / kMsdTile;
@@ -435,7 +449,7 @@ __device__ __forceinline__ uint32_t bucket_of_range(const uint32_t* s_rb0, uint3
 
 // Pass B: range r of a bucket by D2.
 template <int RB, int IN, bool OUT_NARROW, int ITEMS>
-__global__ __launch_bounds__(kMThreads) void k_msd_scatter_b(MsdPlan p) {  // the tile is p.tile_b = ITEMS x 512
+__global__ __launch_bounds__(kMThreads) void k_msd_scatter_b(MsdPlan p) {  // the tile is p.tile_b = ITEMS x kMThreads
   M_SCATTER_LDS(ITEMS * kMThreads)
   __shared__ uint32_t s_rb0[kMNB + 1];
   const uint32_t nb = 1u << p.b1, nd = 1u << p.b2;
@@ -461,7 +475,7 @@ __global__ __launch_bounds__(kMThreads) void k_msd_scatter_b(MsdPlan p) {  // th
   for (uint32_t d = threadIdx.x; d < (uint32_t)kMNB; d += kMThreads) {
     s_run[d] = d < nd ? p.cnt_b[cb + (uint64_t)d * nr] : 0u;
 #pragma unroll
-    for (int v = 0; v < kMWaves; ++v) s_wh[v * kMNB + d] = 0;
+    for (int v = 0; v < kMWaves / 2; ++v) s_wh[v * kMNB + d] = 0;
   }
   lds_barrier();
   const uint32_t ntiles = (be - bs + p.tile_b - 1) / p.tile_b;
@@ -777,11 +791,13 @@ __device__ __forceinline__ void tile_groups(const MsdPlan& p, uint32_t sba, uint
   const uint32_t b3 = p.b3, m3 = (1u << b3) - 1u, nd = nsub << b3;
   const bool present = h != 0;
   const uint64_t bal = __ballot(present);
-  s_ex[d] = ex;
-  s_st[d] = hst;
-  if (lane == 0) {
-    s_bal[2 * wave] = (uint32_t)bal;
-    s_bal[2 * wave + 1] = (uint32_t)(bal >> 32);
+  if (d < (uint32_t)kMNB) {  // threads past the digits hold none
+    s_ex[d] = ex;
+    s_st[d] = hst;
+    if (lane == 0) {
+      s_bal[2 * wave] = (uint32_t)bal;
+      s_bal[2 * wave + 1] = (uint32_t)(bal >> 32);
+    }
   }
   if (d == 0) s_ex[kMNB] = all_present;
   lds_barrier();
@@ -806,11 +822,11 @@ __device__ __forceinline__ void tile_groups(const MsdPlan& p, uint32_t sba, uint
   __shared__ uint32_t s_k[CSize<NARROW>::TILE];              \
   __shared__ uint32_t s_t[NARROW ? 1 : CSize<NARROW>::TILE]; \
   __shared__ uint32_t s_w[CSize<NARROW>::TILE];              \
-  __shared__ uint32_t s_wh[kMWaves * kMNB];      \
+  __shared__ uint32_t s_wh[kMWhWords];           \
   __shared__ uint32_t s_st[kMNB + 1];            \
   __shared__ uint32_t s_ex[kMNB + 1];            \
   __shared__ uint32_t s_tmp[kMWaves];            \
-  __shared__ uint32_t s_sink[kMThreads];         \
+  __shared__ uint32_t s_sink[64];                \
   __shared__ uint32_t s_bal[kMNB / 32];          \
   __shared__ char* s_blk_tab[kMLdsBlocks];
 
@@ -844,7 +860,7 @@ __device__ __forceinline__ char* const* c_setup(const MsdPlan& p, char** s_blk_t
     for (uint32_t b = threadIdx.x; b < n_out_blocks; b += kMThreads) s_blk_tab[b] = C(p.out_blocks, b);
   for (uint32_t d = threadIdx.x; d < (uint32_t)kMNB; d += kMThreads) {
 #pragma unroll
-    for (int v = 0; v < kMWaves; ++v) s_wh[v * kMNB + d] = 0;
+    for (int v = 0; v < kMWaves / 2; ++v) s_wh[v * kMNB + d] = 0;
   }
   return s_blk;
 }
@@ -885,7 +901,7 @@ __device__ __forceinline__ void c_stage(const CFields& f, const Recs<CSize<NARRO
   for (int k = 0; k < CSize<NARROW>::ITEMS; ++k) {
     if (item_index(CSize<NARROW>::ITEMS, k) < cnt) {
       const uint32_t dg = ((r.k[k] >> f.ks) - base) & f.km;
-      const uint32_t q = pos[k] + s_wh[wave * kMNB + dg];
+      const uint32_t q = pos[k] + wh_get(s_wh, wave, dg);
       s_k[q] = r.k[k];
       if constexpr (!NARROW) s_t[q] = r.t[k];
       s_w[q] = r.w[k];
@@ -896,7 +912,7 @@ __device__ __forceinline__ void c_stage(const CFields& f, const Recs<CSize<NARRO
 __device__ __forceinline__ void clear_wh(uint32_t* s_wh) {
   for (uint32_t e = threadIdx.x; e < (uint32_t)kMNB; e += kMThreads) {
 #pragma unroll
-    for (int v = 0; v < kMWaves; ++v) s_wh[v * kMNB + e] = 0;
+    for (int v = 0; v < kMWaves / 2; ++v) s_wh[v * kMNB + e] = 0;
   }
 }
 

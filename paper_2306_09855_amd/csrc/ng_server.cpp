@@ -16,6 +16,8 @@
 //
 // Arithmetic is unchanged: a session's result equals the same calls issued on
 // a context of its own (same seed, same call order).
+#include <sys/prctl.h>
+
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -61,6 +63,11 @@ struct Request {
 };
 
 // Pinned upload region for one packed launch; reusable once its copy ran.
+// Each stream starts with kStagesPerStream of kStageBytes, allocated with the
+// server: pinning host memory takes far longer than a launch, so a burst of
+// launches must not pay for it.
+constexpr int kStagesPerStream = 16;
+constexpr uint64_t kStageBytes = 64 << 10;
 struct Stage {
   char* p = nullptr;
   uint64_t cap = 0;
@@ -125,8 +132,10 @@ struct ng_server {
   // Copy host bytes to device memory on stream k through the stream's pinned
   // stages (allocated once, reused once their last copy ran; the scheduler
   // never frees pinned memory, which would wait for the whole device).
-  int upload(int k, void* d, const void* src, uint64_t nb);
-  int stage_upload(int k, const std::vector<ng::GenDesc>& descs, ng::GenDesc** d_out, uint64_t* bytes);
+  // A second piece (src2, n2 bytes) may follow at offset off2 of the same
+  // copy.
+  int upload(int k, void* d, const void* src, uint64_t nb, const void* src2 = nullptr, uint64_t off2 = 0,
+             uint64_t n2 = 0);
   // Calibrate the collected requests' sessions together (one packed
   // calibration); if that fails, one by one, where a request that does not
   // fit stays queued (and joins oom_wait) unless hopeless(session).
@@ -234,22 +243,24 @@ void ng_server::publish() {
 }
 
 // Copy descriptors to the device through a pinned stage of stream k.
-int ng_server::upload(int k, void* d, const void* src, uint64_t nb) {
+int ng_server::upload(int k, void* d, const void* src, uint64_t nb, const void* src2, uint64_t off2, uint64_t n2) {
+  const uint64_t total = src2 ? off2 + n2 : nb;
   Stage* st = nullptr;
   for (auto& s : stages[k])
-    if (s.cap >= nb && (!s.busy || hipEventQuery(s.busy->ev) == hipSuccess)) {
+    if (s.cap >= total && (!s.busy || hipEventQuery(s.busy->ev) == hipSuccess)) {
       st = &s;
       break;
     }
   if (!st) {
     Stage s;
-    s.cap = std::max<uint64_t>(nb, 1 << 16);
+    s.cap = std::max<uint64_t>(total, kStageBytes);
     if (hipHostMalloc((void**)&s.p, s.cap, hipHostMallocDefault) != hipSuccess) return NG_ERR_DEVICE;
     stages[k].push_back(s);
     st = &stages[k].back();
   }
   memcpy(st->p, src, nb);
-  if (hipMemcpyAsync(d, st->p, nb, hipMemcpyHostToDevice, streams[k]) != hipSuccess) return NG_ERR_DEVICE;
+  if (src2) memcpy(st->p + off2, src2, n2);
+  if (hipMemcpyAsync(d, st->p, total, hipMemcpyHostToDevice, streams[k]) != hipSuccess) return NG_ERR_DEVICE;
   auto box = std::make_shared<EventBox>();
   if (hipEventCreateWithFlags(&box->ev, hipEventDisableTiming) != hipSuccess ||
       hipEventRecord(box->ev, streams[k]) != hipSuccess)
@@ -258,22 +269,12 @@ int ng_server::upload(int k, void* d, const void* src, uint64_t nb) {
   return NG_OK;
 }
 
-int ng_server::stage_upload(int k, const std::vector<ng::GenDesc>& descs, ng::GenDesc** d_out,
-                            uint64_t* bytes) {
-  const uint64_t nb = descs.size() * sizeof(ng::GenDesc);
-  char* d = arena.alloc(nb);
-  if (!d) return NG_ERR_OOM;
-  if (int rc = upload(k, d, descs.data(), nb)) {
-    arena.release(d, nb);
-    return rc;
-  }
-  *d_out = (ng::GenDesc*)d;
-  *bytes = nb;
-  return NG_OK;
-}
-
 void ng_server::run() {
   (void)hipSetDevice(device);
+  // The completion poll below sleeps 10 us at a time; with the default 50 us
+  // timer slack of a thread each of those sleeps would last about 60 us and
+  // add that much to a request's latency.
+  (void)prctl(PR_SET_TIMERSLACK, 1000UL, 0UL, 0UL, 0UL);
   const int ns = (int)streams.size();
   bool progress = true;
   for (;;) {
@@ -282,13 +283,13 @@ void ng_server::run() {
       std::unique_lock<std::mutex> lk(mu);
       publish();
       // Sleep until something can change: new requests, or (polling every
-      // 20 us) device work or memory releases still pending.
+      // 10 us) device work or memory releases still pending.
       auto news = [&] { return stop || !incoming.empty() || !new_sessions.empty(); };
       const bool pending = n_inflight != 0 || arena.deferred_bytes() != 0;
       if (!pending && !progress)
         cv_work.wait(lk, news);
       else if (pending)
-        cv_work.wait_for(lk, std::chrono::microseconds(20), news);
+        cv_work.wait_for(lk, std::chrono::microseconds(10), news);
       for (ng_session* ss : new_sessions) sessions.push_back(ss);
       new_sessions.clear();
       for (Request* r : incoming) {
@@ -326,11 +327,10 @@ void ng_server::run() {
         d.group0 = groups;
         groups += ((uint64_t)d.n_new + 3) / 4;
       }
-      ng::GenDesc* d_descs = nullptr;
-      uint64_t nb = 0;
       int rc = check_descs(descs[k]);
-      // the sessions' new block-table entries, all written by one launch
-      // (or, without arena room for the list, by each context's own)
+      // The sessions' new block-table entries are written by one launch; they
+      // travel in the same upload as the descriptors, behind them (or, without
+      // arena room for both, each context writes its own).
       std::vector<ng::TabEntry> entries;
       std::vector<std::pair<ng_ctx*, uint32_t>> synced;
       for (Request* r : packed[k]) {
@@ -340,24 +340,40 @@ void ng_server::run() {
           take_table_entries(c, entries);
         }
       }
-      char* d_ent = nullptr;
-      const uint64_t ne = entries.size() * sizeof(ng::TabEntry);
+      auto unsync = [&] {  // the entries were not written
+        for (auto& cs : synced) cs.first->tab_synced = cs.second;
+        synced.clear();
+        entries.clear();
+      };
+      const uint64_t nd = descs[k].size() * sizeof(ng::GenDesc);
+      const uint64_t eoff = (nd + 255) / 256 * 256;
+      uint64_t nb = entries.empty() ? nd : eoff + entries.size() * sizeof(ng::TabEntry);
+      char* d = nullptr;
       hipError_t e = hipSuccess;
-      if (rc == NG_OK && !entries.empty()) {
-        d_ent = arena.alloc(ne);
-        if (!d_ent) {
-          for (auto& cs : synced) cs.first->tab_synced = cs.second;
+      if (rc == NG_OK) {
+        d = arena.alloc(nb);
+        if (!d && !entries.empty()) {
+          unsync();
           for (auto& cs : synced)
             if (rc == NG_OK) rc = sync_table(cs.first);
-        } else if ((rc = upload(k, d_ent, entries.data(), ne)) != NG_OK) {
-          for (auto& cs : synced) cs.first->tab_synced = cs.second;  // not written
-          arena.release(d_ent, ne);
-          d_ent = nullptr;
-        } else {
-          e = ng::launch_set_entries((const ng::TabEntry*)d_ent, (uint32_t)entries.size(), streams[k]);
+          nb = nd;
+          if (rc == NG_OK) d = arena.alloc(nb);
+        }
+        if (rc == NG_OK && !d) rc = NG_ERR_OOM;
+      }
+      if (rc == NG_OK) {
+        rc = entries.empty() ? upload(k, d, descs[k].data(), nd)
+                             : upload(k, d, descs[k].data(), nd, entries.data(), eoff,
+                                      entries.size() * sizeof(ng::TabEntry));
+        if (rc != NG_OK) {
+          arena.release(d, nb);
+          d = nullptr;
         }
       }
-      if (rc == NG_OK && e == hipSuccess) rc = stage_upload(k, descs[k], &d_descs, &nb);
+      if (rc != NG_OK) unsync();
+      if (rc == NG_OK && !entries.empty())
+        e = ng::launch_set_entries((const ng::TabEntry*)(d + eoff), (uint32_t)entries.size(), streams[k]);
+      ng::GenDesc* d_descs = (ng::GenDesc*)d;
       std::shared_ptr<EventBox> box;
       if (rc == NG_OK && e == hipSuccess) {
         e = ng::launch_generate_batch(d_descs, (uint32_t)descs[k].size(), groups, log2B, streams[k]);
@@ -368,19 +384,17 @@ void ng_server::run() {
         sched.packed_calls += descs[k].size();
         if (descs[k].size() > sched.max_calls_per_launch) sched.max_calls_per_launch = descs[k].size();
       }
-      if (d_descs || d_ent) {  // descriptors and entries return to the arena after the launches
+      if (d) {  // descriptors and entries return to the arena after the launches
         hipEvent_t fe = nullptr;
         if (hipEventCreateWithFlags(&fe, hipEventDisableTiming) == hipSuccess &&
             hipEventRecord(fe, streams[k]) == hipSuccess) {
           Arena::Ranges rs;
-          if (d_descs) rs.emplace_back((char*)d_descs, nb);
-          if (d_ent) rs.emplace_back(d_ent, ne);
+          rs.emplace_back(d, nb);
           arena.release_after(streams[k], std::move(rs), fe);
         } else {
           if (fe) (void)hipEventDestroy(fe);
           (void)hipStreamSynchronize(streams[k]);
-          if (d_descs) arena.release((char*)d_descs, nb);
-          if (d_ent) arena.release(d_ent, ne);
+          arena.release(d, nb);
         }
       }
       if (rc != NG_OK || e != hipSuccess) {
@@ -535,6 +549,18 @@ int ng_server_create(const ng_server_config* cfg, void* arena, uint64_t arena_by
   for (int i = 0; i < n_streams; ++i) s->streams.push_back((hipStream_t)streams[i]);
   s->stages.resize(n_streams);
   s->inflight.resize(n_streams);
+  for (auto& v : s->stages)
+    for (int i = 0; i < kStagesPerStream; ++i) {
+      Stage st;
+      st.cap = kStageBytes;
+      if (hipHostMalloc((void**)&st.p, st.cap, hipHostMallocDefault) != hipSuccess) {
+        for (auto& w : s->stages)
+          for (auto& x : w) (void)hipHostFree(x.p);
+        delete s;
+        return fail(NG_ERR_DEVICE, "hipHostMalloc of the upload stages failed");
+      }
+      v.push_back(st);
+    }
   const uint64_t B = cfg->block_size ? cfg->block_size : (1ull << 24);
   if (B & (B - 1) || B < (1ull << 16) || B > (1ull << 30)) {
     delete s;
@@ -660,6 +686,16 @@ int ng_submit_close(ng_session* ss, uint64_t* ticket) {
   Request* r = new Request();
   r->kind = REQ_CLOSE;
   return submit(ss, r, ticket);
+}
+
+int ng_session_close(ng_session* ss) {
+  if (!ss) return fail(NG_ERR_INVALID_ARG, "null session");
+  ng_server* srv = ss->server;
+  uint64_t t = 0;
+  if (int rc = ng_submit_close(ss, &t)) return rc;
+  ng_ticket_info info{};
+  if (int rc = ng_wait(srv, t, -1, &info)) return rc;
+  return info.status;
 }
 
 int ng_wait(ng_server* s, uint64_t ticket, int64_t timeout_ns, ng_ticket_info* out) {

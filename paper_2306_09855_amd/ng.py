@@ -159,6 +159,7 @@ def lib():
                                   ctypes.c_int),
             "ng_submit_calibrate": ([vp, P(u64)], ctypes.c_int),
             "ng_submit_close": ([vp, P(u64)], ctypes.c_int),
+            "ng_session_close": ([vp], ctypes.c_int),
             "ng_wait": ([vp, u64, ctypes.c_int64, P(ng_ticket_info)], ctypes.c_int),
             "ng_session_context": ([vp, P(vp)], ctypes.c_int),
             "ng_server_get_stats": ([vp, P(ng_server_stats)], ctypes.c_int),
@@ -455,6 +456,10 @@ def ng_submit_close(session) -> int:
     t = ctypes.c_uint64()
     _check(lib().ng_submit_close(session, ctypes.byref(t)))
     return int(t.value)
+
+
+def ng_session_close(session) -> None:
+    _check(lib().ng_session_close(session))
 
 
 def ng_wait(server, ticket: int, timeout_ns: int = -1) -> ng_ticket_info:

@@ -131,7 +131,7 @@ def test_admission_waits_for_memory():
     with pytest.raises(ng.NGError) as e:
         ng.ng_wait(srv, tb, timeout_ns=200_000_000)
     assert e.value.status == ng.NG_ERR_STATE
-    ng.ng_wait(srv, ng.ng_submit_close(a))
+    ng.ng_session_close(a)  # submits the close and waits for it
     info = ng.ng_wait(srv, tb)
     assert info.status == 0 and info.n_conns == 400_000
     assert ng.ng_wait(srv, ng.ng_submit_calibrate(b)).status == ng.NG_ERR_OOM
