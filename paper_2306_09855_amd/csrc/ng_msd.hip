@@ -39,12 +39,19 @@ constexpr int kMNB = 1 << kMsdMaxDigit;  // 512 digit values at most
 static_assert(kMThreads >= kMNB, "one thread per digit value");
 static_assert(kMWaves % 2 == 0, "wave counters come in pairs");
 constexpr int kMLdsBlocks = 512;
+// Pass C sorts its tiles with twice the waves of the scatter passes: it holds
+// only the packed records (its LDS leaves room for the wave counters of 16
+// waves), and with half the records per thread it fits 1024 threads.
+constexpr int kCThreads = 1024;
+constexpr int kCWaves = kCThreads / 64;
+static_assert(kCWaves % 2 == 0 && kCThreads >= kMNB, "pass C waves");
 
 // Per-wave digit counters in LDS: waves 2v and 2v + 1 share the words
 // wh[v][d], wave 2v in the low and wave 2v + 1 in the high 16 bits.  A
 // wave's count of one digit in a tile is at most 64 x 32 records, and a
 // tile position at most 16,384, so neither half carries into the other.
 constexpr int kMWhWords = kMWaves / 2 * kMNB;
+constexpr int kCWhWords = kCWaves / 2 * kMNB;
 __device__ __forceinline__ uint32_t wh_at(int wave, uint32_t d) { return (uint32_t)(wave >> 1) * kMNB + d; }
 __device__ __forceinline__ uint32_t wh_shift(int wave) { return (uint32_t)(wave & 1) * 16u; }
 __device__ __forceinline__ uint32_t wh_get(const uint32_t* wh, int wave, uint32_t d) {
@@ -53,7 +60,8 @@ __device__ __forceinline__ uint32_t wh_get(const uint32_t* wh, int wave, uint32_
 
 enum { IN_BLOCKS = 0, IN_NARROW = 1, IN_WIDE = 2 };
 
-// Exclusive scan across the 512-thread workgroup; *total = the sum.
+// Exclusive scan across a workgroup of NW waves; *total = the sum.
+template <int NW = kMWaves>
 __device__ __forceinline__ uint32_t m_block_scan(uint32_t v, uint32_t* s_tmp, uint32_t* total) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t inc = wave_inclusive_scan(v);
@@ -61,7 +69,7 @@ __device__ __forceinline__ uint32_t m_block_scan(uint32_t v, uint32_t* s_tmp, ui
   lds_barrier();
   uint32_t off = 0, sum = 0;
 #pragma unroll
-  for (int w = 0; w < kMWaves; ++w) {
+  for (int w = 0; w < NW; ++w) {
     const uint32_t t = s_tmp[w];
     if (w < wave) off += t;
     sum += t;
@@ -202,6 +210,7 @@ __device__ __forceinline__ void rank_digits(const uint32_t (&key)[ITEMS], uint32
 
 // m_block_scan without its closing barrier, for callers whose next use of
 // s_tmp comes after another barrier.
+template <int NW>
 __device__ __forceinline__ uint32_t m_block_scan_open(uint32_t v, uint32_t* s_tmp, uint32_t* total) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t inc = wave_inclusive_scan(v);
@@ -209,7 +218,7 @@ __device__ __forceinline__ uint32_t m_block_scan_open(uint32_t v, uint32_t* s_tm
   lds_barrier();
   uint32_t off = 0, sum = 0;
 #pragma unroll
-  for (int w = 0; w < kMWaves; ++w) {
+  for (int w = 0; w < NW; ++w) {
     const uint32_t t = s_tmp[w];
     if (w < wave) off += t;
     sum += t;
@@ -222,21 +231,22 @@ __device__ __forceinline__ uint32_t m_block_scan_open(uint32_t v, uint32_t* s_tm
 // position of that digit; returns the digit's count in the tile and sets
 // *start to its first tile position.  Leaves each wave's half of
 // wh[wave / 2][d] = that tile position.
+template <int NW = kMWaves>
 __device__ __forceinline__ uint32_t digit_starts(uint32_t nd, uint32_t* wh, uint32_t* s_tmp, uint32_t* start) {
   const uint32_t d = threadIdx.x;
-  uint32_t c[kMWaves];
+  uint32_t c[NW];
   uint32_t tot = 0;
 #pragma unroll
-  for (int v = 0; v < kMWaves; ++v) {
+  for (int v = 0; v < NW; ++v) {
     const uint32_t x = d < nd ? wh_get(wh, v, d) : 0u;
     c[v] = tot;
     tot += x;
   }
   uint32_t all;
-  const uint32_t st = m_block_scan(tot, s_tmp, &all);
+  const uint32_t st = m_block_scan<NW>(tot, s_tmp, &all);
   if (d < nd) {
 #pragma unroll
-    for (int v = 0; v < kMWaves; v += 2) wh[wh_at(v, d)] = (st + c[v]) | ((st + c[v + 1]) << 16);
+    for (int v = 0; v < NW; v += 2) wh[wh_at(v, d)] = (st + c[v]) | ((st + c[v + 1]) << 16);
   }
   *start = st;
   return tot;
@@ -247,23 +257,24 @@ __device__ __forceinline__ uint32_t digit_starts(uint32_t nd, uint32_t* wh, uint
 // and the number of present digits before it (*ex); *all = the tile's
 // records << 10 | its present digits.  Leaves s_tmp in use (a barrier must
 // come before its next use).
+template <int NW>
 __device__ __forceinline__ uint32_t digit_starts_present(uint32_t nd, uint32_t* wh, uint32_t* s_tmp,
                                                          uint32_t* start, uint32_t* ex, uint32_t* all) {
   const uint32_t d = threadIdx.x;
-  uint32_t c[kMWaves];
+  uint32_t c[NW];
   uint32_t tot = 0;
 #pragma unroll
-  for (int v = 0; v < kMWaves; ++v) {
+  for (int v = 0; v < NW; ++v) {
     const uint32_t x = d < nd ? wh_get(wh, v, d) : 0u;
     c[v] = tot;
     tot += x;
   }
   // tot < 2^15 (one load), at most 512 present digits: the fields do not mix
-  const uint32_t sc = m_block_scan_open((tot << 10) | (tot ? 1u : 0u), s_tmp, all);
+  const uint32_t sc = m_block_scan_open<NW>((tot << 10) | (tot ? 1u : 0u), s_tmp, all);
   const uint32_t st = sc >> 10;
   if (d < nd) {
 #pragma unroll
-    for (int v = 0; v < kMWaves; v += 2) wh[wh_at(v, d)] = (st + c[v]) | ((st + c[v + 1]) << 16);
+    for (int v = 0; v < NW; v += 2) wh[wh_at(v, d)] = (st + c[v]) | ((st + c[v + 1]) << 16);
   }
   *start = st;
   *ex = sc & 1023u;
@@ -705,16 +716,19 @@ __device__ __forceinline__ char* m_out_block(const MsdPlan& p, char* const* s_bl
   return s_blk ? s_blk[dest >> p.log2B] : C(p.out_blocks, dest >> p.log2B);
 }
 
-// Records per LDS load of pass C: 10,240 for packed and unpacked records.
-// (Measured on the 3e8 microcircuit: 16,384-record tiles spill registers and
-// took 2.46 ms; 6,144-record tiles with two workgroups per CU need a
-// narrower last digit, hence a 9-bit second scatter, and took 2.38 ms plus
-// 0.7 ms more in pass B; 10,240: 2.27 ms.)
+// Records per LDS load of pass C: 10,240 for packed and unpacked records,
+// 10 per thread of 1,024.  (Measured on the 3e8 microcircuit, with 512
+// threads: 16,384-record tiles spill registers and took 2.46 ms; 6,144-record
+// tiles with two workgroups per CU need a narrower last digit, hence a 9-bit
+// second scatter, and took 2.38 ms plus 0.7 ms more in pass B; 10,240: 2.17
+// ms.  With 1,024 threads: 2.03 ms; stores through a scalar block base for
+// runs inside one block, next to the general store loop: 2.15 ms.)
 template <bool NARROW>
 struct CSize {
-  static constexpr int ITEMS = kMItems;
-  static constexpr uint32_t TILE = (uint32_t)(ITEMS * kMThreads);
+  static constexpr int ITEMS = (int)kMsdTile / kCThreads;
+  static constexpr uint32_t TILE = (uint32_t)(ITEMS * kCThreads);
 };
+static_assert(CSize<true>::TILE == kMsdTile, "tile of pass C");
 constexpr uint32_t kCMaxSub = 63;      // sub-buckets per tile: lanes 1..63 test the ends
 
 // Sub-buckets per tile: bounded by the lanes of one wave, by 9-bit combined
@@ -822,10 +836,10 @@ __device__ __forceinline__ void tile_groups(const MsdPlan& p, uint32_t sba, uint
   __shared__ uint32_t s_k[CSize<NARROW>::TILE];              \
   __shared__ uint32_t s_t[NARROW ? 1 : CSize<NARROW>::TILE]; \
   __shared__ uint32_t s_w[CSize<NARROW>::TILE];              \
-  __shared__ uint32_t s_wh[kMWhWords];           \
+  __shared__ uint32_t s_wh[kCWhWords];           \
   __shared__ uint32_t s_st[kMNB + 1];            \
   __shared__ uint32_t s_ex[kMNB + 1];            \
-  __shared__ uint32_t s_tmp[kMWaves];            \
+  __shared__ uint32_t s_tmp[kCWaves];            \
   __shared__ uint32_t s_sink[64];                \
   __shared__ uint32_t s_bal[kMNB / 32];          \
   __shared__ char* s_blk_tab[kMLdsBlocks];
@@ -857,10 +871,10 @@ __device__ __forceinline__ char* const* c_setup(const MsdPlan& p, char** s_blk_t
   const uint32_t n_out_blocks = (uint32_t)(((uint64_t)p.n + (1ull << p.log2B) - 1) >> p.log2B);
   char* const* s_blk = n_out_blocks <= (uint32_t)kMLdsBlocks ? s_blk_tab : nullptr;
   if (s_blk)
-    for (uint32_t b = threadIdx.x; b < n_out_blocks; b += kMThreads) s_blk_tab[b] = C(p.out_blocks, b);
-  for (uint32_t d = threadIdx.x; d < (uint32_t)kMNB; d += kMThreads) {
+    for (uint32_t b = threadIdx.x; b < n_out_blocks; b += kCThreads) s_blk_tab[b] = C(p.out_blocks, b);
+  for (uint32_t d = threadIdx.x; d < (uint32_t)kMNB; d += kCThreads) {
 #pragma unroll
-    for (int v = 0; v < kMWaves / 2; ++v) s_wh[v * kMNB + d] = 0;
+    for (int v = 0; v < kCWaves / 2; ++v) s_wh[v * kMNB + d] = 0;
   }
   return s_blk;
 }
@@ -874,7 +888,7 @@ __device__ __forceinline__ void c_store(const MsdPlan& p, const CFields& f, char
   const uint64_t B = 1ull << p.log2B;
 #pragma unroll
   for (int k = 0; k < CSize<NARROW>::ITEMS; ++k) {
-    const uint32_t lp = (uint32_t)(k * kMThreads + threadIdx.x);
+    const uint32_t lp = (uint32_t)(k * kCThreads + threadIdx.x);
     if (lp < cnt) {
       const uint32_t kk = s_k[lp];
       const uint32_t dg = ((kk >> f.ks) - base) & f.km;
@@ -910,9 +924,9 @@ __device__ __forceinline__ void c_stage(const CFields& f, const Recs<CSize<NARRO
 }
 
 __device__ __forceinline__ void clear_wh(uint32_t* s_wh) {
-  for (uint32_t e = threadIdx.x; e < (uint32_t)kMNB; e += kMThreads) {
+  for (uint32_t e = threadIdx.x; e < (uint32_t)kMNB; e += kCThreads) {
 #pragma unroll
-    for (int v = 0; v < kMWaves / 2; ++v) s_wh[v * kMNB + e] = 0;
+    for (int v = 0; v < kCWaves / 2; ++v) s_wh[v * kMNB + e] = 0;
   }
 }
 
@@ -920,7 +934,7 @@ __device__ __forceinline__ void clear_wh(uint32_t* s_wh) {
 // records of the next tile load while a tile is written.  Sub-buckets larger
 // than one load are listed for k_msd_big_c.
 template <int RB, bool NARROW>
-__global__ __launch_bounds__(kMThreads) void k_msd_tiles_c(MsdPlan p) {
+__global__ __launch_bounds__(kCThreads) void k_msd_tiles_c(MsdPlan p) {
   M_C_LDS
   __shared__ CTile s_next[2];  // by iteration parity: wave 0 writes one while the other is read
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -971,7 +985,7 @@ __global__ __launch_bounds__(kMThreads) void k_msd_tiles_c(MsdPlan p) {
       lds_barrier();
       uint32_t st, ex, all;
       const uint32_t d = threadIdx.x;
-      const uint32_t tot = digit_starts_present(nd, s_wh, s_tmp, &st, &ex, &all);
+      const uint32_t tot = digit_starts_present<kCWaves>(nd, s_wh, s_tmp, &st, &ex, &all);
       tile_groups(p, cur.sb, nsub, cur.r0, d < nd ? tot : 0u, st, ex, all & 1023u, s_ex, s_st, s_bal);
       c_stage<NARROW>(f, r, pos, n, base, s_wh, s_k, s_t, s_w);
       lds_barrier();
@@ -996,7 +1010,7 @@ __global__ __launch_bounds__(kMThreads) void k_msd_tiles_c(MsdPlan p) {
 // pieces of one load, each piece's records of a D3 value following those of
 // the pieces before.
 template <int RB, bool NARROW>
-__global__ __launch_bounds__(kMThreads) void k_msd_big_c(MsdPlan p) {
+__global__ __launch_bounds__(kCThreads) void k_msd_big_c(MsdPlan p) {
   M_C_LDS
   __shared__ uint32_t s_cur[kMNB];
   __shared__ uint32_t s_dx[kMNB];
@@ -1008,16 +1022,16 @@ __global__ __launch_bounds__(kMThreads) void k_msd_big_c(MsdPlan p) {
     const uint32_t sb = G(p.big_list)[i];
     const uint32_t r0 = G(p.sbstart)[sb], n = G(p.sbstart)[sb + 1] - r0;
     const uint32_t base = (sb << b3) & f.km;
-    for (uint32_t e = d; e < (uint32_t)kMNB; e += kMThreads) s_cur[e] = 0;
+    for (uint32_t e = d; e < (uint32_t)kMNB; e += kCThreads) s_cur[e] = 0;
     lds_barrier();
-    for (uint32_t j = d; j < n; j += kMThreads) atomicAdd(&s_cur[((G(f.ik)[r0 + j] >> f.ks) - base) & f.km], 1u);
+    for (uint32_t j = d; j < n; j += kCThreads) atomicAdd(&s_cur[((G(f.ik)[r0 + j] >> f.ks) - base) & f.km], 1u);
     lds_barrier();
     {
       // a large sub-bucket may hold any number of records per digit: two scans
       const uint32_t h = d < nd ? s_cur[d] : 0u;
       uint32_t all_rec, all_present;
-      const uint32_t hst = m_block_scan(h, s_tmp, &all_rec);
-      const uint32_t ex = m_block_scan(h ? 1u : 0u, s_tmp, &all_present);
+      const uint32_t hst = m_block_scan<kCWaves>(h, s_tmp, &all_rec);
+      const uint32_t ex = m_block_scan<kCWaves>(h ? 1u : 0u, s_tmp, &all_present);
       tile_groups(p, sb, 1u, r0, h, hst, ex, all_present, s_ex, s_st, s_bal);
       lds_barrier();
       if (d < nd) s_cur[d] = r0 + hst;
@@ -1030,7 +1044,7 @@ __global__ __launch_bounds__(kMThreads) void k_msd_big_c(MsdPlan p) {
       rank_digits<RB, CSize<NARROW>::ITEMS, false>(r.k, f.ks, f.km, cnt, s_wh, s_sink, pos, base);
       lds_barrier();
       uint32_t st;
-      const uint32_t tot = digit_starts(nd, s_wh, s_tmp, &st);
+      const uint32_t tot = digit_starts<kCWaves>(nd, s_wh, s_tmp, &st);
       if (d < nd) {
         const uint32_t cp = s_cur[d];
         s_dx[d] = cp - st;  // output position minus piece position
@@ -1159,8 +1173,8 @@ static uint32_t c_digit_bits(const MsdPlan& p, bool narrow) {
 hipError_t launch_msd_tiles_c(const MsdPlan& p, hipStream_t s) {
   const bool narrow = p.b2 ? p.narrow_b : p.narrow_a;
 #define F(RB)                                                                                           \
-  if (narrow) hipLaunchKernelGGL((k_msd_tiles_c<RB, true>), dim3(p.wgs_c), dim3(kMThreads), 0, s, p);   \
-  else hipLaunchKernelGGL((k_msd_tiles_c<RB, false>), dim3(p.wgs_c), dim3(kMThreads), 0, s, p);
+  if (narrow) hipLaunchKernelGGL((k_msd_tiles_c<RB, true>), dim3(p.wgs_c), dim3(kCThreads), 0, s, p);   \
+  else hipLaunchKernelGGL((k_msd_tiles_c<RB, false>), dim3(p.wgs_c), dim3(kCThreads), 0, s, p);
   M_RB_SWITCH(c_digit_bits(p, narrow), F)
 #undef F
   return hipGetLastError();
@@ -1170,8 +1184,8 @@ hipError_t launch_msd_big_c(const MsdPlan& p, hipStream_t s) {
   const bool narrow = p.b2 ? p.narrow_b : p.narrow_a;
   const dim3 grid(p.max_big < 256u ? p.max_big : 256u);
 #define F(RB)                                                                                      \
-  if (narrow) hipLaunchKernelGGL((k_msd_big_c<RB, true>), grid, dim3(kMThreads), 0, s, p);          \
-  else hipLaunchKernelGGL((k_msd_big_c<RB, false>), grid, dim3(kMThreads), 0, s, p);
+  if (narrow) hipLaunchKernelGGL((k_msd_big_c<RB, true>), grid, dim3(kCThreads), 0, s, p);          \
+  else hipLaunchKernelGGL((k_msd_big_c<RB, false>), grid, dim3(kCThreads), 0, s, p);
   M_RB_SWITCH(p.b3, F)
 #undef F
   return hipGetLastError();
