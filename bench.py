@@ -46,12 +46,14 @@ SORT_PASS_KERNELS = ("msd_scatter_a", "msd_scatter_b", "msd_tiles_c", "downsweep
 GEN_KERNELS = ("generate", "generate_batch")
 
 
-def algorithmic_bytes(kernel: str, n_syn: int, kernels: dict) -> float | None:
-    """Algorithmic bytes of `kernel` per step, given the step's launches
-    (name -> (launches, ms)) so that the sort's share is split over its
-    record-moving launches."""
+def algorithmic_bytes(kernel: str, n_syn: int, kernels: dict, steps: int = 1) -> float | None:
+    """Algorithmic bytes of `kernel` per step, given the timed launches
+    (name -> (launches, ms[, records])) so that the sort's share is split
+    over its record-moving launches and generation's over the launches that
+    made the synapses (records = synapses generated, over `steps` steps)."""
     if kernel in GEN_KERNELS:
-        return 14.0 * n_syn
+        rec = kernels.get(kernel, ())
+        return 14.0 * (rec[2] / steps if len(rec) > 2 and rec[2] else n_syn)
     if kernel in SORT_PASS_KERNELS:
         launches = sum(kernels[k][0] for k in SORT_PASS_KERNELS if k in kernels)
         return 28.0 * n_syn * kernels[kernel][0] / launches
@@ -361,7 +363,7 @@ def copass_bench(wl, block_size: int, steps: int, warmup: int, radix_bits: int, 
         per[name] = {"launches_per_step": launches / steps, "ms_per_step": round(k_ms, 4), "GBps_algorithmic": gbps}
         if name == "copass_copy":
             per[name]["records_per_step"] = recs / steps
-    gen_ms = per.get("generate", {}).get("ms_per_step", 0.0)
+    gen_ms = sum(per.get(k, {}).get("ms_per_step", 0.0) for k in GEN_KERNELS)
     return {"ms_per_step": round(ms, 3), "synapses_per_s": wl.n_syn / (ms / 1e3),
             "calibrate_device_ms": round(sum(v["ms_per_step"] for v in per.values()) - gen_ms, 3),
             "block_size": block_size, "blocks": -(-wl.n_syn // block_size),
@@ -474,10 +476,10 @@ def no_autapse_bench(wl, block_size: int, steps: int, warmup: int, radix_bits: i
     n_conns = ng.ng_get_connections(ctx).n_conns
     net.close()
     ms = 1e3 * (t1 - t0) / steps
-    gen = kernels.get("generate", (0, 0.0))
+    gen_ms = sum(kernels.get(k, (0, 0.0))[1] for k in GEN_KERNELS)
     return {"ms_per_step": round(ms, 3), "synapses": n_conns, "synapses_per_s": n_conns / (ms / 1e3),
             "calls_with_overlapping_ranges": overlapping,
-            "generate_ms_per_step": round(gen[1] / steps, 4)}
+            "generate_ms_per_step": round(gen_ms / steps, 4)}
 
 
 def pairwise_bench(wl, block_size: int, steps: int, warmup: int, radix_bits: int, sort_ranges: int,
@@ -578,10 +580,11 @@ SEEDS = tuple(range(1, 11))  # the paper's timings are means over ten seeds
 
 def form_bench(wl, form: str, steps: int, warmup: int, block_size: int) -> dict:
     """One workload built and calibrated in the plain form (one ng_connect
-    per call), the batched form (one ng_connect_batch) or the graph form (the
+    per call; the context queues small calls and launches them together), the
+    plain form with the queue off (plain_unqueued: one generation launch per
+    call), the batched form (one ng_connect_batch) or the graph form (the
     batched build captured once, replayed with each step's seed); steps cycle
-    through the seeds.  Wall time per step and the device time of the
-    generation and calibration kernels."""
+    through the seeds.  Wall time per step."""
     import torch
     from paper_2306_09855_amd import ng
     from paper_2306_09855_amd.network import Network, arena_bytes_for
@@ -590,13 +593,15 @@ def form_bench(wl, form: str, steps: int, warmup: int, block_size: int) -> dict:
     side = torch.cuda.Stream()
     net = Network(wl.seed, wl.h, block_size, arena, stream=side.cuda_stream)
     ctx = net.ctx
+    if form == "plain_unqueued":
+        ng.ng_set_schedule(ctx, {**ng.ng_get_schedule(ctx), "queued_calls": 0})
     calls = [ng.call_args(c) for c in wl.calls]
     batch = [list(x) for x in zip(*calls)]
 
     def build():
         for n in wl.populations:
             ng.ng_create_nodes(ctx, n)
-        if form == "plain":
+        if form in ("plain", "plain_unqueued"):
             for a in calls:
                 ng.ng_connect(ctx, *a)
         else:
@@ -638,8 +643,10 @@ def form_bench(wl, form: str, steps: int, warmup: int, block_size: int) -> dict:
 
 def workload_legs(block_size: int, steps: int) -> dict:
     """The two-population network (four calls, four rules, 1.54e8 synapses)
-    and the 4,096-call batch (~4.3e8 synapses, mixed rules over 1e6 nodes) in
-    the plain form, and the batch also in the batched and graph forms."""
+    in the plain form, and the 4,096-call batch (~4.3e8 synapses, mixed rules
+    over 1e6 nodes) in every form: vs_plain compares with the plain form (its
+    calls queued and launched together), vs_one_launch_per_call with the plain
+    form whose queue is off."""
     from paper_2306_09855_amd import workloads as W
     out = {}
     tp = W.two_pop_mixed()
@@ -647,7 +654,9 @@ def workload_legs(block_size: int, steps: int) -> dict:
                              "plain": form_bench(tp, "plain", steps, 1, block_size)}
     log(f"two-population network: {out['two_population']['plain']['ms_per_step']} ms/step")
     bm = W.batch_mixed()
-    legs = {f: form_bench(bm, f, steps, 1, block_size) for f in ("plain", "batched", "graph")}
+    legs = {f: form_bench(bm, f, steps, 1, block_size) for f in ("plain", "plain_unqueued", "batched", "graph")}
+    for f in ("plain", "batched", "graph"):
+        legs[f]["vs_one_launch_per_call"] = round(legs[f]["synapses_per_s"] / legs["plain_unqueued"]["synapses_per_s"], 2)
     for f in ("batched", "graph"):
         legs[f]["vs_plain"] = round(legs[f]["synapses_per_s"] / legs["plain"]["synapses_per_s"], 2)
     out["batch_4096"] = {"n_syn": bm.n_syn, "n_calls": len(bm.calls), "n_nodes": bm.n_nodes, **legs}
@@ -728,7 +737,7 @@ def main() -> int:
     net = Network(wl.seed, wl.h, args.block_size, arena, stream=side.cuda_stream)
     ctx = net.ctx
     schedule = {"calibration": args.calibration, "radix_bits": args.radix_bits, "sort_ranges": args.sort_ranges,
-                "msd_tile": 16384, "gen_synapses_per_lane": 4}
+                "msd_tile": 16384, "gen_synapses_per_lane": 4, "queued_calls": 256}
     schedule_source = "default"
     if args.tune and args.calibration == "radix":
         from paper_2306_09855_amd.autotune import tune
@@ -783,7 +792,7 @@ def main() -> int:
         ev[i + 1].record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    kernels = ng.ng_read_timing(ctx, reset=True)
+    kernels = ng.ng_read_timing(ctx, reset=True, records=True)
     ng.ng_enable_timing(ctx, False)
     if graph is not None:  # replays carry no per-kernel events: time eager builds instead
         ng.ng_graph_destroy(graph)
@@ -793,7 +802,7 @@ def main() -> int:
             ng.ng_reset(ctx)
             ng.ng_set_seed(ctx, SEEDS[i % len(SEEDS)])
             build()
-        kernels = ng.ng_read_timing(ctx, reset=True)
+        kernels = ng.ng_read_timing(ctx, reset=True, records=True)
         ng.ng_enable_timing(ctx, False)
     log(f"timed {args.steps} steps in {t1 - t0:.4f} s")
 
@@ -810,9 +819,9 @@ def main() -> int:
     sbits = int(wl.n_nodes - 1).bit_length()
     lsd_passes = max(1, -(-(sbits + dbits) // schedule["radix_bits"]))
     per_kernel = {}
-    for name, (launches, total_ms) in kernels.items():
+    for name, (launches, total_ms, _) in kernels.items():
         ms = total_ms / args.steps
-        ab = algorithmic_bytes(name, n_syn, kernels)
+        ab = algorithmic_bytes(name, n_syn, kernels, args.steps)
         mb = moved_bytes(name, n_syn, plan) if msd else None
         per_kernel[name] = {"launches_per_step": launches / args.steps, "ms_per_step": round(ms, 4),
                             "GBps_algorithmic": None if ab is None or ms == 0 else round(ab / ms / 1e6, 1),
@@ -820,8 +829,8 @@ def main() -> int:
     dom = max(kernels.items(), key=lambda kv: kv[1][1])[0] if kernels else None
     roofline = None
     if dom is not None:
-        launches, total_ms = kernels[dom]
-        ab_step = algorithmic_bytes(dom, n_syn, kernels)
+        launches, total_ms = kernels[dom][:2]
+        ab_step = algorithmic_bytes(dom, n_syn, kernels, args.steps)
         if ab_step is not None:
             per_launch_bytes = ab_step * args.steps / launches
             avg_s = total_ms / launches / 1e3
@@ -868,6 +877,10 @@ def main() -> int:
     torch.cuda.empty_cache()
     legs_steps = max(1, min(args.steps, 3))
     if args.legs and args.form == "plain" and wl.name == "microcircuit":
+        # the same build with ng_connect's queue off: one generation launch per call
+        one = form_bench(wl, "plain_unqueued", legs_steps, 1, args.block_size)
+        result["one_launch_per_call"] = {**one, "note": "the headline build with queued_calls = 0"}
+        log(f"one launch per call: {one['ms_per_step']} ms/step")
         result.update(workload_legs(args.block_size, legs_steps))
     if args.copass and args.form == "plain":
         cp = copass_bench(wl, args.block_size, legs_steps, 1, args.radix_bits, args.sort_ranges)

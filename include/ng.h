@@ -186,10 +186,20 @@ int ng_destroy(ng_ctx* ctx);
 int ng_create_nodes(ng_ctx* ctx, uint32_t n, ng_range* out);
 
 /* One Connect call (Sec. 2.1).  Validates, reserves blocks by Eq. (1) and
- * enqueues the generation kernel; returns without waiting.  All-or-nothing:
+ * queues the call's generation; returns without waiting.  All-or-nothing:
  * on error nothing changes and no call id is consumed.  The call creates
  * connections [*out_first, *out_first + *out_n) in creation order and uses
- * Philox call id *out_connect_id.  Any output pointer may be NULL. */
+ * Philox call id *out_connect_id.  Any output pointer may be NULL.
+ * Queued calls (fewer than 2^24 synapses each) go to the context's stream
+ * together, as one generation launch, when a call reads or orders work after
+ * the connections (ng_calibrate, ng_calibrate_many, ng_calibrate_noalloc,
+ * ng_sync and every call that synchronizes, ng_connect_batch,
+ * ng_connect_groups, pairwise_bernoulli, ng_graph_begin), when the queue holds
+ * ng_schedule.queued_calls calls, and before a larger call or any call under
+ * graph capture, which launch at once.  Work ordered on the stream by other
+ * means (events, the caller's own kernels) sees a Connect call's connections
+ * only after such a call: ng_sync, or ng_get_connections, in between.  The
+ * arithmetic is the same either way. */
 int ng_connect(ng_ctx* ctx, ng_range src, ng_range tgt, const ng_conn_spec* conn,
                const ng_syn_spec* syn, uint32_t* out_connect_id, uint64_t* out_first,
                uint64_t* out_n);
@@ -316,15 +326,21 @@ int ng_set_tuning(ng_ctx* ctx, int radix_bits, uint32_t sort_ranges);
  *                          10240 or 16384 (default);
  *   gen_synapses_per_lane  synapses each generation lane makes in groups of
  *                          four: 4 (default), 8, 16 or 32 (fewer
- *                          workgroups per launch).
+ *                          workgroups per launch);
+ *   queued_calls           Connect calls ng_connect queues before their
+ *                          generation goes out as one launch, 0..4096
+ *                          (default 256; 0: every call launches at once, one
+ *                          launch per call).
  * ng_set_schedule: NG_ERR_INVALID_ARG (nothing changed) for a value outside
- * these; ng_get_schedule fills the current values. */
+ * these; ng_get_schedule fills the current values.  Lowering queued_calls
+ * launches what the queue holds beyond it. */
 typedef struct {
   int32_t calibration;
   int32_t radix_bits;
   uint32_t sort_ranges;
   uint32_t msd_tile;
   uint32_t gen_synapses_per_lane;
+  uint32_t queued_calls;
 } ng_schedule;
 int ng_set_schedule(ng_ctx* ctx, const ng_schedule* schedule);
 int ng_get_schedule(ng_ctx* ctx, ng_schedule* schedule);

@@ -26,7 +26,7 @@ import torch
 from . import ng
 
 DEFAULT = {"calibration": "radix", "radix_bits": 9, "sort_ranges": 1024, "msd_tile": 16384,
-           "gen_synapses_per_lane": 4}
+           "gen_synapses_per_lane": 4, "queued_calls": 256}
 GEN_SPL = (4, 8, 16)
 RANGES = (512, 1024, 2048)
 GEN_KERNELS = ("generate", "generate_batch")

@@ -237,6 +237,13 @@ struct ng_ctx {
   uint64_t cap_stage_cap = 0, cap_stage_used = 0;
   int frozen = 0;
 
+  // Connect calls planned and committed whose generation is not launched yet:
+  // they go out together as one batched launch when a call needs their
+  // connections (flush_connects).  Groups of four synapses queued so far.
+  std::vector<ng::GenDesc> queued;
+  uint64_t queued_groups = 0;
+  uint32_t queued_max = 256;  // calls queued before they go out (0: none)
+
   // pinned staging for descriptor uploads
   char* h_stage = nullptr;
   uint64_t h_stage_cap = 0;  // bytes
@@ -359,6 +366,12 @@ int noalloc_scratch_init(int device);
 int check_descs(const std::vector<ng::GenDesc>& descs);
 // Commit a prepared call: consume its call id and count its connections.
 void connect_commit(ng_ctx* c, const ng::GenDesc& d, int32_t max_delay);
+// Launch the queued Connect calls' generation: one batched launch whose
+// descriptors come from the arena, or (batched = false, or no arena room)
+// one launch per call with its descriptor as the argument.  Every entry point
+// that reads the connections or orders work after them calls it first.
+// NG_OK when nothing is queued.
+int flush_connects(ng_ctx* c, bool batched = true);
 
 }  // namespace ngrt
 

@@ -67,7 +67,8 @@ class ng_group(ctypes.Structure):
 
 class ng_schedule(ctypes.Structure):
     _fields_ = [("calibration", ctypes.c_int32), ("radix_bits", ctypes.c_int32), ("sort_ranges", ctypes.c_uint32),
-                ("msd_tile", ctypes.c_uint32), ("gen_synapses_per_lane", ctypes.c_uint32)]
+                ("msd_tile", ctypes.c_uint32), ("gen_synapses_per_lane", ctypes.c_uint32),
+                ("queued_calls", ctypes.c_uint32)]
 
 
 class ng_config(ctypes.Structure):
@@ -389,14 +390,17 @@ def ng_set_calibration(ctx, algorithm) -> None:
     _check(lib().ng_set_calibration(ctx, CALIBRATIONS.get(algorithm, algorithm)))
 
 
-SCHEDULE_KEYS = ("calibration", "radix_bits", "sort_ranges", "msd_tile", "gen_synapses_per_lane")
+SCHEDULE_KEYS = ("calibration", "radix_bits", "sort_ranges", "msd_tile", "gen_synapses_per_lane", "queued_calls")
+QUEUED_CALLS_DEFAULT = 256
 
 
 def ng_set_schedule(ctx, schedule: dict) -> None:
-    """schedule: the fields of ng_schedule; calibration may be a name of CALIBRATIONS."""
+    """schedule: the fields of ng_schedule; calibration may be a name of CALIBRATIONS;
+    queued_calls may be left out (256)."""
     cal = schedule["calibration"]
     sc = ng_schedule(CALIBRATIONS[cal] if isinstance(cal, str) else int(cal), int(schedule["radix_bits"]),
-                     int(schedule["sort_ranges"]), int(schedule["msd_tile"]), int(schedule["gen_synapses_per_lane"]))
+                     int(schedule["sort_ranges"]), int(schedule["msd_tile"]), int(schedule["gen_synapses_per_lane"]),
+                     int(schedule.get("queued_calls", QUEUED_CALLS_DEFAULT)))
     _check(lib().ng_set_schedule(ctx, ctypes.byref(sc)))
 
 

@@ -69,7 +69,8 @@ def test_every_schedule_value_gives_the_default_arrays(spl, tile, cal):
 def test_invalid_schedule_is_refused():
     with Network(1, 0.1, 0, 64 << 20) as net:
         before = ng.ng_get_schedule(net.ctx)
-        for bad in ({"gen_synapses_per_lane": 12}, {"msd_tile": 4096}, {"radix_bits": 10}, {"sort_ranges": 0}):
+        for bad in ({"gen_synapses_per_lane": 12}, {"msd_tile": 4096}, {"radix_bits": 10}, {"sort_ranges": 0},
+                    {"queued_calls": 4097}):
             with pytest.raises(ng.NGError) as e:
                 ng.ng_set_schedule(net.ctx, {**autotune.DEFAULT, **bad})
             assert e.value.status == ng.NG_ERR_INVALID_ARG

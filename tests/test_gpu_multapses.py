@@ -59,10 +59,13 @@ def test_no_multapses_match_oracle(name, batched):
         else:
             for c in calls:
                 net.connect(c)
+        # raises if a permutation walk started at or above its bound or reached its step cap
+        net.sync()
         created = net.fetch()
         net.calibrate()
         out = net.fetch()
         gp, gs = net.group_index()
+        net.sync()
     check_creation_order(created, ref, calls)
     check_calibrated(out, gp, gs, ref, calls)
     pairs = created["src"].astype(np.int64) * N_NODES + created["tgt"]
