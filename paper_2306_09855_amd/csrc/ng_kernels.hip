@@ -174,17 +174,25 @@ __device__ __forceinline__ uint32_t load_blocked_key(const SortIO& io, const Til
          (uint16_t)G(reinterpret_cast<const int16_t*>(blk + 12 * B))[o];
 }
 
+// The histogram has kHistCopies interleaved copies (word 4d + c counts
+// digit d for lanes with lane % 4 == c): lanes of one add that hold the same
+// digit then mostly hit different words in different banks instead of
+// serializing on one word.
+constexpr int kHistCopies = 4;
+static_assert(kHistCopies == 4, "word 4d + c, read back as one uint4 (16-byte aligned array)");
+
 template <int RB, bool IN_BLOCKED>
 __global__ __launch_bounds__(kSortThreads) void k_upsweep(SortPack pk, uint32_t* __restrict__ counts) {
   constexpr int NB = 1 << RB;
-  __shared__ uint32_t hist[NB];
+  __shared__ __align__(16) uint32_t hist[NB * kHistCopies];
   const int gr = range_index(pk);
   if (gr < 0) return;
   const SortSeg sg = sort_seg(pk, (uint32_t)gr);
   const SortIO& io = sg.io;
   const uint32_t r = (uint32_t)gr - sg.range0, shift = sg.shift;
   const uint32_t nd = 1u << sg.nbits, mask = nd - 1;
-  for (uint32_t d = threadIdx.x; d < nd; d += kSortThreads) hist[d] = 0;
+  const uint32_t copy = threadIdx.x & (kHistCopies - 1);
+  for (uint32_t d = threadIdx.x; d < nd * kHistCopies; d += kSortThreads) hist[d] = 0;
   __syncthreads();
   const RangeTiles rt = range_tiles(sg, r);
   for (uint32_t t = 0; t < rt.n_full; ++t) {
@@ -222,7 +230,7 @@ __global__ __launch_bounds__(kSortThreads) void k_upsweep(SortPack pk, uint32_t*
       }
     }
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) atomicAdd(&hist[(key[k] >> shift) & mask], 1u);
+    for (int k = 0; k < kItems; ++k) atomicAdd(&hist[(((key[k] >> shift) & mask) << 2) | copy], 1u);
   }
   if (rt.tail) {  // the ragged last tile of the segment
     const uint64_t base = rt.start + rt.n_full * (uint32_t)kTile;
@@ -244,10 +252,13 @@ __global__ __launch_bounds__(kSortThreads) void k_upsweep(SortPack pk, uint32_t*
     }
 #pragma unroll
     for (int k = 0; k < kItems; ++k)
-      if ((uint32_t)(k * kSortThreads + threadIdx.x) < cnt) atomicAdd(&hist[(key[k] >> shift) & mask], 1u);
+      if ((uint32_t)(k * kSortThreads + threadIdx.x) < cnt) atomicAdd(&hist[(((key[k] >> shift) & mask) << 2) | copy], 1u);
   }
   __syncthreads();
-  for (uint32_t d = threadIdx.x; d < nd; d += kSortThreads) counts[sg.cbase + (uint64_t)d * sg.n_ranges + r] = hist[d];
+  for (uint32_t d = threadIdx.x; d < nd; d += kSortThreads) {
+    const uint4 h = *reinterpret_cast<const uint4*>(&hist[d << 2]);
+    counts[sg.cbase + (uint64_t)d * sg.n_ranges + r] = h.x + h.y + h.z + h.w;
+  }
 }
 
 struct SortLds {
