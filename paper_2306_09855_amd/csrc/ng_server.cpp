@@ -103,6 +103,7 @@ struct ng_server {
   std::thread thr;
   bool stop = false;
   uint64_t next_ticket = 1;
+  uint64_t next_stream = 0;                       // sessions are spread over the streams in turn
   std::vector<Request*> incoming;                 // submitted, not yet taken by the scheduler
   std::vector<ng_session*> new_sessions;          // opened, not yet taken by the scheduler
   std::unordered_map<uint64_t, Request*> tickets;  // not yet collected by ng_wait
@@ -602,12 +603,19 @@ int ng_server_destroy(ng_server* s) {
 
 int ng_session_open(ng_server* s, uint64_t seed, ng_session** out) {
   if (!s || !out) return fail(NG_ERR_INVALID_ARG, "null argument");
-  std::lock_guard<std::mutex> lk(s->mu);
   ng_config cfg{};
   cfg.block_size = s->cfg.block_size;
   cfg.seed = seed;
   cfg.h_ms = s->cfg.h_ms;
-  const int k = (int)(s->stats.sessions_opened % s->streams.size());
+  int k = 0;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    k = (int)(s->next_stream++ % s->streams.size());
+  }
+  // The context is made without the server's lock (its events, tables in the
+  // shared arena, which locks itself, and two small launches on stream k), so
+  // the scheduler is not held up; the scheduler first sees the session when
+  // it is registered below.
   ng_ctx* c = nullptr;
   if (int rc = ctx_create_shared(&cfg, &s->arena, s->streams[k], &c)) return rc;
   if (s->cfg.radix_bits)
@@ -617,6 +625,7 @@ int ng_session_open(ng_server* s, uint64_t seed, ng_session** out) {
   ss->ctx = c;
   ss->base_held = c->held;
   ss->stream = k;
+  std::lock_guard<std::mutex> lk(s->mu);
   s->new_sessions.push_back(ss);
   s->stats.sessions_opened++;
   *out = ss;
