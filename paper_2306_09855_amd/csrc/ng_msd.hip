@@ -556,40 +556,55 @@ __global__ __launch_bounds__(kMThreads) void k_msd_count_a(MsdPlan p) {
   __syncthreads();
   const uint32_t ntiles = (p.n + kMsdTile - 1) / kMsdTile;
   const uint32_t t0 = r * p.tpr, t1 = min(t0 + p.tpr, ntiles);
-  const uint64_t B = 1ull << p.log2B;
-  for (uint32_t t = t0; t < t1; ++t) {
-    const uint32_t base = t * kMsdTile;
-    const uint32_t cnt = min(kMsdTile, p.n - base);
-    // groups of 4 records never straddle a block: base and B are multiples of 4
-    for (uint32_t q = threadIdx.x; 4 * q < cnt; q += kMThreads) {
-      const uint32_t j = base + 4 * q;
-      const char* blk = C(p.in_blocks, j >> p.log2B);
-      const uint64_t o = j & (B - 1);
-      uint32_t key[4];
-      if (4 * q + 4 <= cnt) {
-        const u32x4 s4 = *(const NG_GLOBAL u32x4*)(blk + 4 * o);
-        uint32_t dl[4] = {0, 0, 0, 0};
-        if constexpr (NEED_DELAY) {
-          const u32x2 d4 = *(const NG_GLOBAL u32x2*)(blk + 12 * B + 2 * o);
-          dl[0] = d4.x & 0xFFFFu;
-          dl[1] = d4.x >> 16;
-          dl[2] = d4.y & 0xFFFFu;
-          dl[3] = d4.y >> 16;
-        }
-        key[0] = (s4.x << p.dbits) | dl[0];
-        key[1] = (s4.y << p.dbits) | dl[1];
-        key[2] = (s4.z << p.dbits) | dl[2];
-        key[3] = (s4.w << p.dbits) | dl[3];
-        hist_add4(hist, (key[0] >> shift) & (nd - 1), (key[1] >> shift) & (nd - 1), (key[2] >> shift) & (nd - 1),
-                  (key[3] >> shift) & (nd - 1));
-      } else {
-        for (uint32_t e = 0; 4 * q + e < cnt; ++e) {
-          const uint32_t s = G(reinterpret_cast<const uint32_t*>(blk))[o + e];
-          const uint32_t dl = NEED_DELAY ? (uint16_t)G(reinterpret_cast<const int16_t*>(blk + 12 * B))[o + e] : 0u;
-          atomicAdd(&hist[(((s << p.dbits) | dl) >> shift) & (nd - 1)], 1u);
-        }
+  // The range's records [lo, hi) are contiguous; they are read block by
+  // block, each block's table entry once, 16-byte loads of four sources
+  // (and 8-byte loads of four delays), eight groups in flight per thread
+  // (3e8 microcircuit: 0.31 ms; a table lookup per group of four, one
+  // group in flight: 0.325 ms).
+  // lo and the block starts are multiples of 4, so each piece's groups are
+  // aligned and only its last 0-3 records are read one by one.
+  const uint32_t lo = t0 < t1 ? t0 * kMsdTile : 0u;
+  const uint32_t hi = t0 < t1 ? (uint32_t)min((uint64_t)t1 * kMsdTile, (uint64_t)p.n) : 0u;
+  const uint32_t m = nd - 1;
+  auto key = [&](uint32_t src, uint32_t dl) { return (((src << p.dbits) | dl) >> shift) & m; };
+  for (uint32_t j0 = lo; j0 < hi;) {
+    const uint32_t bi = j0 >> p.log2B;
+    const uint32_t bend = (uint32_t)min((uint64_t)hi, ((uint64_t)bi + 1) << p.log2B);
+    const char* blk = C(p.in_blocks, bi);
+    const uint32_t o0 = j0 - (bi << p.log2B), o1 = bend - (bi << p.log2B);
+    const uint32_t nq = (o1 - o0) / 4, oe = o0 + 4 * nq;
+    const NG_GLOBAL u32x4* vs = (const NG_GLOBAL u32x4*)(blk + 4 * (uint64_t)o0);
+    const NG_GLOBAL u32x2* vd = (const NG_GLOBAL u32x2*)(blk + (12ull << p.log2B) + 2 * (uint64_t)o0);
+    auto group = [&](const u32x4& s4, const u32x2& d4) {
+      hist_add4(hist, key(s4.x, d4.x & 0xFFFFu), key(s4.y, d4.x >> 16), key(s4.z, d4.y & 0xFFFFu),
+                key(s4.w, d4.y >> 16));
+    };
+    uint32_t q = threadIdx.x;
+    for (; q + 7 * kMThreads < nq; q += 8 * kMThreads) {
+      u32x4 s4[8];
+      u32x2 d4[8] = {};
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        s4[u] = vs[q + u * kMThreads];
+        if constexpr (NEED_DELAY) d4[u] = vd[q + u * kMThreads];
       }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) group(s4[u], d4[u]);
     }
+    for (; q < nq; q += kMThreads) {
+      u32x2 d4 = {};
+      if constexpr (NEED_DELAY) d4 = vd[q];
+      const u32x4 s4 = vs[q];
+      group(s4, d4);
+    }
+    if (oe + threadIdx.x < o1) {
+      const uint32_t o = oe + threadIdx.x;
+      const uint32_t src = G(reinterpret_cast<const uint32_t*>(blk))[o];
+      const uint32_t dl =
+          NEED_DELAY ? (uint16_t)G(reinterpret_cast<const int16_t*>(blk + (12ull << p.log2B)))[o] : 0u;
+      atomicAdd(&hist[key(src, dl)], 1u);
+    }
+    j0 = bend;
   }
   __syncthreads();
   for (uint32_t d = threadIdx.x; d < nd; d += kMThreads) p.cnt_a[(uint64_t)d * p.ranges_a + r] = hist[d];

@@ -10,7 +10,8 @@ Geometries (checked through ng_calibration_plan before each run):
     or after neither (many nodes: wide target indices);
   * sub-buckets larger than one LDS piece (heavy keys: a few sources, one
     delay), empty sub-buckets (sparse sources), ragged tails, one record;
-  * range counts from 1 to more ranges than tiles; 2^16-connection blocks.
+  * range counts from 1 to more ranges than tiles; 2^16-connection blocks;
+  * a first digit that reaches into the delay bits.
 """
 import numpy as np
 import pytest
@@ -126,6 +127,20 @@ def test_sparse_sources_and_single_record():
     _vs_oracle(wl)
     one = _ftn("one", [3, 4], (0, 3), (3, 4), 1, ("uniform_int", 2, 5))
     _vs_oracle(one)
+
+
+@pytest.mark.parametrize("pops,max_delay,n", [((20, 30), 1000, 600_001), ((8, 8), 30_000, 900_001)])
+def test_delay_bits_in_first_digit(pops, max_delay, n):
+    # 50 or 16 nodes with delays of up to 10 or 15 bits: the first digit
+    # reaches into the delay bits, so the first count reads delays too; one
+    # scatter pass, then two; 2^16-connection blocks, so that ranges of
+    # 10,240-record tiles cross block ends
+    a, b = pops
+    wl = W.Workload("delay_d1", 31, [a, b], [W.Call("fixed_total_number", (0, a), (a, b), n, ("normal", 0.5, 0.05),
+                                                    ("uniform_int", 1, max_delay))])
+    p = _plan(wl)
+    assert p["msd"] >= 1 and p["b2"] + p["b3"] < max_delay.bit_length()
+    _vs_oracle(wl, block_size=1 << 16)
 
 
 @pytest.mark.parametrize("ranges", [1, 3, 100_000])
