@@ -194,12 +194,13 @@ int ng_create_nodes(ng_ctx* ctx, uint32_t n, ng_range* out);
  * together, as one generation launch, when a call reads or orders work after
  * the connections (ng_calibrate, ng_calibrate_many, ng_calibrate_noalloc,
  * ng_sync and every call that synchronizes, ng_connect_batch,
- * ng_connect_groups, pairwise_bernoulli, ng_graph_begin), when the queue holds
- * ng_schedule.queued_calls calls, and before a larger call or any call under
- * graph capture, which launch at once.  Work ordered on the stream by other
- * means (events, the caller's own kernels) sees a Connect call's connections
- * only after such a call: ng_sync, or ng_get_connections, in between.  The
- * arithmetic is the same either way. */
+ * ng_connect_groups, pairwise_bernoulli, ng_graph_begin) and when the queue
+ * holds ng_schedule.queued_calls calls.  A larger call, and any call under
+ * graph capture, launches at once; the queue keeps waiting (each call writes
+ * its own positions, so the launches may run in any order).  Work ordered on
+ * the stream by other means (events, the caller's own kernels) sees a
+ * Connect call's connections only after such a call: ng_sync, or
+ * ng_get_connections, in between.  The arithmetic is the same either way. */
 int ng_connect(ng_ctx* ctx, ng_range src, ng_range tgt, const ng_conn_spec* conn,
                const ng_syn_spec* syn, uint32_t* out_connect_id, uint64_t* out_first,
                uint64_t* out_n);

@@ -4,8 +4,9 @@ connections.  The arrays never depend on it: every case compares the build
 with the same build whose queue is off (queued_calls = 0: one launch per
 call) bit for bit, and the small builds with the oracle, and each case goes
 through one of the points that launch the queue (calibrate, sync and the
-reads that synchronize, a large call, a batch, node arrays, pairwise_bernoulli,
-a lower queue bound, the fixed-scratch calibration) or drops it (reset)."""
+reads that synchronize, a batch, node arrays, pairwise_bernoulli, a lower queue
+bound, the fixed-scratch calibration) or drops it (reset); a large call
+launches at once and leaves the queue waiting."""
 import numpy as np
 import pytest
 
@@ -85,7 +86,8 @@ def test_queue_equals_one_launch_per_call_and_oracle(queue):
 
 
 def test_large_call_between_queued_calls():
-    # a call of 2^24 + 3 synapses launches at once, after the queued calls before it
+    # a call of 2^24 + 3 synapses launches at once; the queued calls before it
+    # wait and go out after it, with the ones queued later, at the calibration
     big = W.Call("fixed_total_number", (0, N_NODES), (0, N_NODES), (1 << 24) + 3,
                  ("normal", 0.5, 0.05), ("uniform_int", 1, 30))
     calls = _small_calls()[:3] + [big] + _small_calls()[3:]
