@@ -433,6 +433,13 @@ typedef struct {
   uint64_t records;
 } ng_kernel_time;
 int ng_enable_timing(ng_ctx* ctx, int on);
+/* With timing on, bracket only the launches named `name` (a name that
+ * ng_read_timing reports, at most 23 characters) by events; NULL or "" (the
+ * default) brackets every launch.  Each event pair leaves the GPU idle for a
+ * few microseconds between kernels, so a caller timing one kernel inside a
+ * longer run can keep the others free of events.  Host only; applies to
+ * later launches.  NG_ERR_INVALID_ARG: null context, name too long. */
+int ng_time_only(ng_ctx* ctx, const char* name);
 int ng_read_timing(ng_ctx* ctx, ng_kernel_time* out, int capacity, int* count, int reset);
 
 /* --- captured graphs (batched form) -------------------------------------

@@ -225,6 +225,7 @@ struct ng_ctx {
     uint64_t launches = 0, records = 0;
   };
   bool timing = false;
+  std::string timing_only;  // with timing on: only launches of this name get events (empty: all)
   std::vector<hipEvent_t> ev_pool;
   std::vector<Timed> pending;
   std::map<std::string, TimeAcc> timing_acc;
@@ -287,6 +288,10 @@ struct AllocSet {
 
 int dev_fail(ng_ctx* c, hipError_t e, const char* what);
 hipEvent_t take_event(ng_ctx* c);
+// Whether a launch of this name is bracketed by timing events.
+inline bool timed_launch(const ng_ctx* c, const char* name) {
+  return c->timing && (c->timing_only.empty() || c->timing_only == name);
+}
 void collect_timing(ng_ctx* c);
 int enter(ng_ctx* c);
 hipError_t set_table(char** tab, uint32_t first, const std::vector<char*>& ptrs, uint32_t from,
@@ -385,7 +390,7 @@ int flush_connects(ng_ctx* c, bool batched = true);
 #define NG_LAUNCH_N(ctx, name, recs, expr)                                      \
   do {                                                                          \
     hipEvent_t a_ = nullptr;                                                    \
-    if ((ctx)->timing && (a_ = take_event(ctx)) != nullptr)                     \
+    if (timed_launch(ctx, name) && (a_ = take_event(ctx)) != nullptr)          \
       (void)hipEventRecord(a_, (ctx)->stream);                                  \
     hipError_t e_ = (expr);                                                     \
     if (e_ != hipSuccess) return dev_fail(ctx, e_, name);                       \

@@ -146,6 +146,7 @@ def lib():
             "ng_reset": ([vp], ctypes.c_int),
             "ng_set_seed": ([vp, u64], ctypes.c_int),
             "ng_enable_timing": ([vp, ctypes.c_int], ctypes.c_int),
+            "ng_time_only": ([vp, ctypes.c_char_p], ctypes.c_int),
             "ng_read_timing": ([vp, P(ng_kernel_time), ctypes.c_int, P(ctypes.c_int), ctypes.c_int],
                                ctypes.c_int),
             "ng_graph_begin": ([vp, u64], ctypes.c_int),
@@ -342,6 +343,11 @@ def ng_set_seed(ctx, seed: int) -> None:
 
 def ng_enable_timing(ctx, on: bool = True) -> None:
     _check(lib().ng_enable_timing(ctx, 1 if on else 0))
+
+
+def ng_time_only(ctx, name=None) -> None:
+    """With timing on, events only around launches of this kernel name (None: all)."""
+    _check(lib().ng_time_only(ctx, name.encode() if name else None))
 
 
 def ng_read_timing(ctx, reset: bool = True, records: bool = False) -> dict:

@@ -206,6 +206,34 @@ def _kernels_used(wl, calibration):
     return names
 
 
+def test_time_only_brackets_one_kernel():
+    # with ng_time_only, only the named launches are timed; the arrays are
+    # those of the build with every launch timed
+    wl = W.microcircuit(scale=0.35)
+    B = 1 << 24
+    outs = []
+    for only in ("msd_tiles_c", None):
+        with Network(wl.seed, wl.h, 0, arena_bytes_for(wl.n_syn, wl.n_nodes, wl.max_delay, B)) as net:
+            ng.ng_time_only(net.ctx, only)
+            ng.ng_enable_timing(net.ctx, True)
+            ng.ng_read_timing(net.ctx, reset=True)
+            net.build(wl)
+            names = ng.ng_read_timing(net.ctx, reset=True)
+            outs.append((net.fetch(), *net.group_index()))
+        if only:
+            assert set(names) == {"msd_tiles_c"} and names["msd_tiles_c"][0] == 1
+        else:
+            assert {"generate_batch", "msd_scatter_a", "msd_tiles_c", "msd_groups"} <= set(names)
+    a, b = outs
+    for k in ("src", "tgt", "delay"):
+        assert np.array_equal(a[0][k], b[0][k]), k
+    assert np.array_equal(a[0]["w"].view(np.uint32), b[0]["w"].view(np.uint32))
+    assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+    with Network(wl.seed, wl.h, 0, 1 << 26) as net:
+        with pytest.raises(ng.NGError):
+            ng.ng_time_only(net.ctx, "x" * 24)
+
+
 def test_default_form_choice():
     # the default radix calibration sorts most-significant digit first from
     # 2^25 connections on, when the sub-buckets average 256 connections or

@@ -171,3 +171,9 @@ def test_calibration_plan_rejects(L):
     assert ng.ng_calibration_plan(1000, 1, 1)["msd"] == 0     # a one-bit key: LSD
     with pytest.raises(ng.NGError):
         ng.ng_calibration_plan(1000, 10, 0)
+
+
+def test_time_only_rejects(L):
+    # no context, or a name longer than ng_kernel_time holds
+    assert L.ng_time_only(None, b"msd_tiles_c") == ng.NG_ERR_INVALID_ARG
+    assert L.ng_time_only(None, None) == ng.NG_ERR_INVALID_ARG
