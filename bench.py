@@ -892,8 +892,9 @@ def main() -> int:
                           "frac": round(path_alg / (ms_per_step / 1e3) / (HBM_PEAK_GBS * 1e9), 4)},
         "roofline": roofline,
         "kernels": per_kernel,
-        "kernels_note": "per-kernel times from as many eager builds again after the timed steps, with HIP events "
-                        "around every launch; the timed steps carry events around the dominant kernel only",
+        "kernels_note": "per-kernel times from as many eager builds again, untimed (before the timed steps; after "
+                        "the replays for the graph form), with HIP events around every launch; the timed steps "
+                        "carry events around the dominant kernel only",
     }
     radix_peak = net.memory_stats()[1]
     net.close()
