@@ -30,6 +30,10 @@ namespace ng {
 namespace {
 
 constexpr int kMThreads = 512;
+// The counting passes run 1,024 threads (more loads in flight per CU: on the
+// 3e8 microcircuit 0.30 -> 0.295 ms for the first count, 0.254 -> 0.239 ms
+// for the second, against 512).
+constexpr int kCntThreads = 1024;
 constexpr int kMWaves = kMThreads / 64;
 constexpr int kMItems = (int)kMsdTile / kMThreads;   // tile of pass A and of unpacked records
 constexpr int kMItemsN = (int)kMsdTileN / kMThreads;  // tile of packed records (passes B and C)
@@ -547,20 +551,20 @@ __device__ __forceinline__ void hist_add4(uint32_t* hist, uint32_t d0, uint32_t 
 // Pass A: D1 of every creation-order record (the delays are read only when
 // D1 reaches into the delay bits).
 template <bool NEED_DELAY>
-__global__ __launch_bounds__(kMThreads) void k_msd_count_a(MsdPlan p) {
+__global__ __launch_bounds__(kCntThreads) void k_msd_count_a(MsdPlan p) {
   __shared__ uint32_t hist[kMNB];
   const uint32_t r = m_range((p.ranges_a + 7) / 8);
   if (r >= p.ranges_a) return;
   const uint32_t nd = 1u << p.b1, shift = p.b2 + p.b3;
-  for (uint32_t d = threadIdx.x; d < (uint32_t)kMNB; d += kMThreads) hist[d] = 0;
+  for (uint32_t d = threadIdx.x; d < (uint32_t)kMNB; d += kCntThreads) hist[d] = 0;
   __syncthreads();
   const uint32_t ntiles = (p.n + kMsdTile - 1) / kMsdTile;
   const uint32_t t0 = r * p.tpr, t1 = min(t0 + p.tpr, ntiles);
   // The range's records [lo, hi) are contiguous; they are read block by
   // block, each block's table entry once, 16-byte loads of four sources
   // (and 8-byte loads of four delays), eight groups in flight per thread
-  // (3e8 microcircuit: 0.31 ms; a table lookup per group of four, one
-  // group in flight: 0.325 ms).
+  // (3e8 microcircuit, 512 threads: 0.31 ms; a table lookup per group of
+  // four, one group in flight: 0.325 ms).
   // lo and the block starts are multiples of 4, so each piece's groups are
   // aligned and only its last 0-3 records are read one by one.
   const uint32_t lo = t0 < t1 ? t0 * kMsdTile : 0u;
@@ -580,18 +584,18 @@ __global__ __launch_bounds__(kMThreads) void k_msd_count_a(MsdPlan p) {
                 key(s4.w, d4.y >> 16));
     };
     uint32_t q = threadIdx.x;
-    for (; q + 7 * kMThreads < nq; q += 8 * kMThreads) {
+    for (; q + 7 * kCntThreads < nq; q += 8 * kCntThreads) {
       u32x4 s4[8];
       u32x2 d4[8] = {};
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        s4[u] = vs[q + u * kMThreads];
-        if constexpr (NEED_DELAY) d4[u] = vd[q + u * kMThreads];
+        s4[u] = vs[q + u * kCntThreads];
+        if constexpr (NEED_DELAY) d4[u] = vd[q + u * kCntThreads];
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) group(s4[u], d4[u]);
     }
-    for (; q < nq; q += kMThreads) {
+    for (; q < nq; q += kCntThreads) {
       u32x2 d4 = {};
       if constexpr (NEED_DELAY) d4 = vd[q];
       const u32x4 s4 = vs[q];
@@ -607,17 +611,17 @@ __global__ __launch_bounds__(kMThreads) void k_msd_count_a(MsdPlan p) {
     j0 = bend;
   }
   __syncthreads();
-  for (uint32_t d = threadIdx.x; d < nd; d += kMThreads) p.cnt_a[(uint64_t)d * p.ranges_a + r] = hist[d];
+  for (uint32_t d = threadIdx.x; d < nd; d += kCntThreads) p.cnt_a[(uint64_t)d * p.ranges_a + r] = hist[d];
 }
 
 // Pass B: D2 of the records of each range of each bucket.
 template <int IN>
-__global__ __launch_bounds__(kMThreads) void k_msd_count_b(MsdPlan p) {
+__global__ __launch_bounds__(kCntThreads) void k_msd_count_b(MsdPlan p) {
   __shared__ uint32_t hist[kMNB];
   __shared__ uint32_t s_rb0[kMNB + 1];
   const uint32_t nb = 1u << p.b1, nd = 1u << p.b2;
-  for (uint32_t b = threadIdx.x; b <= nb; b += kMThreads) s_rb0[b] = p.rangeb0[b];
-  for (uint32_t d = threadIdx.x; d < (uint32_t)kMNB; d += kMThreads) hist[d] = 0;
+  for (uint32_t b = threadIdx.x; b <= nb; b += kCntThreads) s_rb0[b] = p.rangeb0[b];
+  for (uint32_t d = threadIdx.x; d < (uint32_t)kMNB; d += kCntThreads) hist[d] = 0;
   __syncthreads();
   const uint32_t r = m_range((p.max_ranges_b + 7) / 8);
   if (r >= s_rb0[nb]) return;
@@ -637,23 +641,23 @@ __global__ __launch_bounds__(kMThreads) void k_msd_count_b(MsdPlan p) {
   const NG_GLOBAL u32x4* v = (const NG_GLOBAL u32x4*)(p.a_key + a0);
   const uint32_t nq = (a1 - a0) / 4;
   uint32_t q = threadIdx.x;
-  for (; q + 3 * kMThreads < nq; q += 4 * kMThreads) {
+  for (; q + 3 * kCntThreads < nq; q += 4 * kCntThreads) {
     u32x4 x[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) x[u] = v[q + u * kMThreads];
+    for (int u = 0; u < 4; ++u) x[u] = v[q + u * kCntThreads];
     const uint32_t m = nd - 1;
 #pragma unroll
     for (int u = 0; u < 4; ++u)
       hist_add4(hist, (x[u].x >> shift) & m, (x[u].y >> shift) & m, (x[u].z >> shift) & m, (x[u].w >> shift) & m);
   }
-  for (; q < nq; q += kMThreads) {
+  for (; q < nq; q += kCntThreads) {
     const u32x4 x = v[q];
     const uint32_t m = nd - 1;
     hist_add4(hist, (x.x >> shift) & m, (x.y >> shift) & m, (x.z >> shift) & m, (x.w >> shift) & m);
   }
   __syncthreads();
   const uint64_t cb = ((uint64_t)s_rb0[b] << p.b2) + rl;
-  for (uint32_t d = threadIdx.x; d < nd; d += kMThreads) p.cnt_b[cb + (uint64_t)d * nr] = hist[d];
+  for (uint32_t d = threadIdx.x; d < nd; d += kCntThreads) p.cnt_b[cb + (uint64_t)d * nr] = hist[d];
 }
 
 // ---------------------------------------------------------------------------
@@ -1153,8 +1157,8 @@ uint32_t msd_cap(bool) { return kMsdTile; }
 
 hipError_t launch_msd_count_a(const MsdPlan& p, hipStream_t s) {
   const dim3 grid(8 * ((p.ranges_a + 7) / 8));
-  if (p.b2 + p.b3 < p.dbits) hipLaunchKernelGGL(k_msd_count_a<true>, grid, dim3(kMThreads), 0, s, p);
-  else hipLaunchKernelGGL(k_msd_count_a<false>, grid, dim3(kMThreads), 0, s, p);
+  if (p.b2 + p.b3 < p.dbits) hipLaunchKernelGGL(k_msd_count_a<true>, grid, dim3(kCntThreads), 0, s, p);
+  else hipLaunchKernelGGL(k_msd_count_a<false>, grid, dim3(kCntThreads), 0, s, p);
   return hipGetLastError();
 }
 
@@ -1175,8 +1179,8 @@ hipError_t launch_msd_plan_b(const MsdPlan& p, hipStream_t s) {
 
 hipError_t launch_msd_count_b(const MsdPlan& p, hipStream_t s) {
   const dim3 grid(8 * ((p.max_ranges_b + 7) / 8));
-  if (p.narrow_a) hipLaunchKernelGGL(k_msd_count_b<IN_NARROW>, grid, dim3(kMThreads), 0, s, p);
-  else hipLaunchKernelGGL(k_msd_count_b<IN_WIDE>, grid, dim3(kMThreads), 0, s, p);
+  if (p.narrow_a) hipLaunchKernelGGL(k_msd_count_b<IN_NARROW>, grid, dim3(kCntThreads), 0, s, p);
+  else hipLaunchKernelGGL(k_msd_count_b<IN_WIDE>, grid, dim3(kCntThreads), 0, s, p);
   return hipGetLastError();
 }
 
