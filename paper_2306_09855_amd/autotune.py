@@ -2,8 +2,10 @@
 
 For a workload it times, on this device, the generation kernels for each
 number of synapses per lane and the calibration kernels for each calibration
-form with its tile, digit and range settings, keeps the fastest of each and
-caches the choice as JSON per device, keyed by the connection count and the
+form with its tile, digit and range settings, keeps the fastest of each when
+it beats the default schedule by at least MARGIN (closer than that, the
+timings' noise would decide, and the default stays), and caches the choice
+as JSON per device, keyed by the connection count and the
 key density (both rounded to powers of two) and the key width.  The
 arithmetic never depends on the schedule -- only the speed does -- which the
 tests check by building under the chosen and the default schedule.
@@ -28,6 +30,7 @@ from . import ng
 DEFAULT = {"calibration": "radix", "radix_bits": 9, "sort_ranges": 1024, "msd_tile": 16384,
            "gen_synapses_per_lane": 4, "queued_calls": 256}
 GEN_SPL = (4, 8, 16)
+MARGIN = 0.02  # a candidate replaces the default only when this much faster
 RANGES = (512, 1024, 2048)
 GEN_KERNELS = ("generate", "generate_batch")
 
@@ -103,10 +106,11 @@ def _timed(ctx, fn, names=None) -> float:
     return sum(v[1] for k, v in t.items() if names is None or k in names)
 
 
-def tune(net, workload, batched: bool = False, reps: int = 2, use_cache: bool = True):
-    """The fastest schedule for this workload on this device, as a dict of
-    ng_schedule fields, and whether it came from the cache.  The context is
-    left reset, with its previous schedule."""
+def tune(net, workload, batched: bool = False, reps: int = 3, use_cache: bool = True):
+    """The schedule for this workload on this device, as a dict of
+    ng_schedule fields (per field group, the fastest candidate where it beats
+    the default by MARGIN, else the default), and whether it came from the
+    cache.  The context is left reset, with its previous schedule."""
     key = _key(workload, batched)
     path = cache_path()
     cache = _load(path) if use_cache else {}
@@ -122,21 +126,28 @@ def tune(net, workload, batched: bool = False, reps: int = 2, use_cache: bool = 
         gen_ms[spl] = min(_timed(ctx, lambda: _build(ctx, workload, args, batch, batched), GEN_KERNELS)
                           for _ in range(reps))
     best_spl = min(GEN_SPL, key=lambda s: gen_ms[s])
-    cal_ms = {}
-    for cand in calibration_candidates(workload):
-        sched = {**DEFAULT, **cand, "gen_synapses_per_lane": best_spl}
+    if gen_ms[best_spl] > (1 - MARGIN) * gen_ms[DEFAULT["gen_synapses_per_lane"]]:
+        best_spl = DEFAULT["gen_synapses_per_lane"]
+
+    def calibrate_ms(sched):
         ng.ng_set_schedule(ctx, sched)
         best = math.inf
         for _ in range(reps):
             _build(ctx, workload, args, batch, batched)
             best = min(best, _timed(ctx, lambda: ng.ng_calibrate(ctx)))
-        cal_ms[json.dumps(cand, sort_keys=True)] = best
-    best_cal = json.loads(min(cal_ms, key=cal_ms.get))
+        return best
+
+    default_ms = calibrate_ms({**DEFAULT, "gen_synapses_per_lane": best_spl})
+    cal_ms = {}
+    for cand in calibration_candidates(workload):
+        cal_ms[json.dumps(cand, sort_keys=True)] = calibrate_ms({**DEFAULT, **cand, "gen_synapses_per_lane": best_spl})
+    best_key = min(cal_ms, key=cal_ms.get)
+    best_cal = json.loads(best_key) if cal_ms[best_key] <= (1 - MARGIN) * default_ms else {}
     choice = {**DEFAULT, **best_cal, "gen_synapses_per_lane": best_spl}
     ng.ng_reset(ctx)
     ng.ng_set_schedule(ctx, saved)
     cache[key] = {"choice": choice, "generate_ms": {str(k): v for k, v in gen_ms.items()},
-                  "calibrate_ms": cal_ms}
+                  "calibrate_ms": cal_ms, "default_calibrate_ms": default_ms}
     if use_cache:
         _save(path, cache)
     return choice, False

@@ -45,6 +45,17 @@ def test_tune_caches_reuses_and_keeps_results(tmp_path, monkeypatch, batched):
         # every candidate of the space was timed
         assert len(entry["calibrate_ms"]) == len(autotune.calibration_candidates(wl))
         assert set(entry["generate_ms"]) == {str(s) for s in autotune.GEN_SPL}
+        # a choice away from the default beat the default by the margin
+        g = entry["generate_ms"]
+        spl = choice["gen_synapses_per_lane"]
+        if spl != autotune.DEFAULT["gen_synapses_per_lane"]:
+            assert g[str(spl)] <= (1 - autotune.MARGIN) * g[str(autotune.DEFAULT["gen_synapses_per_lane"])]
+        fields = ("calibration", "msd_tile", "sort_ranges", "radix_bits")
+        cal = {k: choice[k] for k in fields}
+        if cal != {k: autotune.DEFAULT[k] for k in fields}:
+            t = entry["calibrate_ms"][json.dumps(cal, sort_keys=True)]
+            assert t <= (1 - autotune.MARGIN) * entry["default_calibrate_ms"]
+            assert t == min(entry["calibrate_ms"].values())
         again, cached2 = autotune.tune(net, wl, batched=batched)
         assert cached2 and again == choice
     a = _build(wl, autotune.DEFAULT, batched)
