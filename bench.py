@@ -707,7 +707,7 @@ def main() -> int:
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build measures one GPU; the multi-GPU path is a design only",
+        print(json.dumps({"error": "the benchmark runs on one GPU; sharding over several GPUs is not implemented",
                           "n_gpus": args.gpus}))
         return 2
 
