@@ -13,7 +13,7 @@ tests check by building under the chosen and the default schedule.
 Search space:
   gen_synapses_per_lane   4, 8, 16                    (generation kernels)
   most-significant-digit  msd_tile 16384 / 10240 x sort_ranges 512 / 1024 / 2048
-                          (the second scatter takes twice as many ranges)
+                          (the second scatter takes three times as many ranges)
   LSD                     radix_bits 8 / 9 x sort_ranges 512 / 1024 / 2048
 (the MSD form only where it applies: keys of at most 27 bits).
 """

@@ -1010,10 +1010,11 @@ bool msd_geometry(uint64_t N, uint32_t nn, int dbits, int log2B, uint32_t sort_r
   p.ranges_a = (uint32_t)((ntiles + p.tpr - 1) / p.tpr);
   p.tile_b = p.narrow_a && msd_tile != ng::kMsdTile ? ng::kMsdTileN : ng::kMsdTile;
   // each bucket asks for ceil(its tiles x ranges_b / all tiles) ranges;
-  // twice the ranges of pass A (measured: the buckets' tiles spread over
-  // more, shorter ranges balance better: 1.73 ms instead of 1.99 for the 3e8
-  // microcircuit's second scatter)
-  p.ranges_b = 2 * std::max<uint32_t>(sort_ranges, 1);
+  // three times the ranges of pass A (measured on the 3e8 microcircuit's
+  // second scatter: as many as pass A 1.99 ms, twice 1.69, 2.5x 1.66, three
+  // times 1.60, 3.5x 1.73, four times 1.70; the 1.54e8 two-population
+  // network's: 0.78 ms at three times against 0.83 at twice)
+  p.ranges_b = 3 * std::max<uint32_t>(sort_ranges, 1);
   p.max_ranges_b = b2 ? (uint32_t)(p.ranges_b + (1ull << b1)) : 0u;
   // pass C: workgroups of about eight LDS loads of records each, and at
   // least 1,024 (four per CU) so that short tiles of few records -- small or
