@@ -1016,14 +1016,16 @@ bool msd_geometry(uint64_t N, uint32_t nn, int dbits, int log2B, uint32_t sort_r
   // network's: 0.78 ms at three times against 0.83 at twice)
   p.ranges_b = 3 * std::max<uint32_t>(sort_ranges, 1);
   p.max_ranges_b = b2 ? (uint32_t)(p.ranges_b + (1ull << b1)) : 0u;
-  // pass C: workgroups of about eight LDS loads of records each, and at
+  // pass C: workgroups of about six LDS loads of records each (measured:
+  // 3e8 microcircuit 1.90 -> 1.88 ms against eight, 1.54e8 two-population
+  // network 1.10 -> 1.06 ms; two loads: no gain; sixteen: 1.97 ms), and at
   // least 1,024 (four per CU) so that short tiles of few records -- small or
   // sparse calibrations -- still spread over the chip; no more workgroups
   // than sub-buckets
   const uint64_t piece = ng::msd_cap(b2 ? p.narrow_b : p.narrow_a);
   const uint64_t nsb = 1ull << (b1 + b2);
   p.wgs_c = (uint32_t)std::min<uint64_t>(
-      std::max<uint64_t>(1, std::min<uint64_t>(std::max<uint64_t>((N + 8 * piece - 1) / (8 * piece), 1024), nsb)),
+      std::max<uint64_t>(1, std::min<uint64_t>(std::max<uint64_t>((N + 6 * piece - 1) / (6 * piece), 1024), nsb)),
       1u << 20);
   p.max_big = (uint32_t)(N / (piece + 1) + 1);
   p.n_nodes = nn;
